@@ -1,0 +1,220 @@
+"""FP64 CPU oracle for the Barnes-Hut dipolar field -- TEST INFRASTRUCTURE ONLY.
+
+Only the test suite, the package smoke check and the CPU-baseline leg of the benchmark may import this
+package.  The GPU library never loads it; the two share no code.  Arithmetic lives in ``oracle.c`` (plain
+C, FP64, built with gcc and ``-ffp-contract=off``); this module only builds that file and marshals numpy
+arrays into it.  ``md.py`` holds the integrator reference.
+
+Vector fields are float64 arrays of shape (3, n).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_CFLAGS = ["-O2", "-std=c11", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared"]
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c into liboracle.so next to it (gcc)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.run(["gcc", *_CFLAGS, _SRC, "-o", tmp, "-lm"], check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        L = C.CDLL(_LIB)
+        P = C.c_void_p
+        i64 = C.c_int64
+        L.or_allpairs_field.argtypes = [i64, P, P, P]
+        L.or_allpairs_field_subset.argtypes = [i64, P, P, i64, P, P]
+        L.or_energy.argtypes = [i64, P, P, P]
+        L.or_energy.restype = C.c_double
+        L.or_allpairs_grad_r.argtypes = [i64, P, P, P]
+        L.or_allpairs_grad_r_subset.argtypes = [i64, P, P, i64, P, P]
+        L.or_tree_build.argtypes = [i64, P, P, C.c_int]
+        L.or_tree_build.restype = P
+        L.or_tree_free.argtypes = [P]
+        L.or_tree_num_nodes.argtypes = [P]
+        L.or_tree_num_nodes.restype = i64
+        L.or_tree_export.argtypes = [P] + [P] * 13
+        L.or_bh_field.argtypes = [P, C.c_double, P, P, P]
+        L.or_bh_field_subset.argtypes = [P, C.c_double, i64, P, P, P, P]
+        L.or_bh_lists.argtypes = [P, C.c_double, P, P, P, P]
+        L.or_bh_vjp.argtypes = [P, C.c_double, P, P, P]
+        L.or_energy_frozen.argtypes = [i64, P, P, P, i64, P, P, P, P, P, P, P, P]
+        L.or_energy_frozen.restype = C.c_double
+        L.or_fd_grad_frozen.argtypes = [i64, P, P, P, i64, P, P, P, P, P, P, P, C.c_double, P, P]
+        L.or_num_threads.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def num_threads() -> int:
+    return lib().or_num_threads()
+
+
+def allpairs_field(pos, mom):
+    pos, mom = _f64(pos), _f64(mom)
+    H = np.empty_like(pos)
+    assert lib().or_allpairs_field(pos.shape[1], _p(pos), _p(mom), _p(H)) == 0
+    return H
+
+
+def allpairs_field_subset(pos, mom, targets):
+    pos, mom = _f64(pos), _f64(mom)
+    t = np.ascontiguousarray(targets, dtype=np.int64)
+    H = np.empty((3, t.size))
+    assert lib().or_allpairs_field_subset(pos.shape[1], _p(pos), _p(mom), t.size, _p(t), _p(H)) == 0
+    return H
+
+
+def energy(mom, H, hext=None) -> float:
+    mom, H = _f64(mom), _f64(H)
+    he = None if hext is None else _f64(hext)
+    return lib().or_energy(mom.shape[1], _p(mom), _p(H), _p(he))
+
+
+def allpairs_grad_r(pos, mom):
+    pos, mom = _f64(pos), _f64(mom)
+    g = np.empty_like(pos)
+    assert lib().or_allpairs_grad_r(pos.shape[1], _p(pos), _p(mom), _p(g)) == 0
+    return g
+
+
+def allpairs_grad_r_subset(pos, mom, targets):
+    pos, mom = _f64(pos), _f64(mom)
+    t = np.ascontiguousarray(targets, dtype=np.int64)
+    g = np.empty((3, t.size))
+    assert lib().or_allpairs_grad_r_subset(pos.shape[1], _p(pos), _p(mom), t.size, _p(t), _p(g)) == 0
+    return g
+
+
+class Tree:
+    """The uncollapsed octree of the oracle, with pseudo-particles (Eq. magCenter)."""
+
+    def __init__(self, pos, mom, leaf_size: int = 16):
+        self.pos, self.mom = _f64(pos), _f64(mom)
+        self.n = self.pos.shape[1]
+        self.leaf_size = leaf_size
+        h = lib().or_tree_build(self.n, _p(self.pos), _p(self.mom), leaf_size)
+        if not h:
+            raise ValueError("oracle tree build rejected its arguments")
+        self._h = h
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            lib().or_tree_free(self._h)
+            self._h = None
+
+    @property
+    def num_nodes(self) -> int:
+        return lib().or_tree_num_nodes(self._h)
+
+    def export(self) -> dict:
+        n, nn = self.n, self.num_nodes
+        d = dict(bbox=np.empty(5), code=np.empty(n, np.uint64), perm=np.empty(n, np.int64),
+                 level=np.empty(nn, np.int32), first=np.empty(nn, np.int64),
+                 count=np.empty(nn, np.int64), nchild=np.empty(nn, np.int32),
+                 child=np.empty((nn, 8), np.int64), parent=np.empty(nn, np.int64),
+                 S=np.empty((nn, 3)), M=np.empty((nn, 3)), c=np.empty((nn, 3)), s2=np.empty(nn))
+        keys = ["bbox", "code", "perm", "level", "first", "count", "nchild", "child", "parent", "S",
+                "M", "c", "s2"]
+        lib().or_tree_export(self._h, *[_p(d[k]) for k in keys])
+        return d
+
+    def field(self, theta: float):
+        """(H (3, n), n_far (n,), n_near (n,)) for every particle."""
+        H = np.empty((3, self.n))
+        nf = np.empty(self.n, np.int64)
+        nr = np.empty(self.n, np.int64)
+        assert lib().or_bh_field(self._h, theta, _p(H), _p(nf), _p(nr)) == 0
+        return H, nf, nr
+
+    def field_subset(self, theta: float, targets):
+        t = np.ascontiguousarray(targets, dtype=np.int64)
+        H = np.empty((3, t.size))
+        nf = np.empty(t.size, np.int64)
+        nr = np.empty(t.size, np.int64)
+        assert lib().or_bh_field_subset(self._h, theta, t.size, _p(t), _p(H), _p(nf), _p(nr)) == 0
+        return H, nf, nr
+
+    def lists(self, theta: float) -> dict:
+        n = self.n
+        fp = np.zeros(n + 1, np.int64)
+        npt = np.zeros(n + 1, np.int64)
+        assert lib().or_bh_lists(self._h, theta, _p(fp), None, _p(npt), None) == 0
+        fn = np.empty(max(int(fp[-1]), 1), np.int64)
+        ni = np.empty(max(int(npt[-1]), 1), np.int64)
+        assert lib().or_bh_lists(self._h, theta, _p(fp), _p(fn), _p(npt), _p(ni)) == 0
+        return dict(far_ptr=fp, far_node=fn, near_ptr=npt, near_idx=ni)
+
+    def vjp(self, theta: float, hbar):
+        """(dL/dr, dL/dm) for L = sum_i hbar_i . H_i with the structure frozen."""
+        hb = _f64(hbar)
+        dr = np.empty((3, self.n))
+        dm = np.empty((3, self.n))
+        assert lib().or_bh_vjp(self._h, theta, _p(hb), _p(dr), _p(dm)) == 0
+        return dr, dm
+
+    def energy_grad(self, theta: float, hext=None):
+        """(H, E, dE/dr, dE/dm) for E = -1/2 sum m.H - sum m.H_ext, structure frozen."""
+        H, _, _ = self.field(theta)
+        E = energy(self.mom, H, hext)
+        dr, dm = self.vjp(theta, -0.5 * self.mom)
+        he = np.zeros(3) if hext is None else _f64(hext)
+        dm = dm - 0.5 * H - he[:, None]
+        return H, E, dr, dm
+
+
+def frozen_structure(tree: Tree, theta: float) -> dict:
+    d = tree.export()
+    d.update(tree.lists(theta))
+    return d
+
+
+def energy_frozen(pos, mom, hext, st: dict) -> float:
+    pos, mom = _f64(pos), _f64(mom)
+    he = None if hext is None else _f64(hext)
+    nn = st["first"].size
+    scr = np.empty(6 * nn)
+    return lib().or_energy_frozen(pos.shape[1], _p(pos), _p(mom), _p(he), nn, _p(st["first"]),
+                                  _p(st["count"]), _p(st["perm"]), _p(st["far_ptr"]),
+                                  _p(st["far_node"]), _p(st["near_ptr"]), _p(st["near_idx"]),
+                                  _p(scr))
+
+
+def fd_grad_frozen(pos, mom, hext, st: dict, h: float = 1e-6):
+    """Central differences (step h) of the frozen-structure energy in every coordinate."""
+    pos, mom = _f64(pos), _f64(mom)
+    he = None if hext is None else _f64(hext)
+    dr = np.empty_like(pos)
+    dm = np.empty_like(mom)
+    nn = st["first"].size
+    assert lib().or_fd_grad_frozen(pos.shape[1], _p(pos), _p(mom), _p(he), nn, _p(st["first"]),
+                                   _p(st["count"]), _p(st["perm"]), _p(st["far_ptr"]),
+                                   _p(st["far_node"]), _p(st["near_ptr"]), _p(st["near_idx"]),
+                                   h, _p(dr), _p(dm)) == 0
+    return dr, dm
