@@ -1,0 +1,167 @@
+/*
+ * ffbh.h -- C ABI of libffbh: Barnes-Hut dipolar field, its adjoint, and a Langevin MD step on one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The problem is the one stated in Sec. 2 of Polyakov et al., "Large-scale ferrofluid simulations on
+ * graphics processing units" (arXiv:1212.2934): N identical particles with positions r_i and moments
+ * m_i interact through the dipole field of Eq. (H_dip),
+ *     H_i = sum_{j != i} [3 r_ij (m_j . r_ij) - m_j |r_ij|^2] / |r_ij|^5 ,   r_ij = r_i - r_j ,
+ * in reduced units (diameter 1, no mu0/4pi prefactor).  The sum is approximated with the Barnes-Hut
+ * scheme of Sec. 3.2: an octree over a bounding cube, cell pseudo-particles whose moment is the sum of
+ * the members' moments and whose position is the members' geometric centre (Eq. magCenter), and a
+ * per-target traversal that uses a cell's pseudo-particle when the target is far enough from it and
+ * opens the cell otherwise.  "Far enough" (the paper gives no criterion) is, per target i and cell C:
+ *     i is not a member of C  and  s_C^2 < (theta*theta) * d^2 ,
+ * s_C the side of C's cube and d the distance from r_i to C's pseudo-particle.  Leaves hold at most
+ * leaf_size particles; an unaccepted leaf is summed particle by particle (j != i).
+ *
+ * Memory.  Every pointer argument named d_* is DEVICE memory on the current HIP device; all other
+ * pointers are host memory.  Vector fields are FP64 structure-of-arrays: a batch of B systems of n
+ * particles is laid out (B, 3, n) -- x components of system b at [3bn, 3bn+n), y next, z next.
+ * Device buffers are owned by the caller (e.g. torch tensors); the library never allocates or frees
+ * device memory.  Its only device state is the caller-provided workspace, sized by
+ * bh_workspace_bytes, which must stay allocated while the handle is used.  All work is enqueued on the
+ * caller's stream (a hipStream_t passed as void*, NULL = the null stream); no call synchronises with
+ * the host except bh_check_status.
+ *
+ * Errors.  Arguments that can be checked on the host are checked before anything is enqueued; a
+ * failing call returns a negative bh_status and enqueues nothing.  Conditions only the device can see
+ * (non-finite input, two distinct particles at the same position, a cell that cannot be split below
+ * leaf_size, traversal stack overflow) set bits in a device status word that bh_check_status reads.
+ */
+#ifndef FFBH_H
+#define FFBH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t bh_status;
+
+enum {
+    BH_OK = 0,
+    BH_EINVAL = -1,       /* bad argument (null pointer, n < 1, theta < 0, leaf_size outside 1..64) */
+    BH_EWORKSPACE = -2,   /* workspace missing, misaligned or smaller than bh_workspace_bytes       */
+    BH_EDEVICE = -3,      /* a HIP runtime call failed                                              */
+    BH_EDEGENERATE = -4,  /* bh_check_status: the device flagged degenerate input                   */
+    BH_ESTATE = -5        /* bh_field / bh_field_backward / md_step before a successful bh_build    */
+};
+
+/* Device status word bits (bh_check_status). */
+enum {
+    BH_FLAG_NONFINITE = 1u << 0,   /* a position or moment was NaN or infinite                      */
+    BH_FLAG_COINCIDENT = 1u << 1,  /* two distinct particles at zero distance (pair skipped)         */
+    BH_FLAG_DEEP_LEAF = 1u << 2,   /* a level-21 cell holds more than leaf_size particles            */
+    BH_FLAG_STACK = 1u << 3,       /* traversal stack overflow (cannot happen for depth <= 21)       */
+    BH_FLAG_TREE = 1u << 4         /* internal consistency check failed; the affected walk stopped  */
+};
+
+enum { BH_FP64 = 0, BH_FP32_MIXED = 1 };
+
+/* Run parameters, fixed for the life of a handle. */
+typedef struct bh_params {
+    int64_t n;          /* particles per system, >= 1                                                 */
+    int32_t batch;      /* independent systems B, >= 1                                                */
+    int32_t leaf_size;  /* maximum particles per leaf, 1..64                                          */
+    double theta;       /* opening parameter, >= 0 (0 gives the all-pairs sum)                        */
+    int32_t precision;  /* BH_FP64: all arithmetic FP64.  BH_FP32_MIXED: pair arithmetic in FP32 on
+                           FP64 offsets, FP64 acceptance test, FP64 cell sums and accumulation        */
+    int32_t tuning_id;  /* traversal launch shape (see bh_num_tunings); -1 = default                  */
+} bh_params;
+
+typedef struct bh_handle bh_handle;
+
+/* Bytes of device workspace a handle with these parameters needs. */
+bh_status bh_workspace_bytes(const bh_params *p, size_t *out_bytes);
+
+/* Number of traversal launch shapes that tuning_id may select (0..count-1). */
+int32_t bh_num_tunings(void);
+
+/* Create a handle (host memory, owned by the caller until bh_destroy) bound to the current HIP device
+ * and to d_workspace (>= bh_workspace_bytes, 256-byte aligned, owned by the caller). */
+bh_status bh_create(const bh_params *p, void *d_workspace, size_t workspace_bytes, bh_handle **out);
+bh_status bh_destroy(bh_handle *h);
+
+/* Build the tree for positions d_pos (B, 3, n): bounding cube, Morton codes, radix sort, octree and
+ * the geometric centre of every cell (Sec. 3.2 kernels 1-4, Eq. magCenter positions). */
+bh_status bh_build(bh_handle *h, const double *d_pos, void *stream);
+
+/* Dipolar field and energy with the tree of the last bh_build (Eq. H_dip summed by the Sec. 3.2
+ * traversal).  d_mom (B, 3, n) moments; d_hext (B, 3) external field or NULL (zero); d_H (B, 3, n)
+ * receives the dipolar field (without H_ext); d_E (B) receives
+ *     E = -1/2 sum_i m_i . H_i - sum_i m_i . H_ext
+ * or may be NULL. */
+bh_status bh_field(bh_handle *h, const double *d_mom, const double *d_hext, double *d_H, double *d_E,
+                   void *stream);
+
+/* Reverse-mode derivative of the field and energy of bh_field, with the tree, cell membership and
+ * acceptance decisions of the last bh_build held fixed (they are piecewise constant in the
+ * positions).  Given upstream gradients d_gH (B, 3, n) = dL/dH (or NULL = 0) and d_gE (B) = dL/dE (or
+ * NULL = 0), writes d_dpos = dL/dr and d_dmom = dL/dm (B, 3, n) and, if d_dhext is not NULL,
+ * d_dhext = dL/dH_ext (B, 3).  Per interaction the position derivative uses the gradient kernel of
+ * the reduced dipolar force f_dip (Sec. 2). */
+bh_status bh_field_backward(bh_handle *h, const double *d_mom, const double *d_hext,
+                            const double *d_gH, const double *d_gE, double *d_dpos, double *d_dmom,
+                            double *d_dhext, void *stream);
+
+/* Langevin dynamics state, all device FP64 (B, 3, n), updated in place by md_step. */
+typedef struct md_state {
+    double *pos, *vel, *mom, *omega;
+    uint64_t *d_step;   /* device step counter (one uint64), incremented by md_step */
+} md_state;
+
+/* Integrator parameters (reduced units).  Forces: -dE/dr of the Barnes-Hut energy plus a WCA
+ * repulsion (eps, sigma, cut 2^(1/6) sigma) between particles and against the faces of the box
+ * [box_lo, box_hi] (distance centre-to-face, wall sigma = sigma/2).  Torque m x (-dE/dm).
+ * Euler-Maruyama step of size dt for (r, v) and (m, omega) with friction gamma_t, gamma_r and
+ * Gaussian noise of variance 2 gamma kT dt per component; m is rotated by omega*dt and renormalised.
+ * Noise: Philox4x32-10 keyed by (seed, system), counter (step, particle, component-stream). */
+typedef struct md_params {
+    double dt, kT, gamma_t, gamma_r, mass, inertia, wca_eps, wca_sigma;
+    double box_lo[3], box_hi[3];
+    const double *d_hext;   /* (B, 3) or NULL */
+    uint64_t seed;
+} md_params;
+
+/* One MD step: bh_build on the current positions, field + adjoint of the energy, WCA forces, and the
+ * integrator update.  Enqueued on the stream with no host synchronisation (capturable in a graph). */
+bh_status md_step(bh_handle *h, const md_state *s, const md_params *p, void *stream);
+
+/* Read (and clear) the device status word; synchronises the stream.  Returns BH_EDEGENERATE if any
+ * flag was set, BH_OK otherwise; the raw bits go to *flags if not NULL. */
+bh_status bh_check_status(bh_handle *h, void *stream, uint32_t *flags);
+
+/* Per-target interaction counts of the last bh_field (sorted order is undone): far cells and direct
+ * partners, each int32 (B, n) device arrays.  Requires the handle to have been created with
+ * counters enabled (bh_enable_counters before the bh_field call); costs one extra write per target. */
+bh_status bh_enable_counters(bh_handle *h, int32_t *d_n_far, int32_t *d_n_near);
+
+/* ---- Introspection (tests and tools) ------------------------------------------------------------ */
+
+/* Number of octree nodes of the last bh_build (synchronises the stream). */
+bh_status bh_num_nodes(bh_handle *h, void *stream, int64_t *out_nodes);
+
+/* Copy the tree of the last bh_build into caller device buffers (any may be NULL).  Sorted order is
+ * (system, Morton code, index).  d_perm (B*n) int32: sorted position -> global original index b*n+i.
+ * Per node (num_nodes entries): d_first, d_count (sorted positions, global), d_level, d_nchild (0 for a
+ * leaf), d_child_first (-1 for a leaf) as int32; d_centroid (3*num_nodes, AoS xyz) FP64; d_bbox (B*5:
+ * lo_x, lo_y, lo_z, side, scale) FP64.  Roots are nodes 0..B-1.  Unary cells are collapsed: a chain
+ * of cells with one non-empty child each is stored once, at the level of its deepest cell. */
+bh_status bh_export_tree(bh_handle *h, int32_t *d_perm, int32_t *d_first, int32_t *d_count,
+                         int32_t *d_level, int32_t *d_nchild, int32_t *d_child_first,
+                         double *d_centroid, double *d_bbox, void *stream);
+
+/* Host-side reference of the code of a quantised position (21 bits per axis): bit 3k+2 = bit k of qx,
+ * bit 3k+1 = bit k of qy, bit 3k = bit k of qz.  Same function the device uses; no GPU needed. */
+uint64_t bh_morton_code(uint32_t qx, uint32_t qy, uint32_t qz);
+
+/* Static description of a status code. */
+const char *bh_status_str(bh_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FFBH_H */

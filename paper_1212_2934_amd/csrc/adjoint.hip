@@ -1,0 +1,256 @@
+// Adjoint of the Barnes-Hut field: dL/dr and dL/dm for L = sum_i Hbar_i . H_i (+ the explicit
+// dependence of E on m), with the tree, memberships and acceptance decisions of the forward pass held
+// fixed.  The traversal is recomputed (nothing is stored from the forward pass): the same per-lane
+// decisions are taken in the same order, and for every interaction
+//   far (i, C):  dL/dr_i += g(x; Hbar_i, M_C);  B_C -= g;  A_C += T(x) Hbar_i      (x = r_i - c_C)
+//   near (i, k): dL/dr_i += g(x; Hbar_i, m_k);  dL/dr_k -= g;  dL/dm_k += T(x) Hbar_i
+// where g is the summand of the reduced dipolar force f_dip (Sec. 2) and T the dipole-field tensor of
+// Eq. (H_dip).  Cell adjoints reach the members in a downward pass: every member k of C receives
+// A_C in dL/dm_k and B_C / n_C in dL/dr_k (c_C is the mean of the members, Eq. magCenter).
+// Scatters are reduced across the wave before one FP64 atomic per value.
+#include "traverse.h"
+
+namespace ffbh {
+
+__device__ inline void atomic_add_d(double *p, double v)
+{
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <bool MIXED>
+__global__ __launch_bounds__(256) void k_adjoint(
+    const NodeRec *__restrict__ nodes, const double *__restrict__ node_m64, const double *__restrict__ spos,
+    const double *__restrict__ smom, const float *__restrict__ smom32, const double *__restrict__ hbar,
+    double *__restrict__ g_gather, double *__restrict__ g_r, double *__restrict__ g_m,
+    double *__restrict__ node_adj, uint32_t *__restrict__ status, int64_t n, int64_t ntot,
+    int waves_per_seg, int num_waves, double theta2, int max_nodes)
+{
+    using T = typename std::conditional<MIXED, float, double>::type;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wpb = blockDim.x / kWave;
+    const int gw = xcd_block(blockIdx.x, gridDim.x) * wpb + (int)(threadIdx.x / kWave);
+    if (gw >= num_waves) return;
+    const int seg = gw / waves_per_seg;
+    const int local = (gw - seg * waves_per_seg) * kWave + lane;
+    const bool valid = local < n;
+    const int si = (int)(seg * n) + (valid ? local : 0);
+    const double rx = spos[si], ry = spos[ntot + si], rz = spos[2 * ntot + si];
+    const T ax = valid ? (T)hbar[si] : (T)0, ay = valid ? (T)hbar[ntot + si] : (T)0,
+            az = valid ? (T)hbar[2 * ntot + si] : (T)0;
+
+    double grx = 0.0, gry = 0.0, grz = 0.0;
+
+    LaneStack st{0, 0, 0, 0, 0};
+    st.push(lane, seg, seg + 1, __ballot(valid));
+    int guard = max_nodes;  // a wave visits each node at most once
+    while (st.sp > 0) {
+        uint64_t mask;
+        const int cur = st.pop(lane, mask);
+        if (--guard < 0 || (unsigned)cur >= (unsigned)max_nodes) {
+            if (lane == 0) set_flag(status, BH_FLAG_TREE);
+            break;
+        }
+        const NodeRec nd = nodes[cur];
+        if (nd.first < 0 || nd.count < 1 || (int64_t)nd.first + nd.count > ntot) {
+            if (lane == 0) set_flag(status, BH_FLAG_TREE);
+            break;
+        }
+        const bool active = (mask >> lane) & 1ull;
+        const bool inside = (unsigned)(si - nd.first) < (unsigned)nd.count;
+        bool acc = false;
+        T gx = 0, gy = 0, gz = 0, tx = 0, ty = 0, tz = 0;
+        if (active && !inside) {
+            const double dx = rx - nd.cx, dy = ry - nd.cy, dz = rz - nd.cz;
+            const double d2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
+            acc = nd.s2 < theta2 * d2;
+            if (acc) {
+                T bx, by, bz;
+                if (MIXED) {
+                    bx = (T)nd.mx; by = (T)nd.my; bz = (T)nd.mz;
+                } else {
+                    const double *m = node_m64 + 4 * (int64_t)cur;
+                    bx = (T)m[0]; by = (T)m[1]; bz = (T)m[2];
+                }
+                adj_pair<T>((T)dx, (T)dy, (T)dz, ax, ay, az, bx, by, bz, gx, gy, gz, tx, ty, tz);
+                grx += (double)gx;
+                gry += (double)gy;
+                grz += (double)gz;
+            }
+        }
+        const uint64_t accm = __ballot(acc);
+        if (accm != 0ull) {
+            // A_C += sum T(x) Hbar over accepting lanes; B_C -= sum g
+            const double sAx = (double)wave_sum(tx), sAy = (double)wave_sum(ty), sAz = (double)wave_sum(tz);
+            const double sBx = (double)wave_sum(gx), sBy = (double)wave_sum(gy), sBz = (double)wave_sum(gz);
+            if (lane == 0) {
+                double *a = node_adj + 8 * (int64_t)cur;
+                atomic_add_d(a + 0, sAx);
+                atomic_add_d(a + 1, sAy);
+                atomic_add_d(a + 2, sAz);
+                atomic_add_d(a + 3, -sBx);
+                atomic_add_d(a + 4, -sBy);
+                atomic_add_d(a + 5, -sBz);
+            }
+        }
+        const uint64_t open = __ballot(active && !acc);
+        if (open == 0ull) continue;
+        if (nd.nchild != 0) {
+            if (st.sp >= kStackMax) {
+                if (lane == 0) set_flag(status, BH_FLAG_STACK);
+                break;
+            }
+            st.push(lane, nd.child, nd.child + nd.nchild, open);
+            continue;
+        }
+        const bool me = (open >> lane) & 1ull;
+        const int k1 = nd.first + nd.count;
+        T pgx = 0, pgy = 0, pgz = 0;
+        for (int k = nd.first; k < k1; ++k) {
+            const double sx = spos[k], sy = spos[ntot + k], sz = spos[2 * ntot + k];
+            T bx, by, bz;
+            if (MIXED) {
+                bx = smom32[k]; by = smom32[ntot + k]; bz = smom32[2 * ntot + k];
+            } else {
+                bx = smom[k]; by = smom[ntot + k]; bz = smom[2 * ntot + k];
+            }
+            T qx = 0, qy = 0, qz = 0, ux = 0, uy = 0, uz = 0;
+            if (me && k != si) {
+                const T x = (T)(rx - sx), y = (T)(ry - sy), z = (T)(rz - sz);
+                if (!(x == (T)0 && y == (T)0 && z == (T)0)) {
+                    adj_pair<T>(x, y, z, ax, ay, az, bx, by, bz, qx, qy, qz, ux, uy, uz);
+                    pgx += qx;
+                    pgy += qy;
+                    pgz += qz;
+                }
+            }
+            // dL/dr_k -= sum g, dL/dm_k += sum T(x) Hbar over the lanes
+            const double sgx = (double)wave_sum(qx), sgy = (double)wave_sum(qy), sgz = (double)wave_sum(qz);
+            const double sux = (double)wave_sum(ux), suy = (double)wave_sum(uy), suz = (double)wave_sum(uz);
+            if (lane == 0) {
+                atomic_add_d(g_r + k, -sgx);
+                atomic_add_d(g_r + ntot + k, -sgy);
+                atomic_add_d(g_r + 2 * ntot + k, -sgz);
+                atomic_add_d(g_m + k, sux);
+                atomic_add_d(g_m + ntot + k, suy);
+                atomic_add_d(g_m + 2 * ntot + k, suz);
+            }
+        }
+        grx += (double)pgx;
+        gry += (double)pgy;
+        grz += (double)pgz;
+    }
+    if (valid) {
+        g_gather[si] = grx;
+        g_gather[ntot + si] = gry;
+        g_gather[2 * ntot + si] = grz;
+    }
+}
+
+// Upstream field gradient in sorted order: Hbar = gH - 1/2 gE m.
+__global__ __launch_bounds__(256) void k_hbar(const double *__restrict__ gH, const double *__restrict__ gE,
+                                              const double *__restrict__ smom, const uint32_t *__restrict__ perm,
+                                              int64_t n, int64_t ntot, double *__restrict__ hbar)
+{
+    int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (s >= ntot) return;
+    const int64_t o = perm[s], b = o / n, i = o - b * n;
+    const double ge = gE ? gE[b] : 0.0;
+    for (int a = 0; a < 3; ++a) {
+        double v = gH ? gH[b * 3 * n + a * n + i] : 0.0;
+        v += -0.5 * ge * smom[a * ntot + s];
+        hbar[a * ntot + s] = v;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_zero(double *__restrict__ a, int64_t len)
+{
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < len; i += (int64_t)gridDim.x * 256) a[i] = 0.0;
+}
+
+// Downward pass and output: members collect their cells' adjoints along the leaf-to-root path; the
+// explicit derivative of E in m (-1/2 H - H_ext, times dL/dE) is added; results go to caller order.
+__global__ __launch_bounds__(256) void k_downward(
+    const NodeRec *__restrict__ nodes, const int32_t *__restrict__ leaf_of, const double *__restrict__ node_adj,
+    const double *__restrict__ g_gather, const double *__restrict__ g_r, const double *__restrict__ g_m,
+    const double *__restrict__ Hs, const double *__restrict__ hext, const double *__restrict__ gE,
+    const uint32_t *__restrict__ perm, int64_t n, int64_t ntot, double *__restrict__ dpos,
+    double *__restrict__ dmom)
+{
+    int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (s >= ntot) return;
+    double Ax = 0.0, Ay = 0.0, Az = 0.0, Bx = 0.0, By = 0.0, Bz = 0.0;
+    int node = leaf_of[s];
+    for (int depth = 0; node >= 0 && depth < 2 * kMaxLevel + 2; ++depth) {
+        const double *a = node_adj + 8 * (int64_t)node;
+        const double inv = 1.0 / (double)nodes[node].count;
+        Ax += a[0]; Ay += a[1]; Az += a[2];
+        Bx += a[3] * inv; By += a[4] * inv; Bz += a[5] * inv;
+        node = nodes[node].parent;
+    }
+    const int64_t o = perm[s], b = o / n, i = o - b * n;
+    const double ge = gE ? gE[b] : 0.0;
+    const double *he = hext ? hext + 3 * b : nullptr;
+    double *dp = dpos + b * 3 * n, *dm = dmom + b * 3 * n;
+    dp[i] = g_gather[s] + g_r[s] + Bx;
+    dp[n + i] = g_gather[ntot + s] + g_r[ntot + s] + By;
+    dp[2 * n + i] = g_gather[2 * ntot + s] + g_r[2 * ntot + s] + Bz;
+    double ex = -0.5 * Hs[s], ey = -0.5 * Hs[ntot + s], ez = -0.5 * Hs[2 * ntot + s];
+    if (he) { ex -= he[0]; ey -= he[1]; ez -= he[2]; }
+    dm[i] = g_m[s] + Ax + ge * ex;
+    dm[n + i] = g_m[ntot + s] + Ay + ge * ey;
+    dm[2 * n + i] = g_m[2 * ntot + s] + Az + ge * ez;
+}
+
+// dL/dH_ext = -dL/dE * sum_i m_i, one block per system.
+__global__ __launch_bounds__(1024) void k_dhext(const double *__restrict__ mom, const double *__restrict__ gE,
+                                                int64_t n, double *__restrict__ dhext)
+{
+    __shared__ double red[3][1024];
+    const int b = blockIdx.x;
+    double s[3] = {0.0, 0.0, 0.0};
+    for (int64_t i = threadIdx.x; i < n; i += 1024)
+        for (int a = 0; a < 3; ++a) s[a] += mom[(int64_t)b * 3 * n + a * n + i];
+    for (int a = 0; a < 3; ++a) red[a][threadIdx.x] = s[a];
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int a = 0; a < 3; ++a) red[a][threadIdx.x] += red[a][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < 3) dhext[3 * b + threadIdx.x] = gE ? -gE[b] * red[threadIdx.x][0] : 0.0;
+}
+
+hipError_t launch_backward(Handle &h, const double *d_mom, const double *d_hext, const double *d_gH,
+                           const double *d_gE, double *d_dpos, double *d_dmom, double *d_dhext,
+                           hipStream_t s)
+{
+    const Layout &L = h.L;
+    Workspace &w = h.w;
+    // pseudo-particle moments and the field in sorted order for the explicit term
+    hipError_t e = launch_field(h, d_mom, d_hext, w.H_scratch, nullptr, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_hbar, dim3(grid_for(L.ntot, 256)), dim3(256), 0, s, d_gH, d_gE, w.smom, w.perm, L.n,
+                       L.ntot, w.hbar);
+    hipLaunchKernelGGL(k_zero, dim3(grid_for(8 * L.max_nodes, 256, 4096)), dim3(256), 0, s, w.node_adj,
+                       8 * L.max_nodes);
+    hipLaunchKernelGGL(k_zero, dim3(grid_for(6 * L.ntot, 256, 4096)), dim3(256), 0, s, w.g_r, 6 * L.ntot);
+    const int wpb = h.waves_per_block;
+    const unsigned blocks = (unsigned)((L.num_waves + wpb - 1) / wpb);
+    const int waves_per_seg = (int)((L.n + kWave - 1) / kWave);
+    const double theta2 = h.p.theta * h.p.theta;
+    if (h.p.precision == BH_FP32_MIXED)
+        hipLaunchKernelGGL(k_adjoint<true>, dim3(blocks), dim3(wpb * kWave), 0, s, w.nodes, w.node_m64, w.spos,
+                           w.smom, w.smom32, w.hbar, w.g_gather, w.g_r, w.g_m, w.node_adj, w.status, L.n,
+                           L.ntot, waves_per_seg, (int)L.num_waves, theta2, (int)L.max_nodes);
+    else
+        hipLaunchKernelGGL(k_adjoint<false>, dim3(blocks), dim3(wpb * kWave), 0, s, w.nodes, w.node_m64, w.spos,
+                           w.smom, w.smom32, w.hbar, w.g_gather, w.g_r, w.g_m, w.node_adj, w.status, L.n,
+                           L.ntot, waves_per_seg, (int)L.num_waves, theta2, (int)L.max_nodes);
+    hipLaunchKernelGGL(k_downward, dim3(grid_for(L.ntot, 256)), dim3(256), 0, s, w.nodes, w.leaf_of, w.node_adj,
+                       w.g_gather, w.g_r, w.g_m, w.Hs, d_hext, d_gE, w.perm, L.n, L.ntot, d_dpos, d_dmom);
+    if (d_dhext)
+        hipLaunchKernelGGL(k_dhext, dim3((unsigned)L.B), dim3(1024), 0, s, d_mom, d_gE, L.n, d_dhext);
+    return hipGetLastError();
+}
+
+}  // namespace ffbh

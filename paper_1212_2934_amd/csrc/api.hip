@@ -1,0 +1,307 @@
+// C ABI of libffbh: argument checking, workspace layout, and launch sequencing.
+#include <new>
+
+#include "ffbh_internal.h"
+
+namespace ffbh {
+
+static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Traversal launch shapes selectable by tuning_id: waves per workgroup.
+static const int kTuneWaves[] = {4, 1, 2, 8};
+static const int kNumTunings = (int)(sizeof(kTuneWaves) / sizeof(kTuneWaves[0]));
+
+Layout plan_layout(const bh_params &p)
+{
+    Layout L{};
+    L.n = p.n;
+    L.B = p.batch;
+    L.ntot = L.n * L.B;
+    L.max_nodes = 2 * L.ntot + L.B;
+    L.tiles = (L.n + kSortTile - 1) / kSortTile;
+    L.hist_len = L.B * kRadixBins * L.tiles;
+    L.bin_int = L.B * (L.n - 1);
+    L.num_waves = L.B * ((L.n + kWave - 1) / kWave);
+    Workspace w{};
+    carve(L, nullptr, w);
+    return L;
+}
+
+// Carve the workspace; with base == nullptr only computes L.bytes (passed back through a const_cast).
+void carve(const Layout &Lc, void *base, Workspace &w)
+{
+    Layout &L = const_cast<Layout &>(Lc);
+    size_t off = 0;
+    char *b = (char *)base;
+    auto take = [&](size_t bytes) -> void * {
+        off = align_up(off, 256);
+        void *p = b ? (void *)(b + off) : nullptr;
+        off += bytes ? bytes : 1;
+        return p;
+    };
+    const size_t nt = (size_t)L.ntot, mn = (size_t)L.max_nodes, bi = (size_t)(L.bin_int > 0 ? L.bin_int : 1);
+    w.status = (uint32_t *)take(64);
+    w.bbox = (double *)take(8 * sizeof(double) * L.B);
+    w.bbox_part = (double *)take(6 * sizeof(double) * kBboxBlocks * L.B);
+    w.keys[0] = (uint64_t *)take(8 * nt);
+    w.keys[1] = (uint64_t *)take(8 * nt);
+    w.vals[0] = (uint32_t *)take(4 * nt);
+    w.vals[1] = (uint32_t *)take(4 * nt);
+    w.hist = (uint32_t *)take(4 * (size_t)L.hist_len);
+    w.perm = w.vals[0];
+    w.codes = w.keys[0];
+    w.spos = (double *)take(3 * 8 * nt);
+    w.smom = (double *)take(3 * 8 * nt);
+    w.smom32 = (float *)take(3 * 4 * nt);
+    w.bin_left = (int32_t *)take(4 * bi);
+    w.bin_right = (int32_t *)take(4 * bi);
+    w.bin_first = (int32_t *)take(4 * bi);
+    w.bin_last = (int32_t *)take(4 * bi);
+    w.bin_delta = (int32_t *)take(4 * bi);
+    w.bin_parent = (int32_t *)take(4 * bi);
+    w.leaf_parent = (int32_t *)take(4 * nt);
+    w.bin_nchild = (int32_t *)take(4 * bi);
+    w.bin_scan = (uint32_t *)take(4 * bi);
+    w.bin_octid = (int32_t *)take(4 * bi);
+    w.nodes = (NodeRec *)take(sizeof(NodeRec) * mn);
+    w.node_level = (int32_t *)take(4 * mn);
+    w.node_m64 = (double *)take(4 * 8 * mn);
+    w.arrive = (uint32_t *)take(4 * mn);
+    w.leaf_of = (int32_t *)take(4 * nt);
+    w.e_part = (double *)take(8 * (size_t)L.num_waves);
+    w.node_adj = (double *)take(8 * 8 * mn);
+    w.g_gather = (double *)take(3 * 8 * nt);
+    w.g_r = (double *)take(6 * 8 * nt);
+    w.g_m = w.g_r ? w.g_r + 3 * nt : nullptr;
+    w.hbar = (double *)take(3 * 8 * nt);
+    w.Hs = (double *)take(3 * 8 * nt);
+    w.H_scratch = (double *)take(3 * 8 * nt);
+    w.md_force = (double *)take(3 * 8 * nt);
+    w.md_grad_r = (double *)take(3 * 8 * nt);
+    w.md_grad_m = (double *)take(3 * 8 * nt);
+    L.bytes = align_up(off, 256);
+}
+
+static bool params_ok(const bh_params *p)
+{
+    if (!p) return false;
+    if (p->n < 1 || p->batch < 1) return false;
+    if (p->n * (int64_t)p->batch > ((int64_t)1 << 30)) return false;  // 32-bit sorted indices
+    if (p->leaf_size < 1 || p->leaf_size > 64) return false;
+    if (!(p->theta >= 0.0) || !__builtin_isfinite(p->theta)) return false;
+    if (p->precision != BH_FP64 && p->precision != BH_FP32_MIXED) return false;
+    if (p->tuning_id < -1 || p->tuning_id >= kNumTunings) return false;
+    return true;
+}
+
+static bool dptr_ok(const void *p) { return p && ((uintptr_t)p % 8) == 0; }
+
+__global__ void k_clear_status(uint32_t *status)
+{
+    if (threadIdx.x < 16) status[threadIdx.x] = 0u;
+}
+
+__global__ __launch_bounds__(256) void k_export(const NodeRec *__restrict__ nodes,
+                                                const int32_t *__restrict__ level, const uint32_t *__restrict__ nn,
+                                                int32_t *first, int32_t *count, int32_t *lev, int32_t *nchild,
+                                                int32_t *child, double *centroid)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= (int)*nn) return;
+    if (first) first[i] = nodes[i].first;
+    if (count) count[i] = nodes[i].count;
+    if (lev) lev[i] = level[i];
+    if (nchild) nchild[i] = nodes[i].nchild;
+    if (child) child[i] = nodes[i].child;
+    if (centroid) {
+        centroid[3 * i] = nodes[i].cx;
+        centroid[3 * i + 1] = nodes[i].cy;
+        centroid[3 * i + 2] = nodes[i].cz;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_copy_u32(const uint32_t *__restrict__ a, int64_t len, int32_t *__restrict__ b)
+{
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < len) b[i] = (int32_t)a[i];
+}
+
+__global__ void k_copy_bbox(const double *__restrict__ bbox, int64_t B, double *__restrict__ out)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    for (int k = 0; k < 5; ++k) out[5 * b + k] = bbox[8 * b + k];
+}
+
+}  // namespace ffbh
+
+using namespace ffbh;
+
+struct bh_handle {
+    Handle h;
+};
+
+extern "C" {
+
+bh_status bh_workspace_bytes(const bh_params *p, size_t *out_bytes)
+{
+    if (!params_ok(p) || !out_bytes) return BH_EINVAL;
+    *out_bytes = plan_layout(*p).bytes;
+    return BH_OK;
+}
+
+int32_t bh_num_tunings(void) { return kNumTunings; }
+
+uint64_t bh_morton_code(uint32_t qx, uint32_t qy, uint32_t qz)
+{
+    return morton(qx & kQMax, qy & kQMax, qz & kQMax);
+}
+
+bh_status bh_create(const bh_params *p, void *d_workspace, size_t workspace_bytes, bh_handle **out)
+{
+    if (!params_ok(p) || !out) return BH_EINVAL;
+    Layout L = plan_layout(*p);
+    if (!d_workspace || ((uintptr_t)d_workspace % 256) != 0 || workspace_bytes < L.bytes) return BH_EWORKSPACE;
+    bh_handle *hh = new (std::nothrow) bh_handle();
+    if (!hh) return BH_EDEVICE;
+    Handle &h = hh->h;
+    h.p = *p;
+    h.L = L;
+    carve(L, d_workspace, h.w);
+    if (hipGetDevice(&h.device) != hipSuccess) {
+        delete hh;
+        return BH_EDEVICE;
+    }
+    h.built = 0;
+    h.waves_per_block = kTuneWaves[p->tuning_id < 0 ? 0 : p->tuning_id];
+    h.cnt_far = h.cnt_near = nullptr;
+    hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(64), 0, 0, h.w.status);
+    if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+        delete hh;
+        return BH_EDEVICE;
+    }
+    *out = hh;
+    return BH_OK;
+}
+
+bh_status bh_destroy(bh_handle *h)
+{
+    if (!h) return BH_EINVAL;
+    delete h;
+    return BH_OK;
+}
+
+bh_status bh_build(bh_handle *hh, const double *d_pos, void *stream)
+{
+    if (!hh || !dptr_ok(d_pos)) return BH_EINVAL;
+    if (launch_build(hh->h, d_pos, (hipStream_t)stream) != hipSuccess) return BH_EDEVICE;
+    hh->h.built = 1;
+    return BH_OK;
+}
+
+bh_status bh_field(bh_handle *hh, const double *d_mom, const double *d_hext, double *d_H, double *d_E,
+                   void *stream)
+{
+    if (!hh || !dptr_ok(d_mom) || !dptr_ok(d_H)) return BH_EINVAL;
+    if ((d_hext && !dptr_ok(d_hext)) || (d_E && !dptr_ok(d_E))) return BH_EINVAL;
+    if (!hh->h.built) return BH_ESTATE;
+    if (launch_field(hh->h, d_mom, d_hext, d_H, d_E, (hipStream_t)stream) != hipSuccess) return BH_EDEVICE;
+    return BH_OK;
+}
+
+bh_status bh_field_backward(bh_handle *hh, const double *d_mom, const double *d_hext, const double *d_gH,
+                            const double *d_gE, double *d_dpos, double *d_dmom, double *d_dhext, void *stream)
+{
+    if (!hh || !dptr_ok(d_mom) || !dptr_ok(d_dpos) || !dptr_ok(d_dmom)) return BH_EINVAL;
+    if ((d_hext && !dptr_ok(d_hext)) || (d_gH && !dptr_ok(d_gH)) || (d_gE && !dptr_ok(d_gE)) ||
+        (d_dhext && !dptr_ok(d_dhext)))
+        return BH_EINVAL;
+    if (!hh->h.built) return BH_ESTATE;
+    if (launch_backward(hh->h, d_mom, d_hext, d_gH, d_gE, d_dpos, d_dmom, d_dhext, (hipStream_t)stream) !=
+        hipSuccess)
+        return BH_EDEVICE;
+    return BH_OK;
+}
+
+bh_status md_step(bh_handle *hh, const md_state *s, const md_params *p, void *stream)
+{
+    if (!hh || !s || !p) return BH_EINVAL;
+    if (!dptr_ok(s->pos) || !dptr_ok(s->vel) || !dptr_ok(s->mom) || !dptr_ok(s->omega) || !dptr_ok(s->d_step))
+        return BH_EINVAL;
+    if (!(p->dt > 0.0) || !(p->mass > 0.0) || !(p->inertia > 0.0) || !(p->kT >= 0.0) || !(p->gamma_t >= 0.0) ||
+        !(p->gamma_r >= 0.0) || !(p->wca_sigma >= 0.0) || !(p->wca_eps >= 0.0))
+        return BH_EINVAL;
+    for (int a = 0; a < 3; ++a)
+        if (!(p->box_hi[a] > p->box_lo[a])) return BH_EINVAL;
+    if (p->d_hext && !dptr_ok(p->d_hext)) return BH_EINVAL;
+    if (launch_md(hh->h, s, p, (hipStream_t)stream) != hipSuccess) return BH_EDEVICE;
+    hh->h.built = 1;
+    return BH_OK;
+}
+
+bh_status bh_check_status(bh_handle *hh, void *stream, uint32_t *flags)
+{
+    if (!hh) return BH_EINVAL;
+    uint32_t v = 0;
+    hipStream_t s = (hipStream_t)stream;
+    if (hipMemcpyAsync(&v, hh->h.w.status, sizeof(uint32_t), hipMemcpyDeviceToHost, s) != hipSuccess)
+        return BH_EDEVICE;
+    if (hipStreamSynchronize(s) != hipSuccess) return BH_EDEVICE;
+    hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(1), 0, s, hh->h.w.status);
+    if (hipGetLastError() != hipSuccess) return BH_EDEVICE;
+    if (flags) *flags = v;
+    return v ? BH_EDEGENERATE : BH_OK;
+}
+
+bh_status bh_enable_counters(bh_handle *hh, int32_t *d_n_far, int32_t *d_n_near)
+{
+    if (!hh) return BH_EINVAL;
+    if ((d_n_far == nullptr) != (d_n_near == nullptr)) return BH_EINVAL;
+    hh->h.cnt_far = d_n_far;
+    hh->h.cnt_near = d_n_near;
+    return BH_OK;
+}
+
+bh_status bh_num_nodes(bh_handle *hh, void *stream, int64_t *out_nodes)
+{
+    if (!hh || !out_nodes) return BH_EINVAL;
+    if (!hh->h.built) return BH_ESTATE;
+    uint32_t v = 0;
+    hipStream_t s = (hipStream_t)stream;
+    if (hipMemcpyAsync(&v, hh->h.w.status + 2, sizeof(uint32_t), hipMemcpyDeviceToHost, s) != hipSuccess)
+        return BH_EDEVICE;
+    if (hipStreamSynchronize(s) != hipSuccess) return BH_EDEVICE;
+    *out_nodes = v;
+    return BH_OK;
+}
+
+bh_status bh_export_tree(bh_handle *hh, int32_t *d_perm, int32_t *d_first, int32_t *d_count, int32_t *d_level,
+                         int32_t *d_nchild, int32_t *d_child_first, double *d_centroid, double *d_bbox,
+                         void *stream)
+{
+    if (!hh) return BH_EINVAL;
+    if (!hh->h.built) return BH_ESTATE;
+    Handle &h = hh->h;
+    hipStream_t s = (hipStream_t)stream;
+    if (d_perm)
+        hipLaunchKernelGGL(k_copy_u32, dim3(grid_for(h.L.ntot, 256)), dim3(256), 0, s, h.w.perm, h.L.ntot, d_perm);
+    hipLaunchKernelGGL(k_export, dim3(grid_for(h.L.max_nodes, 256)), dim3(256), 0, s, h.w.nodes, h.w.node_level,
+                       h.w.status + 2, d_first, d_count, d_level, d_nchild, d_child_first, d_centroid);
+    if (d_bbox) hipLaunchKernelGGL(k_copy_bbox, dim3(1), dim3(64), 0, s, h.w.bbox, h.L.B, d_bbox);
+    return hipGetLastError() == hipSuccess ? BH_OK : BH_EDEVICE;
+}
+
+const char *bh_status_str(bh_status s)
+{
+    switch (s) {
+    case BH_OK: return "ok";
+    case BH_EINVAL: return "invalid argument";
+    case BH_EWORKSPACE: return "workspace missing, misaligned or too small";
+    case BH_EDEVICE: return "HIP runtime error";
+    case BH_EDEGENERATE: return "device flagged degenerate input";
+    case BH_ESTATE: return "no tree built";
+    default: return "unknown status";
+    }
+}
+
+}  // extern "C"

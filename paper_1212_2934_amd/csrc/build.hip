@@ -1,0 +1,614 @@
+// Tree construction on gfx950: bounding cube, Morton codes, LDS radix sort, binary radix tree,
+// collapsed octree, and the upward pass that forms the pseudo-particles.
+//
+// Paper: Sec. 3.2 (kernels 1-4 of the GPU Barnes-Hut scheme: bounding box, octree, cell centres and
+// moments, sort by location) and Eq. (magCenter) (pseudo-particle = moment sum at the geometric
+// centre of the members).  The lock-based insertion of the paper is replaced by the binary radix tree
+// construction of T. Karras, "Maximizing parallelism in the construction of BVHs, octrees, and k-d
+// trees" (HPG 2012), collapsed to an octree with leaf size leaf_size; the spin-waiting moment kernel
+// is replaced by a lock-free last-arriver upward pass.
+#include "ffbh_internal.h"
+
+namespace ffbh {
+
+// ------------------------------------------------------------------------------------------------
+// Bounding cube: lo = componentwise minimum, side = largest extent, scale = 2^21 / side.
+// ------------------------------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_bbox_partial(const double *__restrict__ pos, int64_t n,
+                                                      double *__restrict__ part,
+                                                      uint32_t *__restrict__ status)
+{
+    __shared__ double red[6][256];
+    const int b = blockIdx.y;
+    const double *p = pos + (int64_t)b * 3 * n;
+    double mn[3], mx[3];
+    bool bad = false;
+    for (int a = 0; a < 3; ++a) { mn[a] = __builtin_inf(); mx[a] = -__builtin_inf(); }
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        for (int a = 0; a < 3; ++a) {
+            double v = p[a * n + i];
+            bad |= !__builtin_isfinite(v);
+            if (v < mn[a]) mn[a] = v;
+            if (v > mx[a]) mx[a] = v;
+        }
+    }
+    if (bad) set_flag(status, BH_FLAG_NONFINITE);
+    for (int a = 0; a < 3; ++a) { red[a][threadIdx.x] = mn[a]; red[3 + a][threadIdx.x] = mx[a]; }
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            for (int a = 0; a < 3; ++a) {
+                double o = red[a][threadIdx.x + s];
+                if (o < red[a][threadIdx.x]) red[a][threadIdx.x] = o;
+                o = red[3 + a][threadIdx.x + s];
+                if (o > red[3 + a][threadIdx.x]) red[3 + a][threadIdx.x] = o;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) part[((int64_t)b * kBboxBlocks + blockIdx.x) * 6 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ void k_bbox_final(const double *__restrict__ part, double *__restrict__ bbox)
+{
+    const int b = blockIdx.x;
+    if (threadIdx.x != 0) return;
+    double lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = part[((int64_t)b * kBboxBlocks) * 6 + a];
+        hi[a] = part[((int64_t)b * kBboxBlocks) * 6 + 3 + a];
+    }
+    for (int k = 1; k < kBboxBlocks; ++k) {
+        for (int a = 0; a < 3; ++a) {
+            double v = part[((int64_t)b * kBboxBlocks + k) * 6 + a];
+            if (v < lo[a]) lo[a] = v;
+            v = part[((int64_t)b * kBboxBlocks + k) * 6 + 3 + a];
+            if (v > hi[a]) hi[a] = v;
+        }
+    }
+    double side = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        double e = hi[a] - lo[a];
+        if (e > side) side = e;
+    }
+    double *o = bbox + 8 * b;
+    o[0] = lo[0]; o[1] = lo[1]; o[2] = lo[2];
+    o[3] = side;
+    o[4] = side > 0.0 ? 2097152.0 / side : 0.0;
+}
+
+// ------------------------------------------------------------------------------------------------
+// Morton codes: q = min(2^21-1, floor((r - lo) * scale)) per axis, interleaved x-major.
+// ------------------------------------------------------------------------------------------------
+
+__device__ inline uint32_t quantise(double r, double lo, double scale)
+{
+    double t = (r - lo) * scale;
+    double f = __builtin_floor(t);
+    if (f >= (double)kQMax) return kQMax;
+    if (f <= 0.0) return 0u;
+    return (uint32_t)f;
+}
+
+__global__ __launch_bounds__(256) void k_morton(const double *__restrict__ pos, int64_t n, int64_t ntot,
+                                                const double *__restrict__ bbox,
+                                                uint64_t *__restrict__ keys, uint32_t *__restrict__ vals)
+{
+    int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (o >= ntot) return;
+    int64_t b = o / n, i = o - b * n;
+    const double *p = pos + b * 3 * n;
+    const double *bb = bbox + 8 * b;
+    uint32_t qx = quantise(p[i], bb[0], bb[4]);
+    uint32_t qy = quantise(p[n + i], bb[1], bb[4]);
+    uint32_t qz = quantise(p[2 * n + i], bb[2], bb[4]);
+    keys[o] = morton(qx, qy, qz);
+    vals[o] = (uint32_t)o;
+}
+
+// ------------------------------------------------------------------------------------------------
+// LSD radix sort, 8-bit digits, stable, segmented by system: a tile never straddles two systems, and
+// histograms are laid out (system, digit, tile) so one exclusive scan yields every output offset.
+// ------------------------------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint64_t *__restrict__ keys, int64_t n,
+                                                             int tiles, int shift,
+                                                             uint32_t *__restrict__ hist)
+{
+    __shared__ uint32_t cnt[kRadixBins];
+    const int b = blockIdx.x / tiles, t = blockIdx.x - b * tiles;
+    const int64_t lo = (int64_t)b * n + (int64_t)t * kSortTile;
+    const int64_t hi = min(lo + (int64_t)kSortTile, (int64_t)(b + 1) * n);
+    cnt[threadIdx.x] = 0;
+    __syncthreads();
+    for (int64_t i = lo + threadIdx.x; i < hi; i += kSortThreads)
+        atomicAdd(&cnt[(keys[i] >> shift) & (kRadixBins - 1)], 1u);
+    __syncthreads();
+    hist[((int64_t)b * kRadixBins + threadIdx.x) * tiles + t] = cnt[threadIdx.x];
+}
+
+// Exclusive scan of a uint32 array in place by one workgroup (len up to a few million).
+__global__ __launch_bounds__(1024) void k_scan_excl(uint32_t *__restrict__ a, int64_t len,
+                                                   uint32_t *__restrict__ total)
+{
+    __shared__ uint32_t part[1024];
+    const int64_t chunk = (len + 1023) / 1024;
+    const int64_t lo = threadIdx.x * chunk, hi = min(lo + chunk, len);
+    uint32_t s = 0;
+    for (int64_t i = lo; i < hi; ++i) s += a[i];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        uint32_t v = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0u;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    uint32_t run = threadIdx.x ? part[threadIdx.x - 1] : 0u;
+    for (int64_t i = lo; i < hi; ++i) {
+        uint32_t v = a[i];
+        a[i] = run;
+        run += v;
+    }
+    if (threadIdx.x == 1023 && total) *total = part[1023];
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
+    const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint64_t *__restrict__ kout,
+    uint32_t *__restrict__ vout, const uint32_t *__restrict__ hist, int64_t n, int tiles, int shift)
+{
+    constexpr int kWaves = kSortThreads / kWave;
+    __shared__ uint32_t base[kRadixBins];
+    __shared__ uint32_t wcnt[kWaves][kRadixBins];
+    const int b = blockIdx.x / tiles, t = blockIdx.x - b * tiles;
+    const int64_t lo = (int64_t)b * n + (int64_t)t * kSortTile;
+    const int64_t hi = min(lo + (int64_t)kSortTile, (int64_t)(b + 1) * n);
+    const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
+    base[tid] = hist[((int64_t)b * kRadixBins + tid) * tiles + t];
+    for (int r = 0; r < kSortItems; ++r) {
+        for (int w = 0; w < kWaves; ++w) wcnt[w][tid] = 0u;
+        __syncthreads();
+        const int64_t idx = lo + (int64_t)r * kSortThreads + tid;
+        const bool valid = idx < hi;
+        uint64_t key = valid ? kin[idx] : 0ull;
+        uint32_t val = valid ? vin[idx] : 0u;
+        uint32_t d = (uint32_t)(key >> shift) & (kRadixBins - 1);
+        uint64_t m = __ballot(valid);
+#pragma unroll
+        for (int bit = 0; bit < kRadixBits; ++bit) {
+            const bool set = (d >> bit) & 1u;
+            uint64_t v = __ballot(set);
+            m &= set ? v : ~v;
+        }
+        const uint32_t before = (uint32_t)__popcll(m & lt);
+        if (valid && before == 0) wcnt[wave][d] = (uint32_t)__popcll(m);
+        __syncthreads();
+        {
+            uint32_t acc = base[tid];
+            for (int w = 0; w < kWaves; ++w) {
+                uint32_t c = wcnt[w][tid];
+                wcnt[w][tid] = acc;
+                acc += c;
+            }
+            base[tid] = acc;
+        }
+        __syncthreads();
+        if (valid) {
+            uint32_t at = wcnt[wave][d] + before;
+            kout[at] = key;
+            vout[at] = val;
+        }
+        __syncthreads();
+    }
+}
+
+// Sorted positions (SoA, global over systems).
+__global__ __launch_bounds__(256) void k_gather3(const double *__restrict__ src, const uint32_t *__restrict__ perm,
+                                                 int64_t n, int64_t ntot, double *__restrict__ dst,
+                                                 float *__restrict__ dst32, uint32_t *__restrict__ status)
+{
+    int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (s >= ntot) return;
+    int64_t o = perm[s];
+    int64_t b = o / n, i = o - b * n;
+    const double *p = src + b * 3 * n;
+    bool bad = false;
+    for (int a = 0; a < 3; ++a) {
+        double v = p[a * n + i];
+        bad |= !__builtin_isfinite(v);
+        dst[a * ntot + s] = v;
+        if (dst32) dst32[a * ntot + s] = (float)v;
+    }
+    if (bad) set_flag(status, BH_FLAG_NONFINITE);
+}
+
+// ------------------------------------------------------------------------------------------------
+// Binary radix tree (Karras 2012), one per system over its n sorted codes.  delta(i, j) is the length
+// of the common prefix of codes i and j within the 63 code bits; equal codes are told apart by their
+// sorted positions (63 + common prefix of the 32-bit positions).  Out-of-range j gives -1.
+// ------------------------------------------------------------------------------------------------
+
+__device__ inline int prefix_len(const uint64_t *k, int n, int i, int j)
+{
+    if (j < 0 || j >= n) return -1;
+    uint64_t a = k[i], c = k[j];
+    if (a == c) return 63 + __clz((unsigned)(i ^ j));
+    return __clzll((long long)(a ^ c)) - 1;
+}
+
+__global__ __launch_bounds__(256) void k_karras(const uint64_t *__restrict__ codes, int64_t n, int64_t nint_tot,
+                                                int32_t *__restrict__ left, int32_t *__restrict__ right,
+                                                int32_t *__restrict__ first, int32_t *__restrict__ last,
+                                                int32_t *__restrict__ delta, int32_t *__restrict__ bparent,
+                                                int32_t *__restrict__ lparent)
+{
+    int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (g >= nint_tot) return;
+    const int nn = (int)n;
+    const int64_t b = g / (n - 1);
+    const int i = (int)(g - b * (n - 1));
+    const uint64_t *k = codes + b * n;
+    const int d = (prefix_len(k, nn, i, i + 1) - prefix_len(k, nn, i, i - 1)) > 0 ? 1 : -1;
+    const int dmin = prefix_len(k, nn, i, i - d);
+    int lmax = 2;
+    while (prefix_len(k, nn, i, i + lmax * d) > dmin) lmax <<= 1;
+    int l = 0;
+    for (int t = lmax >> 1; t >= 1; t >>= 1)
+        if (prefix_len(k, nn, i, i + (l + t) * d) > dmin) l += t;
+    const int j = i + l * d;
+    const int dnode = prefix_len(k, nn, i, j);
+    int s = 0;
+    for (int div = 2;; div <<= 1) {
+        const int t = (l + div - 1) / div;
+        if (prefix_len(k, nn, i, i + (s + t) * d) > dnode) s += t;
+        if (t <= 1) break;
+    }
+    const int gamma = i + s * d + min(d, 0);
+    const int lo = min(i, j), hi = max(i, j);
+    const int64_t ib = b * (n - 1), lb = b * n;
+    int32_t L, R;
+    if (lo == gamma) { L = ~gamma; lparent[lb + gamma] = i; }
+    else { L = gamma; bparent[ib + gamma] = i; }
+    if (hi == gamma + 1) { R = ~(gamma + 1); lparent[lb + gamma + 1] = i; }
+    else { R = gamma + 1; bparent[ib + gamma + 1] = i; }
+    left[g] = L;
+    right[g] = R;
+    first[g] = lo;
+    last[g] = hi;
+    delta[g] = dnode;
+    if (i == 0) bparent[ib] = -1;
+}
+
+// ------------------------------------------------------------------------------------------------
+// Octree from the binary tree.  A binary node whose members share 3*l but no more code bits has its
+// deepest common cell at level lev = min(21, delta / 3).  It starts a new octree cell iff its level
+// exceeds its binary parent's; a run of unary cells is stored once, at its deepest level, which
+// leaves every pseudo-particle and every acceptance decision unchanged (a unary parent has the same
+// members and a larger side).  A cell is in the tree iff its octree parent is internal
+// (count > leaf_size and level < 21).  Leaves sit at the top of their run (they are not split).
+// ------------------------------------------------------------------------------------------------
+
+__device__ inline int bin_level(const int32_t *delta, int64_t g)
+{
+    int l = delta[g] / 3;
+    return l > kMaxLevel ? kMaxLevel : l;
+}
+
+__global__ __launch_bounds__(256) void k_oct_count(int64_t n, int64_t nint_tot, int leaf,
+                                                   const int32_t *__restrict__ left,
+                                                   const int32_t *__restrict__ right,
+                                                   const int32_t *__restrict__ first,
+                                                   const int32_t *__restrict__ last,
+                                                   const int32_t *__restrict__ delta,
+                                                   const int32_t *__restrict__ bparent,
+                                                   int32_t *__restrict__ nchild, uint32_t *__restrict__ scan_in,
+                                                   uint32_t *__restrict__ status)
+{
+    int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (g >= nint_tot) return;
+    const int64_t b = g / (n - 1), ib = b * (n - 1);
+    const int lev = bin_level(delta, g);
+    const int cnt = last[g] - first[g] + 1;
+    int out = 0;
+    // is this node the deepest cell of an octree run, and is that cell in the tree?
+    const int p = bparent[g];
+    bool in_tree;
+    if (p < 0) {
+        in_tree = true;
+    } else if (lev <= bin_level(delta, ib + p)) {
+        in_tree = false;  // an intermediate binary split inside one octant digit
+    } else {
+        // octree parent: nearest binary ancestor that starts a cell
+        int x = p;
+        while (true) {
+            const int px = bparent[ib + x];
+            if (px < 0 || bin_level(delta, ib + x) > bin_level(delta, ib + px)) break;
+            x = px;
+        }
+        const int pc = last[ib + x] - first[ib + x] + 1;
+        in_tree = pc > leaf && bin_level(delta, ib + x) < kMaxLevel;
+    }
+    if (in_tree && cnt > leaf) {
+        if (lev >= kMaxLevel) {
+            set_flag(status, BH_FLAG_DEEP_LEAF);
+        } else {
+            // children: walk the binary subtree down to the nodes that start the next cells
+            int32_t stk[8];
+            int sp = 0;
+            stk[sp++] = right[g];
+            stk[sp++] = left[g];
+            while (sp > 0) {
+                const int32_t c = stk[--sp];
+                if (c < 0 || bin_level(delta, ib + c) > lev) {
+                    ++out;
+                } else {
+                    stk[sp++] = right[ib + c];
+                    stk[sp++] = left[ib + c];
+                }
+            }
+        }
+    }
+    nchild[g] = out;
+    scan_in[g] = (uint32_t)out;
+}
+
+// Write the records of the children of every in-tree internal node (and of the roots).
+__device__ inline void write_leaf_of(int32_t *leaf_of, int64_t first, int cnt, int id)
+{
+    for (int k = 0; k < cnt; ++k) leaf_of[first + k] = id;
+}
+
+__global__ __launch_bounds__(256) void k_oct_emit(int64_t n, int64_t nint_tot, int64_t B, int leaf,
+                                                  const int32_t *__restrict__ left,
+                                                  const int32_t *__restrict__ right,
+                                                  const int32_t *__restrict__ first,
+                                                  const int32_t *__restrict__ last,
+                                                  const int32_t *__restrict__ delta,
+                                                  const int32_t *__restrict__ nchild,
+                                                  const uint32_t *__restrict__ scan,
+                                                  NodeRec *__restrict__ nodes, int32_t *__restrict__ node_level,
+                                                  uint32_t *__restrict__ arrive, int32_t *__restrict__ leaf_of,
+                                                  int32_t *__restrict__ octid, uint32_t *__restrict__ status)
+{
+    int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (g == 0) status[2] = (uint32_t)B + (nint_tot > 0 ? status[1] : 0u);  // number of nodes
+    // roots: one thread per system (threads g < B); node b is the root of system b
+    if (g < B) {
+        const int64_t b = g;
+        NodeRec r{};
+        r.first = (int32_t)(b * n);
+        r.count = (int32_t)n;
+        r.parent = -1;
+        r.child = -1;
+        r.nchild = 0;
+        int lev = 0;
+        if (n > 1 && n > leaf) {
+            const int64_t rg = b * (n - 1);
+            lev = bin_level(delta, rg);  // deepest cell of the root's run (kMaxLevel: one deep leaf)
+            if (nchild[rg] > 0) {
+                r.child = (int32_t)(B + scan[rg]);
+                r.nchild = nchild[rg];
+            }
+            octid[rg] = (int32_t)b;
+        }
+        if (r.nchild == 0) write_leaf_of(leaf_of, b * n, (int)n, (int)b);
+        nodes[b] = r;
+        node_level[b] = lev;
+        arrive[b] = 0u;
+    }
+    if (g >= nint_tot) return;
+    const int nc = nchild[g];
+    if (nc == 0) return;
+    const int64_t b = g / (n - 1), ib = b * (n - 1);
+    const int lev = bin_level(delta, g);
+    int id = (int)(B + scan[g]);
+    int32_t stk[8];
+    int sp = 0;
+    stk[sp++] = right[g];
+    stk[sp++] = left[g];
+    while (sp > 0) {
+        const int32_t c = stk[--sp];
+        const bool particle = c < 0;
+        if (particle || bin_level(delta, ib + c) > lev) {
+            NodeRec r{};
+            int cf, cc, clev;
+            int ch = -1, cn = 0;
+            if (particle) {
+                cf = ~c; cc = 1; clev = lev + 1;
+            } else {
+                const int64_t cg = ib + c;
+                cf = first[cg];
+                cc = last[cg] - first[cg] + 1;
+                if (cc > leaf) {
+                    clev = bin_level(delta, cg);  // deepest cell of the run; kMaxLevel for a deep leaf
+                    if (nchild[cg] > 0) {
+                        ch = (int)(B + scan[cg]);
+                        cn = nchild[cg];
+                    }
+                } else {
+                    clev = lev + 1;  // a leaf is the first cell of its run
+                }
+                octid[cg] = id;
+            }
+            r.first = (int32_t)(b * n + cf);
+            r.count = cc;
+            r.child = ch;
+            r.nchild = cn;
+            r.parent = -1;  // set by k_oct_link
+            nodes[id] = r;
+            node_level[id] = clev;
+            arrive[id] = 0u;
+            if (cn == 0) write_leaf_of(leaf_of, b * n + cf, cc, id);
+            ++id;
+        } else {
+            stk[sp++] = right[ib + c];
+            stk[sp++] = left[ib + c];
+        }
+    }
+}
+
+// Parent links: every in-tree internal node stamps its id into its children.
+__global__ __launch_bounds__(256) void k_oct_link(int64_t nint_tot, int64_t B, const int32_t *__restrict__ nchild,
+                                                  const uint32_t *__restrict__ scan,
+                                                  const int32_t *__restrict__ octid, NodeRec *__restrict__ nodes)
+{
+    int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (g >= nint_tot) return;
+    const int nc = nchild[g];
+    if (nc == 0) return;
+    const int self = octid[g];
+    const int c0 = (int)(B + scan[g]);
+    for (int q = 0; q < nc; ++q) nodes[c0 + q].parent = self;
+}
+
+// ------------------------------------------------------------------------------------------------
+// Upward pass.  A leaf sums its members in sorted order from +0.0; the last child to arrive at a parent
+// sums the children's sums in octant order (the order they are stored in).  Arrival counters are
+// compared modulo the child count, so repeated passes need no reset.
+//   MODE 0: positions -> centroid S / count and squared side into the node record.
+//   MODE 1: moments   -> FP64 moment sum into node_m64 and its FP32 rounding into the record.
+// ------------------------------------------------------------------------------------------------
+
+template <int MODE>
+__device__ inline void finish_node(NodeRec *nodes, double *sums, double *node_m64,
+                                   const int32_t *node_level, int id, const double *bbox_b)
+{
+    const double sx = sums[4 * id], sy = sums[4 * id + 1], sz = sums[4 * id + 2];
+    if (MODE == 0) {
+        const double c = (double)nodes[id].count;
+        nodes[id].cx = sx / c;
+        nodes[id].cy = sy / c;
+        nodes[id].cz = sz / c;
+        const double s = __builtin_ldexp(bbox_b[3], -node_level[id]);
+        nodes[id].s2 = s * s;
+    } else {
+        node_m64[4 * id] = sx;
+        node_m64[4 * id + 1] = sy;
+        node_m64[4 * id + 2] = sz;
+        nodes[id].mx = (float)sx;
+        nodes[id].my = (float)sy;
+        nodes[id].mz = (float)sz;
+    }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_upward(const double *__restrict__ vals, int64_t ntot, int64_t n,
+                                                NodeRec *nodes, double *sums, double *node_m64,
+                                                const int32_t *__restrict__ node_level, uint32_t *arrive,
+                                                const uint32_t *__restrict__ num_nodes,
+                                                const double *__restrict__ bbox, int64_t max_nodes)
+{
+    const int id0 = blockIdx.x * 256 + threadIdx.x;
+    if (id0 >= (int)*num_nodes || id0 >= max_nodes) return;
+    if (nodes[id0].nchild != 0) return;
+    const int first = nodes[id0].first, cnt = nodes[id0].count;
+    const double *bb = bbox + 8 * (first / n);
+    double sx = 0.0, sy = 0.0, sz = 0.0;
+    for (int k = first; k < first + cnt; ++k) {
+        sx = sx + vals[k];
+        sy = sy + vals[ntot + k];
+        sz = sz + vals[2 * ntot + k];
+    }
+    sums[4 * id0] = sx;
+    sums[4 * id0 + 1] = sy;
+    sums[4 * id0 + 2] = sz;
+    finish_node<MODE>(nodes, sums, node_m64, node_level, id0, bb);
+    int id = id0;
+    for (int depth = 0; depth < 2 * kMaxLevel + 2; ++depth) {  // a leaf has at most 22 ancestors
+        const int p = nodes[id].parent;
+        if (p < 0) break;
+        const uint32_t nc = (uint32_t)nodes[p].nchild;
+        const uint32_t prev = __hip_atomic_fetch_add(&arrive[p], 1u, __ATOMIC_ACQ_REL,
+                                                     __HIP_MEMORY_SCOPE_AGENT);
+        if ((prev + 1u) % nc != 0u) break;
+        const int c0 = nodes[p].child;
+        double ax = 0.0, ay = 0.0, az = 0.0;
+        for (uint32_t q = 0; q < nc; ++q) {
+            const int c = c0 + (int)q;
+            ax = ax + __hip_atomic_load(&sums[4 * c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            ay = ay + __hip_atomic_load(&sums[4 * c + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            az = az + __hip_atomic_load(&sums[4 * c + 2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        sums[4 * p] = ax;
+        sums[4 * p + 1] = ay;
+        sums[4 * p + 2] = az;
+        finish_node<MODE>(nodes, sums, node_m64, node_level, p, bb);
+        id = p;
+    }
+}
+
+// ------------------------------------------------------------------------------------------------
+// Host launch sequences
+// ------------------------------------------------------------------------------------------------
+
+#define FFBH_TRY(x)                         \
+    do {                                    \
+        hipError_t e_ = (x);                \
+        if (e_ != hipSuccess) return e_;    \
+    } while (0)
+
+hipError_t launch_build(Handle &h, const double *d_pos, hipStream_t s)
+{
+    const Layout &L = h.L;
+    Workspace &w = h.w;
+    const int64_t n = L.n, B = L.B, ntot = L.ntot;
+    hipLaunchKernelGGL(k_bbox_partial, dim3(kBboxBlocks, (unsigned)B), dim3(256), 0, s, d_pos, n,
+                       w.bbox_part, w.status);
+    hipLaunchKernelGGL(k_bbox_final, dim3((unsigned)B), dim3(64), 0, s, w.bbox_part, w.bbox);
+    hipLaunchKernelGGL(k_morton, dim3(grid_for(ntot, 256)), dim3(256), 0, s, d_pos, n, ntot, w.bbox,
+                       w.keys[0], w.vals[0]);
+    const int tiles = (int)L.tiles;
+    const unsigned sblocks = (unsigned)(B * tiles);
+    for (int pass = 0; pass < kRadixPasses; ++pass) {
+        const int src = pass & 1, dst = src ^ 1;
+        const int shift = pass * kRadixBits;
+        hipLaunchKernelGGL(k_radix_hist, dim3(sblocks), dim3(kSortThreads), 0, s, w.keys[src], n, tiles,
+                           shift, w.hist);
+        hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, s, w.hist, (int64_t)L.hist_len,
+                           (uint32_t *)nullptr);
+        hipLaunchKernelGGL(k_radix_scatter, dim3(sblocks), dim3(kSortThreads), 0, s, w.keys[src],
+                           w.vals[src], w.keys[dst], w.vals[dst], w.hist, n, tiles, shift);
+    }
+    // kRadixPasses is even: the sorted data is back in buffer 0
+    hipLaunchKernelGGL(k_gather3, dim3(grid_for(ntot, 256)), dim3(256), 0, s, d_pos, w.perm, n, ntot,
+                       w.spos, (float *)nullptr, w.status);
+    const int64_t nint = L.bin_int;  // B * (n - 1)
+    if (nint > 0) {
+        hipLaunchKernelGGL(k_karras, dim3(grid_for(nint, 256)), dim3(256), 0, s, w.codes, n, nint,
+                           w.bin_left, w.bin_right, w.bin_first, w.bin_last, w.bin_delta, w.bin_parent,
+                           w.leaf_parent);
+        hipLaunchKernelGGL(k_oct_count, dim3(grid_for(nint, 256)), dim3(256), 0, s, n, nint,
+                           (int)h.p.leaf_size, w.bin_left, w.bin_right, w.bin_first, w.bin_last,
+                           w.bin_delta, w.bin_parent, w.bin_nchild, w.bin_scan, w.status);
+        hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, s, w.bin_scan, nint, w.status + 1);
+    }
+    hipLaunchKernelGGL(k_oct_emit, dim3(grid_for(nint > B ? nint : B, 256)), dim3(256), 0, s, n, nint, B,
+                       (int)h.p.leaf_size, w.bin_left, w.bin_right, w.bin_first, w.bin_last, w.bin_delta,
+                       w.bin_nchild, w.bin_scan, w.nodes, w.node_level, w.arrive, w.leaf_of, w.bin_octid,
+                       w.status);
+    if (nint > 0)
+        hipLaunchKernelGGL(k_oct_link, dim3(grid_for(nint, 256)), dim3(256), 0, s, nint, B,
+                           w.bin_nchild, w.bin_scan, w.bin_octid, w.nodes);
+    hipLaunchKernelGGL(k_upward<0>, dim3(grid_for(L.max_nodes, 256)), dim3(256), 0, s, w.spos, ntot, n,
+                       w.nodes, w.node_adj, w.node_m64, w.node_level, w.arrive, w.status + 2, w.bbox, L.max_nodes);
+    return hipGetLastError();
+}
+
+}  // namespace ffbh
+
+namespace ffbh {
+
+hipError_t launch_upward_moments(Handle &h, const double *d_mom, hipStream_t s)
+{
+    const Layout &L = h.L;
+    Workspace &w = h.w;
+    hipLaunchKernelGGL(k_gather3, dim3(grid_for(L.ntot, 256)), dim3(256), 0, s, d_mom, w.perm, L.n,
+                       L.ntot, w.smom, w.smom32, w.status);
+    hipLaunchKernelGGL(k_upward<1>, dim3(grid_for(L.max_nodes, 256)), dim3(256), 0, s, w.smom, L.ntot,
+                       L.n, w.nodes, w.node_adj, w.node_m64, w.node_level, w.arrive, w.status + 2, w.bbox, L.max_nodes);
+    return hipGetLastError();
+}
+
+}  // namespace ffbh

@@ -1,0 +1,145 @@
+// Internal declarations of libffbh (gfx950).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+#include "../../include/ffbh.h"
+
+namespace ffbh {
+
+constexpr int kBits = 21;                       // quantisation bits per axis
+constexpr uint32_t kQMax = (1u << kBits) - 1u;  // largest quantised coordinate
+constexpr int kMaxLevel = 21;                   // deepest cell level
+constexpr int kWave = 64;                       // CDNA wavefront width
+constexpr int kRadixBits = 8;
+constexpr int kRadixBins = 1 << kRadixBits;
+constexpr int kRadixPasses = 8;                 // 8 x 8 bits cover the 63-bit codes
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 16;                  // keys per thread per tile
+constexpr int kSortTile = kSortThreads * kSortItems;
+constexpr int kStackMax = 64;                   // one traversal stack entry per lane of a wave
+
+// Node record read by the traversal: one 64-byte line, fetched with a single scalar load.
+struct alignas(64) NodeRec {
+    double cx, cy, cz;  // pseudo-particle position (geometric centre of the members)
+    double s2;          // squared side of the cell's cube
+    float mx, my, mz;   // moment sum rounded to FP32 (mixed-precision traversal)
+    int32_t first;      // first member, global sorted position
+    int32_t count;      // number of members
+    int32_t child;      // first child node (children contiguous, octant order); -1 for a leaf
+    int32_t nchild;     // 0 for a leaf
+    int32_t parent;     // -1 for a root
+};
+static_assert(sizeof(NodeRec) == 64, "node record must be one 64-byte line");
+
+// Device workspace, carved from the caller's buffer.  All arrays are global over the B systems.
+struct Workspace {
+    uint32_t *status;        // [0] flags, [1] node count, [2..] scratch counters
+    double *bbox;            // B x 8: lo xyz, side, scale, (pad)
+    double *bbox_part;       // B x kBboxBlocks x 6 partial min/max
+    uint64_t *keys[2];       // N_tot sort keys (ping-pong)
+    uint32_t *vals[2];       // N_tot sort values: global original index (ping-pong)
+    uint32_t *hist;          // radix histograms (B x 256 x tiles_per_system)
+    uint32_t *perm;          // sorted position -> global original index (alias of the final vals)
+    uint64_t *codes;         // sorted codes (alias of the final keys)
+    double *spos;            // 3 x N_tot sorted positions (SoA: x block, y block, z block)
+    double *smom;            // 3 x N_tot sorted moments FP64
+    float *smom32;           // 3 x N_tot sorted moments FP32
+    // binary radix tree (per system: n-1 internal nodes, n leaves)
+    int32_t *bin_left;       // internal node -> left child (>= 0 internal, < 0: leaf ~idx)
+    int32_t *bin_right;
+    int32_t *bin_first;      // range of an internal node (segment-local sorted positions)
+    int32_t *bin_last;
+    int32_t *bin_delta;      // common prefix length in bits (63 + x for equal codes)
+    int32_t *bin_parent;     // internal node -> parent internal node (-1 root)
+    int32_t *leaf_parent;    // sorted particle -> parent internal node (-1 if n == 1)
+    int32_t *bin_nchild;     // octree children of an internal node (0 if not an in-tree internal)
+    uint32_t *bin_scan;      // exclusive scan of bin_nchild
+    // octree
+    int32_t *bin_octid;      // internal node -> octree node id (in-tree internal nodes only)
+    NodeRec *nodes;          // max_nodes
+    int32_t *node_level;     // max_nodes: cell level (side = side_root / 2^level)
+    double *node_m64;        // 4 x max_nodes: moment sum FP64 (x, y, z, pad) per node
+    uint32_t *arrive;        // max_nodes: upward-pass arrival counters
+    int32_t *leaf_of;        // N_tot: sorted particle -> its leaf
+    // traversal outputs and adjoint accumulators
+    double *e_part;          // per wave energy partials
+    double *node_adj;        // 8 x max_nodes: A (3), B (3) per node, padded; also upward-pass sums
+    double *g_gather;        // 3 x N_tot: per-target gathered position adjoint (sorted order)
+    double *g_r;             // 3 x N_tot: scattered position adjoint (sorted order)
+    double *g_m;             // 3 x N_tot: scattered moment adjoint (sorted order), follows g_r
+    double *hbar;            // 3 x N_tot: upstream field gradient (sorted order)
+    double *Hs;              // 3 x N_tot: field in sorted order
+    double *H_scratch;       // B x 3 x n: field in caller order when the caller does not want it
+    double *md_force;        // 3 x N_tot: short-range forces (caller order) for the MD step
+    double *md_grad_r;       // B x 3 x n
+    double *md_grad_m;       // B x 3 x n
+};
+
+constexpr int kBboxBlocks = 64;
+
+struct Layout {
+    int64_t n, B, ntot, max_nodes, tiles, num_waves, hist_len, bin_int;
+    size_t bytes;
+};
+
+Layout plan_layout(const bh_params &p);
+void carve(const Layout &L, void *base, Workspace &w);
+
+// Host-side handle.
+struct Handle {
+    bh_params p;
+    Layout L;
+    Workspace w;
+    int device;
+    int built;           // a bh_build has been enqueued
+    int waves_per_block; // traversal launch shape
+    int32_t *cnt_far, *cnt_near;  // optional per-target counters (device)
+};
+
+// ---- shared device helpers -----------------------------------------------------------------------
+
+__host__ __device__ inline uint64_t spread3(uint32_t v)
+{
+    // Spread the low 21 bits of v so that bit k moves to bit 3k.
+    uint64_t x = v & 0x1fffffu;
+    x = (x | (x << 32)) & 0x001f00000000ffffull;
+    x = (x | (x << 16)) & 0x001f0000ff0000ffull;
+    x = (x | (x << 8)) & 0x100f00f00f00f00full;
+    x = (x | (x << 4)) & 0x10c30c30c30c30c3ull;
+    x = (x | (x << 2)) & 0x1249249249249249ull;
+    return x;
+}
+
+__host__ __device__ inline uint64_t morton(uint32_t qx, uint32_t qy, uint32_t qz)
+{
+    return (spread3(qx) << 2) | (spread3(qy) << 1) | spread3(qz);
+}
+
+__device__ inline void set_flag(uint32_t *status, uint32_t bit)
+{
+    atomicOr(status, bit);
+}
+
+inline unsigned grid_for(int64_t work, int threads, int64_t cap = (int64_t)1 << 30)
+{
+    int64_t g = (work + threads - 1) / threads;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (unsigned)g;
+}
+
+// Launch helpers implemented per source file.
+hipError_t launch_build(Handle &h, const double *d_pos, hipStream_t s);
+hipError_t launch_upward_moments(Handle &h, const double *d_mom, hipStream_t s);
+hipError_t launch_field(Handle &h, const double *d_mom, const double *d_hext, double *d_H,
+                        double *d_E, hipStream_t s);
+hipError_t launch_backward(Handle &h, const double *d_mom, const double *d_hext, const double *d_gH,
+                           const double *d_gE, double *d_dpos, double *d_dmom, double *d_dhext,
+                           hipStream_t s);
+hipError_t launch_md(Handle &h, const md_state *st, const md_params *mp, hipStream_t s);
+
+}  // namespace ffbh

@@ -1,0 +1,192 @@
+// Device building blocks shared by the forward and adjoint traversals (gfx950, wave64).
+#pragma once
+
+#include "ffbh_internal.h"
+
+namespace ffbh {
+
+// 1/sqrt(a) in FP64: hardware estimate refined by two Newton steps y <- y + y (1 - a y^2) / 2.
+__device__ inline double rsqrt64(double a)
+{
+    double y = __builtin_amdgcn_rsq(a);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const double t = a * y;
+        const double r = __builtin_fma(-t, y, 1.0);
+        y = __builtin_fma(0.5 * y, r, y);
+    }
+    return y;
+}
+
+// Field of dipole m at offset x (target minus source), Eq. (H_dip) rearranged as
+// h = (3 (m.x) x / |x|^2 - m) / |x|^3, accumulated into h.
+template <typename T>
+__device__ inline void dip_acc(T x, T y, T z, T mx, T my, T mz, T &hx, T &hy, T &hz);
+
+template <>
+__device__ inline void dip_acc<double>(double x, double y, double z, double mx, double my, double mz,
+                                       double &hx, double &hy, double &hz)
+{
+    const double r2 = __builtin_fma(z, z, __builtin_fma(y, y, x * x));
+    const double ri = rsqrt64(r2);
+    const double ri2 = ri * ri;
+    const double ri3 = ri2 * ri;
+    const double md = __builtin_fma(mz, z, __builtin_fma(my, y, mx * x));
+    const double t = 3.0 * md * ri2;
+    hx = __builtin_fma(__builtin_fma(t, x, -mx), ri3, hx);
+    hy = __builtin_fma(__builtin_fma(t, y, -my), ri3, hy);
+    hz = __builtin_fma(__builtin_fma(t, z, -mz), ri3, hz);
+}
+
+template <>
+__device__ inline void dip_acc<float>(float x, float y, float z, float mx, float my, float mz, float &hx,
+                                      float &hy, float &hz)
+{
+    const float r2 = __builtin_fmaf(z, z, __builtin_fmaf(y, y, x * x));
+    const float ri = __builtin_amdgcn_rsqf(r2);
+    const float ri2 = ri * ri;
+    const float ri3 = ri2 * ri;
+    const float md = __builtin_fmaf(mz, z, __builtin_fmaf(my, y, mx * x));
+    const float t = 3.0f * md * ri2;
+    hx = __builtin_fmaf(__builtin_fmaf(t, x, -mx), ri3, hx);
+    hy = __builtin_fmaf(__builtin_fmaf(t, y, -my), ri3, hy);
+    hz = __builtin_fmaf(__builtin_fmaf(t, z, -mz), ri3, hz);
+}
+
+// Adjoint pair: with a = upstream field gradient of the target, b = source moment, x = offset,
+//   g  = 3 [ (a.b) x + (b.x) a + (a.x) b ] / |x|^5 - 15 (a.x)(b.x) x / |x|^7   (f_dip summand, Sec. 2)
+//   ta = T(x) a = (3 (a.x) x / |x|^2 - a) / |x|^3                                (T symmetric)
+template <typename T>
+__device__ inline void adj_pair(T x, T y, T z, T ax, T ay, T az, T bx, T by, T bz, T &gx, T &gy, T &gz,
+                                T &tx, T &ty, T &tz);
+
+template <typename T>
+__device__ inline T fmaT(T a, T b, T c);
+template <>
+__device__ inline double fmaT<double>(double a, double b, double c) { return __builtin_fma(a, b, c); }
+template <>
+__device__ inline float fmaT<float>(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+template <typename T>
+__device__ inline T rsqT(T a);
+template <>
+__device__ inline double rsqT<double>(double a) { return rsqrt64(a); }
+template <>
+__device__ inline float rsqT<float>(float a) { return __builtin_amdgcn_rsqf(a); }
+
+template <typename T>
+__device__ inline void adj_pair(T x, T y, T z, T ax, T ay, T az, T bx, T by, T bz, T &gx, T &gy, T &gz,
+                                T &tx, T &ty, T &tz)
+{
+    const T r2 = fmaT<T>(z, z, fmaT<T>(y, y, x * x));
+    const T ri = rsqT<T>(r2);
+    const T ri2 = ri * ri;
+    const T ri3 = ri2 * ri;
+    const T ri5 = ri3 * ri2;
+    const T adx = fmaT<T>(az, z, fmaT<T>(ay, y, ax * x));
+    const T bdx = fmaT<T>(bz, z, fmaT<T>(by, y, bx * x));
+    const T ab = fmaT<T>(az, bz, fmaT<T>(ay, by, ax * bx));
+    // g = 3 ri5 [ (ab - 5 adx bdx ri2) x + bdx a + adx b ]
+    const T c0 = fmaT<T>((T)-5 * adx * bdx, ri2, ab);
+    const T s = (T)3 * ri5;
+    gx = s * fmaT<T>(c0, x, fmaT<T>(bdx, ax, adx * bx));
+    gy = s * fmaT<T>(c0, y, fmaT<T>(bdx, ay, adx * by));
+    gz = s * fmaT<T>(c0, z, fmaT<T>(bdx, az, adx * bz));
+    // T(x) a
+    const T t = (T)3 * adx * ri2;
+    tx = fmaT<T>(t, x, -ax) * ri3;
+    ty = fmaT<T>(t, y, -ay) * ri3;
+    tz = fmaT<T>(t, z, -az) * ri3;
+}
+
+// ---- wave64 reductions (DPP) ---------------------------------------------------------------------
+
+template <int CTRL>
+__device__ inline float dpp_f(float v)
+{
+    // bound_ctrl: lanes whose source is out of range read 0
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, true));
+}
+
+// Sum of v over all 64 lanes, returned uniformly (must be called with every lane active).
+__device__ inline float wave_sum(float v)
+{
+    v += dpp_f<0xb1>(v);   // quad_perm [1,0,3,2]
+    v += dpp_f<0x4e>(v);   // quad_perm [2,3,0,1]
+    v += dpp_f<0x141>(v);  // row_half_mirror
+    v += dpp_f<0x140>(v);  // row_mirror: every lane of a row now holds the row's sum
+    const float a = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
+    const float b = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
+    const float c = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
+    const float d = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
+    return (a + b) + (c + d);
+}
+
+template <int CTRL>
+__device__ inline double dpp_d(double v)
+{
+    const long long bits = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(bits & 0xffffffff), CTRL, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(bits >> 32), CTRL, 0xf, 0xf, true);
+    return __longlong_as_double(((long long)(unsigned)lo) | ((long long)hi << 32));
+}
+
+__device__ inline double readlane_d(double v, int lane)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)(unsigned)lo) | ((long long)hi << 32));
+}
+
+__device__ inline double wave_sum(double v)
+{
+    v += dpp_d<0xb1>(v);
+    v += dpp_d<0x4e>(v);
+    v += dpp_d<0x141>(v);
+    v += dpp_d<0x140>(v);
+    const double a = readlane_d(v, 0), b = readlane_d(v, 16), c = readlane_d(v, 32), d = readlane_d(v, 48);
+    return (a + b) + (c + d);
+}
+
+// Logical block index, arranged so that each of the 8 XCDs (which receive workgroups round-robin)
+// works on one contiguous range of Morton-ordered targets and keeps those nodes in its own L2.
+__device__ inline int xcd_block(int bid, int nb)
+{
+    const int q = nb >> 3, r = nb & 7;
+    const int x = bid & 7, k = bid >> 3;
+    return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+}
+
+// Traversal stack held in VGPRs: entry e lives in lane e of four registers (node range [cur, end)
+// and the 64-bit lane mask).  Push and pop run in wave-uniform control flow with every lane active:
+// a push selects lane sp, a pop reads lane sp-1 into scalars with v_readlane.
+struct LaneStack {
+    int cur, end, mlo, mhi;
+    int sp;
+
+    __device__ inline void push(int lane, int c, int e, uint64_t m)
+    {
+        const bool here = lane == sp;
+        cur = here ? c : cur;
+        end = here ? e : end;
+        mlo = here ? (int)(uint32_t)m : mlo;
+        mhi = here ? (int)(uint32_t)(m >> 32) : mhi;
+        ++sp;
+    }
+    // Take the next node of the top range; returns its index and lane mask.
+    __device__ inline int pop(int lane, uint64_t &m)
+    {
+        const int top = sp - 1;
+        const int c = __builtin_amdgcn_readlane(cur, top);
+        const int e = __builtin_amdgcn_readlane(end, top);
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane(mlo, top);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane(mhi, top);
+        m = ((uint64_t)hi << 32) | lo;
+        if (c + 1 < e) cur = (lane == top) ? c + 1 : cur;
+        else sp = top;
+        return c;
+    }
+};
+
+}  // namespace ffbh

@@ -1,0 +1,43 @@
+"""Helpers for the GPU parity tests: run the library on a workload, error metrics against the oracle."""
+import numpy as np
+import torch
+
+from paper_1212_2934_amd.binding import BarnesHut
+
+
+def run_field(pos, mom, hext=None, theta=0.5, leaf=16, precision="fp64", counters=True, tuning_id=-1):
+    """Build + field through the C ABI.  pos/mom (3, n) or (B, 3, n) numpy; returns numpy results."""
+    batched = pos.ndim == 3
+    B = pos.shape[0] if batched else 1
+    n = pos.shape[-1]
+    bh = BarnesHut(n, B, leaf, theta, precision, tuning_id=tuning_id)
+    p = torch.from_numpy(np.ascontiguousarray(pos)).cuda()
+    m = torch.from_numpy(np.ascontiguousarray(mom)).cuda()
+    he = None if hext is None else torch.from_numpy(np.ascontiguousarray(hext, dtype=np.float64)).cuda()
+    bh.build(p)
+    cnt = bh.enable_counters() if counters else None
+    H, E = bh.field(m, he)
+    flags = bh.check_status()
+    out = dict(H=H.cpu().numpy(), E=E.cpu().numpy(), flags=flags, bh=bh)
+    if cnt is not None:
+        out["n_far"] = cnt[0].cpu().numpy().reshape(pos.shape[0] if batched else -1, n)
+        out["n_near"] = cnt[1].cpu().numpy().reshape(out["n_far"].shape)
+        if not batched:
+            out["n_far"], out["n_near"] = out["n_far"][0], out["n_near"][0]
+    return out
+
+
+def errors(H, Href):
+    """Global relative L2, max and 99.9th percentile per-particle relative error (floor 1e-3 rms)."""
+    H = np.asarray(H).reshape(3, -1) if H.ndim == 2 else np.asarray(H)
+    Href = np.asarray(Href).reshape(H.shape)
+    d = np.linalg.norm(H - Href, axis=-2)
+    r = np.linalg.norm(Href, axis=-2)
+    floor = 1e-3 * np.sqrt(np.mean(r ** 2))
+    per = d / np.maximum(r, floor)
+    return dict(l2=float(np.linalg.norm(H - Href) / np.linalg.norm(Href)), max=float(per.max()),
+                p999=float(np.quantile(per, 0.999)))
+
+
+def energy_err(E, Eref, mom, Href):
+    return abs(E - Eref) / (0.5 * np.abs((mom * Href).sum()))

@@ -1,0 +1,128 @@
+"""Barnes-Hut field and energy through the C ABI against the oracle, element by element.
+
+FP64 path: relative L2 <= 1e-12 and energy <= 1e-12 (only summation order differs).
+FP32-mixed path (pair arithmetic in FP32 on FP64 offsets, FP64 acceptance test and accumulation):
+relative L2 <= 1e-5, 99.9th percentile per-particle relative error <= 1e-5 (floor 1e-3 rms|H|),
+energy error normalised by 1/2 sum|m.H| <= 1e-5.  Interaction counts must be identical in both paths:
+the acceptance decisions are the definition's, not an approximation of it.
+"""
+import numpy as np
+import pytest
+
+from paper_1212_2934_amd import workloads
+from gpu_util import energy_err, errors, run_field
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32_mixed": 1e-5}
+
+
+def _check(out, H, E, nf, nr, mom, precision):
+    assert out["flags"] == 0
+    assert (out["n_far"] == nf).all() and (out["n_near"] == nr).all()
+    e = errors(out["H"], H)
+    tol = TOL[precision]
+    assert e["l2"] <= tol, e
+    if precision == "fp32_mixed":
+        assert e["p999"] <= tol, e
+    else:
+        assert e["max"] <= 1e-10, e
+    assert energy_err(out["E"][0], E, mom, H) <= tol
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
+def test_config1_uniform_4096(oracle_mod, precision):
+    w = workloads.config1()
+    t = oracle_mod.Tree(w.pos, w.mom, 16)
+    H, nf, nr = t.field(0.5)
+    E = oracle_mod.energy(w.mom, H, None)
+    out = run_field(w.pos, w.mom, theta=0.5, precision=precision)
+    _check(out, H, E, nf, nr, w.mom, precision)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
+@pytest.mark.parametrize("theta", [0.0, 0.3, 0.7, 1.2])
+def test_theta_sweep_chains(oracle_mod, precision, theta):
+    w = workloads.config3(seed=31, n=6000 + 13)  # several tiles and a ragged last wave
+    hext = np.array([0.1, 0.0, 0.4])
+    t = oracle_mod.Tree(w.pos, w.mom, 16)
+    H, nf, nr = t.field(theta)
+    E = oracle_mod.energy(w.mom, H, hext)
+    out = run_field(w.pos, w.mom, hext=hext, theta=theta, precision=precision)
+    _check(out, H, E, nf, nr, w.mom, precision)
+
+
+@pytest.mark.parametrize("leaf", [1, 3, 8, 32, 64])
+def test_leaf_sizes(oracle_mod, leaf):
+    w = workloads.uniform_cube(3000, 26.0, seed=41)
+    t = oracle_mod.Tree(w.pos, w.mom, leaf)
+    H, nf, nr = t.field(0.5)
+    out = run_field(w.pos, w.mom, theta=0.5, leaf=leaf, precision="fp64")
+    _check(out, H, E=oracle_mod.energy(w.mom, H), nf=nf, nr=nr, mom=w.mom, precision="fp64")
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 16, 17, 63, 64, 65, 129])
+def test_small_and_ragged(oracle_mod, n):
+    w = workloads.uniform_cube(n, 5.0 + n ** (1 / 3), seed=50 + n)
+    Hap = oracle_mod.allpairs_field(w.pos, w.mom)
+    t = oracle_mod.Tree(w.pos, w.mom, 4)
+    H, nf, nr = t.field(0.5)
+    for precision in ("fp64", "fp32_mixed"):
+        out = run_field(w.pos, w.mom, theta=0.5, leaf=4, precision=precision)
+        if n == 1:
+            assert (out["H"] == 0).all() and out["E"][0] == 0.0
+            continue
+        _check(out, H, oracle_mod.energy(w.mom, H), nf, nr, w.mom, precision)
+    out0 = run_field(w.pos, w.mom, theta=0.0, leaf=4, precision="fp64")
+    if n > 1:
+        assert errors(out0["H"], Hap)["l2"] <= 1e-12
+
+
+def test_batch_equals_single_runs(oracle_mod):
+    B, n = 4, 2500
+    ws = [workloads.uniform_cube(n, 30.0, seed=60 + b) for b in range(B)]
+    pos = np.stack([w.pos for w in ws])
+    mom = np.stack([w.mom for w in ws])
+    hext = np.array([[0.0, 0.0, 0.5 * b] for b in range(B)])
+    for precision in ("fp64", "fp32_mixed"):
+        out = run_field(pos, mom, hext=hext, precision=precision)
+        assert out["flags"] == 0
+        for b, w in enumerate(ws):
+            single = run_field(w.pos, w.mom, hext=hext[b], precision=precision)
+            assert (out["H"][b] == single["H"]).all()
+            assert out["E"][b] == single["E"][0]
+            assert (out["n_far"][b] == single["n_far"]).all()
+            H, nf, nr = oracle_mod.Tree(w.pos, w.mom, 16).field(0.5)
+            assert (out["n_far"][b] == nf).all() and (out["n_near"][b] == nr).all()
+            assert errors(out["H"][b], H)["l2"] <= TOL[precision]
+
+
+def test_permutation_and_repeatability():
+    w = workloads.uniform_cube(5000, 36.0, seed=71)
+    p = np.random.default_rng(72).permutation(w.n)
+    a = run_field(w.pos, w.mom, precision="fp64")
+    b = run_field(w.pos[:, p], w.mom[:, p], precision="fp64")
+    c = run_field(w.pos, w.mom, precision="fp64")
+    assert (b["H"] == a["H"][:, p]).all()
+    assert (c["H"] == a["H"]).all() and c["E"][0] == a["E"][0]
+
+
+@pytest.mark.parametrize("tuning_id", [0, 1, 2, 3])
+def test_launch_shape_invariance(tuning_id):
+    w = workloads.config3(seed=81, n=5000)
+    ref = run_field(w.pos, w.mom, precision="fp32_mixed", tuning_id=0)
+    out = run_field(w.pos, w.mom, precision="fp32_mixed", tuning_id=tuning_id)
+    assert (out["H"] == ref["H"]).all() and (out["n_far"] == ref["n_far"]).all()
+
+
+def test_degenerate_inputs_flagged():
+    w = workloads.uniform_cube(300, 12.0, seed=91)
+    pos = w.pos.copy()
+    pos[:, 5] = pos[:, 9]  # two particles at one position
+    out = run_field(pos, w.mom, precision="fp64")
+    assert out["flags"] & 2  # coincident
+    assert np.isfinite(out["H"]).all()
+    pos = w.pos.copy()
+    pos[1, 3] = np.nan
+    out = run_field(pos, w.mom, precision="fp64", counters=False)
+    assert out["flags"] & 1  # non-finite

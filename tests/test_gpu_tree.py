@@ -1,0 +1,70 @@
+"""GPU tree against the oracle's tree: same sorted order (bitwise), same cells (each run of unary cells
+of the oracle's uncollapsed tree appears once on the GPU, at its deepest cell; leaves at the first cell of
+their run), same geometric centres (bitwise: same sums in the same order, Eq. magCenter)."""
+import numpy as np
+import pytest
+
+from paper_1212_2934_amd import workloads
+from gpu_util import run_field
+
+pytestmark = pytest.mark.gpu
+
+
+def _oracle_cells(t):
+    keep = {}
+    for i in range(t["level"].size):
+        if t["nchild"][i] != 1:
+            keep[(int(t["first"][i]), int(t["count"][i]))] = (int(t["level"][i]), t["c"][i],
+                                                              int(t["nchild"][i]) == 0)
+    return keep
+
+
+def _compare(pos, mom, leaf, oracle_mod, offset=0, gtree=None):
+    t = oracle_mod.Tree(pos, mom, leaf).export()
+    n = pos.shape[1]
+    assert (gtree["perm"][offset:offset + n] - offset == t["perm"]).all()
+    ocells = _oracle_cells(t)
+    gcells = {}
+    for i in range(gtree["first"].size):
+        f = int(gtree["first"][i]) - offset
+        if 0 <= f < n and f + int(gtree["count"][i]) <= n:
+            gcells[(f, int(gtree["count"][i]))] = (int(gtree["level"][i]), gtree["centroid"][i],
+                                                   int(gtree["nchild"][i]) == 0)
+    assert set(gcells) == set(ocells)
+    for k, (lev, c, leafy) in ocells.items():
+        glev, gc, gleafy = gcells[k]
+        assert glev == lev and gleafy == leafy, k
+        assert (gc == c).all(), (k, gc, c)
+    return len(ocells)
+
+
+@pytest.mark.parametrize("n,side,leaf,seed", [(4096, 32.0, 16, 1001), (5000, 36.0, 4, 7),
+                                             (777, 20.0, 1, 8), (20000 + 37, 60.0, 16, 9)])
+def test_tree_matches_oracle(oracle_mod, n, side, leaf, seed):
+    w = workloads.uniform_cube(n, side, seed)
+    out = run_field(w.pos, w.mom, leaf=leaf, counters=False)
+    assert out["flags"] == 0
+    g = out["bh"].export_tree()
+    ncells = _compare(w.pos, w.mom, leaf, oracle_mod, gtree=g)
+    assert ncells == g["first"].size
+
+
+def test_tree_chains_and_batch(oracle_mod):
+    ws = [workloads.config3(seed=100 + b, n=3000) for b in range(3)]
+    pos = np.stack([w.pos for w in ws])
+    mom = np.stack([w.mom for w in ws])
+    out = run_field(pos, mom, counters=False)
+    g = out["bh"].export_tree()
+    total = 0
+    for b, w in enumerate(ws):
+        total += _compare(w.pos, w.mom, 16, oracle_mod, offset=b * 3000, gtree=g)
+    assert total == g["first"].size
+    assert (g["first"][:3] == np.array([0, 3000, 6000])).all()  # roots are nodes 0..B-1
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 16, 17, 64, 65])
+def test_tree_small_systems(oracle_mod, n):
+    w = workloads.uniform_cube(n, 6.0 + n ** (1 / 3), seed=n)
+    out = run_field(w.pos, w.mom, leaf=16, counters=False)
+    g = out["bh"].export_tree()
+    _compare(w.pos, w.mom, 16, oracle_mod, gtree=g)
