@@ -1,0 +1,173 @@
+"""Benchmark: Barnes-Hut dipolar field evaluations and MD-path steps at N = 2^20, theta = 0.5, on one
+MI355X, FP32-mixed and FP64, with the dominant kernel's roofline and the FP64 CPU oracle beside it.
+
+Workload: 2^20 particles in straight chains (lengths 2-20, spacing 1.05 d, moments along the chain axis
+with N(0, 0.1) jitter) at volume fraction 0.1 in a cube of side 176.41 d, theta = 0.5, leaf size 16,
+H_ext = 0 (synthetic, seeded).  A timed step is one pass of the hot path on that input: tree build
+(bounding cube, Morton codes, radix sort, octree, centroids), upward moment pass, forward field and
+energy, and the adjoint (dE/dr, dE/dm) by re-traversal.  value = steps/s in FP32-mixed precision.
+
+Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "BH dipolar field evals/s + MD steps/s at N=2^20 θ=0.5, FP32 vs FP64 GPU"
+PEAK_FP32_VECTOR = 157.3e12   # published MI355X FP32 vector peak (packed FMA)
+PEAK_FP32_UNPACKED = 78.6e12  # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz, one FMA per lane
+# algorithmic flops per interaction, fixed from the kernel source (FMA = 2, rsqrt = 1):
+FLOPS_FWD = 30   # 3 FP64 offset subtractions + 27 for the dipole field and its accumulation
+FLOPS_ADJ = 64   # 3 offset + 58 for g and T(x)Hbar + 3 gather accumulation
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--theta", type=float, default=0.5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1212_2934_amd import workloads
+    from paper_1212_2934_amd.binding import BarnesHut
+
+    log("generating workload (2^20 chains, phi 0.1)")
+    w = workloads.cached("chains_n1048576_seed1003", lambda: workloads.config3())
+    n = w.n
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    pos = torch.from_numpy(w.pos).to(dev)
+    mom = torch.from_numpy(w.mom).to(dev)
+    hext = torch.zeros(3, dtype=torch.float64, device=dev)
+    ones = torch.ones(1, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def make(precision):
+        return BarnesHut(n, 1, 16, args.theta, precision)
+
+    # interaction counts (outside timing): identical for both precisions
+    bh = make("fp32_mixed")
+    bh.build(pos)
+    nf, nr = bh.enable_counters()
+    bh.field(mom, hext)
+    assert bh.check_status() == 0
+    n_far, n_near = int(nf.sum().item()), int(nr.sum().item())
+    bh.disable_counters()
+    inter = n_far + n_near
+    log(f"interactions per evaluation: far {n_far}, near {n_near}")
+
+    res = {}
+    for precision in ("fp32_mixed", "fp64"):
+        bh = make(precision)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        bh.set_timing_events((ev[0], ev[1]), (ev[2], ev[3]))
+
+        def step():
+            bh.build(pos)
+            return bh.field_backward(mom, hext, gE=ones)
+
+        def field_only():
+            bh.build(pos)
+            return bh.field(mom, hext)
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        t_fwd = t_adj = 0.0
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+            ev[3].synchronize()
+            t_fwd += ev[0].elapsed_time(ev[1]) * 1e-3
+            t_adj += ev[2].elapsed_time(ev[3]) * 1e-3
+        torch.cuda.synchronize()
+        t_step = (time.perf_counter() - t0) / args.steps
+        # field evaluation alone (build + field)
+        for _ in range(args.warmup):
+            field_only()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            field_only()
+        torch.cuda.synchronize()
+        t_eval = (time.perf_counter() - t0) / args.steps
+        assert bh.check_status() == 0
+        res[precision] = dict(t_step=t_step, t_eval=t_eval, t_fwd_kernel=t_fwd / args.steps,
+                              t_adj_kernel=t_adj / args.steps)
+        log(f"{precision}: step {t_step * 1e3:.3f} ms, eval {t_eval * 1e3:.3f} ms, traversal "
+            f"{res[precision]['t_fwd_kernel'] * 1e3:.3f} ms, adjoint {res[precision]['t_adj_kernel'] * 1e3:.3f} ms")
+        del bh
+    torch.cuda.synchronize()
+
+    r32 = res["fp32_mixed"]
+    # dominant kernel of the FP32-mixed step
+    if r32["t_adj_kernel"] >= r32["t_fwd_kernel"]:
+        kname, kt, flops = "k_adjoint<fp32_mixed>", r32["t_adj_kernel"], FLOPS_ADJ * inter
+    else:
+        kname, kt, flops = "k_field<fp32_mixed>", r32["t_fwd_kernel"], FLOPS_FWD * inter
+    achieved = flops / kt
+    roofline = {"bound": "alu", "kernel": kname, "achieved": achieved / 1e12, "peak": PEAK_FP32_VECTOR / 1e12,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR,
+                "frac_of_unpacked_fp32": achieved / PEAK_FP32_UNPACKED, "traffic": None,
+                "flops_per_launch": flops, "avg_kernel_ms": kt * 1e3}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        log("timing the FP64 CPU oracle on the same workload (tree, field and adjoint for all targets)")
+        t0 = time.perf_counter()
+        tree = oracle.Tree(w.pos, w.mom, 16)
+        tree.energy_grad(args.theta, w.hext)
+        tc = time.perf_counter() - t0
+        cpu = {"value": 1.0 / tc, "unit": "steps/s", "cores": oracle.num_threads(), "kind": "oracle",
+               "sample": "one full step at N=2^20 (tree build, field and adjoint for every target), FP64, "
+                         f"{tc:.1f} s wall"}
+
+    out = {
+        "metric": METRIC,
+        "value": 1.0 / r32["t_step"],
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r32["t_step"] * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 pair arithmetic, f64 tree/accumulation",
+        "data": "synthetic",
+        "config": {"workload": "chains N=2^20 phi=0.1 cube 176.41 theta=0.5 leaf 16 (build+field+adjoint)",
+                   "n": n, "theta": args.theta, "leaf_size": 16},
+        "field_evals_per_s_fp32": 1.0 / r32["t_eval"],
+        "field_evals_per_s_fp64": 1.0 / res["fp64"]["t_eval"],
+        "steps_per_s_fp64": 1.0 / res["fp64"]["t_step"],
+        "speedup_fp32_over_fp64_step": res["fp64"]["t_step"] / r32["t_step"],
+        "interactions_per_eval": inter,
+        "kernel_ms": {p: {"traversal": r["t_fwd_kernel"] * 1e3, "adjoint": r["t_adj_kernel"] * 1e3}
+                      for p, r in res.items()},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -154,6 +154,12 @@ bh_status bh_export_tree(bh_handle *h, int32_t *d_perm, int32_t *d_first, int32_
                          int32_t *d_level, int32_t *d_nchild, int32_t *d_child_first,
                          double *d_centroid, double *d_bbox, void *stream);
 
+/* Timing hook: when set, bh_field records fwd_start / fwd_stop (hipEvent_t, created by the caller)
+ * on its stream immediately before and after its traversal kernel, and bh_field_backward records
+ * adj_start / adj_stop around its adjoint traversal kernel.  Pass NULL to disable. */
+bh_status bh_set_timing_events(bh_handle *h, void *fwd_start, void *fwd_stop, void *adj_start,
+                               void *adj_stop);
+
 /* Host-side reference of the code of a quantised position (21 bits per axis): bit 3k+2 = bit k of qx,
  * bit 3k+1 = bit k of qy, bit 3k = bit k of qz.  Same function the device uses; no GPU needed. */
 uint64_t bh_morton_code(uint32_t qx, uint32_t qy, uint32_t qz);

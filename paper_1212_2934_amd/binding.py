@@ -65,6 +65,8 @@ def lib():
         L.bh_enable_counters.argtypes = [P, P, P]
         L.bh_num_nodes.argtypes = [P, P, C.POINTER(i64)]
         L.bh_export_tree.argtypes = [P] * 10
+        L.bh_set_timing_events.argtypes = [P] * 5
+        L.bh_set_timing_events.restype = i32
         L.bh_morton_code.argtypes = [C.c_uint32, C.c_uint32, C.c_uint32]
         L.bh_morton_code.restype = C.c_uint64
         L.bh_status_str.argtypes = [i32]
@@ -79,7 +81,7 @@ def lib():
 
 EXPORTED = ["bh_workspace_bytes", "bh_num_tunings", "bh_create", "bh_destroy", "bh_build", "bh_field",
             "bh_field_backward", "md_step", "bh_check_status", "bh_enable_counters", "bh_num_nodes",
-            "bh_export_tree", "bh_morton_code", "bh_status_str"]
+            "bh_export_tree", "bh_set_timing_events", "bh_morton_code", "bh_status_str"]
 
 
 def _check(fn: str, st: int):
@@ -207,6 +209,16 @@ class BarnesHut:
     def disable_counters(self):
         _check("bh_enable_counters", lib().bh_enable_counters(self._h, None, None))
         self._counters = None
+
+    def set_timing_events(self, fwd=None, adj=None):
+        """Record torch.cuda.Event pairs around the traversal kernels (None disables)."""
+        def raw(e):
+            return None if e is None else C.c_void_p(e.cuda_event)
+        f0, f1 = fwd if fwd else (None, None)
+        a0, a1 = adj if adj else (None, None)
+        self._events = (fwd, adj)
+        _check("bh_set_timing_events", lib().bh_set_timing_events(self._h, raw(f0), raw(f1), raw(a0),
+                                                                  raw(a1)))
 
     def check_status(self) -> int:
         """Device status flags since the last check (synchronises the stream)."""

@@ -18,7 +18,7 @@ __device__ inline void atomic_add_d(double *p, double v)
 }
 
 template <bool MIXED>
-__global__ __launch_bounds__(256) void k_adjoint(
+__global__ __launch_bounds__(512) void k_adjoint(
     const NodeRec *__restrict__ nodes, const double *__restrict__ node_m64, const double *__restrict__ spos,
     const double *__restrict__ smom, const float *__restrict__ smom32, const double *__restrict__ hbar,
     double *__restrict__ g_gather, double *__restrict__ g_r, double *__restrict__ g_m,
@@ -238,6 +238,7 @@ hipError_t launch_backward(Handle &h, const double *d_mom, const double *d_hext,
     const unsigned blocks = (unsigned)((L.num_waves + wpb - 1) / wpb);
     const int waves_per_seg = (int)((L.n + kWave - 1) / kWave);
     const double theta2 = h.p.theta * h.p.theta;
+    if (h.ev[2]) (void)hipEventRecord(h.ev[2], s);
     if (h.p.precision == BH_FP32_MIXED)
         hipLaunchKernelGGL(k_adjoint<true>, dim3(blocks), dim3(wpb * kWave), 0, s, w.nodes, w.node_m64, w.spos,
                            w.smom, w.smom32, w.hbar, w.g_gather, w.g_r, w.g_m, w.node_adj, w.status, L.n,
@@ -246,6 +247,7 @@ hipError_t launch_backward(Handle &h, const double *d_mom, const double *d_hext,
         hipLaunchKernelGGL(k_adjoint<false>, dim3(blocks), dim3(wpb * kWave), 0, s, w.nodes, w.node_m64, w.spos,
                            w.smom, w.smom32, w.hbar, w.g_gather, w.g_r, w.g_m, w.node_adj, w.status, L.n,
                            L.ntot, waves_per_seg, (int)L.num_waves, theta2, (int)L.max_nodes);
+    if (h.ev[3]) (void)hipEventRecord(h.ev[3], s);
     hipLaunchKernelGGL(k_downward, dim3(grid_for(L.ntot, 256)), dim3(256), 0, s, w.nodes, w.leaf_of, w.node_adj,
                        w.g_gather, w.g_r, w.g_m, w.Hs, d_hext, d_gE, w.perm, L.n, L.ntot, d_dpos, d_dmom);
     if (d_dhext)

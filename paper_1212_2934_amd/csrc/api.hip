@@ -175,6 +175,7 @@ bh_status bh_create(const bh_params *p, void *d_workspace, size_t workspace_byte
     h.built = 0;
     h.waves_per_block = kTuneWaves[p->tuning_id < 0 ? 0 : p->tuning_id];
     h.cnt_far = h.cnt_near = nullptr;
+    for (int k = 0; k < 4; ++k) h.ev[k] = nullptr;
     hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(64), 0, 0, h.w.status);
     if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
         delete hh;
@@ -259,6 +260,18 @@ bh_status bh_enable_counters(bh_handle *hh, int32_t *d_n_far, int32_t *d_n_near)
     if ((d_n_far == nullptr) != (d_n_near == nullptr)) return BH_EINVAL;
     hh->h.cnt_far = d_n_far;
     hh->h.cnt_near = d_n_near;
+    return BH_OK;
+}
+
+bh_status bh_set_timing_events(bh_handle *hh, void *fwd_start, void *fwd_stop, void *adj_start, void *adj_stop)
+{
+    if (!hh) return BH_EINVAL;
+    if ((fwd_start == nullptr) != (fwd_stop == nullptr) || (adj_start == nullptr) != (adj_stop == nullptr))
+        return BH_EINVAL;
+    hh->h.ev[0] = (hipEvent_t)fwd_start;
+    hh->h.ev[1] = (hipEvent_t)fwd_stop;
+    hh->h.ev[2] = (hipEvent_t)adj_start;
+    hh->h.ev[3] = (hipEvent_t)adj_stop;
     return BH_OK;
 }
 

@@ -98,6 +98,7 @@ struct Handle {
     int built;           // a bh_build has been enqueued
     int waves_per_block; // traversal launch shape
     int32_t *cnt_far, *cnt_near;  // optional per-target counters (device)
+    hipEvent_t ev[4];             // optional timing events around the traversal kernels
 };
 
 // ---- shared device helpers -----------------------------------------------------------------------

@@ -14,7 +14,7 @@
 namespace ffbh {
 
 template <bool MIXED, bool COUNT>
-__global__ __launch_bounds__(256) void k_field(
+__global__ __launch_bounds__(512) void k_field(
     const NodeRec *__restrict__ nodes, const double *__restrict__ node_m64, const double *__restrict__ spos,
     const double *__restrict__ smom, const float *__restrict__ smom32, const uint32_t *__restrict__ perm,
     const double *__restrict__ hext, double *__restrict__ H, double *__restrict__ Hs,
@@ -180,10 +180,12 @@ hipError_t launch_field(Handle &h, const double *d_mom, const double *d_hext, do
     if (e != hipSuccess) return e;
     const bool mixed = h.p.precision == BH_FP32_MIXED;
     const bool cnt = h.cnt_far != nullptr;
+    if (h.ev[0]) (void)hipEventRecord(h.ev[0], s);
     if (mixed && cnt) launch_k_field<true, true>(h, d_hext, d_H, s);
     else if (mixed) launch_k_field<true, false>(h, d_hext, d_H, s);
     else if (cnt) launch_k_field<false, true>(h, d_hext, d_H, s);
     else launch_k_field<false, false>(h, d_hext, d_H, s);
+    if (h.ev[1]) (void)hipEventRecord(h.ev[1], s);
     if (d_E) {
         const int waves_per_seg = (int)((h.L.n + kWave - 1) / kWave);
         hipLaunchKernelGGL(k_energy_final, dim3((unsigned)h.L.B), dim3(64), 0, s, h.w.e_part, waves_per_seg,

@@ -235,3 +235,22 @@ def nearest_to_centre(pos: np.ndarray, k: int) -> np.ndarray:
     c = 0.5 * (pos.min(axis=1) + pos.max(axis=1))
     d2 = ((pos - c[:, None]) ** 2).sum(axis=0)
     return np.sort(np.argsort(d2, kind="stable")[:k])
+
+
+def cached(name: str, make):
+    """Workload `name` from an on-disk cache (npz under $FFBH_CACHE or the temp dir), else make() it."""
+    import os
+    import tempfile
+    d = os.environ.get("FFBH_CACHE", os.path.join(tempfile.gettempdir(), "ffbh_cache"))
+    os.makedirs(d, exist_ok=True)
+    f = os.path.join(d, name + ".npz")
+    if os.path.exists(f):
+        z = np.load(f)
+        return Workload(str(z["name"]), z["pos"], z["mom"], z["hext"], z["box_lo"], z["box_hi"],
+                        float(z["theta"]), int(z["leaf_size"]), int(z["seed"]))
+    w = make()
+    tmp = f + ".tmp.npz"
+    np.savez(tmp, name=w.name, pos=w.pos, mom=w.mom, hext=w.hext, box_lo=w.box_lo, box_hi=w.box_hi,
+             theta=w.theta, leaf_size=w.leaf_size, seed=w.seed)
+    os.replace(tmp, f)
+    return w

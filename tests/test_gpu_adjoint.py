@@ -1,0 +1,87 @@
+"""Adjoint through the C ABI against the oracle's frozen-structure adjoint (whose pins are FD, theta = 0
+== the all-pairs analytic gradient built from the paper's f_dip, and the invariants).
+
+E = -1/2 sum m.H - sum m.H_ext; dE/dr, dE/dm and a general vector-Jacobian product with upstream dL/dH.
+FP64 path within 1e-12 (relative L2; FP64 atomics only reorder sums), FP32-mixed within 1e-5.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_1212_2934_amd import workloads
+from paper_1212_2934_amd.binding import BarnesHut
+
+pytestmark = pytest.mark.gpu
+TOL = {"fp64": 1e-12, "fp32_mixed": 1e-5}
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def _gpu_grad(pos, mom, hext, theta, precision, gH=None, gE=1.0, leaf=16, want_dhext=False):
+    bh = BarnesHut(pos.shape[-1], 1 if pos.ndim == 2 else pos.shape[0], leaf, theta, precision)
+    p = torch.from_numpy(pos).cuda()
+    m = torch.from_numpy(mom).cuda()
+    he = torch.from_numpy(np.asarray(hext, float)).cuda()
+    g = None if gH is None else torch.from_numpy(gH).cuda()
+    ge = None if gE is None else torch.full((bh.batch,), gE, dtype=torch.float64, device="cuda")
+    bh.build(p)
+    out = bh.field_backward(m, he, gH=g, gE=ge, want_dhext=want_dhext)
+    assert bh.check_status() == 0
+    return [None if o is None else o.cpu().numpy() for o in out]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
+def test_energy_gradient_config1(oracle_mod, precision):
+    w = workloads.uniform_cube(4096, 32.0, seed=1001, hext=(0.0, 0.0, 1.0))
+    H, E, dr, dm = oracle_mod.Tree(w.pos, w.mom, 16).energy_grad(0.5, w.hext)
+    gdr, gdm, gdh = _gpu_grad(w.pos, w.mom, w.hext, 0.5, precision, want_dhext=True)
+    assert rel(gdr, dr) <= TOL[precision]
+    assert rel(gdm, dm) <= TOL[precision]
+    np.testing.assert_allclose(gdh[0], -w.mom.sum(axis=1), rtol=1e-12)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
+@pytest.mark.parametrize("theta", [0.3, 0.7])
+def test_general_vjp_chains(oracle_mod, precision, theta):
+    w = workloads.config3(seed=11, n=5000 + 3)
+    rng = np.random.default_rng(12)
+    gH = rng.standard_normal((3, w.n))
+    gE = 0.3
+    hext = np.array([0.2, -0.1, 0.05])
+    t = oracle_mod.Tree(w.pos, w.mom, 16)
+    H, _, _ = t.field(theta)
+    dr, dm = t.vjp(theta, gH - 0.5 * gE * w.mom)
+    dm = dm + gE * (-0.5 * H - hext[:, None])
+    gdr, gdm = _gpu_grad(w.pos, w.mom, hext, theta, precision, gH=gH, gE=gE)
+    assert rel(gdr, dr) <= TOL[precision]
+    assert rel(gdm, dm) <= TOL[precision]
+
+
+def test_theta_zero_equals_allpairs_force(oracle_mod):
+    w = workloads.uniform_cube(1500, 20.0, seed=21)
+    g = oracle_mod.allpairs_grad_r(w.pos, w.mom)
+    gdr, gdm = _gpu_grad(w.pos, w.mom, np.zeros(3), 0.0, "fp64")
+    assert rel(gdr, g) <= 1e-12
+    assert rel(gdm, -oracle_mod.allpairs_field(w.pos, w.mom)) <= 1e-12
+
+
+def test_batched_adjoint(oracle_mod):
+    B, n = 3, 2000
+    ws = [workloads.uniform_cube(n, 26.0, seed=30 + b) for b in range(B)]
+    pos = np.stack([x.pos for x in ws])
+    mom = np.stack([x.mom for x in ws])
+    hext = np.array([0.0, 0.0, 0.7])
+    gdr, gdm = _gpu_grad(pos, mom, hext, 0.5, "fp32_mixed")
+    for b, x in enumerate(ws):
+        _, _, dr, dm = oracle_mod.Tree(x.pos, x.mom, 16).energy_grad(0.5, hext)
+        assert rel(gdr[b], dr) <= 1e-5 and rel(gdm[b], dm) <= 1e-5
+
+
+def test_invariants_at_full_size_c4():
+    """Differentiation workload at full size (N = 2^18): translation invariance and the energy symmetry
+    of the transposed traversal hold at any size."""
+    w = workloads.config4()
+    gdr, gdm = _gpu_grad(w.pos, w.mom, np.zeros(3), 0.5, "fp64")
+    assert np.abs(gdr.sum(axis=1)).max() <= 1e-10 * np.abs(gdr).sum()
