@@ -3,9 +3,12 @@ MI355X, FP32-mixed and FP64, with the dominant kernel's roofline and the FP64 CP
 
 Workload: 2^20 particles in straight chains (lengths 2-20, spacing 1.05 d, moments along the chain axis
 with N(0, 0.1) jitter) at volume fraction 0.1 in a cube of side 176.41 d, theta = 0.5, leaf size 16,
-H_ext = 0 (synthetic, seeded).  A timed step is one pass of the hot path on that input: tree build
-(bounding cube, Morton codes, radix sort, octree, centroids), upward moment pass, forward field and
-energy, and the adjoint (dE/dr, dE/dm) by re-traversal.  value = steps/s in FP32-mixed precision.
+H_ext = 0 (synthetic, seeded).  A timed step is one MD step (md_step) on that input, i.e. one pass of
+the whole hot path: tree build (bounding cube, Morton codes, radix sort, octree, centroids), upward
+moment pass, forward field and energy, the adjoint (dE/dr, dE/dm) by re-traversal, WCA pair and wall
+forces by a tree range query, and the Euler-Maruyama update with Philox noise (dt 1e-3, kT 1,
+gamma 0.1, M 1, I 0.1).  value = MD steps/s in FP32-mixed precision; field evaluations/s (tree build +
+field) are reported beside it for both precisions.
 
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
 """
@@ -30,6 +33,35 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+class HipEvents:
+    """Raw hipEvent_t pairs (the library records them around its kernels on the caller's stream)."""
+
+    def __init__(self, count):
+        import ctypes as C
+        self.C = C
+        self.hip = C.CDLL("libamdhip64.so")
+        self.hip.hipEventCreate.argtypes = [C.POINTER(C.c_void_p)]
+        self.hip.hipEventElapsedTime.argtypes = [C.POINTER(C.c_float), C.c_void_p, C.c_void_p]
+        self.hip.hipEventSynchronize.argtypes = [C.c_void_p]
+        self.hip.hipEventDestroy.argtypes = [C.c_void_p]
+        self.ev = []
+        for _ in range(count):
+            e = C.c_void_p()
+            assert self.hip.hipEventCreate(C.byref(e)) == 0
+            self.ev.append(e)
+
+    def seconds(self, a, b):
+        C = self.C
+        assert self.hip.hipEventSynchronize(self.ev[b]) == 0
+        ms = C.c_float(0.0)
+        assert self.hip.hipEventElapsedTime(C.byref(ms), self.ev[a], self.ev[b]) == 0
+        return ms.value * 1e-3
+
+    def __del__(self):
+        for e in self.ev:
+            self.hip.hipEventDestroy(e)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -47,7 +79,9 @@ def main():
     import torch
 
     from paper_1212_2934_amd import workloads
-    from paper_1212_2934_amd.binding import BarnesHut
+    import ctypes
+
+    from paper_1212_2934_amd.binding import BarnesHut, md_params
 
     log("generating workload (2^20 chains, phi 0.1)")
     w = workloads.cached("chains_n1048576_seed1003", lambda: workloads.config3())
@@ -74,15 +108,23 @@ def main():
     inter = n_far + n_near
     log(f"interactions per evaluation: far {n_far}, near {n_near}")
 
+    rng = np.random.default_rng(2003)
+    side = float(w.box_hi[0])
+    vel0 = torch.from_numpy(rng.standard_normal(w.pos.shape)).to(dev)              # kT / M = 1
+    om0 = torch.from_numpy(rng.standard_normal(w.pos.shape) * np.sqrt(10.0)).to(dev)  # kT / I = 10
+    C3 = ctypes.c_double * 3
+    mdp = md_params(1e-3, 1.0, 0.1, 0.1, 1.0, 0.1, 1.0, 1.0, C3(0.0, 0.0, 0.0), C3(side, side, side), None, 2003)
+
     res = {}
     for precision in ("fp32_mixed", "fp64"):
         bh = make(precision)
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
-        bh.set_timing_events((ev[0], ev[1]), (ev[2], ev[3]))
+        ev = HipEvents(4)
+        bh.set_raw_timing_events(ev.ev)
+        state = {"pos": pos.clone(), "vel": vel0.clone(), "mom": mom.clone(), "omega": om0.clone(),
+                 "step": torch.zeros(1, dtype=torch.int64, device=dev)}
 
         def step():
-            bh.build(pos)
-            return bh.field_backward(mom, hext, gE=ones)
+            bh.md_step(state, mdp)
 
         def field_only():
             bh.build(pos)
@@ -95,9 +137,8 @@ def main():
         t0 = time.perf_counter()
         for _ in range(args.steps):
             step()
-            ev[3].synchronize()
-            t_fwd += ev[0].elapsed_time(ev[1]) * 1e-3
-            t_adj += ev[2].elapsed_time(ev[3]) * 1e-3
+            t_fwd += ev.seconds(0, 1)
+            t_adj += ev.seconds(2, 3)
         torch.cuda.synchronize()
         t_step = (time.perf_counter() - t0) / args.steps
         # field evaluation alone (build + field)
@@ -110,6 +151,7 @@ def main():
         torch.cuda.synchronize()
         t_eval = (time.perf_counter() - t0) / args.steps
         assert bh.check_status() == 0
+        bh.set_raw_timing_events(None)
         res[precision] = dict(t_step=t_step, t_eval=t_eval, t_fwd_kernel=t_fwd / args.steps,
                               t_adj_kernel=t_adj / args.steps)
         log(f"{precision}: step {t_step * 1e3:.3f} ms, eval {t_eval * 1e3:.3f} ms, traversal "
@@ -137,14 +179,15 @@ def main():
         tree = oracle.Tree(w.pos, w.mom, 16)
         tree.energy_grad(args.theta, w.hext)
         tc = time.perf_counter() - t0
-        cpu = {"value": 1.0 / tc, "unit": "steps/s", "cores": oracle.num_threads(), "kind": "oracle",
-               "sample": "one full step at N=2^20 (tree build, field and adjoint for every target), FP64, "
+        cpu = {"value": 1.0 / tc, "unit": "MD steps/s", "cores": oracle.num_threads(), "kind": "oracle",
+               "sample": "the force evaluation of one MD step at N=2^20 (tree build, field and adjoint for "
+                         "every target, FP64); the oracle's all-pairs WCA and integrator are not timed, "
                          f"{tc:.1f} s wall"}
 
     out = {
         "metric": METRIC,
         "value": 1.0 / r32["t_step"],
-        "unit": "steps/s",
+        "unit": "MD steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
@@ -154,11 +197,11 @@ def main():
         "vs_baseline": None,
         "dtype": "f32 pair arithmetic, f64 tree/accumulation",
         "data": "synthetic",
-        "config": {"workload": "chains N=2^20 phi=0.1 cube 176.41 theta=0.5 leaf 16 (build+field+adjoint)",
+        "config": {"workload": "chains N=2^20 phi=0.1 cube 176.41 theta=0.5 leaf 16, one MD step",
                    "n": n, "theta": args.theta, "leaf_size": 16},
         "field_evals_per_s_fp32": 1.0 / r32["t_eval"],
         "field_evals_per_s_fp64": 1.0 / res["fp64"]["t_eval"],
-        "steps_per_s_fp64": 1.0 / res["fp64"]["t_step"],
+        "md_steps_per_s_fp64": 1.0 / res["fp64"]["t_step"],
         "speedup_fp32_over_fp64_step": res["fp64"]["t_step"] / r32["t_step"],
         "interactions_per_eval": inter,
         "kernel_ms": {p: {"traversal": r["t_fwd_kernel"] * 1e3, "adjoint": r["t_adj_kernel"] * 1e3}

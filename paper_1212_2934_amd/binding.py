@@ -210,15 +210,12 @@ class BarnesHut:
         _check("bh_enable_counters", lib().bh_enable_counters(self._h, None, None))
         self._counters = None
 
-    def set_timing_events(self, fwd=None, adj=None):
-        """Record torch.cuda.Event pairs around the traversal kernels (None disables)."""
-        def raw(e):
-            return None if e is None else C.c_void_p(e.cuda_event)
-        f0, f1 = fwd if fwd else (None, None)
-        a0, a1 = adj if adj else (None, None)
-        self._events = (fwd, adj)
-        _check("bh_set_timing_events", lib().bh_set_timing_events(self._h, raw(f0), raw(f1), raw(a0),
-                                                                  raw(a1)))
+    def set_raw_timing_events(self, events=None):
+        """Record four raw hipEvent_t handles (forward start/stop, adjoint start/stop) around the
+        traversal kernels; None disables."""
+        ev = list(events) if events else [None] * 4
+        self._events = events
+        _check("bh_set_timing_events", lib().bh_set_timing_events(self._h, *ev))
 
     def check_status(self) -> int:
         """Device status flags since the last check (synchronises the stream)."""
@@ -250,6 +247,11 @@ class BarnesHut:
         return {k: v.cpu().numpy() for k, v in out.items()}
 
     def md_step(self, state: dict, mdp: md_params):
+        """One MD step in place on state = {pos, vel, mom, omega: (B, 3, n) float64, step: int64[1]}."""
+        for k in ("pos", "vel", "mom", "omega"):
+            self._as_batch(state[k], k)
+        if not (state["step"].is_cuda and state["step"].dtype == torch.int64 and state["step"].numel() == 1):
+            raise ValueError("step must be a one-element int64 CUDA tensor")
         st = md_state(state["pos"].data_ptr(), state["vel"].data_ptr(), state["mom"].data_ptr(),
                       state["omega"].data_ptr(), state["step"].data_ptr())
         _check("md_step", lib().md_step(self._h, C.byref(st), C.byref(mdp), _stream()))

@@ -48,6 +48,7 @@ void carve(const Layout &Lc, void *base, Workspace &w)
     w.vals[0] = (uint32_t *)take(4 * nt);
     w.vals[1] = (uint32_t *)take(4 * nt);
     w.hist = (uint32_t *)take(4 * (size_t)L.hist_len);
+    w.scan_tmp = (uint32_t *)take(4 * ((size_t)(L.hist_len > L.bin_int ? L.hist_len : L.bin_int) / 4096 + 64));
     w.perm = w.vals[0];
     w.codes = w.keys[0];
     w.spos = (double *)take(3 * 8 * nt);
@@ -66,7 +67,11 @@ void carve(const Layout &Lc, void *base, Workspace &w)
     w.nodes = (NodeRec *)take(sizeof(NodeRec) * mn);
     w.node_level = (int32_t *)take(4 * mn);
     w.node_m64 = (double *)take(4 * 8 * mn);
+    w.node_box = (double *)take(8 * 8 * mn);
+    w.ones = (double *)take(8 * (size_t)L.B);
     w.arrive = (uint32_t *)take(4 * mn);
+    w.lvl = (uint32_t *)take(4 * 128);
+    w.lvl_nodes = (int32_t *)take(4 * mn);
     w.leaf_of = (int32_t *)take(4 * nt);
     w.e_part = (double *)take(8 * (size_t)L.num_waves);
     w.node_adj = (double *)take(8 * 8 * mn);
@@ -99,6 +104,12 @@ static bool dptr_ok(const void *p) { return p && ((uintptr_t)p % 8) == 0; }
 __global__ void k_clear_status(uint32_t *status)
 {
     if (threadIdx.x < 16) status[threadIdx.x] = 0u;
+}
+
+__global__ void k_init(uint32_t *status, double *ones, int64_t B)
+{
+    if (threadIdx.x < 16) status[threadIdx.x] = 0u;
+    for (int64_t b = threadIdx.x; b < B; b += blockDim.x) ones[b] = 1.0;
 }
 
 __global__ __launch_bounds__(256) void k_export(const NodeRec *__restrict__ nodes,
@@ -176,7 +187,7 @@ bh_status bh_create(const bh_params *p, void *d_workspace, size_t workspace_byte
     h.waves_per_block = kTuneWaves[p->tuning_id < 0 ? 0 : p->tuning_id];
     h.cnt_far = h.cnt_near = nullptr;
     for (int k = 0; k < 4; ++k) h.ev[k] = nullptr;
-    hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(64), 0, 0, h.w.status);
+    hipLaunchKernelGGL(k_init, dim3(1), dim3(256), 0, 0, h.w.status, h.w.ones, (int64_t)L.B);
     if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
         delete hh;
         return BH_EDEVICE;

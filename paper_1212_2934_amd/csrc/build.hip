@@ -128,30 +128,98 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint64_t *__r
     hist[((int64_t)b * kRadixBins + threadIdx.x) * tiles + t] = cnt[threadIdx.x];
 }
 
-// Exclusive scan of a uint32 array in place by one workgroup (len up to a few million).
-__global__ __launch_bounds__(1024) void k_scan_excl(uint32_t *__restrict__ a, int64_t len,
-                                                   uint32_t *__restrict__ total)
+// Device-wide exclusive scan of a uint32 array in place, in three launches: per-tile sums, a scan of
+// the tile sums (one workgroup), and the per-tile scan with its offset.  Tiles are kScanTile entries,
+// read and written through LDS so that global accesses are coalesced.
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+__device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t *sh, uint32_t &total)
 {
-    __shared__ uint32_t part[1024];
-    const int64_t chunk = (len + 1023) / 1024;
-    const int64_t lo = threadIdx.x * chunk, hi = min(lo + chunk, len);
-    uint32_t s = 0;
-    for (int64_t i = lo; i < hi; ++i) s += a[i];
-    part[threadIdx.x] = s;
+    // inclusive Hillis-Steele over 256 threads in LDS, then shift
+    const int t = threadIdx.x;
+    sh[t] = v;
     __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        uint32_t v = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0u;
+    for (int off = 1; off < kScanThreads; off <<= 1) {
+        uint32_t x = t >= off ? sh[t - off] : 0u;
         __syncthreads();
-        part[threadIdx.x] += v;
+        sh[t] += x;
         __syncthreads();
     }
-    uint32_t run = threadIdx.x ? part[threadIdx.x - 1] : 0u;
-    for (int64_t i = lo; i < hi; ++i) {
-        uint32_t v = a[i];
-        a[i] = run;
-        run += v;
+    total = sh[kScanThreads - 1];
+    uint32_t r = t ? sh[t - 1] : 0u;
+    __syncthreads();
+    return r;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_tiles(const uint32_t *__restrict__ a, int64_t len,
+                                                             uint32_t *__restrict__ tile_sum)
+{
+    __shared__ uint32_t sh[kScanThreads];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    uint32_t s = 0;
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t i = base + (int64_t)k * kScanThreads + threadIdx.x;
+        if (i < len) s += a[i];
     }
-    if (threadIdx.x == 1023 && total) *total = part[1023];
+    uint32_t total;
+    block_excl_scan(s, sh, total);
+    if (threadIdx.x == 0) tile_sum[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_sums(uint32_t *__restrict__ tile_sum, int ntiles,
+                                                            uint32_t *__restrict__ total_out)
+{
+    __shared__ uint32_t sh[kScanThreads];
+    uint32_t carry = 0;
+    for (int base = 0; base < ntiles; base += kScanThreads) {
+        const int i = base + (int)threadIdx.x;
+        uint32_t v = i < ntiles ? tile_sum[i] : 0u;
+        uint32_t tot;
+        uint32_t ex = block_excl_scan(v, sh, tot);
+        if (i < ntiles) tile_sum[i] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0 && total_out) *total_out = carry;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_apply(uint32_t *__restrict__ a, int64_t len,
+                                                             const uint32_t *__restrict__ tile_off)
+{
+    __shared__ uint32_t tile[kScanTile];
+    __shared__ uint32_t sh[kScanThreads];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    for (int k = 0; k < kScanItems; ++k) {
+        const int j = k * kScanThreads + threadIdx.x;
+        tile[j] = base + j < len ? a[base + j] : 0u;
+    }
+    __syncthreads();
+    // each thread scans its own run of kScanItems consecutive entries
+    uint32_t run = 0;
+    for (int k = 0; k < kScanItems; ++k) run += tile[threadIdx.x * kScanItems + k];
+    uint32_t total;
+    uint32_t off = block_excl_scan(run, sh, total) + tile_off[blockIdx.x];
+    for (int k = 0; k < kScanItems; ++k) {
+        const int j = threadIdx.x * kScanItems + k;
+        const uint32_t v = tile[j];
+        tile[j] = off;
+        off += v;
+    }
+    __syncthreads();
+    for (int k = 0; k < kScanItems; ++k) {
+        const int j = k * kScanThreads + threadIdx.x;
+        if (base + j < len) a[base + j] = tile[j];
+    }
+}
+
+// Exclusive scan in place; writes the total to *total if not null.  scratch: one uint32 per tile.
+static void scan_excl(uint32_t *a, int64_t len, uint32_t *scratch, uint32_t *total, hipStream_t s)
+{
+    const int ntiles = (int)((len + kScanTile - 1) / kScanTile);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(ntiles), dim3(kScanThreads), 0, s, a, len, scratch);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanThreads), 0, s, scratch, ntiles, total);
+    hipLaunchKernelGGL(k_scan_apply, dim3(ntiles), dim3(kScanThreads), 0, s, a, len, scratch);
 }
 
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
@@ -464,79 +532,135 @@ __global__ __launch_bounds__(256) void k_oct_link(int64_t nint_tot, int64_t B, c
 }
 
 // ------------------------------------------------------------------------------------------------
-// Upward pass.  A leaf sums its members in sorted order from +0.0; the last child to arrive at a parent
-// sums the children's sums in octant order (the order they are stored in).  Arrival counters are
-// compared modulo the child count, so repeated passes need no reset.
-//   MODE 0: positions -> centroid S / count and squared side into the node record.
+// Upward pass, level by level from the deepest cell level to the root.  A leaf sums its members in
+// sorted order starting from +0.0; a parent sums its children's sums in octant order (the order they
+// are stored in).  Every child of a level-l cell sits at a deeper level, so one launch per level (21
+// down to 0) sees all children finished.  Nodes are bucketed by level once per build.
+//   MODE 0: positions -> centroid S / count and squared side into the node record, and the exact
+//           bounding box of the members (used by short-range neighbour queries).
 //   MODE 1: moments   -> FP64 moment sum into node_m64 and its FP32 rounding into the record.
 // ------------------------------------------------------------------------------------------------
 
-template <int MODE>
-__device__ inline void finish_node(NodeRec *nodes, double *sums, double *node_m64,
-                                   const int32_t *node_level, int id, const double *bbox_b)
+__global__ __launch_bounds__(256) void k_level_count(const int32_t *__restrict__ node_level,
+                                                     const uint32_t *__restrict__ num_nodes, int64_t max_nodes,
+                                                     uint32_t *__restrict__ lvl)
 {
-    const double sx = sums[4 * id], sy = sums[4 * id + 1], sz = sums[4 * id + 2];
-    if (MODE == 0) {
-        const double c = (double)nodes[id].count;
-        nodes[id].cx = sx / c;
-        nodes[id].cy = sy / c;
-        nodes[id].cz = sz / c;
-        const double s = __builtin_ldexp(bbox_b[3], -node_level[id]);
-        nodes[id].s2 = s * s;
-    } else {
-        node_m64[4 * id] = sx;
-        node_m64[4 * id + 1] = sy;
-        node_m64[4 * id + 2] = sz;
-        nodes[id].mx = (float)sx;
-        nodes[id].my = (float)sy;
-        nodes[id].mz = (float)sz;
+    __shared__ uint32_t h[kMaxLevel + 1];
+    if (threadIdx.x <= kMaxLevel) h[threadIdx.x] = 0u;
+    __syncthreads();
+    const int64_t nn = min((int64_t)*num_nodes, max_nodes);
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nn; i += (int64_t)gridDim.x * 256)
+        atomicAdd(&h[node_level[i]], 1u);
+    __syncthreads();
+    if (threadIdx.x <= kMaxLevel && h[threadIdx.x]) atomicAdd(&lvl[threadIdx.x], h[threadIdx.x]);
+}
+
+// lvl[0..21] counts -> lvl[32..54] bucket starts (exclusive, 23 entries), lvl[64..85] cursors.
+__global__ void k_level_starts(uint32_t *lvl)
+{
+    if (threadIdx.x != 0) return;
+    uint32_t acc = 0;
+    for (int l = 0; l <= kMaxLevel; ++l) {
+        lvl[32 + l] = acc;
+        lvl[64 + l] = acc;
+        acc += lvl[l];
+    }
+    lvl[32 + kMaxLevel + 1] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_level_scatter(const int32_t *__restrict__ node_level,
+                                                       const uint32_t *__restrict__ num_nodes, int64_t max_nodes,
+                                                       uint32_t *__restrict__ lvl, int32_t *__restrict__ lvl_nodes)
+{
+    const int64_t nn = min((int64_t)*num_nodes, max_nodes);
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nn; i += (int64_t)gridDim.x * 256) {
+        const uint32_t at = atomicAdd(&lvl[64 + node_level[i]], 1u);
+        lvl_nodes[at] = (int32_t)i;
+    }
+}
+
+__global__ void k_zero_u32(uint32_t *a, int len)
+{
+    for (int i = threadIdx.x; i < len; i += blockDim.x) a[i] = 0u;
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_upward_level(const double *__restrict__ vals, int64_t ntot, int64_t n,
+                                                      NodeRec *__restrict__ nodes, double *__restrict__ sums,
+                                                      double *__restrict__ node_m64,
+                                                      const int32_t *__restrict__ node_level,
+                                                      const uint32_t *__restrict__ lvl,
+                                                      const int32_t *__restrict__ lvl_nodes,
+                                                      const double *__restrict__ bbox, double *__restrict__ node_box,
+                                                      int level)
+{
+    const uint32_t b0 = lvl[32 + level], b1 = lvl[32 + level + 1];
+    for (uint32_t q = b0 + blockIdx.x * 256 + threadIdx.x; q < b1; q += gridDim.x * 256) {
+        const int id = lvl_nodes[q];
+        const NodeRec nd = nodes[id];
+        double sx = 0.0, sy = 0.0, sz = 0.0;
+        double lo[3] = {__builtin_inf(), __builtin_inf(), __builtin_inf()};
+        double hi[3] = {-__builtin_inf(), -__builtin_inf(), -__builtin_inf()};
+        if (nd.nchild == 0) {
+            for (int k = nd.first; k < nd.first + nd.count; ++k) {
+                const double x = vals[k], y = vals[ntot + k], z = vals[2 * ntot + k];
+                sx = sx + x;
+                sy = sy + y;
+                sz = sz + z;
+                if (MODE == 0) {
+                    lo[0] = fmin(lo[0], x); lo[1] = fmin(lo[1], y); lo[2] = fmin(lo[2], z);
+                    hi[0] = fmax(hi[0], x); hi[1] = fmax(hi[1], y); hi[2] = fmax(hi[2], z);
+                }
+            }
+        } else {
+            for (int c = nd.child; c < nd.child + nd.nchild; ++c) {
+                sx = sx + sums[4 * c];
+                sy = sy + sums[4 * c + 1];
+                sz = sz + sums[4 * c + 2];
+                if (MODE == 0) {
+                    for (int a = 0; a < 3; ++a) {
+                        lo[a] = fmin(lo[a], node_box[8 * c + a]);
+                        hi[a] = fmax(hi[a], node_box[8 * c + 4 + a]);
+                    }
+                }
+            }
+        }
+        if (MODE == 0) {
+            for (int a = 0; a < 3; ++a) {
+                node_box[8 * id + a] = lo[a];
+                node_box[8 * id + 4 + a] = hi[a];
+            }
+        }
+        sums[4 * id] = sx;
+        sums[4 * id + 1] = sy;
+        sums[4 * id + 2] = sz;
+        if (MODE == 0) {
+            const double cnt = (double)nd.count;
+            nodes[id].cx = sx / cnt;
+            nodes[id].cy = sy / cnt;
+            nodes[id].cz = sz / cnt;
+            const double side = __builtin_ldexp(bbox[8 * (nd.first / n) + 3], -node_level[id]);
+            nodes[id].s2 = side * side;
+        } else {
+            node_m64[4 * id] = sx;
+            node_m64[4 * id + 1] = sy;
+            node_m64[4 * id + 2] = sz;
+            nodes[id].mx = (float)sx;
+            nodes[id].my = (float)sy;
+            nodes[id].mz = (float)sz;
+        }
     }
 }
 
 template <int MODE>
-__global__ __launch_bounds__(256) void k_upward(const double *__restrict__ vals, int64_t ntot, int64_t n,
-                                                NodeRec *nodes, double *sums, double *node_m64,
-                                                const int32_t *__restrict__ node_level, uint32_t *arrive,
-                                                const uint32_t *__restrict__ num_nodes,
-                                                const double *__restrict__ bbox, int64_t max_nodes)
+static void upward(Handle &h, const double *vals, hipStream_t s)
 {
-    const int id0 = blockIdx.x * 256 + threadIdx.x;
-    if (id0 >= (int)*num_nodes || id0 >= max_nodes) return;
-    if (nodes[id0].nchild != 0) return;
-    const int first = nodes[id0].first, cnt = nodes[id0].count;
-    const double *bb = bbox + 8 * (first / n);
-    double sx = 0.0, sy = 0.0, sz = 0.0;
-    for (int k = first; k < first + cnt; ++k) {
-        sx = sx + vals[k];
-        sy = sy + vals[ntot + k];
-        sz = sz + vals[2 * ntot + k];
-    }
-    sums[4 * id0] = sx;
-    sums[4 * id0 + 1] = sy;
-    sums[4 * id0 + 2] = sz;
-    finish_node<MODE>(nodes, sums, node_m64, node_level, id0, bb);
-    int id = id0;
-    for (int depth = 0; depth < 2 * kMaxLevel + 2; ++depth) {  // a leaf has at most 22 ancestors
-        const int p = nodes[id].parent;
-        if (p < 0) break;
-        const uint32_t nc = (uint32_t)nodes[p].nchild;
-        const uint32_t prev = __hip_atomic_fetch_add(&arrive[p], 1u, __ATOMIC_ACQ_REL,
-                                                     __HIP_MEMORY_SCOPE_AGENT);
-        if ((prev + 1u) % nc != 0u) break;
-        const int c0 = nodes[p].child;
-        double ax = 0.0, ay = 0.0, az = 0.0;
-        for (uint32_t q = 0; q < nc; ++q) {
-            const int c = c0 + (int)q;
-            ax = ax + __hip_atomic_load(&sums[4 * c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            ay = ay + __hip_atomic_load(&sums[4 * c + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            az = az + __hip_atomic_load(&sums[4 * c + 2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        sums[4 * p] = ax;
-        sums[4 * p + 1] = ay;
-        sums[4 * p + 2] = az;
-        finish_node<MODE>(nodes, sums, node_m64, node_level, p, bb);
-        id = p;
-    }
+    const Layout &L = h.L;
+    Workspace &w = h.w;
+    const unsigned g = grid_for(L.max_nodes, 256, 512);
+    for (int level = kMaxLevel; level >= 0; --level)
+        hipLaunchKernelGGL(k_upward_level<MODE>, dim3(g), dim3(256), 0, s, vals, L.ntot, L.n, w.nodes, w.node_adj,
+                           w.node_m64, w.node_level, w.lvl, w.lvl_nodes, w.bbox, w.node_box, level);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -566,8 +690,7 @@ hipError_t launch_build(Handle &h, const double *d_pos, hipStream_t s)
         const int shift = pass * kRadixBits;
         hipLaunchKernelGGL(k_radix_hist, dim3(sblocks), dim3(kSortThreads), 0, s, w.keys[src], n, tiles,
                            shift, w.hist);
-        hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, s, w.hist, (int64_t)L.hist_len,
-                           (uint32_t *)nullptr);
+        scan_excl(w.hist, (int64_t)L.hist_len, w.scan_tmp, nullptr, s);
         hipLaunchKernelGGL(k_radix_scatter, dim3(sblocks), dim3(kSortThreads), 0, s, w.keys[src],
                            w.vals[src], w.keys[dst], w.vals[dst], w.hist, n, tiles, shift);
     }
@@ -582,7 +705,7 @@ hipError_t launch_build(Handle &h, const double *d_pos, hipStream_t s)
         hipLaunchKernelGGL(k_oct_count, dim3(grid_for(nint, 256)), dim3(256), 0, s, n, nint,
                            (int)h.p.leaf_size, w.bin_left, w.bin_right, w.bin_first, w.bin_last,
                            w.bin_delta, w.bin_parent, w.bin_nchild, w.bin_scan, w.status);
-        hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, s, w.bin_scan, nint, w.status + 1);
+        scan_excl(w.bin_scan, nint, w.scan_tmp, w.status + 1, s);
     }
     hipLaunchKernelGGL(k_oct_emit, dim3(grid_for(nint > B ? nint : B, 256)), dim3(256), 0, s, n, nint, B,
                        (int)h.p.leaf_size, w.bin_left, w.bin_right, w.bin_first, w.bin_last, w.bin_delta,
@@ -591,8 +714,14 @@ hipError_t launch_build(Handle &h, const double *d_pos, hipStream_t s)
     if (nint > 0)
         hipLaunchKernelGGL(k_oct_link, dim3(grid_for(nint, 256)), dim3(256), 0, s, nint, B,
                            w.bin_nchild, w.bin_scan, w.bin_octid, w.nodes);
-    hipLaunchKernelGGL(k_upward<0>, dim3(grid_for(L.max_nodes, 256)), dim3(256), 0, s, w.spos, ntot, n,
-                       w.nodes, w.node_adj, w.node_m64, w.node_level, w.arrive, w.status + 2, w.bbox, L.max_nodes);
+    // bucket the nodes by level, then the upward pass for the centroids
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(128), 0, s, w.lvl, 128);
+    hipLaunchKernelGGL(k_level_count, dim3(grid_for(L.max_nodes, 256, 1024)), dim3(256), 0, s, w.node_level,
+                       w.status + 2, L.max_nodes, w.lvl);
+    hipLaunchKernelGGL(k_level_starts, dim3(1), dim3(64), 0, s, w.lvl);
+    hipLaunchKernelGGL(k_level_scatter, dim3(grid_for(L.max_nodes, 256, 1024)), dim3(256), 0, s, w.node_level,
+                       w.status + 2, L.max_nodes, w.lvl, w.lvl_nodes);
+    upward<0>(h, w.spos, s);
     return hipGetLastError();
 }
 
@@ -606,8 +735,7 @@ hipError_t launch_upward_moments(Handle &h, const double *d_mom, hipStream_t s)
     Workspace &w = h.w;
     hipLaunchKernelGGL(k_gather3, dim3(grid_for(L.ntot, 256)), dim3(256), 0, s, d_mom, w.perm, L.n,
                        L.ntot, w.smom, w.smom32, w.status);
-    hipLaunchKernelGGL(k_upward<1>, dim3(grid_for(L.max_nodes, 256)), dim3(256), 0, s, w.smom, L.ntot,
-                       L.n, w.nodes, w.node_adj, w.node_m64, w.node_level, w.arrive, w.status + 2, w.bbox, L.max_nodes);
+    upward<1>(h, w.smom, s);
     return hipGetLastError();
 }
 

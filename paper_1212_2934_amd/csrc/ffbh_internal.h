@@ -43,6 +43,7 @@ struct Workspace {
     uint64_t *keys[2];       // N_tot sort keys (ping-pong)
     uint32_t *vals[2];       // N_tot sort values: global original index (ping-pong)
     uint32_t *hist;          // radix histograms (B x 256 x tiles_per_system)
+    uint32_t *scan_tmp;      // per-tile partial sums of the device-wide scan
     uint32_t *perm;          // sorted position -> global original index (alias of the final vals)
     uint64_t *codes;         // sorted codes (alias of the final keys)
     double *spos;            // 3 x N_tot sorted positions (SoA: x block, y block, z block)
@@ -63,7 +64,11 @@ struct Workspace {
     NodeRec *nodes;          // max_nodes
     int32_t *node_level;     // max_nodes: cell level (side = side_root / 2^level)
     double *node_m64;        // 4 x max_nodes: moment sum FP64 (x, y, z, pad) per node
-    uint32_t *arrive;        // max_nodes: upward-pass arrival counters
+    double *node_box;        // 8 x max_nodes: member bounding box (lo xyz, pad, hi xyz, pad)
+    double *ones;            // B: constant 1.0 (dL/dE for the MD force)
+    uint32_t *arrive;        // max_nodes: (unused) arrival counters
+    uint32_t *lvl;           // 128: per-level node counts [0,22), bucket starts [32,55), cursors [64,86)
+    int32_t *lvl_nodes;      // max_nodes: node ids bucketed by level
     int32_t *leaf_of;        // N_tot: sorted particle -> its leaf
     // traversal outputs and adjoint accumulators
     double *e_part;          // per wave energy partials

@@ -149,14 +149,22 @@ __global__ __launch_bounds__(512) void k_field(
     }
 }
 
-// E of every system: ordered sum of its waves' partials.
-__global__ void k_energy_final(const double *__restrict__ e_part, int waves_per_seg, double *__restrict__ E)
+// E of every system: sum of its waves' partials in a fixed order (strided per thread, then a fixed
+// LDS tree), so repeated runs give the same bits.
+__global__ __launch_bounds__(256) void k_energy_final(const double *__restrict__ e_part, int waves_per_seg,
+                                                      double *__restrict__ E)
 {
+    __shared__ double red[256];
     const int b = blockIdx.x;
-    if (threadIdx.x != 0) return;
     double s = 0.0;
-    for (int w = 0; w < waves_per_seg; ++w) s += e_part[(int64_t)b * waves_per_seg + w];
-    E[b] = s;
+    for (int w = threadIdx.x; w < waves_per_seg; w += 256) s += e_part[(int64_t)b * waves_per_seg + w];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) E[b] = red[0];
 }
 
 template <bool MIXED, bool COUNT>
@@ -188,7 +196,7 @@ hipError_t launch_field(Handle &h, const double *d_mom, const double *d_hext, do
     if (h.ev[1]) (void)hipEventRecord(h.ev[1], s);
     if (d_E) {
         const int waves_per_seg = (int)((h.L.n + kWave - 1) / kWave);
-        hipLaunchKernelGGL(k_energy_final, dim3((unsigned)h.L.B), dim3(64), 0, s, h.w.e_part, waves_per_seg,
+        hipLaunchKernelGGL(k_energy_final, dim3((unsigned)h.L.B), dim3(256), 0, s, h.w.e_part, waves_per_seg,
                            d_E);
     }
     return hipGetLastError();

@@ -1,11 +1,252 @@
-// Langevin MD step (placeholder until the integrator lands).
-#include "ffbh_internal.h"
+// One Langevin MD step (Sec. 2 equations of motion in vector form, integrated with the explicit
+// Euler-Maruyama scheme of Sec. 4; Sec. 3.2 kernel 6): tree build, Barnes-Hut field and energy gradient
+// (fused forward + adjoint), a WCA short-range repulsion between particles and against the container
+// walls found by a tree range query, and the update of positions, velocities, moments and angular
+// velocities from the state at the start of the step.
+//
+// Readings: the paper writes the rotation in polar angles (with the theta/phi equations garbled); the
+// vector form used here is m' = R(omega dt) m with I domega/dt = m x H_eff - gamma_r omega + noise,
+// H_eff = -dE/dm.  Noise per Cartesian component has variance 2 gamma kT dt (fluctuation-dissipation).
+// The paper's "Lennard-Jones" term is replaced by its purely repulsive WCA part (cut at 2^(1/6) sigma,
+// shifted to zero there), walls act on the centre-to-face distance with sigma_w = sigma / 2.
+// Thermal noise: Philox4x32-10 (Salmon et al., SC'11) keyed by (seed, system), counter (step, particle,
+// draw), mapped to normals by the Box-Muller transform.
+#include "traverse.h"
 
 namespace ffbh {
 
-hipError_t launch_md(Handle &, const md_state *, const md_params *, hipStream_t)
+// ---- Philox4x32-10 ----------------------------------------------------------------------------------
+
+struct U4 {
+    uint32_t x, y, z, w;
+};
+
+__device__ inline U4 philox_round(U4 c, uint32_t k0, uint32_t k1)
 {
-    return hipErrorNotSupported;
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+    U4 r;
+    r.x = (uint32_t)(p1 >> 32) ^ c.y ^ k0;
+    r.y = (uint32_t)p1;
+    r.z = (uint32_t)(p0 >> 32) ^ c.w ^ k1;
+    r.w = (uint32_t)p0;
+    return r;
+}
+
+__device__ inline U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        c = philox_round(c, k0, k1);
+    }
+    return c;
+}
+
+__device__ inline double u01(uint32_t x) { return ((double)x + 0.5) * (1.0 / 4294967296.0); }
+
+// Two standard normals from two 32-bit words (Box-Muller).
+__device__ inline void box_muller(uint32_t a, uint32_t b, double &n0, double &n1)
+{
+    const double r = sqrt(-2.0 * log(u01(a)));
+    const double t = 6.283185307179586 * u01(b);
+    n0 = r * cos(t);
+    n1 = r * sin(t);
+}
+
+// ---- WCA short-range forces (tree range query) --------------------------------------------------------
+
+// Force on a particle at offset x = r_i - r_k from a WCA partner: 24 eps [2 (s/r)^12 - (s/r)^6] x / r^2.
+__device__ inline void wca_pair(double x, double y, double z, double s2, double eps, double rc2, double &fx,
+                                double &fy, double &fz)
+{
+    const double r2 = x * x + y * y + z * z;
+    if (r2 >= rc2 || r2 <= 0.0) return;
+    const double sr2 = s2 / r2;
+    const double sr6 = sr2 * sr2 * sr2;
+    const double f = 24.0 * eps * (2.0 * sr6 * sr6 - sr6) / r2;
+    fx += f * x;
+    fy += f * y;
+    fz += f * z;
+}
+
+// Wall force along one axis for centre-to-face distances dlo (to the lower face) and dhi.
+__device__ inline double wall_force(double dlo, double dhi, double sw, double eps)
+{
+    const double rcw = 1.122462048309373 * sw;  // 2^(1/6) sigma_w
+    const double dmin = 0.1 * sw;
+    double f = 0.0;
+    if (dlo < rcw) {
+        const double d = dlo > dmin ? dlo : dmin;
+        const double s6 = (sw / d) * (sw / d) * (sw / d) * (sw / d) * (sw / d) * (sw / d);
+        f += 24.0 * eps * (2.0 * s6 * s6 - s6) / d;
+    }
+    if (dhi < rcw) {
+        const double d = dhi > dmin ? dhi : dmin;
+        const double s6 = (sw / d) * (sw / d) * (sw / d) * (sw / d) * (sw / d) * (sw / d);
+        f -= 24.0 * eps * (2.0 * s6 * s6 - s6) / d;
+    }
+    return f;
+}
+
+__global__ __launch_bounds__(256) void k_wca(const NodeRec *__restrict__ nodes, const double *__restrict__ node_box,
+                                             const double *__restrict__ spos, const uint32_t *__restrict__ perm,
+                                             double *__restrict__ F, uint32_t *__restrict__ status, int64_t n,
+                                             int64_t ntot, int waves_per_seg, int num_waves, int max_nodes,
+                                             double sigma, double eps, double3 box_lo, double3 box_hi)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wpb = blockDim.x / kWave;
+    const int gw = xcd_block(blockIdx.x, gridDim.x) * wpb + (int)(threadIdx.x / kWave);
+    if (gw >= num_waves) return;
+    const int seg = gw / waves_per_seg;
+    const int local = (gw - seg * waves_per_seg) * kWave + lane;
+    const bool valid = local < n;
+    const int si = (int)(seg * n) + (valid ? local : 0);
+    const double rx = spos[si], ry = spos[ntot + si], rz = spos[2 * ntot + si];
+    const double rc = 1.122462048309373 * sigma, rc2 = rc * rc, s2 = sigma * sigma;
+    double fx = 0.0, fy = 0.0, fz = 0.0;
+
+    LaneStack st{0, 0, 0, 0, 0};
+    st.push(lane, seg, seg + 1, __ballot(valid));
+    int guard = max_nodes;
+    while (st.sp > 0 && eps > 0.0) {
+        uint64_t mask;
+        const int cur = st.pop(lane, mask);
+        if (--guard < 0 || (unsigned)cur >= (unsigned)max_nodes) {
+            if (lane == 0) set_flag(status, BH_FLAG_TREE);
+            break;
+        }
+        const NodeRec nd = nodes[cur];
+        const double *bx = node_box + 8 * (int64_t)cur;
+        const bool active = (mask >> lane) & 1ull;
+        // squared distance from the target to the members' bounding box
+        const double ex = fmax(fmax(bx[0] - rx, rx - bx[4]), 0.0);
+        const double ey = fmax(fmax(bx[1] - ry, ry - bx[5]), 0.0);
+        const double ez = fmax(fmax(bx[2] - rz, rz - bx[6]), 0.0);
+        const bool hit = active && (ex * ex + ey * ey + ez * ez < rc2);
+        const uint64_t open = __ballot(hit);
+        if (open == 0ull) continue;
+        if (nd.nchild != 0) {
+            if (st.sp >= kStackMax) {
+                if (lane == 0) set_flag(status, BH_FLAG_STACK);
+                break;
+            }
+            st.push(lane, nd.child, nd.child + nd.nchild, open);
+            continue;
+        }
+        const bool me = (open >> lane) & 1ull;
+        for (int k = nd.first; k < nd.first + nd.count; ++k) {
+            const double sx = spos[k], sy = spos[ntot + k], sz = spos[2 * ntot + k];
+            if (me && k != si) wca_pair(rx - sx, ry - sy, rz - sz, s2, eps, rc2, fx, fy, fz);
+        }
+    }
+    if (!valid) return;
+    // container walls
+    const double sw = 0.5 * sigma;
+    if (eps > 0.0) {
+        fx += wall_force(rx - box_lo.x, box_hi.x - rx, sw, eps);
+        fy += wall_force(ry - box_lo.y, box_hi.y - ry, sw, eps);
+        fz += wall_force(rz - box_lo.z, box_hi.z - rz, sw, eps);
+    }
+    const int64_t o = perm[si];
+    const int64_t i = o - (int64_t)seg * n;
+    double *out = F + (int64_t)seg * 3 * n;
+    out[i] = fx;
+    out[n + i] = fy;
+    out[2 * n + i] = fz;
+}
+
+// ---- integrator ---------------------------------------------------------------------------------------
+
+struct MDConst {
+    double dt, kT, gamma_t, gamma_r, mass, inertia;
+    uint64_t seed;
+};
+
+__global__ __launch_bounds__(256) void k_integrate(double *__restrict__ pos, double *__restrict__ vel,
+                                                   double *__restrict__ mom, double *__restrict__ omega,
+                                                   const double *__restrict__ dEdr, const double *__restrict__ dEdm,
+                                                   const double *__restrict__ Fsr, const uint64_t *__restrict__ d_step,
+                                                   int64_t n, int64_t ntot, MDConst c)
+{
+    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (g >= ntot) return;
+    const int64_t b = g / n, i = g - b * n;
+    const int64_t o = b * 3 * n + i;  // x component; y at +n, z at +2n
+    const uint64_t step = *d_step;
+    // noise: two Philox blocks -> eight normals, six used
+    const uint32_t k0 = (uint32_t)c.seed, k1 = (uint32_t)(c.seed >> 32) ^ (uint32_t)b;
+    const U4 q0 = philox4x32_10(U4{(uint32_t)step, (uint32_t)(step >> 32), (uint32_t)i, 0u}, k0, k1);
+    const U4 q1 = philox4x32_10(U4{(uint32_t)step, (uint32_t)(step >> 32), (uint32_t)i, 1u}, k0, k1);
+    double xi[8];
+    box_muller(q0.x, q0.y, xi[0], xi[1]);
+    box_muller(q0.z, q0.w, xi[2], xi[3]);
+    box_muller(q1.x, q1.y, xi[4], xi[5]);
+    box_muller(q1.z, q1.w, xi[6], xi[7]);
+
+    const double r[3] = {pos[o], pos[o + n], pos[o + 2 * n]};
+    const double v[3] = {vel[o], vel[o + n], vel[o + 2 * n]};
+    const double m[3] = {mom[o], mom[o + n], mom[o + 2 * n]};
+    const double w[3] = {omega[o], omega[o + n], omega[o + 2 * n]};
+    const double F[3] = {-dEdr[o] + Fsr[o], -dEdr[o + n] + Fsr[o + n], -dEdr[o + 2 * n] + Fsr[o + 2 * n]};
+    const double He[3] = {-dEdm[o], -dEdm[o + n], -dEdm[o + 2 * n]};
+    const double tq[3] = {m[1] * He[2] - m[2] * He[1], m[2] * He[0] - m[0] * He[2], m[0] * He[1] - m[1] * He[0]};
+    const double at = sqrt(2.0 * c.gamma_t * c.kT * c.dt) / c.mass;
+    const double ar = sqrt(2.0 * c.gamma_r * c.kT * c.dt) / c.inertia;
+    double vn[3], rn[3], wn[3];
+    for (int a = 0; a < 3; ++a) {
+        vn[a] = v[a] + (c.dt / c.mass) * (F[a] - c.gamma_t * v[a]) + at * xi[a];
+        rn[a] = r[a] + c.dt * v[a];
+        wn[a] = w[a] + (c.dt / c.inertia) * (tq[a] - c.gamma_r * w[a]) + ar * xi[3 + a];
+    }
+    // rotate m by the angle |omega| dt about omega (Rodrigues), then renormalise
+    double mn[3] = {m[0], m[1], m[2]};
+    const double wl = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+    if (wl > 0.0) {
+        const double u[3] = {w[0] / wl, w[1] / wl, w[2] / wl};
+        const double ph = wl * c.dt, cs = cos(ph), sn = sin(ph);
+        const double ud = u[0] * m[0] + u[1] * m[1] + u[2] * m[2];
+        const double ux[3] = {u[1] * m[2] - u[2] * m[1], u[2] * m[0] - u[0] * m[2], u[0] * m[1] - u[1] * m[0]};
+        for (int a = 0; a < 3; ++a) mn[a] = m[a] * cs + ux[a] * sn + u[a] * ud * (1.0 - cs);
+    }
+    const double ml = sqrt(mn[0] * mn[0] + mn[1] * mn[1] + mn[2] * mn[2]);
+    for (int a = 0; a < 3; ++a) {
+        pos[o + a * n] = rn[a];
+        vel[o + a * n] = vn[a];
+        omega[o + a * n] = wn[a];
+        mom[o + a * n] = mn[a] / ml;
+    }
+}
+
+__global__ void k_step_inc(uint64_t *d_step)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *d_step += 1ull;
+}
+
+hipError_t launch_md(Handle &h, const md_state *st, const md_params *mp, hipStream_t s)
+{
+    const Layout &L = h.L;
+    Workspace &w = h.w;
+    hipError_t e = launch_build(h, st->pos, s);
+    if (e != hipSuccess) return e;
+    e = launch_backward(h, st->mom, mp->d_hext, nullptr, w.ones, w.md_grad_r, w.md_grad_m, nullptr, s);
+    if (e != hipSuccess) return e;
+    const int wpb = h.waves_per_block;
+    const unsigned blocks = (unsigned)((L.num_waves + wpb - 1) / wpb);
+    const int waves_per_seg = (int)((L.n + kWave - 1) / kWave);
+    hipLaunchKernelGGL(k_wca, dim3(blocks), dim3(wpb * kWave), 0, s, w.nodes, w.node_box, w.spos, w.perm, w.md_force,
+                       w.status, L.n, L.ntot, waves_per_seg, (int)L.num_waves, (int)L.max_nodes, mp->wca_sigma,
+                       mp->wca_eps, make_double3(mp->box_lo[0], mp->box_lo[1], mp->box_lo[2]),
+                       make_double3(mp->box_hi[0], mp->box_hi[1], mp->box_hi[2]));
+    MDConst c{mp->dt, mp->kT, mp->gamma_t, mp->gamma_r, mp->mass, mp->inertia, mp->seed};
+    hipLaunchKernelGGL(k_integrate, dim3(grid_for(L.ntot, 256)), dim3(256), 0, s, st->pos, st->vel, st->mom,
+                       st->omega, w.md_grad_r, w.md_grad_m, w.md_force, st->d_step, L.n, L.ntot, c);
+    hipLaunchKernelGGL(k_step_inc, dim3(1), dim3(64), 0, s, st->d_step);
+    return hipGetLastError();
 }
 
 }  // namespace ffbh

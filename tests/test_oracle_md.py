@@ -1,0 +1,97 @@
+"""Pins of the MD reference: its Philox stream and Box-Muller normals against distribution laws, the
+deterministic friction decay of a free particle (exact geometric law of the Euler scheme), equipartition of
+translational and rotational kinetic energy, and the Langevin magnetisation law <m.h> = L(|h|/kT) of
+non-interacting dipoles (Eq. Langevin, Sec. 5), which fixes the sign of the torque m x H and the noise
+amplitude together."""
+import numpy as np
+import pytest
+
+from oracle import md
+
+
+def test_philox_words_uniform_and_independent():
+    n = 1 << 18
+    i = np.arange(n, dtype=np.uint64)
+    w = md.philox4x32_10(np.full(n, 7), np.zeros(n), i, np.zeros(n), 123, 456)
+    allw = np.concatenate(w)
+    u = (allw.astype(np.float64) + 0.5) / 2 ** 32
+    assert abs(u.mean() - 0.5) < 2e-3
+    # every bit is set half of the time
+    for bit in range(32):
+        f = ((allw >> np.uint64(bit)) & np.uint64(1)).mean()
+        assert abs(f - 0.5) < 3e-3, bit
+    # chi-square over 256 equal bins
+    h = np.bincount((allw >> np.uint64(24)).astype(np.int64), minlength=256)
+    chi2 = ((h - allw.size / 256) ** 2 / (allw.size / 256)).sum()
+    assert chi2 < 400  # 255 dof: mean 255, sd ~23
+    # neighbouring counters and the four words are uncorrelated
+    for a in range(4):
+        for b in range(a + 1, 4):
+            assert abs(np.corrcoef(w[a].astype(float), w[b].astype(float))[0, 1]) < 0.01
+    assert abs(np.corrcoef(w[0][:-1].astype(float), w[0][1:].astype(float))[0, 1]) < 0.01
+    # a different key gives a different stream
+    w2 = md.philox4x32_10(np.full(n, 7), np.zeros(n), i, np.zeros(n), 124, 456)
+    assert (w2[0] != w[0]).mean() > 0.99
+
+
+def test_normals_moments():
+    x = np.concatenate([md.normals(99, b, s, 20000).ravel() for b in range(2) for s in range(3)])
+    assert abs(x.mean()) < 0.01
+    assert abs(x.var() - 1.0) < 0.01
+    assert abs((x ** 4).mean() - 3.0) < 0.05
+    assert abs((x ** 3).mean()) < 0.03
+
+
+def _params(**kw):
+    p = dict(dt=1e-3, kT=1.0, gamma_t=0.1, gamma_r=0.1, mass=1.0, inertia=0.1, wca_eps=0.0, wca_sigma=1.0,
+             box_lo=(-1e3, -1e3, -1e3), box_hi=(1e3, 1e3, 1e3), hext=None, seed=5)
+    p.update(kw)
+    return p
+
+
+def test_free_particle_friction_decay():
+    st = dict(pos=np.array([[[0.0], [0.0], [0.0]]]), vel=np.array([[[1.0], [-2.0], [0.5]]]),
+              mom=np.array([[[0.0], [0.0], [1.0]]]), omega=np.array([[[0.3], [0.0], [0.0]]]))
+    p = _params(kT=0.0, gamma_t=2.0, gamma_r=1.0, dt=0.01)
+    v0, r0 = st["vel"].copy(), st["pos"].copy()
+    r_exp = r0.copy()
+    for k in range(50):
+        r_exp = r_exp + p["dt"] * v0 * (1 - p["gamma_t"] * p["dt"]) ** k
+        st = md.md_step(st, p, k)
+    np.testing.assert_allclose(st["vel"], v0 * (1 - p["gamma_t"] * p["dt"]) ** 50, rtol=1e-12)
+    np.testing.assert_allclose(st["pos"], r_exp, rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(st["omega"][0, 0, 0], 0.3 * (1 - p["gamma_r"] * p["dt"] / p["inertia"]) ** 50,
+                               rtol=1e-12)
+    assert abs(np.linalg.norm(st["mom"][0, :, 0]) - 1.0) < 1e-14
+
+
+def test_equipartition_noninteracting():
+    rng = np.random.default_rng(3)
+    n = 3000
+    st = dict(pos=rng.uniform(-50, 50, (1, 3, n)), vel=np.zeros((1, 3, n)),
+              mom=np.tile(np.array([[[0.0], [0.0], [1.0]]]), (1, 1, n)), omega=np.zeros((1, 3, n)))
+    p = _params(gamma_t=1.0, gamma_r=1.0, dt=0.01)
+    v2, w2 = [], []
+    for k in range(1500):
+        st = md.md_step(st, p, k, field=False)
+        if k >= 500:
+            v2.append((st["vel"] ** 2).sum(axis=1).mean())
+            w2.append((st["omega"] ** 2).sum(axis=1).mean())
+    assert abs(np.mean(v2) / (3 * p["kT"] / p["mass"]) - 1.0) < 0.05
+    assert abs(np.mean(w2) / (3 * p["kT"] / p["inertia"]) - 1.0) < 0.15  # EM bias O(gamma_r dt / I)
+
+
+@pytest.mark.parametrize("alpha", [0.7, 2.0])
+def test_langevin_magnetisation_law(alpha):
+    rng = np.random.default_rng(int(alpha * 10))
+    n = 3000
+    m0 = rng.standard_normal((1, 3, n))
+    m0 /= np.linalg.norm(m0, axis=1, keepdims=True)
+    st = dict(pos=rng.uniform(-50, 50, (1, 3, n)), vel=np.zeros((1, 3, n)), mom=m0, omega=np.zeros((1, 3, n)))
+    p = _params(gamma_r=1.0, gamma_t=1.0, inertia=0.1, dt=2e-3, hext=np.array([[0.0, 0.0, alpha]]))
+    mz = []
+    for k in range(6000):
+        st = md.md_step(st, p, k, field=False)
+        if k >= 1500:
+            mz.append(st["mom"][0, 2].mean())
+    assert abs(np.mean(mz) - md.langevin(alpha)) < 0.015, (np.mean(mz), md.langevin(alpha))
