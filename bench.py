@@ -26,7 +26,7 @@ PEAK_FP32_VECTOR = 157.3e12   # published MI355X FP32 vector peak (packed FMA)
 PEAK_FP32_UNPACKED = 78.6e12  # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz, one FMA per lane
 # algorithmic flops per interaction, fixed from the kernel source (FMA = 2, rsqrt = 1):
 FLOPS_FWD = 30   # 3 FP64 offset subtractions + 27 for the dipole field and its accumulation
-FLOPS_ADJ = 64   # 3 offset + 58 for g and T(x)Hbar + 3 gather accumulation
+FLOPS_ADJ = 75   # 3 offset + 69 for g, T(x)Hbar and the field T(x)m + 3 gather accumulation
 
 
 def log(msg):
@@ -137,10 +137,11 @@ def main():
         t0 = time.perf_counter()
         for _ in range(args.steps):
             step()
-            t_fwd += ev.seconds(0, 1)
-            t_adj += ev.seconds(2, 3)
         torch.cuda.synchronize()
         t_step = (time.perf_counter() - t0) / args.steps
+        for _ in range(args.steps):  # adjoint kernel time, one step at a time
+            step()
+            t_adj += ev.seconds(2, 3)
         # field evaluation alone (build + field)
         for _ in range(args.warmup):
             field_only()
@@ -150,19 +151,23 @@ def main():
             field_only()
         torch.cuda.synchronize()
         t_eval = (time.perf_counter() - t0) / args.steps
+        for _ in range(args.steps):  # forward traversal kernel time
+            field_only()
+            t_fwd += ev.seconds(0, 1)
         assert bh.check_status() == 0
         bh.set_raw_timing_events(None)
         res[precision] = dict(t_step=t_step, t_eval=t_eval, t_fwd_kernel=t_fwd / args.steps,
                               t_adj_kernel=t_adj / args.steps)
-        log(f"{precision}: step {t_step * 1e3:.3f} ms, eval {t_eval * 1e3:.3f} ms, traversal "
-            f"{res[precision]['t_fwd_kernel'] * 1e3:.3f} ms, adjoint {res[precision]['t_adj_kernel'] * 1e3:.3f} ms")
+        log(f"{precision}: md step {t_step * 1e3:.3f} ms, field eval {t_eval * 1e3:.3f} ms, forward traversal "
+            f"{res[precision]['t_fwd_kernel'] * 1e3:.3f} ms, fused forward+adjoint traversal "
+            f"{res[precision]['t_adj_kernel'] * 1e3:.3f} ms")
         del bh
     torch.cuda.synchronize()
 
     r32 = res["fp32_mixed"]
     # dominant kernel of the FP32-mixed step
     if r32["t_adj_kernel"] >= r32["t_fwd_kernel"]:
-        kname, kt, flops = "k_adjoint<fp32_mixed>", r32["t_adj_kernel"], FLOPS_ADJ * inter
+        kname, kt, flops = "k_adjoint<fp32_mixed> (fused forward + adjoint)", r32["t_adj_kernel"], FLOPS_ADJ * inter
     else:
         kname, kt, flops = "k_field<fp32_mixed>", r32["t_fwd_kernel"], FLOPS_FWD * inter
     achieved = flops / kt

@@ -17,12 +17,36 @@ __device__ inline void atomic_add_d(double *p, double v)
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Six scatter values of one wave added to global memory: by the single contributing lane directly, or
+// reduced across the wave (DPP, total in lane 63) and added by lane 63.  Called in uniform control flow.
+template <typename T>
+__device__ inline void scatter6(uint64_t who, int lane, double *p0, double *p1, double *p2, double *p3, double *p4,
+                                double *p5, T v0, T v1, T v2, T v3, T v4, T v5)
+{
+    if (who == 0ull) return;
+    if ((who & (who - 1ull)) == 0ull) {
+        if ((who >> lane) & 1ull) {
+            atomic_add_d(p0, (double)v0); atomic_add_d(p1, (double)v1); atomic_add_d(p2, (double)v2);
+            atomic_add_d(p3, (double)v3); atomic_add_d(p4, (double)v4); atomic_add_d(p5, (double)v5);
+        }
+        return;
+    }
+    v0 = wave_sum_to63(v0); v1 = wave_sum_to63(v1); v2 = wave_sum_to63(v2);
+    v3 = wave_sum_to63(v3); v4 = wave_sum_to63(v4); v5 = wave_sum_to63(v5);
+    if (lane == kWave - 1) {
+        atomic_add_d(p0, (double)v0); atomic_add_d(p1, (double)v1); atomic_add_d(p2, (double)v2);
+        atomic_add_d(p3, (double)v3); atomic_add_d(p4, (double)v4); atomic_add_d(p5, (double)v5);
+    }
+}
+
+// Forward field and adjoint in one traversal (the upstream gradient Hbar does not depend on H).
 template <bool MIXED>
 __global__ __launch_bounds__(512) void k_adjoint(
     const NodeRec *__restrict__ nodes, const double *__restrict__ node_m64, const double *__restrict__ spos,
     const double *__restrict__ smom, const float *__restrict__ smom32, const double *__restrict__ hbar,
-    double *__restrict__ g_gather, double *__restrict__ g_r, double *__restrict__ g_m,
-    double *__restrict__ node_adj, uint32_t *__restrict__ status, int64_t n, int64_t ntot,
+    const uint32_t *__restrict__ perm, const double *__restrict__ hext, double *__restrict__ g_gather,
+    double *__restrict__ g_r, double *__restrict__ g_m, double *__restrict__ node_adj, double *__restrict__ Hs,
+    double *__restrict__ Hout, double *__restrict__ e_part, uint32_t *__restrict__ status, int64_t n, int64_t ntot,
     int waves_per_seg, int num_waves, double theta2, int max_nodes)
 {
     using T = typename std::conditional<MIXED, float, double>::type;
@@ -38,7 +62,9 @@ __global__ __launch_bounds__(512) void k_adjoint(
     const T ax = valid ? (T)hbar[si] : (T)0, ay = valid ? (T)hbar[ntot + si] : (T)0,
             az = valid ? (T)hbar[2 * ntot + si] : (T)0;
 
-    double grx = 0.0, gry = 0.0, grz = 0.0;
+    double grx = 0.0, gry = 0.0, grz = 0.0;  // gathered dL/dr of the target
+    double hx = 0.0, hy = 0.0, hz = 0.0;     // forward field of the target
+    bool coincident = false;
 
     LaneStack st{0, 0, 0, 0, 0};
     st.push(lane, seg, seg + 1, __ballot(valid));
@@ -71,26 +97,16 @@ __global__ __launch_bounds__(512) void k_adjoint(
                     const double *m = node_m64 + 4 * (int64_t)cur;
                     bx = (T)m[0]; by = (T)m[1]; bz = (T)m[2];
                 }
-                adj_pair<T>((T)dx, (T)dy, (T)dz, ax, ay, az, bx, by, bz, gx, gy, gz, tx, ty, tz);
-                grx += (double)gx;
-                gry += (double)gy;
-                grz += (double)gz;
+                T fx, fy, fz;
+                adj_field<T>((T)dx, (T)dy, (T)dz, ax, ay, az, bx, by, bz, gx, gy, gz, tx, ty, tz, fx, fy, fz);
+                grx += (double)gx; gry += (double)gy; grz += (double)gz;
+                hx += (double)fx; hy += (double)fy; hz += (double)fz;
             }
         }
-        const uint64_t accm = __ballot(acc);
-        if (accm != 0ull) {
-            // A_C += sum T(x) Hbar over accepting lanes; B_C -= sum g
-            const double sAx = (double)wave_sum(tx), sAy = (double)wave_sum(ty), sAz = (double)wave_sum(tz);
-            const double sBx = (double)wave_sum(gx), sBy = (double)wave_sum(gy), sBz = (double)wave_sum(gz);
-            if (lane == 0) {
-                double *a = node_adj + 8 * (int64_t)cur;
-                atomic_add_d(a + 0, sAx);
-                atomic_add_d(a + 1, sAy);
-                atomic_add_d(a + 2, sAz);
-                atomic_add_d(a + 3, -sBx);
-                atomic_add_d(a + 4, -sBy);
-                atomic_add_d(a + 5, -sBz);
-            }
+        // A_C += sum T(x) Hbar over the accepting lanes, B_C -= sum g
+        {
+            double *a = node_adj + 8 * (int64_t)cur;
+            scatter6<T>(__ballot(acc), lane, a, a + 1, a + 2, a + 3, a + 4, a + 5, tx, ty, tz, -gx, -gy, -gz);
         }
         const uint64_t open = __ballot(active && !acc);
         if (open == 0ull) continue;
@@ -104,7 +120,7 @@ __global__ __launch_bounds__(512) void k_adjoint(
         }
         const bool me = (open >> lane) & 1ull;
         const int k1 = nd.first + nd.count;
-        T pgx = 0, pgy = 0, pgz = 0;
+        T pgx = 0, pgy = 0, pgz = 0, phx = 0, phy = 0, phz = 0;
         for (int k = nd.first; k < k1; ++k) {
             const double sx = spos[k], sy = spos[ntot + k], sz = spos[2 * ntot + k];
             T bx, by, bz;
@@ -114,35 +130,50 @@ __global__ __launch_bounds__(512) void k_adjoint(
                 bx = smom[k]; by = smom[ntot + k]; bz = smom[2 * ntot + k];
             }
             T qx = 0, qy = 0, qz = 0, ux = 0, uy = 0, uz = 0;
+            bool use = false;
             if (me && k != si) {
                 const T x = (T)(rx - sx), y = (T)(ry - sy), z = (T)(rz - sz);
-                if (!(x == (T)0 && y == (T)0 && z == (T)0)) {
-                    adj_pair<T>(x, y, z, ax, ay, az, bx, by, bz, qx, qy, qz, ux, uy, uz);
-                    pgx += qx;
-                    pgy += qy;
-                    pgz += qz;
+                if (x == (T)0 && y == (T)0 && z == (T)0) {
+                    coincident = true;
+                } else {
+                    T fx, fy, fz;
+                    adj_field<T>(x, y, z, ax, ay, az, bx, by, bz, qx, qy, qz, ux, uy, uz, fx, fy, fz);
+                    pgx += qx; pgy += qy; pgz += qz;
+                    phx += fx; phy += fy; phz += fz;
+                    use = true;
                 }
             }
             // dL/dr_k -= sum g, dL/dm_k += sum T(x) Hbar over the lanes
-            const double sgx = (double)wave_sum(qx), sgy = (double)wave_sum(qy), sgz = (double)wave_sum(qz);
-            const double sux = (double)wave_sum(ux), suy = (double)wave_sum(uy), suz = (double)wave_sum(uz);
-            if (lane == 0) {
-                atomic_add_d(g_r + k, -sgx);
-                atomic_add_d(g_r + ntot + k, -sgy);
-                atomic_add_d(g_r + 2 * ntot + k, -sgz);
-                atomic_add_d(g_m + k, sux);
-                atomic_add_d(g_m + ntot + k, suy);
-                atomic_add_d(g_m + 2 * ntot + k, suz);
-            }
+            scatter6<T>(__ballot(use), lane, g_r + k, g_r + ntot + k, g_r + 2 * ntot + k, g_m + k, g_m + ntot + k,
+                        g_m + 2 * ntot + k, -qx, -qy, -qz, ux, uy, uz);
         }
-        grx += (double)pgx;
-        gry += (double)pgy;
-        grz += (double)pgz;
+        grx += (double)pgx; gry += (double)pgy; grz += (double)pgz;
+        hx += (double)phx; hy += (double)phy; hz += (double)phz;
     }
+    if (__ballot(coincident) != 0ull && lane == 0) set_flag(status, BH_FLAG_COINCIDENT);
+
+    double e = 0.0;
+    if (valid) {
+        const double mx = smom[si], my = smom[ntot + si], mz = smom[2 * ntot + si];
+        e = -0.5 * (mx * hx + my * hy + mz * hz);
+        if (hext) e -= mx * hext[3 * seg] + my * hext[3 * seg + 1] + mz * hext[3 * seg + 2];
+    }
+    e = wave_sum(e);
+    if (lane == 0) e_part[gw] = e;
     if (valid) {
         g_gather[si] = grx;
         g_gather[ntot + si] = gry;
         g_gather[2 * ntot + si] = grz;
+        Hs[si] = hx;
+        Hs[ntot + si] = hy;
+        Hs[2 * ntot + si] = hz;
+        if (Hout) {
+            const int64_t i = (int64_t)perm[si] - (int64_t)seg * n;
+            double *out = Hout + (int64_t)seg * 3 * n;
+            out[i] = hx;
+            out[n + i] = hy;
+            out[2 * n + i] = hz;
+        }
     }
 }
 
@@ -221,13 +252,12 @@ __global__ __launch_bounds__(1024) void k_dhext(const double *__restrict__ mom, 
 }
 
 hipError_t launch_backward(Handle &h, const double *d_mom, const double *d_hext, const double *d_gH,
-                           const double *d_gE, double *d_dpos, double *d_dmom, double *d_dhext,
-                           hipStream_t s)
+                           const double *d_gE, double *d_dpos, double *d_dmom, double *d_dhext, hipStream_t s,
+                           double *d_H, double *d_E)
 {
     const Layout &L = h.L;
     Workspace &w = h.w;
-    // pseudo-particle moments and the field in sorted order for the explicit term
-    hipError_t e = launch_field(h, d_mom, d_hext, w.H_scratch, nullptr, s);
+    hipError_t e = launch_upward_moments(h, d_mom, s);  // pseudo-particle moments
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_hbar, dim3(grid_for(L.ntot, 256)), dim3(256), 0, s, d_gH, d_gE, w.smom, w.perm, L.n,
                        L.ntot, w.hbar);
@@ -241,13 +271,16 @@ hipError_t launch_backward(Handle &h, const double *d_mom, const double *d_hext,
     if (h.ev[2]) (void)hipEventRecord(h.ev[2], s);
     if (h.p.precision == BH_FP32_MIXED)
         hipLaunchKernelGGL(k_adjoint<true>, dim3(blocks), dim3(wpb * kWave), 0, s, w.nodes, w.node_m64, w.spos,
-                           w.smom, w.smom32, w.hbar, w.g_gather, w.g_r, w.g_m, w.node_adj, w.status, L.n,
-                           L.ntot, waves_per_seg, (int)L.num_waves, theta2, (int)L.max_nodes);
+                           w.smom, w.smom32, w.hbar, w.perm, d_hext, w.g_gather, w.g_r, w.g_m, w.node_adj, w.Hs, d_H,
+                           w.e_part, w.status, L.n, L.ntot, waves_per_seg, (int)L.num_waves, theta2,
+                           (int)L.max_nodes);
     else
         hipLaunchKernelGGL(k_adjoint<false>, dim3(blocks), dim3(wpb * kWave), 0, s, w.nodes, w.node_m64, w.spos,
-                           w.smom, w.smom32, w.hbar, w.g_gather, w.g_r, w.g_m, w.node_adj, w.status, L.n,
-                           L.ntot, waves_per_seg, (int)L.num_waves, theta2, (int)L.max_nodes);
+                           w.smom, w.smom32, w.hbar, w.perm, d_hext, w.g_gather, w.g_r, w.g_m, w.node_adj, w.Hs, d_H,
+                           w.e_part, w.status, L.n, L.ntot, waves_per_seg, (int)L.num_waves, theta2,
+                           (int)L.max_nodes);
     if (h.ev[3]) (void)hipEventRecord(h.ev[3], s);
+    if (d_E) launch_energy_final(h, d_E, s);
     hipLaunchKernelGGL(k_downward, dim3(grid_for(L.ntot, 256)), dim3(256), 0, s, w.nodes, w.leaf_of, w.node_adj,
                        w.g_gather, w.g_r, w.g_m, w.Hs, d_hext, d_gE, w.perm, L.n, L.ntot, d_dpos, d_dmom);
     if (d_dhext)

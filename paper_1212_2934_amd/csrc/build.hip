@@ -568,15 +568,24 @@ __global__ void k_level_starts(uint32_t *lvl)
     lvl[32 + kMaxLevel + 1] = acc;
 }
 
+// One block per 256 node ids: ranks within the block come from LDS atomics, and one global atomic per
+// level and block reserves the block's slots.
 __global__ __launch_bounds__(256) void k_level_scatter(const int32_t *__restrict__ node_level,
                                                        const uint32_t *__restrict__ num_nodes, int64_t max_nodes,
                                                        uint32_t *__restrict__ lvl, int32_t *__restrict__ lvl_nodes)
 {
+    __shared__ uint32_t cnt[kMaxLevel + 1], base[kMaxLevel + 1];
     const int64_t nn = min((int64_t)*num_nodes, max_nodes);
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nn; i += (int64_t)gridDim.x * 256) {
-        const uint32_t at = atomicAdd(&lvl[64 + node_level[i]], 1u);
-        lvl_nodes[at] = (int32_t)i;
-    }
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if ((int64_t)blockIdx.x * 256 >= nn) return;  // whole block beyond the nodes
+    if (threadIdx.x <= kMaxLevel) cnt[threadIdx.x] = 0u;
+    __syncthreads();
+    const int lev = i < nn ? node_level[i] : -1;
+    const uint32_t r = lev >= 0 ? atomicAdd(&cnt[lev], 1u) : 0u;
+    __syncthreads();
+    if (threadIdx.x <= kMaxLevel && cnt[threadIdx.x]) base[threadIdx.x] = atomicAdd(&lvl[64 + threadIdx.x], cnt[threadIdx.x]);
+    __syncthreads();
+    if (lev >= 0) lvl_nodes[base[lev] + r] = (int32_t)i;
 }
 
 __global__ void k_zero_u32(uint32_t *a, int len)
@@ -719,7 +728,7 @@ hipError_t launch_build(Handle &h, const double *d_pos, hipStream_t s)
     hipLaunchKernelGGL(k_level_count, dim3(grid_for(L.max_nodes, 256, 1024)), dim3(256), 0, s, w.node_level,
                        w.status + 2, L.max_nodes, w.lvl);
     hipLaunchKernelGGL(k_level_starts, dim3(1), dim3(64), 0, s, w.lvl);
-    hipLaunchKernelGGL(k_level_scatter, dim3(grid_for(L.max_nodes, 256, 1024)), dim3(256), 0, s, w.node_level,
+    hipLaunchKernelGGL(k_level_scatter, dim3(grid_for(L.max_nodes, 256)), dim3(256), 0, s, w.node_level,
                        w.status + 2, L.max_nodes, w.lvl, w.lvl_nodes);
     upward<0>(h, w.spos, s);
     return hipGetLastError();

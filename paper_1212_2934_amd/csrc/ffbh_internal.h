@@ -145,7 +145,8 @@ hipError_t launch_field(Handle &h, const double *d_mom, const double *d_hext, do
                         double *d_E, hipStream_t s);
 hipError_t launch_backward(Handle &h, const double *d_mom, const double *d_hext, const double *d_gH,
                            const double *d_gE, double *d_dpos, double *d_dmom, double *d_dhext,
-                           hipStream_t s);
+                           hipStream_t s, double *d_H = nullptr, double *d_E = nullptr);
+void launch_energy_final(Handle &h, double *d_E, hipStream_t s);
 hipError_t launch_md(Handle &h, const md_state *st, const md_params *mp, hipStream_t s);
 
 }  // namespace ffbh

@@ -99,6 +99,35 @@ __device__ inline void adj_pair(T x, T y, T z, T ax, T ay, T az, T bx, T by, T b
     tz = fmaT<T>(t, z, -az) * ri3;
 }
 
+// Adjoint pair plus the forward field of b: g and T(x) a as in adj_pair, and hb = T(x) b (the field of
+// dipole b at offset x, Eq. H_dip), sharing the distance powers and dot products.
+template <typename T>
+__device__ inline void adj_field(T x, T y, T z, T ax, T ay, T az, T bx, T by, T bz, T &gx, T &gy, T &gz, T &tx,
+                                 T &ty, T &tz, T &hx, T &hy, T &hz)
+{
+    const T r2 = fmaT<T>(z, z, fmaT<T>(y, y, x * x));
+    const T ri = rsqT<T>(r2);
+    const T ri2 = ri * ri;
+    const T ri3 = ri2 * ri;
+    const T ri5 = ri3 * ri2;
+    const T adx = fmaT<T>(az, z, fmaT<T>(ay, y, ax * x));
+    const T bdx = fmaT<T>(bz, z, fmaT<T>(by, y, bx * x));
+    const T ab = fmaT<T>(az, bz, fmaT<T>(ay, by, ax * bx));
+    const T c0 = fmaT<T>((T)-5 * adx * bdx, ri2, ab);
+    const T s = (T)3 * ri5;
+    gx = s * fmaT<T>(c0, x, fmaT<T>(bdx, ax, adx * bx));
+    gy = s * fmaT<T>(c0, y, fmaT<T>(bdx, ay, adx * by));
+    gz = s * fmaT<T>(c0, z, fmaT<T>(bdx, az, adx * bz));
+    const T ta = (T)3 * adx * ri2;
+    tx = fmaT<T>(ta, x, -ax) * ri3;
+    ty = fmaT<T>(ta, y, -ay) * ri3;
+    tz = fmaT<T>(ta, z, -az) * ri3;
+    const T tb = (T)3 * bdx * ri2;
+    hx = fmaT<T>(tb, x, -bx) * ri3;
+    hy = fmaT<T>(tb, y, -by) * ri3;
+    hz = fmaT<T>(tb, z, -bz) * ri3;
+}
+
 // ---- wave64 reductions (DPP) ---------------------------------------------------------------------
 
 template <int CTRL>
@@ -122,6 +151,20 @@ __device__ inline float wave_sum(float v)
     return (a + b) + (c + d);
 }
 
+// Sum over all 64 lanes, left in lane 63 only (other lanes hold partial sums); every lane active.
+// Rows are reduced with quad/half-row/row mirrors, then rows 1 and 3 add the row before them
+// (row_bcast:15) and rows 2 and 3 add lane 31 (row_bcast:31).
+__device__ inline float wave_sum_to63(float v)
+{
+    v += dpp_f<0xb1>(v);
+    v += dpp_f<0x4e>(v);
+    v += dpp_f<0x141>(v);
+    v += dpp_f<0x140>(v);
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x142, 0xa, 0xf, false));
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x143, 0xc, 0xf, false));
+    return v;
+}
+
 template <int CTRL>
 __device__ inline double dpp_d(double v)
 {
@@ -137,6 +180,23 @@ __device__ inline double readlane_d(double v, int lane)
     const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), lane);
     const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
     return __longlong_as_double(((long long)(unsigned)lo) | ((long long)hi << 32));
+}
+
+__device__ inline double wave_sum_to63(double v)
+{
+    v += dpp_d<0xb1>(v);
+    v += dpp_d<0x4e>(v);
+    v += dpp_d<0x141>(v);
+    v += dpp_d<0x140>(v);
+    const long long bits = __double_as_longlong(v);
+    int lo = __builtin_amdgcn_update_dpp(0, (int)(bits & 0xffffffff), 0x142, 0xa, 0xf, false);
+    int hi = __builtin_amdgcn_update_dpp(0, (int)(bits >> 32), 0x142, 0xa, 0xf, false);
+    v += __longlong_as_double(((long long)(unsigned)lo) | ((long long)hi << 32));
+    const long long bits2 = __double_as_longlong(v);
+    lo = __builtin_amdgcn_update_dpp(0, (int)(bits2 & 0xffffffff), 0x143, 0xc, 0xf, false);
+    hi = __builtin_amdgcn_update_dpp(0, (int)(bits2 >> 32), 0x143, 0xc, 0xf, false);
+    v += __longlong_as_double(((long long)(unsigned)lo) | ((long long)hi << 32));
+    return v;
 }
 
 __device__ inline double wave_sum(double v)
