@@ -16,6 +16,8 @@ FLAGS = [
     # packed FP32 instructions are kept out of every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function",
+    # atomics are issued by one lane after an explicit wave reduction; no compiler-inserted scans
+    "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
 ]
 
 

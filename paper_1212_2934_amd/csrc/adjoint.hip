@@ -40,16 +40,20 @@ __device__ inline void scatter6(uint64_t who, int lane, double *p0, double *p1, 
 }
 
 // Forward field and adjoint in one traversal (the upstream gradient Hbar does not depend on H).
+// Control flow is wave-uniform: when any lane accepts a cell (or uses a source), the whole wave
+// computes and the lanes that do not take part add zero.
 template <bool MIXED>
 __global__ __launch_bounds__(512) void k_adjoint(
     const NodeRec *__restrict__ nodes, const double *__restrict__ node_m64, const double *__restrict__ spos,
-    const double *__restrict__ smom, const float *__restrict__ smom32, const double *__restrict__ hbar,
+    const double *__restrict__ smom, const void *__restrict__ src, const double *__restrict__ hbar,
     const uint32_t *__restrict__ perm, const double *__restrict__ hext, double *__restrict__ g_gather,
     double *__restrict__ g_r, double *__restrict__ g_m, double *__restrict__ node_adj, double *__restrict__ Hs,
     double *__restrict__ Hout, double *__restrict__ e_part, uint32_t *__restrict__ status, int64_t n, int64_t ntot,
     int waves_per_seg, int num_waves, double theta2, int max_nodes)
 {
     using T = typename std::conditional<MIXED, float, double>::type;
+    using Src = typename std::conditional<MIXED, Src32, Src64>::type;
+    const Src *__restrict__ sr = (const Src *)src;
     const int lane = threadIdx.x & (kWave - 1);
     const int wpb = blockDim.x / kWave;
     const int gw = xcd_block(blockIdx.x, gridDim.x) * wpb + (int)(threadIdx.x / kWave);
@@ -62,12 +66,13 @@ __global__ __launch_bounds__(512) void k_adjoint(
     const T ax = valid ? (T)hbar[si] : (T)0, ay = valid ? (T)hbar[ntot + si] : (T)0,
             az = valid ? (T)hbar[2 * ntot + si] : (T)0;
 
-    double grx = 0.0, gry = 0.0, grz = 0.0;  // gathered dL/dr of the target
-    double hx = 0.0, hy = 0.0, hz = 0.0;     // forward field of the target
+    double grx = 0.0, gry = 0.0, grz = 0.0;  // gathered dL/dr of the target (FP64)
+    double hx = 0.0, hy = 0.0, hz = 0.0;     // forward field of the target (FP64)
+    T pgx = 0, pgy = 0, pgz = 0, phx = 0, phy = 0, phz = 0;  // partial sums since the last flush
     bool coincident = false;
 
-    LaneStack st{0, 0, 0, 0, 0};
-    st.push(lane, seg, seg + 1, __ballot(valid));
+    LaneStack st{0, 0, 0, 0};
+    st.push(lane, seg, 1, __ballot(valid));
     int guard = max_nodes;  // a wave visits each node at most once
     while (st.sp > 0) {
         uint64_t mask;
@@ -83,30 +88,33 @@ __global__ __launch_bounds__(512) void k_adjoint(
         }
         const bool active = (mask >> lane) & 1ull;
         const bool inside = (unsigned)(si - nd.first) < (unsigned)nd.count;
-        bool acc = false;
-        T gx = 0, gy = 0, gz = 0, tx = 0, ty = 0, tz = 0;
-        if (active && !inside) {
-            const double dx = rx - nd.cx, dy = ry - nd.cy, dz = rz - nd.cz;
-            const double d2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
-            acc = nd.s2 < theta2 * d2;
-            if (acc) {
-                T bx, by, bz;
-                if (MIXED) {
-                    bx = (T)nd.mx; by = (T)nd.my; bz = (T)nd.mz;
-                } else {
-                    const double *m = node_m64 + 4 * (int64_t)cur;
-                    bx = (T)m[0]; by = (T)m[1]; bz = (T)m[2];
-                }
-                T fx, fy, fz;
-                adj_field<T>((T)dx, (T)dy, (T)dz, ax, ay, az, bx, by, bz, gx, gy, gz, tx, ty, tz, fx, fy, fz);
-                grx += (double)gx; gry += (double)gy; grz += (double)gz;
-                hx += (double)fx; hy += (double)fy; hz += (double)fz;
+        const double dx = rx - nd.cx, dy = ry - nd.cy, dz = rz - nd.cz;
+        const double d2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
+        const bool acc = active && !inside && nd.s2 < theta2 * d2;
+        const uint64_t accm = __ballot(acc);
+        if (accm != 0ull) {
+            T bx, by, bz;
+            if (MIXED) {
+                bx = (T)nd.mx; by = (T)nd.my; bz = (T)nd.mz;
+            } else {
+                const double *m = node_m64 + 4 * (int64_t)cur;
+                bx = (T)m[0]; by = (T)m[1]; bz = (T)m[2];
             }
-        }
-        // A_C += sum T(x) Hbar over the accepting lanes, B_C -= sum g
-        {
+            T gx, gy, gz, tx, ty, tz, fx, fy, fz;
+            adj_field<T>((T)dx, (T)dy, (T)dz, ax, ay, az, bx, by, bz, gx, gy, gz, tx, ty, tz, fx, fy, fz);
+            gx = acc ? gx : (T)0; gy = acc ? gy : (T)0; gz = acc ? gz : (T)0;
+            tx = acc ? tx : (T)0; ty = acc ? ty : (T)0; tz = acc ? tz : (T)0;
+            fx = acc ? fx : (T)0; fy = acc ? fy : (T)0; fz = acc ? fz : (T)0;
+            if (MIXED) {
+                pgx += gx; pgy += gy; pgz += gz;
+                phx += fx; phy += fy; phz += fz;
+            } else {
+                grx += gx; gry += gy; grz += gz;
+                hx += fx; hy += fy; hz += fz;
+            }
+            // A_C += sum T(x) Hbar over the accepting lanes, B_C -= sum g
             double *a = node_adj + 8 * (int64_t)cur;
-            scatter6<T>(__ballot(acc), lane, a, a + 1, a + 2, a + 3, a + 4, a + 5, tx, ty, tz, -gx, -gy, -gz);
+            scatter6<T>(accm, lane, a, a + 1, a + 2, a + 3, a + 4, a + 5, tx, ty, tz, -gx, -gy, -gz);
         }
         const uint64_t open = __ballot(active && !acc);
         if (open == 0ull) continue;
@@ -115,38 +123,42 @@ __global__ __launch_bounds__(512) void k_adjoint(
                 if (lane == 0) set_flag(status, BH_FLAG_STACK);
                 break;
             }
-            st.push(lane, nd.child, nd.child + nd.nchild, open);
+            st.push(lane, nd.child, nd.nchild, open);
             continue;
         }
         const bool me = (open >> lane) & 1ull;
-        const int k1 = nd.first + nd.count;
-        T pgx = 0, pgy = 0, pgz = 0, phx = 0, phy = 0, phz = 0;
-        for (int k = nd.first; k < k1; ++k) {
-            const double sx = spos[k], sy = spos[ntot + k], sz = spos[2 * ntot + k];
-            T bx, by, bz;
+        const Src *q = sr + nd.first;
+        for (int k = nd.first; k < nd.first + nd.count; ++k, ++q) {
+            const Src sk = *q;
+            const T x = (T)(rx - sk.x), y = (T)(ry - sk.y), z = (T)(rz - sk.z);
+            const T r2 = x * x + y * y + z * z;
+            const bool other = me && k != si;
+            const bool use = other && r2 > (T)0;
+            coincident |= other && !(r2 > (T)0);
+            const uint64_t usem = __ballot(use);
+            if (usem == 0ull) continue;
+            T qx, qy, qz, ux, uy, uz, fx, fy, fz;
+            adj_field<T>(x, y, z, ax, ay, az, (T)sk.mx, (T)sk.my, (T)sk.mz, qx, qy, qz, ux, uy, uz, fx, fy, fz);
+            qx = use ? qx : (T)0; qy = use ? qy : (T)0; qz = use ? qz : (T)0;
+            ux = use ? ux : (T)0; uy = use ? uy : (T)0; uz = use ? uz : (T)0;
             if (MIXED) {
-                bx = smom32[k]; by = smom32[ntot + k]; bz = smom32[2 * ntot + k];
+                pgx += qx; pgy += qy; pgz += qz;
+                phx += use ? fx : (T)0; phy += use ? fy : (T)0; phz += use ? fz : (T)0;
             } else {
-                bx = smom[k]; by = smom[ntot + k]; bz = smom[2 * ntot + k];
-            }
-            T qx = 0, qy = 0, qz = 0, ux = 0, uy = 0, uz = 0;
-            bool use = false;
-            if (me && k != si) {
-                const T x = (T)(rx - sx), y = (T)(ry - sy), z = (T)(rz - sz);
-                if (x == (T)0 && y == (T)0 && z == (T)0) {
-                    coincident = true;
-                } else {
-                    T fx, fy, fz;
-                    adj_field<T>(x, y, z, ax, ay, az, bx, by, bz, qx, qy, qz, ux, uy, uz, fx, fy, fz);
-                    pgx += qx; pgy += qy; pgz += qz;
-                    phx += fx; phy += fy; phz += fz;
-                    use = true;
-                }
+                grx += qx; gry += qy; grz += qz;
+                hx += use ? fx : (T)0; hy += use ? fy : (T)0; hz += use ? fz : (T)0;
             }
             // dL/dr_k -= sum g, dL/dm_k += sum T(x) Hbar over the lanes
-            scatter6<T>(__ballot(use), lane, g_r + k, g_r + ntot + k, g_r + 2 * ntot + k, g_m + k, g_m + ntot + k,
+            scatter6<T>(usem, lane, g_r + k, g_r + ntot + k, g_r + 2 * ntot + k, g_m + k, g_m + ntot + k,
                         g_m + 2 * ntot + k, -qx, -qy, -qz, ux, uy, uz);
         }
+        if (MIXED) {
+            grx += (double)pgx; gry += (double)pgy; grz += (double)pgz;
+            hx += (double)phx; hy += (double)phy; hz += (double)phz;
+            pgx = pgy = pgz = phx = phy = phz = (T)0;
+        }
+    }
+    if (MIXED) {
         grx += (double)pgx; gry += (double)pgy; grz += (double)pgz;
         hx += (double)phx; hy += (double)phy; hz += (double)phz;
     }
@@ -271,12 +283,12 @@ hipError_t launch_backward(Handle &h, const double *d_mom, const double *d_hext,
     if (h.ev[2]) (void)hipEventRecord(h.ev[2], s);
     if (h.p.precision == BH_FP32_MIXED)
         hipLaunchKernelGGL(k_adjoint<true>, dim3(blocks), dim3(wpb * kWave), 0, s, w.nodes, w.node_m64, w.spos,
-                           w.smom, w.smom32, w.hbar, w.perm, d_hext, w.g_gather, w.g_r, w.g_m, w.node_adj, w.Hs, d_H,
+                           w.smom, w.src32, w.hbar, w.perm, d_hext, w.g_gather, w.g_r, w.g_m, w.node_adj, w.Hs, d_H,
                            w.e_part, w.status, L.n, L.ntot, waves_per_seg, (int)L.num_waves, theta2,
                            (int)L.max_nodes);
     else
         hipLaunchKernelGGL(k_adjoint<false>, dim3(blocks), dim3(wpb * kWave), 0, s, w.nodes, w.node_m64, w.spos,
-                           w.smom, w.smom32, w.hbar, w.perm, d_hext, w.g_gather, w.g_r, w.g_m, w.node_adj, w.Hs, d_H,
+                           w.smom, w.src64, w.hbar, w.perm, d_hext, w.g_gather, w.g_r, w.g_m, w.node_adj, w.Hs, d_H,
                            w.e_part, w.status, L.n, L.ntot, waves_per_seg, (int)L.num_waves, theta2,
                            (int)L.max_nodes);
     if (h.ev[3]) (void)hipEventRecord(h.ev[3], s);

@@ -54,6 +54,8 @@ void carve(const Layout &Lc, void *base, Workspace &w)
     w.spos = (double *)take(3 * 8 * nt);
     w.smom = (double *)take(3 * 8 * nt);
     w.smom32 = (float *)take(3 * 4 * nt);
+    w.src64 = take(48 * nt);
+    w.src32 = take(48 * nt);
     w.bin_left = (int32_t *)take(4 * bi);
     w.bin_right = (int32_t *)take(4 * bi);
     w.bin_first = (int32_t *)take(4 * bi);
@@ -91,7 +93,7 @@ static bool params_ok(const bh_params *p)
 {
     if (!p) return false;
     if (p->n < 1 || p->batch < 1) return false;
-    if (p->n * (int64_t)p->batch > ((int64_t)1 << 30)) return false;  // 32-bit sorted indices
+    if (p->n * (int64_t)p->batch > ((int64_t)1 << 26)) return false;  // node ids below 2^28
     if (p->leaf_size < 1 || p->leaf_size > 64) return false;
     if (!(p->theta >= 0.0) || !__builtin_isfinite(p->theta)) return false;
     if (p->precision != BH_FP64 && p->precision != BH_FP32_MIXED) return false;

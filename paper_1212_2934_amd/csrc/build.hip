@@ -738,12 +738,30 @@ hipError_t launch_build(Handle &h, const double *d_pos, hipStream_t s)
 
 namespace ffbh {
 
+// Sorted source records for the direct sums (position and moment of one particle in 48 bytes).
+__global__ __launch_bounds__(256) void k_pack_sources(const double *__restrict__ spos, const double *__restrict__ smom,
+                                                      int64_t ntot, double *__restrict__ src64, double *__restrict__ src32)
+{
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k >= ntot) return;
+    const double x = spos[k], y = spos[ntot + k], z = spos[2 * ntot + k];
+    const double mx = smom[k], my = smom[ntot + k], mz = smom[2 * ntot + k];
+    double *a = src64 + 6 * k;
+    a[0] = x; a[1] = y; a[2] = z; a[3] = mx; a[4] = my; a[5] = mz;
+    double *b = src32 + 6 * k;
+    b[0] = x; b[1] = y; b[2] = z;
+    float *f = (float *)(b + 3);
+    f[0] = (float)mx; f[1] = (float)my; f[2] = (float)mz; f[3] = 0.0f;
+}
+
 hipError_t launch_upward_moments(Handle &h, const double *d_mom, hipStream_t s)
 {
     const Layout &L = h.L;
     Workspace &w = h.w;
     hipLaunchKernelGGL(k_gather3, dim3(grid_for(L.ntot, 256)), dim3(256), 0, s, d_mom, w.perm, L.n,
                        L.ntot, w.smom, w.smom32, w.status);
+    hipLaunchKernelGGL(k_pack_sources, dim3(grid_for(L.ntot, 256)), dim3(256), 0, s, w.spos, w.smom, L.ntot,
+                       (double *)w.src64, (double *)w.src32);
     upward<1>(h, w.smom, s);
     return hipGetLastError();
 }

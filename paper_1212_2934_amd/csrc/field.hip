@@ -16,12 +16,15 @@ namespace ffbh {
 template <bool MIXED, bool COUNT>
 __global__ __launch_bounds__(512) void k_field(
     const NodeRec *__restrict__ nodes, const double *__restrict__ node_m64, const double *__restrict__ spos,
-    const double *__restrict__ smom, const float *__restrict__ smom32, const uint32_t *__restrict__ perm,
+    const double *__restrict__ smom, const void *__restrict__ src, const uint32_t *__restrict__ perm,
     const double *__restrict__ hext, double *__restrict__ H, double *__restrict__ Hs,
     double *__restrict__ e_part, int32_t *__restrict__ cnt_far, int32_t *__restrict__ cnt_near,
     uint32_t *__restrict__ status, int64_t n, int64_t ntot, int waves_per_seg, int num_waves,
     double theta2, int max_nodes)
 {
+    using T = typename std::conditional<MIXED, float, double>::type;
+    using Src = typename std::conditional<MIXED, Src32, Src64>::type;
+    const Src *__restrict__ sr = (const Src *)src;
     const int lane = threadIdx.x & (kWave - 1);
     const int wpb = blockDim.x / kWave;
     const int gw = xcd_block(blockIdx.x, gridDim.x) * wpb + (int)(threadIdx.x / kWave);
@@ -32,12 +35,13 @@ __global__ __launch_bounds__(512) void k_field(
     const int si = (int)(seg * n) + (valid ? local : 0);
     const double rx = spos[si], ry = spos[ntot + si], rz = spos[2 * ntot + si];
 
-    double hx = 0.0, hy = 0.0, hz = 0.0;
+    double hx = 0.0, hy = 0.0, hz = 0.0;  // FP64 accumulation
+    T px = 0, py = 0, pz = 0;             // partial sums since the last flush (MIXED only)
     int nfar = 0, nnear = 0;
     bool coincident = false;
 
-    LaneStack st{0, 0, 0, 0, 0};
-    st.push(lane, seg, seg + 1, __ballot(valid));
+    LaneStack st{0, 0, 0, 0};
+    st.push(lane, seg, 1, __ballot(valid));
     int guard = max_nodes;  // a wave visits each node at most once
     while (st.sp > 0) {
         uint64_t mask;
@@ -53,24 +57,26 @@ __global__ __launch_bounds__(512) void k_field(
         }
         const bool active = (mask >> lane) & 1ull;
         const bool inside = (unsigned)(si - nd.first) < (unsigned)nd.count;
-        bool acc = false;
-        if (active && !inside) {
-            const double dx = rx - nd.cx, dy = ry - nd.cy, dz = rz - nd.cz;
-            const double d2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
-            acc = nd.s2 < theta2 * d2;
-            if (acc) {
-                if (MIXED) {
-                    float fx = 0.f, fy = 0.f, fz = 0.f;
-                    dip_acc<float>((float)dx, (float)dy, (float)dz, nd.mx, nd.my, nd.mz, fx, fy, fz);
-                    hx += (double)fx;
-                    hy += (double)fy;
-                    hz += (double)fz;
-                } else {
-                    const double *m = node_m64 + 4 * (int64_t)cur;
-                    dip_acc<double>(dx, dy, dz, m[0], m[1], m[2], hx, hy, hz);
-                }
-                if (COUNT) ++nfar;
+        // acceptance test in FP64, exactly as defined
+        const double dx = rx - nd.cx, dy = ry - nd.cy, dz = rz - nd.cz;
+        const double d2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
+        const bool acc = active && !inside && nd.s2 < theta2 * d2;
+        if (__ballot(acc) != 0ull) {
+            // the whole wave computes; lanes that did not accept add zero
+            T fx = 0, fy = 0, fz = 0;
+            if (MIXED) {
+                dip_acc<T>((T)dx, (T)dy, (T)dz, (T)nd.mx, (T)nd.my, (T)nd.mz, fx, fy, fz);
+                px += acc ? fx : (T)0;
+                py += acc ? fy : (T)0;
+                pz += acc ? fz : (T)0;
+            } else {
+                const double *m = node_m64 + 4 * (int64_t)cur;
+                dip_acc<T>((T)dx, (T)dy, (T)dz, (T)m[0], (T)m[1], (T)m[2], fx, fy, fz);
+                hx += acc ? (double)fx : 0.0;
+                hy += acc ? (double)fy : 0.0;
+                hz += acc ? (double)fz : 0.0;
             }
+            if (COUNT) nfar += acc ? 1 : 0;
         }
         const uint64_t open = __ballot(active && !acc);
         if (open == 0ull) continue;
@@ -79,45 +85,39 @@ __global__ __launch_bounds__(512) void k_field(
                 if (lane == 0) set_flag(status, BH_FLAG_STACK);
                 break;
             }
-            st.push(lane, nd.child, nd.child + nd.nchild, open);
+            st.push(lane, nd.child, nd.nchild, open);
             continue;
         }
-        // leaf that this lane must sum directly (members other than the target itself)
+        // leaf: members other than the target itself, summed directly by the lanes that opened it
         const bool me = (open >> lane) & 1ull;
-        const int k1 = nd.first + nd.count;
-        if (MIXED) {
-            float px = 0.f, py = 0.f, pz = 0.f;
-            for (int k = nd.first; k < k1; ++k) {
-                const double sx = spos[k], sy = spos[ntot + k], sz = spos[2 * ntot + k];
-                const float mx = smom32[k], my = smom32[ntot + k], mz = smom32[2 * ntot + k];
-                if (me && k != si) {
-                    const float x = (float)(rx - sx), y = (float)(ry - sy), z = (float)(rz - sz);
-                    if (x == 0.f && y == 0.f && z == 0.f) {
-                        coincident = true;
-                    } else {
-                        dip_acc<float>(x, y, z, mx, my, mz, px, py, pz);
-                        if (COUNT) ++nnear;
-                    }
-                }
+        const Src *q = sr + nd.first;
+        for (int k = 0; k < nd.count; ++k, ++q) {
+            const Src sk = *q;
+            const T x = (T)(rx - sk.x), y = (T)(ry - sk.y), z = (T)(rz - sk.z);
+            const T r2 = x * x + y * y + z * z;
+            const bool other = me && (nd.first + k != si);
+            const bool use = other && r2 > (T)0;
+            coincident |= other && !(r2 > (T)0);
+            T fx = 0, fy = 0, fz = 0;
+            dip_acc<T>(x, y, z, (T)sk.mx, (T)sk.my, (T)sk.mz, fx, fy, fz);
+            if (MIXED) {
+                px += use ? fx : (T)0;
+                py += use ? fy : (T)0;
+                pz += use ? fz : (T)0;
+            } else {
+                hx += use ? (double)fx : 0.0;
+                hy += use ? (double)fy : 0.0;
+                hz += use ? (double)fz : 0.0;
             }
-            hx += (double)px;
-            hy += (double)py;
-            hz += (double)pz;
-        } else {
-            for (int k = nd.first; k < k1; ++k) {
-                const double sx = spos[k], sy = spos[ntot + k], sz = spos[2 * ntot + k];
-                const double mx = smom[k], my = smom[ntot + k], mz = smom[2 * ntot + k];
-                if (me && k != si) {
-                    const double x = rx - sx, y = ry - sy, z = rz - sz;
-                    if (x == 0.0 && y == 0.0 && z == 0.0) {
-                        coincident = true;
-                    } else {
-                        dip_acc<double>(x, y, z, mx, my, mz, hx, hy, hz);
-                        if (COUNT) ++nnear;
-                    }
-                }
-            }
+            if (COUNT) nnear += use ? 1 : 0;
         }
+        if (MIXED) {
+            hx += (double)px; hy += (double)py; hz += (double)pz;
+            px = py = pz = (T)0;
+        }
+    }
+    if (MIXED) {
+        hx += (double)px; hy += (double)py; hz += (double)pz;
     }
     if (__ballot(coincident) != 0ull && lane == 0) set_flag(status, BH_FLAG_COINCIDENT);
 
@@ -125,9 +125,8 @@ __global__ __launch_bounds__(512) void k_field(
     double e = 0.0;
     if (valid) {
         const double mx = smom[si], my = smom[ntot + si], mz = smom[2 * ntot + si];
-        const double *he = hext ? hext + 3 * seg : nullptr;
         e = -0.5 * (mx * hx + my * hy + mz * hz);
-        if (he) e -= mx * he[0] + my * he[1] + mz * he[2];
+        if (hext) e -= mx * hext[3 * seg] + my * hext[3 * seg + 1] + mz * hext[3 * seg + 2];
     }
     e = wave_sum(e);
     if (lane == 0) e_part[gw] = e;
@@ -176,8 +175,9 @@ static void launch_k_field(Handle &h, const double *d_hext, double *d_H, hipStre
     const unsigned blocks = (unsigned)((L.num_waves + wpb - 1) / wpb);
     const int waves_per_seg = (int)((L.n + kWave - 1) / kWave);
     const double theta2 = h.p.theta * h.p.theta;
+    const void *src = MIXED ? (const void *)w.src32 : (const void *)w.src64;
     hipLaunchKernelGGL((k_field<MIXED, COUNT>), dim3(blocks), dim3(wpb * kWave), 0, s, w.nodes,
-                       w.node_m64, w.spos, w.smom, w.smom32, w.perm, d_hext, d_H, w.Hs, w.e_part,
+                       w.node_m64, w.spos, w.smom, src, w.perm, d_hext, d_H, w.Hs, w.e_part,
                        h.cnt_far, h.cnt_near, w.status, L.n, L.ntot, waves_per_seg, (int)L.num_waves, theta2, (int)L.max_nodes);
 }
 

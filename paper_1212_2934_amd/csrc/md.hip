@@ -110,8 +110,8 @@ __global__ __launch_bounds__(256) void k_wca(const NodeRec *__restrict__ nodes, 
     const double rc = 1.122462048309373 * sigma, rc2 = rc * rc, s2 = sigma * sigma;
     double fx = 0.0, fy = 0.0, fz = 0.0;
 
-    LaneStack st{0, 0, 0, 0, 0};
-    st.push(lane, seg, seg + 1, __ballot(valid));
+    LaneStack st{0, 0, 0, 0};
+    st.push(lane, seg, 1, __ballot(valid));
     int guard = max_nodes;
     while (st.sp > 0 && eps > 0.0) {
         uint64_t mask;
@@ -135,7 +135,7 @@ __global__ __launch_bounds__(256) void k_wca(const NodeRec *__restrict__ nodes, 
                 if (lane == 0) set_flag(status, BH_FLAG_STACK);
                 break;
             }
-            st.push(lane, nd.child, nd.child + nd.nchild, open);
+            st.push(lane, nd.child, nd.nchild, open);
             continue;
         }
         const bool me = (open >> lane) & 1ull;

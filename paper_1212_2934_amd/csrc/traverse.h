@@ -218,18 +218,18 @@ __device__ inline int xcd_block(int bid, int nb)
     return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
 }
 
-// Traversal stack held in VGPRs: entry e lives in lane e of four registers (node range [cur, end)
-// and the 64-bit lane mask).  Push and pop run in wave-uniform control flow with every lane active:
-// a push selects lane sp, a pop reads lane sp-1 into scalars with v_readlane.
+// Traversal stack held in VGPRs: entry e lives in lane e of two registers.  The first packs a range
+// of sibling nodes as (next node) | (siblings left after it) << 28; the second pair holds the 64-bit
+// lane mask.  Push and pop run in wave-uniform control flow with every lane active: a push selects
+// lane sp, a pop reads lane sp-1 into scalars with v_readlane.  Node indices stay below 2^28.
 struct LaneStack {
-    int cur, end, mlo, mhi;
+    int ent, mlo, mhi;
     int sp;
 
-    __device__ inline void push(int lane, int c, int e, uint64_t m)
+    __device__ inline void push(int lane, int first, int count, uint64_t m)
     {
         const bool here = lane == sp;
-        cur = here ? c : cur;
-        end = here ? e : end;
+        ent = here ? (first | ((count - 1) << 28)) : ent;
         mlo = here ? (int)(uint32_t)m : mlo;
         mhi = here ? (int)(uint32_t)(m >> 32) : mhi;
         ++sp;
@@ -238,15 +238,27 @@ struct LaneStack {
     __device__ inline int pop(int lane, uint64_t &m)
     {
         const int top = sp - 1;
-        const int c = __builtin_amdgcn_readlane(cur, top);
-        const int e = __builtin_amdgcn_readlane(end, top);
+        const uint32_t e = (uint32_t)__builtin_amdgcn_readlane(ent, top);
         const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane(mlo, top);
         const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane(mhi, top);
         m = ((uint64_t)hi << 32) | lo;
-        if (c + 1 < e) cur = (lane == top) ? c + 1 : cur;
+        const int c = (int)(e & 0x0fffffffu);
+        if (e >> 28) ent = (lane == top) ? (int)(e + 1u - (1u << 28)) : ent;
         else sp = top;
         return c;
     }
 };
+
+// Sorted source particle for the direct sums: position FP64, moment FP64 (Src64) or FP32 (Src32),
+// 48 bytes so that one particle is two scalar loads from one address.
+struct Src64 {
+    double x, y, z, mx, my, mz;
+};
+struct Src32 {
+    double x, y, z;
+    float mx, my, mz, pad;
+    double pad2;
+};
+static_assert(sizeof(Src64) == 48 && sizeof(Src32) == 48, "source records are 48 bytes");
 
 }  // namespace ffbh
