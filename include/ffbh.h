@@ -130,6 +130,16 @@ typedef struct md_params {
  * integrator update.  Enqueued on the stream with no host synchronisation (capturable in a graph). */
 bh_status md_step(bh_handle *h, const md_state *s, const md_params *p, void *stream);
 
+/* Capture one md_step (everything it enqueues, all plain kernel launches) into a HIP graph on `stream`
+ * and instantiate it into *graph_exec.  The stream must not be the null stream.  Replaying the graph
+ * with bh_graph_launch performs one MD step on the same state buffers with the same parameters; the
+ * noise advances with the device step counter, so replays continue the trajectory.  The handle,
+ * workspace and state buffers must outlive the graph.  Release with bh_graph_destroy. */
+bh_status bh_graph_capture_md(bh_handle *h, const md_state *s, const md_params *p, void *stream,
+                              void **graph_exec);
+bh_status bh_graph_launch(void *graph_exec, void *stream);
+bh_status bh_graph_destroy(void *graph_exec);
+
 /* Read (and clear) the device status word; synchronises the stream.  Returns BH_EDEGENERATE if any
  * flag was set, BH_OK otherwise; the raw bits go to *flags if not NULL. */
 bh_status bh_check_status(bh_handle *h, void *stream, uint32_t *flags);

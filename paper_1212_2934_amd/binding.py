@@ -67,6 +67,11 @@ def lib():
         L.bh_export_tree.argtypes = [P] * 10
         L.bh_set_timing_events.argtypes = [P] * 5
         L.bh_set_timing_events.restype = i32
+        L.bh_graph_capture_md.argtypes = [P, C.POINTER(md_state), C.POINTER(md_params), P, C.POINTER(P)]
+        L.bh_graph_launch.argtypes = [P, P]
+        L.bh_graph_destroy.argtypes = [P]
+        for f in ("bh_graph_capture_md", "bh_graph_launch", "bh_graph_destroy"):
+            getattr(L, f).restype = i32
         L.bh_morton_code.argtypes = [C.c_uint32, C.c_uint32, C.c_uint32]
         L.bh_morton_code.restype = C.c_uint64
         L.bh_status_str.argtypes = [i32]
@@ -81,7 +86,8 @@ def lib():
 
 EXPORTED = ["bh_workspace_bytes", "bh_num_tunings", "bh_create", "bh_destroy", "bh_build", "bh_field",
             "bh_field_backward", "md_step", "bh_check_status", "bh_enable_counters", "bh_num_nodes",
-            "bh_export_tree", "bh_set_timing_events", "bh_morton_code", "bh_status_str"]
+            "bh_export_tree", "bh_set_timing_events", "bh_graph_capture_md", "bh_graph_launch",
+            "bh_graph_destroy", "bh_morton_code", "bh_status_str"]
 
 
 def _check(fn: str, st: int):
@@ -246,6 +252,22 @@ class BarnesHut:
         torch.cuda.current_stream().synchronize()
         return {k: v.cpu().numpy() for k, v in out.items()}
 
+    def _md_state(self, state):
+        for k in ("pos", "vel", "mom", "omega"):
+            self._as_batch(state[k], k)
+        if not (state["step"].is_cuda and state["step"].dtype == torch.int64 and state["step"].numel() == 1):
+            raise ValueError("step must be a one-element int64 CUDA tensor")
+        return md_state(state["pos"].data_ptr(), state["vel"].data_ptr(), state["mom"].data_ptr(),
+                        state["omega"].data_ptr(), state["step"].data_ptr())
+
+    def capture_md_graph(self, state: dict, mdp: md_params, stream: "torch.cuda.Stream"):
+        """Capture one md_step on `stream` (not the default stream) into a replayable graph."""
+        st = self._md_state(state)
+        g = C.c_void_p()
+        _check("bh_graph_capture_md", lib().bh_graph_capture_md(self._h, C.byref(st), C.byref(mdp),
+                                                                C.c_void_p(stream.cuda_stream), C.byref(g)))
+        return MDGraph(g, self, state, mdp)
+
     def md_step(self, state: dict, mdp: md_params):
         """One MD step in place on state = {pos, vel, mom, omega: (B, 3, n) float64, step: int64[1]}."""
         for k in ("pos", "vel", "mom", "omega"):
@@ -255,6 +277,23 @@ class BarnesHut:
         st = md_state(state["pos"].data_ptr(), state["vel"].data_ptr(), state["mom"].data_ptr(),
                       state["omega"].data_ptr(), state["step"].data_ptr())
         _check("md_step", lib().md_step(self._h, C.byref(st), C.byref(mdp), _stream()))
+
+
+class MDGraph:
+    """An instantiated HIP graph of one MD step; launch() replays it on a stream."""
+
+    def __init__(self, g, owner, state, mdp):
+        self._g = g
+        self._keep = (owner, state, mdp)  # buffers the graph points into
+
+    def launch(self, stream: "torch.cuda.Stream"):
+        _check("bh_graph_launch", lib().bh_graph_launch(self._g, C.c_void_p(stream.cuda_stream)))
+
+    def __del__(self):
+        g = getattr(self, "_g", None)
+        if g is not None and _lib is not None:
+            _lib.bh_graph_destroy(g)
+            self._g = None
 
 
 def morton_code(qx: int, qy: int, qz: int) -> int:

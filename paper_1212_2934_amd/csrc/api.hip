@@ -237,7 +237,18 @@ bh_status bh_field_backward(bh_handle *hh, const double *d_mom, const double *d_
     return BH_OK;
 }
 
+static bh_status md_args_ok(bh_handle *hh, const md_state *s, const md_params *p);
+
 bh_status md_step(bh_handle *hh, const md_state *s, const md_params *p, void *stream)
+{
+    bh_status st = md_args_ok(hh, s, p);
+    if (st != BH_OK) return st;
+    if (launch_md(hh->h, s, p, (hipStream_t)stream) != hipSuccess) return BH_EDEVICE;
+    hh->h.built = 1;
+    return BH_OK;
+}
+
+static bh_status md_args_ok(bh_handle *hh, const md_state *s, const md_params *p)
 {
     if (!hh || !s || !p) return BH_EINVAL;
     if (!dptr_ok(s->pos) || !dptr_ok(s->vel) || !dptr_ok(s->mom) || !dptr_ok(s->omega) || !dptr_ok(s->d_step))
@@ -248,9 +259,42 @@ bh_status md_step(bh_handle *hh, const md_state *s, const md_params *p, void *st
     for (int a = 0; a < 3; ++a)
         if (!(p->box_hi[a] > p->box_lo[a])) return BH_EINVAL;
     if (p->d_hext && !dptr_ok(p->d_hext)) return BH_EINVAL;
-    if (launch_md(hh->h, s, p, (hipStream_t)stream) != hipSuccess) return BH_EDEVICE;
-    hh->h.built = 1;
     return BH_OK;
+}
+
+bh_status bh_graph_capture_md(bh_handle *hh, const md_state *s, const md_params *p, void *stream, void **graph_exec)
+{
+    bh_status st = md_args_ok(hh, s, p);
+    if (st != BH_OK) return st;
+    if (!stream || !graph_exec) return BH_EINVAL;
+    hipStream_t hs = (hipStream_t)stream;
+    if (hipStreamBeginCapture(hs, hipStreamCaptureModeThreadLocal) != hipSuccess) return BH_EDEVICE;
+    hipError_t le = launch_md(hh->h, s, p, hs);
+    hipGraph_t g = nullptr;
+    hipError_t ce = hipStreamEndCapture(hs, &g);
+    if (le != hipSuccess || ce != hipSuccess || !g) {
+        if (g) (void)hipGraphDestroy(g);
+        return BH_EDEVICE;
+    }
+    hipGraphExec_t ex = nullptr;
+    hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ie != hipSuccess) return BH_EDEVICE;
+    hh->h.built = 1;
+    *graph_exec = (void *)ex;
+    return BH_OK;
+}
+
+bh_status bh_graph_launch(void *graph_exec, void *stream)
+{
+    if (!graph_exec) return BH_EINVAL;
+    return hipGraphLaunch((hipGraphExec_t)graph_exec, (hipStream_t)stream) == hipSuccess ? BH_OK : BH_EDEVICE;
+}
+
+bh_status bh_graph_destroy(void *graph_exec)
+{
+    if (!graph_exec) return BH_EINVAL;
+    return hipGraphExecDestroy((hipGraphExec_t)graph_exec) == hipSuccess ? BH_OK : BH_EDEVICE;
 }
 
 bh_status bh_check_status(bh_handle *hh, void *stream, uint32_t *flags)
