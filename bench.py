@@ -7,8 +7,10 @@ H_ext = 0 (synthetic, seeded).  A timed step is one MD step (md_step) on that in
 the whole hot path: tree build (bounding cube, Morton codes, radix sort, octree, centroids), upward
 moment pass, forward field and energy, the adjoint (dE/dr, dE/dm) by re-traversal, WCA pair and wall
 forces by a tree range query, and the Euler-Maruyama update with Philox noise (dt 1e-3, kT 1,
-gamma 0.1, M 1, I 0.1).  value = MD steps/s in FP32-mixed precision; field evaluations/s (tree build +
-field) are reported beside it for both precisions.
+gamma 0.1, M 1, I 0.1), replayed from a captured HIP graph.  value = MD steps/s in FP32-mixed
+precision; field evaluations/s (tree build + field), eager MD steps/s, FP64 figures and the batched slab
+workload (32 realisations x 2^16 particles in 256 x 256 x 8, graph-replayed MD steps) are reported beside
+it.
 
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
 """
@@ -27,6 +29,30 @@ PEAK_FP32_UNPACKED = 78.6e12  # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz, o
 # algorithmic flops per interaction, fixed from the kernel source (FMA = 2, rsqrt = 1):
 FLOPS_FWD = 30   # 3 FP64 offset subtractions + 27 for the dipole field and its accumulation
 FLOPS_ADJ = 75   # 3 offset + 69 for g, T(x)Hbar and the field T(x)m + 3 gather accumulation
+
+
+def kernel_source_sha1():
+    """Hash of the sources that define the fused traversal kernel (to match committed counter data)."""
+    import hashlib
+    h = hashlib.sha1()
+    for f in ("adjoint.hip", "traverse.h", "ffbh_internal.h"):
+        with open(os.path.join(ROOT, "paper_1212_2934_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def committed_traffic(kernel_key):
+    """HBM bytes per launch from profiles/traffic.json (rocprofv3 FETCH_SIZE + WRITE_SIZE scaled by a
+    plain-copy calibration), or None when the kernel sources changed since the counters were taken."""
+    f = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(f):
+        return None
+    with open(f) as fh:
+        d = json.load(fh)
+    e = d.get(kernel_key)
+    if not e or e.get("source_sha1") != kernel_source_sha1():
+        return None
+    return e["fetch_bytes"] + e["write_bytes"]
 
 
 def log(msg):
@@ -69,6 +95,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--theta", type=float, default=0.5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-slab", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="finish with one plain device copy of MIB MiB (a reference kernel for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)",
@@ -126,6 +155,16 @@ def main():
         def step():
             bh.md_step(state, mdp)
 
+        # the graph gets its own handle: one handle's calls share its workspace and must not overlap
+        side_stream = torch.cuda.Stream()
+        gbh = make(precision)
+        gstate = {k: v.clone() for k, v in state.items()}
+        torch.cuda.synchronize()
+        graph = gbh.capture_md_graph(gstate, mdp, side_stream)
+
+        def gstep():
+            graph.launch(side_stream)
+
         def field_only():
             bh.build(pos)
             return bh.field(mom, hext)
@@ -133,12 +172,22 @@ def main():
         for _ in range(args.warmup):
             step()
         torch.cuda.synchronize()
+        for _ in range(args.warmup):
+            gstep()
+        torch.cuda.synchronize()
         t_fwd = t_adj = 0.0
         t0 = time.perf_counter()
         for _ in range(args.steps):
             step()
         torch.cuda.synchronize()
+        t_step_eager = (time.perf_counter() - t0) / args.steps
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            gstep()
+        torch.cuda.synchronize()
         t_step = (time.perf_counter() - t0) / args.steps
+        assert gbh.check_status() == 0
+        del graph, gbh
         for _ in range(args.steps):  # adjoint kernel time, one step at a time
             step()
             t_adj += ev.seconds(2, 3)
@@ -156,13 +205,45 @@ def main():
             t_fwd += ev.seconds(0, 1)
         assert bh.check_status() == 0
         bh.set_raw_timing_events(None)
-        res[precision] = dict(t_step=t_step, t_eval=t_eval, t_fwd_kernel=t_fwd / args.steps,
+        res[precision] = dict(t_step=t_step, t_step_eager=t_step_eager, t_eval=t_eval, t_fwd_kernel=t_fwd / args.steps,
                               t_adj_kernel=t_adj / args.steps)
-        log(f"{precision}: md step {t_step * 1e3:.3f} ms, field eval {t_eval * 1e3:.3f} ms, forward traversal "
+        log(f"{precision}: md step (graph) {t_step * 1e3:.3f} ms, eager {t_step_eager * 1e3:.3f} ms, field eval {t_eval * 1e3:.3f} ms, forward traversal "
             f"{res[precision]['t_fwd_kernel'] * 1e3:.3f} ms, fused forward+adjoint traversal "
             f"{res[precision]['t_adj_kernel'] * 1e3:.3f} ms")
         del bh
     torch.cuda.synchronize()
+
+    # batched slab: 32 independent realisations of 2^16 particles, graph-replayed MD steps
+    slab = {}
+    if not args.no_slab:
+        log("generating slab workload (32 x 2^16 in 256 x 256 x 8)")
+        ws = workloads.cached("slab_b32_n65536_seed1005", lambda: workloads.config5())
+        sp = torch.from_numpy(ws.pos).to(dev)
+        sm = torch.from_numpy(ws.mom).to(dev)
+        shext = torch.from_numpy(ws.hext).to(dev)
+        srng = np.random.default_rng(2005)
+        smdp = md_params(1e-3, 1.0, 0.1, 0.1, 1.0, 0.1, 1.0, 1.0, C3(*ws.box_lo), C3(*ws.box_hi),
+                         shext.data_ptr(), 2005)
+        for precision in ("fp32_mixed", "fp64"):
+            sbh = BarnesHut(ws.n, ws.batch, 16, 0.5, precision)
+            sst = {"pos": sp.clone(), "vel": torch.from_numpy(srng.standard_normal(ws.pos.shape)).to(dev),
+                   "mom": sm.clone(), "omega": torch.from_numpy(srng.standard_normal(ws.pos.shape) * np.sqrt(10.0)).to(dev),
+                   "step": torch.zeros(1, dtype=torch.int64, device=dev)}
+            ss = torch.cuda.Stream()
+            torch.cuda.synchronize()
+            sg = sbh.capture_md_graph(sst, smdp, ss)
+            for _ in range(args.warmup):
+                sg.launch(ss)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                sg.launch(ss)
+            torch.cuda.synchronize()
+            ts = (time.perf_counter() - t0) / args.steps
+            assert sbh.check_status() == 0
+            slab[precision] = ts
+            log(f"slab {precision}: {ts * 1e3:.3f} ms per batched MD step ({ws.batch} realisations)")
+            del sg, sbh
 
     r32 = res["fp32_mixed"]
     # dominant kernel of the FP32-mixed step
@@ -173,7 +254,8 @@ def main():
     achieved = flops / kt
     roofline = {"bound": "alu", "kernel": kname, "achieved": achieved / 1e12, "peak": PEAK_FP32_VECTOR / 1e12,
                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR,
-                "frac_of_unpacked_fp32": achieved / PEAK_FP32_UNPACKED, "traffic": None,
+                "frac_of_unpacked_fp32": achieved / PEAK_FP32_UNPACKED,
+                "traffic": committed_traffic("k_adjoint<true>") if "adjoint" in kname else None,
                 "flops_per_launch": flops, "avg_kernel_ms": kt * 1e3}
 
     cpu = None
@@ -207,6 +289,8 @@ def main():
         "field_evals_per_s_fp32": 1.0 / r32["t_eval"],
         "field_evals_per_s_fp64": 1.0 / res["fp64"]["t_eval"],
         "md_steps_per_s_fp64": 1.0 / res["fp64"]["t_step"],
+        "md_steps_per_s_fp32_eager": 1.0 / r32["t_step_eager"],
+        "slab_b32_n65536_md_steps_per_s": {p: 1.0 / t for p, t in slab.items()} or None,
         "speedup_fp32_over_fp64_step": res["fp64"]["t_step"] / r32["t_step"],
         "interactions_per_eval": inter,
         "kernel_ms": {p: {"traversal": r["t_fwd_kernel"] * 1e3, "adjoint": r["t_adj_kernel"] * 1e3}
@@ -215,6 +299,13 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+    if args.copy_calibration:
+        src = torch.ones(args.copy_calibration << 17, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {args.copy_calibration} MiB read, {args.copy_calibration} MiB written")
 
 
 if __name__ == "__main__":

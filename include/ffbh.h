@@ -22,7 +22,9 @@
  * device memory.  Its only device state is the caller-provided workspace, sized by
  * bh_workspace_bytes, which must stay allocated while the handle is used.  All work is enqueued on the
  * caller's stream (a hipStream_t passed as void*, NULL = the null stream); no call synchronises with
- * the host except bh_check_status.
+ * the host except bh_check_status.  All calls on one handle -- and replays of graphs captured from it --
+ * share its workspace, so they must be ordered: enqueue them on one stream or order the streams.  Two
+ * handles never share state and may run concurrently.
  *
  * Errors.  Arguments that can be checked on the host are checked before anything is enqueued; a
  * failing call returns a negative bh_status and enqueues nothing.  Conditions only the device can see

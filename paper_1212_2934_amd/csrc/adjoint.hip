@@ -179,8 +179,8 @@ __global__ __launch_bounds__(512) void k_adjoint(
         Hs[si] = hx;
         Hs[ntot + si] = hy;
         Hs[2 * ntot + si] = hz;
-        if (Hout) {
-            const int64_t i = (int64_t)perm[si] - (int64_t)seg * n;
+        const int64_t i = (int64_t)perm[si] - (int64_t)seg * n;
+        if (Hout && i >= 0 && i < n) {
             double *out = Hout + (int64_t)seg * 3 * n;
             out[i] = hx;
             out[n + i] = hy;
@@ -197,6 +197,7 @@ __global__ __launch_bounds__(256) void k_hbar(const double *__restrict__ gH, con
     int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (s >= ntot) return;
     const int64_t o = perm[s], b = o / n, i = o - b * n;
+    if (o >= ntot) return;
     const double ge = gE ? gE[b] : 0.0;
     for (int a = 0; a < 3; ++a) {
         double v = gH ? gH[b * 3 * n + a * n + i] : 0.0;
@@ -217,13 +218,13 @@ __global__ __launch_bounds__(256) void k_downward(
     const double *__restrict__ g_gather, const double *__restrict__ g_r, const double *__restrict__ g_m,
     const double *__restrict__ Hs, const double *__restrict__ hext, const double *__restrict__ gE,
     const uint32_t *__restrict__ perm, int64_t n, int64_t ntot, double *__restrict__ dpos,
-    double *__restrict__ dmom)
+    double *__restrict__ dmom, int64_t max_nodes)
 {
     int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (s >= ntot) return;
     double Ax = 0.0, Ay = 0.0, Az = 0.0, Bx = 0.0, By = 0.0, Bz = 0.0;
     int node = leaf_of[s];
-    for (int depth = 0; node >= 0 && depth < 2 * kMaxLevel + 2; ++depth) {
+    for (int depth = 0; node >= 0 && node < max_nodes && depth < 2 * kMaxLevel + 2; ++depth) {
         const double *a = node_adj + 8 * (int64_t)node;
         const double inv = 1.0 / (double)nodes[node].count;
         Ax += a[0]; Ay += a[1]; Az += a[2];
@@ -231,6 +232,7 @@ __global__ __launch_bounds__(256) void k_downward(
         node = nodes[node].parent;
     }
     const int64_t o = perm[s], b = o / n, i = o - b * n;
+    if (o >= ntot) return;
     const double ge = gE ? gE[b] : 0.0;
     const double *he = hext ? hext + 3 * b : nullptr;
     double *dp = dpos + b * 3 * n, *dm = dmom + b * 3 * n;
@@ -294,7 +296,8 @@ hipError_t launch_backward(Handle &h, const double *d_mom, const double *d_hext,
     if (h.ev[3]) (void)hipEventRecord(h.ev[3], s);
     if (d_E) launch_energy_final(h, d_E, s);
     hipLaunchKernelGGL(k_downward, dim3(grid_for(L.ntot, 256)), dim3(256), 0, s, w.nodes, w.leaf_of, w.node_adj,
-                       w.g_gather, w.g_r, w.g_m, w.Hs, d_hext, d_gE, w.perm, L.n, L.ntot, d_dpos, d_dmom);
+                       w.g_gather, w.g_r, w.g_m, w.Hs, d_hext, d_gE, w.perm, L.n, L.ntot, d_dpos, d_dmom,
+                       L.max_nodes);
     if (d_dhext)
         hipLaunchKernelGGL(k_dhext, dim3((unsigned)L.B), dim3(1024), 0, s, d_mom, d_gE, L.n, d_dhext);
     return hipGetLastError();

@@ -224,7 +224,7 @@ static void scan_excl(uint32_t *a, int64_t len, uint32_t *scratch, uint32_t *tot
 
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint64_t *__restrict__ kout,
-    uint32_t *__restrict__ vout, const uint32_t *__restrict__ hist, int64_t n, int tiles, int shift)
+    uint32_t *__restrict__ vout, const uint32_t *__restrict__ hist, int64_t n, int tiles, int shift, int64_t ntot)
 {
     constexpr int kWaves = kSortThreads / kWave;
     __shared__ uint32_t base[kRadixBins];
@@ -264,9 +264,11 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
         }
         __syncthreads();
         if (valid) {
-            uint32_t at = wcnt[wave][d] + before;
-            kout[at] = key;
-            vout[at] = val;
+            const uint32_t at = wcnt[wave][d] + before;
+            if ((int64_t)at < ntot) {  // always true for a consistent histogram
+                kout[at] = key;
+                vout[at] = val;
+            }
         }
         __syncthreads();
     }
@@ -279,8 +281,12 @@ __global__ __launch_bounds__(256) void k_gather3(const double *__restrict__ src,
 {
     int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (s >= ntot) return;
-    int64_t o = perm[s];
-    int64_t b = o / n, i = o - b * n;
+    const int64_t o = perm[s];
+    if (o >= ntot) {
+        set_flag(status, BH_FLAG_TREE);
+        return;
+    }
+    const int64_t b = o / n, i = o - b * n;
     const double *p = src + b * 3 * n;
     bool bad = false;
     for (int a = 0; a < 3; ++a) {
@@ -388,11 +394,11 @@ __global__ __launch_bounds__(256) void k_oct_count(int64_t n, int64_t nint_tot, 
     } else if (lev <= bin_level(delta, ib + p)) {
         in_tree = false;  // an intermediate binary split inside one octant digit
     } else {
-        // octree parent: nearest binary ancestor that starts a cell
+        // octree parent: nearest binary ancestor that starts a cell (at most 2 binary levels up)
         int x = p;
-        while (true) {
+        for (int up = 0; up < 64; ++up) {
             const int px = bparent[ib + x];
-            if (px < 0 || bin_level(delta, ib + x) > bin_level(delta, ib + px)) break;
+            if (px < 0 || px >= n - 1 || bin_level(delta, ib + x) > bin_level(delta, ib + px)) break;
             x = px;
         }
         const int pc = last[ib + x] - first[ib + x] + 1;
@@ -409,8 +415,11 @@ __global__ __launch_bounds__(256) void k_oct_count(int64_t n, int64_t nint_tot, 
             stk[sp++] = left[g];
             while (sp > 0) {
                 const int32_t c = stk[--sp];
-                if (c < 0 || bin_level(delta, ib + c) > lev) {
+                if (c < 0 || c >= n - 1 || bin_level(delta, ib + c) > lev) {
                     ++out;
+                } else if (sp > 5) {  // one octant digit spans at most three binary levels
+                    set_flag(status, BH_FLAG_TREE);
+                    break;
                 } else {
                     stk[sp++] = right[ib + c];
                     stk[sp++] = left[ib + c];
@@ -423,9 +432,9 @@ __global__ __launch_bounds__(256) void k_oct_count(int64_t n, int64_t nint_tot, 
 }
 
 // Write the records of the children of every in-tree internal node (and of the roots).
-__device__ inline void write_leaf_of(int32_t *leaf_of, int64_t first, int cnt, int id)
+__device__ inline void write_leaf_of(int32_t *leaf_of, int64_t first, int cnt, int id, int64_t ntot)
 {
-    for (int k = 0; k < cnt; ++k) leaf_of[first + k] = id;
+    for (int k = 0; k < cnt && first + k < ntot; ++k) leaf_of[first + k] = id;
 }
 
 __global__ __launch_bounds__(256) void k_oct_emit(int64_t n, int64_t nint_tot, int64_t B, int leaf,
@@ -438,7 +447,8 @@ __global__ __launch_bounds__(256) void k_oct_emit(int64_t n, int64_t nint_tot, i
                                                   const uint32_t *__restrict__ scan,
                                                   NodeRec *__restrict__ nodes, int32_t *__restrict__ node_level,
                                                   uint32_t *__restrict__ arrive, int32_t *__restrict__ leaf_of,
-                                                  int32_t *__restrict__ octid, uint32_t *__restrict__ status)
+                                                  int32_t *__restrict__ octid, uint32_t *__restrict__ status,
+                                                  int64_t max_nodes)
 {
     int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (g == 0) status[2] = (uint32_t)B + (nint_tot > 0 ? status[1] : 0u);  // number of nodes
@@ -461,7 +471,7 @@ __global__ __launch_bounds__(256) void k_oct_emit(int64_t n, int64_t nint_tot, i
             }
             octid[rg] = (int32_t)b;
         }
-        if (r.nchild == 0) write_leaf_of(leaf_of, b * n, (int)n, (int)b);
+        if (r.nchild == 0) write_leaf_of(leaf_of, b * n, (int)n, (int)b, B * n);
         nodes[b] = r;
         node_level[b] = lev;
         arrive[b] = 0u;
@@ -472,6 +482,10 @@ __global__ __launch_bounds__(256) void k_oct_emit(int64_t n, int64_t nint_tot, i
     const int64_t b = g / (n - 1), ib = b * (n - 1);
     const int lev = bin_level(delta, g);
     int id = (int)(B + scan[g]);
+    if ((int64_t)id + nc > max_nodes) {
+        set_flag(status, BH_FLAG_TREE);
+        return;
+    }
     int32_t stk[8];
     int sp = 0;
     stk[sp++] = right[g];
@@ -479,7 +493,15 @@ __global__ __launch_bounds__(256) void k_oct_emit(int64_t n, int64_t nint_tot, i
     while (sp > 0) {
         const int32_t c = stk[--sp];
         const bool particle = c < 0;
+        if (!particle && c >= n - 1) {
+            set_flag(status, BH_FLAG_TREE);
+            break;
+        }
         if (particle || bin_level(delta, ib + c) > lev) {
+            if (id >= B + (int64_t)scan[g] + nc || (particle && ~c >= n)) {
+                set_flag(status, BH_FLAG_TREE);
+                break;
+            }
             NodeRec r{};
             int cf, cc, clev;
             int ch = -1, cn = 0;
@@ -508,8 +530,11 @@ __global__ __launch_bounds__(256) void k_oct_emit(int64_t n, int64_t nint_tot, i
             nodes[id] = r;
             node_level[id] = clev;
             arrive[id] = 0u;
-            if (cn == 0) write_leaf_of(leaf_of, b * n + cf, cc, id);
+            if (cn == 0) write_leaf_of(leaf_of, b * n + cf, cc, id, B * n);
             ++id;
+        } else if (sp > 5) {
+            set_flag(status, BH_FLAG_TREE);
+            break;
         } else {
             stk[sp++] = right[ib + c];
             stk[sp++] = left[ib + c];
@@ -520,7 +545,8 @@ __global__ __launch_bounds__(256) void k_oct_emit(int64_t n, int64_t nint_tot, i
 // Parent links: every in-tree internal node stamps its id into its children.
 __global__ __launch_bounds__(256) void k_oct_link(int64_t nint_tot, int64_t B, const int32_t *__restrict__ nchild,
                                                   const uint32_t *__restrict__ scan,
-                                                  const int32_t *__restrict__ octid, NodeRec *__restrict__ nodes)
+                                                  const int32_t *__restrict__ octid, NodeRec *__restrict__ nodes,
+                                                  int64_t max_nodes)
 {
     int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (g >= nint_tot) return;
@@ -528,6 +554,7 @@ __global__ __launch_bounds__(256) void k_oct_link(int64_t nint_tot, int64_t B, c
     if (nc == 0) return;
     const int self = octid[g];
     const int c0 = (int)(B + scan[g]);
+    if (nc < 0 || nc > 8 || (int64_t)c0 + nc > max_nodes) return;
     for (int q = 0; q < nc; ++q) nodes[c0 + q].parent = self;
 }
 
@@ -549,8 +576,10 @@ __global__ __launch_bounds__(256) void k_level_count(const int32_t *__restrict__
     if (threadIdx.x <= kMaxLevel) h[threadIdx.x] = 0u;
     __syncthreads();
     const int64_t nn = min((int64_t)*num_nodes, max_nodes);
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nn; i += (int64_t)gridDim.x * 256)
-        atomicAdd(&h[node_level[i]], 1u);
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nn; i += (int64_t)gridDim.x * 256) {
+        const int lev = node_level[i];
+        if ((unsigned)lev <= (unsigned)kMaxLevel) atomicAdd(&h[lev], 1u);
+    }
     __syncthreads();
     if (threadIdx.x <= kMaxLevel && h[threadIdx.x]) atomicAdd(&lvl[threadIdx.x], h[threadIdx.x]);
 }
@@ -580,12 +609,13 @@ __global__ __launch_bounds__(256) void k_level_scatter(const int32_t *__restrict
     if ((int64_t)blockIdx.x * 256 >= nn) return;  // whole block beyond the nodes
     if (threadIdx.x <= kMaxLevel) cnt[threadIdx.x] = 0u;
     __syncthreads();
-    const int lev = i < nn ? node_level[i] : -1;
+    int lev = i < nn ? node_level[i] : -1;
+    if (lev > kMaxLevel) lev = -1;
     const uint32_t r = lev >= 0 ? atomicAdd(&cnt[lev], 1u) : 0u;
     __syncthreads();
     if (threadIdx.x <= kMaxLevel && cnt[threadIdx.x]) base[threadIdx.x] = atomicAdd(&lvl[64 + threadIdx.x], cnt[threadIdx.x]);
     __syncthreads();
-    if (lev >= 0) lvl_nodes[base[lev] + r] = (int32_t)i;
+    if (lev >= 0 && (int64_t)base[lev] + r < max_nodes) lvl_nodes[base[lev] + r] = (int32_t)i;
 }
 
 __global__ void k_zero_u32(uint32_t *a, int len)
@@ -601,12 +631,17 @@ __global__ __launch_bounds__(256) void k_upward_level(const double *__restrict__
                                                       const uint32_t *__restrict__ lvl,
                                                       const int32_t *__restrict__ lvl_nodes,
                                                       const double *__restrict__ bbox, double *__restrict__ node_box,
-                                                      int level)
+                                                      int level, int64_t max_nodes)
 {
-    const uint32_t b0 = lvl[32 + level], b1 = lvl[32 + level + 1];
+    const uint32_t b0 = lvl[32 + level];
+    const uint32_t b1 = (int64_t)lvl[32 + level + 1] < max_nodes ? lvl[32 + level + 1] : (uint32_t)max_nodes;
     for (uint32_t q = b0 + blockIdx.x * 256 + threadIdx.x; q < b1; q += gridDim.x * 256) {
         const int id = lvl_nodes[q];
+        if (id < 0 || id >= max_nodes) continue;
         const NodeRec nd = nodes[id];
+        if (nd.first < 0 || nd.count < 1 || (int64_t)nd.first + nd.count > ntot ||
+            (nd.nchild != 0 && (nd.child < 0 || (int64_t)nd.child + nd.nchild > max_nodes)))
+            continue;
         double sx = 0.0, sy = 0.0, sz = 0.0;
         double lo[3] = {__builtin_inf(), __builtin_inf(), __builtin_inf()};
         double hi[3] = {-__builtin_inf(), -__builtin_inf(), -__builtin_inf()};
@@ -669,7 +704,7 @@ static void upward(Handle &h, const double *vals, hipStream_t s)
     const unsigned g = grid_for(L.max_nodes, 256, 512);
     for (int level = kMaxLevel; level >= 0; --level)
         hipLaunchKernelGGL(k_upward_level<MODE>, dim3(g), dim3(256), 0, s, vals, L.ntot, L.n, w.nodes, w.node_adj,
-                           w.node_m64, w.node_level, w.lvl, w.lvl_nodes, w.bbox, w.node_box, level);
+                           w.node_m64, w.node_level, w.lvl, w.lvl_nodes, w.bbox, w.node_box, level, L.max_nodes);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -701,7 +736,7 @@ hipError_t launch_build(Handle &h, const double *d_pos, hipStream_t s)
                            shift, w.hist);
         scan_excl(w.hist, (int64_t)L.hist_len, w.scan_tmp, nullptr, s);
         hipLaunchKernelGGL(k_radix_scatter, dim3(sblocks), dim3(kSortThreads), 0, s, w.keys[src],
-                           w.vals[src], w.keys[dst], w.vals[dst], w.hist, n, tiles, shift);
+                           w.vals[src], w.keys[dst], w.vals[dst], w.hist, n, tiles, shift, ntot);
     }
     // kRadixPasses is even: the sorted data is back in buffer 0
     hipLaunchKernelGGL(k_gather3, dim3(grid_for(ntot, 256)), dim3(256), 0, s, d_pos, w.perm, n, ntot,
@@ -719,10 +754,10 @@ hipError_t launch_build(Handle &h, const double *d_pos, hipStream_t s)
     hipLaunchKernelGGL(k_oct_emit, dim3(grid_for(nint > B ? nint : B, 256)), dim3(256), 0, s, n, nint, B,
                        (int)h.p.leaf_size, w.bin_left, w.bin_right, w.bin_first, w.bin_last, w.bin_delta,
                        w.bin_nchild, w.bin_scan, w.nodes, w.node_level, w.arrive, w.leaf_of, w.bin_octid,
-                       w.status);
+                       w.status, L.max_nodes);
     if (nint > 0)
         hipLaunchKernelGGL(k_oct_link, dim3(grid_for(nint, 256)), dim3(256), 0, s, nint, B,
-                           w.bin_nchild, w.bin_scan, w.bin_octid, w.nodes);
+                           w.bin_nchild, w.bin_scan, w.bin_octid, w.nodes, L.max_nodes);
     // bucket the nodes by level, then the upward pass for the centroids
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(128), 0, s, w.lvl, 128);
     hipLaunchKernelGGL(k_level_count, dim3(grid_for(L.max_nodes, 256, 1024)), dim3(256), 0, s, w.node_level,

@@ -137,13 +137,15 @@ __global__ __launch_bounds__(512) void k_field(
         Hs[2 * ntot + si] = hz;
         const int64_t o = perm[si];
         const int64_t i = o - (int64_t)seg * n;
-        double *out = H + (int64_t)seg * 3 * n;
-        out[i] = hx;
-        out[n + i] = hy;
-        out[2 * n + i] = hz;
-        if (COUNT) {
-            cnt_far[o] = nfar;
-            cnt_near[o] = nnear;
+        if (i >= 0 && i < n) {  // always true for a consistent permutation
+            double *out = H + (int64_t)seg * 3 * n;
+            out[i] = hx;
+            out[n + i] = hy;
+            out[2 * n + i] = hz;
+            if (COUNT) {
+                cnt_far[o] = nfar;
+                cnt_near[o] = nnear;
+            }
         }
     }
 }

@@ -121,6 +121,10 @@ __global__ __launch_bounds__(256) void k_wca(const NodeRec *__restrict__ nodes, 
             break;
         }
         const NodeRec nd = nodes[cur];
+        if (nd.first < 0 || nd.count < 1 || (int64_t)nd.first + nd.count > ntot) {
+            if (lane == 0) set_flag(status, BH_FLAG_TREE);
+            break;
+        }
         const double *bx = node_box + 8 * (int64_t)cur;
         const bool active = (mask >> lane) & 1ull;
         // squared distance from the target to the members' bounding box
@@ -154,6 +158,7 @@ __global__ __launch_bounds__(256) void k_wca(const NodeRec *__restrict__ nodes, 
     }
     const int64_t o = perm[si];
     const int64_t i = o - (int64_t)seg * n;
+    if (i < 0 || i >= n) return;
     double *out = F + (int64_t)seg * 3 * n;
     out[i] = fx;
     out[n + i] = fy;
