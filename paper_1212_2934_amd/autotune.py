@@ -1,8 +1,9 @@
 """Autotuner for the traversal launch shape (tuning_id of bh_params).
 
 Every candidate shape must give the same result as the default shape -- identical per-target interaction
-counts and the same field to the last bit (the traversal of one target does not depend on the shape) --
-before its time counts.  The fastest accepted candidate is cached in a JSON file keyed by device, system
+counts and the same field to the last bit (the traversal of one target does not depend on the shape),
+and the same adjoint to rounding (its scatters are reduced in a shape-dependent order) -- before its
+time counts.  The fastest accepted candidate is cached in a JSON file keyed by device, system
 size, batch, theta, leaf size and precision.
 """
 from __future__ import annotations
@@ -37,7 +38,9 @@ def autotune(pos, mom, hext=None, theta=0.5, leaf=16, precision="fp32_mixed", re
         if key in cache:
             return cache[key]
     ones = torch.ones(batch, dtype=torch.float64, device=pos.device)
+    tol = 1e-12 if precision == "fp64" else 1e-6  # the adjoint's reduction order differs between shapes
     ref = None
+    ref_grad = None
     times = {}
     for tid in range(int(lib().bh_num_tunings())):
         bh = BarnesHut(n, batch, leaf, theta, precision, tuning_id=tid)
@@ -51,7 +54,11 @@ def autotune(pos, mom, hext=None, theta=0.5, leaf=16, precision="fp32_mixed", re
         elif not (torch.equal(H, ref[0]) and torch.equal(counts[0], ref[1][0]) and
                   torch.equal(counts[1], ref[1][1])):
             raise RuntimeError(f"tuning {tid} changed the result; refusing it")
-        bh.field_backward(mom, hext, gE=ones)  # warm
+        dr, _ = bh.field_backward(mom, hext, gE=ones)
+        if ref_grad is None:
+            ref_grad = dr.clone()
+        elif ((dr - ref_grad).norm() / ref_grad.norm()).item() > tol:
+            raise RuntimeError(f"tuning {tid} changed the adjoint beyond rounding; refusing it")
         torch.cuda.synchronize()
         best = float("inf")
         for _ in range(repeats):

@@ -189,6 +189,204 @@ __global__ __launch_bounds__(512) void k_adjoint(
     }
 }
 
+// Workgroup-cooperative variant: NW waves (NW*64 consecutive targets of one system) walk the union of
+// their traversals in lock-step, one barrier per node visit.  Each wave reduces its lanes' scatter
+// values with DPP; the NW wave partials meet in LDS and one set of atomics per node (and per source of a
+// leaf) is issued for the whole workgroup instead of one per wave.  Every wave keeps its own lane stack;
+// the stacks stay identical because push and pop decisions use the workgroup-wide "any lane opened"
+// flag.  Per-lane decisions, and therefore every lane's sum, are those of the definition.
+template <bool MIXED, int NW>
+__global__ __launch_bounds__(NW * 64) void k_adjoint_wg(
+    const NodeRec *__restrict__ nodes, const double *__restrict__ node_m64, const double *__restrict__ spos,
+    const double *__restrict__ smom, const void *__restrict__ src, const double *__restrict__ hbar,
+    const uint32_t *__restrict__ perm, const double *__restrict__ hext, double *__restrict__ g_gather,
+    double *__restrict__ g_r, double *__restrict__ g_m, double *__restrict__ node_adj, double *__restrict__ Hs,
+    double *__restrict__ Hout, double *__restrict__ e_part, uint32_t *__restrict__ status, int64_t n, int64_t ntot,
+    int waves_per_seg, int blocks_per_seg, double theta2, int max_nodes)
+{
+    using T = typename std::conditional<MIXED, float, double>::type;
+    using Src = typename std::conditional<MIXED, Src32, Src64>::type;
+    __shared__ T fpart[2][NW][6];      // far-node partials per wave, double-buffered by visit parity
+    __shared__ uint32_t flags[2][NW];  // bit 0: some lane of the wave opened the node; bit 1: accepted
+    __shared__ T lpart[NW][64][6];     // leaf source partials per wave (one chunk of up to 64 sources)
+    const Src *__restrict__ sr = (const Src *)src;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wv = (int)(threadIdx.x / kWave);
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    const int seg = blk / blocks_per_seg;
+    const int wseg = (blk - seg * blocks_per_seg) * NW + wv;  // wave index within the system
+    const int local = wseg * kWave + lane;
+    const bool valid = wseg < waves_per_seg && local < n;
+    const int si = (int)(seg * n) + (valid ? local : 0);
+    const double rx = spos[si], ry = spos[ntot + si], rz = spos[2 * ntot + si];
+    const T ax = valid ? (T)hbar[si] : (T)0, ay = valid ? (T)hbar[ntot + si] : (T)0,
+            az = valid ? (T)hbar[2 * ntot + si] : (T)0;
+
+    double grx = 0.0, gry = 0.0, grz = 0.0, hx = 0.0, hy = 0.0, hz = 0.0;
+    T pgx = 0, pgy = 0, pgz = 0, phx = 0, phy = 0, phz = 0;
+    bool coincident = false;
+
+    LaneStack st{0, 0, 0, 0};
+    st.push(lane, seg, 1, __ballot(valid));  // every wave pushes the root, even with no valid lane
+    int guard = max_nodes;
+    int par = 0;
+    bool broken = false;
+    while (st.sp > 0) {
+        uint64_t mask;
+        const int cur = st.pop(lane, mask);
+        if (--guard < 0 || (unsigned)cur >= (unsigned)max_nodes) {  // identical in every wave
+            broken = true;
+            break;
+        }
+        const NodeRec nd = nodes[cur];
+        if (nd.first < 0 || nd.count < 1 || (int64_t)nd.first + nd.count > ntot) {
+            broken = true;
+            break;
+        }
+        const bool active = (mask >> lane) & 1ull;
+        const bool inside = (unsigned)(si - nd.first) < (unsigned)nd.count;
+        const double dx = rx - nd.cx, dy = ry - nd.cy, dz = rz - nd.cz;
+        const double d2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
+        const bool acc = active && !inside && nd.s2 < theta2 * d2;
+        const uint64_t accm = __ballot(acc);
+        T v0 = 0, v1 = 0, v2 = 0, v3 = 0, v4 = 0, v5 = 0;
+        if (accm != 0ull) {
+            T bx, by, bz;
+            if (MIXED) {
+                bx = (T)nd.mx; by = (T)nd.my; bz = (T)nd.mz;
+            } else {
+                const double *m = node_m64 + 4 * (int64_t)cur;
+                bx = (T)m[0]; by = (T)m[1]; bz = (T)m[2];
+            }
+            T gx, gy, gz, tx, ty, tz, fx, fy, fz;
+            adj_field<T>((T)dx, (T)dy, (T)dz, ax, ay, az, bx, by, bz, gx, gy, gz, tx, ty, tz, fx, fy, fz);
+            gx = acc ? gx : (T)0; gy = acc ? gy : (T)0; gz = acc ? gz : (T)0;
+            tx = acc ? tx : (T)0; ty = acc ? ty : (T)0; tz = acc ? tz : (T)0;
+            fx = acc ? fx : (T)0; fy = acc ? fy : (T)0; fz = acc ? fz : (T)0;
+            if (MIXED) {
+                pgx += gx; pgy += gy; pgz += gz;
+                phx += fx; phy += fy; phz += fz;
+            } else {
+                grx += gx; gry += gy; grz += gz;
+                hx += fx; hy += fy; hz += fz;
+            }
+            v0 = wave_sum_to63(tx); v1 = wave_sum_to63(ty); v2 = wave_sum_to63(tz);
+            v3 = wave_sum_to63(-gx); v4 = wave_sum_to63(-gy); v5 = wave_sum_to63(-gz);
+        }
+        const uint64_t open = __ballot(active && !acc);
+        if (lane == kWave - 1) {
+            fpart[par][wv][0] = v0; fpart[par][wv][1] = v1; fpart[par][wv][2] = v2;
+            fpart[par][wv][3] = v3; fpart[par][wv][4] = v4; fpart[par][wv][5] = v5;
+            flags[par][wv] = (open != 0ull ? 1u : 0u) | (accm != 0ull ? 2u : 0u);
+        }
+        __syncthreads();
+        uint32_t any = 0u;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) any |= flags[par][w];
+        if ((any & 2u) && wv == 0 && lane < 6) {
+            T sum = 0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) sum += fpart[par][w][lane];
+            atomic_add_d(node_adj + 8 * (int64_t)cur + lane, (double)sum);
+        }
+        par ^= 1;
+        if (!(any & 1u)) continue;
+        if (nd.nchild != 0) {
+            if (st.sp >= kStackMax) {
+                broken = true;
+                break;
+            }
+            st.push(lane, nd.child, nd.nchild, open);  // with this wave's mask, possibly empty
+            continue;
+        }
+        // leaf: sources in chunks of 64; per chunk every wave writes its per-source partials, then the
+        // workgroup adds them and issues one atomic per (source, component)
+        const bool me = (open >> lane) & 1ull;
+        for (int c0 = 0; c0 < nd.count; c0 += 64) {
+            const int cn = min(64, nd.count - c0);
+            const Src *q = sr + nd.first + c0;
+            for (int j = 0; j < cn; ++j, ++q) {
+                const int k = nd.first + c0 + j;
+                const Src sk = *q;
+                const T x = (T)(rx - sk.x), y = (T)(ry - sk.y), z = (T)(rz - sk.z);
+                const T r2 = x * x + y * y + z * z;
+                const bool other = me && k != si;
+                const bool use = other && r2 > (T)0;
+                coincident |= other && !(r2 > (T)0);
+                T w0 = 0, w1 = 0, w2 = 0, w3 = 0, w4 = 0, w5 = 0;
+                if (__ballot(use) != 0ull) {
+                    T qx, qy, qz, ux, uy, uz, fx, fy, fz;
+                    adj_field<T>(x, y, z, ax, ay, az, (T)sk.mx, (T)sk.my, (T)sk.mz, qx, qy, qz, ux, uy, uz, fx, fy,
+                                 fz);
+                    qx = use ? qx : (T)0; qy = use ? qy : (T)0; qz = use ? qz : (T)0;
+                    ux = use ? ux : (T)0; uy = use ? uy : (T)0; uz = use ? uz : (T)0;
+                    if (MIXED) {
+                        pgx += qx; pgy += qy; pgz += qz;
+                        phx += use ? fx : (T)0; phy += use ? fy : (T)0; phz += use ? fz : (T)0;
+                    } else {
+                        grx += qx; gry += qy; grz += qz;
+                        hx += use ? fx : (T)0; hy += use ? fy : (T)0; hz += use ? fz : (T)0;
+                    }
+                    w0 = wave_sum_to63(-qx); w1 = wave_sum_to63(-qy); w2 = wave_sum_to63(-qz);
+                    w3 = wave_sum_to63(ux); w4 = wave_sum_to63(uy); w5 = wave_sum_to63(uz);
+                }
+                if (lane == kWave - 1) {
+                    lpart[wv][j][0] = w0; lpart[wv][j][1] = w1; lpart[wv][j][2] = w2;
+                    lpart[wv][j][3] = w3; lpart[wv][j][4] = w4; lpart[wv][j][5] = w5;
+                }
+            }
+            __syncthreads();
+            for (int p = threadIdx.x; p < cn * 6; p += NW * 64) {
+                const int j = p / 6, comp = p - 6 * j;
+                T sum = 0;
+#pragma unroll
+                for (int w = 0; w < NW; ++w) sum += lpart[w][j][comp];
+                if (sum != (T)0) {
+                    const int k = nd.first + c0 + j;
+                    double *dst = comp < 3 ? g_r + comp * ntot + k : g_m + (comp - 3) * ntot + k;
+                    atomic_add_d(dst, (double)sum);
+                }
+            }
+            __syncthreads();  // lpart is rewritten by the next chunk
+        }
+        if (MIXED) {
+            grx += (double)pgx; gry += (double)pgy; grz += (double)pgz;
+            hx += (double)phx; hy += (double)phy; hz += (double)phz;
+            pgx = pgy = pgz = phx = phy = phz = (T)0;
+        }
+    }
+    if (broken && threadIdx.x == 0) set_flag(status, BH_FLAG_TREE);
+    if (MIXED) {
+        grx += (double)pgx; gry += (double)pgy; grz += (double)pgz;
+        hx += (double)phx; hy += (double)phy; hz += (double)phz;
+    }
+    if (__ballot(coincident) != 0ull && lane == 0) set_flag(status, BH_FLAG_COINCIDENT);
+
+    double e = 0.0;
+    if (valid) {
+        const double mx = smom[si], my = smom[ntot + si], mz = smom[2 * ntot + si];
+        e = -0.5 * (mx * hx + my * hy + mz * hz);
+        if (hext) e -= mx * hext[3 * seg] + my * hext[3 * seg + 1] + mz * hext[3 * seg + 2];
+    }
+    e = wave_sum(e);
+    if (lane == 0 && wseg < waves_per_seg) e_part[(int64_t)seg * waves_per_seg + wseg] = e;
+    if (valid) {
+        g_gather[si] = grx;
+        g_gather[ntot + si] = gry;
+        g_gather[2 * ntot + si] = grz;
+        Hs[si] = hx;
+        Hs[ntot + si] = hy;
+        Hs[2 * ntot + si] = hz;
+        const int64_t i = (int64_t)perm[si] - (int64_t)seg * n;
+        if (Hout && i >= 0 && i < n) {
+            double *out = Hout + (int64_t)seg * 3 * n;
+            out[i] = hx;
+            out[n + i] = hy;
+            out[2 * n + i] = hz;
+        }
+    }
+}
+
 // Upstream field gradient in sorted order: Hbar = gH - 1/2 gE m.
 __global__ __launch_bounds__(256) void k_hbar(const double *__restrict__ gH, const double *__restrict__ gE,
                                               const double *__restrict__ smom, const uint32_t *__restrict__ perm,
@@ -283,7 +481,22 @@ hipError_t launch_backward(Handle &h, const double *d_mom, const double *d_hext,
     const int waves_per_seg = (int)((L.n + kWave - 1) / kWave);
     const double theta2 = h.p.theta * h.p.theta;
     if (h.ev[2]) (void)hipEventRecord(h.ev[2], s);
-    if (h.p.precision == BH_FP32_MIXED)
+    const bool mixed = h.p.precision == BH_FP32_MIXED;
+    const int nw = h.adj_coop;
+    if (nw > 1) {
+        const int bps = (waves_per_seg + nw - 1) / nw;
+        const unsigned gblocks = (unsigned)(L.B * bps);
+#define FFBH_WG(MX, NWV)                                                                                       \
+    hipLaunchKernelGGL((k_adjoint_wg<MX, NWV>), dim3(gblocks), dim3(NWV * kWave), 0, s, w.nodes, w.node_m64,  \
+                       w.spos, w.smom, MX ? w.src32 : w.src64, w.hbar, w.perm, d_hext, w.g_gather, w.g_r, w.g_m, \
+                       w.node_adj, w.Hs, d_H, w.e_part, w.status, L.n, L.ntot, waves_per_seg, bps, theta2,         \
+                       (int)L.max_nodes)
+        if (mixed && nw == 2) FFBH_WG(true, 2);
+        else if (mixed) FFBH_WG(true, 4);
+        else if (nw == 2) FFBH_WG(false, 2);
+        else FFBH_WG(false, 4);
+#undef FFBH_WG
+    } else if (mixed)
         hipLaunchKernelGGL(k_adjoint<true>, dim3(blocks), dim3(wpb * kWave), 0, s, w.nodes, w.node_m64, w.spos,
                            w.smom, w.src32, w.hbar, w.perm, d_hext, w.g_gather, w.g_r, w.g_m, w.node_adj, w.Hs, d_H,
                            w.e_part, w.status, L.n, L.ntot, waves_per_seg, (int)L.num_waves, theta2,

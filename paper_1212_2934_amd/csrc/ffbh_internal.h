@@ -104,6 +104,7 @@ struct Handle {
     int device;
     int built;           // a bh_build has been enqueued
     int waves_per_block; // traversal launch shape
+    int adj_coop;        // waves walking the adjoint traversal together (1: independent waves)
     int32_t *cnt_far, *cnt_near;  // optional per-target counters (device)
     hipEvent_t ev[4];             // optional timing events around the traversal kernels
 };

@@ -19,8 +19,9 @@ def rel(a, b):
     return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
-def _gpu_grad(pos, mom, hext, theta, precision, gH=None, gE=1.0, leaf=16, want_dhext=False):
-    bh = BarnesHut(pos.shape[-1], 1 if pos.ndim == 2 else pos.shape[0], leaf, theta, precision)
+def _gpu_grad(pos, mom, hext, theta, precision, gH=None, gE=1.0, leaf=16, want_dhext=False, tuning_id=-1):
+    bh = BarnesHut(pos.shape[-1], 1 if pos.ndim == 2 else pos.shape[0], leaf, theta, precision,
+                   tuning_id=tuning_id)
     p = torch.from_numpy(pos).cuda()
     m = torch.from_numpy(mom).cuda()
     he = torch.from_numpy(np.asarray(hext, float)).cuda()
@@ -32,19 +33,21 @@ def _gpu_grad(pos, mom, hext, theta, precision, gH=None, gE=1.0, leaf=16, want_d
     return [None if o is None else o.cpu().numpy() for o in out]
 
 
+@pytest.mark.parametrize("tuning_id", [0, 4, 5])  # independent waves; 2 and 4 waves walking together
 @pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
-def test_energy_gradient_config1(oracle_mod, precision):
+def test_energy_gradient_config1(oracle_mod, precision, tuning_id):
     w = workloads.uniform_cube(4096, 32.0, seed=1001, hext=(0.0, 0.0, 1.0))
     H, E, dr, dm = oracle_mod.Tree(w.pos, w.mom, 16).energy_grad(0.5, w.hext)
-    gdr, gdm, gdh = _gpu_grad(w.pos, w.mom, w.hext, 0.5, precision, want_dhext=True)
+    gdr, gdm, gdh = _gpu_grad(w.pos, w.mom, w.hext, 0.5, precision, want_dhext=True, tuning_id=tuning_id)
     assert rel(gdr, dr) <= TOL[precision]
     assert rel(gdm, dm) <= TOL[precision]
     np.testing.assert_allclose(gdh[0], -w.mom.sum(axis=1), rtol=1e-12)
 
 
+@pytest.mark.parametrize("tuning_id", [0, 5])
 @pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
 @pytest.mark.parametrize("theta", [0.3, 0.7])
-def test_general_vjp_chains(oracle_mod, precision, theta):
+def test_general_vjp_chains(oracle_mod, precision, theta, tuning_id):
     w = workloads.config3(seed=11, n=5000 + 3)
     rng = np.random.default_rng(12)
     gH = rng.standard_normal((3, w.n))
@@ -54,7 +57,7 @@ def test_general_vjp_chains(oracle_mod, precision, theta):
     H, _, _ = t.field(theta)
     dr, dm = t.vjp(theta, gH - 0.5 * gE * w.mom)
     dm = dm + gE * (-0.5 * H - hext[:, None])
-    gdr, gdm = _gpu_grad(w.pos, w.mom, hext, theta, precision, gH=gH, gE=gE)
+    gdr, gdm = _gpu_grad(w.pos, w.mom, hext, theta, precision, gH=gH, gE=gE, tuning_id=tuning_id)
     assert rel(gdr, dr) <= TOL[precision]
     assert rel(gdm, dm) <= TOL[precision]
 
@@ -67,13 +70,14 @@ def test_theta_zero_equals_allpairs_force(oracle_mod):
     assert rel(gdm, -oracle_mod.allpairs_field(w.pos, w.mom)) <= 1e-12
 
 
-def test_batched_adjoint(oracle_mod):
-    B, n = 3, 2000
+@pytest.mark.parametrize("tuning_id", [0, 4, 5])
+def test_batched_adjoint(oracle_mod, tuning_id):
+    B, n = 3, 2000 + 77  # ragged: the last workgroup of each system is partly empty
     ws = [workloads.uniform_cube(n, 26.0, seed=30 + b) for b in range(B)]
     pos = np.stack([x.pos for x in ws])
     mom = np.stack([x.mom for x in ws])
     hext = np.array([0.0, 0.0, 0.7])
-    gdr, gdm = _gpu_grad(pos, mom, hext, 0.5, "fp32_mixed")
+    gdr, gdm = _gpu_grad(pos, mom, hext, 0.5, "fp32_mixed", tuning_id=tuning_id)
     for b, x in enumerate(ws):
         _, _, dr, dm = oracle_mod.Tree(x.pos, x.mom, 16).energy_grad(0.5, hext)
         assert rel(gdr[b], dr) <= 1e-5 and rel(gdm[b], dm) <= 1e-5
