@@ -17,26 +17,26 @@ __device__ inline void atomic_add_d(double *p, double v)
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Six scatter values of one wave added to global memory: by the single contributing lane directly, or
-// reduced across the wave (DPP, total in lane 63) and added by lane 63.  Called in uniform control flow.
+// Six scatter values of one wave added to six consecutive doubles at p (a 64-byte aligned record): the values
+// are reduced across the contributing lanes (DPP, total in lane 63; or taken from the single
+// contributing lane), made uniform with v_readlane, and lanes 0..5 add component `lane` with one
+// atomic instruction, so the memory system sees one request per record.  Uniform control flow.
 template <typename T>
-__device__ inline void scatter6(uint64_t who, int lane, double *p0, double *p1, double *p2, double *p3, double *p4,
-                                double *p5, T v0, T v1, T v2, T v3, T v4, T v5)
+__device__ inline void scatter6(uint64_t who, int lane, double *p, T v0, T v1, T v2, T v3, T v4, T v5)
 {
     if (who == 0ull) return;
+    int src;
     if ((who & (who - 1ull)) == 0ull) {
-        if ((who >> lane) & 1ull) {
-            atomic_add_d(p0, (double)v0); atomic_add_d(p1, (double)v1); atomic_add_d(p2, (double)v2);
-            atomic_add_d(p3, (double)v3); atomic_add_d(p4, (double)v4); atomic_add_d(p5, (double)v5);
-        }
-        return;
+        src = __builtin_ctzll(who);
+    } else {
+        v0 = wave_sum_to63(v0); v1 = wave_sum_to63(v1); v2 = wave_sum_to63(v2);
+        v3 = wave_sum_to63(v3); v4 = wave_sum_to63(v4); v5 = wave_sum_to63(v5);
+        src = kWave - 1;
     }
-    v0 = wave_sum_to63(v0); v1 = wave_sum_to63(v1); v2 = wave_sum_to63(v2);
-    v3 = wave_sum_to63(v3); v4 = wave_sum_to63(v4); v5 = wave_sum_to63(v5);
-    if (lane == kWave - 1) {
-        atomic_add_d(p0, (double)v0); atomic_add_d(p1, (double)v1); atomic_add_d(p2, (double)v2);
-        atomic_add_d(p3, (double)v3); atomic_add_d(p4, (double)v4); atomic_add_d(p5, (double)v5);
-    }
+    const double u0 = (double)readlane_t(v0, src), u1 = (double)readlane_t(v1, src), u2 = (double)readlane_t(v2, src);
+    const double u3 = (double)readlane_t(v3, src), u4 = (double)readlane_t(v4, src), u5 = (double)readlane_t(v5, src);
+    const double mine = lane == 0 ? u0 : lane == 1 ? u1 : lane == 2 ? u2 : lane == 3 ? u3 : lane == 4 ? u4 : u5;
+    if (lane < 6) atomic_add_d(p + lane, mine);
 }
 
 // Forward field and adjoint in one traversal (the upstream gradient Hbar does not depend on H).
@@ -47,7 +47,7 @@ __global__ __launch_bounds__(512) void k_adjoint(
     const NodeRec *__restrict__ nodes, const double *__restrict__ node_m64, const double *__restrict__ spos,
     const double *__restrict__ smom, const void *__restrict__ src, const double *__restrict__ hbar,
     const uint32_t *__restrict__ perm, const double *__restrict__ hext, double *__restrict__ g_gather,
-    double *__restrict__ g_r, double *__restrict__ g_m, double *__restrict__ node_adj, double *__restrict__ Hs,
+    double *__restrict__ g_rm, double *__restrict__ node_adj, double *__restrict__ Hs,
     double *__restrict__ Hout, double *__restrict__ e_part, uint32_t *__restrict__ status, int64_t n, int64_t ntot,
     int waves_per_seg, int num_waves, double theta2, int max_nodes)
 {
@@ -113,8 +113,7 @@ __global__ __launch_bounds__(512) void k_adjoint(
                 hx += fx; hy += fy; hz += fz;
             }
             // A_C += sum T(x) Hbar over the accepting lanes, B_C -= sum g
-            double *a = node_adj + 8 * (int64_t)cur;
-            scatter6<T>(accm, lane, a, a + 1, a + 2, a + 3, a + 4, a + 5, tx, ty, tz, -gx, -gy, -gz);
+            scatter6<T>(accm, lane, node_adj + 8 * (int64_t)cur, tx, ty, tz, -gx, -gy, -gz);
         }
         const uint64_t open = __ballot(active && !acc);
         if (open == 0ull) continue;
@@ -149,8 +148,7 @@ __global__ __launch_bounds__(512) void k_adjoint(
                 hx += use ? fx : (T)0; hy += use ? fy : (T)0; hz += use ? fz : (T)0;
             }
             // dL/dr_k -= sum g, dL/dm_k += sum T(x) Hbar over the lanes
-            scatter6<T>(usem, lane, g_r + k, g_r + ntot + k, g_r + 2 * ntot + k, g_m + k, g_m + ntot + k,
-                        g_m + 2 * ntot + k, -qx, -qy, -qz, ux, uy, uz);
+            scatter6<T>(usem, lane, g_rm + 8 * (int64_t)k, -qx, -qy, -qz, ux, uy, uz);
         }
         if (MIXED) {
             grx += (double)pgx; gry += (double)pgy; grz += (double)pgz;
@@ -200,7 +198,7 @@ __global__ __launch_bounds__(NW * 64) void k_adjoint_wg(
     const NodeRec *__restrict__ nodes, const double *__restrict__ node_m64, const double *__restrict__ spos,
     const double *__restrict__ smom, const void *__restrict__ src, const double *__restrict__ hbar,
     const uint32_t *__restrict__ perm, const double *__restrict__ hext, double *__restrict__ g_gather,
-    double *__restrict__ g_r, double *__restrict__ g_m, double *__restrict__ node_adj, double *__restrict__ Hs,
+    double *__restrict__ g_rm, double *__restrict__ node_adj, double *__restrict__ Hs,
     double *__restrict__ Hout, double *__restrict__ e_part, uint32_t *__restrict__ status, int64_t n, int64_t ntot,
     int waves_per_seg, int blocks_per_seg, double theta2, int max_nodes)
 {
@@ -341,11 +339,7 @@ __global__ __launch_bounds__(NW * 64) void k_adjoint_wg(
                 T sum = 0;
 #pragma unroll
                 for (int w = 0; w < NW; ++w) sum += lpart[w][j][comp];
-                if (sum != (T)0) {
-                    const int k = nd.first + c0 + j;
-                    double *dst = comp < 3 ? g_r + comp * ntot + k : g_m + (comp - 3) * ntot + k;
-                    atomic_add_d(dst, (double)sum);
-                }
+                if (sum != (T)0) atomic_add_d(g_rm + 8 * (int64_t)(nd.first + c0 + j) + comp, (double)sum);
             }
             __syncthreads();  // lpart is rewritten by the next chunk
         }
@@ -413,8 +407,7 @@ __global__ __launch_bounds__(256) void k_zero(double *__restrict__ a, int64_t le
 // explicit derivative of E in m (-1/2 H - H_ext, times dL/dE) is added; results go to caller order.
 __global__ __launch_bounds__(256) void k_downward(
     const NodeRec *__restrict__ nodes, const int32_t *__restrict__ leaf_of, const double *__restrict__ node_adj,
-    const double *__restrict__ g_gather, const double *__restrict__ g_r, const double *__restrict__ g_m,
-    const double *__restrict__ Hs, const double *__restrict__ hext, const double *__restrict__ gE,
+    const double *__restrict__ g_gather, const double *__restrict__ g_rm, const double *__restrict__ Hs, const double *__restrict__ hext, const double *__restrict__ gE,
     const uint32_t *__restrict__ perm, int64_t n, int64_t ntot, double *__restrict__ dpos,
     double *__restrict__ dmom, int64_t max_nodes)
 {
@@ -434,14 +427,15 @@ __global__ __launch_bounds__(256) void k_downward(
     const double ge = gE ? gE[b] : 0.0;
     const double *he = hext ? hext + 3 * b : nullptr;
     double *dp = dpos + b * 3 * n, *dm = dmom + b * 3 * n;
-    dp[i] = g_gather[s] + g_r[s] + Bx;
-    dp[n + i] = g_gather[ntot + s] + g_r[ntot + s] + By;
-    dp[2 * n + i] = g_gather[2 * ntot + s] + g_r[2 * ntot + s] + Bz;
+    const double *q = g_rm + 8 * s;
+    dp[i] = g_gather[s] + q[0] + Bx;
+    dp[n + i] = g_gather[ntot + s] + q[1] + By;
+    dp[2 * n + i] = g_gather[2 * ntot + s] + q[2] + Bz;
     double ex = -0.5 * Hs[s], ey = -0.5 * Hs[ntot + s], ez = -0.5 * Hs[2 * ntot + s];
     if (he) { ex -= he[0]; ey -= he[1]; ez -= he[2]; }
-    dm[i] = g_m[s] + Ax + ge * ex;
-    dm[n + i] = g_m[ntot + s] + Ay + ge * ey;
-    dm[2 * n + i] = g_m[2 * ntot + s] + Az + ge * ez;
+    dm[i] = q[3] + Ax + ge * ex;
+    dm[n + i] = q[4] + Ay + ge * ey;
+    dm[2 * n + i] = q[5] + Az + ge * ez;
 }
 
 // dL/dH_ext = -dL/dE * sum_i m_i, one block per system.
@@ -475,7 +469,7 @@ hipError_t launch_backward(Handle &h, const double *d_mom, const double *d_hext,
                        L.ntot, w.hbar);
     hipLaunchKernelGGL(k_zero, dim3(grid_for(8 * L.max_nodes, 256, 4096)), dim3(256), 0, s, w.node_adj,
                        8 * L.max_nodes);
-    hipLaunchKernelGGL(k_zero, dim3(grid_for(6 * L.ntot, 256, 4096)), dim3(256), 0, s, w.g_r, 6 * L.ntot);
+    hipLaunchKernelGGL(k_zero, dim3(grid_for(8 * L.ntot, 256, 4096)), dim3(256), 0, s, w.g_rm, 8 * L.ntot);
     const int wpb = h.waves_per_block;
     const unsigned blocks = (unsigned)((L.num_waves + wpb - 1) / wpb);
     const int waves_per_seg = (int)((L.n + kWave - 1) / kWave);
@@ -488,7 +482,7 @@ hipError_t launch_backward(Handle &h, const double *d_mom, const double *d_hext,
         const unsigned gblocks = (unsigned)(L.B * bps);
 #define FFBH_WG(MX, NWV)                                                                                       \
     hipLaunchKernelGGL((k_adjoint_wg<MX, NWV>), dim3(gblocks), dim3(NWV * kWave), 0, s, w.nodes, w.node_m64,  \
-                       w.spos, w.smom, MX ? w.src32 : w.src64, w.hbar, w.perm, d_hext, w.g_gather, w.g_r, w.g_m, \
+                       w.spos, w.smom, MX ? w.src32 : w.src64, w.hbar, w.perm, d_hext, w.g_gather, w.g_rm,      \
                        w.node_adj, w.Hs, d_H, w.e_part, w.status, L.n, L.ntot, waves_per_seg, bps, theta2,         \
                        (int)L.max_nodes)
         if (mixed && nw == 2) FFBH_WG(true, 2);
@@ -498,18 +492,18 @@ hipError_t launch_backward(Handle &h, const double *d_mom, const double *d_hext,
 #undef FFBH_WG
     } else if (mixed)
         hipLaunchKernelGGL(k_adjoint<true>, dim3(blocks), dim3(wpb * kWave), 0, s, w.nodes, w.node_m64, w.spos,
-                           w.smom, w.src32, w.hbar, w.perm, d_hext, w.g_gather, w.g_r, w.g_m, w.node_adj, w.Hs, d_H,
+                           w.smom, w.src32, w.hbar, w.perm, d_hext, w.g_gather, w.g_rm, w.node_adj, w.Hs, d_H,
                            w.e_part, w.status, L.n, L.ntot, waves_per_seg, (int)L.num_waves, theta2,
                            (int)L.max_nodes);
     else
         hipLaunchKernelGGL(k_adjoint<false>, dim3(blocks), dim3(wpb * kWave), 0, s, w.nodes, w.node_m64, w.spos,
-                           w.smom, w.src64, w.hbar, w.perm, d_hext, w.g_gather, w.g_r, w.g_m, w.node_adj, w.Hs, d_H,
+                           w.smom, w.src64, w.hbar, w.perm, d_hext, w.g_gather, w.g_rm, w.node_adj, w.Hs, d_H,
                            w.e_part, w.status, L.n, L.ntot, waves_per_seg, (int)L.num_waves, theta2,
                            (int)L.max_nodes);
     if (h.ev[3]) (void)hipEventRecord(h.ev[3], s);
     if (d_E) launch_energy_final(h, d_E, s);
     hipLaunchKernelGGL(k_downward, dim3(grid_for(L.ntot, 256)), dim3(256), 0, s, w.nodes, w.leaf_of, w.node_adj,
-                       w.g_gather, w.g_r, w.g_m, w.Hs, d_hext, d_gE, w.perm, L.n, L.ntot, d_dpos, d_dmom,
+                       w.g_gather, w.g_rm, w.Hs, d_hext, d_gE, w.perm, L.n, L.ntot, d_dpos, d_dmom,
                        L.max_nodes);
     if (d_dhext)
         hipLaunchKernelGGL(k_dhext, dim3((unsigned)L.B), dim3(1024), 0, s, d_mom, d_gE, L.n, d_dhext);

@@ -80,8 +80,7 @@ void carve(const Layout &Lc, void *base, Workspace &w)
     w.e_part = (double *)take(8 * (size_t)L.num_waves);
     w.node_adj = (double *)take(8 * 8 * mn);
     w.g_gather = (double *)take(3 * 8 * nt);
-    w.g_r = (double *)take(6 * 8 * nt);
-    w.g_m = w.g_r ? w.g_r + 3 * nt : nullptr;
+    w.g_rm = (double *)take(8 * 8 * nt);
     w.hbar = (double *)take(3 * 8 * nt);
     w.Hs = (double *)take(3 * 8 * nt);
     w.H_scratch = (double *)take(3 * 8 * nt);

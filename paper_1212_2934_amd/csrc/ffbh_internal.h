@@ -76,8 +76,7 @@ struct Workspace {
     double *e_part;          // per wave energy partials
     double *node_adj;        // 8 x max_nodes: A (3), B (3) per node, padded; also upward-pass sums
     double *g_gather;        // 3 x N_tot: per-target gathered position adjoint (sorted order)
-    double *g_r;             // 3 x N_tot: scattered position adjoint (sorted order)
-    double *g_m;             // 3 x N_tot: scattered moment adjoint (sorted order), follows g_r
+    double *g_rm;            // N_tot x 8: scattered position (3) and moment (3) adjoint per sorted particle
     double *hbar;            // 3 x N_tot: upstream field gradient (sorted order)
     double *Hs;              // 3 x N_tot: field in sorted order
     double *H_scratch;       // B x 3 x n: field in caller order when the caller does not want it

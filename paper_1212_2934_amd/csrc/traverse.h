@@ -199,6 +199,12 @@ __device__ inline double wave_sum_to63(double v)
     return v;
 }
 
+__device__ inline float readlane_t(float v, int lane)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+__device__ inline double readlane_t(double v, int lane) { return readlane_d(v, lane); }
+
 __device__ inline double wave_sum(double v)
 {
     v += dpp_d<0xb1>(v);
