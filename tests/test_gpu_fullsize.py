@@ -1,0 +1,158 @@
+"""Parity at the full workload sizes, in the launch configuration the benchmark times.
+
+- 2^20 chains (phi 0.1), theta in {0.3, 0.5, 0.7}: FP32-mixed (and FP64 at 0.5) field against the oracle on
+  2048 sampled targets (the oracle computes targets one by one), interaction counts equal on every sampled
+  target; energy against the oracle's full evaluation at theta 0.5.
+- 2^18 differentiation workload: full FP32-mixed adjoint against the oracle's frozen-structure adjoint, and
+  on the 512-particle subset the GPU adjoint against central finite differences of the oracle's frozen
+  energy (h = 1e-6).
+- 2^17 dilute MD: ten FP32-mixed MD steps; on every step the field on the current state against the oracle
+  on sampled targets.
+- 32 x 2^16 slab: graph-replayed batched steps stay finite and flag nothing; step-0 field of two
+  realisations against the oracle.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import energy_err, errors
+from paper_1212_2934_amd import workloads
+from paper_1212_2934_amd.binding import BarnesHut, md_params
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def chains():
+    return workloads.cached("chains_n1048576_seed1003", lambda: workloads.config3())
+
+
+def _field(w, theta, precision, counters=True):
+    bh = BarnesHut(w.n, 1, 16, theta, precision)
+    pos = torch.from_numpy(w.pos).cuda()
+    mom = torch.from_numpy(w.mom).cuda()
+    bh.build(pos)
+    cnt = bh.enable_counters() if counters else None
+    H, E = bh.field(mom, torch.from_numpy(np.asarray(w.hext, float)).cuda())
+    assert bh.check_status() == 0
+    out = dict(H=H.cpu().numpy(), E=E.item())
+    if cnt:
+        out["nf"], out["nr"] = cnt[0].cpu().numpy()[0], cnt[1].cpu().numpy()[0]
+    return out
+
+
+@pytest.mark.parametrize("theta,precision", [(0.3, "fp32_mixed"), (0.5, "fp32_mixed"), (0.7, "fp32_mixed"),
+                                             (0.5, "fp64")])
+def test_chains_2p20_sampled_targets(oracle_mod, chains, theta, precision):
+    w = chains
+    t = oracle_mod.Tree(w.pos, w.mom, 16)
+    idx = np.sort(np.random.default_rng(int(theta * 100)).choice(w.n, 2048, replace=False))
+    Href, nf, nr = t.field_subset(theta, idx)
+    g = _field(w, theta, precision)
+    assert (g["nf"][idx] == nf).all() and (g["nr"][idx] == nr).all()
+    e = errors(g["H"][:, idx], Href)
+    tol = 1e-5 if precision == "fp32_mixed" else 1e-12
+    assert e["l2"] <= tol and (e["p999"] <= tol if precision == "fp32_mixed" else e["max"] <= 1e-10), e
+    if theta == 0.5:
+        H, _, _ = t.field(theta)
+        assert energy_err(g["E"], oracle_mod.energy(w.mom, H), w.mom, H) <= tol
+
+
+def test_differentiation_2p18_full_adjoint(oracle_mod):
+    w = workloads.config4()
+    _, _, dr, dm = oracle_mod.Tree(w.pos, w.mom, 16).energy_grad(0.5, w.hext)
+    bh = BarnesHut(w.n, 1, 16, 0.5, "fp32_mixed")
+    bh.build(torch.from_numpy(w.pos).cuda())
+    gdr, gdm = bh.field_backward(torch.from_numpy(w.mom).cuda(), torch.from_numpy(w.hext).cuda(),
+                                 gE=torch.ones(1, dtype=torch.float64, device="cuda"))
+    assert bh.check_status() == 0
+    gdr, gdm = gdr.cpu().numpy(), gdm.cpu().numpy()
+    assert np.linalg.norm(gdr - dr) / np.linalg.norm(dr) <= 1e-5
+    assert np.linalg.norm(gdm - dm) / np.linalg.norm(dm) <= 1e-5
+    assert errors(gdr, dr)["p999"] <= 1e-4  # per-particle tail of the gradient
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-7), ("fp32_mixed", 1e-5)])
+def test_differentiation_subset_against_finite_differences(oracle_mod, precision, tol):
+    w = workloads.config4()
+    idx = workloads.nearest_to_centre(w.pos, 512)
+    pos, mom = w.pos[:, idx].copy(), w.mom[:, idx].copy()
+    st = oracle_mod.frozen_structure(oracle_mod.Tree(pos, mom, 16), 0.5)
+    fr, fm = oracle_mod.fd_grad_frozen(pos, mom, w.hext, st, 1e-6)
+    bh = BarnesHut(512, 1, 16, 0.5, precision)
+    bh.build(torch.from_numpy(pos).cuda())
+    gdr, gdm = bh.field_backward(torch.from_numpy(mom).cuda(), torch.from_numpy(w.hext).cuda(),
+                                 gE=torch.ones(1, dtype=torch.float64, device="cuda"))
+    gdr, gdm = gdr.cpu().numpy(), gdm.cpu().numpy()
+    assert np.linalg.norm(gdr - fr) / np.linalg.norm(fr) <= tol
+    assert np.linalg.norm(gdm - fm) / np.linalg.norm(fm) <= tol
+
+
+def test_dilute_md_2p17_per_step_field_error(oracle_mod):
+    w = workloads.config2()
+    rng = np.random.default_rng(2002)
+    side = float(w.box_hi[0])
+    state = {"pos": torch.from_numpy(w.pos[None].copy()).cuda(),
+             "vel": torch.from_numpy(rng.standard_normal((1, 3, w.n))).cuda(),
+             "mom": torch.from_numpy(w.mom[None].copy()).cuda(),
+             "omega": torch.from_numpy(rng.standard_normal((1, 3, w.n)) * np.sqrt(10.0)).cuda(),
+             "step": torch.zeros(1, dtype=torch.int64, device="cuda")}
+    hext = torch.from_numpy(np.array([w.hext])).cuda()
+    C3 = ctypes.c_double * 3
+    mdp = md_params(1e-3, 1.0, 0.1, 0.1, 1.0, 0.1, 1.0, 1.0, C3(0, 0, 0), C3(side, side, side), hext.data_ptr(), 2002)
+    md = BarnesHut(w.n, 1, 16, 0.5, "fp32_mixed")
+    probe = BarnesHut(w.n, 1, 16, 0.5, "fp32_mixed")
+    idx = np.sort(np.random.default_rng(7).choice(w.n, 1024, replace=False))
+    worst = 0.0
+    for step in range(10):
+        pos = state["pos"][0].contiguous()
+        mom = state["mom"][0].contiguous()
+        probe.build(pos)
+        H = probe.field(mom, energy=False).cpu().numpy()
+        Href, _, _ = oracle_mod.Tree(pos.cpu().numpy(), mom.cpu().numpy(), 16).field_subset(0.5, idx)
+        e = errors(H[:, idx], Href)
+        worst = max(worst, e["l2"])
+        assert e["l2"] <= 1e-5 and e["p999"] <= 1e-5, (step, e)
+        md.md_step(state, mdp)
+    assert md.check_status() == 0 and probe.check_status() == 0
+    print(f"dilute MD, 10 steps: worst per-step relative L2 field error {worst:.2e}")
+
+
+def test_slab_batch_full_size():
+    w = workloads.cached("slab_b32_n65536_seed1005", lambda: workloads.config5())
+    rng = np.random.default_rng(2005)
+    hext = torch.from_numpy(w.hext).cuda()
+    C3 = ctypes.c_double * 3
+    mdp = md_params(1e-3, 1.0, 0.1, 0.1, 1.0, 0.1, 1.0, 1.0, C3(*w.box_lo), C3(*w.box_hi), hext.data_ptr(), 2005)
+    bh = BarnesHut(w.n, w.batch, 16, 0.5, "fp32_mixed")
+    # step-0 field of two realisations against the oracle (sampled targets)
+    bh.build(torch.from_numpy(w.pos).cuda())
+    H, E = bh.field(torch.from_numpy(w.mom).cuda(), hext)
+    H = H.cpu().numpy()
+    import oracle
+    for b in (0, 31):
+        idx = np.sort(np.random.default_rng(b).choice(w.n, 1024, replace=False))
+        Href, _, _ = oracle.Tree(w.pos[b], w.mom[b], 16).field_subset(0.5, idx)
+        assert errors(H[b][:, idx], Href)["l2"] <= 1e-5
+    state = {"pos": torch.from_numpy(w.pos.copy()).cuda(),
+             "vel": torch.from_numpy(rng.standard_normal(w.pos.shape)).cuda(),
+             "mom": torch.from_numpy(w.mom.copy()).cuda(),
+             "omega": torch.from_numpy(rng.standard_normal(w.pos.shape) * np.sqrt(10.0)).cuda(),
+             "step": torch.zeros(1, dtype=torch.int64, device="cuda")}
+    g = BarnesHut(w.n, w.batch, 16, 0.5, "fp32_mixed")
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    graph = g.capture_md_graph(state, mdp, s)
+    for _ in range(20):
+        graph.launch(s)
+    s.synchronize()
+    assert g.check_status() == 0
+    assert int(state["step"].item()) == 20
+    for k in ("pos", "vel", "mom", "omega"):
+        assert torch.isfinite(state[k]).all()
+    # particles stay inside the slab (walls) and moments stay unit
+    p = state["pos"]
+    assert (p[:, 2] > -0.5).all() and (p[:, 2] < 8.5).all()
+    assert ((state["mom"].norm(dim=1) - 1.0).abs() < 1e-12).all()
