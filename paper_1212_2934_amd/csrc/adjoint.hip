@@ -187,6 +187,210 @@ __global__ __launch_bounds__(512) void k_adjoint(
     }
 }
 
+// Two targets per lane: a wave owns 128 consecutive targets (lane l: targets l and 64 + l of its range).
+// Each lane computes both of its targets against the node (or source) on top of the stack, adds the two
+// contributions before the wave reduction, and one atomic request per node visit or leaf source then
+// covers 128 targets.  Per-target decisions and sums are unchanged.
+template <bool MIXED>
+struct Tgt {
+    using T = typename std::conditional<MIXED, float, double>::type;
+    double rx, ry, rz;
+    T ax, ay, az;
+    double gx, gy, gz, hx, hy, hz;  // FP64 accumulation
+    T pgx, pgy, pgz, phx, phy, phz;  // partial sums since the last flush (MIXED)
+    int si;
+    bool valid;
+
+    __device__ inline void flush()
+    {
+        if (MIXED) {
+            gx += (double)pgx; gy += (double)pgy; gz += (double)pgz;
+            hx += (double)phx; hy += (double)phy; hz += (double)phz;
+            pgx = pgy = pgz = phx = phy = phz = (T)0;
+        }
+    }
+    // accumulate the pair results selected by `use`; returns the scatter values through the refs
+    __device__ inline void add(bool use, T qx, T qy, T qz, T fx, T fy, T fz)
+    {
+        qx = use ? qx : (T)0; qy = use ? qy : (T)0; qz = use ? qz : (T)0;
+        fx = use ? fx : (T)0; fy = use ? fy : (T)0; fz = use ? fz : (T)0;
+        if (MIXED) {
+            pgx += qx; pgy += qy; pgz += qz;
+            phx += fx; phy += fy; phz += fz;
+        } else {
+            gx += qx; gy += qy; gz += qz;
+            hx += fx; hy += fy; hz += fz;
+        }
+    }
+};
+
+template <bool MIXED>
+__device__ inline void tgt_init(Tgt<MIXED> &t, const double *spos, const double *hbar, int64_t ntot, int64_t n,
+                                int seg, int local)
+{
+    using T = typename Tgt<MIXED>::T;
+    t.valid = local < n;
+    t.si = (int)(seg * n) + (t.valid ? local : 0);
+    t.rx = spos[t.si]; t.ry = spos[ntot + t.si]; t.rz = spos[2 * ntot + t.si];
+    t.ax = t.valid ? (T)hbar[t.si] : (T)0;
+    t.ay = t.valid ? (T)hbar[ntot + t.si] : (T)0;
+    t.az = t.valid ? (T)hbar[2 * ntot + t.si] : (T)0;
+    t.gx = t.gy = t.gz = t.hx = t.hy = t.hz = 0.0;
+    t.pgx = t.pgy = t.pgz = t.phx = t.phy = t.phz = (T)0;
+}
+
+template <bool MIXED>
+__device__ inline void tgt_finish(Tgt<MIXED> &t, const double *smom, const double *hext, const uint32_t *perm,
+                                  double *g_gather, double *Hs, double *Hout, int64_t ntot, int64_t n, int seg,
+                                  double &e)
+{
+    t.flush();
+    if (!t.valid) return;
+    const double mx = smom[t.si], my = smom[ntot + t.si], mz = smom[2 * ntot + t.si];
+    e += -0.5 * (mx * t.hx + my * t.hy + mz * t.hz);
+    if (hext) e -= mx * hext[3 * seg] + my * hext[3 * seg + 1] + mz * hext[3 * seg + 2];
+    g_gather[t.si] = t.gx;
+    g_gather[ntot + t.si] = t.gy;
+    g_gather[2 * ntot + t.si] = t.gz;
+    Hs[t.si] = t.hx;
+    Hs[ntot + t.si] = t.hy;
+    Hs[2 * ntot + t.si] = t.hz;
+    const int64_t i = (int64_t)perm[t.si] - (int64_t)seg * n;
+    if (Hout && i >= 0 && i < n) {
+        double *out = Hout + (int64_t)seg * 3 * n;
+        out[i] = t.hx;
+        out[n + i] = t.hy;
+        out[2 * n + i] = t.hz;
+    }
+}
+
+template <bool MIXED>
+__global__ __launch_bounds__(256) void k_adjoint2(
+    const NodeRec *__restrict__ nodes, const double *__restrict__ node_m64, const double *__restrict__ spos,
+    const double *__restrict__ smom, const void *__restrict__ src, const double *__restrict__ hbar,
+    const uint32_t *__restrict__ perm, const double *__restrict__ hext, double *__restrict__ g_gather,
+    double *__restrict__ g_rm, double *__restrict__ node_adj, double *__restrict__ Hs,
+    double *__restrict__ Hout, double *__restrict__ e_part, uint32_t *__restrict__ status, int64_t n, int64_t ntot,
+    int waves_per_seg, int num_waves, double theta2, int max_nodes)
+{
+    using T = typename std::conditional<MIXED, float, double>::type;
+    using Src = typename std::conditional<MIXED, Src32, Src64>::type;
+    const Src *__restrict__ sr = (const Src *)src;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wpb = blockDim.x / kWave;
+    const int gw = xcd_block(blockIdx.x, gridDim.x) * wpb + (int)(threadIdx.x / kWave);
+    if (gw >= num_waves) return;  // whole waves; num_waves counts waves of 128 targets
+    const int seg = gw / waves_per_seg;
+    const int base = (gw - seg * waves_per_seg) * 2 * kWave;
+    Tgt<MIXED> ta, tb;
+    tgt_init<MIXED>(ta, spos, hbar, ntot, n, seg, base + lane);
+    tgt_init<MIXED>(tb, spos, hbar, ntot, n, seg, base + kWave + lane);
+    bool coincident = false;
+
+    LaneStack2 st{0, 0, 0, 0, 0, 0};
+    st.push(lane, seg, 1, __ballot(ta.valid), __ballot(tb.valid));
+    int guard = max_nodes;
+    while (st.sp > 0) {
+        uint64_t ma, mb;
+        const int cur = st.pop(lane, ma, mb);
+        if (--guard < 0 || (unsigned)cur >= (unsigned)max_nodes) {
+            if (lane == 0) set_flag(status, BH_FLAG_TREE);
+            break;
+        }
+        const NodeRec nd = nodes[cur];
+        if (nd.first < 0 || nd.count < 1 || (int64_t)nd.first + nd.count > ntot) {
+            if (lane == 0) set_flag(status, BH_FLAG_TREE);
+            break;
+        }
+        const bool act_a = (ma >> lane) & 1ull, act_b = (mb >> lane) & 1ull;
+        const double dxa = ta.rx - nd.cx, dya = ta.ry - nd.cy, dza = ta.rz - nd.cz;
+        const double dxb = tb.rx - nd.cx, dyb = tb.ry - nd.cy, dzb = tb.rz - nd.cz;
+        const bool acc_a = act_a && (unsigned)(ta.si - nd.first) >= (unsigned)nd.count &&
+                           nd.s2 < theta2 * __builtin_fma(dza, dza, __builtin_fma(dya, dya, dxa * dxa));
+        const bool acc_b = act_b && (unsigned)(tb.si - nd.first) >= (unsigned)nd.count &&
+                           nd.s2 < theta2 * __builtin_fma(dzb, dzb, __builtin_fma(dyb, dyb, dxb * dxb));
+        const uint64_t acca = __ballot(acc_a), accb = __ballot(acc_b);
+        if ((acca | accb) != 0ull) {
+            T bx, by, bz;
+            if (MIXED) {
+                bx = (T)nd.mx; by = (T)nd.my; bz = (T)nd.mz;
+            } else {
+                const double *m = node_m64 + 4 * (int64_t)cur;
+                bx = (T)m[0]; by = (T)m[1]; bz = (T)m[2];
+            }
+            T s0 = 0, s1 = 0, s2v = 0, s3 = 0, s4 = 0, s5 = 0;  // this lane's scatter values, both targets
+            if (acca) {
+                T gx, gy, gz, tx, ty, tz, fx, fy, fz;
+                adj_field<T>((T)dxa, (T)dya, (T)dza, ta.ax, ta.ay, ta.az, bx, by, bz, gx, gy, gz, tx, ty, tz, fx, fy,
+                             fz);
+                ta.add(acc_a, gx, gy, gz, fx, fy, fz);
+                s0 += acc_a ? tx : (T)0; s1 += acc_a ? ty : (T)0; s2v += acc_a ? tz : (T)0;
+                s3 -= acc_a ? gx : (T)0; s4 -= acc_a ? gy : (T)0; s5 -= acc_a ? gz : (T)0;
+            }
+            if (accb) {
+                T gx, gy, gz, tx, ty, tz, fx, fy, fz;
+                adj_field<T>((T)dxb, (T)dyb, (T)dzb, tb.ax, tb.ay, tb.az, bx, by, bz, gx, gy, gz, tx, ty, tz, fx, fy,
+                             fz);
+                tb.add(acc_b, gx, gy, gz, fx, fy, fz);
+                s0 += acc_b ? tx : (T)0; s1 += acc_b ? ty : (T)0; s2v += acc_b ? tz : (T)0;
+                s3 -= acc_b ? gx : (T)0; s4 -= acc_b ? gy : (T)0; s5 -= acc_b ? gz : (T)0;
+            }
+            // A_C += T(x) Hbar, B_C -= g, over the accepting targets of the wave
+            scatter6<T>(acca | accb, lane, node_adj + 8 * (int64_t)cur, s0, s1, s2v, s3, s4, s5);
+        }
+        const uint64_t opa = __ballot(act_a && !acc_a), opb = __ballot(act_b && !acc_b);
+        if ((opa | opb) == 0ull) continue;
+        if (nd.nchild != 0) {
+            if (st.sp >= kStackMax) {
+                if (lane == 0) set_flag(status, BH_FLAG_STACK);
+                break;
+            }
+            st.push(lane, nd.child, nd.nchild, opa, opb);
+            continue;
+        }
+        const bool me_a = (opa >> lane) & 1ull, me_b = (opb >> lane) & 1ull;
+        const Src *q = sr + nd.first;
+        for (int k = nd.first; k < nd.first + nd.count; ++k, ++q) {
+            const Src sk = *q;
+            const T xa = (T)(ta.rx - sk.x), ya = (T)(ta.ry - sk.y), za = (T)(ta.rz - sk.z);
+            const T xb = (T)(tb.rx - sk.x), yb = (T)(tb.ry - sk.y), zb = (T)(tb.rz - sk.z);
+            const T r2a = xa * xa + ya * ya + za * za, r2b = xb * xb + yb * yb + zb * zb;
+            const bool oa = me_a && k != ta.si, ob = me_b && k != tb.si;
+            const bool ua = oa && r2a > (T)0, ub = ob && r2b > (T)0;
+            coincident |= (oa && !(r2a > (T)0)) || (ob && !(r2b > (T)0));
+            const uint64_t usa = __ballot(ua), usb = __ballot(ub);
+            if ((usa | usb) == 0ull) continue;
+            T s0 = 0, s1 = 0, s2v = 0, s3 = 0, s4 = 0, s5 = 0;
+            if (usa) {
+                T qx, qy, qz, ux, uy, uz, fx, fy, fz;
+                adj_field<T>(xa, ya, za, ta.ax, ta.ay, ta.az, (T)sk.mx, (T)sk.my, (T)sk.mz, qx, qy, qz, ux, uy, uz, fx,
+                             fy, fz);
+                ta.add(ua, qx, qy, qz, fx, fy, fz);
+                s0 -= ua ? qx : (T)0; s1 -= ua ? qy : (T)0; s2v -= ua ? qz : (T)0;
+                s3 += ua ? ux : (T)0; s4 += ua ? uy : (T)0; s5 += ua ? uz : (T)0;
+            }
+            if (usb) {
+                T qx, qy, qz, ux, uy, uz, fx, fy, fz;
+                adj_field<T>(xb, yb, zb, tb.ax, tb.ay, tb.az, (T)sk.mx, (T)sk.my, (T)sk.mz, qx, qy, qz, ux, uy, uz, fx,
+                             fy, fz);
+                tb.add(ub, qx, qy, qz, fx, fy, fz);
+                s0 -= ub ? qx : (T)0; s1 -= ub ? qy : (T)0; s2v -= ub ? qz : (T)0;
+                s3 += ub ? ux : (T)0; s4 += ub ? uy : (T)0; s5 += ub ? uz : (T)0;
+            }
+            // dL/dr_k -= sum g, dL/dm_k += sum T(x) Hbar over the wave's targets
+            scatter6<T>(usa | usb, lane, g_rm + 8 * (int64_t)k, s0, s1, s2v, s3, s4, s5);
+        }
+        ta.flush();
+        tb.flush();
+    }
+    if (__ballot(coincident) != 0ull && lane == 0) set_flag(status, BH_FLAG_COINCIDENT);
+    double e = 0.0;
+    tgt_finish<MIXED>(ta, smom, hext, perm, g_gather, Hs, Hout, ntot, n, seg, e);
+    tgt_finish<MIXED>(tb, smom, hext, perm, g_gather, Hs, Hout, ntot, n, seg, e);
+    e = wave_sum(e);
+    if (lane == 0) e_part[gw] = e;
+}
+
 // Workgroup-cooperative variant: NW waves (NW*64 consecutive targets of one system) walk the union of
 // their traversals in lock-step, one barrier per node visit.  Each wave reduces its lanes' scatter
 // values with DPP; the NW wave partials meet in LDS and one set of atomics per node (and per source of a
@@ -490,6 +694,19 @@ hipError_t launch_backward(Handle &h, const double *d_mom, const double *d_hext,
         else if (nw == 2) FFBH_WG(false, 2);
         else FFBH_WG(false, 4);
 #undef FFBH_WG
+    } else if (h.adj_two) {
+        // waves of 128 targets; the energy partials are indexed by these waves
+        const int wps2 = (int)((L.n + 2 * kWave - 1) / (2 * kWave));
+        const int nw2 = (int)(L.B * wps2);
+        const unsigned blocks2 = (unsigned)((nw2 + wpb - 1) / wpb);
+        if (mixed)
+            hipLaunchKernelGGL(k_adjoint2<true>, dim3(blocks2), dim3(wpb * kWave), 0, s, w.nodes, w.node_m64, w.spos,
+                               w.smom, w.src32, w.hbar, w.perm, d_hext, w.g_gather, w.g_rm, w.node_adj, w.Hs, d_H,
+                               w.e_part, w.status, L.n, L.ntot, wps2, nw2, theta2, (int)L.max_nodes);
+        else
+            hipLaunchKernelGGL(k_adjoint2<false>, dim3(blocks2), dim3(wpb * kWave), 0, s, w.nodes, w.node_m64, w.spos,
+                               w.smom, w.src64, w.hbar, w.perm, d_hext, w.g_gather, w.g_rm, w.node_adj, w.Hs, d_H,
+                               w.e_part, w.status, L.n, L.ntot, wps2, nw2, theta2, (int)L.max_nodes);
     } else if (mixed)
         hipLaunchKernelGGL(k_adjoint<true>, dim3(blocks), dim3(wpb * kWave), 0, s, w.nodes, w.node_m64, w.spos,
                            w.smom, w.src32, w.hbar, w.perm, d_hext, w.g_gather, w.g_rm, w.node_adj, w.Hs, d_H,
@@ -501,7 +718,7 @@ hipError_t launch_backward(Handle &h, const double *d_mom, const double *d_hext,
                            w.e_part, w.status, L.n, L.ntot, waves_per_seg, (int)L.num_waves, theta2,
                            (int)L.max_nodes);
     if (h.ev[3]) (void)hipEventRecord(h.ev[3], s);
-    if (d_E) launch_energy_final(h, d_E, s);
+    if (d_E) launch_energy_final(h, d_E, s, h.adj_two && nw <= 1 ? 2 * kWave : kWave);
     hipLaunchKernelGGL(k_downward, dim3(grid_for(L.ntot, 256)), dim3(256), 0, s, w.nodes, w.leaf_of, w.node_adj,
                        w.g_gather, w.g_rm, w.Hs, d_hext, d_gE, w.perm, L.n, L.ntot, d_dpos, d_dmom,
                        L.max_nodes);

@@ -9,8 +9,9 @@ static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // Traversal launch shapes selectable by tuning_id: waves per workgroup of the independent-wave
 // traversals, and how many waves walk the adjoint traversal together (1 = independently).
-static const int kTuneWaves[] = {4, 1, 2, 8, 4, 4};
-static const int kTuneCoop[] = {1, 1, 1, 1, 2, 4};
+static const int kTuneWaves[] = {4, 1, 2, 8, 4, 4, 4, 2};
+static const int kTuneCoop[] = {1, 1, 1, 1, 2, 4, 1, 1};
+static const int kTuneTwo[] = {0, 0, 0, 0, 0, 0, 1, 1};  // adjoint waves own two targets per lane
 static const int kNumTunings = (int)(sizeof(kTuneWaves) / sizeof(kTuneWaves[0]));
 
 Layout plan_layout(const bh_params &p)
@@ -189,6 +190,7 @@ bh_status bh_create(const bh_params *p, void *d_workspace, size_t workspace_byte
     h.built = 0;
     h.waves_per_block = kTuneWaves[p->tuning_id < 0 ? 0 : p->tuning_id];
     h.adj_coop = kTuneCoop[p->tuning_id < 0 ? 0 : p->tuning_id];
+    h.adj_two = kTuneTwo[p->tuning_id < 0 ? 0 : p->tuning_id];
     h.cnt_far = h.cnt_near = nullptr;
     for (int k = 0; k < 4; ++k) h.ev[k] = nullptr;
     hipLaunchKernelGGL(k_init, dim3(1), dim3(256), 0, 0, h.w.status, h.w.ones, (int64_t)L.B);

@@ -104,6 +104,7 @@ struct Handle {
     int built;           // a bh_build has been enqueued
     int waves_per_block; // traversal launch shape
     int adj_coop;        // waves walking the adjoint traversal together (1: independent waves)
+    int adj_two;         // adjoint waves own two targets per lane
     int32_t *cnt_far, *cnt_near;  // optional per-target counters (device)
     hipEvent_t ev[4];             // optional timing events around the traversal kernels
 };
@@ -148,7 +149,7 @@ hipError_t launch_field(Handle &h, const double *d_mom, const double *d_hext, do
 hipError_t launch_backward(Handle &h, const double *d_mom, const double *d_hext, const double *d_gH,
                            const double *d_gE, double *d_dpos, double *d_dmom, double *d_dhext,
                            hipStream_t s, double *d_H = nullptr, double *d_E = nullptr);
-void launch_energy_final(Handle &h, double *d_E, hipStream_t s);
+void launch_energy_final(Handle &h, double *d_E, hipStream_t s, int targets_per_wave);
 hipError_t launch_md(Handle &h, const md_state *st, const md_params *mp, hipStream_t s);
 
 }  // namespace ffbh

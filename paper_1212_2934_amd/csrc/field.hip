@@ -196,13 +196,13 @@ hipError_t launch_field(Handle &h, const double *d_mom, const double *d_hext, do
     else if (cnt) launch_k_field<false, true>(h, d_hext, d_H, s);
     else launch_k_field<false, false>(h, d_hext, d_H, s);
     if (h.ev[1]) (void)hipEventRecord(h.ev[1], s);
-    if (d_E) launch_energy_final(h, d_E, s);
+    if (d_E) launch_energy_final(h, d_E, s, kWave);
     return hipGetLastError();
 }
 
-void launch_energy_final(Handle &h, double *d_E, hipStream_t s)
+void launch_energy_final(Handle &h, double *d_E, hipStream_t s, int targets_per_wave)
 {
-    const int waves_per_seg = (int)((h.L.n + kWave - 1) / kWave);
+    const int waves_per_seg = (int)((h.L.n + targets_per_wave - 1) / targets_per_wave);
     hipLaunchKernelGGL(k_energy_final, dim3((unsigned)h.L.B), dim3(256), 0, s, h.w.e_part, waves_per_seg, d_E);
 }
 

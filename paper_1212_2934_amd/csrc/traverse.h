@@ -255,6 +255,37 @@ struct LaneStack {
     }
 };
 
+// Stack for a wave that owns two targets per lane: entry e in lane e holds the packed node range and
+// the two 64-bit lane masks (first and second target of every lane).
+struct LaneStack2 {
+    int ent, a_lo, a_hi, b_lo, b_hi;
+    int sp;
+
+    __device__ inline void push(int lane, int first, int count, uint64_t ma, uint64_t mb)
+    {
+        const bool here = lane == sp;
+        ent = here ? (first | ((count - 1) << 28)) : ent;
+        a_lo = here ? (int)(uint32_t)ma : a_lo;
+        a_hi = here ? (int)(uint32_t)(ma >> 32) : a_hi;
+        b_lo = here ? (int)(uint32_t)mb : b_lo;
+        b_hi = here ? (int)(uint32_t)(mb >> 32) : b_hi;
+        ++sp;
+    }
+    __device__ inline int pop(int lane, uint64_t &ma, uint64_t &mb)
+    {
+        const int top = sp - 1;
+        const uint32_t e = (uint32_t)__builtin_amdgcn_readlane(ent, top);
+        ma = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(a_hi, top) << 32) |
+             (uint32_t)__builtin_amdgcn_readlane(a_lo, top);
+        mb = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(b_hi, top) << 32) |
+             (uint32_t)__builtin_amdgcn_readlane(b_lo, top);
+        const int c = (int)(e & 0x0fffffffu);
+        if (e >> 28) ent = (lane == top) ? (int)(e + 1u - (1u << 28)) : ent;
+        else sp = top;
+        return c;
+    }
+};
+
 // Sorted source particle for the direct sums: position FP64, moment FP64 (Src64) or FP32 (Src32),
 // 48 bytes so that one particle is two scalar loads from one address.
 struct Src64 {

@@ -33,7 +33,7 @@ def _gpu_grad(pos, mom, hext, theta, precision, gH=None, gE=1.0, leaf=16, want_d
     return [None if o is None else o.cpu().numpy() for o in out]
 
 
-@pytest.mark.parametrize("tuning_id", [0, 4, 5])  # independent waves; 2 and 4 waves walking together
+@pytest.mark.parametrize("tuning_id", [0, 4, 5, 6])  # independent waves; 2 and 4 waves together; two targets per lane
 @pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
 def test_energy_gradient_config1(oracle_mod, precision, tuning_id):
     w = workloads.uniform_cube(4096, 32.0, seed=1001, hext=(0.0, 0.0, 1.0))
@@ -44,7 +44,7 @@ def test_energy_gradient_config1(oracle_mod, precision, tuning_id):
     np.testing.assert_allclose(gdh[0], -w.mom.sum(axis=1), rtol=1e-12)
 
 
-@pytest.mark.parametrize("tuning_id", [0, 5])
+@pytest.mark.parametrize("tuning_id", [0, 5, 7])
 @pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
 @pytest.mark.parametrize("theta", [0.3, 0.7])
 def test_general_vjp_chains(oracle_mod, precision, theta, tuning_id):
@@ -70,7 +70,7 @@ def test_theta_zero_equals_allpairs_force(oracle_mod):
     assert rel(gdm, -oracle_mod.allpairs_field(w.pos, w.mom)) <= 1e-12
 
 
-@pytest.mark.parametrize("tuning_id", [0, 4, 5])
+@pytest.mark.parametrize("tuning_id", [0, 4, 5, 6])
 def test_batched_adjoint(oracle_mod, tuning_id):
     B, n = 3, 2000 + 77  # ragged: the last workgroup of each system is partly empty
     ws = [workloads.uniform_cube(n, 26.0, seed=30 + b) for b in range(B)]
