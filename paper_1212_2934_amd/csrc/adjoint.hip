@@ -18,25 +18,15 @@ __device__ inline void atomic_add_d(double *p, double v)
 }
 
 // Six scatter values of one wave added to six consecutive doubles at p (a 64-byte aligned record): the values
-// are reduced across the contributing lanes (DPP, total in lane 63; or taken from the single
-// contributing lane), made uniform with v_readlane, and lanes 0..5 add component `lane` with one
-// atomic instruction, so the memory system sees one request per record.  Uniform control flow.
+// are summed over the wave (lanes that do not contribute pass zeros) by the transposed reduction, which
+// leaves value c in lane c, and lanes 0..5 add their component with one atomic instruction, so the memory
+// system sees one request per record.  Uniform control flow.
 template <typename T>
 __device__ inline void scatter6(uint64_t who, int lane, double *p, T v0, T v1, T v2, T v3, T v4, T v5)
 {
     if (who == 0ull) return;
-    int src;
-    if ((who & (who - 1ull)) == 0ull) {
-        src = __builtin_ctzll(who);
-    } else {
-        v0 = wave_sum_to63(v0); v1 = wave_sum_to63(v1); v2 = wave_sum_to63(v2);
-        v3 = wave_sum_to63(v3); v4 = wave_sum_to63(v4); v5 = wave_sum_to63(v5);
-        src = kWave - 1;
-    }
-    const double u0 = (double)readlane_t(v0, src), u1 = (double)readlane_t(v1, src), u2 = (double)readlane_t(v2, src);
-    const double u3 = (double)readlane_t(v3, src), u4 = (double)readlane_t(v4, src), u5 = (double)readlane_t(v5, src);
-    const double mine = lane == 0 ? u0 : lane == 1 ? u1 : lane == 2 ? u2 : lane == 3 ? u3 : lane == 4 ? u4 : u5;
-    if (lane < 6) atomic_add_d(p + lane, mine);
+    const T t = wave_sum6<T>(lane, v0, v1, v2, v3, v4, v5);  // lane c < 6 holds the total of value c
+    if (lane < 6) atomic_add_d(p + lane, (double)t);
 }
 
 // Forward field and adjoint in one traversal (the upstream gradient Hbar does not depend on H).
@@ -451,7 +441,7 @@ __global__ __launch_bounds__(NW * 64) void k_adjoint_wg(
         const double d2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
         const bool acc = active && !inside && nd.s2 < theta2 * d2;
         const uint64_t accm = __ballot(acc);
-        T v0 = 0, v1 = 0, v2 = 0, v3 = 0, v4 = 0, v5 = 0;
+        T vs = 0;
         if (accm != 0ull) {
             T bx, by, bz;
             if (MIXED) {
@@ -472,15 +462,11 @@ __global__ __launch_bounds__(NW * 64) void k_adjoint_wg(
                 grx += gx; gry += gy; grz += gz;
                 hx += fx; hy += fy; hz += fz;
             }
-            v0 = wave_sum_to63(tx); v1 = wave_sum_to63(ty); v2 = wave_sum_to63(tz);
-            v3 = wave_sum_to63(-gx); v4 = wave_sum_to63(-gy); v5 = wave_sum_to63(-gz);
+            vs = wave_sum6<T>(lane, tx, ty, tz, -gx, -gy, -gz);
         }
         const uint64_t open = __ballot(active && !acc);
-        if (lane == kWave - 1) {
-            fpart[par][wv][0] = v0; fpart[par][wv][1] = v1; fpart[par][wv][2] = v2;
-            fpart[par][wv][3] = v3; fpart[par][wv][4] = v4; fpart[par][wv][5] = v5;
-            flags[par][wv] = (open != 0ull ? 1u : 0u) | (accm != 0ull ? 2u : 0u);
-        }
+        if (lane < 6) fpart[par][wv][lane] = vs;
+        if (lane == 0) flags[par][wv] = (open != 0ull ? 1u : 0u) | (accm != 0ull ? 2u : 0u);
         __syncthreads();
         uint32_t any = 0u;
 #pragma unroll
@@ -515,7 +501,7 @@ __global__ __launch_bounds__(NW * 64) void k_adjoint_wg(
                 const bool other = me && k != si;
                 const bool use = other && r2 > (T)0;
                 coincident |= other && !(r2 > (T)0);
-                T w0 = 0, w1 = 0, w2 = 0, w3 = 0, w4 = 0, w5 = 0;
+                T ws = 0;
                 if (__ballot(use) != 0ull) {
                     T qx, qy, qz, ux, uy, uz, fx, fy, fz;
                     adj_field<T>(x, y, z, ax, ay, az, (T)sk.mx, (T)sk.my, (T)sk.mz, qx, qy, qz, ux, uy, uz, fx, fy,
@@ -529,13 +515,9 @@ __global__ __launch_bounds__(NW * 64) void k_adjoint_wg(
                         grx += qx; gry += qy; grz += qz;
                         hx += use ? fx : (T)0; hy += use ? fy : (T)0; hz += use ? fz : (T)0;
                     }
-                    w0 = wave_sum_to63(-qx); w1 = wave_sum_to63(-qy); w2 = wave_sum_to63(-qz);
-                    w3 = wave_sum_to63(ux); w4 = wave_sum_to63(uy); w5 = wave_sum_to63(uz);
+                    ws = wave_sum6<T>(lane, -qx, -qy, -qz, ux, uy, uz);
                 }
-                if (lane == kWave - 1) {
-                    lpart[wv][j][0] = w0; lpart[wv][j][1] = w1; lpart[wv][j][2] = w2;
-                    lpart[wv][j][3] = w3; lpart[wv][j][4] = w4; lpart[wv][j][5] = w5;
-                }
+                if (lane < 6) lpart[wv][j][lane] = ws;
             }
             __syncthreads();
             for (int p = threadIdx.x; p < cn * 6; p += NW * 64) {

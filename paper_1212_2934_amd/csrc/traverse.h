@@ -215,6 +215,69 @@ __device__ inline double wave_sum(double v)
     return (a + b) + (c + d);
 }
 
+// Sum over the two lanes l and l ^ 16 (permlane16_swap) or l and l ^ 32 (permlane32_swap): the swap of
+// a register with itself hands every lane the value of its partner row in the second result.
+__device__ inline float swap16_sum(float v)
+{
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ inline float swap32_sum(float v)
+{
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ inline double swap16_sum(double v)
+{
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const auto lo = __builtin_amdgcn_permlane16_swap((uint32_t)b, (uint32_t)b, false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap((uint32_t)(b >> 32), (uint32_t)(b >> 32), false, false);
+    return __longlong_as_double((long long)(((uint64_t)hi[0] << 32) | lo[0])) +
+           __longlong_as_double((long long)(((uint64_t)hi[1] << 32) | lo[1]));
+}
+__device__ inline double swap32_sum(double v)
+{
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const auto lo = __builtin_amdgcn_permlane32_swap((uint32_t)b, (uint32_t)b, false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap((uint32_t)(b >> 32), (uint32_t)(b >> 32), false, false);
+    return __longlong_as_double((long long)(((uint64_t)hi[0] << 32) | lo[0])) +
+           __longlong_as_double((long long)(((uint64_t)hi[1] << 32) | lo[1]));
+}
+template <int CTRL>
+__device__ inline float dpp_t(float v) { return dpp_f<CTRL>(v); }
+template <int CTRL>
+__device__ inline double dpp_t(double v) { return dpp_d<CTRL>(v); }
+
+// Wave sums of six per-lane values by a transposed butterfly.  Inside each group of eight lanes three
+// exchange steps halve the number of values a lane carries (8 -> 4 -> 2 -> 1; slots 6 and 7 are zero):
+// at each step the two partners split the values between them and each adds the partner's copy of the
+// half it keeps, so lane l ends with value (l & 7) summed over its group.  A rotate by eight inside the
+// row and two row swaps then add the eight groups.  Every lane returns the wave total of value (l & 7)
+// (zero for 6 and 7); all 64 lanes must be active.
+template <typename T>
+__device__ inline T wave_sum6(int lane, T v0, T v1, T v2, T v3, T v4, T v5)
+{
+    const bool b2 = (lane & 4) != 0, b1 = (lane & 2) != 0, b0 = (lane & 1) != 0;
+    // partner 7 - i in the group (row_half_mirror); the lane with bit 2 keeps values 4..7
+    T k0 = b2 ? v4 : v0, k1 = b2 ? v5 : v1, k2 = b2 ? (T)0 : v2, k3 = b2 ? (T)0 : v3;
+    const T s0 = b2 ? v0 : v4, s1 = b2 ? v1 : v5, s2 = b2 ? v2 : (T)0, s3 = b2 ? v3 : (T)0;
+    k0 += dpp_t<0x141>(s0);
+    k1 += dpp_t<0x141>(s1);
+    k2 += dpp_t<0x141>(s2);
+    k3 += dpp_t<0x141>(s3);
+    // partner i ^ 2 (quad_perm [2,3,0,1]); bit 1 keeps the upper pair
+    T u0 = b1 ? k2 : k0, u1 = b1 ? k3 : k1;
+    const T t0 = b1 ? k0 : k2, t1 = b1 ? k1 : k3;
+    u0 += dpp_t<0x4e>(t0);
+    u1 += dpp_t<0x4e>(t1);
+    // partner i ^ 1 (quad_perm [1,0,3,2]); bit 0 keeps the upper one
+    T z = b0 ? u1 : u0;
+    z += dpp_t<0xb1>(b0 ? u0 : u1);
+    z += dpp_t<0x128>(z);  // row_ror 8: the two groups of the row
+    z = swap16_sum(z);     // rows 0+1, 2+3
+    return swap32_sum(z);  // all four rows
+}
+
 // Logical block index, arranged so that each of the 8 XCDs (which receive workgroups round-robin)
 // works on one contiguous range of Morton-ordered targets and keeps those nodes in its own L2.
 __device__ inline int xcd_block(int bid, int nb)
