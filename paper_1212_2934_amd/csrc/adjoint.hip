@@ -32,6 +32,96 @@ __device__ inline void scatter6(uint64_t who, int lane, double *p, T v0, T v1, T
 // Forward field and adjoint in one traversal (the upstream gradient Hbar does not depend on H).
 // Control flow is wave-uniform: when any lane accepts a cell (or uses a source), the whole wave
 // computes and the lanes that do not take part add zero.
+// One pair of the fused traversal for a target with upstream field gradient a: adds the gathered dL/dr
+// (g) and the field of b to the target's sums (FP32 partials since the last flush in MIXED mode, FP64
+// otherwise) and returns g and T(x) a for the scatter.  Lanes with `use` false add and return zeros.
+template <bool MIXED, typename T>
+__device__ inline void fused_pair(bool use, T x, T y, T z, T ax, T ay, T az, T bx, T by, T bz, T &gx, T &gy, T &gz,
+                                  T &tx, T &ty, T &tz, T &pgx, T &pgy, T &pgz, T &phx, T &phy, T &phz, double &grx,
+                                  double &gry, double &grz, double &hx, double &hy, double &hz)
+{
+    if constexpr (MIXED) {
+        adj_field<T>(use, x, y, z, ax, ay, az, bx, by, bz, gx, gy, gz, tx, ty, tz, phx, phy, phz);
+        pgx += gx; pgy += gy; pgz += gz;
+    } else {
+        adj_field<T>(use, x, y, z, ax, ay, az, bx, by, bz, gx, gy, gz, tx, ty, tz, hx, hy, hz);
+        grx += gx; gry += gy; grz += gz;
+    }
+}
+
+// Per-wave LDS of the fused traversal (dynamic shared memory, one record per wave of the block).
+template <typename T>
+struct AdjLds {
+    LdsTarget tgt[kWave];  // the wave's targets
+    T hb[kWave][4];        // their upstream field gradients
+    T acc[kWave][6];       // direct-sum g (0..2) and field (3..5) of the current leaf, by owner lane
+    T sbuf[16][6];         // member totals of the current chunk: -sum g (0..2), sum T(x) a (3..5)
+    int list[kWave];       // lanes that opened the current leaf
+};
+
+// Direct sums of one leaf (first, count) for the c listed lanes, in groups of G lanes (see the compacted
+// direct sums in traverse.h).  Lane b of group g pairs member b with listed target t0 + g: the group's
+// totals of g and of the field go to the target's LDS slot; the member's totals over all listed targets
+// are summed across the groups and added to its record with one atomic per component.
+template <int G, typename T, typename Src>
+__device__ inline void adj_leaf(AdjLds<T> &W, int lane, const Src *__restrict__ sr, double *__restrict__ g_rm,
+                                int first, int count, int c, bool &coincident)
+{
+    const int grp = lane / G, b = lane % G;
+    for (int c0 = 0; c0 < count; c0 += G) {
+        const int cn = min(G, count - c0);
+        const bool sok = b < cn;
+        const int k = first + c0 + (sok ? b : 0);
+        const Src sk = sr[k];
+        const T mx = (T)sk.mx, my = (T)sk.my, mz = (T)sk.mz;
+        T s0 = 0, s1 = 0, s2 = 0, s3 = 0, s4 = 0, s5 = 0;
+        for (int t0 = 0; t0 < c; t0 += kWave / G) {
+            const int a = t0 + grp;
+            const bool tok = a < c;
+            const int tl = W.list[tok ? a : 0];
+            const LdsTarget tg = W.tgt[tl];
+            const T ax = W.hb[tl][0], ay = W.hb[tl][1], az = W.hb[tl][2];
+            const T x = (T)(tg.rx - sk.x), y = (T)(tg.ry - sk.y), z = (T)(tg.rz - sk.z);
+            const T r2 = x * x + y * y + z * z;
+            const bool other = tok && sok && k != tg.si;
+            const bool use = other && r2 > (T)0;
+            coincident |= other && !(r2 > (T)0);
+            T qx, qy, qz, ux, uy, uz, hx = 0, hy = 0, hz = 0;
+            adj_field<T>(use, x, y, z, ax, ay, az, mx, my, mz, qx, qy, qz, ux, uy, uz, hx, hy, hz);
+            s0 -= qx; s1 -= qy; s2 -= qz;
+            s3 += ux; s4 += uy; s5 += uz;
+            T o0, o1;
+            group_sum6<G>(lane, qx, qy, qz, hx, hy, hz, o0, o1);
+            if constexpr (G == 4) {
+                const int j = lane & 3;  // holds slots 2j, 2j + 1
+                if (tok && j < 3) {
+                    lds_add(&W.acc[tl][2 * j], o0);
+                    lds_add(&W.acc[tl][2 * j + 1], o1);
+                }
+            } else {
+                if (tok && b < 6) lds_add(&W.acc[tl][b], o0);  // lane b < 6 holds slot b
+            }
+        }
+        // dL/dr_k -= sum g, dL/dm_k += sum T(x) a over the listed targets
+        s0 = stride_sum<G>(s0); s1 = stride_sum<G>(s1); s2 = stride_sum<G>(s2);
+        s3 = stride_sum<G>(s3); s4 = stride_sum<G>(s4); s5 = stride_sum<G>(s5);
+        if (lane < cn) {
+            W.sbuf[lane][0] = s0; W.sbuf[lane][1] = s1; W.sbuf[lane][2] = s2;
+            W.sbuf[lane][3] = s3; W.sbuf[lane][4] = s4; W.sbuf[lane][5] = s5;
+        }
+        wave_lds_sync();
+        for (int base = 0; base < 6 * cn; base += kWave) {
+            const int idx = base + lane;
+            if (idx < 6 * cn) {
+                const int m = idx / 6, comp = idx - 6 * m;
+                const T v = W.sbuf[m][comp];
+                if (v != (T)0) atomic_add_d(g_rm + 8 * (int64_t)(first + c0 + m) + comp, (double)v);
+            }
+        }
+        wave_lds_sync();
+    }
+}
+
 template <bool MIXED>
 __global__ __launch_bounds__(512) void k_adjoint(
     const NodeRec *__restrict__ nodes, const double *__restrict__ node_m64, const double *__restrict__ spos,
@@ -60,6 +150,11 @@ __global__ __launch_bounds__(512) void k_adjoint(
     double hx = 0.0, hy = 0.0, hz = 0.0;     // forward field of the target (FP64)
     T pgx = 0, pgy = 0, pgz = 0, phx = 0, phy = 0, phz = 0;  // partial sums since the last flush
     bool coincident = false;
+    AdjLds<T> &W = ((AdjLds<T> *)ffbh_dyn_lds)[threadIdx.x / kWave];
+    W.tgt[lane] = LdsTarget{rx, ry, rz, si, 0};
+    W.hb[lane][0] = ax; W.hb[lane][1] = ay; W.hb[lane][2] = az;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) W.acc[lane][j] = (T)0;
 
     LaneStack st{0, 0, 0, 0};
     st.push(lane, seg, 1, __ballot(valid));
@@ -90,18 +185,9 @@ __global__ __launch_bounds__(512) void k_adjoint(
                 const double *m = node_m64 + 4 * (int64_t)cur;
                 bx = (T)m[0]; by = (T)m[1]; bz = (T)m[2];
             }
-            T gx, gy, gz, tx, ty, tz, fx, fy, fz;
-            adj_field<T>((T)dx, (T)dy, (T)dz, ax, ay, az, bx, by, bz, gx, gy, gz, tx, ty, tz, fx, fy, fz);
-            gx = acc ? gx : (T)0; gy = acc ? gy : (T)0; gz = acc ? gz : (T)0;
-            tx = acc ? tx : (T)0; ty = acc ? ty : (T)0; tz = acc ? tz : (T)0;
-            fx = acc ? fx : (T)0; fy = acc ? fy : (T)0; fz = acc ? fz : (T)0;
-            if (MIXED) {
-                pgx += gx; pgy += gy; pgz += gz;
-                phx += fx; phy += fy; phz += fz;
-            } else {
-                grx += gx; gry += gy; grz += gz;
-                hx += fx; hy += fy; hz += fz;
-            }
+            T gx, gy, gz, tx, ty, tz;
+            fused_pair<MIXED, T>(acc, (T)dx, (T)dy, (T)dz, ax, ay, az, bx, by, bz, gx, gy, gz, tx, ty, tz, pgx, pgy,
+                                 pgz, phx, phy, phz, grx, gry, grz, hx, hy, hz);
             // A_C += sum T(x) Hbar over the accepting lanes, B_C -= sum g
             scatter6<T>(accm, lane, node_adj + 8 * (int64_t)cur, tx, ty, tz, -gx, -gy, -gz);
         }
@@ -115,35 +201,26 @@ __global__ __launch_bounds__(512) void k_adjoint(
             st.push(lane, nd.child, nd.nchild, open);
             continue;
         }
-        const bool me = (open >> lane) & 1ull;
-        const Src *q = sr + nd.first;
-        for (int k = nd.first; k < nd.first + nd.count; ++k, ++q) {
-            const Src sk = *q;
-            const T x = (T)(rx - sk.x), y = (T)(ry - sk.y), z = (T)(rz - sk.z);
-            const T r2 = x * x + y * y + z * z;
-            const bool other = me && k != si;
-            const bool use = other && r2 > (T)0;
-            coincident |= other && !(r2 > (T)0);
-            const uint64_t usem = __ballot(use);
-            if (usem == 0ull) continue;
-            T qx, qy, qz, ux, uy, uz, fx, fy, fz;
-            adj_field<T>(x, y, z, ax, ay, az, (T)sk.mx, (T)sk.my, (T)sk.mz, qx, qy, qz, ux, uy, uz, fx, fy, fz);
-            qx = use ? qx : (T)0; qy = use ? qy : (T)0; qz = use ? qz : (T)0;
-            ux = use ? ux : (T)0; uy = use ? uy : (T)0; uz = use ? uz : (T)0;
-            if (MIXED) {
-                pgx += qx; pgy += qy; pgz += qz;
-                phx += use ? fx : (T)0; phy += use ? fy : (T)0; phz += use ? fz : (T)0;
-            } else {
-                grx += qx; gry += qy; grz += qz;
-                hx += use ? fx : (T)0; hy += use ? fy : (T)0; hz += use ? fz : (T)0;
-            }
-            // dL/dr_k -= sum g, dL/dm_k += sum T(x) Hbar over the lanes
-            scatter6<T>(usem, lane, g_rm + 8 * (int64_t)k, -qx, -qy, -qz, ux, uy, uz);
+        // leaf: direct sums over its members, packed over the lanes that opened it
+        if (open & (1ull << lane)) W.list[lanes_below(open)] = lane;
+        const int c = __builtin_popcountll(open);
+        wave_lds_sync();
+        if (nd.count <= 4) adj_leaf<4>(W, lane, sr, g_rm, nd.first, nd.count, c, coincident);
+        else if (nd.count <= 8) adj_leaf<8>(W, lane, sr, g_rm, nd.first, nd.count, c, coincident);
+        else adj_leaf<16>(W, lane, sr, g_rm, nd.first, nd.count, c, coincident);
+        T d[6];
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            d[j] = W.acc[lane][j];
+            W.acc[lane][j] = (T)0;
         }
         if (MIXED) {
-            grx += (double)pgx; gry += (double)pgy; grz += (double)pgz;
-            hx += (double)phx; hy += (double)phy; hz += (double)phz;
+            grx += (double)(pgx + d[0]); gry += (double)(pgy + d[1]); grz += (double)(pgz + d[2]);
+            hx += (double)(phx + d[3]); hy += (double)(phy + d[4]); hz += (double)(phz + d[5]);
             pgx = pgy = pgz = phx = phy = phz = (T)0;
+        } else {
+            grx += (double)d[0]; gry += (double)d[1]; grz += (double)d[2];
+            hx += (double)d[3]; hy += (double)d[4]; hz += (double)d[5];
         }
     }
     if (MIXED) {
@@ -199,18 +276,11 @@ struct Tgt {
             pgx = pgy = pgz = phx = phy = phz = (T)0;
         }
     }
-    // accumulate the pair results selected by `use`; returns the scatter values through the refs
-    __device__ inline void add(bool use, T qx, T qy, T qz, T fx, T fy, T fz)
+    // one pair against source (or cell) moment b at offset x: accumulates, returns g and T(x) a
+    __device__ inline void pair(bool use, T x, T y, T z, T bx, T by, T bz, T &qx, T &qy, T &qz, T &ux, T &uy, T &uz)
     {
-        qx = use ? qx : (T)0; qy = use ? qy : (T)0; qz = use ? qz : (T)0;
-        fx = use ? fx : (T)0; fy = use ? fy : (T)0; fz = use ? fz : (T)0;
-        if (MIXED) {
-            pgx += qx; pgy += qy; pgz += qz;
-            phx += fx; phy += fy; phz += fz;
-        } else {
-            gx += qx; gy += qy; gz += qz;
-            hx += fx; hy += fy; hz += fz;
-        }
+        fused_pair<MIXED, T>(use, x, y, z, ax, ay, az, bx, by, bz, qx, qy, qz, ux, uy, uz, pgx, pgy, pgz, phx, phy,
+                             phz, gx, gy, gz, hx, hy, hz);
     }
 };
 
@@ -310,20 +380,16 @@ __global__ __launch_bounds__(256) void k_adjoint2(
             }
             T s0 = 0, s1 = 0, s2v = 0, s3 = 0, s4 = 0, s5 = 0;  // this lane's scatter values, both targets
             if (acca) {
-                T gx, gy, gz, tx, ty, tz, fx, fy, fz;
-                adj_field<T>((T)dxa, (T)dya, (T)dza, ta.ax, ta.ay, ta.az, bx, by, bz, gx, gy, gz, tx, ty, tz, fx, fy,
-                             fz);
-                ta.add(acc_a, gx, gy, gz, fx, fy, fz);
-                s0 += acc_a ? tx : (T)0; s1 += acc_a ? ty : (T)0; s2v += acc_a ? tz : (T)0;
-                s3 -= acc_a ? gx : (T)0; s4 -= acc_a ? gy : (T)0; s5 -= acc_a ? gz : (T)0;
+                T gx, gy, gz, tx, ty, tz;
+                ta.pair(acc_a, (T)dxa, (T)dya, (T)dza, bx, by, bz, gx, gy, gz, tx, ty, tz);
+                s0 += tx; s1 += ty; s2v += tz;
+                s3 -= gx; s4 -= gy; s5 -= gz;
             }
             if (accb) {
-                T gx, gy, gz, tx, ty, tz, fx, fy, fz;
-                adj_field<T>((T)dxb, (T)dyb, (T)dzb, tb.ax, tb.ay, tb.az, bx, by, bz, gx, gy, gz, tx, ty, tz, fx, fy,
-                             fz);
-                tb.add(acc_b, gx, gy, gz, fx, fy, fz);
-                s0 += acc_b ? tx : (T)0; s1 += acc_b ? ty : (T)0; s2v += acc_b ? tz : (T)0;
-                s3 -= acc_b ? gx : (T)0; s4 -= acc_b ? gy : (T)0; s5 -= acc_b ? gz : (T)0;
+                T gx, gy, gz, tx, ty, tz;
+                tb.pair(acc_b, (T)dxb, (T)dyb, (T)dzb, bx, by, bz, gx, gy, gz, tx, ty, tz);
+                s0 += tx; s1 += ty; s2v += tz;
+                s3 -= gx; s4 -= gy; s5 -= gz;
             }
             // A_C += T(x) Hbar, B_C -= g, over the accepting targets of the wave
             scatter6<T>(acca | accb, lane, node_adj + 8 * (int64_t)cur, s0, s1, s2v, s3, s4, s5);
@@ -352,20 +418,16 @@ __global__ __launch_bounds__(256) void k_adjoint2(
             if ((usa | usb) == 0ull) continue;
             T s0 = 0, s1 = 0, s2v = 0, s3 = 0, s4 = 0, s5 = 0;
             if (usa) {
-                T qx, qy, qz, ux, uy, uz, fx, fy, fz;
-                adj_field<T>(xa, ya, za, ta.ax, ta.ay, ta.az, (T)sk.mx, (T)sk.my, (T)sk.mz, qx, qy, qz, ux, uy, uz, fx,
-                             fy, fz);
-                ta.add(ua, qx, qy, qz, fx, fy, fz);
-                s0 -= ua ? qx : (T)0; s1 -= ua ? qy : (T)0; s2v -= ua ? qz : (T)0;
-                s3 += ua ? ux : (T)0; s4 += ua ? uy : (T)0; s5 += ua ? uz : (T)0;
+                T qx, qy, qz, ux, uy, uz;
+                ta.pair(ua, xa, ya, za, (T)sk.mx, (T)sk.my, (T)sk.mz, qx, qy, qz, ux, uy, uz);
+                s0 -= qx; s1 -= qy; s2v -= qz;
+                s3 += ux; s4 += uy; s5 += uz;
             }
             if (usb) {
-                T qx, qy, qz, ux, uy, uz, fx, fy, fz;
-                adj_field<T>(xb, yb, zb, tb.ax, tb.ay, tb.az, (T)sk.mx, (T)sk.my, (T)sk.mz, qx, qy, qz, ux, uy, uz, fx,
-                             fy, fz);
-                tb.add(ub, qx, qy, qz, fx, fy, fz);
-                s0 -= ub ? qx : (T)0; s1 -= ub ? qy : (T)0; s2v -= ub ? qz : (T)0;
-                s3 += ub ? ux : (T)0; s4 += ub ? uy : (T)0; s5 += ub ? uz : (T)0;
+                T qx, qy, qz, ux, uy, uz;
+                tb.pair(ub, xb, yb, zb, (T)sk.mx, (T)sk.my, (T)sk.mz, qx, qy, qz, ux, uy, uz);
+                s0 -= qx; s1 -= qy; s2v -= qz;
+                s3 += ux; s4 += uy; s5 += uz;
             }
             // dL/dr_k -= sum g, dL/dm_k += sum T(x) Hbar over the wave's targets
             scatter6<T>(usa | usb, lane, g_rm + 8 * (int64_t)k, s0, s1, s2v, s3, s4, s5);
@@ -450,18 +512,9 @@ __global__ __launch_bounds__(NW * 64) void k_adjoint_wg(
                 const double *m = node_m64 + 4 * (int64_t)cur;
                 bx = (T)m[0]; by = (T)m[1]; bz = (T)m[2];
             }
-            T gx, gy, gz, tx, ty, tz, fx, fy, fz;
-            adj_field<T>((T)dx, (T)dy, (T)dz, ax, ay, az, bx, by, bz, gx, gy, gz, tx, ty, tz, fx, fy, fz);
-            gx = acc ? gx : (T)0; gy = acc ? gy : (T)0; gz = acc ? gz : (T)0;
-            tx = acc ? tx : (T)0; ty = acc ? ty : (T)0; tz = acc ? tz : (T)0;
-            fx = acc ? fx : (T)0; fy = acc ? fy : (T)0; fz = acc ? fz : (T)0;
-            if (MIXED) {
-                pgx += gx; pgy += gy; pgz += gz;
-                phx += fx; phy += fy; phz += fz;
-            } else {
-                grx += gx; gry += gy; grz += gz;
-                hx += fx; hy += fy; hz += fz;
-            }
+            T gx, gy, gz, tx, ty, tz;
+            fused_pair<MIXED, T>(acc, (T)dx, (T)dy, (T)dz, ax, ay, az, bx, by, bz, gx, gy, gz, tx, ty, tz, pgx, pgy,
+                                 pgz, phx, phy, phz, grx, gry, grz, hx, hy, hz);
             vs = wave_sum6<T>(lane, tx, ty, tz, -gx, -gy, -gz);
         }
         const uint64_t open = __ballot(active && !acc);
@@ -503,18 +556,9 @@ __global__ __launch_bounds__(NW * 64) void k_adjoint_wg(
                 coincident |= other && !(r2 > (T)0);
                 T ws = 0;
                 if (__ballot(use) != 0ull) {
-                    T qx, qy, qz, ux, uy, uz, fx, fy, fz;
-                    adj_field<T>(x, y, z, ax, ay, az, (T)sk.mx, (T)sk.my, (T)sk.mz, qx, qy, qz, ux, uy, uz, fx, fy,
-                                 fz);
-                    qx = use ? qx : (T)0; qy = use ? qy : (T)0; qz = use ? qz : (T)0;
-                    ux = use ? ux : (T)0; uy = use ? uy : (T)0; uz = use ? uz : (T)0;
-                    if (MIXED) {
-                        pgx += qx; pgy += qy; pgz += qz;
-                        phx += use ? fx : (T)0; phy += use ? fy : (T)0; phz += use ? fz : (T)0;
-                    } else {
-                        grx += qx; gry += qy; grz += qz;
-                        hx += use ? fx : (T)0; hy += use ? fy : (T)0; hz += use ? fz : (T)0;
-                    }
+                    T qx, qy, qz, ux, uy, uz;
+                    fused_pair<MIXED, T>(use, x, y, z, ax, ay, az, (T)sk.mx, (T)sk.my, (T)sk.mz, qx, qy, qz, ux, uy,
+                                         uz, pgx, pgy, pgz, phx, phy, phz, grx, gry, grz, hx, hy, hz);
                     ws = wave_sum6<T>(lane, -qx, -qy, -qz, ux, uy, uz);
                 }
                 if (lane < 6) lpart[wv][j][lane] = ws;
@@ -690,12 +734,12 @@ hipError_t launch_backward(Handle &h, const double *d_mom, const double *d_hext,
                                w.smom, w.src64, w.hbar, w.perm, d_hext, w.g_gather, w.g_rm, w.node_adj, w.Hs, d_H,
                                w.e_part, w.status, L.n, L.ntot, wps2, nw2, theta2, (int)L.max_nodes);
     } else if (mixed)
-        hipLaunchKernelGGL(k_adjoint<true>, dim3(blocks), dim3(wpb * kWave), 0, s, w.nodes, w.node_m64, w.spos,
+        hipLaunchKernelGGL(k_adjoint<true>, dim3(blocks), dim3(wpb * kWave), wpb * sizeof(AdjLds<float>), s, w.nodes, w.node_m64, w.spos,
                            w.smom, w.src32, w.hbar, w.perm, d_hext, w.g_gather, w.g_rm, w.node_adj, w.Hs, d_H,
                            w.e_part, w.status, L.n, L.ntot, waves_per_seg, (int)L.num_waves, theta2,
                            (int)L.max_nodes);
     else
-        hipLaunchKernelGGL(k_adjoint<false>, dim3(blocks), dim3(wpb * kWave), 0, s, w.nodes, w.node_m64, w.spos,
+        hipLaunchKernelGGL(k_adjoint<false>, dim3(blocks), dim3(wpb * kWave), wpb * sizeof(AdjLds<double>), s, w.nodes, w.node_m64, w.spos,
                            w.smom, w.src64, w.hbar, w.perm, d_hext, w.g_gather, w.g_rm, w.node_adj, w.Hs, d_H,
                            w.e_part, w.status, L.n, L.ntot, waves_per_seg, (int)L.num_waves, theta2,
                            (int)L.max_nodes);

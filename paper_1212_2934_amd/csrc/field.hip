@@ -13,6 +13,55 @@
 
 namespace ffbh {
 
+// Per-wave LDS of the forward traversal (dynamic shared memory, one record per wave of the block).
+template <typename T>
+struct FieldLds {
+    LdsTarget tgt[kWave];  // the wave's targets
+    T acc[kWave][4];       // direct-sum field of the current leaf, by owner lane
+    int cnt[kWave];        // direct interactions of the current leaf (counting launches)
+    int list[kWave];       // lanes that opened the current leaf
+};
+
+// Direct sums of one leaf (first, count) for the c listed lanes, in groups of G lanes (see the compacted
+// direct sums in traverse.h): lane b of group g pairs member b with listed target t0 + g; the group's
+// field total is added to the target's LDS slot.  Pairs are skipped for the target itself and flagged when
+// coincident, as in the definition of the direct sum.
+template <bool COUNT, int G, typename T, typename Src>
+__device__ inline void field_leaf(FieldLds<T> &W, int lane, const Src *__restrict__ sr, int first, int count, int c,
+                                  bool &coincident)
+{
+    const int grp = lane / G, b = lane % G;
+    const int slot = group3_slot<G>(lane);
+    const bool wr = group3_writer<G>(lane) && slot < 3;
+    for (int c0 = 0; c0 < count; c0 += G) {
+        const int cn = min(G, count - c0);
+        const bool sok = b < cn;
+        const int k = first + c0 + (sok ? b : 0);
+        const Src sk = sr[k];
+        const T mx = (T)sk.mx, my = (T)sk.my, mz = (T)sk.mz;
+        for (int t0 = 0; t0 < c; t0 += kWave / G) {
+            const int a = t0 + grp;
+            const bool tok = a < c;
+            const int tl = W.list[tok ? a : 0];
+            const LdsTarget tg = W.tgt[tl];
+            const T x = (T)(tg.rx - sk.x), y = (T)(tg.ry - sk.y), z = (T)(tg.rz - sk.z);
+            const T r2 = x * x + y * y + z * z;
+            const bool other = tok && sok && k != tg.si;
+            const bool use = other && r2 > (T)0;
+            coincident |= other && !(r2 > (T)0);
+            T hx = 0, hy = 0, hz = 0;
+            dip_acc<T>(use, x, y, z, mx, my, mz, hx, hy, hz);
+            const T v = group_sum3<G>(lane, hx, hy, hz);
+            if (tok && wr) lds_add(&W.acc[tl][slot], v);
+            if constexpr (COUNT) {
+                const uint64_t um = __ballot(use) >> (grp * G);
+                const int nu = __builtin_popcountll(um & ((1ull << G) - 1ull));
+                if (tok && b == 0) lds_add(&W.cnt[tl], nu);
+            }
+        }
+    }
+}
+
 template <bool MIXED, bool COUNT>
 __global__ __launch_bounds__(512) void k_field(
     const NodeRec *__restrict__ nodes, const double *__restrict__ node_m64, const double *__restrict__ spos,
@@ -39,6 +88,10 @@ __global__ __launch_bounds__(512) void k_field(
     T px = 0, py = 0, pz = 0;             // partial sums since the last flush (MIXED only)
     int nfar = 0, nnear = 0;
     bool coincident = false;
+    FieldLds<T> &W = ((FieldLds<T> *)ffbh_dyn_lds)[threadIdx.x / kWave];
+    W.tgt[lane] = LdsTarget{rx, ry, rz, si, 0};
+    W.acc[lane][0] = W.acc[lane][1] = W.acc[lane][2] = (T)0;
+    W.cnt[lane] = 0;
 
     LaneStack st{0, 0, 0, 0};
     st.push(lane, seg, 1, __ballot(valid));
@@ -63,18 +116,11 @@ __global__ __launch_bounds__(512) void k_field(
         const bool acc = active && !inside && nd.s2 < theta2 * d2;
         if (__ballot(acc) != 0ull) {
             // the whole wave computes; lanes that did not accept add zero
-            T fx = 0, fy = 0, fz = 0;
             if (MIXED) {
-                dip_acc<T>((T)dx, (T)dy, (T)dz, (T)nd.mx, (T)nd.my, (T)nd.mz, fx, fy, fz);
-                px += acc ? fx : (T)0;
-                py += acc ? fy : (T)0;
-                pz += acc ? fz : (T)0;
+                dip_acc<T>(acc, (T)dx, (T)dy, (T)dz, (T)nd.mx, (T)nd.my, (T)nd.mz, px, py, pz);
             } else {
                 const double *m = node_m64 + 4 * (int64_t)cur;
-                dip_acc<T>((T)dx, (T)dy, (T)dz, (T)m[0], (T)m[1], (T)m[2], fx, fy, fz);
-                hx += acc ? (double)fx : 0.0;
-                hy += acc ? (double)fy : 0.0;
-                hz += acc ? (double)fz : 0.0;
+                dip_acc<double>(acc, dx, dy, dz, m[0], m[1], m[2], hx, hy, hz);
             }
             if (COUNT) nfar += acc ? 1 : 0;
         }
@@ -88,32 +134,25 @@ __global__ __launch_bounds__(512) void k_field(
             st.push(lane, nd.child, nd.nchild, open);
             continue;
         }
-        // leaf: members other than the target itself, summed directly by the lanes that opened it
-        const bool me = (open >> lane) & 1ull;
-        const Src *q = sr + nd.first;
-        for (int k = 0; k < nd.count; ++k, ++q) {
-            const Src sk = *q;
-            const T x = (T)(rx - sk.x), y = (T)(ry - sk.y), z = (T)(rz - sk.z);
-            const T r2 = x * x + y * y + z * z;
-            const bool other = me && (nd.first + k != si);
-            const bool use = other && r2 > (T)0;
-            coincident |= other && !(r2 > (T)0);
-            T fx = 0, fy = 0, fz = 0;
-            dip_acc<T>(x, y, z, (T)sk.mx, (T)sk.my, (T)sk.mz, fx, fy, fz);
-            if (MIXED) {
-                px += use ? fx : (T)0;
-                py += use ? fy : (T)0;
-                pz += use ? fz : (T)0;
-            } else {
-                hx += use ? (double)fx : 0.0;
-                hy += use ? (double)fy : 0.0;
-                hz += use ? (double)fz : 0.0;
-            }
-            if (COUNT) nnear += use ? 1 : 0;
+        // leaf: direct sums over its members, packed over the lanes that opened it
+        if (open & (1ull << lane)) W.list[lanes_below(open)] = lane;
+        const int c = __builtin_popcountll(open);
+        wave_lds_sync();
+        if (nd.count <= 4) field_leaf<COUNT, 4>(W, lane, sr, nd.first, nd.count, c, coincident);
+        else if (nd.count <= 8) field_leaf<COUNT, 8>(W, lane, sr, nd.first, nd.count, c, coincident);
+        else field_leaf<COUNT, 16>(W, lane, sr, nd.first, nd.count, c, coincident);
+        wave_lds_sync();
+        const T a0 = W.acc[lane][0], a1 = W.acc[lane][1], a2 = W.acc[lane][2];
+        W.acc[lane][0] = W.acc[lane][1] = W.acc[lane][2] = (T)0;
+        if (COUNT) {
+            nnear += W.cnt[lane];
+            W.cnt[lane] = 0;
         }
         if (MIXED) {
-            hx += (double)px; hy += (double)py; hz += (double)pz;
+            hx += (double)(px + a0); hy += (double)(py + a1); hz += (double)(pz + a2);
             px = py = pz = (T)0;
+        } else {
+            hx += (double)a0; hy += (double)a1; hz += (double)a2;
         }
     }
     if (MIXED) {
@@ -178,7 +217,9 @@ static void launch_k_field(Handle &h, const double *d_hext, double *d_H, hipStre
     const int waves_per_seg = (int)((L.n + kWave - 1) / kWave);
     const double theta2 = h.p.theta * h.p.theta;
     const void *src = MIXED ? (const void *)w.src32 : (const void *)w.src64;
-    hipLaunchKernelGGL((k_field<MIXED, COUNT>), dim3(blocks), dim3(wpb * kWave), 0, s, w.nodes,
+    using T = typename std::conditional<MIXED, float, double>::type;
+    const size_t lds = (size_t)wpb * sizeof(FieldLds<T>);
+    hipLaunchKernelGGL((k_field<MIXED, COUNT>), dim3(blocks), dim3(wpb * kWave), lds, s, w.nodes,
                        w.node_m64, w.spos, w.smom, src, w.perm, d_hext, d_H, w.Hs, w.e_part,
                        h.cnt_far, h.cnt_near, w.status, L.n, L.ntot, waves_per_seg, (int)L.num_waves, theta2, (int)L.max_nodes);
 }

@@ -120,17 +120,19 @@ __global__ __launch_bounds__(256) void k_wca(const NodeRec *__restrict__ nodes, 
             if (lane == 0) set_flag(status, BH_FLAG_TREE);
             break;
         }
+        // the record and the member box are read together (cur is in range)
         const NodeRec nd = nodes[cur];
+        const double *bx = node_box + 8 * (int64_t)cur;
+        const double lox = bx[0], loy = bx[1], loz = bx[2], hix = bx[4], hiy = bx[5], hiz = bx[6];
         if (nd.first < 0 || nd.count < 1 || (int64_t)nd.first + nd.count > ntot) {
             if (lane == 0) set_flag(status, BH_FLAG_TREE);
             break;
         }
-        const double *bx = node_box + 8 * (int64_t)cur;
         const bool active = (mask >> lane) & 1ull;
         // squared distance from the target to the members' bounding box
-        const double ex = fmax(fmax(bx[0] - rx, rx - bx[4]), 0.0);
-        const double ey = fmax(fmax(bx[1] - ry, ry - bx[5]), 0.0);
-        const double ez = fmax(fmax(bx[2] - rz, rz - bx[6]), 0.0);
+        const double ex = fmax(fmax(lox - rx, rx - hix), 0.0);
+        const double ey = fmax(fmax(loy - ry, ry - hiy), 0.0);
+        const double ez = fmax(fmax(loz - rz, rz - hiz), 0.0);
         const bool hit = active && (ex * ex + ey * ey + ez * ez < rc2);
         const uint64_t open = __ballot(hit);
         if (open == 0ull) continue;
@@ -142,10 +144,20 @@ __global__ __launch_bounds__(256) void k_wca(const NodeRec *__restrict__ nodes, 
             st.push(lane, nd.child, nd.nchild, open);
             continue;
         }
+        // leaf: members in chunks of 64, one per lane (one vector load per coordinate), then broadcast to
+        // the wave one at a time; the pair force is evaluated only when some lane is within the cut-off
         const bool me = (open >> lane) & 1ull;
-        for (int k = nd.first; k < nd.first + nd.count; ++k) {
-            const double sx = spos[k], sy = spos[ntot + k], sz = spos[2 * ntot + k];
-            if (me && k != si) wca_pair(rx - sx, ry - sy, rz - sz, s2, eps, rc2, fx, fy, fz);
+        for (int c0 = 0; c0 < nd.count; c0 += kWave) {
+            const int cn = min(kWave, nd.count - c0);
+            const int kl = nd.first + c0 + (lane < cn ? lane : 0);
+            const double qx = spos[kl], qy = spos[ntot + kl], qz = spos[2 * ntot + kl];
+            for (int j = 0; j < cn; ++j) {
+                const double x = rx - readlane_d(qx, j), y = ry - readlane_d(qy, j), z = rz - readlane_d(qz, j);
+                const double r2 = x * x + y * y + z * z;
+                const bool near = me && nd.first + c0 + j != si && r2 < rc2 && r2 > 0.0;
+                if (__ballot(near) == 0ull) continue;
+                if (near) wca_pair(x, y, z, s2, eps, rc2, fx, fy, fz);
+            }
         }
     }
     if (!valid) return;

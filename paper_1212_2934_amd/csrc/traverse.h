@@ -18,48 +18,6 @@ __device__ inline double rsqrt64(double a)
     return y;
 }
 
-// Field of dipole m at offset x (target minus source), Eq. (H_dip) rearranged as
-// h = (3 (m.x) x / |x|^2 - m) / |x|^3, accumulated into h.
-template <typename T>
-__device__ inline void dip_acc(T x, T y, T z, T mx, T my, T mz, T &hx, T &hy, T &hz);
-
-template <>
-__device__ inline void dip_acc<double>(double x, double y, double z, double mx, double my, double mz,
-                                       double &hx, double &hy, double &hz)
-{
-    const double r2 = __builtin_fma(z, z, __builtin_fma(y, y, x * x));
-    const double ri = rsqrt64(r2);
-    const double ri2 = ri * ri;
-    const double ri3 = ri2 * ri;
-    const double md = __builtin_fma(mz, z, __builtin_fma(my, y, mx * x));
-    const double t = 3.0 * md * ri2;
-    hx = __builtin_fma(__builtin_fma(t, x, -mx), ri3, hx);
-    hy = __builtin_fma(__builtin_fma(t, y, -my), ri3, hy);
-    hz = __builtin_fma(__builtin_fma(t, z, -mz), ri3, hz);
-}
-
-template <>
-__device__ inline void dip_acc<float>(float x, float y, float z, float mx, float my, float mz, float &hx,
-                                      float &hy, float &hz)
-{
-    const float r2 = __builtin_fmaf(z, z, __builtin_fmaf(y, y, x * x));
-    const float ri = __builtin_amdgcn_rsqf(r2);
-    const float ri2 = ri * ri;
-    const float ri3 = ri2 * ri;
-    const float md = __builtin_fmaf(mz, z, __builtin_fmaf(my, y, mx * x));
-    const float t = 3.0f * md * ri2;
-    hx = __builtin_fmaf(__builtin_fmaf(t, x, -mx), ri3, hx);
-    hy = __builtin_fmaf(__builtin_fmaf(t, y, -my), ri3, hy);
-    hz = __builtin_fmaf(__builtin_fmaf(t, z, -mz), ri3, hz);
-}
-
-// Adjoint pair: with a = upstream field gradient of the target, b = source moment, x = offset,
-//   g  = 3 [ (a.b) x + (b.x) a + (a.x) b ] / |x|^5 - 15 (a.x)(b.x) x / |x|^7   (f_dip summand, Sec. 2)
-//   ta = T(x) a = (3 (a.x) x / |x|^2 - a) / |x|^3                                (T symmetric)
-template <typename T>
-__device__ inline void adj_pair(T x, T y, T z, T ax, T ay, T az, T bx, T by, T bz, T &gx, T &gy, T &gz,
-                                T &tx, T &ty, T &tz);
-
 template <typename T>
 __device__ inline T fmaT(T a, T b, T c);
 template <>
@@ -74,39 +32,37 @@ __device__ inline double rsqT<double>(double a) { return rsqrt64(a); }
 template <>
 __device__ inline float rsqT<float>(float a) { return __builtin_amdgcn_rsqf(a); }
 
+// Field of dipole m at offset x (target minus source), Eq. (H_dip) rearranged as
+// h += (3 (m.x) x / |x|^2 - m) / |x|^3 when `use`; otherwise the inverse distance is replaced by zero
+// and h receives exactly zero, so lanes of a wave that do not take part need no select on the result.
 template <typename T>
-__device__ inline void adj_pair(T x, T y, T z, T ax, T ay, T az, T bx, T by, T bz, T &gx, T &gy, T &gz,
-                                T &tx, T &ty, T &tz)
+__device__ inline void dip_acc(bool use, T x, T y, T z, T mx, T my, T mz, T &hx, T &hy, T &hz)
 {
     const T r2 = fmaT<T>(z, z, fmaT<T>(y, y, x * x));
-    const T ri = rsqT<T>(r2);
+    const T ri = use ? rsqT<T>(r2) : (T)0;
     const T ri2 = ri * ri;
     const T ri3 = ri2 * ri;
-    const T ri5 = ri3 * ri2;
-    const T adx = fmaT<T>(az, z, fmaT<T>(ay, y, ax * x));
-    const T bdx = fmaT<T>(bz, z, fmaT<T>(by, y, bx * x));
-    const T ab = fmaT<T>(az, bz, fmaT<T>(ay, by, ax * bx));
-    // g = 3 ri5 [ (ab - 5 adx bdx ri2) x + bdx a + adx b ]
-    const T c0 = fmaT<T>((T)-5 * adx * bdx, ri2, ab);
-    const T s = (T)3 * ri5;
-    gx = s * fmaT<T>(c0, x, fmaT<T>(bdx, ax, adx * bx));
-    gy = s * fmaT<T>(c0, y, fmaT<T>(bdx, ay, adx * by));
-    gz = s * fmaT<T>(c0, z, fmaT<T>(bdx, az, adx * bz));
-    // T(x) a
-    const T t = (T)3 * adx * ri2;
-    tx = fmaT<T>(t, x, -ax) * ri3;
-    ty = fmaT<T>(t, y, -ay) * ri3;
-    tz = fmaT<T>(t, z, -az) * ri3;
+    const T md = fmaT<T>(mz, z, fmaT<T>(my, y, mx * x));
+    const T t = (T)3 * md * ri2;
+    hx = fmaT<T>(fmaT<T>(t, x, -mx), ri3, hx);
+    hy = fmaT<T>(fmaT<T>(t, y, -my), ri3, hy);
+    hz = fmaT<T>(fmaT<T>(t, z, -mz), ri3, hz);
 }
 
-// Adjoint pair plus the forward field of b: g and T(x) a as in adj_pair, and hb = T(x) b (the field of
-// dipole b at offset x, Eq. H_dip), sharing the distance powers and dot products.
+// Adjoint pair plus the forward field.  With a = upstream field gradient of the target, b = source
+// moment, x = offset (target minus source):
+//   g  = 3 [ (a.b) x + (b.x) a + (a.x) b ] / |x|^5 - 15 (a.x)(b.x) x / |x|^7   (f_dip summand, Sec. 2)
+//      = 3 |x|^-5 [ (a.b - 5 (a.x)(b.x) / |x|^2) x + (b.x) a + (a.x) b ]
+//   t  = T(x) a = (3 (a.x) x / |x|^2 - a) / |x|^3                                (T symmetric)
+//   h += T(x) b, the field of dipole b at x (Eq. H_dip),
+// sharing the distance powers and dot products.  When `use` is false the inverse distance is zero and
+// g, t and the increment of h are exactly zero.
 template <typename T>
-__device__ inline void adj_field(T x, T y, T z, T ax, T ay, T az, T bx, T by, T bz, T &gx, T &gy, T &gz, T &tx,
-                                 T &ty, T &tz, T &hx, T &hy, T &hz)
+__device__ inline void adj_field(bool use, T x, T y, T z, T ax, T ay, T az, T bx, T by, T bz, T &gx, T &gy,
+                                 T &gz, T &tx, T &ty, T &tz, T &hx, T &hy, T &hz)
 {
     const T r2 = fmaT<T>(z, z, fmaT<T>(y, y, x * x));
-    const T ri = rsqT<T>(r2);
+    const T ri = use ? rsqT<T>(r2) : (T)0;
     const T ri2 = ri * ri;
     const T ri3 = ri2 * ri;
     const T ri5 = ri3 * ri2;
@@ -123,9 +79,9 @@ __device__ inline void adj_field(T x, T y, T z, T ax, T ay, T az, T bx, T by, T 
     ty = fmaT<T>(ta, y, -ay) * ri3;
     tz = fmaT<T>(ta, z, -az) * ri3;
     const T tb = (T)3 * bdx * ri2;
-    hx = fmaT<T>(tb, x, -bx) * ri3;
-    hy = fmaT<T>(tb, y, -by) * ri3;
-    hz = fmaT<T>(tb, z, -bz) * ri3;
+    hx = fmaT<T>(fmaT<T>(tb, x, -bx), ri3, hx);
+    hy = fmaT<T>(fmaT<T>(tb, y, -by), ri3, hy);
+    hz = fmaT<T>(fmaT<T>(tb, z, -bz), ri3, hz);
 }
 
 // ---- wave64 reductions (DPP) ---------------------------------------------------------------------
@@ -277,6 +233,114 @@ __device__ inline T wave_sum6(int lane, T v0, T v1, T v2, T v3, T v4, T v5)
     z = swap16_sum(z);     // rows 0+1, 2+3
     return swap32_sum(z);  // all four rows
 }
+
+// ---- compacted direct sums (leaf cells) -----------------------------------------------------------
+//
+// At a leaf, only the lanes that opened it (typically about a sixth of the wave) have pairs to sum.  The
+// opening lanes are listed in LDS and the pairs are packed densely: the wave is cut into groups of G lanes
+// (G = 4, 8 or 16, the smallest that holds the leaf's members, larger leaves in chunks of 16), lane b of
+// group g takes member b against listed target t0 + g, so one pass covers 64 / G targets.  Per-target sums
+// are group reductions added to the target's LDS slot; the owner lane collects them after the leaf.
+
+// One exchange step of a transposed reduction: the two lanes paired by DPP control CTRL each keep one of
+// two values (the lane with `hi` keeps u, its partner l) and add the partner's copy of it.
+template <int CTRL, typename T>
+__device__ inline T xkeep(bool hi, T l, T u)
+{
+    const T keep = hi ? u : l, give = hi ? l : u;
+    return keep + dpp_t<CTRL>(give);
+}
+
+// Sum of three values over each aligned group of G lanes.  Returns the group total of value
+// group3_slot<G>(lane) (3 means none).
+template <int G>
+__device__ inline int group3_slot(int lane)
+{
+    return G == 4 ? (lane & 3) : ((lane >> 1) & 3);
+}
+// The lane that writes the group's total of its slot (one per slot and group).
+template <int G>
+__device__ inline bool group3_writer(int lane)
+{
+    return G == 4 ? true : G == 8 ? (lane & 1) == 0 : (lane & 9) == 0;
+}
+template <int G, typename T>
+__device__ inline T group_sum3(int lane, T v0, T v1, T v2)
+{
+    const bool b0 = lane & 1, b1 = lane & 2, b2 = lane & 4;
+    if constexpr (G == 4) {
+        const T a0 = xkeep<0x4e>(b1, v0, v2), a1 = xkeep<0x4e>(b1, v1, (T)0);  // partner i ^ 2
+        return xkeep<0xb1>(b0, a0, a1);                                         // partner i ^ 1
+    } else {
+        const T a0 = xkeep<0x141>(b2, v0, v2), a1 = xkeep<0x141>(b2, v1, (T)0);  // partner 7 - i
+        T r = xkeep<0x4e>(b1, a0, a1);                                           // slot 2 b2 + b1
+        r += dpp_t<0xb1>(r);                                                     // i and i ^ 1 hold it
+        if constexpr (G == 16) r += dpp_t<0x128>(r);                             // row_ror 8: both halves
+        return r;
+    }
+}
+
+// Sum of six values over each aligned group of G lanes (slots 6, 7 are zero).  G = 8, 16: one value per
+// lane, slot (lane & 7).  G = 4: two values per lane, slots 2 (lane & 3) and 2 (lane & 3) + 1.
+template <int G, typename T>
+__device__ inline void group_sum6(int lane, T v0, T v1, T v2, T v3, T v4, T v5, T &o0, T &o1)
+{
+    const bool b0 = lane & 1, b1 = lane & 2, b2 = lane & 4;
+    if constexpr (G == 4) {
+        const T k0 = xkeep<0x4e>(b1, v0, v4), k1 = xkeep<0x4e>(b1, v1, v5);
+        const T k2 = xkeep<0x4e>(b1, v2, (T)0), k3 = xkeep<0x4e>(b1, v3, (T)0);  // slots 4 b1 + j
+        o0 = xkeep<0xb1>(b0, k0, k2);
+        o1 = xkeep<0xb1>(b0, k1, k3);
+    } else {
+        const T k0 = xkeep<0x141>(b2, v0, v4), k1 = xkeep<0x141>(b2, v1, v5);
+        const T k2 = xkeep<0x141>(b2, v2, (T)0), k3 = xkeep<0x141>(b2, v3, (T)0);
+        const T u0 = xkeep<0x4e>(b1, k0, k2), u1 = xkeep<0x4e>(b1, k1, k3);
+        T z = xkeep<0xb1>(b0, u0, u1);
+        if constexpr (G == 16) z += dpp_t<0x128>(z);
+        o0 = z;
+        o1 = (T)0;
+    }
+}
+
+// Sum over the lanes of equal (lane mod G), returned in every lane: rotations inside the row, then the
+// row swaps.
+template <int G, typename T>
+__device__ inline T stride_sum(T v)
+{
+    if constexpr (G == 4) v += dpp_t<0x124>(v);  // row_ror 4
+    if constexpr (G <= 8) v += dpp_t<0x128>(v);  // row_ror 8
+    v = swap16_sum(v);
+    return swap32_sum(v);
+}
+
+// Number of set bits of m below this lane.
+__device__ inline int lanes_below(uint64_t m)
+{
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// Orders this wave's LDS accesses around a cross-lane exchange (DS instructions of one wave execute in
+// order; this keeps the compiler from moving accesses across the exchange).
+__device__ inline void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename T>
+__device__ inline void lds_add(T *p, T v)
+{
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+
+// Target of a lane, as the compacted direct sums read it.
+struct LdsTarget {
+    double rx, ry, rz;
+    int si, pad;
+};
+
+extern __shared__ __align__(16) unsigned char ffbh_dyn_lds[];
 
 // Logical block index, arranged so that each of the 8 XCDs (which receive workgroups round-robin)
 // works on one contiguous range of Morton-ordered targets and keeps those nodes in its own L2.
