@@ -17,21 +17,18 @@ __device__ inline void atomic_add_d(double *p, double v)
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Six scatter values of one wave added to six consecutive doubles at p (a 64-byte aligned record): the values
-// are summed over the wave (lanes that do not contribute pass zeros) by the transposed reduction, which
-// leaves value c in lane c, and lanes 0..5 add their component with one atomic instruction, so the memory
-// system sees one request per record.  Uniform control flow.
+// Six scatter values of one wave added to six consecutive doubles at p (a 64-byte aligned record): the
+// values are summed over the wave (lanes that do not contribute pass zeros) and the six lanes holding the
+// totals add them with one atomic instruction, so the memory system sees one request per record.
+// wcomp = total6_comp(lane).  Uniform control flow.
 template <typename T>
-__device__ inline void scatter6(uint64_t who, int lane, double *p, T v0, T v1, T v2, T v3, T v4, T v5)
+__device__ inline void scatter6(uint64_t who, int lane, int wcomp, double *p, T v0, T v1, T v2, T v3, T v4, T v5)
 {
     if (who == 0ull) return;
-    const T t = wave_sum6<T>(lane, v0, v1, v2, v3, v4, v5);  // lane c < 6 holds the total of value c
-    if (lane < 6) atomic_add_d(p + lane, (double)t);
+    const T t = wave_total6<T>(lane, v0, v1, v2, v3, v4, v5);
+    if (wcomp >= 0) atomic_add_d(p + wcomp, (double)t);
 }
 
-// Forward field and adjoint in one traversal (the upstream gradient Hbar does not depend on H).
-// Control flow is wave-uniform: when any lane accepts a cell (or uses a source), the whole wave
-// computes and the lanes that do not take part add zero.
 // One pair of the fused traversal for a target with upstream field gradient a: adds the gathered dL/dr
 // (g) and the field of b to the target's sums (FP32 partials since the last flush in MIXED mode, FP64
 // otherwise) and returns g and T(x) a for the scatter.  Lanes with `use` false add and return zeros.
@@ -135,6 +132,7 @@ __global__ __launch_bounds__(512) void k_adjoint(
     using Src = typename std::conditional<MIXED, Src32, Src64>::type;
     const Src *__restrict__ sr = (const Src *)src;
     const int lane = threadIdx.x & (kWave - 1);
+    const int wcomp = total6_comp(lane);
     const int wpb = blockDim.x / kWave;
     const int gw = xcd_block(blockIdx.x, gridDim.x) * wpb + (int)(threadIdx.x / kWave);
     if (gw >= num_waves) return;
@@ -171,13 +169,15 @@ __global__ __launch_bounds__(512) void k_adjoint(
             if (lane == 0) set_flag(status, BH_FLAG_TREE);
             break;
         }
-        const bool active = (mask >> lane) & 1ull;
+        const bool active = lane_in(mask);
         const bool inside = (unsigned)(si - nd.first) < (unsigned)nd.count;
         const double dx = rx - nd.cx, dy = ry - nd.cy, dz = rz - nd.cz;
         const double d2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
         const bool acc = active && !inside && nd.s2 < theta2 * d2;
         const uint64_t accm = __ballot(acc);
-        if (accm != 0ull) {
+        {
+            // nearly every visit has accepting lanes, so the pair is evaluated unconditionally (lanes that
+            // do not accept add zeros) and only the scatter is skipped for an empty mask
             T bx, by, bz;
             if (MIXED) {
                 bx = (T)nd.mx; by = (T)nd.my; bz = (T)nd.mz;
@@ -189,7 +189,7 @@ __global__ __launch_bounds__(512) void k_adjoint(
             fused_pair<MIXED, T>(acc, (T)dx, (T)dy, (T)dz, ax, ay, az, bx, by, bz, gx, gy, gz, tx, ty, tz, pgx, pgy,
                                  pgz, phx, phy, phz, grx, gry, grz, hx, hy, hz);
             // A_C += sum T(x) Hbar over the accepting lanes, B_C -= sum g
-            scatter6<T>(accm, lane, node_adj + 8 * (int64_t)cur, tx, ty, tz, -gx, -gy, -gz);
+            scatter6<T>(accm, lane, wcomp, node_adj + 8 * (int64_t)cur, tx, ty, tz, -gx, -gy, -gz);
         }
         const uint64_t open = __ballot(active && !acc);
         if (open == 0ull) continue;
@@ -202,7 +202,7 @@ __global__ __launch_bounds__(512) void k_adjoint(
             continue;
         }
         // leaf: direct sums over its members, packed over the lanes that opened it
-        if (open & (1ull << lane)) W.list[lanes_below(open)] = lane;
+        if (lane_in(open)) W.list[lanes_below(open)] = lane;
         const int c = __builtin_popcountll(open);
         wave_lds_sync();
         if (nd.count <= 4) adj_leaf<4>(W, lane, sr, g_rm, nd.first, nd.count, c, coincident);
@@ -337,6 +337,7 @@ __global__ __launch_bounds__(256) void k_adjoint2(
     using Src = typename std::conditional<MIXED, Src32, Src64>::type;
     const Src *__restrict__ sr = (const Src *)src;
     const int lane = threadIdx.x & (kWave - 1);
+    const int wcomp = total6_comp(lane);
     const int wpb = blockDim.x / kWave;
     const int gw = xcd_block(blockIdx.x, gridDim.x) * wpb + (int)(threadIdx.x / kWave);
     if (gw >= num_waves) return;  // whole waves; num_waves counts waves of 128 targets
@@ -362,7 +363,7 @@ __global__ __launch_bounds__(256) void k_adjoint2(
             if (lane == 0) set_flag(status, BH_FLAG_TREE);
             break;
         }
-        const bool act_a = (ma >> lane) & 1ull, act_b = (mb >> lane) & 1ull;
+        const bool act_a = lane_in(ma), act_b = lane_in(mb);
         const double dxa = ta.rx - nd.cx, dya = ta.ry - nd.cy, dza = ta.rz - nd.cz;
         const double dxb = tb.rx - nd.cx, dyb = tb.ry - nd.cy, dzb = tb.rz - nd.cz;
         const bool acc_a = act_a && (unsigned)(ta.si - nd.first) >= (unsigned)nd.count &&
@@ -392,7 +393,7 @@ __global__ __launch_bounds__(256) void k_adjoint2(
                 s3 -= gx; s4 -= gy; s5 -= gz;
             }
             // A_C += T(x) Hbar, B_C -= g, over the accepting targets of the wave
-            scatter6<T>(acca | accb, lane, node_adj + 8 * (int64_t)cur, s0, s1, s2v, s3, s4, s5);
+            scatter6<T>(acca | accb, lane, wcomp, node_adj + 8 * (int64_t)cur, s0, s1, s2v, s3, s4, s5);
         }
         const uint64_t opa = __ballot(act_a && !acc_a), opb = __ballot(act_b && !acc_b);
         if ((opa | opb) == 0ull) continue;
@@ -404,7 +405,7 @@ __global__ __launch_bounds__(256) void k_adjoint2(
             st.push(lane, nd.child, nd.nchild, opa, opb);
             continue;
         }
-        const bool me_a = (opa >> lane) & 1ull, me_b = (opb >> lane) & 1ull;
+        const bool me_a = lane_in(opa), me_b = lane_in(opb);
         const Src *q = sr + nd.first;
         for (int k = nd.first; k < nd.first + nd.count; ++k, ++q) {
             const Src sk = *q;
@@ -430,7 +431,7 @@ __global__ __launch_bounds__(256) void k_adjoint2(
                 s3 += ux; s4 += uy; s5 += uz;
             }
             // dL/dr_k -= sum g, dL/dm_k += sum T(x) Hbar over the wave's targets
-            scatter6<T>(usa | usb, lane, g_rm + 8 * (int64_t)k, s0, s1, s2v, s3, s4, s5);
+            scatter6<T>(usa | usb, lane, wcomp, g_rm + 8 * (int64_t)k, s0, s1, s2v, s3, s4, s5);
         }
         ta.flush();
         tb.flush();
@@ -465,6 +466,7 @@ __global__ __launch_bounds__(NW * 64) void k_adjoint_wg(
     __shared__ T lpart[NW][64][6];     // leaf source partials per wave (one chunk of up to 64 sources)
     const Src *__restrict__ sr = (const Src *)src;
     const int lane = threadIdx.x & (kWave - 1);
+    const int wcomp = total6_comp(lane);
     const int wv = (int)(threadIdx.x / kWave);
     const int blk = xcd_block(blockIdx.x, gridDim.x);
     const int seg = blk / blocks_per_seg;
@@ -497,7 +499,7 @@ __global__ __launch_bounds__(NW * 64) void k_adjoint_wg(
             broken = true;
             break;
         }
-        const bool active = (mask >> lane) & 1ull;
+        const bool active = lane_in(mask);
         const bool inside = (unsigned)(si - nd.first) < (unsigned)nd.count;
         const double dx = rx - nd.cx, dy = ry - nd.cy, dz = rz - nd.cz;
         const double d2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
@@ -515,10 +517,10 @@ __global__ __launch_bounds__(NW * 64) void k_adjoint_wg(
             T gx, gy, gz, tx, ty, tz;
             fused_pair<MIXED, T>(acc, (T)dx, (T)dy, (T)dz, ax, ay, az, bx, by, bz, gx, gy, gz, tx, ty, tz, pgx, pgy,
                                  pgz, phx, phy, phz, grx, gry, grz, hx, hy, hz);
-            vs = wave_sum6<T>(lane, tx, ty, tz, -gx, -gy, -gz);
+            vs = wave_total6<T>(lane, tx, ty, tz, -gx, -gy, -gz);
         }
         const uint64_t open = __ballot(active && !acc);
-        if (lane < 6) fpart[par][wv][lane] = vs;
+        if (wcomp >= 0) fpart[par][wv][wcomp] = vs;
         if (lane == 0) flags[par][wv] = (open != 0ull ? 1u : 0u) | (accm != 0ull ? 2u : 0u);
         __syncthreads();
         uint32_t any = 0u;
@@ -542,7 +544,7 @@ __global__ __launch_bounds__(NW * 64) void k_adjoint_wg(
         }
         // leaf: sources in chunks of 64; per chunk every wave writes its per-source partials, then the
         // workgroup adds them and issues one atomic per (source, component)
-        const bool me = (open >> lane) & 1ull;
+        const bool me = lane_in(open);
         for (int c0 = 0; c0 < nd.count; c0 += 64) {
             const int cn = min(64, nd.count - c0);
             const Src *q = sr + nd.first + c0;
@@ -559,9 +561,9 @@ __global__ __launch_bounds__(NW * 64) void k_adjoint_wg(
                     T qx, qy, qz, ux, uy, uz;
                     fused_pair<MIXED, T>(use, x, y, z, ax, ay, az, (T)sk.mx, (T)sk.my, (T)sk.mz, qx, qy, qz, ux, uy,
                                          uz, pgx, pgy, pgz, phx, phy, phz, grx, gry, grz, hx, hy, hz);
-                    ws = wave_sum6<T>(lane, -qx, -qy, -qz, ux, uy, uz);
+                    ws = wave_total6<T>(lane, -qx, -qy, -qz, ux, uy, uz);
                 }
-                if (lane < 6) lpart[wv][j][lane] = ws;
+                if (wcomp >= 0) lpart[wv][j][wcomp] = ws;
             }
             __syncthreads();
             for (int p = threadIdx.x; p < cn * 6; p += NW * 64) {

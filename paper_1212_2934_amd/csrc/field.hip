@@ -108,7 +108,7 @@ __global__ __launch_bounds__(512) void k_field(
             if (lane == 0) set_flag(status, BH_FLAG_TREE);
             break;
         }
-        const bool active = (mask >> lane) & 1ull;
+        const bool active = lane_in(mask);
         const bool inside = (unsigned)(si - nd.first) < (unsigned)nd.count;
         // acceptance test in FP64, exactly as defined
         const double dx = rx - nd.cx, dy = ry - nd.cy, dz = rz - nd.cz;
@@ -135,7 +135,7 @@ __global__ __launch_bounds__(512) void k_field(
             continue;
         }
         // leaf: direct sums over its members, packed over the lanes that opened it
-        if (open & (1ull << lane)) W.list[lanes_below(open)] = lane;
+        if (lane_in(open)) W.list[lanes_below(open)] = lane;
         const int c = __builtin_popcountll(open);
         wave_lds_sync();
         if (nd.count <= 4) field_leaf<COUNT, 4>(W, lane, sr, nd.first, nd.count, c, coincident);

@@ -128,7 +128,7 @@ __global__ __launch_bounds__(256) void k_wca(const NodeRec *__restrict__ nodes, 
             if (lane == 0) set_flag(status, BH_FLAG_TREE);
             break;
         }
-        const bool active = (mask >> lane) & 1ull;
+        const bool active = lane_in(mask);
         // squared distance from the target to the members' bounding box
         const double ex = fmax(fmax(lox - rx, rx - hix), 0.0);
         const double ey = fmax(fmax(loy - ry, ry - hiy), 0.0);
@@ -146,7 +146,7 @@ __global__ __launch_bounds__(256) void k_wca(const NodeRec *__restrict__ nodes, 
         }
         // leaf: members in chunks of 64, one per lane (one vector load per coordinate), then broadcast to
         // the wave one at a time; the pair force is evaluated only when some lane is within the cut-off
-        const bool me = (open >> lane) & 1ull;
+        const bool me = lane_in(open);
         for (int c0 = 0; c0 < nd.count; c0 += kWave) {
             const int cn = min(kWave, nd.count - c0);
             const int kl = nd.first + c0 + (lane < cn ? lane : 0);

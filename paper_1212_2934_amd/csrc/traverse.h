@@ -204,34 +204,70 @@ __device__ inline float dpp_t(float v) { return dpp_f<CTRL>(v); }
 template <int CTRL>
 __device__ inline double dpp_t(double v) { return dpp_d<CTRL>(v); }
 
-// Wave sums of six per-lane values by a transposed butterfly.  Inside each group of eight lanes three
-// exchange steps halve the number of values a lane carries (8 -> 4 -> 2 -> 1; slots 6 and 7 are zero):
-// at each step the two partners split the values between them and each adds the partner's copy of the
-// half it keeps, so lane l ends with value (l & 7) summed over its group.  A rotate by eight inside the
-// row and two row swaps then add the eight groups.  Every lane returns the wave total of value (l & 7)
-// (zero for 6 and 7); all 64 lanes must be active.
-template <typename T>
-__device__ inline T wave_sum6(int lane, T v0, T v1, T v2, T v3, T v4, T v5)
+// One exchange step of a transposed reduction: the two lanes paired by DPP control CTRL each keep one of
+// two values (the lane with `hi` keeps u, its partner l) and add the partner's copy of it.
+template <int CTRL, typename T>
+__device__ inline T xkeep(bool hi, T l, T u)
 {
-    const bool b2 = (lane & 4) != 0, b1 = (lane & 2) != 0, b0 = (lane & 1) != 0;
-    // partner 7 - i in the group (row_half_mirror); the lane with bit 2 keeps values 4..7
-    T k0 = b2 ? v4 : v0, k1 = b2 ? v5 : v1, k2 = b2 ? (T)0 : v2, k3 = b2 ? (T)0 : v3;
-    const T s0 = b2 ? v0 : v4, s1 = b2 ? v1 : v5, s2 = b2 ? v2 : (T)0, s3 = b2 ? v3 : (T)0;
-    k0 += dpp_t<0x141>(s0);
-    k1 += dpp_t<0x141>(s1);
-    k2 += dpp_t<0x141>(s2);
-    k3 += dpp_t<0x141>(s3);
-    // partner i ^ 2 (quad_perm [2,3,0,1]); bit 1 keeps the upper pair
-    T u0 = b1 ? k2 : k0, u1 = b1 ? k3 : k1;
-    const T t0 = b1 ? k0 : k2, t1 = b1 ? k1 : k3;
-    u0 += dpp_t<0x4e>(t0);
-    u1 += dpp_t<0x4e>(t1);
-    // partner i ^ 1 (quad_perm [1,0,3,2]); bit 0 keeps the upper one
-    T z = b0 ? u1 : u0;
-    z += dpp_t<0xb1>(b0 ? u0 : u1);
-    z += dpp_t<0x128>(z);  // row_ror 8: the two groups of the row
-    z = swap16_sum(z);     // rows 0+1, 2+3
-    return swap32_sum(z);  // all four rows
+    const T keep = hi ? u : l, give = hi ? l : u;
+    return keep + dpp_t<CTRL>(give);
+}
+
+// Row exchanges of two different values in one instruction.  permlane32_swap(a, b) leaves lanes 0..31 of
+// one result and of the other holding the two halves of a, and lanes 32..63 the two halves of b, so the
+// sum of the results is a + (a from lane l ^ 32) in lanes 0..31 and the same for b in lanes 32..63.
+// permlane16_swap(a, b) does the same with rows: rows 0 and 2 sum a with the row above or below (l ^ 16),
+// rows 1 and 3 sum b.
+__device__ inline float swap32_pair(float a, float b)
+{
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ inline float swap16_pair(float a, float b)
+{
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ inline double swap32_pair(double a, double b)
+{
+    const uint64_t x = (uint64_t)__double_as_longlong(a), y = (uint64_t)__double_as_longlong(b);
+    const auto lo = __builtin_amdgcn_permlane32_swap((uint32_t)x, (uint32_t)y, false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap((uint32_t)(x >> 32), (uint32_t)(y >> 32), false, false);
+    return __longlong_as_double((long long)(((uint64_t)hi[0] << 32) | lo[0])) +
+           __longlong_as_double((long long)(((uint64_t)hi[1] << 32) | lo[1]));
+}
+__device__ inline double swap16_pair(double a, double b)
+{
+    const uint64_t x = (uint64_t)__double_as_longlong(a), y = (uint64_t)__double_as_longlong(b);
+    const auto lo = __builtin_amdgcn_permlane16_swap((uint32_t)x, (uint32_t)y, false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap((uint32_t)(x >> 32), (uint32_t)(y >> 32), false, false);
+    return __longlong_as_double((long long)(((uint64_t)hi[0] << 32) | lo[0])) +
+           __longlong_as_double((long long)(((uint64_t)hi[1] << 32) | lo[1]));
+}
+
+// Wave totals of six per-lane values (all 64 lanes active).  The row exchanges come first and move two
+// values each: after the 32-lane swaps lanes 0..31 carry v0, v2, v4 and lanes 32..63 carry v1, v3, v5;
+// after the 16-lane swaps rows 0..3 carry v0, v2, v1, v3 in one register and rows 0, 1 / 2, 3 carry v4 / v5
+// in another.  Inside each row one exchange step over l ^ 8 keeps the first register in lanes 0..7 and the
+// second in lanes 8..15, and three DPP additions finish the eight-lane groups.  The total of value c is
+// then held by lane total6_lane(c): 0, 32, 16, 48, 8, 40 for c = 0..5.
+template <typename T>
+__device__ inline T wave_total6(int lane, T v0, T v1, T v2, T v3, T v4, T v5)
+{
+    const T w0 = swap32_pair(v0, v1), w1 = swap32_pair(v2, v3), w2 = swap32_pair(v4, v5);
+    const T x0 = swap16_pair(w0, w1), x1 = swap16_sum(w2);
+    T y = xkeep<0x128>((lane & 8) != 0, x0, x1);  // row_ror 8 pairs l and l ^ 8
+    y += dpp_t<0x141>(y);
+    y += dpp_t<0x4e>(y);
+    return y + dpp_t<0xb1>(y);
+}
+// Which of the six totals this lane holds for writing (-1: none).
+__device__ inline int total6_comp(int lane)
+{
+    if ((lane & 7) != 0) return -1;
+    const int row = lane >> 4;
+    if (lane & 8) return (row & 1) ? -1 : 4 + (row >> 1);
+    return row == 0 ? 0 : row == 1 ? 2 : row == 2 ? 1 : 3;
 }
 
 // ---- compacted direct sums (leaf cells) -----------------------------------------------------------
@@ -241,15 +277,6 @@ __device__ inline T wave_sum6(int lane, T v0, T v1, T v2, T v3, T v4, T v5)
 // (G = 4, 8 or 16, the smallest that holds the leaf's members, larger leaves in chunks of 16), lane b of
 // group g takes member b against listed target t0 + g, so one pass covers 64 / G targets.  Per-target sums
 // are group reductions added to the target's LDS slot; the owner lane collects them after the leaf.
-
-// One exchange step of a transposed reduction: the two lanes paired by DPP control CTRL each keep one of
-// two values (the lane with `hi` keeps u, its partner l) and add the partner's copy of it.
-template <int CTRL, typename T>
-__device__ inline T xkeep(bool hi, T l, T u)
-{
-    const T keep = hi ? u : l, give = hi ? l : u;
-    return keep + dpp_t<CTRL>(give);
-}
 
 // Sum of three values over each aligned group of G lanes.  Returns the group total of value
 // group3_slot<G>(lane) (3 means none).
@@ -312,6 +339,10 @@ __device__ inline T stride_sum(T v)
     v = swap16_sum(v);
     return swap32_sum(v);
 }
+
+// This lane's bit of a wave-uniform lane mask, as a lane condition (the mask is used as the condition
+// directly, without per-lane shifts).
+__device__ inline bool lane_in(uint64_t m) { return __builtin_amdgcn_inverse_ballot_w64(m); }
 
 // Number of set bits of m below this lane.
 __device__ inline int lanes_below(uint64_t m)
