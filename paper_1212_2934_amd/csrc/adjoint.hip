@@ -154,27 +154,27 @@ __global__ __launch_bounds__(512) void k_adjoint(
 #pragma unroll
     for (int j = 0; j < 6; ++j) W.acc[lane][j] = (T)0;
 
-    LaneStack st{0, 0, 0, 0};
-    st.push(lane, seg, 1, __ballot(valid));
+    LaneStack st;
+    st.init(seg, 1, ballot(valid));
     int guard = max_nodes;  // a wave visits each node at most once
-    while (st.sp > 0) {
+    while (st.more()) {
         uint64_t mask;
-        const int cur = st.pop(lane, mask);
+        const int cur = st.pop(mask);
         if (--guard < 0 || (unsigned)cur >= (unsigned)max_nodes) {
             if (lane == 0) set_flag(status, BH_FLAG_TREE);
             break;
         }
         const NodeRec nd = nodes[cur];
-        if (nd.first < 0 || nd.count < 1 || (int64_t)nd.first + nd.count > ntot) {
+        if (nd.first < 0 || nd.count < 1 || (uint32_t)nd.first + (uint32_t)nd.count > (uint32_t)ntot) {
             if (lane == 0) set_flag(status, BH_FLAG_TREE);
             break;
         }
-        const bool active = lane_in(mask);
-        const bool inside = (unsigned)(si - nd.first) < (unsigned)nd.count;
+        // masks of the lanes that take part, of the targets inside the node and of the acceptance test
+        const uint64_t insm = ballot((unsigned)(si - nd.first) < (unsigned)nd.count);
         const double dx = rx - nd.cx, dy = ry - nd.cy, dz = rz - nd.cz;
         const double d2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
-        const bool acc = active && !inside && nd.s2 < theta2 * d2;
-        const uint64_t accm = __ballot(acc);
+        const uint64_t accm = mask & ~insm & ballot(nd.s2 < theta2 * d2);
+        const bool acc = lane_in(accm);
         {
             // nearly every visit has accepting lanes, so the pair is evaluated unconditionally (lanes that
             // do not accept add zeros) and only the scatter is skipped for an empty mask
@@ -191,7 +191,7 @@ __global__ __launch_bounds__(512) void k_adjoint(
             // A_C += sum T(x) Hbar over the accepting lanes, B_C -= sum g
             scatter6<T>(accm, lane, wcomp, node_adj + 8 * (int64_t)cur, tx, ty, tz, -gx, -gy, -gz);
         }
-        const uint64_t open = __ballot(active && !acc);
+        const uint64_t open = mask & ~accm;
         if (open == 0ull) continue;
         if (nd.nchild != 0) {
             if (st.sp >= kStackMax) {
@@ -227,7 +227,7 @@ __global__ __launch_bounds__(512) void k_adjoint(
         grx += (double)pgx; gry += (double)pgy; grz += (double)pgz;
         hx += (double)phx; hy += (double)phy; hz += (double)phz;
     }
-    if (__ballot(coincident) != 0ull && lane == 0) set_flag(status, BH_FLAG_COINCIDENT);
+    if (ballot(coincident) != 0ull && lane == 0) set_flag(status, BH_FLAG_COINCIDENT);
 
     double e = 0.0;
     if (valid) {
@@ -349,7 +349,7 @@ __global__ __launch_bounds__(256) void k_adjoint2(
     bool coincident = false;
 
     LaneStack2 st{0, 0, 0, 0, 0, 0};
-    st.push(lane, seg, 1, __ballot(ta.valid), __ballot(tb.valid));
+    st.push(lane, seg, 1, ballot(ta.valid), ballot(tb.valid));
     int guard = max_nodes;
     while (st.sp > 0) {
         uint64_t ma, mb;
@@ -359,7 +359,7 @@ __global__ __launch_bounds__(256) void k_adjoint2(
             break;
         }
         const NodeRec nd = nodes[cur];
-        if (nd.first < 0 || nd.count < 1 || (int64_t)nd.first + nd.count > ntot) {
+        if (nd.first < 0 || nd.count < 1 || (uint32_t)nd.first + (uint32_t)nd.count > (uint32_t)ntot) {
             if (lane == 0) set_flag(status, BH_FLAG_TREE);
             break;
         }
@@ -370,7 +370,7 @@ __global__ __launch_bounds__(256) void k_adjoint2(
                            nd.s2 < theta2 * __builtin_fma(dza, dza, __builtin_fma(dya, dya, dxa * dxa));
         const bool acc_b = act_b && (unsigned)(tb.si - nd.first) >= (unsigned)nd.count &&
                            nd.s2 < theta2 * __builtin_fma(dzb, dzb, __builtin_fma(dyb, dyb, dxb * dxb));
-        const uint64_t acca = __ballot(acc_a), accb = __ballot(acc_b);
+        const uint64_t acca = ballot(acc_a), accb = ballot(acc_b);
         if ((acca | accb) != 0ull) {
             T bx, by, bz;
             if (MIXED) {
@@ -395,7 +395,7 @@ __global__ __launch_bounds__(256) void k_adjoint2(
             // A_C += T(x) Hbar, B_C -= g, over the accepting targets of the wave
             scatter6<T>(acca | accb, lane, wcomp, node_adj + 8 * (int64_t)cur, s0, s1, s2v, s3, s4, s5);
         }
-        const uint64_t opa = __ballot(act_a && !acc_a), opb = __ballot(act_b && !acc_b);
+        const uint64_t opa = ballot(act_a && !acc_a), opb = ballot(act_b && !acc_b);
         if ((opa | opb) == 0ull) continue;
         if (nd.nchild != 0) {
             if (st.sp >= kStackMax) {
@@ -415,7 +415,7 @@ __global__ __launch_bounds__(256) void k_adjoint2(
             const bool oa = me_a && k != ta.si, ob = me_b && k != tb.si;
             const bool ua = oa && r2a > (T)0, ub = ob && r2b > (T)0;
             coincident |= (oa && !(r2a > (T)0)) || (ob && !(r2b > (T)0));
-            const uint64_t usa = __ballot(ua), usb = __ballot(ub);
+            const uint64_t usa = ballot(ua), usb = ballot(ub);
             if ((usa | usb) == 0ull) continue;
             T s0 = 0, s1 = 0, s2v = 0, s3 = 0, s4 = 0, s5 = 0;
             if (usa) {
@@ -436,7 +436,7 @@ __global__ __launch_bounds__(256) void k_adjoint2(
         ta.flush();
         tb.flush();
     }
-    if (__ballot(coincident) != 0ull && lane == 0) set_flag(status, BH_FLAG_COINCIDENT);
+    if (ballot(coincident) != 0ull && lane == 0) set_flag(status, BH_FLAG_COINCIDENT);
     double e = 0.0;
     tgt_finish<MIXED>(ta, smom, hext, perm, g_gather, Hs, Hout, ntot, n, seg, e);
     tgt_finish<MIXED>(tb, smom, hext, perm, g_gather, Hs, Hout, ntot, n, seg, e);
@@ -482,29 +482,29 @@ __global__ __launch_bounds__(NW * 64) void k_adjoint_wg(
     T pgx = 0, pgy = 0, pgz = 0, phx = 0, phy = 0, phz = 0;
     bool coincident = false;
 
-    LaneStack st{0, 0, 0, 0};
-    st.push(lane, seg, 1, __ballot(valid));  // every wave pushes the root, even with no valid lane
+    LaneStack st;
+    st.init(seg, 1, ballot(valid));  // every wave starts at the root, even with no valid lane
     int guard = max_nodes;
     int par = 0;
     bool broken = false;
-    while (st.sp > 0) {
+    while (st.more()) {
         uint64_t mask;
-        const int cur = st.pop(lane, mask);
+        const int cur = st.pop(mask);
         if (--guard < 0 || (unsigned)cur >= (unsigned)max_nodes) {  // identical in every wave
             broken = true;
             break;
         }
         const NodeRec nd = nodes[cur];
-        if (nd.first < 0 || nd.count < 1 || (int64_t)nd.first + nd.count > ntot) {
+        if (nd.first < 0 || nd.count < 1 || (uint32_t)nd.first + (uint32_t)nd.count > (uint32_t)ntot) {
             broken = true;
             break;
         }
-        const bool active = lane_in(mask);
-        const bool inside = (unsigned)(si - nd.first) < (unsigned)nd.count;
+        // masks of the lanes that take part, of the targets inside the node and of the acceptance test
+        const uint64_t insm = ballot((unsigned)(si - nd.first) < (unsigned)nd.count);
         const double dx = rx - nd.cx, dy = ry - nd.cy, dz = rz - nd.cz;
         const double d2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
-        const bool acc = active && !inside && nd.s2 < theta2 * d2;
-        const uint64_t accm = __ballot(acc);
+        const uint64_t accm = mask & ~insm & ballot(nd.s2 < theta2 * d2);
+        const bool acc = lane_in(accm);
         T vs = 0;
         if (accm != 0ull) {
             T bx, by, bz;
@@ -519,7 +519,7 @@ __global__ __launch_bounds__(NW * 64) void k_adjoint_wg(
                                  pgz, phx, phy, phz, grx, gry, grz, hx, hy, hz);
             vs = wave_total6<T>(lane, tx, ty, tz, -gx, -gy, -gz);
         }
-        const uint64_t open = __ballot(active && !acc);
+        const uint64_t open = mask & ~accm;
         if (wcomp >= 0) fpart[par][wv][wcomp] = vs;
         if (lane == 0) flags[par][wv] = (open != 0ull ? 1u : 0u) | (accm != 0ull ? 2u : 0u);
         __syncthreads();
@@ -557,7 +557,7 @@ __global__ __launch_bounds__(NW * 64) void k_adjoint_wg(
                 const bool use = other && r2 > (T)0;
                 coincident |= other && !(r2 > (T)0);
                 T ws = 0;
-                if (__ballot(use) != 0ull) {
+                if (ballot(use) != 0ull) {
                     T qx, qy, qz, ux, uy, uz;
                     fused_pair<MIXED, T>(use, x, y, z, ax, ay, az, (T)sk.mx, (T)sk.my, (T)sk.mz, qx, qy, qz, ux, uy,
                                          uz, pgx, pgy, pgz, phx, phy, phz, grx, gry, grz, hx, hy, hz);
@@ -586,7 +586,7 @@ __global__ __launch_bounds__(NW * 64) void k_adjoint_wg(
         grx += (double)pgx; gry += (double)pgy; grz += (double)pgz;
         hx += (double)phx; hy += (double)phy; hz += (double)phz;
     }
-    if (__ballot(coincident) != 0ull && lane == 0) set_flag(status, BH_FLAG_COINCIDENT);
+    if (ballot(coincident) != 0ull && lane == 0) set_flag(status, BH_FLAG_COINCIDENT);
 
     double e = 0.0;
     if (valid) {

@@ -54,7 +54,7 @@ __device__ inline void field_leaf(FieldLds<T> &W, int lane, const Src *__restric
             const T v = group_sum3<G>(lane, hx, hy, hz);
             if (tok && wr) lds_add(&W.acc[tl][slot], v);
             if constexpr (COUNT) {
-                const uint64_t um = __ballot(use) >> (grp * G);
+                const uint64_t um = ballot(use) >> (grp * G);
                 const int nu = __builtin_popcountll(um & ((1ull << G) - 1ull));
                 if (tok && b == 0) lds_add(&W.cnt[tl], nu);
             }
@@ -93,28 +93,29 @@ __global__ __launch_bounds__(512) void k_field(
     W.acc[lane][0] = W.acc[lane][1] = W.acc[lane][2] = (T)0;
     W.cnt[lane] = 0;
 
-    LaneStack st{0, 0, 0, 0};
-    st.push(lane, seg, 1, __ballot(valid));
+    LaneStack st;
+    st.init(seg, 1, ballot(valid));
     int guard = max_nodes;  // a wave visits each node at most once
-    while (st.sp > 0) {
+    while (st.more()) {
         uint64_t mask;
-        const int cur = st.pop(lane, mask);
+        const int cur = st.pop(mask);
         if (--guard < 0 || (unsigned)cur >= (unsigned)max_nodes) {
             if (lane == 0) set_flag(status, BH_FLAG_TREE);
             break;
         }
         const NodeRec nd = nodes[cur];
-        if (nd.first < 0 || nd.count < 1 || (int64_t)nd.first + nd.count > ntot) {
+        if (nd.first < 0 || nd.count < 1 || (uint32_t)nd.first + (uint32_t)nd.count > (uint32_t)ntot) {
             if (lane == 0) set_flag(status, BH_FLAG_TREE);
             break;
         }
-        const bool active = lane_in(mask);
-        const bool inside = (unsigned)(si - nd.first) < (unsigned)nd.count;
+        // masks of the lanes that take part, of the targets inside the node and of the acceptance test
+        const uint64_t insm = ballot((unsigned)(si - nd.first) < (unsigned)nd.count);
         // acceptance test in FP64, exactly as defined
         const double dx = rx - nd.cx, dy = ry - nd.cy, dz = rz - nd.cz;
         const double d2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
-        const bool acc = active && !inside && nd.s2 < theta2 * d2;
-        if (__ballot(acc) != 0ull) {
+        const uint64_t accm = mask & ~insm & ballot(nd.s2 < theta2 * d2);
+        const bool acc = lane_in(accm);
+        if (accm != 0ull) {
             // the whole wave computes; lanes that did not accept add zero
             if (MIXED) {
                 dip_acc<T>(acc, (T)dx, (T)dy, (T)dz, (T)nd.mx, (T)nd.my, (T)nd.mz, px, py, pz);
@@ -124,7 +125,7 @@ __global__ __launch_bounds__(512) void k_field(
             }
             if (COUNT) nfar += acc ? 1 : 0;
         }
-        const uint64_t open = __ballot(active && !acc);
+        const uint64_t open = mask & ~accm;
         if (open == 0ull) continue;
         if (nd.nchild != 0) {
             if (st.sp >= kStackMax) {
@@ -158,7 +159,7 @@ __global__ __launch_bounds__(512) void k_field(
     if (MIXED) {
         hx += (double)px; hy += (double)py; hz += (double)pz;
     }
-    if (__ballot(coincident) != 0ull && lane == 0) set_flag(status, BH_FLAG_COINCIDENT);
+    if (ballot(coincident) != 0ull && lane == 0) set_flag(status, BH_FLAG_COINCIDENT);
 
     // energy contribution of this wave: -1/2 m.H - m.H_ext
     double e = 0.0;

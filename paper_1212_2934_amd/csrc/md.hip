@@ -110,12 +110,12 @@ __global__ __launch_bounds__(256) void k_wca(const NodeRec *__restrict__ nodes, 
     const double rc = 1.122462048309373 * sigma, rc2 = rc * rc, s2 = sigma * sigma;
     double fx = 0.0, fy = 0.0, fz = 0.0;
 
-    LaneStack st{0, 0, 0, 0};
-    st.push(lane, seg, 1, __ballot(valid));
+    LaneStack st;
+    st.init(seg, 1, ballot(valid));
     int guard = max_nodes;
-    while (st.sp > 0 && eps > 0.0) {
+    while (st.more() && eps > 0.0) {
         uint64_t mask;
-        const int cur = st.pop(lane, mask);
+        const int cur = st.pop(mask);
         if (--guard < 0 || (unsigned)cur >= (unsigned)max_nodes) {
             if (lane == 0) set_flag(status, BH_FLAG_TREE);
             break;
@@ -124,17 +124,15 @@ __global__ __launch_bounds__(256) void k_wca(const NodeRec *__restrict__ nodes, 
         const NodeRec nd = nodes[cur];
         const double *bx = node_box + 8 * (int64_t)cur;
         const double lox = bx[0], loy = bx[1], loz = bx[2], hix = bx[4], hiy = bx[5], hiz = bx[6];
-        if (nd.first < 0 || nd.count < 1 || (int64_t)nd.first + nd.count > ntot) {
+        if (nd.first < 0 || nd.count < 1 || (uint32_t)nd.first + (uint32_t)nd.count > (uint32_t)ntot) {
             if (lane == 0) set_flag(status, BH_FLAG_TREE);
             break;
         }
-        const bool active = lane_in(mask);
         // squared distance from the target to the members' bounding box
         const double ex = fmax(fmax(lox - rx, rx - hix), 0.0);
         const double ey = fmax(fmax(loy - ry, ry - hiy), 0.0);
         const double ez = fmax(fmax(loz - rz, rz - hiz), 0.0);
-        const bool hit = active && (ex * ex + ey * ey + ez * ez < rc2);
-        const uint64_t open = __ballot(hit);
+        const uint64_t open = mask & ballot(ex * ex + ey * ey + ez * ez < rc2);
         if (open == 0ull) continue;
         if (nd.nchild != 0) {
             if (st.sp >= kStackMax) {
@@ -155,7 +153,7 @@ __global__ __launch_bounds__(256) void k_wca(const NodeRec *__restrict__ nodes, 
                 const double x = rx - readlane_d(qx, j), y = ry - readlane_d(qy, j), z = rz - readlane_d(qz, j);
                 const double r2 = x * x + y * y + z * z;
                 const bool near = me && nd.first + c0 + j != si && r2 < rc2 && r2 > 0.0;
-                if (__ballot(near) == 0ull) continue;
+                if (ballot(near) == 0ull) continue;
                 if (near) wca_pair(x, y, z, s2, eps, rc2, fx, fy, fz);
             }
         }

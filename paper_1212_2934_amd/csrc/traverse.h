@@ -340,6 +340,9 @@ __device__ inline T stride_sum(T v)
     return swap32_sum(v);
 }
 
+// Lane mask of a lane condition (the condition is already a mask; no conversion through an integer).
+__device__ inline uint64_t ballot(bool b) { return __builtin_amdgcn_ballot_w64(b); }
+
 // This lane's bit of a wave-uniform lane mask, as a lane condition (the mask is used as the condition
 // directly, without per-lane shifts).
 __device__ inline bool lane_in(uint64_t m) { return __builtin_amdgcn_inverse_ballot_w64(m); }
@@ -382,34 +385,56 @@ __device__ inline int xcd_block(int bid, int nb)
     return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
 }
 
-// Traversal stack held in VGPRs: entry e lives in lane e of two registers.  The first packs a range
-// of sibling nodes as (next node) | (siblings left after it) << 28; the second pair holds the 64-bit
-// lane mask.  Push and pop run in wave-uniform control flow with every lane active: a push selects
-// lane sp, a pop reads lane sp-1 into scalars with v_readlane.  Node indices stay below 2^28.
+// Depth-first stack of node ranges for one wave.  The range being walked is held in scalar registers (next
+// node, nodes left, lane mask), so taking the next node costs no vector instructions; the ranges below it
+// are held one per lane (entry e in lane e: first node | (count - 1) << 28 and the 64-bit mask) and are
+// read back with v_readlane when the walked range runs out.  A push first parks the rest of the walked
+// range in the next lane, so nodes are visited in the same order as with a plain stack of ranges.
 struct LaneStack {
-    int ent, mlo, mhi;
-    int sp;
+    int ent, mlo, mhi;  // parked ranges, entry `lane` in this lane
+    int sp;             // number of parked ranges
+    int tnode, tleft;   // walked range: next node and nodes left
+    uint64_t tmask;     // walked range: lane mask
 
+    // Start with one range; first and count must be wave-uniform (read from lane 0 so that the compiler
+    // can keep the walked range, and the node loads that depend on it, scalar).
+    __device__ inline void init(int first, int count, uint64_t m)
+    {
+        ent = mlo = mhi = 0;
+        sp = 0;
+        tnode = __builtin_amdgcn_readfirstlane(first);
+        tleft = __builtin_amdgcn_readfirstlane(count);
+        tmask = m;
+    }
+    __device__ inline bool more() const { return tleft > 0 || sp > 0; }
     __device__ inline void push(int lane, int first, int count, uint64_t m)
     {
-        const bool here = lane == sp;
-        ent = here ? (first | ((count - 1) << 28)) : ent;
-        mlo = here ? (int)(uint32_t)m : mlo;
-        mhi = here ? (int)(uint32_t)(m >> 32) : mhi;
-        ++sp;
+        if (tleft > 0) {
+            const bool here = lane == sp;
+            ent = here ? (tnode | ((tleft - 1) << 28)) : ent;
+            mlo = here ? (int)(uint32_t)tmask : mlo;
+            mhi = here ? (int)(uint32_t)(tmask >> 32) : mhi;
+            ++sp;
+        }
+        tnode = first;
+        tleft = count;
+        tmask = m;
     }
-    // Take the next node of the top range; returns its index and lane mask.
-    __device__ inline int pop(int lane, uint64_t &m)
+    // Next node and its lane mask (call only while more()).
+    __device__ inline int pop(uint64_t &m)
     {
-        const int top = sp - 1;
-        const uint32_t e = (uint32_t)__builtin_amdgcn_readlane(ent, top);
-        const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane(mlo, top);
-        const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane(mhi, top);
-        m = ((uint64_t)hi << 32) | lo;
-        const int c = (int)(e & 0x0fffffffu);
-        if (e >> 28) ent = (lane == top) ? (int)(e + 1u - (1u << 28)) : ent;
-        else sp = top;
-        return c;
+        if (tleft == 0) {
+            --sp;
+            const uint32_t e = (uint32_t)__builtin_amdgcn_readlane(ent, sp);
+            const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane(mlo, sp);
+            const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane(mhi, sp);
+            tnode = (int)(e & 0x0fffffffu);
+            tleft = (int)(e >> 28) + 1;
+            tmask = ((uint64_t)hi << 32) | lo;
+        }
+        m = tmask;
+        --tleft;
+        return tnode++;
     }
 };
 
