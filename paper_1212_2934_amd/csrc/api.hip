@@ -25,6 +25,11 @@ Layout plan_layout(const bh_params &p)
     L.hist_len = L.B * kRadixBins * L.tiles;
     L.bin_int = L.B * (L.n - 1);
     L.num_waves = L.B * ((L.n + kWave - 1) / kWave);
+    // short-range grid: at most 32 entries per particle and level 7
+    int lg = 0;
+    while (((int64_t)2 << lg) <= 32 * L.n) ++lg;
+    L.cell_lcap = lg / 3 < 7 ? lg / 3 : 7;
+    L.cell_T = (int64_t)1 << (3 * L.cell_lcap);
     Workspace w{};
     carve(L, nullptr, w);
     return L;
@@ -72,7 +77,6 @@ void carve(const Layout &Lc, void *base, Workspace &w)
     w.nodes = (NodeRec *)take(sizeof(NodeRec) * mn);
     w.node_level = (int32_t *)take(4 * mn);
     w.node_m64 = (double *)take(4 * 8 * mn);
-    w.node_box = (double *)take(8 * 8 * mn);
     w.ones = (double *)take(8 * (size_t)L.B);
     w.arrive = (uint32_t *)take(4 * mn);
     w.lvl = (uint32_t *)take(4 * 128);
@@ -88,6 +92,7 @@ void carve(const Layout &Lc, void *base, Workspace &w)
     w.md_force = (double *)take(3 * 8 * nt);
     w.md_grad_r = (double *)take(3 * 8 * nt);
     w.md_grad_m = (double *)take(3 * 8 * nt);
+    w.cell_first = (uint32_t *)take(4 * (size_t)L.B * (size_t)L.cell_T);
     L.bytes = align_up(off, 256);
 }
 

@@ -630,8 +630,8 @@ __global__ __launch_bounds__(256) void k_upward_level(const double *__restrict__
                                                       const int32_t *__restrict__ node_level,
                                                       const uint32_t *__restrict__ lvl,
                                                       const int32_t *__restrict__ lvl_nodes,
-                                                      const double *__restrict__ bbox, double *__restrict__ node_box,
-                                                      int level, int64_t max_nodes)
+                                                      const double *__restrict__ bbox, int level,
+                                                      int64_t max_nodes)
 {
     const uint32_t b0 = lvl[32 + level];
     const uint32_t b1 = (int64_t)lvl[32 + level + 1] < max_nodes ? lvl[32 + level + 1] : (uint32_t)max_nodes;
@@ -643,36 +643,17 @@ __global__ __launch_bounds__(256) void k_upward_level(const double *__restrict__
             (nd.nchild != 0 && (nd.child < 0 || (int64_t)nd.child + nd.nchild > max_nodes)))
             continue;
         double sx = 0.0, sy = 0.0, sz = 0.0;
-        double lo[3] = {__builtin_inf(), __builtin_inf(), __builtin_inf()};
-        double hi[3] = {-__builtin_inf(), -__builtin_inf(), -__builtin_inf()};
         if (nd.nchild == 0) {
             for (int k = nd.first; k < nd.first + nd.count; ++k) {
-                const double x = vals[k], y = vals[ntot + k], z = vals[2 * ntot + k];
-                sx = sx + x;
-                sy = sy + y;
-                sz = sz + z;
-                if (MODE == 0) {
-                    lo[0] = fmin(lo[0], x); lo[1] = fmin(lo[1], y); lo[2] = fmin(lo[2], z);
-                    hi[0] = fmax(hi[0], x); hi[1] = fmax(hi[1], y); hi[2] = fmax(hi[2], z);
-                }
+                sx = sx + vals[k];
+                sy = sy + vals[ntot + k];
+                sz = sz + vals[2 * ntot + k];
             }
         } else {
             for (int c = nd.child; c < nd.child + nd.nchild; ++c) {
                 sx = sx + sums[4 * c];
                 sy = sy + sums[4 * c + 1];
                 sz = sz + sums[4 * c + 2];
-                if (MODE == 0) {
-                    for (int a = 0; a < 3; ++a) {
-                        lo[a] = fmin(lo[a], node_box[8 * c + a]);
-                        hi[a] = fmax(hi[a], node_box[8 * c + 4 + a]);
-                    }
-                }
-            }
-        }
-        if (MODE == 0) {
-            for (int a = 0; a < 3; ++a) {
-                node_box[8 * id + a] = lo[a];
-                node_box[8 * id + 4 + a] = hi[a];
             }
         }
         sums[4 * id] = sx;
@@ -704,7 +685,7 @@ static void upward(Handle &h, const double *vals, hipStream_t s)
     const unsigned g = grid_for(L.max_nodes, 256, 512);
     for (int level = kMaxLevel; level >= 0; --level)
         hipLaunchKernelGGL(k_upward_level<MODE>, dim3(g), dim3(256), 0, s, vals, L.ntot, L.n, w.nodes, w.node_adj,
-                           w.node_m64, w.node_level, w.lvl, w.lvl_nodes, w.bbox, w.node_box, level, L.max_nodes);
+                           w.node_m64, w.node_level, w.lvl, w.lvl_nodes, w.bbox, level, L.max_nodes);
 }
 
 // ------------------------------------------------------------------------------------------------

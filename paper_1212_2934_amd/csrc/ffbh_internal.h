@@ -66,7 +66,7 @@ struct Workspace {
     NodeRec *nodes;          // max_nodes
     int32_t *node_level;     // max_nodes: cell level (side = side_root / 2^level)
     double *node_m64;        // 4 x max_nodes: moment sum FP64 (x, y, z, pad) per node
-    double *node_box;        // 8 x max_nodes: member bounding box (lo xyz, pad, hi xyz, pad)
+    uint32_t *cell_first;    // short-range grid: first sorted particle of each cell (B x cell_T)
     double *ones;            // B: constant 1.0 (dL/dE for the MD force)
     uint32_t *arrive;        // max_nodes: (unused) arrival counters
     uint32_t *lvl;           // 128: per-level node counts [0,22), bucket starts [32,55), cursors [64,86)
@@ -89,6 +89,8 @@ constexpr int kBboxBlocks = 64;
 
 struct Layout {
     int64_t n, B, ntot, max_nodes, tiles, num_waves, hist_len, bin_int;
+    int cell_lcap;       // finest level of the short-range cell grid
+    int64_t cell_T;      // grid entries per system, 2^(3 cell_lcap)
     size_t bytes;
 };
 
@@ -121,6 +123,18 @@ __host__ __device__ inline uint64_t spread3(uint32_t v)
     x = (x | (x << 4)) & 0x10c30c30c30c30c3ull;
     x = (x | (x << 2)) & 0x1249249249249249ull;
     return x;
+}
+
+// Inverse of spread3: gather bits 0, 3, 6, ... of x into the low 21 bits.
+__host__ __device__ inline uint32_t compact3(uint64_t x)
+{
+    x &= 0x1249249249249249ull;
+    x = (x ^ (x >> 2)) & 0x10c30c30c30c30c3ull;
+    x = (x ^ (x >> 4)) & 0x100f00f00f00f00full;
+    x = (x ^ (x >> 8)) & 0x001f0000ff0000ffull;
+    x = (x ^ (x >> 16)) & 0x001f00000000ffffull;
+    x = (x ^ (x >> 32)) & 0x1fffffull;
+    return (uint32_t)x;
 }
 
 __host__ __device__ inline uint64_t morton(uint32_t qx, uint32_t qy, uint32_t qz)

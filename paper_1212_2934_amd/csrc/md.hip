@@ -1,8 +1,8 @@
 // One Langevin MD step (Sec. 2 equations of motion in vector form, integrated with the explicit
 // Euler-Maruyama scheme of Sec. 4; Sec. 3.2 kernel 6): tree build, Barnes-Hut field and energy gradient
-// (fused forward + adjoint), a WCA short-range repulsion between particles and against the container
-// walls found by a tree range query, and the update of positions, velocities, moments and angular
-// velocities from the state at the start of the step.
+// (fused forward + adjoint), a WCA short-range repulsion between particles (partners from a cell grid cut
+// from the build's Morton codes) and against the container walls, and the update of positions,
+// velocities, moments and angular velocities from the state at the start of the step.
 //
 // Readings: the paper writes the rotation in polar angles (with the theta/phi equations garbled); the
 // vector form used here is m' = R(omega dt) m with I domega/dt = m x H_eff - gamma_r omega + noise,
@@ -92,84 +92,81 @@ __device__ inline double wall_force(double dlo, double dhi, double sw, double ep
     return f;
 }
 
-__global__ __launch_bounds__(256) void k_wca(const NodeRec *__restrict__ nodes, const double *__restrict__ node_box,
-                                             const double *__restrict__ spos, const uint32_t *__restrict__ perm,
-                                             double *__restrict__ F, uint32_t *__restrict__ status, int64_t n,
-                                             int64_t ntot, int waves_per_seg, int num_waves, int max_nodes,
-                                             double sigma, double eps, double3 box_lo, double3 box_hi)
+// Short-range partners are found on a cell grid cut from the Morton codes of the tree build: the level-L
+// cell of a particle is the top 3L bits of its code, so the members of a cell are contiguous in the
+// sorted order.  L is the finest level (at most the grid's cap) whose cells are at least the cut-off wide
+// after allowing one quantisation step, so every partner within the cut-off lies in the 27 cells around a
+// particle's own.
+__device__ inline int grid_level(double side, double rc, int lcap)
 {
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wpb = blockDim.x / kWave;
-    const int gw = xcd_block(blockIdx.x, gridDim.x) * wpb + (int)(threadIdx.x / kWave);
-    if (gw >= num_waves) return;
-    const int seg = gw / waves_per_seg;
-    const int local = (gw - seg * waves_per_seg) * kWave + lane;
-    const bool valid = local < n;
-    const int si = (int)(seg * n) + (valid ? local : 0);
-    const double rx = spos[si], ry = spos[ntot + si], rz = spos[2 * ntot + si];
+    int L = lcap;
+    while (L > 0 && side * (__builtin_ldexp(1.0, -L) - __builtin_ldexp(1.0, -kBits)) <= rc) --L;
+    return L;
+}
+
+// First sorted particle of every occupied cell.  Entries of cells that are empty in this build are left
+// as they are: a reader accepts an entry only if that particle's cell is the one it looks up, which holds
+// exactly for the entries written here.
+__global__ __launch_bounds__(256) void k_cell_fill(const uint64_t *__restrict__ codes, const double *__restrict__ bbox,
+                                                   int64_t n, int64_t ntot, double rc, int lcap, int64_t T,
+                                                   uint32_t *__restrict__ cell_first)
+{
+    const int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (o >= ntot) return;
+    const int64_t b = o / n, s = o - b * n;
+    const int shift = 3 * (kBits - grid_level(bbox[8 * b + 3], rc, lcap));
+    const uint64_t c = codes[o] >> shift;
+    if (s == 0 || (codes[o - 1] >> shift) != c) cell_first[b * T + (int64_t)c] = (uint32_t)o;
+}
+
+// WCA forces on every particle (one thread per sorted particle): partners from the 27 surrounding cells,
+// then the container walls; written in the caller's order.
+__global__ __launch_bounds__(256) void k_wca(const uint64_t *__restrict__ codes, const double *__restrict__ bbox,
+                                             const uint32_t *__restrict__ cell_first, const double *__restrict__ spos,
+                                             const uint32_t *__restrict__ perm, double *__restrict__ F, int64_t n,
+                                             int64_t ntot, int lcap, int64_t T, double sigma, double eps,
+                                             double3 box_lo, double3 box_hi)
+{
+    const int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (o >= ntot) return;
+    const int64_t b = o / n, lo_i = b * n, hi_i = lo_i + n;
+    const double rx = spos[o], ry = spos[ntot + o], rz = spos[2 * ntot + o];
     const double rc = 1.122462048309373 * sigma, rc2 = rc * rc, s2 = sigma * sigma;
     double fx = 0.0, fy = 0.0, fz = 0.0;
-
-    LaneStack st;
-    st.init(seg, 1, ballot(valid));
-    int guard = max_nodes;
-    while (st.more() && eps > 0.0) {
-        uint64_t mask;
-        const int cur = st.pop(mask);
-        if (--guard < 0 || (unsigned)cur >= (unsigned)max_nodes) {
-            if (lane == 0) set_flag(status, BH_FLAG_TREE);
-            break;
-        }
-        // the record and the member box are read together (cur is in range)
-        const NodeRec nd = nodes[cur];
-        const double *bx = node_box + 8 * (int64_t)cur;
-        const double lox = bx[0], loy = bx[1], loz = bx[2], hix = bx[4], hiy = bx[5], hiz = bx[6];
-        if (nd.first < 0 || nd.count < 1 || (uint32_t)nd.first + (uint32_t)nd.count > (uint32_t)ntot) {
-            if (lane == 0) set_flag(status, BH_FLAG_TREE);
-            break;
-        }
-        // squared distance from the target to the members' bounding box
-        const double ex = fmax(fmax(lox - rx, rx - hix), 0.0);
-        const double ey = fmax(fmax(loy - ry, ry - hiy), 0.0);
-        const double ez = fmax(fmax(loz - rz, rz - hiz), 0.0);
-        const uint64_t open = mask & ballot(ex * ex + ey * ey + ez * ez < rc2);
-        if (open == 0ull) continue;
-        if (nd.nchild != 0) {
-            if (st.sp >= kStackMax) {
-                if (lane == 0) set_flag(status, BH_FLAG_STACK);
-                break;
-            }
-            st.push(lane, nd.child, nd.nchild, open);
-            continue;
-        }
-        // leaf: members in chunks of 64, one per lane (one vector load per coordinate), then broadcast to
-        // the wave one at a time; the pair force is evaluated only when some lane is within the cut-off
-        const bool me = lane_in(open);
-        for (int c0 = 0; c0 < nd.count; c0 += kWave) {
-            const int cn = min(kWave, nd.count - c0);
-            const int kl = nd.first + c0 + (lane < cn ? lane : 0);
-            const double qx = spos[kl], qy = spos[ntot + kl], qz = spos[2 * ntot + kl];
-            for (int j = 0; j < cn; ++j) {
-                const double x = rx - readlane_d(qx, j), y = ry - readlane_d(qy, j), z = rz - readlane_d(qz, j);
-                const double r2 = x * x + y * y + z * z;
-                const bool near = me && nd.first + c0 + j != si && r2 < rc2 && r2 > 0.0;
-                if (ballot(near) == 0ull) continue;
-                if (near) wca_pair(x, y, z, s2, eps, rc2, fx, fy, fz);
-            }
-        }
-    }
-    if (!valid) return;
-    // container walls
-    const double sw = 0.5 * sigma;
     if (eps > 0.0) {
+        const int L = grid_level(bbox[8 * b + 3], rc, lcap);
+        const int shift = 3 * (kBits - L), down = kBits - L;
+        const uint64_t code = codes[o];
+        const int cx = (int)(compact3(code >> 2) >> down), cy = (int)(compact3(code >> 1) >> down),
+                  cz = (int)(compact3(code) >> down);
+        const int cmax = (1 << L) - 1;
+        const uint32_t *tab = cell_first + b * T;
+        for (int nx = cx - 1; nx <= cx + 1; ++nx) {
+            if (nx < 0 || nx > cmax) continue;
+            for (int ny = cy - 1; ny <= cy + 1; ++ny) {
+                if (ny < 0 || ny > cmax) continue;
+                for (int nz = cz - 1; nz <= cz + 1; ++nz) {
+                    if (nz < 0 || nz > cmax) continue;
+                    const uint64_t c = morton((uint32_t)nx, (uint32_t)ny, (uint32_t)nz);
+                    int64_t j = tab[c];
+                    if (j < lo_i || j >= hi_i || (codes[j] >> shift) != c) continue;
+                    for (; j < hi_i && (codes[j] >> shift) == c; ++j) {
+                        if (j == o) continue;
+                        wca_pair(rx - spos[j], ry - spos[ntot + j], rz - spos[2 * ntot + j], s2, eps, rc2, fx, fy,
+                                 fz);
+                    }
+                }
+            }
+        }
+        // container walls
+        const double sw = 0.5 * sigma;
         fx += wall_force(rx - box_lo.x, box_hi.x - rx, sw, eps);
         fy += wall_force(ry - box_lo.y, box_hi.y - ry, sw, eps);
         fz += wall_force(rz - box_lo.z, box_hi.z - rz, sw, eps);
     }
-    const int64_t o = perm[si];
-    const int64_t i = o - (int64_t)seg * n;
+    const int64_t i = (int64_t)perm[o] - lo_i;
     if (i < 0 || i >= n) return;
-    double *out = F + (int64_t)seg * 3 * n;
+    double *out = F + b * 3 * n;
     out[i] = fx;
     out[n + i] = fy;
     out[2 * n + i] = fz;
@@ -250,12 +247,12 @@ hipError_t launch_md(Handle &h, const md_state *st, const md_params *mp, hipStre
     if (e != hipSuccess) return e;
     e = launch_backward(h, st->mom, mp->d_hext, nullptr, w.ones, w.md_grad_r, w.md_grad_m, nullptr, s);
     if (e != hipSuccess) return e;
-    const int wpb = h.waves_per_block;
-    const unsigned blocks = (unsigned)((L.num_waves + wpb - 1) / wpb);
-    const int waves_per_seg = (int)((L.n + kWave - 1) / kWave);
-    hipLaunchKernelGGL(k_wca, dim3(blocks), dim3(wpb * kWave), 0, s, w.nodes, w.node_box, w.spos, w.perm, w.md_force,
-                       w.status, L.n, L.ntot, waves_per_seg, (int)L.num_waves, (int)L.max_nodes, mp->wca_sigma,
-                       mp->wca_eps, make_double3(mp->box_lo[0], mp->box_lo[1], mp->box_lo[2]),
+    const double rc = 1.122462048309373 * mp->wca_sigma;
+    hipLaunchKernelGGL(k_cell_fill, dim3(grid_for(L.ntot, 256)), dim3(256), 0, s, w.codes, w.bbox, L.n, L.ntot, rc,
+                       L.cell_lcap, L.cell_T, w.cell_first);
+    hipLaunchKernelGGL(k_wca, dim3(grid_for(L.ntot, 256)), dim3(256), 0, s, w.codes, w.bbox, w.cell_first, w.spos,
+                       w.perm, w.md_force, L.n, L.ntot, L.cell_lcap, L.cell_T, mp->wca_sigma, mp->wca_eps,
+                       make_double3(mp->box_lo[0], mp->box_lo[1], mp->box_lo[2]),
                        make_double3(mp->box_hi[0], mp->box_hi[1], mp->box_hi[2]));
     MDConst c{mp->dt, mp->kT, mp->gamma_t, mp->gamma_r, mp->mass, mp->inertia, mp->seed};
     hipLaunchKernelGGL(k_integrate, dim3(grid_for(L.ntot, 256)), dim3(256), 0, s, st->pos, st->vel, st->mom,

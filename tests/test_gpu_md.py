@@ -62,6 +62,41 @@ def test_trajectory_matches_reference(precision, tol):
         assert err <= tol, (key, err)
 
 
+@pytest.mark.parametrize("batch", [1, 3])
+def test_chain_contacts_short_range_forces(batch):
+    """Chains (spacing 1.05 d) put every bead's neighbours inside the WCA cut-off (2^(1/6) d), and the
+    walls touch the outermost beads: two FP64 steps against the reference integrator, whose WCA term is a
+    brute-force sum over all pairs.  Three realisations in a batch exercise per-system grids of different
+    levels (box sides 16, 30 and 60)."""
+    rng = np.random.default_rng(31)
+    sides = [16.0, 30.0, 60.0][:batch] if batch > 1 else [30.0]
+    n = 900
+    pos, mom = [], []
+    for side in sides:
+        p_, m_ = workloads.rsa_chains(rng, n, (0.0, 0.0, 0.0), (side, side, side))
+        pos.append(p_)
+        mom.append(m_)
+    st = dict(pos=np.stack(pos), vel=rng.standard_normal((batch, 3, n)), mom=np.stack(mom),
+              omega=rng.standard_normal((batch, 3, n)))
+    side = max(sides)
+    p = _params(side)
+    p["hext"] = np.tile(p["hext"], (batch, 1))
+    p["box_hi"] = (side, side, side)
+    bh = BarnesHut(n, batch, 16, 0.5, "fp64")
+    d = _to_dev(st)
+    he = torch.from_numpy(p["hext"]).cuda()
+    mp = _mdp(p, he)
+    ref = st
+    for k in range(2):
+        bh.md_step(d, mp)
+        ref = omd.md_step(ref, p, k, theta=0.5, leaf=16)
+    assert bh.check_status() == 0
+    for key in ("pos", "vel", "mom", "omega"):
+        g = d[key].cpu().numpy()
+        err = np.abs(g - ref[key]).max() / np.abs(ref[key]).max()
+        assert err <= 1e-11, (key, err)
+
+
 def test_resume_continues_the_same_trajectory():
     w = workloads.uniform_cube(2000, 24.0, seed=6)
     rng = np.random.default_rng(7)
