@@ -99,12 +99,15 @@ __device__ inline void adj_leaf(AdjLds<T> &W, int lane, const Src *__restrict__ 
                 if (tok && b < 6) lds_add(&W.acc[tl][b], o0);  // lane b < 6 holds slot b
             }
         }
-        // dL/dr_k -= sum g, dL/dm_k += sum T(x) a over the listed targets
-        s0 = stride_sum<G>(s0); s1 = stride_sum<G>(s1); s2 = stride_sum<G>(s2);
-        s3 = stride_sum<G>(s3); s4 = stride_sum<G>(s4); s5 = stride_sum<G>(s5);
-        if (lane < cn) {
-            W.sbuf[lane][0] = s0; W.sbuf[lane][1] = s1; W.sbuf[lane][2] = s2;
-            W.sbuf[lane][3] = s3; W.sbuf[lane][4] = s4; W.sbuf[lane][5] = s5;
+        // dL/dr_k -= sum g, dL/dm_k += sum T(x) a over the listed targets: the row swaps move two of the six
+        // values each (rows 0..3 of x0 carry components 0, 2, 1, 3 and rows 0, 1 / 2, 3 of x1 carry 4 / 5),
+        // then lanes of equal member index inside a row are added
+        const T w0 = swap32_pair(s0, s1), w1 = swap32_pair(s2, s3), w2 = swap32_pair(s4, s5);
+        const T x0 = row_stride_sum<G>(swap16_pair(w0, w1)), x1 = row_stride_sum<G>(swap16_sum(w2));
+        const int row = lane >> 4, p = lane & 15;
+        if (p < cn) {
+            W.sbuf[p][row == 0 ? 0 : row == 1 ? 2 : row == 2 ? 1 : 3] = x0;
+            if ((row & 1) == 0) W.sbuf[p][4 + (row >> 1)] = x1;
         }
         wave_lds_sync();
         for (int base = 0; base < 6 * cn; base += kWave) {

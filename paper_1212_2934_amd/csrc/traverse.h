@@ -329,15 +329,14 @@ __device__ inline void group_sum6(int lane, T v0, T v1, T v2, T v3, T v4, T v5, 
     }
 }
 
-// Sum over the lanes of equal (lane mod G), returned in every lane: rotations inside the row, then the
-// row swaps.
+// Sum over the lanes of a row with equal (lane mod G), returned in every lane of the row: rotations
+// inside the row.
 template <int G, typename T>
-__device__ inline T stride_sum(T v)
+__device__ inline T row_stride_sum(T v)
 {
     if constexpr (G == 4) v += dpp_t<0x124>(v);  // row_ror 4
     if constexpr (G <= 8) v += dpp_t<0x128>(v);  // row_ror 8
-    v = swap16_sum(v);
-    return swap32_sum(v);
+    return v;
 }
 
 // Lane mask of a lane condition (the condition is already a mask; no conversion through an integer).
