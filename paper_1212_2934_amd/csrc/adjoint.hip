@@ -694,12 +694,14 @@ __global__ __launch_bounds__(1024) void k_dhext(const double *__restrict__ mom, 
 
 hipError_t launch_backward(Handle &h, const double *d_mom, const double *d_hext, const double *d_gH,
                            const double *d_gE, double *d_dpos, double *d_dmom, double *d_dhext, hipStream_t s,
-                           double *d_H, double *d_E)
+                           double *d_H, double *d_E, bool moments_done)
 {
     const Layout &L = h.L;
     Workspace &w = h.w;
-    hipError_t e = launch_upward_moments(h, d_mom, s);  // pseudo-particle moments
-    if (e != hipSuccess) return e;
+    if (!moments_done) {
+        hipError_t e = launch_upward_moments(h, d_mom, s);  // pseudo-particle moments
+        if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(k_hbar, dim3(grid_for(L.ntot, 256)), dim3(256), 0, s, d_gH, d_gE, w.smom, w.perm, L.n,
                        L.ntot, w.hbar);
     hipLaunchKernelGGL(k_zero, dim3(grid_for(8 * L.max_nodes, 256, 4096)), dim3(256), 0, s, w.node_adj,

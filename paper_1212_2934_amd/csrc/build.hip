@@ -623,8 +623,12 @@ __global__ void k_zero_u32(uint32_t *a, int len)
     for (int i = threadIdx.x; i < len; i += blockDim.x) a[i] = 0u;
 }
 
+// MODE 0: member positions -> centroids and s^2; MODE 1: member moments -> FP64 and FP32 moment sums;
+// MODE 2: both in one pass (vals = positions, vals2 = moments).  Child sums are read from `sums` (8 doubles
+// per node: position sums at 0..2, moment sums at 4..6).
 template <int MODE>
-__global__ __launch_bounds__(256) void k_upward_level(const double *__restrict__ vals, int64_t ntot, int64_t n,
+__global__ __launch_bounds__(256) void k_upward_level(const double *__restrict__ vals,
+                                                      const double *__restrict__ vals2, int64_t ntot, int64_t n,
                                                       NodeRec *__restrict__ nodes, double *__restrict__ sums,
                                                       double *__restrict__ node_m64,
                                                       const int32_t *__restrict__ node_level,
@@ -642,50 +646,70 @@ __global__ __launch_bounds__(256) void k_upward_level(const double *__restrict__
         if (nd.first < 0 || nd.count < 1 || (int64_t)nd.first + nd.count > ntot ||
             (nd.nchild != 0 && (nd.child < 0 || (int64_t)nd.child + nd.nchild > max_nodes)))
             continue;
-        double sx = 0.0, sy = 0.0, sz = 0.0;
+        const int o = MODE == 1 ? 4 : 0;  // slot of the (first) sum
+        double sx = 0.0, sy = 0.0, sz = 0.0, mx = 0.0, my = 0.0, mz = 0.0;
         if (nd.nchild == 0) {
             for (int k = nd.first; k < nd.first + nd.count; ++k) {
                 sx = sx + vals[k];
                 sy = sy + vals[ntot + k];
                 sz = sz + vals[2 * ntot + k];
+                if (MODE == 2) {
+                    mx = mx + vals2[k];
+                    my = my + vals2[ntot + k];
+                    mz = mz + vals2[2 * ntot + k];
+                }
             }
         } else {
             for (int c = nd.child; c < nd.child + nd.nchild; ++c) {
-                sx = sx + sums[4 * c];
-                sy = sy + sums[4 * c + 1];
-                sz = sz + sums[4 * c + 2];
+                sx = sx + sums[8 * c + o];
+                sy = sy + sums[8 * c + o + 1];
+                sz = sz + sums[8 * c + o + 2];
+                if (MODE == 2) {
+                    mx = mx + sums[8 * c + 4];
+                    my = my + sums[8 * c + 5];
+                    mz = mz + sums[8 * c + 6];
+                }
             }
         }
-        sums[4 * id] = sx;
-        sums[4 * id + 1] = sy;
-        sums[4 * id + 2] = sz;
-        if (MODE == 0) {
+        if (MODE == 1) {
+            mx = sx; my = sy; mz = sz;
+        }
+        sums[8 * id + o] = sx;
+        sums[8 * id + o + 1] = sy;
+        sums[8 * id + o + 2] = sz;
+        if (MODE == 2) {
+            sums[8 * id + 4] = mx;
+            sums[8 * id + 5] = my;
+            sums[8 * id + 6] = mz;
+        }
+        if (MODE != 1) {
             const double cnt = (double)nd.count;
             nodes[id].cx = sx / cnt;
             nodes[id].cy = sy / cnt;
             nodes[id].cz = sz / cnt;
             const double side = __builtin_ldexp(bbox[8 * (nd.first / n) + 3], -node_level[id]);
             nodes[id].s2 = side * side;
-        } else {
-            node_m64[4 * id] = sx;
-            node_m64[4 * id + 1] = sy;
-            node_m64[4 * id + 2] = sz;
-            nodes[id].mx = (float)sx;
-            nodes[id].my = (float)sy;
-            nodes[id].mz = (float)sz;
+        }
+        if (MODE != 0) {
+            node_m64[4 * id] = mx;
+            node_m64[4 * id + 1] = my;
+            node_m64[4 * id + 2] = mz;
+            nodes[id].mx = (float)mx;
+            nodes[id].my = (float)my;
+            nodes[id].mz = (float)mz;
         }
     }
 }
 
 template <int MODE>
-static void upward(Handle &h, const double *vals, hipStream_t s)
+static void upward(Handle &h, const double *vals, const double *vals2, hipStream_t s)
 {
     const Layout &L = h.L;
     Workspace &w = h.w;
     const unsigned g = grid_for(L.max_nodes, 256, 512);
     for (int level = kMaxLevel; level >= 0; --level)
-        hipLaunchKernelGGL(k_upward_level<MODE>, dim3(g), dim3(256), 0, s, vals, L.ntot, L.n, w.nodes, w.node_adj,
-                           w.node_m64, w.node_level, w.lvl, w.lvl_nodes, w.bbox, level, L.max_nodes);
+        hipLaunchKernelGGL(k_upward_level<MODE>, dim3(g), dim3(256), 0, s, vals, vals2, L.ntot, L.n, w.nodes,
+                           w.node_adj, w.node_m64, w.node_level, w.lvl, w.lvl_nodes, w.bbox, level, L.max_nodes);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -698,7 +722,9 @@ static void upward(Handle &h, const double *vals, hipStream_t s)
         if (e_ != hipSuccess) return e_;    \
     } while (0)
 
-hipError_t launch_build(Handle &h, const double *d_pos, hipStream_t s)
+static void gather_moments(Handle &h, const double *d_mom, hipStream_t s);
+
+hipError_t launch_build(Handle &h, const double *d_pos, hipStream_t s, const double *d_mom)
 {
     const Layout &L = h.L;
     Workspace &w = h.w;
@@ -746,7 +772,13 @@ hipError_t launch_build(Handle &h, const double *d_pos, hipStream_t s)
     hipLaunchKernelGGL(k_level_starts, dim3(1), dim3(64), 0, s, w.lvl);
     hipLaunchKernelGGL(k_level_scatter, dim3(grid_for(L.max_nodes, 256)), dim3(256), 0, s, w.node_level,
                        w.status + 2, L.max_nodes, w.lvl, w.lvl_nodes);
-    upward<0>(h, w.spos, s);
+    if (d_mom) {
+        // positions and moments summed in one upward pass
+        gather_moments(h, d_mom, s);
+        upward<2>(h, w.spos, w.smom, s);
+    } else {
+        upward<0>(h, w.spos, nullptr, s);
+    }
     return hipGetLastError();
 }
 
@@ -770,7 +802,8 @@ __global__ __launch_bounds__(256) void k_pack_sources(const double *__restrict__
     f[0] = (float)mx; f[1] = (float)my; f[2] = (float)mz; f[3] = 0.0f;
 }
 
-hipError_t launch_upward_moments(Handle &h, const double *d_mom, hipStream_t s)
+// Moments in sorted order (FP64 and FP32) and the packed source records.
+static void gather_moments(Handle &h, const double *d_mom, hipStream_t s)
 {
     const Layout &L = h.L;
     Workspace &w = h.w;
@@ -778,7 +811,12 @@ hipError_t launch_upward_moments(Handle &h, const double *d_mom, hipStream_t s)
                        L.ntot, w.smom, w.smom32, w.status);
     hipLaunchKernelGGL(k_pack_sources, dim3(grid_for(L.ntot, 256)), dim3(256), 0, s, w.spos, w.smom, L.ntot,
                        (double *)w.src64, (double *)w.src32);
-    upward<1>(h, w.smom, s);
+}
+
+hipError_t launch_upward_moments(Handle &h, const double *d_mom, hipStream_t s)
+{
+    gather_moments(h, d_mom, s);
+    upward<1>(h, h.w.smom, nullptr, s);
     return hipGetLastError();
 }
 

@@ -156,13 +156,15 @@ inline unsigned grid_for(int64_t work, int threads, int64_t cap = (int64_t)1 << 
 }
 
 // Launch helpers implemented per source file.
-hipError_t launch_build(Handle &h, const double *d_pos, hipStream_t s);
+// Tree build; with d_mom the moments are gathered and summed in the same upward pass (the MD step).
+hipError_t launch_build(Handle &h, const double *d_pos, hipStream_t s, const double *d_mom = nullptr);
 hipError_t launch_upward_moments(Handle &h, const double *d_mom, hipStream_t s);
 hipError_t launch_field(Handle &h, const double *d_mom, const double *d_hext, double *d_H,
                         double *d_E, hipStream_t s);
+// moments_done: the build already summed the moments (launch_build with d_mom).
 hipError_t launch_backward(Handle &h, const double *d_mom, const double *d_hext, const double *d_gH,
                            const double *d_gE, double *d_dpos, double *d_dmom, double *d_dhext,
-                           hipStream_t s, double *d_H = nullptr, double *d_E = nullptr);
+                           hipStream_t s, double *d_H = nullptr, double *d_E = nullptr, bool moments_done = false);
 void launch_energy_final(Handle &h, double *d_E, hipStream_t s, int targets_per_wave);
 hipError_t launch_md(Handle &h, const md_state *st, const md_params *mp, hipStream_t s);
 

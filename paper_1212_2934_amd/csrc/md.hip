@@ -104,6 +104,17 @@ __device__ inline int grid_level(double side, double rc, int lcap)
     return L;
 }
 
+// Spread the low 10 bits of v so that bit k moves to bit 3k (grid coordinates have at most 7 bits).
+__device__ inline uint32_t spread3_small(uint32_t v)
+{
+    uint32_t x = v & 0x3ffu;
+    x = (x | (x << 16)) & 0x030000ffu;
+    x = (x | (x << 8)) & 0x0300f00fu;
+    x = (x | (x << 4)) & 0x030c30c3u;
+    x = (x | (x << 2)) & 0x09249249u;
+    return x;
+}
+
 // First sorted particle of every occupied cell.  Entries of cells that are empty in this build are left
 // as they are: a reader accepts an entry only if that particle's cell is the one it looks up, which holds
 // exactly for the entries written here.
@@ -141,20 +152,27 @@ __global__ __launch_bounds__(256) void k_wca(const uint64_t *__restrict__ codes,
                   cz = (int)(compact3(code) >> down);
         const int cmax = (1 << L) - 1;
         const uint32_t *tab = cell_first + b * T;
-        for (int nx = cx - 1; nx <= cx + 1; ++nx) {
-            if (nx < 0 || nx > cmax) continue;
-            for (int ny = cy - 1; ny <= cy + 1; ++ny) {
-                if (ny < 0 || ny > cmax) continue;
-                for (int nz = cz - 1; nz <= cz + 1; ++nz) {
-                    if (nz < 0 || nz > cmax) continue;
-                    const uint64_t c = morton((uint32_t)nx, (uint32_t)ny, (uint32_t)nz);
-                    int64_t j = tab[c];
-                    if (j < lo_i || j >= hi_i || (codes[j] >> shift) != c) continue;
-                    for (; j < hi_i && (codes[j] >> shift) == c; ++j) {
-                        if (j == o) continue;
-                        wca_pair(rx - spos[j], ry - spos[ntot + j], rz - spos[2 * ntot + j], s2, eps, rc2, fx, fy,
-                                 fz);
-                    }
+        // per slab of nine cells, the table entries are read before any member, so their loads overlap
+        for (int dz = -1; dz <= 1; ++dz) {
+            const int nz = cz + dz;
+            if ((unsigned)nz > (unsigned)cmax) continue;
+            uint32_t cell[9], first[9];
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                const int nx = cx + k % 3 - 1, ny = cy + k / 3 - 1;
+                const bool in = (unsigned)nx <= (unsigned)cmax && (unsigned)ny <= (unsigned)cmax;
+                cell[k] = in ? (spread3_small((uint32_t)nx) << 2) | (spread3_small((uint32_t)ny) << 1) |
+                                   spread3_small((uint32_t)nz)
+                             : 0xffffffffu;
+                first[k] = in ? tab[cell[k]] : 0xffffffffu;
+            }
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                const uint64_t c = cell[k];
+                for (int64_t j = first[k]; j >= lo_i && j < hi_i && (codes[j] >> shift) == c; ++j) {
+                    if (j == o) continue;
+                    wca_pair(rx - spos[j], ry - spos[ntot + j], rz - spos[2 * ntot + j], s2, eps, rc2, fx, fy,
+                             fz);
                 }
             }
         }
@@ -243,9 +261,10 @@ hipError_t launch_md(Handle &h, const md_state *st, const md_params *mp, hipStre
 {
     const Layout &L = h.L;
     Workspace &w = h.w;
-    hipError_t e = launch_build(h, st->pos, s);
+    hipError_t e = launch_build(h, st->pos, s, st->mom);  // tree, centroids and moment sums
     if (e != hipSuccess) return e;
-    e = launch_backward(h, st->mom, mp->d_hext, nullptr, w.ones, w.md_grad_r, w.md_grad_m, nullptr, s);
+    e = launch_backward(h, st->mom, mp->d_hext, nullptr, w.ones, w.md_grad_r, w.md_grad_m, nullptr, s, nullptr,
+                        nullptr, true);
     if (e != hipSuccess) return e;
     const double rc = 1.122462048309373 * mp->wca_sigma;
     hipLaunchKernelGGL(k_cell_fill, dim3(grid_for(L.ntot, 256)), dim3(256), 0, s, w.codes, w.bbox, L.n, L.ntot, rc,
