@@ -88,6 +88,57 @@ class HipEvents:
             self.hip.hipEventDestroy(e)
 
 
+def table1(args, workloads, BarnesHut, allpairs, md_params):
+    """Per-step time of the all-pairs and Barnes-Hut paths for N = 10^3 .. 10^6 (the shape of the paper's
+    Table 1): random sequential addition at volume fraction 0.1 in a cube, theta 0.5, leaf 16.  AP step =
+    all-pairs field and energy gradient (one kernel); BH step = md_step (build, field, adjoint, WCA,
+    integrator); field = all-pairs field alone vs bh_build + bh_field."""
+    import ctypes
+    import math
+    import numpy as np
+    import torch
+    dev = torch.device("cuda", 0)
+    C3 = ctypes.c_double * 3
+    print("| N | AP field FP32-mixed ms | AP field FP64 ms | AP step FP32-mixed ms | AP step FP64 ms | "
+          "BH field FP32-mixed ms | BH field FP64 ms | BH step FP32-mixed ms | BH step FP64 ms | "
+          "AP/BH step FP32-mixed |")
+    print("|---|---|---|---|---|---|---|---|---|---|")
+    for n in (1000, 10000, 100000, 1000000):
+        side = (n * math.pi / 6.0 / 0.1) ** (1.0 / 3.0)
+        w = workloads.cached(f"uniform_phi0.1_n{n}_seed{3000 + n}",
+                             lambda: workloads.uniform_cube(n, side, seed=3000 + n))
+        pos = torch.from_numpy(w.pos).to(dev)
+        mom = torch.from_numpy(w.mom).to(dev)
+        reps = 3 if n >= 100000 else 20
+
+        def timed(fn):
+            fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                fn()
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t0) / reps * 1e3
+
+        row = {}
+        for p in ("fp32_mixed", "fp64"):
+            row["apf", p] = timed(lambda: allpairs(pos, mom, precision=p))
+            row["aps", p] = timed(lambda: allpairs(pos, mom, precision=p, want_dEdr=True))
+            bh = BarnesHut(n, 1, 16, 0.5, p)
+            row["bhf", p] = timed(lambda: (bh.build(pos), bh.field(mom)))
+            st = {"pos": pos.clone(), "vel": torch.zeros_like(pos), "mom": mom.clone(),
+                  "omega": torch.zeros_like(pos), "step": torch.zeros(1, dtype=torch.int64, device=dev)}
+            mdp = md_params(1e-3, 1.0, 0.1, 0.1, 1.0, 0.1, 1.0, 1.0, C3(0.0, 0.0, 0.0), C3(side, side, side),
+                            None, 7)
+            row["bhs", p] = timed(lambda: bh.md_step(st, mdp))
+            assert bh.check_status() == 0
+            del bh
+        f = lambda k, p: f"{row[k, p]:.3f}"
+        print(f"| {n} | {f('apf', 'fp32_mixed')} | {f('apf', 'fp64')} | {f('aps', 'fp32_mixed')} | "
+              f"{f('aps', 'fp64')} | {f('bhf', 'fp32_mixed')} | {f('bhf', 'fp64')} | {f('bhs', 'fp32_mixed')} | "
+              f"{f('bhs', 'fp64')} | {row['aps', 'fp32_mixed'] / row['bhs', 'fp32_mixed']:.2f} |", flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -96,6 +147,8 @@ def main():
     ap.add_argument("--theta", type=float, default=0.5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-slab", action="store_true")
+    ap.add_argument("--table1", action="store_true",
+                    help="print the all-pairs vs Barnes-Hut per-step sweep over N (the paper's Table 1) and exit")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="finish with one plain device copy of MIB MiB (a reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -110,7 +163,11 @@ def main():
     from paper_1212_2934_amd import workloads
     import ctypes
 
-    from paper_1212_2934_amd.binding import BarnesHut, md_params
+    from paper_1212_2934_amd.binding import BarnesHut, allpairs, md_params
+
+    if args.table1:
+        table1(args, workloads, BarnesHut, allpairs, md_params)
+        return
 
     log("generating workload (2^20 chains, phi 0.1)")
     w = workloads.cached("chains_n1048576_seed1003", lambda: workloads.config3())
@@ -144,7 +201,7 @@ def main():
     C3 = ctypes.c_double * 3
     mdp = md_params(1e-3, 1.0, 0.1, 0.1, 1.0, 0.1, 1.0, 1.0, C3(0.0, 0.0, 0.0), C3(side, side, side), None, 2003)
 
-    res = {}
+    res, H_bh = {}, {}
     for precision in ("fp32_mixed", "fp64"):
         bh = make(precision)
         ev = HipEvents(4)
@@ -205,6 +262,7 @@ def main():
             t_fwd += ev.seconds(0, 1)
         assert bh.check_status() == 0
         bh.set_raw_timing_events(None)
+        H_bh[precision] = field_only()[0].clone()
         res[precision] = dict(t_step=t_step, t_step_eager=t_step_eager, t_eval=t_eval, t_fwd_kernel=t_fwd / args.steps,
                               t_adj_kernel=t_adj / args.steps)
         log(f"{precision}: md step (graph) {t_step * 1e3:.3f} ms, eager {t_step_eager * 1e3:.3f} ms, field eval {t_eval * 1e3:.3f} ms, forward traversal "
@@ -212,6 +270,29 @@ def main():
             f"{res[precision]['t_adj_kernel'] * 1e3:.3f} ms")
         del bh
     torch.cuda.synchronize()
+
+    # all-pairs reference on the same state: its time, and the Barnes-Hut field error against it
+    ap_ms, H_ap = {}, {}
+    for precision in ("fp32_mixed", "fp64"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        H_ap[precision] = allpairs(pos, mom, precision=precision)[0]
+        torch.cuda.synchronize()
+        ap_ms[precision] = (time.perf_counter() - t0) * 1e3
+        log(f"all-pairs {precision}: {ap_ms[precision]:.1f} ms per field evaluation")
+
+    def rel_err(H, ref):
+        d = torch.linalg.vector_norm(H - ref, dim=0)
+        r = torch.linalg.vector_norm(ref, dim=0)
+        per = d / torch.clamp(r, min=1e-3 * torch.sqrt(torch.mean(r * r)))
+        return {"rel_l2": (torch.linalg.vector_norm(H - ref) / torch.linalg.vector_norm(ref)).item(),
+                "p999": torch.quantile(per[torch.randperm(per.numel(), device=per.device)[:1 << 16]], 0.999).item()}
+
+    ap_err = {"bh_fp32_mixed": rel_err(H_bh["fp32_mixed"], H_ap["fp64"]),
+              "bh_fp64": rel_err(H_bh["fp64"], H_ap["fp64"]),
+              "allpairs_fp32_mixed": rel_err(H_ap["fp32_mixed"], H_ap["fp64"])}
+    log(f"field error against the FP64 all-pairs sum: {ap_err}")
+    del H_ap
 
     # batched slab: 32 independent realisations of 2^16 particles, graph-replayed MD steps
     slab = {}
@@ -295,6 +376,8 @@ def main():
         "interactions_per_eval": inter,
         "kernel_ms": {p: {"traversal": r["t_fwd_kernel"] * 1e3, "adjoint": r["t_adj_kernel"] * 1e3}
                       for p, r in res.items()},
+        "allpairs_ms": ap_ms,
+        "field_rel_error_vs_allpairs_fp64": ap_err,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

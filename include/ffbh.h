@@ -142,6 +142,19 @@ bh_status bh_graph_capture_md(bh_handle *h, const md_state *s, const md_params *
 bh_status bh_graph_launch(void *graph_exec, void *stream);
 bh_status bh_graph_destroy(void *graph_exec);
 
+/* All-pairs reference (Sec. 3.1, the all-pairs GPU step of Alg. 1).  For `batch` systems of n
+ * particles in caller order (d_pos, d_mom: (B, 3, n) FP64), writes d_H (B, 3, n) with
+ * H_i = sum_{j != i} T(r_i - r_j) m_j (Eq. H_dip); if not NULL, d_dEdr (B, 3, n) with the all-pairs
+ * energy gradient dE/dr_i = -sum_{j != i} f_dip(r_i - r_j; m_i, m_j) (Sec. 2), and d_E (B) with
+ * E = -1/2 sum m.H - sum m.H_ext (d_hext (B, 3) or NULL for no external field).  precision BH_FP64, or
+ * BH_FP32_MIXED: offsets formed in FP64, pair arithmetic in FP32, partial sums over 256 sources
+ * accumulated in FP64.  Distinct particles at the same position contribute nothing to each other.
+ * O(n^2) work per system; needs no handle or workspace; enqueued on `stream` without host
+ * synchronisation.  Returns BH_EINVAL for n < 1, batch outside [1, 65535], an unknown precision, or a
+ * NULL or misaligned required pointer; BH_EDEVICE if the launch fails. */
+bh_status bh_allpairs(int64_t n, int32_t batch, int32_t precision, const double *d_pos, const double *d_mom,
+                      const double *d_hext, double *d_H, double *d_dEdr, double *d_E, void *stream);
+
 /* Read (and clear) the device status word; synchronises the stream.  Returns BH_EDEGENERATE if any
  * flag was set, BH_OK otherwise; the raw bits go to *flags if not NULL. */
 bh_status bh_check_status(bh_handle *h, void *stream, uint32_t *flags);

@@ -74,6 +74,8 @@ def lib():
             getattr(L, f).restype = i32
         L.bh_morton_code.argtypes = [C.c_uint32, C.c_uint32, C.c_uint32]
         L.bh_morton_code.restype = C.c_uint64
+        L.bh_allpairs.argtypes = [i64, i32, i32, P, P, P, P, P, P, P]
+        L.bh_allpairs.restype = i32
         L.bh_status_str.argtypes = [i32]
         L.bh_status_str.restype = C.c_char_p
         for f in ("bh_workspace_bytes", "bh_create", "bh_destroy", "bh_build", "bh_field",
@@ -87,7 +89,7 @@ def lib():
 EXPORTED = ["bh_workspace_bytes", "bh_num_tunings", "bh_create", "bh_destroy", "bh_build", "bh_field",
             "bh_field_backward", "md_step", "bh_check_status", "bh_enable_counters", "bh_num_nodes",
             "bh_export_tree", "bh_set_timing_events", "bh_graph_capture_md", "bh_graph_launch",
-            "bh_graph_destroy", "bh_morton_code", "bh_status_str"]
+            "bh_graph_destroy", "bh_allpairs", "bh_morton_code", "bh_status_str"]
 
 
 def _check(fn: str, st: int):
@@ -298,3 +300,28 @@ class MDGraph:
 
 def morton_code(qx: int, qy: int, qz: int) -> int:
     return int(lib().bh_morton_code(qx, qy, qz))
+
+
+def allpairs(pos, mom, hext=None, precision="fp64", want_dEdr=False, want_E=False):
+    """All-pairs field (and optionally energy gradient and energy) of one or a batch of systems.
+
+    pos, mom: (3, n) or (B, 3, n) contiguous float64 CUDA tensors; hext: (3,) or (B, 3) or None.
+    Returns (H, dEdr or None, E or None) with the batch dimension of the input."""
+    squeeze = pos.dim() == 2
+    P = pos.unsqueeze(0) if squeeze else pos
+    M = mom.unsqueeze(0) if squeeze else mom
+    B, _, n = P.shape
+    _dev64(P, (B, 3, n), "pos")
+    _dev64(M, (B, 3, n), "mom")
+    he = None
+    if hext is not None:
+        he = _dev64(hext.reshape(B, 3).contiguous(), (B, 3), "hext")
+    H = torch.empty_like(P)
+    G = torch.empty_like(P) if want_dEdr else None
+    E = torch.empty(B, dtype=torch.float64, device=P.device) if want_E else None
+    _check("bh_allpairs", lib().bh_allpairs(int(n), int(B), PRECISIONS[precision], _ptr(P), _ptr(M), _ptr(he),
+                                            _ptr(H), _ptr(G), _ptr(E), _stream()))
+    if squeeze:
+        H = H[0]
+        G = None if G is None else G[0]
+    return H, G, E

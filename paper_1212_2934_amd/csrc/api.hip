@@ -306,6 +306,18 @@ bh_status bh_graph_destroy(void *graph_exec)
     return hipGraphExecDestroy((hipGraphExec_t)graph_exec) == hipSuccess ? BH_OK : BH_EDEVICE;
 }
 
+bh_status bh_allpairs(int64_t n, int32_t batch, int32_t precision, const double *d_pos, const double *d_mom,
+                      const double *d_hext, double *d_H, double *d_dEdr, double *d_E, void *stream)
+{
+    if (n < 1 || batch < 1 || batch > 65535) return BH_EINVAL;
+    if (precision != BH_FP64 && precision != BH_FP32_MIXED) return BH_EINVAL;
+    if (!dptr_ok(d_pos) || !dptr_ok(d_mom) || !dptr_ok(d_H)) return BH_EINVAL;
+    if ((d_dEdr && !dptr_ok(d_dEdr)) || (d_E && !dptr_ok(d_E)) || (d_hext && !dptr_ok(d_hext))) return BH_EINVAL;
+    if (launch_ap(n, batch, precision, d_pos, d_mom, d_hext, d_H, d_dEdr, d_E, (hipStream_t)stream) != hipSuccess)
+        return BH_EDEVICE;
+    return BH_OK;
+}
+
 bh_status bh_check_status(bh_handle *hh, void *stream, uint32_t *flags)
 {
     if (!hh) return BH_EINVAL;

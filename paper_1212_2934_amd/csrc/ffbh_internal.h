@@ -166,6 +166,8 @@ hipError_t launch_backward(Handle &h, const double *d_mom, const double *d_hext,
                            const double *d_gE, double *d_dpos, double *d_dmom, double *d_dhext,
                            hipStream_t s, double *d_H = nullptr, double *d_E = nullptr, bool moments_done = false);
 void launch_energy_final(Handle &h, double *d_E, hipStream_t s, int targets_per_wave);
+hipError_t launch_ap(int64_t n, int32_t batch, int32_t precision, const double *pos, const double *mom,
+                     const double *hext, double *H, double *dEdr, double *E, hipStream_t s);
 hipError_t launch_md(Handle &h, const md_state *st, const md_params *mp, hipStream_t s);
 
 }  // namespace ffbh

@@ -72,3 +72,20 @@ def test_morton_code_bit_layout():
     qs = rng.integers(0, 1 << 21, size=(200, 3))
     for qx, qy, qz in list(qs) + [(0, 0, 0), ((1 << 21) - 1,) * 3, (1, 0, 0), (0, 1, 0), (0, 0, 1)]:
         assert binding.morton_code(int(qx), int(qy), int(qz)) == _interleave_loop(int(qx), int(qy), int(qz))
+
+
+def test_allpairs_argument_checks():
+    """Host-checkable errors return BH_EINVAL before anything is enqueued (no device needed).  Skipped
+    where a GPU is present: the placeholder pointers must never reach a kernel."""
+    import ctypes as C
+    import torch
+    if torch.cuda.device_count() > 0:
+        pytest.skip("host-only check")
+    L = binding.lib()
+    fake = C.c_void_p(4096)  # never dereferenced: every call below fails its checks first
+    assert L.bh_allpairs(0, 1, 0, fake, fake, None, fake, None, None, None) == -1
+    assert L.bh_allpairs(16, 0, 0, fake, fake, None, fake, None, None, None) == -1
+    assert L.bh_allpairs(16, 70000, 0, fake, fake, None, fake, None, None, None) == -1
+    assert L.bh_allpairs(16, 1, 7, fake, fake, None, fake, None, None, None) == -1
+    assert L.bh_allpairs(16, 1, 0, None, fake, None, fake, None, None, None) == -1
+    assert L.bh_allpairs(16, 1, 0, fake, fake, None, C.c_void_p(4097), None, None, None) == -1

@@ -1,0 +1,79 @@
+"""All-pairs GPU kernel (bh_allpairs, the paper's all-pairs step) through the C ABI against the oracle's
+plain FP64 all-pairs sums: field, energy gradient and energy, FP64 and FP32-mixed, ragged sizes around the
+512-target workgroup and the 256-source tile, batches, and the Barnes-Hut path at theta = 0 (which sums
+every pair directly and must agree with it).  At 2^20 the GPU all-pairs field is checked on sampled
+targets, which the oracle computes one by one."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_util import errors, run_field
+from paper_1212_2934_amd import workloads
+from paper_1212_2934_amd.binding import allpairs
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32_mixed": 1e-5}
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
+def test_field_gradient_energy_against_oracle(precision):
+    w = workloads.uniform_cube(3000, 30.0, seed=41, hext=(0.3, -0.2, 0.5))
+    H, G, E = allpairs(_dev(w.pos), _dev(w.mom), _dev(w.hext), precision, want_dEdr=True, want_E=True)
+    Href = oracle.allpairs_field(w.pos, w.mom)
+    Gref = oracle.allpairs_grad_r(w.pos, w.mom)
+    Eref = oracle.energy(w.mom, Href, w.hext)
+    eh, eg = errors(H.cpu().numpy(), Href), errors(G.cpu().numpy(), Gref)
+    tol = TOL[precision]
+    assert eh["l2"] <= tol and eh["p999"] <= 10 * tol, eh
+    assert eg["l2"] <= tol and eg["p999"] <= 10 * tol, eg
+    assert abs(E.item() - Eref) <= tol * abs(Eref)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 255, 256, 257, 511, 512, 513, 1025])
+def test_ragged_sizes(n):
+    rng = np.random.default_rng(n)
+    pos = rng.uniform(0.0, 2.0 * n ** (1.0 / 3.0) + 2.0, (3, n))
+    mom = workloads.unit_vectors(rng, n)
+    H, G, _ = allpairs(_dev(pos), _dev(mom), precision="fp64", want_dEdr=True)
+    H, G = H.cpu().numpy(), G.cpu().numpy()
+    if n == 1:
+        assert (H == 0).all() and (G == 0).all()
+        return
+    assert errors(H, oracle.allpairs_field(pos, mom))["max"] <= 1e-11
+    assert errors(G, oracle.allpairs_grad_r(pos, mom))["max"] <= 1e-11
+
+
+def test_batch_equals_single_runs():
+    rng = np.random.default_rng(43)
+    B, n = 3, 700
+    pos = np.stack([workloads.rsa_uniform(rng, n, (0, 0, 0), (14.0, 14.0, 14.0)) for _ in range(B)])
+    mom = np.stack([workloads.unit_vectors(rng, n) for _ in range(B)])
+    hext = rng.standard_normal((B, 3))
+    H, G, E = allpairs(_dev(pos), _dev(mom), _dev(hext), "fp64", want_dEdr=True, want_E=True)
+    for b in range(B):
+        h1, g1, e1 = allpairs(_dev(pos[b]), _dev(mom[b]), _dev(hext[b]), "fp64", want_dEdr=True, want_E=True)
+        assert torch.equal(H[b], h1) and torch.equal(G[b], g1) and torch.equal(E[b:b + 1], e1)
+
+
+def test_barnes_hut_at_theta_zero_is_all_pairs():
+    w = workloads.uniform_cube(2500, 28.0, seed=44)
+    H, _, _ = allpairs(_dev(w.pos), _dev(w.mom), precision="fp64")
+    bh = run_field(w.pos, w.mom, theta=0.0, precision="fp64", counters=False)
+    assert errors(bh["H"], H.cpu().numpy())["max"] <= 1e-12
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
+def test_chains_2p20_sampled_targets(precision):
+    w = workloads.cached("chains_n1048576_seed1003", lambda: workloads.config3())
+    H, _, _ = allpairs(_dev(w.pos), _dev(w.mom), precision=precision)
+    idx = np.sort(np.random.default_rng(45).choice(w.n, 256, replace=False))
+    Href = oracle.allpairs_field_subset(w.pos, w.mom, idx)
+    e = errors(H.cpu().numpy()[:, idx], Href)
+    tol = TOL[precision]
+    assert e["l2"] <= tol and e["max"] <= 10 * tol, e
