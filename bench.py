@@ -297,6 +297,7 @@ def main():
         return {"rel_l2": (torch.linalg.vector_norm(H - ref) / torch.linalg.vector_norm(ref)).item(),
                 "p999": torch.quantile(per[torch.randperm(per.numel(), device=per.device)[:1 << 16]], 0.999).item()}
 
+    fp32_vs_fp64 = rel_err(H_bh["fp32_mixed"], H_bh["fp64"])
     ap_err = {"bh_fp32_mixed": rel_err(H_bh["fp32_mixed"], H_ap["fp64"]),
               "bh_fp64": rel_err(H_bh["fp64"], H_ap["fp64"]),
               "allpairs_fp32_mixed": rel_err(H_ap["fp32_mixed"], H_ap["fp64"])}
@@ -382,6 +383,9 @@ def main():
                    "n": n, "theta": args.theta, "leaf_size": 16},
         "field_evals_per_s_fp32": 1.0 / r32["t_eval"],
         "field_evals_per_s_fp64": 1.0 / res["fp64"]["t_eval"],
+        "particle_fields_per_s_fp32": n / r32["t_eval"],
+        "interactions_per_s_fp32": inter / r32["t_eval"],
+        "field_rel_l2_fp32_mixed_vs_fp64": fp32_vs_fp64,
         "md_steps_per_s_fp64": 1.0 / res["fp64"]["t_step"],
         "md_steps_per_s_fp32_eager": 1.0 / r32["t_step_eager"],
         "slab_b32_n65536_md_steps_per_s": {p: 1.0 / t for p, t in slab.items()} or None,

@@ -638,6 +638,14 @@ __global__ __launch_bounds__(256) void k_zero(double *__restrict__ a, int64_t le
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < len; i += (int64_t)gridDim.x * 256) a[i] = 0.0;
 }
 
+// The node adjoint records of the nodes the last build made (their count is on the device).
+__global__ __launch_bounds__(256) void k_zero_nodes(double *__restrict__ a, const uint32_t *__restrict__ nn,
+                                                    int64_t max_nodes)
+{
+    const int64_t len = 8 * ((int64_t)*nn < max_nodes ? (int64_t)*nn : max_nodes);
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < len; i += (int64_t)gridDim.x * 256) a[i] = 0.0;
+}
+
 // Downward pass and output: members collect their cells' adjoints along the leaf-to-root path; the
 // explicit derivative of E in m (-1/2 H - H_ext, times dL/dE) is added; results go to caller order.
 __global__ __launch_bounds__(256) void k_downward(
@@ -704,8 +712,8 @@ hipError_t launch_backward(Handle &h, const double *d_mom, const double *d_hext,
     }
     hipLaunchKernelGGL(k_hbar, dim3(grid_for(L.ntot, 256)), dim3(256), 0, s, d_gH, d_gE, w.smom, w.perm, L.n,
                        L.ntot, w.hbar);
-    hipLaunchKernelGGL(k_zero, dim3(grid_for(8 * L.max_nodes, 256, 4096)), dim3(256), 0, s, w.node_adj,
-                       8 * L.max_nodes);
+    hipLaunchKernelGGL(k_zero_nodes, dim3(grid_for(8 * L.max_nodes, 256, 2048)), dim3(256), 0, s, w.node_adj,
+                       w.status + 2, L.max_nodes);
     hipLaunchKernelGGL(k_zero, dim3(grid_for(8 * L.ntot, 256, 4096)), dim3(256), 0, s, w.g_rm, 8 * L.ntot);
     const int wpb = h.waves_per_block;
     const unsigned blocks = (unsigned)((L.num_waves + wpb - 1) / wpb);

@@ -50,30 +50,42 @@ __global__ __launch_bounds__(256) void k_bbox_partial(const double *__restrict__
     if (threadIdx.x < 6) part[((int64_t)b * kBboxBlocks + blockIdx.x) * 6 + threadIdx.x] = red[threadIdx.x][0];
 }
 
-__global__ void k_bbox_final(const double *__restrict__ part, double *__restrict__ bbox)
+// One workgroup of 256 per system folds the nb partial boxes (min and max are exact in any order).
+__global__ __launch_bounds__(256) void k_bbox_final(const double *__restrict__ part, int nb,
+                                                    double *__restrict__ bbox)
 {
+    __shared__ double red[6][256];
     const int b = blockIdx.x;
-    if (threadIdx.x != 0) return;
-    double lo[3], hi[3];
+    double v[6];
     for (int a = 0; a < 3; ++a) {
-        lo[a] = part[((int64_t)b * kBboxBlocks) * 6 + a];
-        hi[a] = part[((int64_t)b * kBboxBlocks) * 6 + 3 + a];
+        v[a] = __builtin_inf();
+        v[3 + a] = -__builtin_inf();
     }
-    for (int k = 1; k < kBboxBlocks; ++k) {
+    for (int k = threadIdx.x; k < nb; k += 256) {
+        const double *q = part + ((int64_t)b * kBboxBlocks + k) * 6;
         for (int a = 0; a < 3; ++a) {
-            double v = part[((int64_t)b * kBboxBlocks + k) * 6 + a];
-            if (v < lo[a]) lo[a] = v;
-            v = part[((int64_t)b * kBboxBlocks + k) * 6 + 3 + a];
-            if (v > hi[a]) hi[a] = v;
+            v[a] = fmin(v[a], q[a]);
+            v[3 + a] = fmax(v[3 + a], q[3 + a]);
         }
     }
+    for (int a = 0; a < 6; ++a) red[a][threadIdx.x] = v[a];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int a = 0; a < 3; ++a) {
+                red[a][threadIdx.x] = fmin(red[a][threadIdx.x], red[a][threadIdx.x + s]);
+                red[3 + a][threadIdx.x] = fmax(red[3 + a][threadIdx.x], red[3 + a][threadIdx.x + s]);
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
     double side = 0.0;
     for (int a = 0; a < 3; ++a) {
-        double e = hi[a] - lo[a];
+        const double e = red[3 + a][0] - red[a][0];
         if (e > side) side = e;
     }
     double *o = bbox + 8 * b;
-    o[0] = lo[0]; o[1] = lo[1]; o[2] = lo[2];
+    o[0] = red[0][0]; o[1] = red[1][0]; o[2] = red[2][0];
     o[3] = side;
     o[4] = side > 0.0 ? 2097152.0 / side : 0.0;
 }
@@ -729,9 +741,11 @@ hipError_t launch_build(Handle &h, const double *d_pos, hipStream_t s, const dou
     const Layout &L = h.L;
     Workspace &w = h.w;
     const int64_t n = L.n, B = L.B, ntot = L.ntot;
-    hipLaunchKernelGGL(k_bbox_partial, dim3(kBboxBlocks, (unsigned)B), dim3(256), 0, s, d_pos, n,
+    // partial boxes: at most kBboxBlocks per system, no more than one workgroup per 256 particles
+    const int nb = (int)((n + 255) / 256 < kBboxBlocks ? (n + 255) / 256 : kBboxBlocks);
+    hipLaunchKernelGGL(k_bbox_partial, dim3((unsigned)nb, (unsigned)B), dim3(256), 0, s, d_pos, n,
                        w.bbox_part, w.status);
-    hipLaunchKernelGGL(k_bbox_final, dim3((unsigned)B), dim3(64), 0, s, w.bbox_part, w.bbox);
+    hipLaunchKernelGGL(k_bbox_final, dim3((unsigned)B), dim3(256), 0, s, w.bbox_part, nb, w.bbox);
     hipLaunchKernelGGL(k_morton, dim3(grid_for(ntot, 256)), dim3(256), 0, s, d_pos, n, ntot, w.bbox,
                        w.keys[0], w.vals[0]);
     const int tiles = (int)L.tiles;

@@ -85,7 +85,7 @@ struct Workspace {
     double *md_grad_m;       // B x 3 x n
 };
 
-constexpr int kBboxBlocks = 64;
+constexpr int kBboxBlocks = 512;  // partial bounding boxes per system (two workgroups per CU)
 
 struct Layout {
     int64_t n, B, ntot, max_nodes, tiles, num_waves, hist_len, bin_int;
