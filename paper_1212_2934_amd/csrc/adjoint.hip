@@ -7,7 +7,9 @@
 // where g is the summand of the reduced dipolar force f_dip (Sec. 2) and T the dipole-field tensor of
 // Eq. (H_dip).  Cell adjoints reach the members in a downward pass: every member k of C receives
 // A_C in dL/dm_k and B_C / n_C in dL/dr_k (c_C is the mean of the members, Eq. magCenter).
-// Scatters are reduced across the wave before one FP64 atomic per value.
+// Scatters are reduced across the wave before one FP64 atomic per value.  The records hold the sums of
+// +g (S_C = -B_C for a cell, the sum of g over a source's partners for a particle), and the downward pass
+// subtracts them, so the scattered values need no negation.
 #include "traverse.h"
 
 namespace ffbh {
@@ -52,7 +54,7 @@ struct AdjLds {
     LdsTarget tgt[kWave];  // the wave's targets
     T hb[kWave][4];        // their upstream field gradients
     T acc[kWave][6];       // direct-sum g (0..2) and field (3..5) of the current leaf, by owner lane
-    T sbuf[16][6];         // member totals of the current chunk: -sum g (0..2), sum T(x) a (3..5)
+    T sbuf[16][6];         // member totals of the current chunk: sum g (0..2), sum T(x) a (3..5)
     int list[kWave];       // lanes that opened the current leaf
 };
 
@@ -85,7 +87,7 @@ __device__ inline void adj_leaf(AdjLds<T> &W, int lane, const Src *__restrict__ 
             coincident |= other && !(r2 > (T)0);
             T qx, qy, qz, ux, uy, uz, hx = 0, hy = 0, hz = 0;
             adj_field<T>(use, x, y, z, ax, ay, az, mx, my, mz, qx, qy, qz, ux, uy, uz, hx, hy, hz);
-            s0 -= qx; s1 -= qy; s2 -= qz;
+            s0 += qx; s1 += qy; s2 += qz;
             s3 += ux; s4 += uy; s5 += uz;
             T o0, o1;
             group_sum6<G>(lane, qx, qy, qz, hx, hy, hz, o0, o1);
@@ -99,8 +101,9 @@ __device__ inline void adj_leaf(AdjLds<T> &W, int lane, const Src *__restrict__ 
                 if (tok && b < 6) lds_add(&W.acc[tl][b], o0);  // lane b < 6 holds slot b
             }
         }
-        // dL/dr_k -= sum g, dL/dm_k += sum T(x) a over the listed targets: the row swaps move two of the six
-        // values each (rows 0..3 of x0 carry components 0, 2, 1, 3 and rows 0, 1 / 2, 3 of x1 carry 4 / 5),
+        // sum g (subtracted from dL/dr_k downstream), dL/dm_k += sum T(x) a over the listed targets: the row
+        // swaps move two of the six values each (rows 0..3 of x0 carry components 0, 2, 1, 3 and rows 0, 1 /
+        // 2, 3 of x1 carry 4 / 5),
         // then lanes of equal member index inside a row are added
         const T w0 = swap32_pair(s0, s1), w1 = swap32_pair(s2, s3), w2 = swap32_pair(s4, s5);
         const T x0 = row_stride_sum<G>(swap16_pair(w0, w1)), x1 = row_stride_sum<G>(swap16_sum(w2));
@@ -191,8 +194,8 @@ __global__ __launch_bounds__(512) void k_adjoint(
             T gx, gy, gz, tx, ty, tz;
             fused_pair<MIXED, T>(acc, (T)dx, (T)dy, (T)dz, ax, ay, az, bx, by, bz, gx, gy, gz, tx, ty, tz, pgx, pgy,
                                  pgz, phx, phy, phz, grx, gry, grz, hx, hy, hz);
-            // A_C += sum T(x) Hbar over the accepting lanes, B_C -= sum g
-            scatter6<T>(accm, lane, wcomp, node_adj + 8 * (int64_t)cur, tx, ty, tz, -gx, -gy, -gz);
+            // A_C += sum T(x) Hbar over the accepting lanes, S_C += sum g (B_C = -S_C)
+            scatter6<T>(accm, lane, wcomp, node_adj + 8 * (int64_t)cur, tx, ty, tz, gx, gy, gz);
         }
         const uint64_t open = mask & ~accm;
         if (open == 0ull) continue;
@@ -387,15 +390,15 @@ __global__ __launch_bounds__(256) void k_adjoint2(
                 T gx, gy, gz, tx, ty, tz;
                 ta.pair(acc_a, (T)dxa, (T)dya, (T)dza, bx, by, bz, gx, gy, gz, tx, ty, tz);
                 s0 += tx; s1 += ty; s2v += tz;
-                s3 -= gx; s4 -= gy; s5 -= gz;
+                s3 += gx; s4 += gy; s5 += gz;
             }
             if (accb) {
                 T gx, gy, gz, tx, ty, tz;
                 tb.pair(acc_b, (T)dxb, (T)dyb, (T)dzb, bx, by, bz, gx, gy, gz, tx, ty, tz);
                 s0 += tx; s1 += ty; s2v += tz;
-                s3 -= gx; s4 -= gy; s5 -= gz;
+                s3 += gx; s4 += gy; s5 += gz;
             }
-            // A_C += T(x) Hbar, B_C -= g, over the accepting targets of the wave
+            // A_C += T(x) Hbar, S_C += g, over the accepting targets of the wave
             scatter6<T>(acca | accb, lane, wcomp, node_adj + 8 * (int64_t)cur, s0, s1, s2v, s3, s4, s5);
         }
         const uint64_t opa = ballot(act_a && !acc_a), opb = ballot(act_b && !acc_b);
@@ -424,16 +427,16 @@ __global__ __launch_bounds__(256) void k_adjoint2(
             if (usa) {
                 T qx, qy, qz, ux, uy, uz;
                 ta.pair(ua, xa, ya, za, (T)sk.mx, (T)sk.my, (T)sk.mz, qx, qy, qz, ux, uy, uz);
-                s0 -= qx; s1 -= qy; s2v -= qz;
+                s0 += qx; s1 += qy; s2v += qz;
                 s3 += ux; s4 += uy; s5 += uz;
             }
             if (usb) {
                 T qx, qy, qz, ux, uy, uz;
                 tb.pair(ub, xb, yb, zb, (T)sk.mx, (T)sk.my, (T)sk.mz, qx, qy, qz, ux, uy, uz);
-                s0 -= qx; s1 -= qy; s2v -= qz;
+                s0 += qx; s1 += qy; s2v += qz;
                 s3 += ux; s4 += uy; s5 += uz;
             }
-            // dL/dr_k -= sum g, dL/dm_k += sum T(x) Hbar over the wave's targets
+            // sum g (subtracted from dL/dr_k downstream), dL/dm_k += sum T(x) Hbar over the wave's targets
             scatter6<T>(usa | usb, lane, wcomp, g_rm + 8 * (int64_t)k, s0, s1, s2v, s3, s4, s5);
         }
         ta.flush();
@@ -520,7 +523,7 @@ __global__ __launch_bounds__(NW * 64) void k_adjoint_wg(
             T gx, gy, gz, tx, ty, tz;
             fused_pair<MIXED, T>(acc, (T)dx, (T)dy, (T)dz, ax, ay, az, bx, by, bz, gx, gy, gz, tx, ty, tz, pgx, pgy,
                                  pgz, phx, phy, phz, grx, gry, grz, hx, hy, hz);
-            vs = wave_total6<T>(lane, tx, ty, tz, -gx, -gy, -gz);
+            vs = wave_total6<T>(lane, tx, ty, tz, gx, gy, gz);
         }
         const uint64_t open = mask & ~accm;
         if (wcomp >= 0) fpart[par][wv][wcomp] = vs;
@@ -564,7 +567,7 @@ __global__ __launch_bounds__(NW * 64) void k_adjoint_wg(
                     T qx, qy, qz, ux, uy, uz;
                     fused_pair<MIXED, T>(use, x, y, z, ax, ay, az, (T)sk.mx, (T)sk.my, (T)sk.mz, qx, qy, qz, ux, uy,
                                          uz, pgx, pgy, pgz, phx, phy, phz, grx, gry, grz, hx, hy, hz);
-                    ws = wave_total6<T>(lane, -qx, -qy, -qz, ux, uy, uz);
+                    ws = wave_total6<T>(lane, qx, qy, qz, ux, uy, uz);
                 }
                 if (wcomp >= 0) lpart[wv][j][wcomp] = ws;
             }
@@ -671,9 +674,9 @@ __global__ __launch_bounds__(256) void k_downward(
     const double *he = hext ? hext + 3 * b : nullptr;
     double *dp = dpos + b * 3 * n, *dm = dmom + b * 3 * n;
     const double *q = g_rm + 8 * s;
-    dp[i] = g_gather[s] + q[0] + Bx;
-    dp[n + i] = g_gather[ntot + s] + q[1] + By;
-    dp[2 * n + i] = g_gather[2 * ntot + s] + q[2] + Bz;
+    dp[i] = g_gather[s] - q[0] - Bx;
+    dp[n + i] = g_gather[ntot + s] - q[1] - By;
+    dp[2 * n + i] = g_gather[2 * ntot + s] - q[2] - Bz;
     double ex = -0.5 * Hs[s], ey = -0.5 * Hs[ntot + s], ez = -0.5 * Hs[2 * ntot + s];
     if (he) { ex -= he[0]; ey -= he[1]; ez -= he[2]; }
     dm[i] = q[3] + Ax + ge * ex;
