@@ -6,7 +6,8 @@ Sec. 4 (all updates from the state at the start of the step):
     r' = r + dt v
     w' = w + dt/I (m x H_eff - gamma_r w) + sqrt(2 gamma_r kT dt)/I xi_r
     m' = rotation of m by the angle |w| dt about w (Rodrigues), renormalised
-F = -dE/dr + WCA pair and wall forces, H_eff = -dE/dm, E the Barnes-Hut energy (frozen-structure
+F = -dE/dr + short-range pair and wall forces (WCA, or with p["sr_kind"] = 1 the paper's form of Eq. LJ),
+H_eff = -dE/dm, E the Barnes-Hut energy (frozen-structure
 gradient from the C oracle).  Readings (the paper's angle equations are garbled and its noise variance
 for rotations reads 3 kT G_r): vector form, variance 2 gamma kT dt per component.
 
@@ -85,17 +86,52 @@ def wca_forces(pos, sigma=1.0, eps=1.0):
     return F
 
 
-def wall_forces(pos, box_lo, box_hi, sigma=1.0, eps=1.0):
-    """WCA walls on the centre-to-face distance, sigma_w = sigma / 2 (distance floored at sigma_w / 10)."""
+def lj_forces(pos, sigma=1.0, eps=1.0, cut=0.0):
+    """The paper's short-range force (Eq. LJ, Sec. 2) by brute force over all pairs:
+    24 eps [(s/r)^12 - (s/r)^6] r_ij / r^2, which vanishes at r = s, repels below it and attracts above it
+    (potential 2 eps (s/r)^12 - 4 eps (s/r)^6, depth 2 eps at r = s); cut at `cut` (default 2.5 s)."""
+    n = pos.shape[1]
+    F = np.zeros_like(pos)
+    if eps == 0.0:
+        return F
+    rc = cut if cut > 0.0 else 2.5 * sigma
+    rc2 = rc * rc
+    for i0 in range(0, n, 512):
+        i1 = min(n, i0 + 512)
+        d = pos[:, i0:i1, None] - pos[:, None, :]  # (3, b, n)
+        r2 = (d * d).sum(axis=0)
+        idx = np.arange(i0, i1)
+        r2[idx - i0, idx] = np.inf
+        sel = r2 < rc2
+        sr6 = np.where(sel, (sigma * sigma / np.where(sel, r2, 1.0)) ** 3, 0.0)
+        f = np.where(sel, 24.0 * eps * (sr6 * sr6 - sr6) / np.where(sel, r2, 1.0), 0.0)
+        F[:, i0:i1] = (f[None] * d).sum(axis=2)
+    return F
+
+
+def short_range_forces(pos, p):
+    """Pair forces of the short-range law selected by p["sr_kind"]: 0 WCA (default), 1 the paper's form."""
+    if p.get("sr_kind", 0) == 1:
+        return lj_forces(pos, p["wca_sigma"], p["wca_eps"], p.get("sr_cut", 0.0))
+    return wca_forces(pos, p["wca_sigma"], p["wca_eps"])
+
+
+def wall_forces(pos, box_lo, box_hi, sigma=1.0, eps=1.0, kind=0, cut=0.0):
+    """Walls on the centre-to-face distance with sigma_w = sigma / 2 (distance floored at sigma_w / 10):
+    kind 0 the WCA form, cut at 2^(1/6) sigma_w; kind 1 the paper's form (a wall "of the same type" as the
+    pair force), cut at half the pair cut-off."""
     if eps == 0.0:
         return np.zeros_like(pos)
     sw = 0.5 * sigma
-    rcw = 2.0 ** (1.0 / 6.0) * sw
+    if kind == 1:
+        c12, rcw = 1.0, 0.5 * (cut if cut > 0.0 else 2.5 * sigma)
+    else:
+        c12, rcw = 2.0, 2.0 ** (1.0 / 6.0) * sw
 
     def mag(d):
         dd = np.maximum(d, 0.1 * sw)
         s6 = (sw / dd) ** 6
-        return np.where(d < rcw, 24.0 * eps * (2.0 * s6 * s6 - s6) / dd, 0.0)
+        return np.where(d < rcw, 24.0 * eps * (c12 * s6 * s6 - s6) / dd, 0.0)
 
     lo = np.asarray(box_lo, float)[:, None]
     hi = np.asarray(box_hi, float)[:, None]
@@ -117,7 +153,8 @@ def rodrigues(m, w, dt):
 def md_step(state: dict, p: dict, step: int, theta=0.5, leaf=16, field=True):
     """One step for every system of state (arrays (B, 3, n)); returns the new state (copies).
 
-    p: dt, kT, gamma_t, gamma_r, mass, inertia, wca_eps, wca_sigma, box_lo, box_hi, hext (B, 3), seed.
+    p: dt, kT, gamma_t, gamma_r, mass, inertia, wca_eps, wca_sigma, box_lo, box_hi, hext (B, 3), seed, and
+    optionally sr_kind (0 WCA, 1 the paper's Eq. LJ form) and sr_cut (its cut-off; 0 = 2.5 sigma).
     field=False drops the dipolar forces and torques (non-interacting particles in H_ext only).
     """
     pos, vel, mom, om = (np.array(state[k], dtype=np.float64) for k in ("pos", "vel", "mom", "omega"))
@@ -129,8 +166,9 @@ def md_step(state: dict, p: dict, step: int, theta=0.5, leaf=16, field=True):
             _, _, dr, dm = Tree(pos[b], mom[b], leaf).energy_grad(theta, hext[b])
         else:
             dr, dm = np.zeros((3, n)), -np.repeat(hext[b][:, None], n, axis=1)
-        F = -dr + wca_forces(pos[b], p["wca_sigma"], p["wca_eps"]) + \
-            wall_forces(pos[b], p["box_lo"], p["box_hi"], p["wca_sigma"], p["wca_eps"])
+        F = -dr + short_range_forces(pos[b], p) + \
+            wall_forces(pos[b], p["box_lo"], p["box_hi"], p["wca_sigma"], p["wca_eps"], p.get("sr_kind", 0),
+                        p.get("sr_cut", 0.0))
         He = -dm
         tq = np.cross(mom[b].T, He.T).T
         xi = normals(p["seed"], b, step, n)

@@ -95,3 +95,37 @@ def test_langevin_magnetisation_law(alpha):
         if k >= 1500:
             mz.append(st["mom"][0, 2].mean())
     assert abs(np.mean(mz) - md.langevin(alpha)) < 0.015, (np.mean(mz), md.langevin(alpha))
+
+
+def test_paper_short_range_force_law():
+    """Eq. LJ as printed: the force vanishes at r = s (the equilibrium distance the paper names), is minus the
+    derivative of the potential 2 eps (s/r)^12 - 4 eps (s/r)^6 (well depth 2 eps at s; checked by central
+    differences of that potential, written independently of the force), repels below s, attracts above,
+    and is cut at 2.5 s by default."""
+    s, eps = 1.3, 0.7
+    pot = lambda r: 2.0 * eps * (s / r) ** 12 - 4.0 * eps * (s / r) ** 6
+    for r in (0.9 * s, s, 1.2 * s, 2.0 * s):
+        pos = np.array([[0.0, r], [0.0, 0.0], [0.0, 0.0]])
+        F = md.lj_forces(pos, s, eps)
+        h = 1e-6 * r
+        fd = -(pot(r + h) - pot(r - h)) / (2.0 * h)
+        assert abs(F[0, 1] - fd) <= 1e-6 * max(1.0, abs(fd)), (r, F[0, 1], fd)
+        assert F[0, 0] == -F[0, 1] and not F[1:].any()
+    assert md.lj_forces(np.array([[0.0, s], [0.0, 0.0], [0.0, 0.0]]), s, eps)[0, 1] == 0.0
+    far = np.array([[0.0, 2.6 * s], [0.0, 0.0], [0.0, 0.0]])
+    assert not md.lj_forces(far, s, eps).any()
+    assert md.lj_forces(far, s, eps, cut=3.0 * s)[0, 1] < 0.0  # attractive: particle 1 (at +x) pulled back
+
+
+def test_paper_short_range_momentum_and_walls():
+    rng = np.random.default_rng(12)
+    pos = rng.uniform(0.0, 6.0, (3, 200))
+    F = md.lj_forces(pos, 1.0, 1.0)
+    assert np.abs(F.sum(axis=1)).max() <= 1e-9 * np.abs(F).max()  # pair forces cancel
+    # walls of the same type (sigma_w = sigma / 2): zero at distance sigma_w, repulsive inside, attractive
+    # outside up to half the pair cut-off
+    lo, hi = (0.0, 0.0, 0.0), (10.0, 10.0, 10.0)
+    x = np.array([[0.5, 0.4, 0.8, 1.3, 5.0], [5.0] * 5, [5.0] * 5])
+    W = md.wall_forces(x, lo, hi, 1.0, 1.0, kind=1)
+    assert W[0, 0] == 0.0 and W[0, 1] > 0.0 and W[0, 2] < 0.0 and W[0, 3] == 0.0 and W[0, 4] == 0.0
+    assert not W[1:].any()
