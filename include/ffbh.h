@@ -115,9 +115,13 @@ typedef struct md_state {
     uint64_t *d_step;   /* device step counter (one uint64), incremented by md_step */
 } md_state;
 
-/* Integrator parameters (reduced units).  Forces: -dE/dr of the Barnes-Hut energy plus a WCA
- * repulsion (eps, sigma, cut 2^(1/6) sigma) between particles and against the faces of the box
- * [box_lo, box_hi] (distance centre-to-face, wall sigma = sigma/2).  Torque m x (-dE/dm).
+/* Integrator parameters (reduced units).  Forces: -dE/dr of the Barnes-Hut energy plus a short-range
+ * force between particles and against the faces of the box [box_lo, box_hi] (distance centre-to-face,
+ * wall sigma = sigma/2), with strength wca_eps and length wca_sigma:
+ *   sr_kind 0 (default): WCA repulsion 24 eps [2 (s/r)^12 - (s/r)^6] / r, cut at 2^(1/6) s;
+ *   sr_kind 1: the paper's form (Eq. LJ, Sec. 2) 24 eps [(s/r)^12 - (s/r)^6] / r, zero at s, attractive
+ *   beyond, cut at sr_cut (0: 2.5 s); walls of the same form, cut at sr_cut / 2.
+ * Torque m x (-dE/dm).
  * Euler-Maruyama step of size dt for (r, v) and (m, omega) with friction gamma_t, gamma_r and
  * Gaussian noise of variance 2 gamma kT dt per component; m is rotated by omega*dt and renormalised.
  * Noise: Philox4x32-10 keyed by (seed, system), counter (step, particle, component-stream). */
@@ -126,6 +130,8 @@ typedef struct md_params {
     double box_lo[3], box_hi[3];
     const double *d_hext;   /* (B, 3) or NULL */
     uint64_t seed;
+    int32_t sr_kind;        /* 0 WCA, 1 the paper's form (see above) */
+    double sr_cut;          /* cut-off of sr_kind 1; 0 = 2.5 sigma */
 } md_params;
 
 /* One MD step: bh_build on the current positions, field + adjoint of the energy, WCA forces, and the

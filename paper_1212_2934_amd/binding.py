@@ -36,7 +36,8 @@ class md_params(C.Structure):
                 ("gamma_r", C.c_double), ("mass", C.c_double), ("inertia", C.c_double),
                 ("wca_eps", C.c_double), ("wca_sigma", C.c_double),
                 ("box_lo", C.c_double * 3), ("box_hi", C.c_double * 3),
-                ("d_hext", C.c_void_p), ("seed", C.c_uint64)]
+                ("d_hext", C.c_void_p), ("seed", C.c_uint64),
+                ("sr_kind", C.c_int32), ("sr_cut", C.c_double)]
 
 
 class BHError(RuntimeError):

@@ -268,6 +268,8 @@ static bh_status md_args_ok(bh_handle *hh, const md_state *s, const md_params *p
     for (int a = 0; a < 3; ++a)
         if (!(p->box_hi[a] > p->box_lo[a])) return BH_EINVAL;
     if (p->d_hext && !dptr_ok(p->d_hext)) return BH_EINVAL;
+    if (p->sr_kind != 0 && p->sr_kind != 1) return BH_EINVAL;
+    if (!(p->sr_cut >= 0.0) || !__builtin_isfinite(p->sr_cut)) return BH_EINVAL;
     return BH_OK;
 }
 

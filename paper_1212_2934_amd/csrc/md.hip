@@ -59,35 +59,36 @@ __device__ inline void box_muller(uint32_t a, uint32_t b, double &n0, double &n1
 
 // ---- WCA short-range forces (tree range query) --------------------------------------------------------
 
-// Force on a particle at offset x = r_i - r_k from a WCA partner: 24 eps [2 (s/r)^12 - (s/r)^6] x / r^2.
-__device__ inline void wca_pair(double x, double y, double z, double s2, double eps, double rc2, double &fx,
-                                double &fy, double &fz)
+// Force on a particle at offset x = r_i - r_k from a short-range partner, 24 eps [c12 (s/r)^12 - (s/r)^6] x / r^2
+// for r < rc: c12 = 2 is the WCA repulsion, c12 = 1 the paper's form (Eq. LJ).
+__device__ inline void sr_pair(double x, double y, double z, double s2, double eps, double c12, double rc2,
+                               double &fx, double &fy, double &fz)
 {
     const double r2 = x * x + y * y + z * z;
     if (r2 >= rc2 || r2 <= 0.0) return;
     const double sr2 = s2 / r2;
     const double sr6 = sr2 * sr2 * sr2;
-    const double f = 24.0 * eps * (2.0 * sr6 * sr6 - sr6) / r2;
+    const double f = 24.0 * eps * (c12 * sr6 * sr6 - sr6) / r2;
     fx += f * x;
     fy += f * y;
     fz += f * z;
 }
 
-// Wall force along one axis for centre-to-face distances dlo (to the lower face) and dhi.
-__device__ inline double wall_force(double dlo, double dhi, double sw, double eps)
+// Wall force along one axis for centre-to-face distances dlo (to the lower face) and dhi, the same law with
+// sigma_w = sigma / 2 and cut rcw, the distance floored at sigma_w / 10.
+__device__ inline double wall_force(double dlo, double dhi, double sw, double eps, double c12, double rcw)
 {
-    const double rcw = 1.122462048309373 * sw;  // 2^(1/6) sigma_w
     const double dmin = 0.1 * sw;
     double f = 0.0;
     if (dlo < rcw) {
         const double d = dlo > dmin ? dlo : dmin;
         const double s6 = (sw / d) * (sw / d) * (sw / d) * (sw / d) * (sw / d) * (sw / d);
-        f += 24.0 * eps * (2.0 * s6 * s6 - s6) / d;
+        f += 24.0 * eps * (c12 * s6 * s6 - s6) / d;
     }
     if (dhi < rcw) {
         const double d = dhi > dmin ? dhi : dmin;
         const double s6 = (sw / d) * (sw / d) * (sw / d) * (sw / d) * (sw / d) * (sw / d);
-        f -= 24.0 * eps * (2.0 * s6 * s6 - s6) / d;
+        f -= 24.0 * eps * (c12 * s6 * s6 - s6) / d;
     }
     return f;
 }
@@ -130,19 +131,19 @@ __global__ __launch_bounds__(256) void k_cell_fill(const uint64_t *__restrict__ 
     if (s == 0 || (codes[o - 1] >> shift) != c) cell_first[b * T + (int64_t)c] = (uint32_t)o;
 }
 
-// WCA forces on every particle (one thread per sorted particle): partners from the 27 surrounding cells,
-// then the container walls; written in the caller's order.
+// Short-range forces on every particle (one thread per sorted particle): partners from the 27 surrounding
+// cells, then the container walls; written in the caller's order.  SrLaw selects the law (c12) and cut-offs.
 __global__ __launch_bounds__(256) void k_wca(const uint64_t *__restrict__ codes, const double *__restrict__ bbox,
                                              const uint32_t *__restrict__ cell_first, const double *__restrict__ spos,
                                              const uint32_t *__restrict__ perm, double *__restrict__ F, int64_t n,
                                              int64_t ntot, int lcap, int64_t T, double sigma, double eps,
-                                             double3 box_lo, double3 box_hi)
+                                             double c12, double rc, double rcw, double3 box_lo, double3 box_hi)
 {
     const int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (o >= ntot) return;
     const int64_t b = o / n, lo_i = b * n, hi_i = lo_i + n;
     const double rx = spos[o], ry = spos[ntot + o], rz = spos[2 * ntot + o];
-    const double rc = 1.122462048309373 * sigma, rc2 = rc * rc, s2 = sigma * sigma;
+    const double rc2 = rc * rc, s2 = sigma * sigma;
     double fx = 0.0, fy = 0.0, fz = 0.0;
     if (eps > 0.0) {
         const int L = grid_level(bbox[8 * b + 3], rc, lcap);
@@ -171,16 +172,16 @@ __global__ __launch_bounds__(256) void k_wca(const uint64_t *__restrict__ codes,
                 const uint64_t c = cell[k];
                 for (int64_t j = first[k]; j >= lo_i && j < hi_i && (codes[j] >> shift) == c; ++j) {
                     if (j == o) continue;
-                    wca_pair(rx - spos[j], ry - spos[ntot + j], rz - spos[2 * ntot + j], s2, eps, rc2, fx, fy,
-                             fz);
+                    sr_pair(rx - spos[j], ry - spos[ntot + j], rz - spos[2 * ntot + j], s2, eps, c12, rc2, fx, fy,
+                            fz);
                 }
             }
         }
         // container walls
         const double sw = 0.5 * sigma;
-        fx += wall_force(rx - box_lo.x, box_hi.x - rx, sw, eps);
-        fy += wall_force(ry - box_lo.y, box_hi.y - ry, sw, eps);
-        fz += wall_force(rz - box_lo.z, box_hi.z - rz, sw, eps);
+        fx += wall_force(rx - box_lo.x, box_hi.x - rx, sw, eps, c12, rcw);
+        fy += wall_force(ry - box_lo.y, box_hi.y - ry, sw, eps, c12, rcw);
+        fz += wall_force(rz - box_lo.z, box_hi.z - rz, sw, eps, c12, rcw);
     }
     const int64_t i = (int64_t)perm[o] - lo_i;
     if (i < 0 || i >= n) return;
@@ -266,11 +267,16 @@ hipError_t launch_md(Handle &h, const md_state *st, const md_params *mp, hipStre
     e = launch_backward(h, st->mom, mp->d_hext, nullptr, w.ones, w.md_grad_r, w.md_grad_m, nullptr, s, nullptr,
                         nullptr, true);
     if (e != hipSuccess) return e;
-    const double rc = 1.122462048309373 * mp->wca_sigma;
+    // sr_kind 0: WCA, pair and wall cut at the potential minimum; 1: the paper's form, walls at half the pair cut
+    const double wca_rc = 1.122462048309373;  // 2^(1/6)
+    const bool lj = mp->sr_kind == 1;
+    const double c12 = lj ? 1.0 : 2.0;
+    const double rc = lj ? (mp->sr_cut > 0.0 ? mp->sr_cut : 2.5 * mp->wca_sigma) : wca_rc * mp->wca_sigma;
+    const double rcw = lj ? 0.5 * rc : wca_rc * 0.5 * mp->wca_sigma;
     hipLaunchKernelGGL(k_cell_fill, dim3(grid_for(L.ntot, 256)), dim3(256), 0, s, w.codes, w.bbox, L.n, L.ntot, rc,
                        L.cell_lcap, L.cell_T, w.cell_first);
     hipLaunchKernelGGL(k_wca, dim3(grid_for(L.ntot, 256)), dim3(256), 0, s, w.codes, w.bbox, w.cell_first, w.spos,
-                       w.perm, w.md_force, L.n, L.ntot, L.cell_lcap, L.cell_T, mp->wca_sigma, mp->wca_eps,
+                       w.perm, w.md_force, L.n, L.ntot, L.cell_lcap, L.cell_T, mp->wca_sigma, mp->wca_eps, c12, rc, rcw,
                        make_double3(mp->box_lo[0], mp->box_lo[1], mp->box_lo[2]),
                        make_double3(mp->box_hi[0], mp->box_hi[1], mp->box_hi[2]));
     MDConst c{mp->dt, mp->kT, mp->gamma_t, mp->gamma_r, mp->mass, mp->inertia, mp->seed};

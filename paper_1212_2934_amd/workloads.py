@@ -225,6 +225,33 @@ def config5(seed: int = 1005, batch: int = 32, n: int = 1 << 16,
                     0.5, 16, seed)
 
 
+def fig2_cube(seed: int = 2001, batch: int = 1, n: int = 20000, side: float = 75.0) -> Workload:
+    """Cubic confinement of the paper's Fig. 2(a): N = 20000 in a cube of edge 150 R = 75 d (phi = 2.5 %),
+    isotropic moments, no external field; one placement per realisation (seed*1000 + r)."""
+    return _batched(f"fig2_cube_n{n}", seed, batch, n, (side, side, side))
+
+
+def fig2_monolayer(seed: int = 2002, batch: int = 1, n: int = 300, side: float = 75.0,
+                   height: float = 1.05) -> Workload:
+    """Monolayer of the paper's Fig. 2(b): N = 300 in a flat box of height 2.1 R = 1.05 d.  The paper gives
+    no lateral size; the cube's edge (150 R = 75 d) is taken, an area fraction of 4.2 %.  Centres start at
+    mid-height (the d/2 margin leaves a 0.05 d band)."""
+    return _batched(f"fig2_monolayer_n{n}", seed, batch, n, (side, side, height))
+
+
+def _batched(name: str, seed: int, batch: int, n: int, box) -> Workload:
+    pos = np.empty((batch, 3, n))
+    mom = np.empty((batch, 3, n))
+    for r in range(batch):
+        rng = np.random.default_rng(seed * 1000 + r)
+        pos[r] = rsa_uniform(rng, n, (0.0, 0.0, 0.0), box)
+        mom[r] = unit_vectors(rng, n)
+    if batch == 1:
+        pos, mom = pos[0], mom[0]
+    return Workload(name, pos, mom, np.zeros(3) if batch == 1 else np.zeros((batch, 3)), np.zeros(3),
+                    np.asarray(box, float), 0.5, 16, seed)
+
+
 def maxwell_boltzmann(rng: np.random.Generator, shape, kT: float, mass: float) -> np.ndarray:
     """Gaussian velocities (or angular velocities with mass -> inertia) at temperature kT."""
     return rng.standard_normal(shape) * math.sqrt(kT / mass)

@@ -10,7 +10,7 @@ import torch
 
 from oracle import md as omd
 from paper_1212_2934_amd import workloads
-from paper_1212_2934_amd.binding import BarnesHut, md_params
+from paper_1212_2934_amd.binding import BarnesHut, BHError, md_params
 
 pytestmark = pytest.mark.gpu
 
@@ -95,6 +95,61 @@ def test_chain_contacts_short_range_forces(batch):
         g = d[key].cpu().numpy()
         err = np.abs(g - ref[key]).max() / np.abs(ref[key]).max()
         assert err <= 1e-11, (key, err)
+
+
+@pytest.mark.parametrize("batch,sr_cut", [(1, 0.0), (3, 0.0), (3, 2.0)])
+def test_paper_short_range_law(batch, sr_cut):
+    """The paper's short-range force (Eq. LJ, Sec. 2; sr_kind 1): zero at sigma, attractive out to the
+    cut-off (2.5 sigma by default), walls of the same law at half the cut.  Chains at spacing 1.05 d sit
+    just outside the zero, so every bead feels attraction from its neighbours and repulsion-free walls
+    within reach; two FP64 steps against the reference integrator's brute-force pair sum.  The longer
+    cut-off coarsens the cell grid of each system (sides 16, 30 and 60)."""
+    rng = np.random.default_rng(41)
+    sides = [16.0, 30.0, 60.0][:batch] if batch > 1 else [20.0]
+    n = 900
+    pos, mom = [], []
+    for side in sides:
+        p_, m_ = workloads.rsa_chains(rng, n, (0.0, 0.0, 0.0), (side, side, side))
+        pos.append(p_)
+        mom.append(m_)
+    st = dict(pos=np.stack(pos), vel=rng.standard_normal((batch, 3, n)), mom=np.stack(mom),
+              omega=rng.standard_normal((batch, 3, n)))
+    side = max(sides)
+    p = _params(side)
+    p["hext"] = np.tile(p["hext"], (batch, 1))
+    p["sr_kind"], p["sr_cut"] = 1, sr_cut
+    bh = BarnesHut(n, batch, 16, 0.5, "fp64")
+    d = _to_dev(st)
+    he = torch.from_numpy(p["hext"]).cuda()
+    mp = _mdp(p, he)
+    mp.sr_kind, mp.sr_cut = 1, sr_cut
+    ref = st
+    for k in range(2):
+        bh.md_step(d, mp)
+        ref = omd.md_step(ref, p, k, theta=0.5, leaf=16)
+    assert bh.check_status() == 0
+    for key in ("pos", "vel", "mom", "omega"):
+        g = d[key].cpu().numpy()
+        err = np.abs(g - ref[key]).max() / np.abs(ref[key]).max()
+        assert err <= 1e-11, (key, err)
+
+
+def test_short_range_law_argument_checks():
+    """An unknown law or a negative or non-finite cut-off is rejected before anything is enqueued."""
+    w = workloads.uniform_cube(256, 10.0, seed=3)
+    st = _to_dev(_state(w, np.random.default_rng(3)))
+    p = _params(10.0)
+    he = torch.from_numpy(p["hext"]).cuda()
+    bh = BarnesHut(w.n, 1, 16, 0.5, "fp64")
+    before = {k: v.clone() for k, v in st.items()}
+    for kind, cut in [(2, 0.0), (-1, 0.0), (1, -1.0), (1, float("nan")), (1, float("inf"))]:
+        mp = _mdp(p, he)
+        mp.sr_kind, mp.sr_cut = kind, cut
+        with pytest.raises(BHError):
+            bh.md_step(st, mp)
+    torch.cuda.synchronize()
+    for k in before:
+        assert torch.equal(before[k], st[k]), k
 
 
 def test_resume_continues_the_same_trajectory():
