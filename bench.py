@@ -92,7 +92,9 @@ def table1(args, workloads, BarnesHut, allpairs, md_params):
     """Per-step time of the all-pairs and Barnes-Hut paths for N = 10^3 .. 10^6 (the shape of the paper's
     Table 1): random sequential addition at volume fraction 0.1 in a cube, theta 0.5, leaf 16.  AP step =
     all-pairs field and energy gradient (one kernel); BH step = md_step (build, field, adjoint, WCA,
-    integrator); field = all-pairs field alone vs bh_build + bh_field."""
+    integrator) replayed from a HIP graph in the autotuner's launch shape; field = all-pairs field alone vs
+    bh_build + bh_field (eager calls)."""
+    from paper_1212_2934_amd.autotune import autotune
     import ctypes
     import math
     import numpy as np
@@ -101,8 +103,8 @@ def table1(args, workloads, BarnesHut, allpairs, md_params):
     C3 = ctypes.c_double * 3
     print("| N | AP field FP32-mixed ms | AP field FP64 ms | AP step FP32-mixed ms | AP step FP64 ms | "
           "BH field FP32-mixed ms | BH field FP64 ms | BH step FP32-mixed ms | BH step FP64 ms | "
-          "AP/BH step FP32-mixed |")
-    print("|---|---|---|---|---|---|---|---|---|---|")
+          "AP/BH step FP32-mixed | BH tuning FP32-mixed, FP64 |")
+    print("|---|---|---|---|---|---|---|---|---|---|---|")
     for n in (1000, 10000, 100000, 1000000):
         side = (n * math.pi / 6.0 / 0.1) ** (1.0 / 3.0)
         w = workloads.cached(f"uniform_phi0.1_n{n}_seed{3000 + n}",
@@ -120,23 +122,28 @@ def table1(args, workloads, BarnesHut, allpairs, md_params):
             torch.cuda.synchronize()
             return (time.perf_counter() - t0) / reps * 1e3
 
-        row = {}
+        row, tun = {}, {}
         for p in ("fp32_mixed", "fp64"):
             row["apf", p] = timed(lambda: allpairs(pos, mom, precision=p))
             row["aps", p] = timed(lambda: allpairs(pos, mom, precision=p, want_dEdr=True))
-            bh = BarnesHut(n, 1, 16, 0.5, p)
+            tun[p] = autotune(pos, mom, None, 0.5, 16, p)["tuning_id"]
+            bh = BarnesHut(n, 1, 16, 0.5, p, tuning_id=tun[p])
             row["bhf", p] = timed(lambda: (bh.build(pos), bh.field(mom)))
             st = {"pos": pos.clone(), "vel": torch.zeros_like(pos), "mom": mom.clone(),
                   "omega": torch.zeros_like(pos), "step": torch.zeros(1, dtype=torch.int64, device=dev)}
             mdp = md_params(1e-3, 1.0, 0.1, 0.1, 1.0, 0.1, 1.0, 1.0, C3(0.0, 0.0, 0.0), C3(side, side, side),
                             None, 7)
-            row["bhs", p] = timed(lambda: bh.md_step(st, mdp))
+            stream = torch.cuda.Stream()
+            torch.cuda.synchronize()
+            graph = bh.capture_md_graph(st, mdp, stream)
+            row["bhs", p] = timed(lambda: graph.launch(stream))
             assert bh.check_status() == 0
-            del bh
+            del graph, bh
         f = lambda k, p: f"{row[k, p]:.3f}"
         print(f"| {n} | {f('apf', 'fp32_mixed')} | {f('apf', 'fp64')} | {f('aps', 'fp32_mixed')} | "
               f"{f('aps', 'fp64')} | {f('bhf', 'fp32_mixed')} | {f('bhf', 'fp64')} | {f('bhs', 'fp32_mixed')} | "
-              f"{f('bhs', 'fp64')} | {row['aps', 'fp32_mixed'] / row['bhs', 'fp32_mixed']:.2f} |", flush=True)
+              f"{f('bhs', 'fp64')} | {row['aps', 'fp32_mixed'] / row['bhs', 'fp32_mixed']:.2f} | "
+              f"{tun['fp32_mixed']}, {tun['fp64']} |", flush=True)
 
 
 def main():

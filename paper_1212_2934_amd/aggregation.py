@@ -34,6 +34,7 @@ from scipy.sparse.csgraph import connected_components
 from scipy.spatial import cKDTree
 
 from . import workloads
+from .autotune import autotune
 from .binding import BarnesHut, md_params
 
 KB = 1.380649e-23       # J/K
@@ -82,9 +83,9 @@ def temperatures(st, mass, inertia):
 
 
 def run(geometry="cube", batch=1, steps=100000, report=10000, precision="fp32_mixed", theta=0.5, seed=11,
-        eps_over_kT=1.0, **si):
+        eps_over_kT=1.0, tuning="auto", **si):
     """Integrate the geometry from random placement; yields one dict of statistics per report interval
-    (and one for the initial state)."""
+    (and one for the initial state).  tuning: a launch shape, or "auto" for the autotuner's choice."""
     u = reduced_units(**si)
     w = workloads.fig2_cube(batch=batch) if geometry == "cube" else workloads.fig2_monolayer(batch=batch)
     pos = w.pos if w.pos.ndim == 3 else w.pos[None]
@@ -102,7 +103,9 @@ def run(geometry="cube", batch=1, steps=100000, report=10000, precision="fp32_mi
     mdp = md_params(u["dt"], kT, u["gamma_t"], u["gamma_r"], u["mass"], u["inertia"], eps_over_kT * kT, 1.0,
                     C3(*w.box_lo), C3(*w.box_hi), None, seed)
     mdp.sr_kind, mdp.sr_cut = 1, 0.0
-    sim = BarnesHut(n, batch, 16, theta, precision)
+    if tuning == "auto":
+        tuning = autotune(st["pos"], st["mom"], None, theta, 16, precision)["tuning_id"]
+    sim = BarnesHut(n, batch, 16, theta, precision, tuning_id=int(tuning))
     stream = torch.cuda.Stream()
     torch.cuda.synchronize()
 
@@ -115,7 +118,8 @@ def run(geometry="cube", batch=1, steps=100000, report=10000, precision="fp32_mi
                    T_rot=tr / kT, ms_per_step=ms, z_min=float(p[:, 2].min()), z_max=float(p[:, 2].max()))
         return out
 
-    yield {**stats(0, float("nan")), **{"kT": kT, "lambda": u["lambda"], "dt": u["dt"], "n": n, "batch": batch}}
+    yield {**stats(0, float("nan")), **{"kT": kT, "lambda": u["lambda"], "dt": u["dt"], "n": n, "batch": batch,
+                                        "tuning_id": int(tuning)}}
     graph = sim.capture_md_graph(st, mdp, stream)
     done = 0
     while done < steps:
@@ -150,7 +154,7 @@ def main():
                  dtau=a.dtau):
         if s["step"] == 0:
             print(f"<!-- kT {s['kT']:.5f} (lambda {s['lambda']:.3f}), dt {s['dt']:.4g} t0, N {s['n']}, "
-                  f"{s['batch']} realisation(s) -->")
+                  f"{s['batch']} realisation(s), tuning {s['tuning_id']} -->")
         print(f"| {s['step']} | {s['time_Tch']:.1f} | {s['bonded_fraction']:.3f} | {s['bonds_per_particle']:.3f} | "
               f"{s['clusters']:.0f} | {s['mean_cluster_size']:.2f} | {s['largest_cluster']:.0f} | "
               f"{s['branch_fraction']:.3f} | {s['T_trans']:.3f} | {s['T_rot']:.3f} | "

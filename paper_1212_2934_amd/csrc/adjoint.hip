@@ -132,7 +132,7 @@ __global__ __launch_bounds__(512) void k_adjoint(
     const uint32_t *__restrict__ perm, const double *__restrict__ hext, double *__restrict__ g_gather,
     double *__restrict__ g_rm, double *__restrict__ node_adj, double *__restrict__ Hs,
     double *__restrict__ Hout, double *__restrict__ e_part, uint32_t *__restrict__ status, int64_t n, int64_t ntot,
-    int waves_per_seg, int num_waves, double theta2, int max_nodes)
+    int waves_per_seg, int num_waves, double theta2, int max_nodes, int tpw, int parts, double *__restrict__ part_buf)
 {
     using T = typename std::conditional<MIXED, float, double>::type;
     using Src = typename std::conditional<MIXED, Src32, Src64>::type;
@@ -142,9 +142,13 @@ __global__ __launch_bounds__(512) void k_adjoint(
     const int wpb = blockDim.x / kWave;
     const int gw = xcd_block(blockIdx.x, gridDim.x) * wpb + (int)(threadIdx.x / kWave);
     if (gw >= num_waves) return;
-    const int seg = gw / waves_per_seg;
-    const int local = (gw - seg * waves_per_seg) * kWave + lane;
-    const bool valid = local < n;
+    // a wave owns tpw consecutive targets (lanes at and above tpw stay idle) and, with parts > 1, walks
+    // the subtree of one child of the root (part p: child p); the parts' sums meet in k_parts_sum
+    const int per_seg = waves_per_seg * parts;
+    const int seg = gw / per_seg;
+    const int grp = (gw - seg * per_seg) / parts, part = gw - seg * per_seg - grp * parts;
+    const int local = grp * tpw + lane;
+    const bool valid = lane < tpw && local < n;
     const int si = (int)(seg * n) + (valid ? local : 0);
     const double rx = spos[si], ry = spos[ntot + si], rz = spos[2 * ntot + si];
     const T ax = valid ? (T)hbar[si] : (T)0, ay = valid ? (T)hbar[ntot + si] : (T)0,
@@ -161,7 +165,17 @@ __global__ __launch_bounds__(512) void k_adjoint(
     for (int j = 0; j < 6; ++j) W.acc[lane][j] = (T)0;
 
     LaneStack st;
-    st.init(seg, 1, ballot(valid));
+    if (parts == 1) {
+        st.init(seg, 1, ballot(valid));
+    } else {
+        // the root holds every target of the system, so it is always opened: start at child `part` (a leaf
+        // root is walked by part 0 alone)
+        const NodeRec r = nodes[seg];
+        const bool leaf_root = r.nchild == 0;
+        const int first = leaf_root ? seg : r.child + part;
+        const int cnt = leaf_root ? (part == 0 ? 1 : 0) : (part < r.nchild ? 1 : 0);
+        st.init(first, cnt, ballot(valid));
+    }
     int guard = max_nodes;  // a wave visits each node at most once
     while (st.more()) {
         uint64_t mask;
@@ -234,6 +248,14 @@ __global__ __launch_bounds__(512) void k_adjoint(
         hx += (double)phx; hy += (double)phy; hz += (double)phz;
     }
     if (ballot(coincident) != 0ull && lane == 0) set_flag(status, BH_FLAG_COINCIDENT);
+    if (parts > 1) {
+        if (valid) {
+            double *q = part_buf + (int64_t)part * 6 * ntot;
+            q[si] = grx; q[ntot + si] = gry; q[2 * ntot + si] = grz;
+            q[3 * ntot + si] = hx; q[4 * ntot + si] = hy; q[5 * ntot + si] = hz;
+        }
+        return;
+    }
 
     double e = 0.0;
     if (valid) {
@@ -258,6 +280,47 @@ __global__ __launch_bounds__(512) void k_adjoint(
             out[2 * n + i] = hz;
         }
     }
+}
+
+// Sum of the parts of a split adjoint walk for every target, in part order (so the result does not depend
+// on scheduling): gathered dL/dr, forward field (sorted order and caller order), and per-wave energy
+// partials of 64 targets.  Grid: (ceil(n / 256), B) workgroups of 256.
+__global__ __launch_bounds__(256) void k_parts_sum(const double *__restrict__ part_buf, int parts,
+                                                   const double *__restrict__ smom, const double *__restrict__ hext,
+                                                   const uint32_t *__restrict__ perm, double *__restrict__ g_gather,
+                                                   double *__restrict__ Hs, double *__restrict__ Hout,
+                                                   double *__restrict__ e_part, int64_t n, int64_t ntot)
+{
+    const int64_t local = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int seg = blockIdx.y;
+    const bool valid = local < n;
+    const int64_t si = (int64_t)seg * n + (valid ? local : 0);
+    double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (valid)
+        for (int p = 0; p < parts; ++p)
+#pragma unroll
+            for (int c = 0; c < 6; ++c) v[c] += part_buf[((int64_t)p * 6 + c) * ntot + si];
+    double e = 0.0;
+    if (valid) {
+        const double mx = smom[si], my = smom[ntot + si], mz = smom[2 * ntot + si];
+        e = -0.5 * (mx * v[3] + my * v[4] + mz * v[5]);
+        if (hext) e -= mx * hext[3 * seg] + my * hext[3 * seg + 1] + mz * hext[3 * seg + 2];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            g_gather[c * ntot + si] = v[c];
+            Hs[c * ntot + si] = v[3 + c];
+        }
+        const int64_t i = (int64_t)perm[si] - (int64_t)seg * n;
+        if (Hout && i >= 0 && i < n) {
+            double *out = Hout + (int64_t)seg * 3 * n;
+            out[i] = v[3];
+            out[n + i] = v[4];
+            out[2 * n + i] = v[5];
+        }
+    }
+    e = wave_sum(e);
+    const int64_t wps = (n + kWave - 1) / kWave;
+    if ((threadIdx.x & (kWave - 1)) == 0 && local < n) e_part[(int64_t)seg * wps + local / kWave] = e;
 }
 
 // Two targets per lane: a wave owns 128 consecutive targets (lane l: targets l and 64 + l of its range).
@@ -719,7 +782,6 @@ hipError_t launch_backward(Handle &h, const double *d_mom, const double *d_hext,
                        w.status + 2, L.max_nodes);
     hipLaunchKernelGGL(k_zero, dim3(grid_for(8 * L.ntot, 256, 4096)), dim3(256), 0, s, w.g_rm, 8 * L.ntot);
     const int wpb = h.waves_per_block;
-    const unsigned blocks = (unsigned)((L.num_waves + wpb - 1) / wpb);
     const int waves_per_seg = (int)((L.n + kWave - 1) / kWave);
     const double theta2 = h.p.theta * h.p.theta;
     if (h.ev[2]) (void)hipEventRecord(h.ev[2], s);
@@ -751,18 +813,29 @@ hipError_t launch_backward(Handle &h, const double *d_mom, const double *d_hext,
             hipLaunchKernelGGL(k_adjoint2<false>, dim3(blocks2), dim3(wpb * kWave), 0, s, w.nodes, w.node_m64, w.spos,
                                w.smom, w.src64, w.hbar, w.perm, d_hext, w.g_gather, w.g_rm, w.node_adj, w.Hs, d_H,
                                w.e_part, w.status, L.n, L.ntot, wps2, nw2, theta2, (int)L.max_nodes);
-    } else if (mixed)
-        hipLaunchKernelGGL(k_adjoint<true>, dim3(blocks), dim3(wpb * kWave), wpb * sizeof(AdjLds<float>), s, w.nodes, w.node_m64, w.spos,
-                           w.smom, w.src32, w.hbar, w.perm, d_hext, w.g_gather, w.g_rm, w.node_adj, w.Hs, d_H,
-                           w.e_part, w.status, L.n, L.ntot, waves_per_seg, (int)L.num_waves, theta2,
-                           (int)L.max_nodes);
-    else
-        hipLaunchKernelGGL(k_adjoint<false>, dim3(blocks), dim3(wpb * kWave), wpb * sizeof(AdjLds<double>), s, w.nodes, w.node_m64, w.spos,
-                           w.smom, w.src64, w.hbar, w.perm, d_hext, w.g_gather, w.g_rm, w.node_adj, w.Hs, d_H,
-                           w.e_part, w.status, L.n, L.ntot, waves_per_seg, (int)L.num_waves, theta2,
-                           (int)L.max_nodes);
+    } else {
+        const int tpw = h.adj_tpw, parts = h.adj_parts;
+        const int wps = (int)((L.n + tpw - 1) / tpw);
+        const int nwv = (int)(L.B * wps * parts);
+        const unsigned blk = (unsigned)((nwv + wpb - 1) / wpb);
+        if (mixed)
+            hipLaunchKernelGGL(k_adjoint<true>, dim3(blk), dim3(wpb * kWave), wpb * sizeof(AdjLds<float>), s, w.nodes,
+                               w.node_m64, w.spos, w.smom, w.src32, w.hbar, w.perm, d_hext, w.g_gather, w.g_rm,
+                               w.node_adj, w.Hs, d_H, w.e_part, w.status, L.n, L.ntot, wps, nwv, theta2,
+                               (int)L.max_nodes, tpw, parts, w.part_buf);
+        else
+            hipLaunchKernelGGL(k_adjoint<false>, dim3(blk), dim3(wpb * kWave), wpb * sizeof(AdjLds<double>), s,
+                               w.nodes, w.node_m64, w.spos, w.smom, w.src64, w.hbar, w.perm, d_hext, w.g_gather,
+                               w.g_rm, w.node_adj, w.Hs, d_H, w.e_part, w.status, L.n, L.ntot, wps, nwv, theta2,
+                               (int)L.max_nodes, tpw, parts, w.part_buf);
+        if (parts > 1)
+            hipLaunchKernelGGL(k_parts_sum, dim3((unsigned)((L.n + 255) / 256), (unsigned)L.B), dim3(256), 0, s,
+                               w.part_buf, parts, w.smom, d_hext, w.perm, w.g_gather, w.Hs, d_H, w.e_part, L.n,
+                               L.ntot);
+    }
     if (h.ev[3]) (void)hipEventRecord(h.ev[3], s);
-    if (d_E) launch_energy_final(h, d_E, s, h.adj_two && nw <= 1 ? 2 * kWave : kWave);
+    if (d_E)
+        launch_energy_final(h, d_E, s, nw > 1 || h.adj_parts > 1 ? kWave : h.adj_two ? 2 * kWave : h.adj_tpw);
     hipLaunchKernelGGL(k_downward, dim3(grid_for(L.ntot, 256)), dim3(256), 0, s, w.nodes, w.leaf_of, w.node_adj,
                        w.g_gather, w.g_rm, w.Hs, d_hext, d_gE, w.perm, L.n, L.ntot, d_dpos, d_dmom,
                        L.max_nodes);

@@ -8,11 +8,19 @@ namespace ffbh {
 static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // Traversal launch shapes selectable by tuning_id: waves per workgroup of the independent-wave
-// traversals, and how many waves walk the adjoint traversal together (1 = independently).
-static const int kTuneWaves[] = {4, 1, 2, 8, 4, 4, 4, 2};
-static const int kTuneCoop[] = {1, 1, 1, 1, 2, 4, 1, 1};
-static const int kTuneTwo[] = {0, 0, 0, 0, 0, 0, 1, 1};  // adjoint waves own two targets per lane
+// traversals, how many waves walk the adjoint traversal together (1 = independently), whether adjoint
+// waves own two targets per lane, and how many targets an independent adjoint wave owns (fewer than 64
+// gives small systems more walks in flight).
+static const int kTuneWaves[] = {4, 1, 2, 8, 4, 4, 4, 2, 4, 4, 4, 4, 4};
+static const int kTuneCoop[] = {1, 1, 1, 1, 2, 4, 1, 1, 1, 1, 1, 1, 1};
+static const int kTuneTwo[] = {0, 0, 0, 0, 0, 0, 1, 1, 0, 0, 0, 0, 0};
+static const int kTuneTpw[] = {64, 64, 64, 64, 64, 64, 64, 64, 32, 16, 64, 32, 16};
+// independent adjoint waves split each walk over the root's children (8 parts) or not (1)
+static const int kTuneParts[] = {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 8, 8, 8};
 static const int kNumTunings = (int)(sizeof(kTuneWaves) / sizeof(kTuneWaves[0]));
+static_assert(sizeof(kTuneCoop) == sizeof(kTuneWaves) && sizeof(kTuneTwo) == sizeof(kTuneWaves) &&
+                  sizeof(kTuneTpw) == sizeof(kTuneWaves) && sizeof(kTuneParts) == sizeof(kTuneWaves),
+              "one entry per tuning in every table");
 
 Layout plan_layout(const bh_params &p)
 {
@@ -21,7 +29,13 @@ Layout plan_layout(const bh_params &p)
     L.B = p.batch;
     L.ntot = L.n * L.B;
     L.max_nodes = 2 * L.ntot + L.B;
-    L.tiles = (L.n + kSortTile - 1) / kSortTile;
+    const int tid = p.tuning_id < 0 || p.tuning_id >= kNumTunings ? 0 : p.tuning_id;
+    L.adj_parts = kTuneParts[tid] > 1 ? kTuneParts[tid] : 0;
+    // radix-sort tiles of 256 x sort_items keys: 16 items per thread once there are 2^20 keys, fewer
+    // below so that a pass still spreads over about 256 workgroups
+    const int64_t items = (L.ntot + 65535) / 65536;
+    L.sort_items = (int)(items < 1 ? 1 : items > kSortItems ? kSortItems : items);
+    L.tiles = (L.n + (int64_t)kSortThreads * L.sort_items - 1) / ((int64_t)kSortThreads * L.sort_items);
     L.hist_len = L.B * kRadixBins * L.tiles;
     L.bin_int = L.B * (L.n - 1);
     L.num_waves = L.B * ((L.n + kWave - 1) / kWave);
@@ -82,7 +96,7 @@ void carve(const Layout &Lc, void *base, Workspace &w)
     w.lvl = (uint32_t *)take(4 * 128);
     w.lvl_nodes = (int32_t *)take(4 * mn);
     w.leaf_of = (int32_t *)take(4 * nt);
-    w.e_part = (double *)take(8 * (size_t)L.num_waves);
+    w.e_part = (double *)take(8 * (size_t)(L.B * ((L.n + kMinTpw - 1) / kMinTpw)));  // waves of kMinTpw targets
     w.node_adj = (double *)take(8 * 8 * mn);
     w.g_gather = (double *)take(3 * 8 * nt);
     w.g_rm = (double *)take(8 * 8 * nt);
@@ -93,6 +107,7 @@ void carve(const Layout &Lc, void *base, Workspace &w)
     w.md_grad_r = (double *)take(3 * 8 * nt);
     w.md_grad_m = (double *)take(3 * 8 * nt);
     w.cell_first = (uint32_t *)take(4 * (size_t)L.B * (size_t)L.cell_T);
+    w.part_buf = (double *)take(6 * 8 * nt * (size_t)L.adj_parts);  // split-walk partial sums (parts > 1)
     L.bytes = align_up(off, 256);
 }
 
@@ -196,6 +211,8 @@ bh_status bh_create(const bh_params *p, void *d_workspace, size_t workspace_byte
     h.waves_per_block = kTuneWaves[p->tuning_id < 0 ? 0 : p->tuning_id];
     h.adj_coop = kTuneCoop[p->tuning_id < 0 ? 0 : p->tuning_id];
     h.adj_two = kTuneTwo[p->tuning_id < 0 ? 0 : p->tuning_id];
+    h.adj_tpw = kTuneTpw[p->tuning_id < 0 ? 0 : p->tuning_id];
+    h.adj_parts = kTuneParts[p->tuning_id < 0 ? 0 : p->tuning_id];
     h.cnt_far = h.cnt_near = nullptr;
     for (int k = 0; k < 4; ++k) h.ev[k] = nullptr;
     hipLaunchKernelGGL(k_init, dim3(1), dim3(256), 0, 0, h.w.status, h.w.ones, (int64_t)L.B);

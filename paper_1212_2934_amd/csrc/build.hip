@@ -125,13 +125,14 @@ __global__ __launch_bounds__(256) void k_morton(const double *__restrict__ pos, 
 // ------------------------------------------------------------------------------------------------
 
 __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint64_t *__restrict__ keys, int64_t n,
-                                                             int tiles, int shift,
+                                                             int tiles, int items, int shift,
                                                              uint32_t *__restrict__ hist)
 {
     __shared__ uint32_t cnt[kRadixBins];
     const int b = blockIdx.x / tiles, t = blockIdx.x - b * tiles;
-    const int64_t lo = (int64_t)b * n + (int64_t)t * kSortTile;
-    const int64_t hi = min(lo + (int64_t)kSortTile, (int64_t)(b + 1) * n);
+    const int64_t tile = (int64_t)kSortThreads * items;
+    const int64_t lo = (int64_t)b * n + (int64_t)t * tile;
+    const int64_t hi = min(lo + tile, (int64_t)(b + 1) * n);
     cnt[threadIdx.x] = 0;
     __syncthreads();
     for (int64_t i = lo + threadIdx.x; i < hi; i += kSortThreads)
@@ -225,29 +226,125 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_apply(uint32_t *__restric
     }
 }
 
+// Inclusive scan over the 64 lanes of a wave.
+__device__ inline uint32_t wave_incl_scan_u32(uint32_t v, int lane)
+{
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const uint32_t x = __shfl_up(v, off, kWave);
+        if (lane >= off) v += x;
+    }
+    return v;
+}
+
+// Exclusive scan of a short array (len <= kScanSmallMax) in one launch of one workgroup: chunks of
+// 8192 entries pass through LDS (coalesced loads and stores); each thread scans a run of 8 consecutive
+// entries, offset by a wave scan and the wave totals.  LDS index j is padded to j + j/32 against bank
+// conflicts of the strided run accesses.
+constexpr int kScanSmallThreads = 1024;
+constexpr int kScanSmallItems = 8;
+constexpr int kScanSmallChunk = kScanSmallThreads * kScanSmallItems;
+constexpr int64_t kScanSmallMax = 4 * (int64_t)kScanSmallChunk;
+
+__device__ inline int scan_pad(int j) { return j + (j >> 5); }
+
+__global__ __launch_bounds__(kScanSmallThreads) void k_scan_small(uint32_t *__restrict__ a, int64_t len,
+                                                                  uint32_t *__restrict__ total_out)
+{
+    constexpr int kWaves = kScanSmallThreads / kWave;
+    __shared__ uint32_t tile[kScanSmallChunk + kScanSmallChunk / 32];
+    __shared__ uint32_t wsum[kWaves];
+    const int t = threadIdx.x, lane = t & (kWave - 1), wave = t / kWave;
+    uint32_t carry = 0;
+    for (int64_t base = 0; base < len; base += kScanSmallChunk) {
+#pragma unroll
+        for (int k = 0; k < kScanSmallItems; ++k) {
+            const int j = k * kScanSmallThreads + t;
+            tile[scan_pad(j)] = base + j < len ? a[base + j] : 0u;
+        }
+        __syncthreads();
+        uint32_t run = 0;
+#pragma unroll
+        for (int k = 0; k < kScanSmallItems; ++k) run += tile[scan_pad(t * kScanSmallItems + k)];
+        const uint32_t incl = wave_incl_scan_u32(run, lane);
+        if (lane == kWave - 1) wsum[wave] = incl;
+        __syncthreads();
+        uint32_t woff = 0, ctot = 0;
+        for (int w = 0; w < kWaves; ++w) {
+            const uint32_t x = wsum[w];
+            woff += w < wave ? x : 0u;
+            ctot += x;
+        }
+        uint32_t off = carry + woff + incl - run;
+#pragma unroll
+        for (int k = 0; k < kScanSmallItems; ++k) {
+            const int j = scan_pad(t * kScanSmallItems + k);
+            const uint32_t v = tile[j];
+            tile[j] = off;
+            off += v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kScanSmallItems; ++k) {
+            const int j = k * kScanSmallThreads + t;
+            if (base + j < len) a[base + j] = tile[scan_pad(j)];
+        }
+        carry += ctot;
+        __syncthreads();  // tile and wsum are rewritten by the next chunk
+    }
+    if (t == 0 && total_out) *total_out = carry;
+}
+
 // Exclusive scan in place; writes the total to *total if not null.  scratch: one uint32 per tile.
 static void scan_excl(uint32_t *a, int64_t len, uint32_t *scratch, uint32_t *total, hipStream_t s)
 {
+    if (len <= kScanSmallMax) {
+        hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(kScanSmallThreads), 0, s, a, len, total);
+        return;
+    }
     const int ntiles = (int)((len + kScanTile - 1) / kScanTile);
     hipLaunchKernelGGL(k_scan_tiles, dim3(ntiles), dim3(kScanThreads), 0, s, a, len, scratch);
     hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanThreads), 0, s, scratch, ntiles, total);
     hipLaunchKernelGGL(k_scan_apply, dim3(ntiles), dim3(kScanThreads), 0, s, a, len, scratch);
 }
 
+constexpr int kFusedTiles = 128;
+
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint64_t *__restrict__ kout,
-    uint32_t *__restrict__ vout, const uint32_t *__restrict__ hist, int64_t n, int tiles, int shift, int64_t ntot)
+    uint32_t *__restrict__ vout, const uint32_t *__restrict__ hist, int64_t n, int tiles, int items, int shift,
+    int64_t ntot, int fused)
 {
     constexpr int kWaves = kSortThreads / kWave;
     __shared__ uint32_t base[kRadixBins];
     __shared__ uint32_t wcnt[kWaves][kRadixBins];
+    __shared__ uint32_t dsum[kWaves];
     const int b = blockIdx.x / tiles, t = blockIdx.x - b * tiles;
-    const int64_t lo = (int64_t)b * n + (int64_t)t * kSortTile;
-    const int64_t hi = min(lo + (int64_t)kSortTile, (int64_t)(b + 1) * n);
+    const int64_t tile = (int64_t)kSortThreads * items;
+    const int64_t lo = (int64_t)b * n + (int64_t)t * tile;
+    const int64_t hi = min(lo + tile, (int64_t)(b + 1) * n);
     const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
-    base[tid] = hist[((int64_t)b * kRadixBins + tid) * tiles + t];
-    for (int r = 0; r < kSortItems; ++r) {
+    if (fused) {
+        // hist holds raw counts: the offset of (digit, tile t) is the system's start, plus the keys of
+        // smaller digits, plus this digit's keys in earlier tiles
+        const uint32_t *hd = hist + ((int64_t)b * kRadixBins + tid) * tiles;
+        uint32_t pre = 0, tot = 0;
+        for (int u = 0; u < tiles; ++u) {
+            const uint32_t c = hd[u];
+            tot += c;
+            pre += u < t ? c : 0u;
+        }
+        const uint32_t incl = wave_incl_scan_u32(tot, lane);
+        if (lane == kWave - 1) dsum[wave] = incl;
+        __syncthreads();
+        uint32_t woff = 0;
+        for (int w = 0; w < wave; ++w) woff += dsum[w];
+        base[tid] = (uint32_t)((int64_t)b * n) + woff + incl - tot + pre;
+    } else {
+        base[tid] = hist[((int64_t)b * kRadixBins + tid) * tiles + t];
+    }
+    for (int r = 0; r < items; ++r) {
         for (int w = 0; w < kWaves; ++w) wcnt[w][tid] = 0u;
         __syncthreads();
         const int64_t idx = lo + (int64_t)r * kSortThreads + tid;
@@ -639,6 +736,80 @@ __global__ void k_zero_u32(uint32_t *a, int len)
 // MODE 2: both in one pass (vals = positions, vals2 = moments).  Child sums are read from `sums` (8 doubles
 // per node: position sums at 0..2, moment sums at 4..6).
 template <int MODE>
+__device__ inline void upward_node(uint32_t q, const double *__restrict__ vals, const double *__restrict__ vals2,
+                                   int64_t ntot, int64_t n, NodeRec *__restrict__ nodes, double *__restrict__ sums,
+                                   double *__restrict__ node_m64, const int32_t *__restrict__ node_level,
+                                   const int32_t *__restrict__ lvl_nodes, const double *__restrict__ bbox,
+                                   int64_t max_nodes)
+{
+    const int id = lvl_nodes[q];
+    if (id < 0 || id >= max_nodes) return;
+    const NodeRec nd = nodes[id];
+    if (nd.first < 0 || nd.count < 1 || (int64_t)nd.first + nd.count > ntot ||
+        (nd.nchild != 0 && (nd.child < 0 || (int64_t)nd.child + nd.nchild > max_nodes)))
+        return;
+    const int o = MODE == 1 ? 4 : 0;  // slot of the (first) sum
+    double sx = 0.0, sy = 0.0, sz = 0.0, mx = 0.0, my = 0.0, mz = 0.0;
+    if (nd.nchild == 0) {
+        for (int k = nd.first; k < nd.first + nd.count; ++k) {
+            sx = sx + vals[k];
+            sy = sy + vals[ntot + k];
+            sz = sz + vals[2 * ntot + k];
+            if (MODE == 2) {
+                mx = mx + vals2[k];
+                my = my + vals2[ntot + k];
+                mz = mz + vals2[2 * ntot + k];
+            }
+        }
+    } else {
+        for (int c = nd.child; c < nd.child + nd.nchild; ++c) {
+            sx = sx + sums[8 * c + o];
+            sy = sy + sums[8 * c + o + 1];
+            sz = sz + sums[8 * c + o + 2];
+            if (MODE == 2) {
+                mx = mx + sums[8 * c + 4];
+                my = my + sums[8 * c + 5];
+                mz = mz + sums[8 * c + 6];
+            }
+        }
+    }
+    if (MODE == 1) {
+        mx = sx; my = sy; mz = sz;
+    }
+    sums[8 * id + o] = sx;
+    sums[8 * id + o + 1] = sy;
+    sums[8 * id + o + 2] = sz;
+    if (MODE == 2) {
+        sums[8 * id + 4] = mx;
+        sums[8 * id + 5] = my;
+        sums[8 * id + 6] = mz;
+    }
+    if (MODE != 1) {
+        const double cnt = (double)nd.count;
+        nodes[id].cx = sx / cnt;
+        nodes[id].cy = sy / cnt;
+        nodes[id].cz = sz / cnt;
+        const double side = __builtin_ldexp(bbox[8 * (nd.first / n) + 3], -node_level[id]);
+        nodes[id].s2 = side * side;
+    }
+    if (MODE != 0) {
+        node_m64[4 * id] = mx;
+        node_m64[4 * id + 1] = my;
+        node_m64[4 * id + 2] = mz;
+        nodes[id].mx = (float)mx;
+        nodes[id].my = (float)my;
+        nodes[id].mz = (float)mz;
+    }
+}
+
+// Level bucket [b0, b1) of the level-sorted node list.
+__device__ inline void level_range(const uint32_t *lvl, int level, int64_t max_nodes, uint32_t &b0, uint32_t &b1)
+{
+    b0 = lvl[32 + level];
+    b1 = (int64_t)lvl[32 + level + 1] < max_nodes ? lvl[32 + level + 1] : (uint32_t)max_nodes;
+}
+
+template <int MODE>
 __global__ __launch_bounds__(256) void k_upward_level(const double *__restrict__ vals,
                                                       const double *__restrict__ vals2, int64_t ntot, int64_t n,
                                                       NodeRec *__restrict__ nodes, double *__restrict__ sums,
@@ -649,67 +820,32 @@ __global__ __launch_bounds__(256) void k_upward_level(const double *__restrict__
                                                       const double *__restrict__ bbox, int level,
                                                       int64_t max_nodes)
 {
-    const uint32_t b0 = lvl[32 + level];
-    const uint32_t b1 = (int64_t)lvl[32 + level + 1] < max_nodes ? lvl[32 + level + 1] : (uint32_t)max_nodes;
-    for (uint32_t q = b0 + blockIdx.x * 256 + threadIdx.x; q < b1; q += gridDim.x * 256) {
-        const int id = lvl_nodes[q];
-        if (id < 0 || id >= max_nodes) continue;
-        const NodeRec nd = nodes[id];
-        if (nd.first < 0 || nd.count < 1 || (int64_t)nd.first + nd.count > ntot ||
-            (nd.nchild != 0 && (nd.child < 0 || (int64_t)nd.child + nd.nchild > max_nodes)))
-            continue;
-        const int o = MODE == 1 ? 4 : 0;  // slot of the (first) sum
-        double sx = 0.0, sy = 0.0, sz = 0.0, mx = 0.0, my = 0.0, mz = 0.0;
-        if (nd.nchild == 0) {
-            for (int k = nd.first; k < nd.first + nd.count; ++k) {
-                sx = sx + vals[k];
-                sy = sy + vals[ntot + k];
-                sz = sz + vals[2 * ntot + k];
-                if (MODE == 2) {
-                    mx = mx + vals2[k];
-                    my = my + vals2[ntot + k];
-                    mz = mz + vals2[2 * ntot + k];
-                }
-            }
-        } else {
-            for (int c = nd.child; c < nd.child + nd.nchild; ++c) {
-                sx = sx + sums[8 * c + o];
-                sy = sy + sums[8 * c + o + 1];
-                sz = sz + sums[8 * c + o + 2];
-                if (MODE == 2) {
-                    mx = mx + sums[8 * c + 4];
-                    my = my + sums[8 * c + 5];
-                    mz = mz + sums[8 * c + 6];
-                }
-            }
-        }
-        if (MODE == 1) {
-            mx = sx; my = sy; mz = sz;
-        }
-        sums[8 * id + o] = sx;
-        sums[8 * id + o + 1] = sy;
-        sums[8 * id + o + 2] = sz;
-        if (MODE == 2) {
-            sums[8 * id + 4] = mx;
-            sums[8 * id + 5] = my;
-            sums[8 * id + 6] = mz;
-        }
-        if (MODE != 1) {
-            const double cnt = (double)nd.count;
-            nodes[id].cx = sx / cnt;
-            nodes[id].cy = sy / cnt;
-            nodes[id].cz = sz / cnt;
-            const double side = __builtin_ldexp(bbox[8 * (nd.first / n) + 3], -node_level[id]);
-            nodes[id].s2 = side * side;
-        }
-        if (MODE != 0) {
-            node_m64[4 * id] = mx;
-            node_m64[4 * id + 1] = my;
-            node_m64[4 * id + 2] = mz;
-            nodes[id].mx = (float)mx;
-            nodes[id].my = (float)my;
-            nodes[id].mz = (float)mz;
-        }
+    uint32_t b0, b1;
+    level_range(lvl, level, max_nodes, b0, b1);
+    for (uint32_t q = b0 + blockIdx.x * 256 + threadIdx.x; q < b1; q += gridDim.x * 256)
+        upward_node<MODE>(q, vals, vals2, ntot, n, nodes, sums, node_m64, node_level, lvl_nodes, bbox, max_nodes);
+}
+
+// Every level in one workgroup, deepest first, a barrier between levels (the children's sums are written
+// by this workgroup before their parents read them): for small trees, where the per-level launches of
+// k_upward_level would cost more than the work.
+constexpr int kUpwardOneThreads = 1024;
+constexpr int64_t kUpwardOneMaxNodes = 1 << 16;
+
+template <int MODE>
+__global__ __launch_bounds__(kUpwardOneThreads) void k_upward_all(
+    const double *__restrict__ vals, const double *__restrict__ vals2, int64_t ntot, int64_t n,
+    NodeRec *__restrict__ nodes, double *__restrict__ sums, double *__restrict__ node_m64,
+    const int32_t *__restrict__ node_level, const uint32_t *__restrict__ lvl, const int32_t *__restrict__ lvl_nodes,
+    const double *__restrict__ bbox, int64_t max_nodes)
+{
+    for (int level = kMaxLevel; level >= 0; --level) {
+        uint32_t b0, b1;
+        level_range(lvl, level, max_nodes, b0, b1);
+        for (uint32_t q = b0 + threadIdx.x; q < b1; q += kUpwardOneThreads)
+            upward_node<MODE>(q, vals, vals2, ntot, n, nodes, sums, node_m64, node_level, lvl_nodes, bbox,
+                              max_nodes);
+        __syncthreads();
     }
 }
 
@@ -718,6 +854,11 @@ static void upward(Handle &h, const double *vals, const double *vals2, hipStream
 {
     const Layout &L = h.L;
     Workspace &w = h.w;
+    if (L.max_nodes <= kUpwardOneMaxNodes) {
+        hipLaunchKernelGGL(k_upward_all<MODE>, dim3(1), dim3(kUpwardOneThreads), 0, s, vals, vals2, L.ntot, L.n,
+                           w.nodes, w.node_adj, w.node_m64, w.node_level, w.lvl, w.lvl_nodes, w.bbox, L.max_nodes);
+        return;
+    }
     const unsigned g = grid_for(L.max_nodes, 256, 512);
     for (int level = kMaxLevel; level >= 0; --level)
         hipLaunchKernelGGL(k_upward_level<MODE>, dim3(g), dim3(256), 0, s, vals, vals2, L.ntot, L.n, w.nodes,
@@ -754,10 +895,13 @@ hipError_t launch_build(Handle &h, const double *d_pos, hipStream_t s, const dou
         const int src = pass & 1, dst = src ^ 1;
         const int shift = pass * kRadixBits;
         hipLaunchKernelGGL(k_radix_hist, dim3(sblocks), dim3(kSortThreads), 0, s, w.keys[src], n, tiles,
-                           shift, w.hist);
-        scan_excl(w.hist, (int64_t)L.hist_len, w.scan_tmp, nullptr, s);
+                           L.sort_items, shift, w.hist);
+        // up to kFusedTiles tiles per system the scatter derives its offsets from the raw counts
+        const int fused = tiles <= kFusedTiles;
+        if (!fused) scan_excl(w.hist, (int64_t)L.hist_len, w.scan_tmp, nullptr, s);
         hipLaunchKernelGGL(k_radix_scatter, dim3(sblocks), dim3(kSortThreads), 0, s, w.keys[src],
-                           w.vals[src], w.keys[dst], w.vals[dst], w.hist, n, tiles, shift, ntot);
+                           w.vals[src], w.keys[dst], w.vals[dst], w.hist, n, tiles, L.sort_items, shift, ntot,
+                           fused);
     }
     // kRadixPasses is even: the sorted data is back in buffer 0
     hipLaunchKernelGGL(k_gather3, dim3(grid_for(ntot, 256)), dim3(256), 0, s, d_pos, w.perm, n, ntot,

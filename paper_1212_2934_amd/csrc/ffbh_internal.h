@@ -18,8 +18,8 @@ constexpr int kRadixBits = 8;
 constexpr int kRadixBins = 1 << kRadixBits;
 constexpr int kRadixPasses = 8;                 // 8 x 8 bits cover the 63-bit codes
 constexpr int kSortThreads = 256;
-constexpr int kSortItems = 16;                  // keys per thread per tile
-constexpr int kSortTile = kSortThreads * kSortItems;
+constexpr int kSortItems = 16;                  // most keys per thread per tile
+constexpr int kMinTpw = 16;                     // fewest targets an adjoint wave owns
 constexpr int kStackMax = 64;                   // one traversal stack entry per lane of a wave
 
 // Node record read by the traversal: one 64-byte line, fetched with a single scalar load.
@@ -67,6 +67,7 @@ struct Workspace {
     int32_t *node_level;     // max_nodes: cell level (side = side_root / 2^level)
     double *node_m64;        // 4 x max_nodes: moment sum FP64 (x, y, z, pad) per node
     uint32_t *cell_first;    // short-range grid: first sorted particle of each cell (B x cell_T)
+    double *part_buf;        // (parts, 6, ntot) partial sums of split adjoint walks
     double *ones;            // B: constant 1.0 (dL/dE for the MD force)
     uint32_t *arrive;        // max_nodes: (unused) arrival counters
     uint32_t *lvl;           // 128: per-level node counts [0,22), bucket starts [32,55), cursors [64,86)
@@ -89,6 +90,8 @@ constexpr int kBboxBlocks = 512;  // partial bounding boxes per system (two work
 
 struct Layout {
     int64_t n, B, ntot, max_nodes, tiles, num_waves, hist_len, bin_int;
+    int sort_items;         // keys per thread per radix-sort tile (1..kSortItems)
+    int adj_parts;          // parts of a split adjoint walk that the workspace holds (0: none)
     int cell_lcap;       // finest level of the short-range cell grid
     int64_t cell_T;      // grid entries per system, 2^(3 cell_lcap)
     size_t bytes;
@@ -107,6 +110,8 @@ struct Handle {
     int waves_per_block; // traversal launch shape
     int adj_coop;        // waves walking the adjoint traversal together (1: independent waves)
     int adj_two;         // adjoint waves own two targets per lane
+    int adj_tpw;         // targets per independent adjoint wave (16, 32 or 64)
+    int adj_parts;       // independent adjoint walks split over the root's children (8) or not (1)
     int32_t *cnt_far, *cnt_near;  // optional per-target counters (device)
     hipEvent_t ev[4];             // optional timing events around the traversal kernels
 };

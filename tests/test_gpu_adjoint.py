@@ -33,7 +33,9 @@ def _gpu_grad(pos, mom, hext, theta, precision, gH=None, gE=1.0, leaf=16, want_d
     return [None if o is None else o.cpu().numpy() for o in out]
 
 
-@pytest.mark.parametrize("tuning_id", [0, 4, 5, 6])  # independent waves; 2 and 4 waves together; two targets per lane
+# independent waves; 2 and 4 waves together; two targets per lane; 32 and 16 targets per wave; each walk
+# split over the root's children, with 64, 32 and 16 targets per wave
+@pytest.mark.parametrize("tuning_id", [0, 4, 5, 6, 8, 9, 10, 11, 12])
 @pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
 def test_energy_gradient_config1(oracle_mod, precision, tuning_id):
     w = workloads.uniform_cube(4096, 32.0, seed=1001, hext=(0.0, 0.0, 1.0))
@@ -44,7 +46,7 @@ def test_energy_gradient_config1(oracle_mod, precision, tuning_id):
     np.testing.assert_allclose(gdh[0], -w.mom.sum(axis=1), rtol=1e-12)
 
 
-@pytest.mark.parametrize("tuning_id", [0, 5, 7])
+@pytest.mark.parametrize("tuning_id", [0, 5, 7, 9, 11])
 @pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
 @pytest.mark.parametrize("theta", [0.3, 0.7])
 def test_general_vjp_chains(oracle_mod, precision, theta, tuning_id):
@@ -70,7 +72,7 @@ def test_theta_zero_equals_allpairs_force(oracle_mod):
     assert rel(gdm, -oracle_mod.allpairs_field(w.pos, w.mom)) <= 1e-12
 
 
-@pytest.mark.parametrize("tuning_id", [0, 4, 5, 6])
+@pytest.mark.parametrize("tuning_id", [0, 4, 5, 6, 9, 10, 12])
 def test_batched_adjoint(oracle_mod, tuning_id):
     B, n = 3, 2000 + 77  # ragged: the last workgroup of each system is partly empty
     ws = [workloads.uniform_cube(n, 26.0, seed=30 + b) for b in range(B)]
@@ -81,6 +83,21 @@ def test_batched_adjoint(oracle_mod, tuning_id):
     for b, x in enumerate(ws):
         _, _, dr, dm = oracle_mod.Tree(x.pos, x.mom, 16).energy_grad(0.5, hext)
         assert rel(gdr[b], dr) <= 1e-5 and rel(gdm[b], dm) <= 1e-5
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 16, 17, 65, 300])
+@pytest.mark.parametrize("tuning_id", [0, 10])
+def test_small_systems(oracle_mod, n, tuning_id):
+    """Down to a single particle and a root that is a leaf (n <= 16), where a split walk has one part."""
+    w = workloads.uniform_cube(n, 4.0 + n ** (1.0 / 3.0) * 2.0, seed=60 + n, hext=(0.3, 0.0, 0.5))
+    H, E, dr, dm = oracle_mod.Tree(w.pos, w.mom, 16).energy_grad(0.5, w.hext)
+    gdr, gdm = _gpu_grad(w.pos, w.mom, w.hext, 0.5, "fp64", tuning_id=tuning_id)
+    if n == 1:
+        assert np.abs(gdr).max() == 0.0
+        np.testing.assert_allclose(gdm, dm, rtol=1e-14)
+        return
+    assert rel(gdr, dr) <= 1e-12
+    assert rel(gdm, dm) <= 1e-12
 
 
 def test_invariants_at_full_size_c4():

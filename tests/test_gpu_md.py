@@ -40,13 +40,17 @@ def _params(side, hext=(0.0, 0.0, 0.5)):
                 box_lo=(0.0, 0.0, 0.0), box_hi=(side, side, side), hext=np.array([hext]), seed=2002)
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32_mixed", 1e-8)])
-def test_trajectory_matches_reference(precision, tol):
+@pytest.mark.parametrize("precision,tol,tuning_id", [("fp64", 1e-11, -1), ("fp32_mixed", 1e-8, -1),
+                                                     ("fp64", 1e-11, 9), ("fp32_mixed", 1e-8, 9),
+                                                     ("fp64", 1e-11, 10), ("fp32_mixed", 1e-8, 11)])
+def test_trajectory_matches_reference(precision, tol, tuning_id):
+    """tuning 9: adjoint waves of 16 targets; 10 and 11: walks split over the root's children (the
+    small-system launch shapes)."""
     w = workloads.uniform_cube(1500, 20.0, seed=4)
     rng = np.random.default_rng(5)
     st = _state(w, rng)
     p = _params(20.0)
-    bh = BarnesHut(w.n, 1, 16, 0.5, precision)
+    bh = BarnesHut(w.n, 1, 16, 0.5, precision, tuning_id=tuning_id)
     d = _to_dev(st)
     he = torch.from_numpy(p["hext"]).cuda()
     mp = _mdp(p, he)

@@ -39,7 +39,8 @@ def _compare(pos, mom, leaf, oracle_mod, offset=0, gtree=None):
 
 
 @pytest.mark.parametrize("n,side,leaf,seed", [(4096, 32.0, 16, 1001), (5000, 36.0, 4, 7),
-                                             (777, 20.0, 1, 8), (20000 + 37, 60.0, 16, 9)])
+                                             (777, 20.0, 1, 8), (20000 + 37, 60.0, 16, 9),
+                                             (32000 + 11, 80.0, 16, 10), (40000 + 3, 85.0, 16, 11)])
 def test_tree_matches_oracle(oracle_mod, n, side, leaf, seed):
     w = workloads.uniform_cube(n, side, seed)
     out = run_field(w.pos, w.mom, leaf=leaf, counters=False)
