@@ -53,6 +53,8 @@ def lib():
         L.or_tree_num_nodes.restype = i64
         L.or_tree_export.argtypes = [P] + [P] * 13
         L.or_bh_field.argtypes = [P, C.c_double, P, P, P]
+        L.or_bh_field_order.argtypes = [P, C.c_double, C.c_int, P, P, P]
+        L.or_tree_export_D.argtypes = [P, P]
         L.or_bh_field_subset.argtypes = [P, C.c_double, i64, P, P, P, P]
         L.or_bh_lists.argtypes = [P, C.c_double, P, P, P, P]
         L.or_bh_vjp.argtypes = [P, C.c_double, P, P, P]
@@ -145,13 +147,23 @@ class Tree:
         lib().or_tree_export(self._h, *[_p(d[k]) for k in keys])
         return d
 
-    def field(self, theta: float):
-        """(H (3, n), n_far (n,), n_near (n,)) for every particle."""
+    def field(self, theta: float, order: int = 1):
+        """(H (3, n), n_far (n,), n_near (n,)) for every particle.  order 1: the paper's pseudo-particles
+        (Eq. magCenter); order 2: plus the first-moment term of every accepted cell (beyond the paper)."""
         H = np.empty((3, self.n))
         nf = np.empty(self.n, np.int64)
         nr = np.empty(self.n, np.int64)
-        assert lib().or_bh_field(self._h, theta, _p(H), _p(nf), _p(nr)) == 0
+        if order == 1:
+            assert lib().or_bh_field(self._h, theta, _p(H), _p(nf), _p(nr)) == 0
+        else:
+            assert lib().or_bh_field_order(self._h, theta, order, _p(H), _p(nf), _p(nr)) == 0
         return H, nf, nr
+
+    def first_moments(self):
+        """(nn, 3, 3): D[c, k, b] = sum over the members j of cell c of (r_j - c_c)_k m_j,b."""
+        D = np.empty((self.num_nodes, 3, 3))
+        lib().or_tree_export_D(self._h, _p(D))
+        return D
 
     def field_subset(self, theta: float, targets):
         t = np.ascontiguousarray(targets, dtype=np.int64)

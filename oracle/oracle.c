@@ -199,6 +199,7 @@ typedef struct or_tree {
     int64_t *child;      /* 8 per node, first nchild used, octant order */
     double *S, *M, *c;   /* per node, 3 each: position sum, moment sum, centroid */
     double *s2;          /* per node: squared side of the cell */
+    double *D;           /* per node, 9: first moment D[3k+b] = sum_j (r_j - c)_k m_j,b (order-2 cells) */
 } or_tree;
 
 static uint64_t interleave(uint32_t qx, uint32_t qy, uint32_t qz)
@@ -303,12 +304,35 @@ static void upward_rec(or_tree *t, int64_t id)
     t->s2[id] = s * s;
 }
 
+/* First moment of every cell about its pseudo-particle position (beyond the paper: the next term of the
+ * cell's expansion, used by the order-2 field).  Taylor-expanding Eq. (H_dip) of a member j at offset
+ * x - delta_j (x = r_i - c, delta_j = r_j - c) gives
+ *     sum_j T(x - delta_j) m_j = T(x) M - sum_{k,b} d_k T_ab(x) D_kb + O(|delta|^2),
+ *     D_kb = sum_j delta_j,k m_j,b ,
+ * the first term being the paper's pseudo-particle.  D is formed here straight from that definition,
+ * member by member in sorted order, for every cell.                                                    */
+static void first_moments(or_tree *t)
+{
+    int64_t n = t->n;
+    t->D = malloc(9 * t->nn * sizeof(double));
+    for (int64_t id = 0; id < t->nn; ++id) {
+        double D[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        for (int64_t k = t->first[id]; k < t->first[id] + t->count[id]; ++k) {
+            int64_t j = t->perm[k];
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b)
+                    D[3 * a + b] += (t->pos[a * n + j] - t->c[3 * id + a]) * t->mom[b * n + j];
+        }
+        memcpy(&t->D[9 * id], D, sizeof(D));
+    }
+}
+
 void or_tree_free(or_tree *t)
 {
     if (!t) return;
     free(t->pos); free(t->mom); free(t->code); free(t->perm); free(t->rank);
     free(t->level); free(t->nchild); free(t->first); free(t->count); free(t->parent); free(t->child);
-    free(t->S); free(t->M); free(t->c); free(t->s2);
+    free(t->S); free(t->M); free(t->c); free(t->s2); free(t->D);
     free(t);
 }
 
@@ -361,6 +385,7 @@ or_tree *or_tree_build(int64_t n, const double *pos, const double *mom, int leaf
     t->c = malloc(3 * t->nn * sizeof(double));
     t->s2 = malloc(t->nn * sizeof(double));
     upward_rec(t, 0);
+    first_moments(t);
     return t;
 }
 
@@ -391,6 +416,12 @@ void or_tree_export(const or_tree *t, double *bbox, uint64_t *code, int64_t *per
     if (s2) memcpy(s2, t->s2, nn * sizeof(double));
 }
 
+/* First moments of every cell, (nn, 9) row-major D[3k+b]. */
+void or_tree_export_D(const or_tree *t, double *D)
+{
+    memcpy(D, t->D, 9 * t->nn * sizeof(double));
+}
+
 /* ------------------------------------------------------------------------------------------------ */
 /* Traversal (Sec. 3.2): starting at the root, a cell that is far enough from the target is replaced  */
 /* by its pseudo-particle; otherwise its sub-cells are examined, down to the leaves, whose particles  */
@@ -405,6 +436,7 @@ void or_tree_export(const or_tree *t, double *bbox, uint64_t *code, int64_t *per
 typedef struct {
     const or_tree *t;
     double theta2;
+    int order;       /* 1: the paper's pseudo-particle; 2: plus the first-moment term (forward only) */
     int64_t si;      /* target's sorted position */
     double ri[3];
     /* forward */
@@ -419,6 +451,26 @@ typedef struct {
     int64_t *far_out, *near_out;
 } visit_ctx;
 
+/* Field of a cell's first moment D at offset x from its pseudo-particle: h_a = -sum_{k,b} d_k T_ab(x) D_kb
+ * with T_ab(x) = 3 x_a x_b / |x|^5 - delta_ab / |x|^3 (the tensor of Eq. H_dip), whose derivative is
+ *     d_k T_ab = 3 (delta_ak x_b + delta_bk x_a + delta_ab x_k) / |x|^5 - 15 x_a x_b x_k / |x|^7 ,
+ * so that, with u = D x (u_a = sum_b D_ab x_b), w = D^T x, tr D and q = x.D x,
+ *     h = -3 (u + w + x tr D) / |x|^5 + 15 q x / |x|^7 .                                              */
+static void first_moment_field(const double x[3], const double D[9], double h[3])
+{
+    double r2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
+    double r = sqrt(r2);
+    double r5 = r2 * r2 * r;
+    double r7 = r5 * r2;
+    double u[3], w[3], tr = D[0] + D[4] + D[8], q = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        u[a] = D[3 * a] * x[0] + D[3 * a + 1] * x[1] + D[3 * a + 2] * x[2];
+        w[a] = D[a] * x[0] + D[3 + a] * x[1] + D[6 + a] * x[2];
+    }
+    for (int a = 0; a < 3; ++a) q += x[a] * u[a];
+    for (int a = 0; a < 3; ++a) h[a] = -3.0 * (u[a] + w[a] + x[a] * tr) / r5 + 15.0 * q * x[a] / r7;
+}
+
 static void do_far(visit_ctx *v, int64_t id)
 {
     const or_tree *t = v->t;
@@ -429,6 +481,10 @@ static void do_far(visit_ctx *v, int64_t id)
     if (!v->hbar) {
         dip_field(x, &t->M[3 * id], h);
         for (int a = 0; a < 3; ++a) v->H[a] += h[a];
+        if (v->order == 2) {
+            first_moment_field(x, &t->D[9 * id], h);
+            for (int a = 0; a < 3; ++a) v->H[a] += h[a];
+        }
     } else {
         double g[3];
         grad_kernel(x, v->hbar, &t->M[3 * id], g);
@@ -500,6 +556,7 @@ static void ctx_init(visit_ctx *v, const or_tree *t, double theta, int64_t i)
 {
     memset(v, 0, sizeof(*v));
     v->t = t;
+    v->order = 1;
     v->theta2 = theta * theta;
     v->si = t->rank[i];
     load3(t->pos, t->n, i, v->ri);
@@ -514,6 +571,25 @@ int or_bh_field(const or_tree *t, double theta, double *H, int64_t *n_far, int64
     for (int64_t i = 0; i < n; ++i) {
         visit_ctx v;
         ctx_init(&v, t, theta, i);
+        visit(&v, 0);
+        for (int a = 0; a < 3; ++a) H[a * n + i] = v.H[a];
+        if (n_far) n_far[i] = v.n_far;
+        if (n_near) n_near[i] = v.n_near;
+    }
+    return 0;
+}
+
+/* Barnes-Hut field with cells of the given order (1: Eq. magCenter pseudo-particles, the paper's
+ * scheme; 2: plus each accepted cell's first-moment term), all particles, original order. */
+int or_bh_field_order(const or_tree *t, double theta, int order, double *H, int64_t *n_far, int64_t *n_near)
+{
+    if (!t || !(theta >= 0.0) || (order != 1 && order != 2)) return -1;
+    int64_t n = t->n;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < n; ++i) {
+        visit_ctx v;
+        ctx_init(&v, t, theta, i);
+        v.order = order;
         visit(&v, 0);
         for (int a = 0; a < 3; ++a) H[a * n + i] = v.H[a];
         if (n_far) n_far[i] = v.n_far;
