@@ -146,6 +146,53 @@ def table1(args, workloads, BarnesHut, allpairs, md_params):
               f"{tun['fp32_mixed']}, {tun['fp64']} |", flush=True)
 
 
+def accuracy(args, workloads, BarnesHut, allpairs):
+    """Field accuracy against cost at N = 2^20 (the benchmark's chain workload): for each theta, the
+    paper's pseudo-particles (order 1) and cells with their first moment (order 2).  Error = relative L2
+    and 99.9th percentile per particle against the FP64 all-pairs sum; time = build + field (eager calls,
+    synchronised, best of 5) and the forward traversal kernel alone (HIP events around it)."""
+    import torch
+    dev = torch.device("cuda", 0)
+    w = workloads.cached("chains_n1048576_seed1003", lambda: workloads.config3())
+    n = w.n
+    pos = torch.from_numpy(w.pos).to(dev)
+    mom = torch.from_numpy(w.mom).to(dev)
+    ref = allpairs(pos, mom, precision="fp64")[0]
+
+    def err(H):
+        d = torch.linalg.vector_norm(H - ref, dim=0)
+        r = torch.linalg.vector_norm(ref, dim=0)
+        per = d / torch.clamp(r, min=1e-3 * torch.sqrt(torch.mean(r * r)))
+        return ((torch.linalg.vector_norm(H - ref) / torch.linalg.vector_norm(ref)).item(),
+                torch.quantile(per[torch.randperm(per.numel(), device=dev)[:1 << 16]], 0.999).item())
+
+    print("| theta | cells | precision | rel. L2 error | 99.9th pct error | build + field ms | traversal ms |")
+    print("|---|---|---|---|---|---|---|")
+    for theta in (0.3, 0.4, 0.5, 0.6, 0.7, 0.8):
+        for order in (1, 2):
+            for precision in ("fp32_mixed", "fp64"):
+                bh = BarnesHut(n, 1, 16, theta, precision, expansion=order)
+                ev = HipEvents(4)
+                bh.set_raw_timing_events(ev.ev)
+                bh.build(pos)
+                H = bh.field(mom, energy=False)
+                torch.cuda.synchronize()
+                best, kern = float("inf"), float("inf")
+                for _ in range(5):
+                    t0 = time.perf_counter()
+                    bh.build(pos)
+                    bh.field(mom, energy=False)
+                    torch.cuda.synchronize()
+                    best = min(best, (time.perf_counter() - t0) * 1e3)
+                    kern = min(kern, ev.seconds(0, 1) * 1e3)
+                bh.set_raw_timing_events(None)
+                assert bh.check_status() == 0
+                e2, e999 = err(H)
+                print(f"| {theta} | {'order ' + str(order)} | {precision} | {e2:.3e} | {e999:.3e} | {best:.3f} | "
+                      f"{kern:.3f} |", flush=True)
+                del bh, H
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -156,6 +203,8 @@ def main():
     ap.add_argument("--no-slab", action="store_true")
     ap.add_argument("--table1", action="store_true",
                     help="print the all-pairs vs Barnes-Hut per-step sweep over N (the paper's Table 1) and exit")
+    ap.add_argument("--accuracy", action="store_true",
+                    help="print field error against cost over theta for order-1 and order-2 cells and exit")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="finish with one plain device copy of MIB MiB (a reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -174,6 +223,9 @@ def main():
 
     if args.table1:
         table1(args, workloads, BarnesHut, allpairs, md_params)
+        return
+    if args.accuracy:
+        accuracy(args, workloads, BarnesHut, allpairs)
         return
 
     log("generating workload (2^20 chains, phi 0.1)")

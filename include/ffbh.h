@@ -45,7 +45,8 @@ typedef int32_t bh_status;
 
 enum {
     BH_OK = 0,
-    BH_EINVAL = -1,       /* bad argument (null pointer, n < 1, theta < 0, leaf_size outside 1..64) */
+    BH_EINVAL = -1,       /* bad argument (null pointer, n < 1, theta < 0, leaf_size outside 1..64),
+                             or a call the handle's parameters do not support                        */
     BH_EWORKSPACE = -2,   /* workspace missing, misaligned or smaller than bh_workspace_bytes       */
     BH_EDEVICE = -3,      /* a HIP runtime call failed                                              */
     BH_EDEGENERATE = -4,  /* bh_check_status: the device flagged degenerate input                   */
@@ -72,6 +73,10 @@ typedef struct bh_params {
     int32_t precision;  /* BH_FP64: all arithmetic FP64.  BH_FP32_MIXED: pair arithmetic in FP32 on
                            FP64 offsets, FP64 acceptance test, FP64 cell sums and accumulation        */
     int32_t tuning_id;  /* traversal launch shape (see bh_num_tunings); -1 = default                  */
+    int32_t expansion;  /* cells of bh_field: 0 or 1 = the paper's pseudo-particles (Eq. magCenter);
+                           2 = plus each accepted cell's first moment D = sum_j (r_j - c) m_j^T, the next
+                           term of the Taylor expansion of Eq. H_dip about c (beyond the paper; error one
+                           power of theta lower).  bh_field_backward and md_step require 0 or 1.       */
 } bh_params;
 
 typedef struct bh_handle bh_handle;

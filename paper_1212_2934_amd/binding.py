@@ -23,7 +23,8 @@ PRECISIONS = {"fp64": FP64, "fp32_mixed": FP32_MIXED}
 
 class bh_params(C.Structure):
     _fields_ = [("n", C.c_int64), ("batch", C.c_int32), ("leaf_size", C.c_int32),
-                ("theta", C.c_double), ("precision", C.c_int32), ("tuning_id", C.c_int32)]
+                ("theta", C.c_double), ("precision", C.c_int32), ("tuning_id", C.c_int32),
+                ("expansion", C.c_int32)]
 
 
 class md_state(C.Structure):
@@ -116,9 +117,10 @@ def _dev64(t, shape=None, name="tensor"):
     return t
 
 
-def make_params(n, batch=1, leaf_size=16, theta=0.5, precision="fp32_mixed", tuning_id=-1):
+def make_params(n, batch=1, leaf_size=16, theta=0.5, precision="fp32_mixed", tuning_id=-1, expansion=1):
+    """expansion 1: the paper's pseudo-particles; 2: plus each accepted cell's first moment (field only)."""
     return bh_params(int(n), int(batch), int(leaf_size), float(theta), PRECISIONS[precision],
-                     int(tuning_id))
+                     int(tuning_id), int(expansion))
 
 
 def workspace_bytes(params: bh_params) -> int:
@@ -135,8 +137,8 @@ class BarnesHut:
     """
 
     def __init__(self, n, batch=1, leaf_size=16, theta=0.5, precision="fp32_mixed", tuning_id=-1,
-                 device=None):
-        self.params = make_params(n, batch, leaf_size, theta, precision, tuning_id)
+                 device=None, expansion=1):
+        self.params = make_params(n, batch, leaf_size, theta, precision, tuning_id, expansion)
         self.n, self.batch = int(n), int(batch)
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None \
             else torch.device(device)

@@ -31,6 +31,7 @@ Layout plan_layout(const bh_params &p)
     L.max_nodes = 2 * L.ntot + L.B;
     const int tid = p.tuning_id < 0 || p.tuning_id >= kNumTunings ? 0 : p.tuning_id;
     L.adj_parts = kTuneParts[tid] > 1 ? kTuneParts[tid] : 0;
+    L.expansion = p.expansion == 2 ? 2 : 1;
     // radix-sort tiles of 256 x sort_items keys: 16 items per thread once there are 2^20 keys, fewer
     // below so that a pass still spreads over about 256 workgroups
     const int64_t items = (L.ntot + 65535) / 65536;
@@ -108,6 +109,9 @@ void carve(const Layout &Lc, void *base, Workspace &w)
     w.md_grad_m = (double *)take(3 * 8 * nt);
     w.cell_first = (uint32_t *)take(4 * (size_t)L.B * (size_t)L.cell_T);
     w.part_buf = (double *)take(6 * 8 * nt * (size_t)L.adj_parts);  // split-walk partial sums (parts > 1)
+    const size_t qn = L.expansion == 2 ? mn : 0;  // first moments only for order-2 cells
+    w.node_q64 = (double *)take(16 * 8 * qn);
+    w.node_q32 = (float *)take(16 * 4 * qn);
     L.bytes = align_up(off, 256);
 }
 
@@ -120,6 +124,7 @@ static bool params_ok(const bh_params *p)
     if (!(p->theta >= 0.0) || !__builtin_isfinite(p->theta)) return false;
     if (p->precision != BH_FP64 && p->precision != BH_FP32_MIXED) return false;
     if (p->tuning_id < -1 || p->tuning_id >= kNumTunings) return false;
+    if (p->expansion < 0 || p->expansion > 2) return false;
     return true;
 }
 
@@ -256,6 +261,7 @@ bh_status bh_field_backward(bh_handle *hh, const double *d_mom, const double *d_
     if ((d_hext && !dptr_ok(d_hext)) || (d_gH && !dptr_ok(d_gH)) || (d_gE && !dptr_ok(d_gE)) ||
         (d_dhext && !dptr_ok(d_dhext)))
         return BH_EINVAL;
+    if (hh->h.L.expansion == 2) return BH_EINVAL;  // the adjoint follows the paper's cells only
     if (!hh->h.built) return BH_ESTATE;
     if (launch_backward(hh->h, d_mom, d_hext, d_gH, d_gE, d_dpos, d_dmom, d_dhext, (hipStream_t)stream) !=
         hipSuccess)
@@ -277,6 +283,7 @@ bh_status md_step(bh_handle *hh, const md_state *s, const md_params *p, void *st
 static bh_status md_args_ok(bh_handle *hh, const md_state *s, const md_params *p)
 {
     if (!hh || !s || !p) return BH_EINVAL;
+    if (hh->h.L.expansion == 2) return BH_EINVAL;  // forces follow the paper's cells only
     if (!dptr_ok(s->pos) || !dptr_ok(s->vel) || !dptr_ok(s->mom) || !dptr_ok(s->omega) || !dptr_ok(s->d_step))
         return BH_EINVAL;
     if (!(p->dt > 0.0) || !(p->mass > 0.0) || !(p->inertia > 0.0) || !(p->kT >= 0.0) || !(p->gamma_t >= 0.0) ||

@@ -735,12 +735,16 @@ __global__ void k_zero_u32(uint32_t *a, int len)
 // MODE 0: member positions -> centroids and s^2; MODE 1: member moments -> FP64 and FP32 moment sums;
 // MODE 2: both in one pass (vals = positions, vals2 = moments).  Child sums are read from `sums` (8 doubles
 // per node: position sums at 0..2, moment sums at 4..6).
+// MODE 0: position sums and centres; 1: moment sums; 2: both; 3: moment sums and first moments
+// D = sum_j (r_j - c) m_j^T about the centre c (vals = moments, vals2 = positions; centres from MODE 0/2):
+// a leaf sums its members in sorted order, a parent adds its children's D shifted to its own centre,
+// D_child + (c_child - c) M_child^T, in octant order.
 template <int MODE>
 __device__ inline void upward_node(uint32_t q, const double *__restrict__ vals, const double *__restrict__ vals2,
                                    int64_t ntot, int64_t n, NodeRec *__restrict__ nodes, double *__restrict__ sums,
                                    double *__restrict__ node_m64, const int32_t *__restrict__ node_level,
                                    const int32_t *__restrict__ lvl_nodes, const double *__restrict__ bbox,
-                                   int64_t max_nodes)
+                                   int64_t max_nodes, double *__restrict__ q64, float *__restrict__ q32)
 {
     const int id = lvl_nodes[q];
     if (id < 0 || id >= max_nodes) return;
@@ -748,8 +752,33 @@ __device__ inline void upward_node(uint32_t q, const double *__restrict__ vals, 
     if (nd.first < 0 || nd.count < 1 || (int64_t)nd.first + nd.count > ntot ||
         (nd.nchild != 0 && (nd.child < 0 || (int64_t)nd.child + nd.nchild > max_nodes)))
         return;
-    const int o = MODE == 1 ? 4 : 0;  // slot of the (first) sum
+    const int o = MODE == 1 || MODE == 3 ? 4 : 0;  // slot of the (first) sum
     double sx = 0.0, sy = 0.0, sz = 0.0, mx = 0.0, my = 0.0, mz = 0.0;
+    double D[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (MODE == 3) {
+        const double c[3] = {nd.cx, nd.cy, nd.cz};
+        if (nd.nchild == 0) {
+            for (int k = nd.first; k < nd.first + nd.count; ++k) {
+                const double d[3] = {vals2[k] - c[0], vals2[ntot + k] - c[1], vals2[2 * ntot + k] - c[2]};
+                const double m[3] = {vals[k], vals[ntot + k], vals[2 * ntot + k]};
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+#pragma unroll
+                    for (int b = 0; b < 3; ++b) D[3 * a + b] = D[3 * a + b] + d[a] * m[b];
+            }
+        } else {
+            for (int ch = nd.child; ch < nd.child + nd.nchild; ++ch) {
+                const NodeRec cn = nodes[ch];
+                const double d[3] = {cn.cx - c[0], cn.cy - c[1], cn.cz - c[2]};
+                const double m[3] = {sums[8 * ch + 4], sums[8 * ch + 5], sums[8 * ch + 6]};
+                const double *dc = q64 + 16 * (int64_t)ch;
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+#pragma unroll
+                    for (int b = 0; b < 3; ++b) D[3 * a + b] = D[3 * a + b] + (dc[3 * a + b] + d[a] * m[b]);
+            }
+        }
+    }
     if (nd.nchild == 0) {
         for (int k = nd.first; k < nd.first + nd.count; ++k) {
             sx = sx + vals[k];
@@ -773,8 +802,15 @@ __device__ inline void upward_node(uint32_t q, const double *__restrict__ vals, 
             }
         }
     }
-    if (MODE == 1) {
+    if (MODE == 1 || MODE == 3) {
         mx = sx; my = sy; mz = sz;
+    }
+    if (MODE == 3) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            q64[16 * (int64_t)id + k] = D[k];
+            q32[16 * (int64_t)id + k] = (float)D[k];
+        }
     }
     sums[8 * id + o] = sx;
     sums[8 * id + o + 1] = sy;
@@ -784,7 +820,7 @@ __device__ inline void upward_node(uint32_t q, const double *__restrict__ vals, 
         sums[8 * id + 5] = my;
         sums[8 * id + 6] = mz;
     }
-    if (MODE != 1) {
+    if (MODE == 0 || MODE == 2) {
         const double cnt = (double)nd.count;
         nodes[id].cx = sx / cnt;
         nodes[id].cy = sy / cnt;
@@ -818,12 +854,14 @@ __global__ __launch_bounds__(256) void k_upward_level(const double *__restrict__
                                                       const uint32_t *__restrict__ lvl,
                                                       const int32_t *__restrict__ lvl_nodes,
                                                       const double *__restrict__ bbox, int level,
-                                                      int64_t max_nodes)
+                                                      int64_t max_nodes, double *__restrict__ q64,
+                                                      float *__restrict__ q32)
 {
     uint32_t b0, b1;
     level_range(lvl, level, max_nodes, b0, b1);
     for (uint32_t q = b0 + blockIdx.x * 256 + threadIdx.x; q < b1; q += gridDim.x * 256)
-        upward_node<MODE>(q, vals, vals2, ntot, n, nodes, sums, node_m64, node_level, lvl_nodes, bbox, max_nodes);
+        upward_node<MODE>(q, vals, vals2, ntot, n, nodes, sums, node_m64, node_level, lvl_nodes, bbox, max_nodes,
+                          q64, q32);
 }
 
 // Every level in one workgroup, deepest first, a barrier between levels (the children's sums are written
@@ -837,14 +875,14 @@ __global__ __launch_bounds__(kUpwardOneThreads) void k_upward_all(
     const double *__restrict__ vals, const double *__restrict__ vals2, int64_t ntot, int64_t n,
     NodeRec *__restrict__ nodes, double *__restrict__ sums, double *__restrict__ node_m64,
     const int32_t *__restrict__ node_level, const uint32_t *__restrict__ lvl, const int32_t *__restrict__ lvl_nodes,
-    const double *__restrict__ bbox, int64_t max_nodes)
+    const double *__restrict__ bbox, int64_t max_nodes, double *__restrict__ q64, float *__restrict__ q32)
 {
     for (int level = kMaxLevel; level >= 0; --level) {
         uint32_t b0, b1;
         level_range(lvl, level, max_nodes, b0, b1);
         for (uint32_t q = b0 + threadIdx.x; q < b1; q += kUpwardOneThreads)
             upward_node<MODE>(q, vals, vals2, ntot, n, nodes, sums, node_m64, node_level, lvl_nodes, bbox,
-                              max_nodes);
+                              max_nodes, q64, q32);
         __syncthreads();
     }
 }
@@ -856,13 +894,15 @@ static void upward(Handle &h, const double *vals, const double *vals2, hipStream
     Workspace &w = h.w;
     if (L.max_nodes <= kUpwardOneMaxNodes) {
         hipLaunchKernelGGL(k_upward_all<MODE>, dim3(1), dim3(kUpwardOneThreads), 0, s, vals, vals2, L.ntot, L.n,
-                           w.nodes, w.node_adj, w.node_m64, w.node_level, w.lvl, w.lvl_nodes, w.bbox, L.max_nodes);
+                           w.nodes, w.node_adj, w.node_m64, w.node_level, w.lvl, w.lvl_nodes, w.bbox, L.max_nodes,
+                           w.node_q64, w.node_q32);
         return;
     }
     const unsigned g = grid_for(L.max_nodes, 256, 512);
     for (int level = kMaxLevel; level >= 0; --level)
         hipLaunchKernelGGL(k_upward_level<MODE>, dim3(g), dim3(256), 0, s, vals, vals2, L.ntot, L.n, w.nodes,
-                           w.node_adj, w.node_m64, w.node_level, w.lvl, w.lvl_nodes, w.bbox, level, L.max_nodes);
+                           w.node_adj, w.node_m64, w.node_level, w.lvl, w.lvl_nodes, w.bbox, level, L.max_nodes,
+                           w.node_q64, w.node_q32);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -974,7 +1014,10 @@ static void gather_moments(Handle &h, const double *d_mom, hipStream_t s)
 hipError_t launch_upward_moments(Handle &h, const double *d_mom, hipStream_t s)
 {
     gather_moments(h, d_mom, s);
-    upward<1>(h, h.w.smom, nullptr, s);
+    if (h.L.expansion == 2)
+        upward<3>(h, h.w.smom, h.w.spos, s);
+    else
+        upward<1>(h, h.w.smom, nullptr, s);
     return hipGetLastError();
 }
 

@@ -68,6 +68,8 @@ struct Workspace {
     double *node_m64;        // 4 x max_nodes: moment sum FP64 (x, y, z, pad) per node
     uint32_t *cell_first;    // short-range grid: first sorted particle of each cell (B x cell_T)
     double *part_buf;        // (parts, 6, ntot) partial sums of split adjoint walks
+    double *node_q64;        // max_nodes x 16: first moment D (row-major 3x3, then pad) per node, FP64
+    float *node_q32;         // max_nodes x 16: the same rounded to FP32 (mixed-precision traversal)
     double *ones;            // B: constant 1.0 (dL/dE for the MD force)
     uint32_t *arrive;        // max_nodes: (unused) arrival counters
     uint32_t *lvl;           // 128: per-level node counts [0,22), bucket starts [32,55), cursors [64,86)
@@ -92,6 +94,7 @@ struct Layout {
     int64_t n, B, ntot, max_nodes, tiles, num_waves, hist_len, bin_int;
     int sort_items;         // keys per thread per radix-sort tile (1..kSortItems)
     int adj_parts;          // parts of a split adjoint walk that the workspace holds (0: none)
+    int expansion;          // 2: first moments are kept (order-2 cells); else 1
     int cell_lcap;       // finest level of the short-range cell grid
     int64_t cell_T;      // grid entries per system, 2^(3 cell_lcap)
     size_t bytes;

@@ -62,14 +62,15 @@ __device__ inline void field_leaf(FieldLds<T> &W, int lane, const Src *__restric
     }
 }
 
-template <bool MIXED, bool COUNT>
+// QUAD: accepted cells add their first-moment term (order-2 cells; node_q holds D per node, stride 16).
+template <bool MIXED, bool COUNT, bool QUAD>
 __global__ __launch_bounds__(512) void k_field(
     const NodeRec *__restrict__ nodes, const double *__restrict__ node_m64, const double *__restrict__ spos,
     const double *__restrict__ smom, const void *__restrict__ src, const uint32_t *__restrict__ perm,
     const double *__restrict__ hext, double *__restrict__ H, double *__restrict__ Hs,
     double *__restrict__ e_part, int32_t *__restrict__ cnt_far, int32_t *__restrict__ cnt_near,
     uint32_t *__restrict__ status, int64_t n, int64_t ntot, int waves_per_seg, int num_waves,
-    double theta2, int max_nodes)
+    double theta2, int max_nodes, const void *__restrict__ node_q)
 {
     using T = typename std::conditional<MIXED, float, double>::type;
     using Src = typename std::conditional<MIXED, Src32, Src64>::type;
@@ -122,6 +123,11 @@ __global__ __launch_bounds__(512) void k_field(
             } else {
                 const double *m = node_m64 + 4 * (int64_t)cur;
                 dip_acc<double>(acc, dx, dy, dz, m[0], m[1], m[2], hx, hy, hz);
+            }
+            if (QUAD) {
+                const T *D = (const T *)node_q + 16 * (int64_t)cur;
+                if (MIXED) first_moment_acc<T>(acc, (T)dx, (T)dy, (T)dz, D, px, py, pz);
+                else first_moment_acc<double>(acc, dx, dy, dz, (const double *)D, hx, hy, hz);
             }
             if (COUNT) nfar += acc ? 1 : 0;
         }
@@ -208,7 +214,7 @@ __global__ __launch_bounds__(256) void k_energy_final(const double *__restrict__
     if (threadIdx.x == 0) E[b] = red[0];
 }
 
-template <bool MIXED, bool COUNT>
+template <bool MIXED, bool COUNT, bool QUAD>
 static void launch_k_field(Handle &h, const double *d_hext, double *d_H, hipStream_t s)
 {
     const Layout &L = h.L;
@@ -220,9 +226,11 @@ static void launch_k_field(Handle &h, const double *d_hext, double *d_H, hipStre
     const void *src = MIXED ? (const void *)w.src32 : (const void *)w.src64;
     using T = typename std::conditional<MIXED, float, double>::type;
     const size_t lds = (size_t)wpb * sizeof(FieldLds<T>);
-    hipLaunchKernelGGL((k_field<MIXED, COUNT>), dim3(blocks), dim3(wpb * kWave), lds, s, w.nodes,
+    const void *q = MIXED ? (const void *)w.node_q32 : (const void *)w.node_q64;
+    hipLaunchKernelGGL((k_field<MIXED, COUNT, QUAD>), dim3(blocks), dim3(wpb * kWave), lds, s, w.nodes,
                        w.node_m64, w.spos, w.smom, src, w.perm, d_hext, d_H, w.Hs, w.e_part,
-                       h.cnt_far, h.cnt_near, w.status, L.n, L.ntot, waves_per_seg, (int)L.num_waves, theta2, (int)L.max_nodes);
+                       h.cnt_far, h.cnt_near, w.status, L.n, L.ntot, waves_per_seg, (int)L.num_waves, theta2,
+                       (int)L.max_nodes, q);
 }
 
 hipError_t launch_field(Handle &h, const double *d_mom, const double *d_hext, double *d_H, double *d_E,
@@ -233,10 +241,17 @@ hipError_t launch_field(Handle &h, const double *d_mom, const double *d_hext, do
     const bool mixed = h.p.precision == BH_FP32_MIXED;
     const bool cnt = h.cnt_far != nullptr;
     if (h.ev[0]) (void)hipEventRecord(h.ev[0], s);
-    if (mixed && cnt) launch_k_field<true, true>(h, d_hext, d_H, s);
-    else if (mixed) launch_k_field<true, false>(h, d_hext, d_H, s);
-    else if (cnt) launch_k_field<false, true>(h, d_hext, d_H, s);
-    else launch_k_field<false, false>(h, d_hext, d_H, s);
+    if (h.L.expansion == 2) {
+        if (mixed && cnt) launch_k_field<true, true, true>(h, d_hext, d_H, s);
+        else if (mixed) launch_k_field<true, false, true>(h, d_hext, d_H, s);
+        else if (cnt) launch_k_field<false, true, true>(h, d_hext, d_H, s);
+        else launch_k_field<false, false, true>(h, d_hext, d_H, s);
+    } else {
+        if (mixed && cnt) launch_k_field<true, true, false>(h, d_hext, d_H, s);
+        else if (mixed) launch_k_field<true, false, false>(h, d_hext, d_H, s);
+        else if (cnt) launch_k_field<false, true, false>(h, d_hext, d_H, s);
+        else launch_k_field<false, false, false>(h, d_hext, d_H, s);
+    }
     if (h.ev[1]) (void)hipEventRecord(h.ev[1], s);
     if (d_E) launch_energy_final(h, d_E, s, kWave);
     return hipGetLastError();

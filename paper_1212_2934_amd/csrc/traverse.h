@@ -49,6 +49,31 @@ __device__ inline void dip_acc(bool use, T x, T y, T z, T mx, T my, T mz, T &hx,
     hz = fmaT<T>(fmaT<T>(t, z, -mz), ri3, hz);
 }
 
+// Field of a cell's first moment D (row-major, D[3k+b] = sum_j (r_j - c)_k m_j,b) at offset x from the
+// cell's centre c: the next term of the Taylor expansion of Eq. H_dip about c,
+//   h = -3 (D x + D^T x + x tr D) / |x|^5 + 15 (x.D x) x / |x|^7 .
+// When `use` is false the inverse distance is zero and the increment is exactly zero.
+template <typename T>
+__device__ inline void first_moment_acc(bool use, T x, T y, T z, const T *D, T &hx, T &hy, T &hz)
+{
+    const T r2 = fmaT<T>(z, z, fmaT<T>(y, y, x * x));
+    const T ri = use ? rsqT<T>(r2) : (T)0;
+    const T ri2 = ri * ri;
+    const T ri5 = ri2 * ri2 * ri;
+    const T u0 = fmaT<T>(D[2], z, fmaT<T>(D[1], y, D[0] * x));
+    const T u1 = fmaT<T>(D[5], z, fmaT<T>(D[4], y, D[3] * x));
+    const T u2 = fmaT<T>(D[8], z, fmaT<T>(D[7], y, D[6] * x));
+    const T w0 = fmaT<T>(D[6], z, fmaT<T>(D[3], y, D[0] * x));
+    const T w1 = fmaT<T>(D[7], z, fmaT<T>(D[4], y, D[1] * x));
+    const T w2 = fmaT<T>(D[8], z, fmaT<T>(D[5], y, D[2] * x));
+    const T tr = D[0] + D[4] + D[8];
+    const T qd = fmaT<T>(z, u2, fmaT<T>(y, u1, x * u0));
+    const T s = (T)15 * qd * ri2;
+    hx = fmaT<T>(fmaT<T>(s, x, (T)-3 * (u0 + w0 + x * tr)), ri5, hx);
+    hy = fmaT<T>(fmaT<T>(s, y, (T)-3 * (u1 + w1 + y * tr)), ri5, hy);
+    hz = fmaT<T>(fmaT<T>(s, z, (T)-3 * (u2 + w2 + z * tr)), ri5, hz);
+}
+
 // Adjoint pair plus the forward field.  With a = upstream field gradient of the target, b = source
 // moment, x = offset (target minus source):
 //   g  = 3 [ (a.b) x + (b.x) a + (a.x) b ] / |x|^5 - 15 (a.x)(b.x) x / |x|^7   (f_dip summand, Sec. 2)

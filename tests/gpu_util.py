@@ -5,12 +5,13 @@ import torch
 from paper_1212_2934_amd.binding import BarnesHut
 
 
-def run_field(pos, mom, hext=None, theta=0.5, leaf=16, precision="fp64", counters=True, tuning_id=-1):
+def run_field(pos, mom, hext=None, theta=0.5, leaf=16, precision="fp64", counters=True, tuning_id=-1,
+              expansion=1):
     """Build + field through the C ABI.  pos/mom (3, n) or (B, 3, n) numpy; returns numpy results."""
     batched = pos.ndim == 3
     B = pos.shape[0] if batched else 1
     n = pos.shape[-1]
-    bh = BarnesHut(n, B, leaf, theta, precision, tuning_id=tuning_id)
+    bh = BarnesHut(n, B, leaf, theta, precision, tuning_id=tuning_id, expansion=expansion)
     p = torch.from_numpy(np.ascontiguousarray(pos)).cuda()
     m = torch.from_numpy(np.ascontiguousarray(mom)).cuda()
     he = None if hext is None else torch.from_numpy(np.ascontiguousarray(hext, dtype=np.float64)).cuda()
