@@ -203,6 +203,8 @@ def main():
     ap.add_argument("--no-slab", action="store_true")
     ap.add_argument("--table1", action="store_true",
                     help="print the all-pairs vs Barnes-Hut per-step sweep over N (the paper's Table 1) and exit")
+    ap.add_argument("--tuning", type=int, nargs=2, metavar=("FP32_MIXED", "FP64"), default=None,
+                    help="launch shapes to use instead of running the autotuner")
     ap.add_argument("--accuracy", action="store_true",
                     help="print field error against cost over theta for order-1 and order-2 cells and exit")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -239,10 +241,15 @@ def main():
     ones = torch.ones(1, dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()
 
-    # launch shape per precision: the autotuner's fastest result-invariant candidate for this input
+    # launch shape per precision: the autotuner's fastest result-invariant candidate for this input, or
+    # the one given with --tuning (profiler runs, so that only the timed shape's kernels are counted)
     from paper_1212_2934_amd.autotune import autotune
     tuning = {}
     for precision in ("fp32_mixed", "fp64"):
+        if args.tuning is not None:
+            tuning[precision] = args.tuning[0 if precision == "fp32_mixed" else 1]
+            log(f"launch shape {precision}: tuning {tuning[precision]} (given)")
+            continue
         t = autotune(pos, mom, hext, args.theta, 16, precision, repeats=3)
         tuning[precision] = t["tuning_id"]
         log(f"autotune {precision}: tuning {t['tuning_id']} "
