@@ -125,23 +125,28 @@ __device__ inline void adj_leaf(AdjLds<T> &W, int lane, const Src *__restrict__ 
     }
 }
 
+#define FFBH_ADJ_PARAMS                                                                                         \
+    const NodeRec *__restrict__ nodes, const double *__restrict__ node_m64, const double *__restrict__ spos,     \
+        const double *__restrict__ smom, const void *__restrict__ src, const double *__restrict__ hbar,          \
+        const uint32_t *__restrict__ perm, const double *__restrict__ hext, double *__restrict__ g_gather,       \
+        double *__restrict__ g_rm, double *__restrict__ node_adj, double *__restrict__ Hs,                       \
+        double *__restrict__ Hout, double *__restrict__ e_part, uint32_t *__restrict__ status, int64_t n,        \
+        int64_t ntot, int waves_per_seg, int num_waves, double theta2, int max_nodes, int tpw, int parts,        \
+        double *__restrict__ part_buf, uint32_t *__restrict__ wave_cost
+#define FFBH_ADJ_ARGS                                                                                           \
+    nodes, node_m64, spos, smom, src, hbar, perm, hext, g_gather, g_rm, node_adj, Hs, Hout, e_part, status, n,   \
+        ntot, waves_per_seg, num_waves, theta2, max_nodes, tpw, parts, part_buf, wave_cost
+
+// The fused walk of wave item gw.  If wave_cost is not null, lane 0 stores there a deterministic measure of
+// the item's work (node visits plus leaf pair rounds), which orders the next launch.
 template <bool MIXED>
-__global__ __launch_bounds__(512) void k_adjoint(
-    const NodeRec *__restrict__ nodes, const double *__restrict__ node_m64, const double *__restrict__ spos,
-    const double *__restrict__ smom, const void *__restrict__ src, const double *__restrict__ hbar,
-    const uint32_t *__restrict__ perm, const double *__restrict__ hext, double *__restrict__ g_gather,
-    double *__restrict__ g_rm, double *__restrict__ node_adj, double *__restrict__ Hs,
-    double *__restrict__ Hout, double *__restrict__ e_part, uint32_t *__restrict__ status, int64_t n, int64_t ntot,
-    int waves_per_seg, int num_waves, double theta2, int max_nodes, int tpw, int parts, double *__restrict__ part_buf)
+__device__ __forceinline__ void adjoint_wave(int gw, FFBH_ADJ_PARAMS)
 {
     using T = typename std::conditional<MIXED, float, double>::type;
     using Src = typename std::conditional<MIXED, Src32, Src64>::type;
     const Src *__restrict__ sr = (const Src *)src;
     const int lane = threadIdx.x & (kWave - 1);
     const int wcomp = total6_comp(lane);
-    const int wpb = blockDim.x / kWave;
-    const int gw = xcd_block(blockIdx.x, gridDim.x) * wpb + (int)(threadIdx.x / kWave);
-    if (gw >= num_waves) return;
     // a wave owns tpw consecutive targets (lanes at and above tpw stay idle) and, with parts > 1, walks
     // the subtree of one child of the root (part p: child p); the parts' sums meet in k_parts_sum
     const int per_seg = waves_per_seg * parts;
@@ -177,6 +182,7 @@ __global__ __launch_bounds__(512) void k_adjoint(
         st.init(first, cnt, ballot(valid));
     }
     int guard = max_nodes;  // a wave visits each node at most once
+    uint32_t work = 0;      // node visits plus leaf pair rounds (wave-uniform)
     while (st.more()) {
         uint64_t mask;
         const int cur = st.pop(mask);
@@ -189,6 +195,7 @@ __global__ __launch_bounds__(512) void k_adjoint(
             if (lane == 0) set_flag(status, BH_FLAG_TREE);
             break;
         }
+        ++work;
         // masks of the lanes that take part, of the targets inside the node and of the acceptance test
         const uint64_t insm = ballot((unsigned)(si - nd.first) < (unsigned)nd.count);
         const double dx = rx - nd.cx, dy = ry - nd.cy, dz = rz - nd.cz;
@@ -228,6 +235,10 @@ __global__ __launch_bounds__(512) void k_adjoint(
         if (nd.count <= 4) adj_leaf<4>(W, lane, sr, g_rm, nd.first, nd.count, c, coincident);
         else if (nd.count <= 8) adj_leaf<8>(W, lane, sr, g_rm, nd.first, nd.count, c, coincident);
         else adj_leaf<16>(W, lane, sr, g_rm, nd.first, nd.count, c, coincident);
+        {
+            const int G = nd.count <= 4 ? 4 : nd.count <= 8 ? 8 : 16;
+            work += (uint32_t)(((nd.count + G - 1) / G) * ((c * G + kWave - 1) / kWave + 1));
+        }
         T d[6];
 #pragma unroll
         for (int j = 0; j < 6; ++j) {
@@ -248,6 +259,7 @@ __global__ __launch_bounds__(512) void k_adjoint(
         hx += (double)phx; hy += (double)phy; hz += (double)phz;
     }
     if (ballot(coincident) != 0ull && lane == 0) set_flag(status, BH_FLAG_COINCIDENT);
+    if (wave_cost && lane == 0) wave_cost[gw] = work;
     if (parts > 1) {
         if (valid) {
             double *q = part_buf + (int64_t)part * 6 * ntot;
@@ -280,6 +292,111 @@ __global__ __launch_bounds__(512) void k_adjoint(
             out[2 * n + i] = hz;
         }
     }
+}
+
+// Independent-wave fused traversal.  Without `order` every wave takes one item (its global wave index).
+// With `order`, the launch is persistent: each wave takes item after item from the work counter, in the
+// order given (the heaviest items of the previous launch first, so the launch does not end on a long
+// item), until the items run out.  Every wave reaches the exit: the counter only grows.
+template <bool MIXED>
+__global__ __launch_bounds__(512) void k_adjoint(FFBH_ADJ_PARAMS, const uint32_t *__restrict__ order,
+                                                 uint32_t *__restrict__ work_ctr)
+{
+    if (!order) {
+        const int wpb = blockDim.x / kWave;
+        const int gw = xcd_block(blockIdx.x, gridDim.x) * wpb + (int)(threadIdx.x / kWave);
+        if (gw >= num_waves) return;
+        adjoint_wave<MIXED>(gw, FFBH_ADJ_ARGS);
+        return;
+    }
+    const int lane = threadIdx.x & (kWave - 1);
+    for (;;) {
+        uint32_t v = 0u;
+        if (lane == 0) v = atomicAdd(work_ctr, 1u);
+        const uint32_t item = __builtin_amdgcn_readfirstlane(v);
+        if (item >= (uint32_t)num_waves) return;
+        const uint32_t gw = order[item];
+        if (gw >= (uint32_t)num_waves) {
+            if (lane == 0) set_flag(status, BH_FLAG_TREE);
+            return;
+        }
+        adjoint_wave<MIXED>((int)gw, FFBH_ADJ_ARGS);
+    }
+}
+
+// Order of the wave items of the next persistent launch: 64 buckets of the previous launch's cost range,
+// heaviest bucket first, items of one bucket in index order (a stable counting sort in one workgroup);
+// then the work counter is reset.  Costs all zero (first launch) give the index order.
+constexpr int kOrderThreads = 1024;
+constexpr int kOrderBins = 64;
+
+__global__ __launch_bounds__(kOrderThreads) void k_order_waves(const uint32_t *__restrict__ cost, int nw,
+                                                               uint32_t *__restrict__ order,
+                                                               uint32_t *__restrict__ work_ctr)
+{
+    constexpr int kWaves = kOrderThreads / kWave;
+    __shared__ uint32_t red[kWaves];
+    __shared__ uint32_t hist[kOrderBins];
+    __shared__ uint32_t wcnt[kWaves][kOrderBins];
+    const int t = threadIdx.x, lane = t & (kWave - 1), wave = t / kWave;
+    uint32_t mx = 0u;
+    for (int i = t; i < nw; i += kOrderThreads) mx = max(mx, cost[i]);
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, off, kWave));
+    if (lane == 0) red[wave] = mx;
+    if (t < kOrderBins) hist[t] = 0u;
+    __syncthreads();
+    uint32_t cmax = 0u;
+    for (int w = 0; w < kWaves; ++w) cmax = max(cmax, red[w]);
+    auto bin_of = [cmax](uint32_t c) -> int {
+        const uint64_t q = (uint64_t)c * kOrderBins / ((uint64_t)cmax + 1u);  // 0 .. kOrderBins - 1
+        return kOrderBins - 1 - (int)q;                                       // heaviest first
+    };
+    for (int i = t; i < nw; i += kOrderThreads) atomicAdd(&hist[bin_of(cost[i])], 1u);
+    __syncthreads();
+    if (t == 0) {
+        uint32_t acc = 0u;
+        for (int b = 0; b < kOrderBins; ++b) {
+            const uint32_t c = hist[b];
+            hist[b] = acc;  // start of bin b
+            acc += c;
+        }
+    }
+    __syncthreads();
+    for (int c0 = 0; c0 < nw; c0 += kOrderThreads) {
+        for (int k = t; k < kWaves * kOrderBins; k += kOrderThreads) (&wcnt[0][0])[k] = 0u;
+        __syncthreads();
+        const int i = c0 + t;
+        const bool ok = i < nw;
+        const int b = ok ? bin_of(cost[i]) : 0;
+        // lanes of this wave in the same bin, and this lane's rank among them
+        uint64_t m = ballot(ok);
+#pragma unroll
+        for (int bit = 0; bit < 6; ++bit) {
+            const bool set = (b >> bit) & 1;
+            const uint64_t v = ballot(set);
+            m &= set ? v : ~v;
+        }
+        const int before = lanes_below(m);
+        if (ok && before == 0) wcnt[wave][b] = (uint32_t)__builtin_popcountll(m);
+        __syncthreads();
+        if (t < kOrderBins) {
+            uint32_t acc = hist[t];
+            for (int w = 0; w < kWaves; ++w) {
+                const uint32_t c = wcnt[w][t];
+                wcnt[w][t] = acc;
+                acc += c;
+            }
+            hist[t] = acc;
+        }
+        __syncthreads();
+        if (ok) {
+            const uint32_t at = wcnt[wave][b] + (uint32_t)before;
+            if (at < (uint32_t)nw) order[at] = (uint32_t)i;
+        }
+        __syncthreads();
+    }
+    if (t == 0) *work_ctr = 0u;
 }
 
 // Sum of the parts of a split adjoint walk for every target, in part order (so the result does not depend
@@ -818,16 +935,24 @@ hipError_t launch_backward(Handle &h, const double *d_mom, const double *d_hext,
         const int wps = (int)((L.n + tpw - 1) / tpw);
         const int nwv = (int)(L.B * wps * parts);
         const unsigned blk = (unsigned)((nwv + wpb - 1) / wpb);
+        // persistent, cost-ordered launch: as many workgroups as can be resident at once
+        const bool sched = h.adj_sched && parts == 1;
+        if (sched)
+            hipLaunchKernelGGL(k_order_waves, dim3(1), dim3(kOrderThreads), 0, s, w.wave_cost, nwv, w.wave_order,
+                               w.sched_ctr);
+        const unsigned grid = sched && (unsigned)h.adj_resident < blk ? (unsigned)h.adj_resident : blk;
+        const uint32_t *ord = sched ? w.wave_order : nullptr;
+        uint32_t *cost = parts == 1 ? w.wave_cost : nullptr;
         if (mixed)
-            hipLaunchKernelGGL(k_adjoint<true>, dim3(blk), dim3(wpb * kWave), wpb * sizeof(AdjLds<float>), s, w.nodes,
-                               w.node_m64, w.spos, w.smom, w.src32, w.hbar, w.perm, d_hext, w.g_gather, w.g_rm,
-                               w.node_adj, w.Hs, d_H, w.e_part, w.status, L.n, L.ntot, wps, nwv, theta2,
-                               (int)L.max_nodes, tpw, parts, w.part_buf);
+            hipLaunchKernelGGL(k_adjoint<true>, dim3(grid), dim3(wpb * kWave), wpb * sizeof(AdjLds<float>), s,
+                               w.nodes, w.node_m64, w.spos, w.smom, w.src32, w.hbar, w.perm, d_hext, w.g_gather,
+                               w.g_rm, w.node_adj, w.Hs, d_H, w.e_part, w.status, L.n, L.ntot, wps, nwv, theta2,
+                               (int)L.max_nodes, tpw, parts, w.part_buf, cost, ord, w.sched_ctr);
         else
-            hipLaunchKernelGGL(k_adjoint<false>, dim3(blk), dim3(wpb * kWave), wpb * sizeof(AdjLds<double>), s,
+            hipLaunchKernelGGL(k_adjoint<false>, dim3(grid), dim3(wpb * kWave), wpb * sizeof(AdjLds<double>), s,
                                w.nodes, w.node_m64, w.spos, w.smom, w.src64, w.hbar, w.perm, d_hext, w.g_gather,
                                w.g_rm, w.node_adj, w.Hs, d_H, w.e_part, w.status, L.n, L.ntot, wps, nwv, theta2,
-                               (int)L.max_nodes, tpw, parts, w.part_buf);
+                               (int)L.max_nodes, tpw, parts, w.part_buf, cost, ord, w.sched_ctr);
         if (parts > 1)
             hipLaunchKernelGGL(k_parts_sum, dim3((unsigned)((L.n + 255) / 256), (unsigned)L.B), dim3(256), 0, s,
                                w.part_buf, parts, w.smom, d_hext, w.perm, w.g_gather, w.Hs, d_H, w.e_part, L.n,
@@ -842,6 +967,26 @@ hipError_t launch_backward(Handle &h, const double *d_mom, const double *d_hext,
     if (d_dhext)
         hipLaunchKernelGGL(k_dhext, dim3((unsigned)L.B), dim3(1024), 0, s, d_mom, d_gE, L.n, d_dhext);
     return hipGetLastError();
+}
+
+// Workgroups of the independent-wave fused traversal that fit on the device at once (for the persistent
+// launch), with this handle's precision and waves per workgroup.
+hipError_t adjoint_resident_blocks(Handle &h, int &blocks)
+{
+    const int wpb = h.waves_per_block;
+    int per_cu = 0, cus = 0;
+    hipError_t e;
+    if (h.p.precision == BH_FP32_MIXED)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_adjoint<true>, wpb * kWave,
+                                                         wpb * sizeof(AdjLds<float>));
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_adjoint<false>, wpb * kWave,
+                                                         wpb * sizeof(AdjLds<double>));
+    if (e != hipSuccess) return e;
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h.device);
+    if (e != hipSuccess) return e;
+    blocks = per_cu * cus;
+    return blocks > 0 ? hipSuccess : hipErrorInvalidValue;
 }
 
 }  // namespace ffbh

@@ -11,15 +11,18 @@ static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 // traversals, how many waves walk the adjoint traversal together (1 = independently), whether adjoint
 // waves own two targets per lane, and how many targets an independent adjoint wave owns (fewer than 64
 // gives small systems more walks in flight).
-static const int kTuneWaves[] = {4, 1, 2, 8, 4, 4, 4, 2, 4, 4, 4, 4, 4};
-static const int kTuneCoop[] = {1, 1, 1, 1, 2, 4, 1, 1, 1, 1, 1, 1, 1};
-static const int kTuneTwo[] = {0, 0, 0, 0, 0, 0, 1, 1, 0, 0, 0, 0, 0};
-static const int kTuneTpw[] = {64, 64, 64, 64, 64, 64, 64, 64, 32, 16, 64, 32, 16};
+static const int kTuneWaves[] = {4, 1, 2, 8, 4, 4, 4, 2, 4, 4, 4, 4, 4, 2, 4, 1};
+static const int kTuneCoop[] = {1, 1, 1, 1, 2, 4, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1};
+static const int kTuneTwo[] = {0, 0, 0, 0, 0, 0, 1, 1, 0, 0, 0, 0, 0, 0, 0, 0};
+static const int kTuneTpw[] = {64, 64, 64, 64, 64, 64, 64, 64, 32, 16, 64, 32, 16, 64, 64, 64};
 // independent adjoint waves split each walk over the root's children (8 parts) or not (1)
-static const int kTuneParts[] = {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 8, 8, 8};
+static const int kTuneParts[] = {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 8, 8, 8, 1, 1, 1};
+// independent adjoint waves in one persistent launch, heaviest items of the previous launch first
+static const int kTuneSched[] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 1};
 static const int kNumTunings = (int)(sizeof(kTuneWaves) / sizeof(kTuneWaves[0]));
 static_assert(sizeof(kTuneCoop) == sizeof(kTuneWaves) && sizeof(kTuneTwo) == sizeof(kTuneWaves) &&
-                  sizeof(kTuneTpw) == sizeof(kTuneWaves) && sizeof(kTuneParts) == sizeof(kTuneWaves),
+                  sizeof(kTuneTpw) == sizeof(kTuneWaves) && sizeof(kTuneParts) == sizeof(kTuneWaves) &&
+                  sizeof(kTuneSched) == sizeof(kTuneWaves),
               "one entry per tuning in every table");
 
 Layout plan_layout(const bh_params &p)
@@ -109,6 +112,10 @@ void carve(const Layout &Lc, void *base, Workspace &w)
     w.md_grad_m = (double *)take(3 * 8 * nt);
     w.cell_first = (uint32_t *)take(4 * (size_t)L.B * (size_t)L.cell_T);
     w.part_buf = (double *)take(6 * 8 * nt * (size_t)L.adj_parts);  // split-walk partial sums (parts > 1)
+    const size_t nwmax = (size_t)(L.B * ((L.n + kMinTpw - 1) / kMinTpw));  // wave items of any shape
+    w.wave_cost = (uint32_t *)take(4 * nwmax);
+    w.wave_order = (uint32_t *)take(4 * nwmax);
+    w.sched_ctr = (uint32_t *)take(64);
     const size_t qn = L.expansion == 2 ? mn : 0;  // first moments only for order-2 cells
     w.node_q64 = (double *)take(16 * 8 * qn);
     w.node_q32 = (float *)take(16 * 4 * qn);
@@ -133,6 +140,11 @@ static bool dptr_ok(const void *p) { return p && ((uintptr_t)p % 8) == 0; }
 __global__ void k_clear_status(uint32_t *status)
 {
     if (threadIdx.x < 16) status[threadIdx.x] = 0u;
+}
+
+__global__ __launch_bounds__(256) void k_fill_u32(uint32_t *a, int64_t len, uint32_t v)
+{
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < len; i += (int64_t)gridDim.x * 256) a[i] = v;
 }
 
 __global__ void k_init(uint32_t *status, double *ones, int64_t B)
@@ -218,9 +230,17 @@ bh_status bh_create(const bh_params *p, void *d_workspace, size_t workspace_byte
     h.adj_two = kTuneTwo[p->tuning_id < 0 ? 0 : p->tuning_id];
     h.adj_tpw = kTuneTpw[p->tuning_id < 0 ? 0 : p->tuning_id];
     h.adj_parts = kTuneParts[p->tuning_id < 0 ? 0 : p->tuning_id];
+    h.adj_sched = kTuneSched[p->tuning_id < 0 ? 0 : p->tuning_id];
+    h.adj_resident = 0;
+    if (h.adj_sched && adjoint_resident_blocks(h, h.adj_resident) != hipSuccess) {
+        delete hh;
+        return BH_EDEVICE;
+    }
     h.cnt_far = h.cnt_near = nullptr;
     for (int k = 0; k < 4; ++k) h.ev[k] = nullptr;
     hipLaunchKernelGGL(k_init, dim3(1), dim3(256), 0, 0, h.w.status, h.w.ones, (int64_t)L.B);
+    hipLaunchKernelGGL(k_fill_u32, dim3(64), dim3(256), 0, 0, h.w.wave_cost,
+                       (int64_t)(L.B * ((L.n + kMinTpw - 1) / kMinTpw)), 0u);
     if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
         delete hh;
         return BH_EDEVICE;

@@ -68,6 +68,9 @@ struct Workspace {
     double *node_m64;        // 4 x max_nodes: moment sum FP64 (x, y, z, pad) per node
     uint32_t *cell_first;    // short-range grid: first sorted particle of each cell (B x cell_T)
     double *part_buf;        // (parts, 6, ntot) partial sums of split adjoint walks
+    uint32_t *wave_cost;     // per adjoint wave item: work of the last launch (orders the next one)
+    uint32_t *wave_order;    // item order of the next persistent launch
+    uint32_t *sched_ctr;     // [0]: work counter of the persistent launch
     double *node_q64;        // max_nodes x 16: first moment D (row-major 3x3, then pad) per node, FP64
     float *node_q32;         // max_nodes x 16: the same rounded to FP32 (mixed-precision traversal)
     double *ones;            // B: constant 1.0 (dL/dE for the MD force)
@@ -115,6 +118,8 @@ struct Handle {
     int adj_two;         // adjoint waves own two targets per lane
     int adj_tpw;         // targets per independent adjoint wave (16, 32 or 64)
     int adj_parts;       // independent adjoint walks split over the root's children (8) or not (1)
+    int adj_sched;       // independent adjoint waves in one persistent, cost-ordered launch
+    int adj_resident;    // workgroups of that launch resident at once (grid of the persistent launch)
     int32_t *cnt_far, *cnt_near;  // optional per-target counters (device)
     hipEvent_t ev[4];             // optional timing events around the traversal kernels
 };
@@ -174,6 +179,7 @@ hipError_t launch_backward(Handle &h, const double *d_mom, const double *d_hext,
                            const double *d_gE, double *d_dpos, double *d_dmom, double *d_dhext,
                            hipStream_t s, double *d_H = nullptr, double *d_E = nullptr, bool moments_done = false);
 void launch_energy_final(Handle &h, double *d_E, hipStream_t s, int targets_per_wave);
+hipError_t adjoint_resident_blocks(Handle &h, int &blocks);
 hipError_t launch_ap(int64_t n, int32_t batch, int32_t precision, const double *pos, const double *mom,
                      const double *hext, double *H, double *dEdr, double *E, hipStream_t s);
 hipError_t launch_md(Handle &h, const md_state *st, const md_params *mp, hipStream_t s);

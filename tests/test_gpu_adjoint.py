@@ -34,8 +34,8 @@ def _gpu_grad(pos, mom, hext, theta, precision, gH=None, gE=1.0, leaf=16, want_d
 
 
 # independent waves; 2 and 4 waves together; two targets per lane; 32 and 16 targets per wave; each walk
-# split over the root's children, with 64, 32 and 16 targets per wave
-@pytest.mark.parametrize("tuning_id", [0, 4, 5, 6, 8, 9, 10, 11, 12])
+# split over the root's children, with 64, 32 and 16 targets per wave; one persistent cost-ordered launch
+@pytest.mark.parametrize("tuning_id", [0, 4, 5, 6, 8, 9, 10, 11, 12, 13, 14, 15])
 @pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
 def test_energy_gradient_config1(oracle_mod, precision, tuning_id):
     w = workloads.uniform_cube(4096, 32.0, seed=1001, hext=(0.0, 0.0, 1.0))
@@ -46,7 +46,7 @@ def test_energy_gradient_config1(oracle_mod, precision, tuning_id):
     np.testing.assert_allclose(gdh[0], -w.mom.sum(axis=1), rtol=1e-12)
 
 
-@pytest.mark.parametrize("tuning_id", [0, 5, 7, 9, 11])
+@pytest.mark.parametrize("tuning_id", [0, 5, 7, 9, 11, 14])
 @pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
 @pytest.mark.parametrize("theta", [0.3, 0.7])
 def test_general_vjp_chains(oracle_mod, precision, theta, tuning_id):
@@ -72,7 +72,7 @@ def test_theta_zero_equals_allpairs_force(oracle_mod):
     assert rel(gdm, -oracle_mod.allpairs_field(w.pos, w.mom)) <= 1e-12
 
 
-@pytest.mark.parametrize("tuning_id", [0, 4, 5, 6, 9, 10, 12])
+@pytest.mark.parametrize("tuning_id", [0, 4, 5, 6, 9, 10, 12, 13])
 def test_batched_adjoint(oracle_mod, tuning_id):
     B, n = 3, 2000 + 77  # ragged: the last workgroup of each system is partly empty
     ws = [workloads.uniform_cube(n, 26.0, seed=30 + b) for b in range(B)]
@@ -98,6 +98,32 @@ def test_small_systems(oracle_mod, n, tuning_id):
         return
     assert rel(gdr, dr) <= 1e-12
     assert rel(gdm, dm) <= 1e-12
+
+
+@pytest.mark.parametrize("tuning_id", [13, 15])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
+def test_persistent_launch_repeats(oracle_mod, precision, tuning_id):
+    """The persistent launch orders its items by the previous launch's costs: the first call runs them in
+    index order, later calls heaviest first.  Every call agrees with the oracle (ragged batch of 3)."""
+    B, n = 3, 3000 + 5
+    ws = [workloads.uniform_cube(n, 30.0, seed=70 + b) for b in range(B)]
+    pos = np.stack([x.pos for x in ws])
+    mom = np.stack([x.mom for x in ws])
+    hext = np.array([0.2, 0.0, 0.4])
+    bh = BarnesHut(n, B, 16, 0.5, precision, tuning_id=tuning_id)
+    p = torch.from_numpy(pos).cuda()
+    m = torch.from_numpy(mom).cuda()
+    he = torch.from_numpy(hext).cuda()
+    ge = torch.ones(B, dtype=torch.float64, device="cuda")
+    bh.build(p)
+    refs = [oracle_mod.Tree(x.pos, x.mom, 16).energy_grad(0.5, hext) for x in ws]
+    for call in range(3):
+        dr, dm = bh.field_backward(m, he, gE=ge)
+        assert bh.check_status() == 0
+        dr, dm = dr.cpu().numpy(), dm.cpu().numpy()
+        for b in range(B):
+            assert rel(dr[b], refs[b][2]) <= TOL[precision], (call, b)
+            assert rel(dm[b], refs[b][3]) <= TOL[precision], (call, b)
 
 
 def test_invariants_at_full_size_c4():

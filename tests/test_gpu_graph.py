@@ -34,14 +34,16 @@ def _close(a, b, tol=1e-12):
     assert torch.equal(a["step"], b["step"])
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
-def test_batched_slab_graph_replay_matches_eager(precision):
+@pytest.mark.parametrize("precision,tuning_id", [("fp64", -1), ("fp32_mixed", -1), ("fp32_mixed", 14)])
+def test_batched_slab_graph_replay_matches_eager(precision, tuning_id):
+    """tuning 14: the persistent adjoint launch, whose item order comes from the previous replay's costs
+    (ordering kernel and work-counter reset inside the graph)."""
     w = workloads.config5(batch=4, n=4096, box=(64.0, 64.0, 8.0))
     hext = torch.from_numpy(w.hext).cuda()
     mdp = _mdp(w.box_lo, w.box_hi, hext)
     s0 = _state(w.pos, w.mom, 5)
     eager = {k: v.clone() for k, v in s0.items()}
-    bh = BarnesHut(w.n, w.batch, 16, 0.5, precision)
+    bh = BarnesHut(w.n, w.batch, 16, 0.5, precision, tuning_id=tuning_id)
     snaps = []
     for _ in range(4):
         bh.md_step(eager, mdp)
@@ -49,7 +51,7 @@ def test_batched_slab_graph_replay_matches_eager(precision):
     torch.cuda.synchronize()
 
     g_state = {k: v.clone() for k, v in s0.items()}
-    bh2 = BarnesHut(w.n, w.batch, 16, 0.5, precision)
+    bh2 = BarnesHut(w.n, w.batch, 16, 0.5, precision, tuning_id=tuning_id)
     stream = torch.cuda.Stream()
     torch.cuda.synchronize()
     graph = bh2.capture_md_graph(g_state, mdp, stream)

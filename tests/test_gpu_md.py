@@ -42,10 +42,11 @@ def _params(side, hext=(0.0, 0.0, 0.5)):
 
 @pytest.mark.parametrize("precision,tol,tuning_id", [("fp64", 1e-11, -1), ("fp32_mixed", 1e-8, -1),
                                                      ("fp64", 1e-11, 9), ("fp32_mixed", 1e-8, 9),
-                                                     ("fp64", 1e-11, 10), ("fp32_mixed", 1e-8, 11)])
+                                                     ("fp64", 1e-11, 10), ("fp32_mixed", 1e-8, 11),
+                                                     ("fp64", 1e-11, 13), ("fp32_mixed", 1e-8, 14)])
 def test_trajectory_matches_reference(precision, tol, tuning_id):
     """tuning 9: adjoint waves of 16 targets; 10 and 11: walks split over the root's children (the
-    small-system launch shapes)."""
+    small-system launch shapes); 13 and 14: one persistent launch ordered by the previous step's costs."""
     w = workloads.uniform_cube(1500, 20.0, seed=4)
     rng = np.random.default_rng(5)
     st = _state(w, rng)
