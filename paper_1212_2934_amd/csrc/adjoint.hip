@@ -296,8 +296,8 @@ __device__ __forceinline__ void adjoint_wave(int gw, FFBH_ADJ_PARAMS)
 
 // Independent-wave fused traversal.  Without `order` every wave takes one item (its global wave index).
 // With `order`, the launch is persistent: each wave takes item after item from the work counter, in the
-// order given (the heaviest items of the previous launch first, so the launch does not end on a long
-// item), until the items run out.  Every wave reaches the exit: the counter only grows.
+// order given (light items of the previous launch last, so the launch does not end on a long item), until
+// the items run out.  Every wave reaches the exit: the counter only grows.
 template <bool MIXED>
 __global__ __launch_bounds__(512) void k_adjoint(FFBH_ADJ_PARAMS, const uint32_t *__restrict__ order,
                                                  uint32_t *__restrict__ work_ctr)
@@ -324,9 +324,11 @@ __global__ __launch_bounds__(512) void k_adjoint(FFBH_ADJ_PARAMS, const uint32_t
     }
 }
 
-// Order of the wave items of the next persistent launch: 64 buckets of the previous launch's cost range,
-// heaviest bucket first, items of one bucket in index order (a stable counting sort in one workgroup);
-// then the work counter is reset.  Costs all zero (first launch) give the index order.
+// Order of the wave items of the next persistent launch, from the previous launch's costs: the items
+// outside the lightest ~30 % first, in index order (neighbouring items share tree data, so the launch
+// keeps its cache locality), then the light items, heaviest first (64 buckets of the cost range), so the
+// launch ends on short items.  A stable counting sort in one workgroup; then the work counter is reset.
+// Costs all zero (first launch) give the index order.
 constexpr int kOrderThreads = 1024;
 constexpr int kOrderBins = 64;
 
@@ -336,40 +338,53 @@ __global__ __launch_bounds__(kOrderThreads) void k_order_waves(const uint32_t *_
 {
     constexpr int kWaves = kOrderThreads / kWave;
     __shared__ uint32_t red[kWaves];
-    __shared__ uint32_t hist[kOrderBins];
+    __shared__ uint32_t fine[kOrderBins];  // items per cost bucket, lightest bucket first
+    __shared__ uint32_t hist[kOrderBins];  // items per key, then the start of each key
     __shared__ uint32_t wcnt[kWaves][kOrderBins];
+    __shared__ int split;                  // buckets below it are the light items
     const int t = threadIdx.x, lane = t & (kWave - 1), wave = t / kWave;
     uint32_t mx = 0u;
     for (int i = t; i < nw; i += kOrderThreads) mx = max(mx, cost[i]);
 #pragma unroll
     for (int off = 1; off < kWave; off <<= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, off, kWave));
     if (lane == 0) red[wave] = mx;
-    if (t < kOrderBins) hist[t] = 0u;
+    if (t < kOrderBins) fine[t] = 0u;
     __syncthreads();
     uint32_t cmax = 0u;
     for (int w = 0; w < kWaves; ++w) cmax = max(cmax, red[w]);
-    auto bin_of = [cmax](uint32_t c) -> int {
-        const uint64_t q = (uint64_t)c * kOrderBins / ((uint64_t)cmax + 1u);  // 0 .. kOrderBins - 1
-        return kOrderBins - 1 - (int)q;                                       // heaviest first
-    };
-    for (int i = t; i < nw; i += kOrderThreads) atomicAdd(&hist[bin_of(cost[i])], 1u);
+    auto bucket = [cmax](uint32_t c) -> int { return (int)((uint64_t)c * kOrderBins / ((uint64_t)cmax + 1u)); };
+    for (int i = t; i < nw; i += kOrderThreads) atomicAdd(&fine[bucket(cost[i])], 1u);
     __syncthreads();
     if (t == 0) {
+        // the light items: the lowest buckets holding at most 30 % of the items (bucket 63 holds the
+        // heaviest item, so split <= 63 and the keys below fit in six bits)
         uint32_t acc = 0u;
-        for (int b = 0; b < kOrderBins; ++b) {
-            const uint32_t c = hist[b];
-            hist[b] = acc;  // start of bin b
-            acc += c;
+        int sp = 0;
+        while (sp < kOrderBins && (uint64_t)(acc + fine[sp]) * 10u <= (uint64_t)nw * 3u) acc += fine[sp++];
+        split = sp;
+        uint32_t heavy = 0u;
+        for (int q = sp; q < kOrderBins; ++q) heavy += fine[q];
+        // key 0: heavy items; key k = 1..split: light bucket split - k (heaviest light bucket first)
+        uint32_t start = 0u;
+        for (int k = 0; k < kOrderBins; ++k) {
+            const uint32_t c = k == 0 ? heavy : k <= sp ? fine[sp - k] : 0u;
+            hist[k] = start;
+            start += c;
         }
     }
     __syncthreads();
+    const int sp = split;
+    auto key_of = [&](uint32_t c) -> int {
+        const int q = bucket(c);
+        return q >= sp ? 0 : sp - q;
+    };
     for (int c0 = 0; c0 < nw; c0 += kOrderThreads) {
         for (int k = t; k < kWaves * kOrderBins; k += kOrderThreads) (&wcnt[0][0])[k] = 0u;
         __syncthreads();
         const int i = c0 + t;
         const bool ok = i < nw;
-        const int b = ok ? bin_of(cost[i]) : 0;
-        // lanes of this wave in the same bin, and this lane's rank among them
+        const int b = ok ? key_of(cost[i]) : 0;
+        // lanes of this wave with the same key, and this lane's rank among them
         uint64_t m = ballot(ok);
 #pragma unroll
         for (int bit = 0; bit < 6; ++bit) {
