@@ -4,7 +4,9 @@ Every candidate shape must give the same result as the default shape -- identica
 counts and the same field to the last bit (the traversal of one target does not depend on the shape),
 and the same adjoint to rounding (its scatters are reduced in a shape-dependent order) -- before its
 time counts.  The fastest accepted candidate is cached in a JSON file keyed by device, system
-size, batch, theta, leaf size and precision.
+size, batch, theta, leaf size and precision.  The time is that of build + field + adjoint on the given
+state, or, when MD parameters are given, of MD steps from it (each step rebuilds the tree from moved
+particles, which is what a launch shape that learns from the previous launch meets in a simulation).
 """
 from __future__ import annotations
 
@@ -17,20 +19,22 @@ import torch
 from .binding import BarnesHut, lib
 
 
-def _key(n, batch, theta, leaf, precision):
+def _key(n, batch, theta, leaf, precision, md=False):
     dev = torch.cuda.get_device_name(torch.cuda.current_device())
-    return f"{dev}|n={n}|b={batch}|theta={theta}|leaf={leaf}|{precision}"
+    return f"{dev}|n={n}|b={batch}|theta={theta}|leaf={leaf}|{precision}" + ("|md" if md else "")
 
 
 def autotune(pos, mom, hext=None, theta=0.5, leaf=16, precision="fp32_mixed", repeats=3,
-             cache_path=None, verbose=False) -> dict:
-    """Pick the fastest result-invariant tuning_id for build + forward + adjoint on this input.
+             cache_path=None, verbose=False, md=None) -> dict:
+    """Pick the fastest result-invariant tuning_id for build + forward + adjoint on this input, or for
+    MD steps when md = (state, md_params) is given (state: pos, vel, mom, omega, step tensors; it is
+    copied, not advanced).
 
     pos, mom: (B, 3, n) or (3, n) float64 CUDA tensors.  Returns {"tuning_id", "times_ms", "key"}.
     """
     batch = 1 if pos.dim() == 2 else pos.shape[0]
     n = pos.shape[-1]
-    key = _key(n, batch, theta, leaf, precision)
+    key = _key(n, batch, theta, leaf, precision, md is not None)
     cache = {}
     if cache_path and os.path.exists(cache_path):
         with open(cache_path) as f:
@@ -61,10 +65,17 @@ def autotune(pos, mom, hext=None, theta=0.5, leaf=16, precision="fp32_mixed", re
             raise RuntimeError(f"tuning {tid} changed the adjoint beyond rounding; refusing it")
         torch.cuda.synchronize()
         best = float("inf")
+        if md is not None:
+            st = {k: v.clone() for k, v in md[0].items()}
+            bh.md_step(st, md[1])  # the first step has no previous launch to learn from
+            torch.cuda.synchronize()
         for _ in range(repeats):
             t0 = time.perf_counter()
-            bh.build(pos)
-            bh.field_backward(mom, hext, gE=ones)
+            if md is not None:
+                bh.md_step(st, md[1])
+            else:
+                bh.build(pos)
+                bh.field_backward(mom, hext, gE=ones)
             torch.cuda.synchronize()
             best = min(best, time.perf_counter() - t0)
         times[tid] = best * 1e3
