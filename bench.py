@@ -92,8 +92,8 @@ def table1(args, workloads, BarnesHut, allpairs, md_params):
     """Per-step time of the all-pairs and Barnes-Hut paths for N = 10^3 .. 10^6 (the shape of the paper's
     Table 1): random sequential addition at volume fraction 0.1 in a cube, theta 0.5, leaf 16.  AP step =
     all-pairs field and energy gradient (one kernel); BH step = md_step (build, field, adjoint, WCA,
-    integrator) replayed from a HIP graph in the autotuner's launch shape; field = all-pairs field alone vs
-    bh_build + bh_field (eager calls)."""
+    integrator) replayed from a HIP graph in the launch shape the autotuner picks for MD steps; field =
+    all-pairs field alone vs bh_build + bh_field (eager calls, same shape)."""
     from paper_1212_2934_amd.autotune import autotune
     import ctypes
     import math
@@ -126,13 +126,13 @@ def table1(args, workloads, BarnesHut, allpairs, md_params):
         for p in ("fp32_mixed", "fp64"):
             row["apf", p] = timed(lambda: allpairs(pos, mom, precision=p))
             row["aps", p] = timed(lambda: allpairs(pos, mom, precision=p, want_dEdr=True))
-            tun[p] = autotune(pos, mom, None, 0.5, 16, p)["tuning_id"]
-            bh = BarnesHut(n, 1, 16, 0.5, p, tuning_id=tun[p])
-            row["bhf", p] = timed(lambda: (bh.build(pos), bh.field(mom)))
             st = {"pos": pos.clone(), "vel": torch.zeros_like(pos), "mom": mom.clone(),
                   "omega": torch.zeros_like(pos), "step": torch.zeros(1, dtype=torch.int64, device=dev)}
             mdp = md_params(1e-3, 1.0, 0.1, 0.1, 1.0, 0.1, 1.0, 1.0, C3(0.0, 0.0, 0.0), C3(side, side, side),
                             None, 7)
+            tun[p] = autotune(pos, mom, None, 0.5, 16, p, md=(st, mdp))["tuning_id"]
+            bh = BarnesHut(n, 1, 16, 0.5, p, tuning_id=tun[p])
+            row["bhf", p] = timed(lambda: (bh.build(pos), bh.field(mom)))
             stream = torch.cuda.Stream()
             torch.cuda.synchronize()
             graph = bh.capture_md_graph(st, mdp, stream)

@@ -104,7 +104,7 @@ def run(geometry="cube", batch=1, steps=100000, report=10000, precision="fp32_mi
                     C3(*w.box_lo), C3(*w.box_hi), None, seed)
     mdp.sr_kind, mdp.sr_cut = 1, 0.0
     if tuning == "auto":
-        tuning = autotune(st["pos"], st["mom"], None, theta, 16, precision)["tuning_id"]
+        tuning = autotune(st["pos"], st["mom"], None, theta, 16, precision, md=(st, mdp))["tuning_id"]
     sim = BarnesHut(n, batch, 16, theta, precision, tuning_id=int(tuning))
     stream = torch.cuda.Stream()
     torch.cuda.synchronize()

@@ -74,6 +74,23 @@ def test_morton_code_bit_layout():
         assert binding.morton_code(int(qx), int(qy), int(qz)) == _interleave_loop(int(qx), int(qy), int(qz))
 
 
+def test_params_expansion_checked():
+    """bh_params.expansion: 0 or 1 (the paper's cells) and 2 (with first moments) are valid, others not;
+    order-2 cells keep their first moments in the workspace."""
+    import ctypes as C
+    L = binding.lib()
+    out = C.c_size_t(0)
+    sizes = {}
+    for e in (0, 1, 2):
+        p = binding.make_params(5000, 2, 16, 0.5, "fp64", -1, e)
+        assert L.bh_workspace_bytes(C.byref(p), C.byref(out)) == 0
+        sizes[e] = out.value
+    assert sizes[0] == sizes[1] < sizes[2]
+    for e in (-1, 3):
+        p = binding.make_params(5000, 2, 16, 0.5, "fp64", -1, e)
+        assert L.bh_workspace_bytes(C.byref(p), C.byref(out)) == -1
+
+
 def test_allpairs_argument_checks():
     """Host-checkable errors return BH_EINVAL before anything is enqueued (no device needed).  Skipped
     where a GPU is present: the placeholder pointers must never reach a kernel."""
