@@ -110,7 +110,7 @@ void carve(const Layout &Lc, void *base, Workspace &w)
     w.md_force = (double *)take(3 * 8 * nt);
     w.md_grad_r = (double *)take(3 * 8 * nt);
     w.md_grad_m = (double *)take(3 * 8 * nt);
-    w.cell_first = (uint32_t *)take(4 * (size_t)L.B * (size_t)L.cell_T);
+    w.cells = (uint2 *)take(8 * (size_t)L.B * (size_t)L.cell_T);
     w.part_buf = (double *)take(6 * 8 * nt * (size_t)L.adj_parts);  // split-walk partial sums (parts > 1)
     const size_t nwmax = (size_t)(L.B * ((L.n + kMinTpw - 1) / kMinTpw));  // wave items of any shape
     w.wave_cost = (uint32_t *)take(4 * nwmax);

@@ -66,7 +66,7 @@ struct Workspace {
     NodeRec *nodes;          // max_nodes
     int32_t *node_level;     // max_nodes: cell level (side = side_root / 2^level)
     double *node_m64;        // 4 x max_nodes: moment sum FP64 (x, y, z, pad) per node
-    uint32_t *cell_first;    // short-range grid: first sorted particle of each cell (B x cell_T)
+    uint2 *cells;            // short-range grid: member range [start, end) of each cell (B x cell_T)
     double *part_buf;        // (parts, 6, ntot) partial sums of split adjoint walks
     uint32_t *wave_cost;     // per adjoint wave item: work of the last launch (orders the next one)
     uint32_t *wave_order;    // item order of the next persistent launch

@@ -116,25 +116,32 @@ __device__ inline uint32_t spread3_small(uint32_t v)
     return x;
 }
 
-// First sorted particle of every occupied cell.  Entries of cells that are empty in this build are left
-// as they are: a reader accepts an entry only if that particle's cell is the one it looks up, which holds
-// exactly for the entries written here.
+// Member range [start, end) of the sorted particles of every occupied cell, written by the cell's first and
+// last members; the table is cleared before (k_clear_cells), so an unoccupied cell reads as empty.
+__global__ __launch_bounds__(256) void k_clear_cells(uint2 *__restrict__ cells, int64_t len)
+{
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < len; i += (int64_t)gridDim.x * 256)
+        cells[i] = make_uint2(0u, 0u);
+}
+
 __global__ __launch_bounds__(256) void k_cell_fill(const uint64_t *__restrict__ codes, const double *__restrict__ bbox,
                                                    int64_t n, int64_t ntot, double rc, int lcap, int64_t T,
-                                                   uint32_t *__restrict__ cell_first)
+                                                   uint2 *__restrict__ cells)
 {
     const int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (o >= ntot) return;
     const int64_t b = o / n, s = o - b * n;
     const int shift = 3 * (kBits - grid_level(bbox[8 * b + 3], rc, lcap));
     const uint64_t c = codes[o] >> shift;
-    if (s == 0 || (codes[o - 1] >> shift) != c) cell_first[b * T + (int64_t)c] = (uint32_t)o;
+    uint2 *e = cells + b * T + (int64_t)c;
+    if (s == 0 || (codes[o - 1] >> shift) != c) e->x = (uint32_t)o;
+    if (s == n - 1 || (codes[o + 1] >> shift) != c) e->y = (uint32_t)(o + 1);
 }
 
 // Short-range forces on every particle (one thread per sorted particle): partners from the 27 surrounding
-// cells, then the container walls; written in the caller's order.  SrLaw selects the law (c12) and cut-offs.
+// cells, then the container walls; written in the caller's order.  c12 selects the law, rc and rcw the cut-offs.
 __global__ __launch_bounds__(256) void k_wca(const uint64_t *__restrict__ codes, const double *__restrict__ bbox,
-                                             const uint32_t *__restrict__ cell_first, const double *__restrict__ spos,
+                                             const uint2 *__restrict__ cells, const double *__restrict__ spos,
                                              const uint32_t *__restrict__ perm, double *__restrict__ F, int64_t n,
                                              int64_t ntot, int lcap, int64_t T, double sigma, double eps,
                                              double c12, double rc, double rcw, double3 box_lo, double3 box_hi)
@@ -152,25 +159,26 @@ __global__ __launch_bounds__(256) void k_wca(const uint64_t *__restrict__ codes,
         const int cx = (int)(compact3(code >> 2) >> down), cy = (int)(compact3(code >> 1) >> down),
                   cz = (int)(compact3(code) >> down);
         const int cmax = (1 << L) - 1;
-        const uint32_t *tab = cell_first + b * T;
-        // per slab of nine cells, the table entries are read before any member, so their loads overlap
+        const uint2 *tab = cells + b * T;
+        // per slab of nine cells, the member ranges are read before any member, so their loads overlap
         for (int dz = -1; dz <= 1; ++dz) {
             const int nz = cz + dz;
             if ((unsigned)nz > (unsigned)cmax) continue;
-            uint32_t cell[9], first[9];
+            uint2 rg[9];
 #pragma unroll
             for (int k = 0; k < 9; ++k) {
                 const int nx = cx + k % 3 - 1, ny = cy + k / 3 - 1;
                 const bool in = (unsigned)nx <= (unsigned)cmax && (unsigned)ny <= (unsigned)cmax;
-                cell[k] = in ? (spread3_small((uint32_t)nx) << 2) | (spread3_small((uint32_t)ny) << 1) |
-                                   spread3_small((uint32_t)nz)
-                             : 0xffffffffu;
-                first[k] = in ? tab[cell[k]] : 0xffffffffu;
+                rg[k] = in ? tab[(spread3_small((uint32_t)nx) << 2) | (spread3_small((uint32_t)ny) << 1) |
+                                 spread3_small((uint32_t)nz)]
+                           : make_uint2(0u, 0u);
             }
 #pragma unroll
             for (int k = 0; k < 9; ++k) {
-                const uint64_t c = cell[k];
-                for (int64_t j = first[k]; j >= lo_i && j < hi_i && (codes[j] >> shift) == c; ++j) {
+                // a range always lies inside this system's block of sorted particles
+                const int64_t j0 = (int64_t)rg[k].x > lo_i ? (int64_t)rg[k].x : lo_i;
+                const int64_t j1 = (int64_t)rg[k].y < hi_i ? (int64_t)rg[k].y : hi_i;
+                for (int64_t j = j0; j < j1; ++j) {
                     if (j == o) continue;
                     sr_pair(rx - spos[j], ry - spos[ntot + j], rz - spos[2 * ntot + j], s2, eps, c12, rc2, fx, fy,
                             fz);
@@ -273,9 +281,11 @@ hipError_t launch_md(Handle &h, const md_state *st, const md_params *mp, hipStre
     const double c12 = lj ? 1.0 : 2.0;
     const double rc = lj ? (mp->sr_cut > 0.0 ? mp->sr_cut : 2.5 * mp->wca_sigma) : wca_rc * mp->wca_sigma;
     const double rcw = lj ? 0.5 * rc : wca_rc * 0.5 * mp->wca_sigma;
+    const int64_t ncell = L.B * L.cell_T;
+    hipLaunchKernelGGL(k_clear_cells, dim3(grid_for(ncell, 256, 2048)), dim3(256), 0, s, w.cells, ncell);
     hipLaunchKernelGGL(k_cell_fill, dim3(grid_for(L.ntot, 256)), dim3(256), 0, s, w.codes, w.bbox, L.n, L.ntot, rc,
-                       L.cell_lcap, L.cell_T, w.cell_first);
-    hipLaunchKernelGGL(k_wca, dim3(grid_for(L.ntot, 256)), dim3(256), 0, s, w.codes, w.bbox, w.cell_first, w.spos,
+                       L.cell_lcap, L.cell_T, w.cells);
+    hipLaunchKernelGGL(k_wca, dim3(grid_for(L.ntot, 256)), dim3(256), 0, s, w.codes, w.bbox, w.cells, w.spos,
                        w.perm, w.md_force, L.n, L.ntot, L.cell_lcap, L.cell_T, mp->wca_sigma, mp->wca_eps, c12, rc, rcw,
                        make_double3(mp->box_lo[0], mp->box_lo[1], mp->box_lo[2]),
                        make_double3(mp->box_hi[0], mp->box_hi[1], mp->box_hi[2]));
