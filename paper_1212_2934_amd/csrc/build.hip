@@ -308,7 +308,7 @@ static void scan_excl(uint32_t *a, int64_t len, uint32_t *scratch, uint32_t *tot
     hipLaunchKernelGGL(k_scan_apply, dim3(ntiles), dim3(kScanThreads), 0, s, a, len, scratch);
 }
 
-constexpr int kFusedTiles = 128;
+constexpr int kFusedTiles = 256;
 
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint64_t *__restrict__ kout,
@@ -330,10 +330,21 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
         // smaller digits, plus this digit's keys in earlier tiles
         const uint32_t *hd = hist + ((int64_t)b * kRadixBins + tid) * tiles;
         uint32_t pre = 0, tot = 0;
-        for (int u = 0; u < tiles; ++u) {
-            const uint32_t c = hd[u];
-            tot += c;
-            pre += u < t ? c : 0u;
+        if ((tiles & 3) == 0) {
+            // rows of a multiple of four counts start 16-byte aligned: read them four at a time
+            const uint4 *h4 = (const uint4 *)hd;
+            for (int u4 = 0; u4 < tiles / 4; ++u4) {
+                const uint4 c = h4[u4];
+                const int u = 4 * u4;
+                tot += c.x + c.y + c.z + c.w;
+                pre += (u < t ? c.x : 0u) + (u + 1 < t ? c.y : 0u) + (u + 2 < t ? c.z : 0u) + (u + 3 < t ? c.w : 0u);
+            }
+        } else {
+            for (int u = 0; u < tiles; ++u) {
+                const uint32_t c = hd[u];
+                tot += c;
+                pre += u < t ? c : 0u;
+            }
         }
         const uint32_t incl = wave_incl_scan_u32(tot, lane);
         if (lane == kWave - 1) dsum[wave] = incl;
