@@ -2,7 +2,10 @@
 
 - 2^20 chains (phi 0.1), theta in {0.3, 0.5, 0.7}: FP32-mixed (and FP64 at 0.5) field against the oracle on
   2048 sampled targets (the oracle computes targets one by one), interaction counts equal on every sampled
-  target; energy against the oracle's full evaluation at theta 0.5.
+  target; energy against the oracle's full evaluation at theta 0.5; at theta 0.5 also in launch shape 15,
+  the persistent cost-ordered shape the benchmark's autotuner picks for the MD step.
+- 2^20 chains: the MD step's fused forward + adjoint walk in launch shape 15, both precisions, two calls
+  (the second ordered by the first's costs), against the oracle's full frozen-structure adjoint.
 - 2^18 differentiation workload: full FP32-mixed adjoint against the oracle's frozen-structure adjoint, and
   on the 512-particle subset the GPU adjoint against central finite differences of the oracle's frozen
   energy (h = 1e-6).
@@ -29,8 +32,8 @@ def chains():
     return workloads.cached("chains_n1048576_seed1003", lambda: workloads.config3())
 
 
-def _field(w, theta, precision, counters=True):
-    bh = BarnesHut(w.n, 1, 16, theta, precision)
+def _field(w, theta, precision, counters=True, tuning_id=-1):
+    bh = BarnesHut(w.n, 1, 16, theta, precision, tuning_id=tuning_id)
     pos = torch.from_numpy(w.pos).cuda()
     mom = torch.from_numpy(w.mom).cuda()
     bh.build(pos)
@@ -43,14 +46,15 @@ def _field(w, theta, precision, counters=True):
     return out
 
 
-@pytest.mark.parametrize("theta,precision", [(0.3, "fp32_mixed"), (0.5, "fp32_mixed"), (0.7, "fp32_mixed"),
-                                             (0.5, "fp64")])
-def test_chains_2p20_sampled_targets(oracle_mod, chains, theta, precision):
+@pytest.mark.parametrize("theta,precision,tuning_id", [(0.3, "fp32_mixed", -1), (0.5, "fp32_mixed", -1),
+                                                       (0.7, "fp32_mixed", -1), (0.5, "fp64", -1),
+                                                       (0.5, "fp32_mixed", 15), (0.5, "fp64", 15)])
+def test_chains_2p20_sampled_targets(oracle_mod, chains, theta, precision, tuning_id):
     w = chains
     t = oracle_mod.Tree(w.pos, w.mom, 16)
     idx = np.sort(np.random.default_rng(int(theta * 100)).choice(w.n, 2048, replace=False))
     Href, nf, nr = t.field_subset(theta, idx)
-    g = _field(w, theta, precision)
+    g = _field(w, theta, precision, tuning_id=tuning_id)
     assert (g["nf"][idx] == nf).all() and (g["nr"][idx] == nr).all()
     e = errors(g["H"][:, idx], Href)
     tol = 1e-5 if precision == "fp32_mixed" else 1e-12
@@ -58,6 +62,27 @@ def test_chains_2p20_sampled_targets(oracle_mod, chains, theta, precision):
     if theta == 0.5:
         H, _, _ = t.field(theta)
         assert energy_err(g["E"], oracle_mod.energy(w.mom, H), w.mom, H) <= tol
+
+
+@pytest.fixture(scope="module")
+def chains_grad(oracle_mod, chains):
+    _, _, dr, dm = oracle_mod.Tree(chains.pos, chains.mom, 16).energy_grad(0.5, None)
+    return dr, dm
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32_mixed", 1e-5), ("fp64", 1e-12)])
+def test_chains_2p20_md_adjoint_bench_shape(chains, chains_grad, precision, tol):
+    w = chains
+    dr, dm = chains_grad
+    bh = BarnesHut(w.n, 1, 16, 0.5, precision, tuning_id=15)
+    bh.build(torch.from_numpy(w.pos).cuda())
+    mom = torch.from_numpy(w.mom).cuda()
+    for call in range(2):
+        gdr, gdm = bh.field_backward(mom, None, gE=torch.ones(1, dtype=torch.float64, device="cuda"))
+        assert bh.check_status() == 0
+        gdr, gdm = gdr.cpu().numpy(), gdm.cpu().numpy()
+        assert np.linalg.norm(gdr - dr) / np.linalg.norm(dr) <= tol, call
+        assert np.linalg.norm(gdm - dm) / np.linalg.norm(dm) <= tol, call
 
 
 def test_differentiation_2p18_full_adjoint(oracle_mod):
