@@ -96,7 +96,6 @@ void carve(const Layout &Lc, void *base, Workspace &w)
     w.node_level = (int32_t *)take(4 * mn);
     w.node_m64 = (double *)take(4 * 8 * mn);
     w.ones = (double *)take(8 * (size_t)L.B);
-    w.arrive = (uint32_t *)take(4 * mn);
     w.lvl = (uint32_t *)take(4 * 128);
     w.lvl_nodes = (int32_t *)take(4 * mn);
     w.leaf_of = (int32_t *)take(4 * nt);

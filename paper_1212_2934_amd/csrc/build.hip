@@ -6,7 +6,7 @@
 // centre of the members).  The lock-based insertion of the paper is replaced by the binary radix tree
 // construction of T. Karras, "Maximizing parallelism in the construction of BVHs, octrees, and k-d
 // trees" (HPG 2012), collapsed to an octree with leaf size leaf_size; the spin-waiting moment kernel
-// is replaced by a lock-free last-arriver upward pass.
+// is replaced by a level-synchronous upward pass (one launch per level, or one workgroup for small trees).
 #include "ffbh_internal.h"
 
 namespace ffbh {
@@ -566,7 +566,7 @@ __global__ __launch_bounds__(256) void k_oct_emit(int64_t n, int64_t nint_tot, i
                                                   const int32_t *__restrict__ nchild,
                                                   const uint32_t *__restrict__ scan,
                                                   NodeRec *__restrict__ nodes, int32_t *__restrict__ node_level,
-                                                  uint32_t *__restrict__ arrive, int32_t *__restrict__ leaf_of,
+                                                  int32_t *__restrict__ leaf_of,
                                                   int32_t *__restrict__ octid, uint32_t *__restrict__ status,
                                                   int64_t max_nodes)
 {
@@ -594,7 +594,6 @@ __global__ __launch_bounds__(256) void k_oct_emit(int64_t n, int64_t nint_tot, i
         if (r.nchild == 0) write_leaf_of(leaf_of, b * n, (int)n, (int)b, B * n);
         nodes[b] = r;
         node_level[b] = lev;
-        arrive[b] = 0u;
     }
     if (g >= nint_tot) return;
     const int nc = nchild[g];
@@ -649,7 +648,6 @@ __global__ __launch_bounds__(256) void k_oct_emit(int64_t n, int64_t nint_tot, i
             r.parent = -1;  // set by k_oct_link
             nodes[id] = r;
             node_level[id] = clev;
-            arrive[id] = 0u;
             if (cn == 0) write_leaf_of(leaf_of, b * n + cf, cc, id, B * n);
             ++id;
         } else if (sp > 5) {
@@ -969,7 +967,7 @@ hipError_t launch_build(Handle &h, const double *d_pos, hipStream_t s, const dou
     }
     hipLaunchKernelGGL(k_oct_emit, dim3(grid_for(nint > B ? nint : B, 256)), dim3(256), 0, s, n, nint, B,
                        (int)h.p.leaf_size, w.bin_left, w.bin_right, w.bin_first, w.bin_last, w.bin_delta,
-                       w.bin_nchild, w.bin_scan, w.nodes, w.node_level, w.arrive, w.leaf_of, w.bin_octid,
+                       w.bin_nchild, w.bin_scan, w.nodes, w.node_level, w.leaf_of, w.bin_octid,
                        w.status, L.max_nodes);
     if (nint > 0)
         hipLaunchKernelGGL(k_oct_link, dim3(grid_for(nint, 256)), dim3(256), 0, s, nint, B,

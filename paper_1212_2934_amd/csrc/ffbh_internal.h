@@ -74,7 +74,6 @@ struct Workspace {
     double *node_q64;        // max_nodes x 16: first moment D (row-major 3x3, then pad) per node, FP64
     float *node_q32;         // max_nodes x 16: the same rounded to FP32 (mixed-precision traversal)
     double *ones;            // B: constant 1.0 (dL/dE for the MD force)
-    uint32_t *arrive;        // max_nodes: (unused) arrival counters
     uint32_t *lvl;           // 128: per-level node counts [0,22), bucket starts [32,55), cursors [64,86)
     int32_t *lvl_nodes;      // max_nodes: node ids bucketed by level
     int32_t *leaf_of;        // N_tot: sorted particle -> its leaf
