@@ -61,6 +61,10 @@ def lib():
         L.or_energy_frozen.argtypes = [i64, P, P, P, i64, P, P, P, P, P, P, P, P]
         L.or_energy_frozen.restype = C.c_double
         L.or_fd_grad_frozen.argtypes = [i64, P, P, P, i64, P, P, P, P, P, P, P, C.c_double, P, P]
+        L.or_bh_vjp_order.argtypes = [P, C.c_double, C.c_int, P, P, P]
+        L.or_energy_frozen_order.argtypes = [i64, P, P, P, i64, P, P, P, P, P, P, P, C.c_int, P]
+        L.or_energy_frozen_order.restype = C.c_double
+        L.or_fd_grad_frozen_order.argtypes = [i64, P, P, P, i64, P, P, P, P, P, P, P, C.c_double, C.c_int, P, P]
         L.or_num_threads.restype = C.c_int
         _lib = L
     return _lib
@@ -183,19 +187,23 @@ class Tree:
         assert lib().or_bh_lists(self._h, theta, _p(fp), _p(fn), _p(npt), _p(ni)) == 0
         return dict(far_ptr=fp, far_node=fn, near_ptr=npt, near_idx=ni)
 
-    def vjp(self, theta: float, hbar):
-        """(dL/dr, dL/dm) for L = sum_i hbar_i . H_i with the structure frozen."""
+    def vjp(self, theta: float, hbar, order: int = 1):
+        """(dL/dr, dL/dm) for L = sum_i hbar_i . H_i with the structure frozen (cells of the given order)."""
         hb = _f64(hbar)
         dr = np.empty((3, self.n))
         dm = np.empty((3, self.n))
-        assert lib().or_bh_vjp(self._h, theta, _p(hb), _p(dr), _p(dm)) == 0
+        if order == 1:
+            assert lib().or_bh_vjp(self._h, theta, _p(hb), _p(dr), _p(dm)) == 0
+        else:
+            assert lib().or_bh_vjp_order(self._h, theta, order, _p(hb), _p(dr), _p(dm)) == 0
         return dr, dm
 
-    def energy_grad(self, theta: float, hext=None):
-        """(H, E, dE/dr, dE/dm) for E = -1/2 sum m.H - sum m.H_ext, structure frozen."""
-        H, _, _ = self.field(theta)
+    def energy_grad(self, theta: float, hext=None, order: int = 1):
+        """(H, E, dE/dr, dE/dm) for E = -1/2 sum m.H - sum m.H_ext, structure frozen; H is linear in the
+        moments for either order, so dE/dm = -1/2 H - H_ext + the adjoint of -1/2 m."""
+        H, _, _ = self.field(theta, order)
         E = energy(self.mom, H, hext)
-        dr, dm = self.vjp(theta, -0.5 * self.mom)
+        dr, dm = self.vjp(theta, -0.5 * self.mom, order)
         he = np.zeros(3) if hext is None else _f64(hext)
         dm = dm - 0.5 * H - he[:, None]
         return H, E, dr, dm
@@ -207,26 +215,26 @@ def frozen_structure(tree: Tree, theta: float) -> dict:
     return d
 
 
-def energy_frozen(pos, mom, hext, st: dict) -> float:
+def energy_frozen(pos, mom, hext, st: dict, order: int = 1) -> float:
     pos, mom = _f64(pos), _f64(mom)
     he = None if hext is None else _f64(hext)
     nn = st["first"].size
-    scr = np.empty(6 * nn)
-    return lib().or_energy_frozen(pos.shape[1], _p(pos), _p(mom), _p(he), nn, _p(st["first"]),
-                                  _p(st["count"]), _p(st["perm"]), _p(st["far_ptr"]),
-                                  _p(st["far_node"]), _p(st["near_ptr"]), _p(st["near_idx"]),
-                                  _p(scr))
+    scr = np.empty(15 * nn)
+    return lib().or_energy_frozen_order(pos.shape[1], _p(pos), _p(mom), _p(he), nn, _p(st["first"]),
+                                        _p(st["count"]), _p(st["perm"]), _p(st["far_ptr"]),
+                                        _p(st["far_node"]), _p(st["near_ptr"]), _p(st["near_idx"]),
+                                        order, _p(scr))
 
 
-def fd_grad_frozen(pos, mom, hext, st: dict, h: float = 1e-6):
+def fd_grad_frozen(pos, mom, hext, st: dict, h: float = 1e-6, order: int = 1):
     """Central differences (step h) of the frozen-structure energy in every coordinate."""
     pos, mom = _f64(pos), _f64(mom)
     he = None if hext is None else _f64(hext)
     dr = np.empty_like(pos)
     dm = np.empty_like(mom)
     nn = st["first"].size
-    assert lib().or_fd_grad_frozen(pos.shape[1], _p(pos), _p(mom), _p(he), nn, _p(st["first"]),
-                                   _p(st["count"]), _p(st["perm"]), _p(st["far_ptr"]),
-                                   _p(st["far_node"]), _p(st["near_ptr"]), _p(st["near_idx"]),
-                                   h, _p(dr), _p(dm)) == 0
+    assert lib().or_fd_grad_frozen_order(pos.shape[1], _p(pos), _p(mom), _p(he), nn, _p(st["first"]),
+                                         _p(st["count"]), _p(st["perm"]), _p(st["far_ptr"]),
+                                         _p(st["far_node"]), _p(st["near_ptr"]), _p(st["near_idx"]),
+                                         h, order, _p(dr), _p(dm)) == 0
     return dr, dm

@@ -446,6 +446,7 @@ typedef struct {
     const double *hbar;  /* the target's upstream gradient (3) */
     double gr[3];        /* gathered d/dr_i */
     double *A, *B;       /* per-node accumulators (3 * nn) */
+    double *E;           /* order 2: per-node first-moment adjoint accumulators (9 * nn) */
     double *sr, *sm;     /* per-particle scatters (3, n), original order */
     /* list recording (NULL when not used) */
     int64_t *far_out, *near_out;
@@ -471,6 +472,65 @@ static void first_moment_field(const double x[3], const double D[9], double h[3]
     for (int a = 0; a < 3; ++a) h[a] = -3.0 * (u[a] + w[a] + x[a] * tr) / r5 + 15.0 * q * x[a] / r7;
 }
 
+/* Third and fourth derivatives of phi = 1/|x| (T_ab = d_a d_b phi is the tensor of Eq. H_dip):
+ *   P_abk  = d_a d_b d_k phi = 3 (delta_ab x_k + delta_ak x_b + delta_bk x_a) / r^5 - 15 x_a x_b x_k / r^7,
+ *   Q_abkl = d_l P_abk = 105 x_a x_b x_k x_l / r^9
+ *            - 15 (delta_ab x_k x_l + delta_ak x_b x_l + delta_bk x_a x_l
+ *                  + delta_al x_b x_k + delta_bl x_a x_k + delta_kl x_a x_b) / r^7
+ *            + 3 (delta_ab delta_kl + delta_ak delta_bl + delta_bk delta_al) / r^5 .                      */
+static void phi3(const double x[3], double P[27])
+{
+    double r2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
+    double r = sqrt(r2);
+    double r5 = r2 * r2 * r, r7 = r5 * r2;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+            for (int k = 0; k < 3; ++k)
+                P[(3 * a + b) * 3 + k] = 3.0 * ((a == b) * x[k] + (a == k) * x[b] + (b == k) * x[a]) / r5 -
+                                         15.0 * x[a] * x[b] * x[k] / r7;
+}
+
+static void phi4(const double x[3], double Q[81])
+{
+    double r2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
+    double r = sqrt(r2);
+    double r5 = r2 * r2 * r, r7 = r5 * r2, r9 = r7 * r2;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+            for (int k = 0; k < 3; ++k)
+                for (int l = 0; l < 3; ++l) {
+                    double t4 = 105.0 * x[a] * x[b] * x[k] * x[l] / r9;
+                    double t2 = ((a == b) * x[k] * x[l] + (a == k) * x[b] * x[l] + (b == k) * x[a] * x[l] +
+                                 (a == l) * x[b] * x[k] + (b == l) * x[a] * x[k] + (k == l) * x[a] * x[b]) / r7;
+                    double t0 = ((a == b) * (k == l) + (a == k) * (b == l) + (b == k) * (a == l)) / r5;
+                    Q[((3 * a + b) * 3 + k) * 3 + l] = t4 - 15.0 * t2 + 3.0 * t0;
+                }
+}
+
+/* Adjoint of one order-2 cell term Lambda = u . h_D(x), h_D,a = -sum_{k,b} P_abk D_kb, for u = the
+ * target's upstream gradient: d Lambda / d x_l = -sum_{a,b,k} u_a D_kb Q_abkl (to the target, and with
+ * the opposite sign to the cell's centre) and d Lambda / d D_kb = -sum_a u_a P_abk.                     */
+static void first_moment_adjoint(const double x[3], const double D[9], const double u[3], double G[3],
+                                 double E[9])
+{
+    double P[27], Q[81];
+    phi3(x, P);
+    phi4(x, Q);
+    for (int l = 0; l < 3; ++l) {
+        double s = 0.0;
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b)
+                for (int k = 0; k < 3; ++k) s += u[a] * D[3 * k + b] * Q[((3 * a + b) * 3 + k) * 3 + l];
+        G[l] = -s;
+    }
+    for (int k = 0; k < 3; ++k)
+        for (int b = 0; b < 3; ++b) {
+            double s = 0.0;
+            for (int a = 0; a < 3; ++a) s += u[a] * P[(3 * a + b) * 3 + k];
+            E[3 * k + b] = -s;
+        }
+}
+
 static void do_far(visit_ctx *v, int64_t id)
 {
     const or_tree *t = v->t;
@@ -493,6 +553,15 @@ static void do_far(visit_ctx *v, int64_t id)
             v->gr[a] += g[a];
             v->B[3 * id + a] -= g[a];
             v->A[3 * id + a] += h[a];
+        }
+        if (v->order == 2) {
+            double G[3], E[9];
+            first_moment_adjoint(x, &t->D[9 * id], v->hbar, G, E);
+            for (int a = 0; a < 3; ++a) {
+                v->gr[a] += G[a];
+                v->B[3 * id + a] -= G[a];
+            }
+            for (int q = 0; q < 9; ++q) v->E[9 * id + q] += E[q];
         }
     }
 }
@@ -717,6 +786,86 @@ int or_bh_vjp(const or_tree *t, double theta, const double *hbar, double *dLdr, 
     return 0;
 }
 
+/* Adjoint with cells of the given order (see or_bh_field_order).  Order 2 adds, per accepted cell, the
+ * first-moment term's gradient to the target and the cell centre, and accumulates dL/dD_C (E_C); since
+ * D_C = sum_j (r_j - c_C) m_j^T with c_C the members' mean, every member j of C then receives
+ *     dL/dr_j += E_C m_j - E_C M_C / n_C ,   dL/dm_j += E_C^T (r_j - c_C) .                              */
+int or_bh_vjp_order(const or_tree *t, double theta, int order, const double *hbar, double *dLdr, double *dLdm)
+{
+    if (!t || !(theta >= 0.0) || !hbar || !dLdr || !dLdm || (order != 1 && order != 2)) return -1;
+    int64_t n = t->n, nn = t->nn;
+    int nth = omp_get_max_threads();
+    double *A = calloc((size_t)nth * 3 * nn, sizeof(double));
+    double *B = calloc((size_t)nth * 3 * nn, sizeof(double));
+    double *E = calloc((size_t)nth * 9 * nn, sizeof(double));
+    double *sr = calloc((size_t)nth * 3 * n, sizeof(double));
+    double *sm = calloc((size_t)nth * 3 * n, sizeof(double));
+    double *gather = calloc((size_t)3 * n, sizeof(double));
+    if (!A || !B || !E || !sr || !sm || !gather) {
+        free(A); free(B); free(E); free(sr); free(sm); free(gather);
+        return -2;
+    }
+#pragma omp parallel num_threads(nth)
+    {
+        int tid = omp_get_thread_num();
+#pragma omp for schedule(static)
+        for (int64_t i = 0; i < n; ++i) {
+            visit_ctx v;
+            double hb[3];
+            ctx_init(&v, t, theta, i);
+            v.order = order;
+            load3(hbar, n, i, hb);
+            v.hbar = hb;
+            v.A = A + (size_t)tid * 3 * nn;
+            v.B = B + (size_t)tid * 3 * nn;
+            v.E = E + (size_t)tid * 9 * nn;
+            v.sr = sr + (size_t)tid * 3 * n;
+            v.sm = sm + (size_t)tid * 3 * n;
+            visit(&v, 0);
+            for (int a = 0; a < 3; ++a) gather[a * n + i] = v.gr[a];
+        }
+    }
+    for (int q = 1; q < nth; ++q) {
+        for (int64_t x = 0; x < 3 * nn; ++x) {
+            A[x] += A[(size_t)q * 3 * nn + x];
+            B[x] += B[(size_t)q * 3 * nn + x];
+        }
+        for (int64_t x = 0; x < 9 * nn; ++x) E[x] += E[(size_t)q * 9 * nn + x];
+        for (int64_t x = 0; x < 3 * n; ++x) {
+            sr[x] += sr[(size_t)q * 3 * n + x];
+            sm[x] += sm[(size_t)q * 3 * n + x];
+        }
+    }
+    for (int64_t i = 0; i < 3 * n; ++i) {
+        dLdr[i] = gather[i] + sr[i];
+        dLdm[i] = sm[i];
+    }
+    for (int64_t id = 0; id < nn; ++id) {
+        double inv = 1.0 / (double)t->count[id];
+        const double *Ec = &E[9 * id], *Mc = &t->M[3 * id], *cc = &t->c[3 * id];
+        double EM[3];
+        for (int k = 0; k < 3; ++k) EM[k] = Ec[3 * k] * Mc[0] + Ec[3 * k + 1] * Mc[1] + Ec[3 * k + 2] * Mc[2];
+        for (int64_t q = t->first[id]; q < t->first[id] + t->count[id]; ++q) {
+            int64_t j = t->perm[q];
+            for (int a = 0; a < 3; ++a) {
+                dLdm[a * n + j] += A[3 * id + a];
+                dLdr[a * n + j] += B[3 * id + a] * inv;
+            }
+            if (order == 2) {
+                double mj[3], dj[3];
+                load3(t->mom, n, j, mj);
+                for (int a = 0; a < 3; ++a) dj[a] = t->pos[a * n + j] - cc[a];
+                for (int k = 0; k < 3; ++k)
+                    dLdr[k * n + j] += Ec[3 * k] * mj[0] + Ec[3 * k + 1] * mj[1] + Ec[3 * k + 2] * mj[2] - EM[k] * inv;
+                for (int b = 0; b < 3; ++b)
+                    dLdm[b * n + j] += Ec[b] * dj[0] + Ec[3 + b] * dj[1] + Ec[6 + b] * dj[2];
+            }
+        }
+    }
+    free(A); free(B); free(E); free(sr); free(sm); free(gather);
+    return 0;
+}
+
 /* ------------------------------------------------------------------------------------------------ */
 /* Frozen-structure energy and its finite-difference gradient.                                        */
 /* The structure is: node membership (first/count over the sorted order `perm`) and the lists of      */
@@ -724,12 +873,37 @@ int or_bh_vjp(const or_tree *t, double theta, const double *hbar, double *dLdr, 
 /* given (pos, mom), so this is the function whose exact gradient the adjoint returns.                */
 /* ------------------------------------------------------------------------------------------------ */
 
+static double energy_frozen_order(int64_t n, const double *pos, const double *mom, const double *hext,
+                                  int64_t nn, const int64_t *first, const int64_t *count, const int64_t *perm,
+                                  const int64_t *far_ptr, const int64_t *far_node, const int64_t *near_ptr,
+                                  const int64_t *near_idx, int order, double *scratch /* 15 * nn */);
+
 double or_energy_frozen(int64_t n, const double *pos, const double *mom, const double *hext,
                         int64_t nn, const int64_t *first, const int64_t *count, const int64_t *perm,
                         const int64_t *far_ptr, const int64_t *far_node, const int64_t *near_ptr,
                         const int64_t *near_idx, double *scratch /* 6 * nn */)
 {
-    double *c = scratch, *M = scratch + 3 * nn;
+    return energy_frozen_order(n, pos, mom, hext, nn, first, count, perm, far_ptr, far_node, near_ptr, near_idx,
+                               1, scratch);
+}
+
+/* Frozen-structure energy with cells of the given order (order 2: each far cell also contributes its
+ * first moment, recomputed from (pos, mom) about the recomputed centre). */
+double or_energy_frozen_order(int64_t n, const double *pos, const double *mom, const double *hext,
+                              int64_t nn, const int64_t *first, const int64_t *count, const int64_t *perm,
+                              const int64_t *far_ptr, const int64_t *far_node, const int64_t *near_ptr,
+                              const int64_t *near_idx, int order, double *scratch /* 15 * nn */)
+{
+    return energy_frozen_order(n, pos, mom, hext, nn, first, count, perm, far_ptr, far_node, near_ptr, near_idx,
+                               order, scratch);
+}
+
+static double energy_frozen_order(int64_t n, const double *pos, const double *mom, const double *hext,
+                                  int64_t nn, const int64_t *first, const int64_t *count, const int64_t *perm,
+                                  const int64_t *far_ptr, const int64_t *far_node, const int64_t *near_ptr,
+                                  const int64_t *near_idx, int order, double *scratch)
+{
+    double *c = scratch, *M = scratch + 3 * nn, *D = scratch + 6 * nn;
     for (int64_t id = 0; id < nn; ++id) {
         double S[3] = {0.0, 0.0, 0.0}, Ms[3] = {0.0, 0.0, 0.0};
         for (int64_t k = first[id]; k < first[id] + count[id]; ++k) {
@@ -743,6 +917,15 @@ double or_energy_frozen(int64_t n, const double *pos, const double *mom, const d
             c[3 * id + a] = S[a] / (double)count[id];
             M[3 * id + a] = Ms[a];
         }
+        if (order == 2) {
+            double Dc[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+            for (int64_t k = first[id]; k < first[id] + count[id]; ++k) {
+                int64_t j = perm[k];
+                for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b) Dc[3 * a + b] += (pos[a * n + j] - c[3 * id + a]) * mom[b * n + j];
+            }
+            memcpy(&D[9 * id], Dc, sizeof(Dc));
+        }
     }
     double e_dip = 0.0, e_ext = 0.0;
     for (int64_t i = 0; i < n; ++i) {
@@ -754,6 +937,10 @@ double or_energy_frozen(int64_t n, const double *pos, const double *mom, const d
             for (int a = 0; a < 3; ++a) x[a] = ri[a] - c[3 * id + a];
             dip_field(x, &M[3 * id], h);
             for (int a = 0; a < 3; ++a) H[a] += h[a];
+            if (order == 2) {
+                first_moment_field(x, &D[9 * id], h);
+                for (int a = 0; a < 3; ++a) H[a] += h[a];
+            }
         }
         for (int64_t q = near_ptr[i]; q < near_ptr[i + 1]; ++q) {
             int64_t j = near_idx[q];
@@ -770,17 +957,32 @@ double or_energy_frozen(int64_t n, const double *pos, const double *mom, const d
     return -0.5 * e_dip - e_ext;
 }
 
-/* Central differences of or_energy_frozen in every coordinate of pos and mom (step h). */
+/* Central differences of the frozen-structure energy (cells of the given order) in every coordinate of
+ * pos and mom (step h). */
+int or_fd_grad_frozen_order(int64_t n, const double *pos, const double *mom, const double *hext,
+                            int64_t nn, const int64_t *first, const int64_t *count, const int64_t *perm,
+                            const int64_t *far_ptr, const int64_t *far_node, const int64_t *near_ptr,
+                            const int64_t *near_idx, double h, int order, double *dEdr, double *dEdm);
+
 int or_fd_grad_frozen(int64_t n, const double *pos, const double *mom, const double *hext,
                       int64_t nn, const int64_t *first, const int64_t *count, const int64_t *perm,
                       const int64_t *far_ptr, const int64_t *far_node, const int64_t *near_ptr,
                       const int64_t *near_idx, double h, double *dEdr, double *dEdm)
 {
+    return or_fd_grad_frozen_order(n, pos, mom, hext, nn, first, count, perm, far_ptr, far_node, near_ptr,
+                                   near_idx, h, 1, dEdr, dEdm);
+}
+
+int or_fd_grad_frozen_order(int64_t n, const double *pos, const double *mom, const double *hext,
+                            int64_t nn, const int64_t *first, const int64_t *count, const int64_t *perm,
+                            const int64_t *far_ptr, const int64_t *far_node, const int64_t *near_ptr,
+                            const int64_t *near_idx, double h, int order, double *dEdr, double *dEdm)
+{
 #pragma omp parallel
     {
         double *p = malloc(3 * n * sizeof(double));
         double *m = malloc(3 * n * sizeof(double));
-        double *scr = malloc(6 * nn * sizeof(double));
+        double *scr = malloc(15 * nn * sizeof(double));
         memcpy(p, pos, 3 * n * sizeof(double));
         memcpy(m, mom, 3 * n * sizeof(double));
 #pragma omp for schedule(dynamic, 4)
@@ -789,11 +991,11 @@ int or_fd_grad_frozen(int64_t n, const double *pos, const double *mom, const dou
             int64_t x = q < 3 * n ? q : q - 3 * n;
             double keep = arr[x];
             arr[x] = keep + h;
-            double ep = or_energy_frozen(n, p, m, hext, nn, first, count, perm, far_ptr, far_node,
-                                         near_ptr, near_idx, scr);
+            double ep = energy_frozen_order(n, p, m, hext, nn, first, count, perm, far_ptr, far_node,
+                                            near_ptr, near_idx, order, scr);
             arr[x] = keep - h;
-            double em = or_energy_frozen(n, p, m, hext, nn, first, count, perm, far_ptr, far_node,
-                                         near_ptr, near_idx, scr);
+            double em = energy_frozen_order(n, p, m, hext, nn, first, count, perm, far_ptr, far_node,
+                                            near_ptr, near_idx, order, scr);
             arr[x] = keep;
             double d = (ep - em) / (2.0 * h);
             if (q < 3 * n) dEdr[x] = d; else dEdm[x] = d;

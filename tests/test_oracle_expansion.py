@@ -100,3 +100,22 @@ def test_order_two_is_more_accurate(oracle_mod):
     assert ratio[0.25] > 1.5 * ratio[0.5] and ratio[0.5] > ratio[0.7]
     slope = np.log(ratio[0.25] / ratio[0.5]) / np.log(2.0)  # gained power of theta
     assert 0.5 < slope < 1.6, slope
+
+
+def test_order_two_adjoint_matches_finite_differences(oracle_mod):
+    """The order-2 adjoint (the first-moment term's gradient to targets and cell centres, dL/dD_C to the
+    members) against central differences of the frozen-structure order-2 energy; the frozen energy itself
+    equals the traversal's."""
+    w = workloads.uniform_cube(240, 9.0, seed=23, hext=(0.1, -0.2, 0.3))
+    t = oracle_mod.Tree(w.pos, w.mom, 4)
+    st = oracle_mod.frozen_structure(t, 0.7)
+    assert st["far_ptr"][-1] > 5 * w.n  # many accepted cells, so the first-moment terms matter
+    H, E, dr, dm = t.energy_grad(0.7, w.hext, order=2)
+    Ef = oracle_mod.energy_frozen(w.pos, w.mom, w.hext, st, order=2)
+    assert abs(Ef - E) <= 1e-13 * abs(E)
+    fr, fm = oracle_mod.fd_grad_frozen(w.pos, w.mom, w.hext, st, h=1e-6, order=2)
+    assert np.linalg.norm(dr - fr) <= 1e-7 * np.linalg.norm(fr)
+    assert np.linalg.norm(dm - fm) <= 1e-7 * np.linalg.norm(fm)
+    # and the order-2 terms are not negligible here: the order-1 gradient differs by far more
+    _, _, dr1, dm1 = t.energy_grad(0.7, w.hext, order=1)
+    assert np.linalg.norm(dr1 - fr) > 100 * np.linalg.norm(dr - fr)
