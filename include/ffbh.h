@@ -73,10 +73,11 @@ typedef struct bh_params {
     int32_t precision;  /* BH_FP64: all arithmetic FP64.  BH_FP32_MIXED: pair arithmetic in FP32 on
                            FP64 offsets, FP64 acceptance test, FP64 cell sums and accumulation        */
     int32_t tuning_id;  /* traversal launch shape (see bh_num_tunings); -1 = default                  */
-    int32_t expansion;  /* cells of bh_field: 0 or 1 = the paper's pseudo-particles (Eq. magCenter);
-                           2 = plus each accepted cell's first moment D = sum_j (r_j - c) m_j^T, the next
-                           term of the Taylor expansion of Eq. H_dip about c (beyond the paper; error one
-                           power of theta lower).  bh_field_backward and md_step require 0 or 1.       */
+    int32_t expansion;  /* cells of the field, its adjoint and md_step: 0 or 1 = the paper's
+                           pseudo-particles (Eq. magCenter); 2 = plus each accepted cell's first moment
+                           D = sum_j (r_j - c) m_j^T, the next term of the Taylor expansion of Eq. H_dip
+                           about c (beyond the paper; field error one power of theta lower).  Order 2
+                           runs the adjoint walk with independent waves whatever tuning_id asks.       */
 } bh_params;
 
 typedef struct bh_handle bh_handle;

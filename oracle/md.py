@@ -150,12 +150,13 @@ def rodrigues(m, w, dt):
     return out / np.linalg.norm(out, axis=0)
 
 
-def md_step(state: dict, p: dict, step: int, theta=0.5, leaf=16, field=True):
+def md_step(state: dict, p: dict, step: int, theta=0.5, leaf=16, field=True, order=1):
     """One step for every system of state (arrays (B, 3, n)); returns the new state (copies).
 
     p: dt, kT, gamma_t, gamma_r, mass, inertia, wca_eps, wca_sigma, box_lo, box_hi, hext (B, 3), seed, and
     optionally sr_kind (0 WCA, 1 the paper's Eq. LJ form) and sr_cut (its cut-off; 0 = 2.5 sigma).
-    field=False drops the dipolar forces and torques (non-interacting particles in H_ext only).
+    field=False drops the dipolar forces and torques (non-interacting particles in H_ext only).  order: the
+    cells of the dipolar energy (1: the paper's pseudo-particles; 2: with first moments).
     """
     pos, vel, mom, om = (np.array(state[k], dtype=np.float64) for k in ("pos", "vel", "mom", "omega"))
     B, _, n = pos.shape
@@ -163,7 +164,7 @@ def md_step(state: dict, p: dict, step: int, theta=0.5, leaf=16, field=True):
     out = {k: np.empty_like(pos) for k in ("pos", "vel", "mom", "omega")}
     for b in range(B):
         if field:
-            _, _, dr, dm = Tree(pos[b], mom[b], leaf).energy_grad(theta, hext[b])
+            _, _, dr, dm = Tree(pos[b], mom[b], leaf).energy_grad(theta, hext[b], order=order)
         else:
             dr, dm = np.zeros((3, n)), -np.repeat(hext[b][:, None], n, axis=1)
         F = -dr + short_range_forces(pos[b], p) + \

@@ -132,14 +132,17 @@ __device__ inline void adj_leaf(AdjLds<T> &W, int lane, const Src *__restrict__ 
         double *__restrict__ g_rm, double *__restrict__ node_adj, double *__restrict__ Hs,                       \
         double *__restrict__ Hout, double *__restrict__ e_part, uint32_t *__restrict__ status, int64_t n,        \
         int64_t ntot, int waves_per_seg, int num_waves, double theta2, int max_nodes, int tpw, int parts,        \
-        double *__restrict__ part_buf, uint32_t *__restrict__ wave_cost
+        double *__restrict__ part_buf, uint32_t *__restrict__ wave_cost, const void *__restrict__ node_q,         \
+        double *__restrict__ node_adjq
 #define FFBH_ADJ_ARGS                                                                                           \
     nodes, node_m64, spos, smom, src, hbar, perm, hext, g_gather, g_rm, node_adj, Hs, Hout, e_part, status, n,   \
-        ntot, waves_per_seg, num_waves, theta2, max_nodes, tpw, parts, part_buf, wave_cost
+        ntot, waves_per_seg, num_waves, theta2, max_nodes, tpw, parts, part_buf, wave_cost, node_q, node_adjq
 
 // The fused walk of wave item gw.  If wave_cost is not null, lane 0 stores there a deterministic measure of
-// the item's work (node visits plus leaf pair rounds), which orders the next launch.
-template <bool MIXED>
+// the item's work (node visits plus leaf pair rounds), which orders the next launch.  QUAD: order-2 cells
+// (node_q holds each node's first moment D, stride 16); an accepted cell adds its first-moment field, its
+// gradient to the target and (negated) to the cell centre, and d/dD to node_adjq (six values, stride 8).
+template <bool MIXED, bool QUAD>
 __device__ __forceinline__ void adjoint_wave(int gw, FFBH_ADJ_PARAMS)
 {
     using T = typename std::conditional<MIXED, float, double>::type;
@@ -215,8 +218,23 @@ __device__ __forceinline__ void adjoint_wave(int gw, FFBH_ADJ_PARAMS)
             T gx, gy, gz, tx, ty, tz;
             fused_pair<MIXED, T>(acc, (T)dx, (T)dy, (T)dz, ax, ay, az, bx, by, bz, gx, gy, gz, tx, ty, tz, pgx, pgy,
                                  pgz, phx, phy, phz, grx, gry, grz, hx, hy, hz);
+            T e0 = 0, e1 = 0, e2 = 0, e3 = 0, e4 = 0, e5 = 0;
+            if constexpr (QUAD) {
+                const T *qd = (const T *)node_q + 16 * (int64_t)cur;
+                T Gx, Gy, Gz;
+                first_moment_adj<T>(acc, (T)dx, (T)dy, (T)dz, qd, ax, ay, az, Gx, Gy, Gz, e0, e1, e2, e3, e4, e5);
+                if constexpr (MIXED) {
+                    first_moment_acc<T>(acc, (T)dx, (T)dy, (T)dz, qd, phx, phy, phz);
+                    pgx += Gx; pgy += Gy; pgz += Gz;
+                } else {
+                    first_moment_acc<T>(acc, (T)dx, (T)dy, (T)dz, qd, hx, hy, hz);
+                    grx += Gx; gry += Gy; grz += Gz;
+                }
+                gx += Gx; gy += Gy; gz += Gz;
+            }
             // A_C += sum T(x) Hbar over the accepting lanes, S_C += sum g (B_C = -S_C)
             scatter6<T>(accm, lane, wcomp, node_adj + 8 * (int64_t)cur, tx, ty, tz, gx, gy, gz);
+            if constexpr (QUAD) scatter6<T>(accm, lane, wcomp, node_adjq + 8 * (int64_t)cur, e0, e1, e2, e3, e4, e5);
         }
         const uint64_t open = mask & ~accm;
         if (open == 0ull) continue;
@@ -300,7 +318,7 @@ __device__ __forceinline__ void adjoint_wave(int gw, FFBH_ADJ_PARAMS)
 // the items run out.  Every wave reaches the exit: the counter only grows.
 // Four waves per SIMD: the FP64 walk fits 128 VGPRs with a few spilled bytes and runs 7 % faster than
 // at three; the FP32-mixed walk needs fewer registers and is unaffected.
-template <bool MIXED>
+template <bool MIXED, bool QUAD>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_adjoint(
     FFBH_ADJ_PARAMS, const uint32_t *__restrict__ order,
                                                  uint32_t *__restrict__ work_ctr)
@@ -309,7 +327,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
         const int wpb = blockDim.x / kWave;
         const int gw = xcd_block(blockIdx.x, gridDim.x) * wpb + (int)(threadIdx.x / kWave);
         if (gw >= num_waves) return;
-        adjoint_wave<MIXED>(gw, FFBH_ADJ_ARGS);
+        adjoint_wave<MIXED, QUAD>(gw, FFBH_ADJ_ARGS);
         return;
     }
     const int lane = threadIdx.x & (kWave - 1);
@@ -323,7 +341,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
             if (lane == 0) set_flag(status, BH_FLAG_TREE);
             return;
         }
-        adjoint_wave<MIXED>((int)gw, FFBH_ADJ_ARGS);
+        adjoint_wave<MIXED, QUAD>((int)gw, FFBH_ADJ_ARGS);
     }
 }
 
@@ -849,22 +867,46 @@ __global__ __launch_bounds__(256) void k_zero_nodes(double *__restrict__ a, cons
 
 // Downward pass and output: members collect their cells' adjoints along the leaf-to-root path; the
 // explicit derivative of E in m (-1/2 H - H_ext, times dL/dE) is added; results go to caller order.
+// With order-2 cells (node_adjq not null) a member j of cell C also receives, through
+// D_C = sum (r_j - c_C) m_j^T and c_C = the members' mean, dL/dr_j += E_C m_j - E_C M_C / n_C and
+// dL/dm_j += E_C (r_j - c_C) (E_C symmetric, stored as xx, yy, zz, xy, xz, yz).
 __global__ __launch_bounds__(256) void k_downward(
     const NodeRec *__restrict__ nodes, const int32_t *__restrict__ leaf_of, const double *__restrict__ node_adj,
     const double *__restrict__ g_gather, const double *__restrict__ g_rm, const double *__restrict__ Hs, const double *__restrict__ hext, const double *__restrict__ gE,
     const uint32_t *__restrict__ perm, int64_t n, int64_t ntot, double *__restrict__ dpos,
-    double *__restrict__ dmom, int64_t max_nodes)
+    double *__restrict__ dmom, int64_t max_nodes, const double *__restrict__ node_adjq,
+    const double *__restrict__ node_m64, const double *__restrict__ spos, const double *__restrict__ smom)
 {
     int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (s >= ntot) return;
     double Ax = 0.0, Ay = 0.0, Az = 0.0, Bx = 0.0, By = 0.0, Bz = 0.0;
+    double qr[3] = {0.0, 0.0, 0.0}, qm[3] = {0.0, 0.0, 0.0};
+    double rj[3] = {0.0, 0.0, 0.0}, mj[3] = {0.0, 0.0, 0.0};
+    if (node_adjq) {
+        for (int a = 0; a < 3; ++a) {
+            rj[a] = spos[a * ntot + s];
+            mj[a] = smom[a * ntot + s];
+        }
+    }
     int node = leaf_of[s];
     for (int depth = 0; node >= 0 && node < max_nodes && depth < 2 * kMaxLevel + 2; ++depth) {
         const double *a = node_adj + 8 * (int64_t)node;
-        const double inv = 1.0 / (double)nodes[node].count;
+        const NodeRec nd = nodes[node];
+        const double inv = 1.0 / (double)nd.count;
         Ax += a[0]; Ay += a[1]; Az += a[2];
         Bx += a[3] * inv; By += a[4] * inv; Bz += a[5] * inv;
-        node = nodes[node].parent;
+        if (node_adjq) {
+            const double *e = node_adjq + 8 * (int64_t)node;
+            const double E[3][3] = {{e[0], e[3], e[4]}, {e[3], e[1], e[5]}, {e[4], e[5], e[2]}};
+            const double *M = node_m64 + 4 * (int64_t)node;
+            const double d[3] = {rj[0] - nd.cx, rj[1] - nd.cy, rj[2] - nd.cz};
+            for (int k = 0; k < 3; ++k) {
+                qr[k] += E[k][0] * (mj[0] - M[0] * inv) + E[k][1] * (mj[1] - M[1] * inv) +
+                         E[k][2] * (mj[2] - M[2] * inv);
+                qm[k] += E[k][0] * d[0] + E[k][1] * d[1] + E[k][2] * d[2];
+            }
+        }
+        node = nd.parent;
     }
     const int64_t o = perm[s], b = o / n, i = o - b * n;
     if (o >= ntot) return;
@@ -872,14 +914,14 @@ __global__ __launch_bounds__(256) void k_downward(
     const double *he = hext ? hext + 3 * b : nullptr;
     double *dp = dpos + b * 3 * n, *dm = dmom + b * 3 * n;
     const double *q = g_rm + 8 * s;
-    dp[i] = g_gather[s] - q[0] - Bx;
-    dp[n + i] = g_gather[ntot + s] - q[1] - By;
-    dp[2 * n + i] = g_gather[2 * ntot + s] - q[2] - Bz;
+    dp[i] = g_gather[s] - q[0] - Bx + qr[0];
+    dp[n + i] = g_gather[ntot + s] - q[1] - By + qr[1];
+    dp[2 * n + i] = g_gather[2 * ntot + s] - q[2] - Bz + qr[2];
     double ex = -0.5 * Hs[s], ey = -0.5 * Hs[ntot + s], ez = -0.5 * Hs[2 * ntot + s];
     if (he) { ex -= he[0]; ey -= he[1]; ez -= he[2]; }
-    dm[i] = q[3] + Ax + ge * ex;
-    dm[n + i] = q[4] + Ay + ge * ey;
-    dm[2 * n + i] = q[5] + Az + ge * ez;
+    dm[i] = q[3] + Ax + ge * ex + qm[0];
+    dm[n + i] = q[4] + Ay + ge * ey + qm[1];
+    dm[2 * n + i] = q[5] + Az + ge * ez + qm[2];
 }
 
 // dL/dH_ext = -dL/dE * sum_i m_i, one block per system.
@@ -915,13 +957,18 @@ hipError_t launch_backward(Handle &h, const double *d_mom, const double *d_hext,
                        L.ntot, w.hbar);
     hipLaunchKernelGGL(k_zero_nodes, dim3(grid_for(8 * L.max_nodes, 256, 2048)), dim3(256), 0, s, w.node_adj,
                        w.status + 2, L.max_nodes);
+    const bool quad = L.expansion == 2;
+    if (quad)
+        hipLaunchKernelGGL(k_zero_nodes, dim3(grid_for(8 * L.max_nodes, 256, 2048)), dim3(256), 0, s, w.node_adjq,
+                           w.status + 2, L.max_nodes);
     hipLaunchKernelGGL(k_zero, dim3(grid_for(8 * L.ntot, 256, 4096)), dim3(256), 0, s, w.g_rm, 8 * L.ntot);
     const int wpb = h.waves_per_block;
     const int waves_per_seg = (int)((L.n + kWave - 1) / kWave);
     const double theta2 = h.p.theta * h.p.theta;
     if (h.ev[2]) (void)hipEventRecord(h.ev[2], s);
     const bool mixed = h.p.precision == BH_FP32_MIXED;
-    const int nw = h.adj_coop;
+    // order-2 cells run the independent-wave walk whatever the shape's cooperative or two-target setting
+    const int nw = quad ? 1 : h.adj_coop;
     if (nw > 1) {
         const int bps = (waves_per_seg + nw - 1) / nw;
         const unsigned gblocks = (unsigned)(L.B * bps);
@@ -935,7 +982,7 @@ hipError_t launch_backward(Handle &h, const double *d_mom, const double *d_hext,
         else if (nw == 2) FFBH_WG(false, 2);
         else FFBH_WG(false, 4);
 #undef FFBH_WG
-    } else if (h.adj_two) {
+    } else if (h.adj_two && !quad) {
         // waves of 128 targets; the energy partials are indexed by these waves
         const int wps2 = (int)((L.n + 2 * kWave - 1) / (2 * kWave));
         const int nw2 = (int)(L.B * wps2);
@@ -961,16 +1008,17 @@ hipError_t launch_backward(Handle &h, const double *d_mom, const double *d_hext,
         const unsigned grid = sched && (unsigned)h.adj_resident < blk ? (unsigned)h.adj_resident : blk;
         const uint32_t *ord = sched ? w.wave_order : nullptr;
         uint32_t *cost = parts == 1 ? w.wave_cost : nullptr;
-        if (mixed)
-            hipLaunchKernelGGL(k_adjoint<true>, dim3(grid), dim3(wpb * kWave), wpb * sizeof(AdjLds<float>), s,
-                               w.nodes, w.node_m64, w.spos, w.smom, w.src32, w.hbar, w.perm, d_hext, w.g_gather,
-                               w.g_rm, w.node_adj, w.Hs, d_H, w.e_part, w.status, L.n, L.ntot, wps, nwv, theta2,
-                               (int)L.max_nodes, tpw, parts, w.part_buf, cost, ord, w.sched_ctr);
-        else
-            hipLaunchKernelGGL(k_adjoint<false>, dim3(grid), dim3(wpb * kWave), wpb * sizeof(AdjLds<double>), s,
-                               w.nodes, w.node_m64, w.spos, w.smom, w.src64, w.hbar, w.perm, d_hext, w.g_gather,
-                               w.g_rm, w.node_adj, w.Hs, d_H, w.e_part, w.status, L.n, L.ntot, wps, nwv, theta2,
-                               (int)L.max_nodes, tpw, parts, w.part_buf, cost, ord, w.sched_ctr);
+        const void *nq = mixed ? (const void *)w.node_q32 : (const void *)w.node_q64;
+#define FFBH_ADJ(MX, QD, T)                                                                                     \
+    hipLaunchKernelGGL((k_adjoint<MX, QD>), dim3(grid), dim3(wpb * kWave), wpb * sizeof(AdjLds<T>), s, w.nodes,     \
+                       w.node_m64, w.spos, w.smom, MX ? w.src32 : w.src64, w.hbar, w.perm, d_hext, w.g_gather,    \
+                       w.g_rm, w.node_adj, w.Hs, d_H, w.e_part, w.status, L.n, L.ntot, wps, nwv, theta2,          \
+                       (int)L.max_nodes, tpw, parts, w.part_buf, cost, nq, w.node_adjq, ord, w.sched_ctr)
+        if (mixed && quad) FFBH_ADJ(true, true, float);
+        else if (mixed) FFBH_ADJ(true, false, float);
+        else if (quad) FFBH_ADJ(false, true, double);
+        else FFBH_ADJ(false, false, double);
+#undef FFBH_ADJ
         if (parts > 1)
             hipLaunchKernelGGL(k_parts_sum, dim3((unsigned)((L.n + 255) / 256), (unsigned)L.B), dim3(256), 0, s,
                                w.part_buf, parts, w.smom, d_hext, w.perm, w.g_gather, w.Hs, d_H, w.e_part, L.n,
@@ -981,7 +1029,7 @@ hipError_t launch_backward(Handle &h, const double *d_mom, const double *d_hext,
         launch_energy_final(h, d_E, s, nw > 1 || h.adj_parts > 1 ? kWave : h.adj_two ? 2 * kWave : h.adj_tpw);
     hipLaunchKernelGGL(k_downward, dim3(grid_for(L.ntot, 256)), dim3(256), 0, s, w.nodes, w.leaf_of, w.node_adj,
                        w.g_gather, w.g_rm, w.Hs, d_hext, d_gE, w.perm, L.n, L.ntot, d_dpos, d_dmom,
-                       L.max_nodes);
+                       L.max_nodes, quad ? w.node_adjq : nullptr, w.node_m64, w.spos, w.smom);
     if (d_dhext)
         hipLaunchKernelGGL(k_dhext, dim3((unsigned)L.B), dim3(1024), 0, s, d_mom, d_gE, L.n, d_dhext);
     return hipGetLastError();
@@ -994,12 +1042,14 @@ hipError_t adjoint_resident_blocks(Handle &h, int &blocks)
     const int wpb = h.waves_per_block;
     int per_cu = 0, cus = 0;
     hipError_t e;
+    const bool quad = h.L.expansion == 2;
     if (h.p.precision == BH_FP32_MIXED)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_adjoint<true>, wpb * kWave,
-                                                         wpb * sizeof(AdjLds<float>));
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, quad ? k_adjoint<true, true> : k_adjoint<true, false>,
+                                                         wpb * kWave, wpb * sizeof(AdjLds<float>));
     else
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_adjoint<false>, wpb * kWave,
-                                                         wpb * sizeof(AdjLds<double>));
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu,
+                                                         quad ? k_adjoint<false, true> : k_adjoint<false, false>,
+                                                         wpb * kWave, wpb * sizeof(AdjLds<double>));
     if (e != hipSuccess) return e;
     e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h.device);
     if (e != hipSuccess) return e;

@@ -118,6 +118,7 @@ void carve(const Layout &Lc, void *base, Workspace &w)
     const size_t qn = L.expansion == 2 ? mn : 0;  // first moments only for order-2 cells
     w.node_q64 = (double *)take(16 * 8 * qn);
     w.node_q32 = (float *)take(16 * 4 * qn);
+    w.node_adjq = (double *)take(8 * 8 * qn);  // adjoints of the first moments
     L.bytes = align_up(off, 256);
 }
 
@@ -280,7 +281,6 @@ bh_status bh_field_backward(bh_handle *hh, const double *d_mom, const double *d_
     if ((d_hext && !dptr_ok(d_hext)) || (d_gH && !dptr_ok(d_gH)) || (d_gE && !dptr_ok(d_gE)) ||
         (d_dhext && !dptr_ok(d_dhext)))
         return BH_EINVAL;
-    if (hh->h.L.expansion == 2) return BH_EINVAL;  // the adjoint follows the paper's cells only
     if (!hh->h.built) return BH_ESTATE;
     if (launch_backward(hh->h, d_mom, d_hext, d_gH, d_gE, d_dpos, d_dmom, d_dhext, (hipStream_t)stream) !=
         hipSuccess)
@@ -302,7 +302,6 @@ bh_status md_step(bh_handle *hh, const md_state *s, const md_params *p, void *st
 static bh_status md_args_ok(bh_handle *hh, const md_state *s, const md_params *p)
 {
     if (!hh || !s || !p) return BH_EINVAL;
-    if (hh->h.L.expansion == 2) return BH_EINVAL;  // forces follow the paper's cells only
     if (!dptr_ok(s->pos) || !dptr_ok(s->vel) || !dptr_ok(s->mom) || !dptr_ok(s->omega) || !dptr_ok(s->d_step))
         return BH_EINVAL;
     if (!(p->dt > 0.0) || !(p->mass > 0.0) || !(p->inertia > 0.0) || !(p->kT >= 0.0) || !(p->gamma_t >= 0.0) ||

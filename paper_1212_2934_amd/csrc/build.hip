@@ -1020,6 +1020,14 @@ static void gather_moments(Handle &h, const double *d_mom, hipStream_t s)
                        (double *)w.src64, (double *)w.src32);
 }
 
+// First moments of every node from the sorted moments and positions already in the workspace (after a
+// build with moments): the order-2 cells of an MD step.
+hipError_t launch_upward_first_moments(Handle &h, hipStream_t s)
+{
+    upward<3>(h, h.w.smom, h.w.spos, s);
+    return hipGetLastError();
+}
+
 hipError_t launch_upward_moments(Handle &h, const double *d_mom, hipStream_t s)
 {
     gather_moments(h, d_mom, s);

@@ -73,6 +73,7 @@ struct Workspace {
     uint32_t *sched_ctr;     // [0]: work counter of the persistent launch
     double *node_q64;        // max_nodes x 16: first moment D (row-major 3x3, then pad) per node, FP64
     float *node_q32;         // max_nodes x 16: the same rounded to FP32 (mixed-precision traversal)
+    double *node_adjq;       // max_nodes x 8: dL/dD of each node, symmetric (xx, yy, zz, xy, xz, yz)
     double *ones;            // B: constant 1.0 (dL/dE for the MD force)
     uint32_t *lvl;           // 128: per-level node counts [0,22), bucket starts [32,55), cursors [64,86)
     int32_t *lvl_nodes;      // max_nodes: node ids bucketed by level
@@ -171,6 +172,7 @@ inline unsigned grid_for(int64_t work, int threads, int64_t cap = (int64_t)1 << 
 // Tree build; with d_mom the moments are gathered and summed in the same upward pass (the MD step).
 hipError_t launch_build(Handle &h, const double *d_pos, hipStream_t s, const double *d_mom = nullptr);
 hipError_t launch_upward_moments(Handle &h, const double *d_mom, hipStream_t s);
+hipError_t launch_upward_first_moments(Handle &h, hipStream_t s);
 hipError_t launch_field(Handle &h, const double *d_mom, const double *d_hext, double *d_H,
                         double *d_E, hipStream_t s);
 // moments_done: the build already summed the moments (launch_build with d_mom).

@@ -272,6 +272,10 @@ hipError_t launch_md(Handle &h, const md_state *st, const md_params *mp, hipStre
     Workspace &w = h.w;
     hipError_t e = launch_build(h, st->pos, s, st->mom);  // tree, centroids and moment sums
     if (e != hipSuccess) return e;
+    if (L.expansion == 2) {
+        e = launch_upward_first_moments(h, s);  // order-2 cells
+        if (e != hipSuccess) return e;
+    }
     e = launch_backward(h, st->mom, mp->d_hext, nullptr, w.ones, w.md_grad_r, w.md_grad_m, nullptr, s, nullptr,
                         nullptr, true);
     if (e != hipSuccess) return e;

@@ -74,6 +74,51 @@ __device__ inline void first_moment_acc(bool use, T x, T y, T z, const T *D, T &
     hz = fmaT<T>(fmaT<T>(s, z, (T)-3 * (u2 + w2 + z * tr)), ri5, hz);
 }
 
+// Adjoint of the first-moment term for the target's upstream field gradient u: with phi = 1/|x|, the
+// term is h_D,a = -sum D_kb d_a d_b d_k phi, and for u . h_D
+//   G = d(u.h_D)/dx = -[105 (u.x) q x / r^9 - 15 (x (x.Du + u.Dx + (u.x) tr D) + u q + (u.x)(Dx + D^T x)) / r^7
+//                       + 3 (Du + D^T u + u tr D) / r^5]              (q = x.Dx; target gather, centre -G)
+//   E = d(u.h_D)/dD = -[3 (x u^T + u x^T + (u.x) I) / r^5 - 15 (u.x) x x^T / r^7]    (symmetric)
+// E is returned as (xx, yy, zz, xy, xz, yz).  When `use` is false every output is exactly zero.
+template <typename T>
+__device__ inline void first_moment_adj(bool use, T x, T y, T z, const T *D, T ux, T uy, T uz, T &gx, T &gy,
+                                        T &gz, T &e0, T &e1, T &e2, T &e3, T &e4, T &e5)
+{
+    const T r2 = fmaT<T>(z, z, fmaT<T>(y, y, x * x));
+    const T ri = use ? rsqT<T>(r2) : (T)0;
+    const T ri2 = ri * ri;
+    const T ri5 = ri2 * ri2 * ri, ri7 = ri5 * ri2, ri9 = ri7 * ri2;
+    const T p0 = fmaT<T>(D[2], z, fmaT<T>(D[1], y, D[0] * x));   // D x
+    const T p1 = fmaT<T>(D[5], z, fmaT<T>(D[4], y, D[3] * x));
+    const T p2 = fmaT<T>(D[8], z, fmaT<T>(D[7], y, D[6] * x));
+    const T w0 = fmaT<T>(D[6], z, fmaT<T>(D[3], y, D[0] * x));   // D^T x
+    const T w1 = fmaT<T>(D[7], z, fmaT<T>(D[4], y, D[1] * x));
+    const T w2 = fmaT<T>(D[8], z, fmaT<T>(D[5], y, D[2] * x));
+    const T d0 = fmaT<T>(D[2], uz, fmaT<T>(D[1], uy, D[0] * ux));  // D u
+    const T d1 = fmaT<T>(D[5], uz, fmaT<T>(D[4], uy, D[3] * ux));
+    const T d2 = fmaT<T>(D[8], uz, fmaT<T>(D[7], uy, D[6] * ux));
+    const T t0 = fmaT<T>(D[6], uz, fmaT<T>(D[3], uy, D[0] * ux));  // D^T u
+    const T t1 = fmaT<T>(D[7], uz, fmaT<T>(D[4], uy, D[1] * ux));
+    const T t2 = fmaT<T>(D[8], uz, fmaT<T>(D[5], uy, D[2] * ux));
+    const T tr = D[0] + D[4] + D[8];
+    const T q = fmaT<T>(z, p2, fmaT<T>(y, p1, x * p0));
+    const T ud = fmaT<T>(uz, z, fmaT<T>(uy, y, ux * x));            // u.x
+    const T uDx = fmaT<T>(uz, p2, fmaT<T>(uy, p1, ux * p0));
+    const T xDu = fmaT<T>(z, d2, fmaT<T>(y, d1, x * d0));
+    const T c9 = (T)105 * ud * q * ri9, c7 = (T)15 * ri7, c5 = (T)3 * ri5;
+    const T sx = xDu + uDx + ud * tr;
+    gx = -(c9 * x - c7 * (x * sx + ux * q + ud * (w0 + p0)) + c5 * (d0 + t0 + ux * tr));
+    gy = -(c9 * y - c7 * (y * sx + uy * q + ud * (w1 + p1)) + c5 * (d1 + t1 + uy * tr));
+    gz = -(c9 * z - c7 * (z * sx + uz * q + ud * (w2 + p2)) + c5 * (d2 + t2 + uz * tr));
+    const T f = c7 * ud;
+    e0 = -(c5 * ((T)2 * ux * x + ud) - f * x * x);
+    e1 = -(c5 * ((T)2 * uy * y + ud) - f * y * y);
+    e2 = -(c5 * ((T)2 * uz * z + ud) - f * z * z);
+    e3 = -(c5 * (uy * x + ux * y) - f * x * y);
+    e4 = -(c5 * (uz * x + ux * z) - f * x * z);
+    e5 = -(c5 * (uz * y + uy * z) - f * y * z);
+}
+
 // Adjoint pair plus the forward field.  With a = upstream field gradient of the target, b = source
 // moment, x = offset (target minus source):
 //   g  = 3 [ (a.b) x + (b.x) a + (a.x) b ] / |x|^5 - 15 (a.x)(b.x) x / |x|^7   (f_dip summand, Sec. 2)

@@ -8,7 +8,7 @@ import pytest
 import torch
 
 from paper_1212_2934_amd import workloads
-from paper_1212_2934_amd.binding import BarnesHut, BHError, md_params
+from paper_1212_2934_amd.binding import BarnesHut, md_params
 from gpu_util import run_field
 
 pytestmark = pytest.mark.gpu
@@ -75,21 +75,92 @@ def test_more_accurate_than_order_one(oracle_mod):
     assert e2 < 0.6 * e1, (e1, e2)
 
 
-def test_backward_and_md_step_rejected():
-    """The adjoint and the MD forces follow the paper's cells only: order-2 handles refuse them before
-    anything is enqueued."""
-    w = workloads.uniform_cube(500, 12.0, seed=3)
-    bh = BarnesHut(w.n, 1, 16, 0.5, "fp64", expansion=2)
+@pytest.mark.parametrize("tuning_id", [0, 5, 6, 10, 13])  # coop and two-target shapes run the plain walk
+@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
+@pytest.mark.parametrize("theta", [0.5, 0.8])
+def test_adjoint_matches_oracle(oracle_mod, precision, theta, tuning_id):
+    """dE/dr and dE/dm with order-2 cells against the oracle's order-2 adjoint (pinned by finite
+    differences of the order-2 frozen energy), three calls (persistent shapes reorder after the first)."""
+    w = workloads.uniform_cube(4096, 32.0, seed=1001, hext=(0.0, 0.0, 1.0))
+    _, _, dr, dm = oracle_mod.Tree(w.pos, w.mom, 16).energy_grad(theta, w.hext, order=2)
+    bh = BarnesHut(w.n, 1, 16, theta, precision, tuning_id=tuning_id, expansion=2)
     p = torch.from_numpy(w.pos).cuda()
     m = torch.from_numpy(w.mom).cuda()
+    he = torch.from_numpy(w.hext).cuda()
     bh.build(p)
-    with pytest.raises(BHError) as ei:
-        bh.field_backward(m, gE=torch.ones(1, dtype=torch.float64, device="cuda"))
-    assert ei.value.status == -1
-    st = {"pos": p.clone(), "vel": torch.zeros_like(p), "mom": m.clone(), "omega": torch.zeros_like(p),
-          "step": torch.zeros(1, dtype=torch.int64, device="cuda")}
-    C3 = __import__("ctypes").c_double * 3
-    mdp = md_params(1e-3, 1.0, 0.1, 0.1, 1.0, 0.1, 1.0, 1.0, C3(0, 0, 0), C3(12, 12, 12), None, 1)
-    with pytest.raises(BHError):
-        bh.md_step(st, mdp)
-    assert torch.equal(st["pos"], p)
+    for _ in range(3):
+        gdr, gdm = bh.field_backward(m, he, gE=torch.ones(1, dtype=torch.float64, device="cuda"))
+        assert bh.check_status() == 0
+        assert rel(gdr.cpu().numpy(), dr) <= TOL[precision]
+        assert rel(gdm.cpu().numpy(), dm) <= TOL[precision]
+
+
+def test_adjoint_general_vjp_batched(oracle_mod):
+    """A general upstream gradient (dL/dH and dL/dE) on a ragged batch of chains, FP64."""
+    B, n = 2, 1500 + 13
+    ws = [workloads.config3(seed=140 + b, n=n) for b in range(B)]
+    pos = np.stack([x.pos for x in ws])
+    mom = np.stack([x.mom for x in ws])
+    rng = np.random.default_rng(5)
+    gH = rng.standard_normal(pos.shape)
+    gE = np.array([0.7, -1.3])
+    bh = BarnesHut(n, B, 16, 0.6, "fp64", expansion=2)
+    bh.build(torch.from_numpy(pos).cuda())
+    gdr, gdm = bh.field_backward(torch.from_numpy(mom).cuda(), None, gH=torch.from_numpy(gH).cuda(),
+                                 gE=torch.from_numpy(gE).cuda())
+    assert bh.check_status() == 0
+    gdr, gdm = gdr.cpu().numpy(), gdm.cpu().numpy()
+    for b, x in enumerate(ws):
+        t = oracle_mod.Tree(x.pos, x.mom, 16)
+        H, _, _ = t.field(0.6, order=2)
+        # L = gH . H + gE E, E = -1/2 m.H: hbar = gH - gE/2 m; dL/dm adds gE (-1/2 H)
+        dr, dm = t.vjp(0.6, gH[b] - 0.5 * gE[b] * x.mom, order=2)
+        dm = dm - 0.5 * gE[b] * H
+        assert rel(gdr[b], dr) <= 1e-12 and rel(gdm[b], dm) <= 1e-12
+
+
+@pytest.mark.parametrize("n", [1, 2, 17, 300])
+def test_adjoint_small_systems(oracle_mod, n):
+    w = workloads.uniform_cube(n, 4.0 + 2.0 * n ** (1.0 / 3.0), seed=150 + n, hext=(0.2, 0.1, -0.3))
+    _, _, dr, dm = oracle_mod.Tree(w.pos, w.mom, 16).energy_grad(0.7, w.hext, order=2)
+    bh = BarnesHut(w.n, 1, 16, 0.7, "fp64", expansion=2)
+    bh.build(torch.from_numpy(w.pos).cuda())
+    gdr, gdm = bh.field_backward(torch.from_numpy(w.mom).cuda(), torch.from_numpy(w.hext).cuda(),
+                                 gE=torch.ones(1, dtype=torch.float64, device="cuda"))
+    assert bh.check_status() == 0
+    gdr, gdm = gdr.cpu().numpy(), gdm.cpu().numpy()
+    if n == 1:
+        assert np.abs(gdr).max() == 0.0
+        np.testing.assert_allclose(gdm, dm, rtol=1e-14)
+    else:
+        assert rel(gdr, dr) <= 1e-12 and rel(gdm, dm) <= 1e-12
+
+
+@pytest.mark.parametrize("precision,tol,tuning_id", [("fp64", 1e-11, -1), ("fp32_mixed", 1e-8, -1),
+                                                     ("fp64", 1e-11, 15)])
+def test_md_trajectory_matches_reference(precision, tol, tuning_id):
+    """MD steps with order-2 cells against the reference integrator with order-2 forces and torques."""
+    from oracle import md as omd
+    import ctypes
+    w = workloads.uniform_cube(1200, 18.0, seed=8)
+    rng = np.random.default_rng(9)
+    st = dict(pos=w.pos[None].copy(), vel=rng.standard_normal((1, 3, w.n)), mom=w.mom[None].copy(),
+              omega=rng.standard_normal((1, 3, w.n)) * np.sqrt(10.0))
+    p = dict(dt=1e-3, kT=1.0, gamma_t=0.1, gamma_r=0.1, mass=1.0, inertia=0.1, wca_eps=1.0, wca_sigma=1.0,
+             box_lo=(0.0, 0.0, 0.0), box_hi=(18.0, 18.0, 18.0), hext=np.array([[0.0, 0.0, 0.5]]), seed=77)
+    bh = BarnesHut(w.n, 1, 16, 0.6, precision, tuning_id=tuning_id, expansion=2)
+    d = {k: torch.from_numpy(np.ascontiguousarray(v)).cuda() for k, v in st.items()}
+    d["step"] = torch.zeros(1, dtype=torch.int64, device="cuda")
+    he = torch.from_numpy(p["hext"]).cuda()
+    C3 = ctypes.c_double * 3
+    mdp = md_params(p["dt"], p["kT"], p["gamma_t"], p["gamma_r"], p["mass"], p["inertia"], p["wca_eps"],
+                    p["wca_sigma"], C3(*p["box_lo"]), C3(*p["box_hi"]), he.data_ptr(), p["seed"])
+    ref = st
+    for k in range(3):
+        bh.md_step(d, mdp)
+        ref = omd.md_step(ref, p, k, theta=0.6, leaf=16, order=2)
+    assert bh.check_status() == 0
+    for key in ("pos", "vel", "mom", "omega"):
+        g = d[key].cpu().numpy()
+        err = np.abs(g - ref[key]).max() / np.abs(ref[key]).max()
+        assert err <= tol, (key, err)
