@@ -146,18 +146,23 @@ def table1(args, workloads, BarnesHut, allpairs, md_params):
               f"{tun['fp32_mixed']}, {tun['fp64']} |", flush=True)
 
 
-def accuracy(args, workloads, BarnesHut, allpairs):
+def accuracy(args, workloads, BarnesHut, allpairs, md_params):
     """Field accuracy against cost at N = 2^20 (the benchmark's chain workload): for each theta, the
     paper's pseudo-particles (order 1) and cells with their first moment (order 2).  Error = relative L2
     and 99.9th percentile per particle against the FP64 all-pairs sum; time = build + field (eager calls,
-    synchronised, best of 5) and the forward traversal kernel alone (HIP events around it)."""
+    synchronised, best of 5) and the forward traversal kernel alone (HIP events around it).  Then the
+    forces (dE/dr) against the all-pairs energy gradient and the eager MD step time, FP32-mixed."""
     import torch
     dev = torch.device("cuda", 0)
     w = workloads.cached("chains_n1048576_seed1003", lambda: workloads.config3())
     n = w.n
     pos = torch.from_numpy(w.pos).to(dev)
     mom = torch.from_numpy(w.mom).to(dev)
-    ref = allpairs(pos, mom, precision="fp64")[0]
+    ref, ref_f, _ = allpairs(pos, mom, precision="fp64", want_dEdr=True)
+    import ctypes
+    side = float(w.box_hi[0])
+    C3 = ctypes.c_double * 3
+    mdp = md_params(1e-3, 1.0, 0.1, 0.1, 1.0, 0.1, 1.0, 1.0, C3(0.0, 0.0, 0.0), C3(side, side, side), None, 11)
 
     def err(H):
         d = torch.linalg.vector_norm(H - ref, dim=0)
@@ -168,6 +173,7 @@ def accuracy(args, workloads, BarnesHut, allpairs):
 
     print("| theta | cells | precision | rel. L2 error | 99.9th pct error | build + field ms | traversal ms |")
     print("|---|---|---|---|---|---|---|")
+    rows_md = []
     for theta in (0.3, 0.4, 0.5, 0.6, 0.7, 0.8):
         for order in (1, 2):
             for precision in ("fp32_mixed", "fp64"):
@@ -190,7 +196,26 @@ def accuracy(args, workloads, BarnesHut, allpairs):
                 e2, e999 = err(H)
                 print(f"| {theta} | {'order ' + str(order)} | {precision} | {e2:.3e} | {e999:.3e} | {best:.3f} | "
                       f"{kern:.3f} |", flush=True)
+                if precision == "fp32_mixed":
+                    # forces: dE/dr of the MD step against the all-pairs gradient, and the MD step time
+                    dr, _ = bh.field_backward(mom, None, gE=torch.ones(1, dtype=torch.float64, device=dev))
+                    fe = (torch.linalg.vector_norm(dr - ref_f) / torch.linalg.vector_norm(ref_f)).item()
+                    st = {"pos": pos.clone(), "vel": torch.zeros_like(pos), "mom": mom.clone(),
+                          "omega": torch.zeros_like(pos), "step": torch.zeros(1, dtype=torch.int64, device=dev)}
+                    bh.md_step(st, mdp)
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    for _ in range(5):
+                        bh.md_step(st, mdp)
+                    torch.cuda.synchronize()
+                    rows_md.append((theta, order, fe, (time.perf_counter() - t0) / 5 * 1e3))
+                    assert bh.check_status() == 0
                 del bh, H
+    print()
+    print("| theta | cells | force rel. L2 error (FP32-mixed) | MD step ms (FP32-mixed, eager) |")
+    print("|---|---|---|---|")
+    for theta, order, fe, ms in rows_md:
+        print(f"| {theta} | order {order} | {fe:.3e} | {ms:.3f} |", flush=True)
 
 
 def main():
@@ -227,7 +252,7 @@ def main():
         table1(args, workloads, BarnesHut, allpairs, md_params)
         return
     if args.accuracy:
-        accuracy(args, workloads, BarnesHut, allpairs)
+        accuracy(args, workloads, BarnesHut, allpairs, md_params)
         return
 
     log("generating workload (2^20 chains, phi 0.1)")
