@@ -434,7 +434,7 @@ def main():
     # the fused kernel that the chosen launch shape runs (waves walking together, or two targets per lane)
     tid = tuning["fp32_mixed"]
     adj_key = {4: "k_adjoint_wg<true, 2>", 5: "k_adjoint_wg<true, 4>", 6: "k_adjoint2<true>",
-               7: "k_adjoint2<true>"}.get(tid, "k_adjoint<true>")
+               7: "k_adjoint2<true>"}.get(tid, "k_adjoint<true, false>")
     if r32["t_adj_kernel"] >= r32["t_fwd_kernel"]:
         kname, kt, flops = f"{adj_key} (fused forward + adjoint, tuning {tid})", r32["t_adj_kernel"], FLOPS_ADJ * inter
     else:
