@@ -94,7 +94,9 @@ bh_status bh_workspace_bytes(const bh_params *p, size_t *out_bytes);
 int32_t bh_num_tunings(void);
 
 /* Create a handle (host memory, owned by the caller until bh_destroy) bound to the current HIP device
- * and to d_workspace (>= bh_workspace_bytes, 256-byte aligned, owned by the caller). */
+ * and to d_workspace (>= bh_workspace_bytes, 256-byte aligned, owned by the caller).  The handle also
+ * owns one non-blocking HIP stream of default priority and three events, which md_step uses internally;
+ * bh_destroy waits for that stream and releases them. */
 bh_status bh_create(const bh_params *p, void *d_workspace, size_t workspace_bytes, bh_handle **out);
 bh_status bh_destroy(bh_handle *h);
 
@@ -146,10 +148,14 @@ typedef struct md_params {
 } md_params;
 
 /* One MD step: bh_build on the current positions, field + adjoint of the energy, WCA forces, and the
- * integrator update.  Enqueued on the stream with no host synchronisation (capturable in a graph). */
+ * integrator update.  Enqueued on the stream with no host synchronisation (capturable in a graph).  The
+ * short-range forces and the ordering of the traversal's work run on the handle's own stream, forked from
+ * `stream` (event record + wait) and joined back to it before the traversal: the step starts after
+ * everything enqueued on `stream` before it and is complete for everything enqueued after it. */
 bh_status md_step(bh_handle *h, const md_state *s, const md_params *p, void *stream);
 
-/* Capture one md_step (everything it enqueues, all plain kernel launches) into a HIP graph on `stream`
+/* Capture one md_step (everything it enqueues: kernel launches, and the fork to and join from the
+ * handle's stream, which become graph edges) into a HIP graph on `stream`
  * and instantiate it into *graph_exec.  The stream must not be the null stream.  Replaying the graph
  * with bh_graph_launch performs one MD step on the same state buffers with the same parameters; the
  * noise advances with the device step counter, so replays continue the trajectory.  The handle,

@@ -943,9 +943,30 @@ __global__ __launch_bounds__(1024) void k_dhext(const double *__restrict__ mom, 
     if (threadIdx.x < 3) dhext[3 * b + threadIdx.x] = gE ? -gE[b] * red[threadIdx.x][0] : 0.0;
 }
 
+// Items of the independent-wave fused traversal: (system, target wave, part).
+static int adjoint_items(const Handle &h)
+{
+    const int wps = (int)((h.L.n + h.adj_tpw - 1) / h.adj_tpw);
+    return (int)(h.L.B * wps * h.adj_parts);
+}
+
+bool uses_wave_order(const Handle &h)
+{
+    // order-2 cells take the independent-wave walk whatever the cooperative or two-target setting
+    const bool quad = h.L.expansion == 2;
+    const bool independent = quad || (h.adj_coop == 1 && !h.adj_two);
+    return independent && h.adj_sched && h.adj_parts == 1;
+}
+
+void launch_order_waves(Handle &h, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_order_waves, dim3(1), dim3(kOrderThreads), 0, s, h.w.wave_cost, adjoint_items(h),
+                       h.w.wave_order, h.w.sched_ctr);
+}
+
 hipError_t launch_backward(Handle &h, const double *d_mom, const double *d_hext, const double *d_gH,
                            const double *d_gE, double *d_dpos, double *d_dmom, double *d_dhext, hipStream_t s,
-                           double *d_H, double *d_E, bool moments_done)
+                           double *d_H, double *d_E, bool moments_done, bool order_done)
 {
     const Layout &L = h.L;
     Workspace &w = h.w;
@@ -998,13 +1019,11 @@ hipError_t launch_backward(Handle &h, const double *d_mom, const double *d_hext,
     } else {
         const int tpw = h.adj_tpw, parts = h.adj_parts;
         const int wps = (int)((L.n + tpw - 1) / tpw);
-        const int nwv = (int)(L.B * wps * parts);
+        const int nwv = adjoint_items(h);
         const unsigned blk = (unsigned)((nwv + wpb - 1) / wpb);
         // persistent, cost-ordered launch: as many workgroups as can be resident at once
-        const bool sched = h.adj_sched && parts == 1;
-        if (sched)
-            hipLaunchKernelGGL(k_order_waves, dim3(1), dim3(kOrderThreads), 0, s, w.wave_cost, nwv, w.wave_order,
-                               w.sched_ctr);
+        const bool sched = uses_wave_order(h);
+        if (sched && !order_done) launch_order_waves(h, s);
         const unsigned grid = sched && (unsigned)h.adj_resident < blk ? (unsigned)h.adj_resident : blk;
         const uint32_t *ord = sched ? w.wave_order : nullptr;
         uint32_t *cost = parts == 1 ? w.wave_cost : nullptr;

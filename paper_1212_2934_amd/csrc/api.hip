@@ -193,6 +193,27 @@ struct bh_handle {
     Handle h;
 };
 
+// The MD step's side stream and events (none of them carries timing).
+static hipError_t create_side(Handle &h)
+{
+    h.side = nullptr;
+    h.fork_ev = h.sorted_ev = h.join_ev = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&h.side, hipStreamNonBlocking);
+    hipEvent_t *evs[3] = {&h.fork_ev, &h.sorted_ev, &h.join_ev};
+    for (int k = 0; k < 3 && e == hipSuccess; ++k) e = hipEventCreateWithFlags(evs[k], hipEventDisableTiming);
+    return e;
+}
+
+static void destroy_side(Handle &h)
+{
+    hipEvent_t evs[3] = {h.fork_ev, h.sorted_ev, h.join_ev};
+    for (hipEvent_t ev : evs)
+        if (ev) (void)hipEventDestroy(ev);
+    if (h.side) (void)hipStreamDestroy(h.side);
+    h.side = nullptr;
+    h.fork_ev = h.sorted_ev = h.join_ev = nullptr;
+}
+
 extern "C" {
 
 bh_status bh_workspace_bytes(const bh_params *p, size_t *out_bytes)
@@ -238,10 +259,16 @@ bh_status bh_create(const bh_params *p, void *d_workspace, size_t workspace_byte
     }
     h.cnt_far = h.cnt_near = nullptr;
     for (int k = 0; k < 4; ++k) h.ev[k] = nullptr;
+    if (create_side(h) != hipSuccess) {
+        destroy_side(h);
+        delete hh;
+        return BH_EDEVICE;
+    }
     hipLaunchKernelGGL(k_init, dim3(1), dim3(256), 0, 0, h.w.status, h.w.ones, (int64_t)L.B);
     hipLaunchKernelGGL(k_fill_u32, dim3(64), dim3(256), 0, 0, h.w.wave_cost,
                        (int64_t)(L.B * ((L.n + kMinTpw - 1) / kMinTpw)), 0u);
     if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+        destroy_side(h);
         delete hh;
         return BH_EDEVICE;
     }
@@ -252,6 +279,9 @@ bh_status bh_create(const bh_params *p, void *d_workspace, size_t workspace_byte
 bh_status bh_destroy(bh_handle *h)
 {
     if (!h) return BH_EINVAL;
+    // a step still running on the side stream must not lose its stream
+    if (h->h.side) (void)hipStreamSynchronize(h->h.side);
+    destroy_side(h->h);
     delete h;
     return BH_OK;
 }

@@ -310,21 +310,82 @@ static void scan_excl(uint32_t *a, int64_t len, uint32_t *scratch, uint32_t *tot
 
 constexpr int kFusedTiles = 256;
 
+// One pass of the stable LSD sort over one tile of up to kSortThreads * items keys.  Each wave ranks a
+// contiguous chunk of 64 * items keys (the keys of equal digit before it in the chunk: match masks from
+// ballots plus running per-wave digit counts in LDS); the chunks' counts give every key its position in
+// the tile sorted by digit, where the keys are staged in LDS; then each digit's run of the tile is
+// written out to consecutive addresses.
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint64_t *__restrict__ kout,
     uint32_t *__restrict__ vout, const uint32_t *__restrict__ hist, int64_t n, int tiles, int items, int shift,
     int64_t ntot, int fused)
 {
     constexpr int kWaves = kSortThreads / kWave;
-    __shared__ uint32_t base[kRadixBins];
-    __shared__ uint32_t wcnt[kWaves][kRadixBins];
+    constexpr int kTileMax = kSortThreads * kSortItems;
+    __shared__ uint32_t gbase[kRadixBins];        // output offset of the tile's first key of digit d
+    __shared__ uint32_t lstart[kRadixBins];       // position of that key in the digit-sorted tile
+    __shared__ uint32_t wcnt[kWaves][kRadixBins]; // per-wave digit counts, then per-wave digit offsets
     __shared__ uint32_t dsum[kWaves];
+    __shared__ uint64_t skey[kTileMax];
+    __shared__ uint32_t sval[kTileMax];
     const int b = blockIdx.x / tiles, t = blockIdx.x - b * tiles;
     const int64_t tile = (int64_t)kSortThreads * items;
     const int64_t lo = (int64_t)b * n + (int64_t)t * tile;
     const int64_t hi = min(lo + tile, (int64_t)(b + 1) * n);
+    const int count = (int)(hi - lo);
     const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
+    const uint32_t dmask = kRadixBins - 1;
+    for (int w = 0; w < kWaves; ++w) wcnt[w][tid] = 0u;
+
+    // this wave's chunk, loaded up front (coalesced, all loads in flight together)
+    const int c0 = wave * kWave * items;
+    uint64_t key[kSortItems];
+    uint32_t val[kSortItems], rank[kSortItems];
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r) {
+        const int p = c0 + r * kWave + lane;
+        const bool valid = r < items && p < count;
+        key[r] = valid ? kin[lo + p] : 0ull;
+        val[r] = valid ? vin[lo + p] : 0u;
+    }
+    __syncthreads();  // wcnt cleared
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r) {
+        if (r < items) {
+            const bool valid = c0 + r * kWave + lane < count;
+            const uint32_t d = (uint32_t)(key[r] >> shift) & dmask;
+            uint64_t m = __ballot(valid);
+#pragma unroll
+            for (int bit = 0; bit < kRadixBits; ++bit) {
+                const bool set = (d >> bit) & 1u;
+                const uint64_t v = __ballot(set);
+                m &= set ? v : ~v;
+            }
+            const uint32_t before = (uint32_t)__popcll(m & lt);
+            // one wave's LDS accesses complete in order: this read sees the previous round's update
+            const uint32_t cur = valid ? wcnt[wave][d] : 0u;
+            rank[r] = cur + before;
+            if (valid && before == 0) wcnt[wave][d] = cur + (uint32_t)__popcll(m);
+        }
+    }
+    __syncthreads();
+
+    // thread tid owns digit tid: per-wave offsets, the tile's digit starts, and the output offset
+    uint32_t tot_tile = 0;
+    for (int w = 0; w < kWaves; ++w) {
+        const uint32_t c = wcnt[w][tid];
+        wcnt[w][tid] = tot_tile;
+        tot_tile += c;
+    }
+    {
+        const uint32_t incl = wave_incl_scan_u32(tot_tile, lane);
+        if (lane == kWave - 1) dsum[wave] = incl;
+        __syncthreads();
+        uint32_t woff = 0;
+        for (int w = 0; w < wave; ++w) woff += dsum[w];
+        lstart[tid] = woff + incl - tot_tile;
+    }
     if (fused) {
         // hist holds raw counts: the offset of (digit, tile t) is the system's start, plus the keys of
         // smaller digits, plus this digit's keys in earlier tiles
@@ -346,51 +407,40 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
                 pre += u < t ? c : 0u;
             }
         }
+        __syncthreads();  // dsum is reused
         const uint32_t incl = wave_incl_scan_u32(tot, lane);
         if (lane == kWave - 1) dsum[wave] = incl;
         __syncthreads();
         uint32_t woff = 0;
         for (int w = 0; w < wave; ++w) woff += dsum[w];
-        base[tid] = (uint32_t)((int64_t)b * n) + woff + incl - tot + pre;
+        gbase[tid] = (uint32_t)((int64_t)b * n) + woff + incl - tot + pre;
     } else {
-        base[tid] = hist[((int64_t)b * kRadixBins + tid) * tiles + t];
+        gbase[tid] = hist[((int64_t)b * kRadixBins + tid) * tiles + t];
     }
-    for (int r = 0; r < items; ++r) {
-        for (int w = 0; w < kWaves; ++w) wcnt[w][tid] = 0u;
-        __syncthreads();
-        const int64_t idx = lo + (int64_t)r * kSortThreads + tid;
-        const bool valid = idx < hi;
-        uint64_t key = valid ? kin[idx] : 0ull;
-        uint32_t val = valid ? vin[idx] : 0u;
-        uint32_t d = (uint32_t)(key >> shift) & (kRadixBins - 1);
-        uint64_t m = __ballot(valid);
+    __syncthreads();
+
+    // stage the tile in digit order
 #pragma unroll
-        for (int bit = 0; bit < kRadixBits; ++bit) {
-            const bool set = (d >> bit) & 1u;
-            uint64_t v = __ballot(set);
-            m &= set ? v : ~v;
-        }
-        const uint32_t before = (uint32_t)__popcll(m & lt);
-        if (valid && before == 0) wcnt[wave][d] = (uint32_t)__popcll(m);
-        __syncthreads();
-        {
-            uint32_t acc = base[tid];
-            for (int w = 0; w < kWaves; ++w) {
-                uint32_t c = wcnt[w][tid];
-                wcnt[w][tid] = acc;
-                acc += c;
-            }
-            base[tid] = acc;
-        }
-        __syncthreads();
-        if (valid) {
-            const uint32_t at = wcnt[wave][d] + before;
-            if ((int64_t)at < ntot) {  // always true for a consistent histogram
-                kout[at] = key;
-                vout[at] = val;
+    for (int r = 0; r < kSortItems; ++r) {
+        if (r < items && c0 + r * kWave + lane < count) {
+            const uint32_t d = (uint32_t)(key[r] >> shift) & dmask;
+            const uint32_t at = lstart[d] + wcnt[wave][d] + rank[r];
+            if (at < (uint32_t)kTileMax) {  // always true for a consistent count
+                skey[at] = key[r];
+                sval[at] = val[r];
             }
         }
-        __syncthreads();
+    }
+    __syncthreads();
+    // each digit's run goes to consecutive output addresses
+    for (int j = tid; j < count; j += kSortThreads) {
+        const uint64_t k = skey[j];
+        const uint32_t d = (uint32_t)(k >> shift) & dmask;
+        const int64_t at = (int64_t)gbase[d] + (j - (int64_t)lstart[d]);
+        if (at >= 0 && at < ntot) {  // always true for a consistent histogram
+            kout[at] = k;
+            vout[at] = sval[j];
+        }
     }
 }
 
@@ -873,20 +923,29 @@ __global__ __launch_bounds__(256) void k_upward_level(const double *__restrict__
                           q64, q32);
 }
 
-// Every level in one workgroup, deepest first, a barrier between levels (the children's sums are written
-// by this workgroup before their parents read them): for small trees, where the per-level launches of
-// k_upward_level would cost more than the work.
+// Levels level_hi down to level_lo in one workgroup, deepest first, a barrier between levels (the
+// children's sums are written by this workgroup before their parents read them): where the per-level
+// launches of k_upward_level would cost more than the work.  Any number of nodes is handled; few are
+// expected.
 constexpr int kUpwardOneThreads = 1024;
 constexpr int64_t kUpwardOneMaxNodes = 1 << 16;
+// Larger trees: the levels at and below kUpwardDeepLevel hold a node only where more than leaf_size
+// particles share a cell 2^-kUpwardDeepLevel of the cube wide (none in the dense liquids and chain
+// systems simulated), so they take one workgroup launch; the top levels 0..kUpwardTopLevel (at most
+// 585 cells per system) take one more when the batch is small.
+constexpr int kUpwardDeepLevel = 10;
+constexpr int kUpwardTopLevel = 3;
+constexpr int64_t kUpwardTopMaxSystems = 7;  // 7 x 585 cells: four passes of 1024 threads
 
 template <int MODE>
 __global__ __launch_bounds__(kUpwardOneThreads) void k_upward_all(
     const double *__restrict__ vals, const double *__restrict__ vals2, int64_t ntot, int64_t n,
     NodeRec *__restrict__ nodes, double *__restrict__ sums, double *__restrict__ node_m64,
     const int32_t *__restrict__ node_level, const uint32_t *__restrict__ lvl, const int32_t *__restrict__ lvl_nodes,
-    const double *__restrict__ bbox, int64_t max_nodes, double *__restrict__ q64, float *__restrict__ q32)
+    const double *__restrict__ bbox, int64_t max_nodes, double *__restrict__ q64, float *__restrict__ q32,
+    int level_hi, int level_lo)
 {
-    for (int level = kMaxLevel; level >= 0; --level) {
+    for (int level = level_hi; level >= level_lo; --level) {
         uint32_t b0, b1;
         level_range(lvl, level, max_nodes, b0, b1);
         for (uint32_t q = b0 + threadIdx.x; q < b1; q += kUpwardOneThreads)
@@ -901,17 +960,23 @@ static void upward(Handle &h, const double *vals, const double *vals2, hipStream
 {
     const Layout &L = h.L;
     Workspace &w = h.w;
-    if (L.max_nodes <= kUpwardOneMaxNodes) {
+    auto one = [&](int level_hi, int level_lo) {
         hipLaunchKernelGGL(k_upward_all<MODE>, dim3(1), dim3(kUpwardOneThreads), 0, s, vals, vals2, L.ntot, L.n,
                            w.nodes, w.node_adj, w.node_m64, w.node_level, w.lvl, w.lvl_nodes, w.bbox, L.max_nodes,
-                           w.node_q64, w.node_q32);
+                           w.node_q64, w.node_q32, level_hi, level_lo);
+    };
+    if (L.max_nodes <= kUpwardOneMaxNodes) {
+        one(kMaxLevel, 0);
         return;
     }
+    one(kMaxLevel, kUpwardDeepLevel);
+    const int top = L.B <= kUpwardTopMaxSystems ? kUpwardTopLevel + 1 : 0;
     const unsigned g = grid_for(L.max_nodes, 256, 512);
-    for (int level = kMaxLevel; level >= 0; --level)
+    for (int level = kUpwardDeepLevel - 1; level >= top; --level)
         hipLaunchKernelGGL(k_upward_level<MODE>, dim3(g), dim3(256), 0, s, vals, vals2, L.ntot, L.n, w.nodes,
                            w.node_adj, w.node_m64, w.node_level, w.lvl, w.lvl_nodes, w.bbox, level, L.max_nodes,
                            w.node_q64, w.node_q32);
+    if (top > 0) one(kUpwardTopLevel, 0);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -926,7 +991,7 @@ static void upward(Handle &h, const double *vals, const double *vals2, hipStream
 
 static void gather_moments(Handle &h, const double *d_mom, hipStream_t s);
 
-hipError_t launch_build(Handle &h, const double *d_pos, hipStream_t s, const double *d_mom)
+hipError_t launch_build(Handle &h, const double *d_pos, hipStream_t s, const double *d_mom, hipEvent_t sorted_ev)
 {
     const Layout &L = h.L;
     Workspace &w = h.w;
@@ -955,6 +1020,11 @@ hipError_t launch_build(Handle &h, const double *d_pos, hipStream_t s, const dou
     // kRadixPasses is even: the sorted data is back in buffer 0
     hipLaunchKernelGGL(k_gather3, dim3(grid_for(ntot, 256)), dim3(256), 0, s, d_pos, w.perm, n, ntot,
                        w.spos, (float *)nullptr, w.status);
+    // the sorted codes, permutation and positions and the bounding cube are final from here on
+    if (sorted_ev) {
+        const hipError_t e = hipEventRecord(sorted_ev, s);
+        if (e != hipSuccess) return e;
+    }
     const int64_t nint = L.bin_int;  // B * (n - 1)
     if (nint > 0) {
         hipLaunchKernelGGL(k_karras, dim3(grid_for(nint, 256)), dim3(256), 0, s, w.codes, n, nint,

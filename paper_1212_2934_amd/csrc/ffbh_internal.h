@@ -122,6 +122,10 @@ struct Handle {
     int adj_resident;    // workgroups of that launch resident at once (grid of the persistent launch)
     int32_t *cnt_far, *cnt_near;  // optional per-target counters (device)
     hipEvent_t ev[4];             // optional timing events around the traversal kernels
+    // The MD step's side stream (default priority, non-blocking) and its fork/join events: the wave
+    // ordering and the short-range forces run there, beside the tree build.
+    hipStream_t side;
+    hipEvent_t fork_ev, sorted_ev, join_ev;
 };
 
 // ---- shared device helpers -----------------------------------------------------------------------
@@ -170,15 +174,23 @@ inline unsigned grid_for(int64_t work, int threads, int64_t cap = (int64_t)1 << 
 
 // Launch helpers implemented per source file.
 // Tree build; with d_mom the moments are gathered and summed in the same upward pass (the MD step).
-hipError_t launch_build(Handle &h, const double *d_pos, hipStream_t s, const double *d_mom = nullptr);
+// sorted_ev, if not null, is recorded once the sorted codes, permutation, positions and cube are final.
+hipError_t launch_build(Handle &h, const double *d_pos, hipStream_t s, const double *d_mom = nullptr,
+                        hipEvent_t sorted_ev = nullptr);
 hipError_t launch_upward_moments(Handle &h, const double *d_mom, hipStream_t s);
 hipError_t launch_upward_first_moments(Handle &h, hipStream_t s);
 hipError_t launch_field(Handle &h, const double *d_mom, const double *d_hext, double *d_H,
                         double *d_E, hipStream_t s);
 // moments_done: the build already summed the moments (launch_build with d_mom).
+// order_done: the wave order of the persistent launch was already enqueued (launch_order_waves).
 hipError_t launch_backward(Handle &h, const double *d_mom, const double *d_hext, const double *d_gH,
                            const double *d_gE, double *d_dpos, double *d_dmom, double *d_dhext,
-                           hipStream_t s, double *d_H = nullptr, double *d_E = nullptr, bool moments_done = false);
+                           hipStream_t s, double *d_H = nullptr, double *d_E = nullptr, bool moments_done = false,
+                           bool order_done = false);
+// Whether the fused traversal of this handle runs the persistent, cost-ordered launch, and the launch
+// that orders its items from the costs the previous traversal recorded.
+bool uses_wave_order(const Handle &h);
+void launch_order_waves(Handle &h, hipStream_t s);
 void launch_energy_final(Handle &h, double *d_E, hipStream_t s, int targets_per_wave);
 hipError_t adjoint_resident_blocks(Handle &h, int &blocks);
 hipError_t launch_ap(int64_t n, int32_t batch, int32_t precision, const double *pos, const double *mom,

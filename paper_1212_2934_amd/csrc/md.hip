@@ -270,15 +270,23 @@ hipError_t launch_md(Handle &h, const md_state *st, const md_params *mp, hipStre
 {
     const Layout &L = h.L;
     Workspace &w = h.w;
-    hipError_t e = launch_build(h, st->pos, s, st->mom);  // tree, centroids and moment sums
-    if (e != hipSuccess) return e;
-    if (L.expansion == 2) {
-        e = launch_upward_first_moments(h, s);  // order-2 cells
-        if (e != hipSuccess) return e;
+    // Two streams.  The caller's carries build -> fused traversal -> downward pass -> integrator.  The
+    // side stream orders the traversal's items (from the costs of the previous step) and computes the
+    // short-range forces as soon as the build has sorted the particles, both beside the rest of the build
+    // (octree, levels, upward pass: short, latency-bound launches).  The side stream rejoins the caller's
+    // before the traversal, which therefore has the whole device.  The step starts after everything
+    // enqueued on the caller's stream before it and is complete for everything enqueued after it; under
+    // graph capture the fork and the join become edges.
+    hipError_t e;
+    const bool order = uses_wave_order(h);
+    if (order) {
+        if ((e = hipEventRecord(h.fork_ev, s)) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(h.side, h.fork_ev, 0)) != hipSuccess) return e;
+        launch_order_waves(h, h.side);
     }
-    e = launch_backward(h, st->mom, mp->d_hext, nullptr, w.ones, w.md_grad_r, w.md_grad_m, nullptr, s, nullptr,
-                        nullptr, true);
+    e = launch_build(h, st->pos, s, st->mom, h.sorted_ev);  // tree, centroids and moment sums
     if (e != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(h.side, h.sorted_ev, 0)) != hipSuccess) return e;
     // sr_kind 0: WCA, pair and wall cut at the potential minimum; 1: the paper's form, walls at half the pair cut
     const double wca_rc = 1.122462048309373;  // 2^(1/6)
     const bool lj = mp->sr_kind == 1;
@@ -286,13 +294,23 @@ hipError_t launch_md(Handle &h, const md_state *st, const md_params *mp, hipStre
     const double rc = lj ? (mp->sr_cut > 0.0 ? mp->sr_cut : 2.5 * mp->wca_sigma) : wca_rc * mp->wca_sigma;
     const double rcw = lj ? 0.5 * rc : wca_rc * 0.5 * mp->wca_sigma;
     const int64_t ncell = L.B * L.cell_T;
-    hipLaunchKernelGGL(k_clear_cells, dim3(grid_for(ncell, 256, 2048)), dim3(256), 0, s, w.cells, ncell);
-    hipLaunchKernelGGL(k_cell_fill, dim3(grid_for(L.ntot, 256)), dim3(256), 0, s, w.codes, w.bbox, L.n, L.ntot, rc,
-                       L.cell_lcap, L.cell_T, w.cells);
-    hipLaunchKernelGGL(k_wca, dim3(grid_for(L.ntot, 256)), dim3(256), 0, s, w.codes, w.bbox, w.cells, w.spos,
+    hipLaunchKernelGGL(k_clear_cells, dim3(grid_for(ncell, 256, 2048)), dim3(256), 0, h.side, w.cells, ncell);
+    hipLaunchKernelGGL(k_cell_fill, dim3(grid_for(L.ntot, 256)), dim3(256), 0, h.side, w.codes, w.bbox, L.n, L.ntot,
+                       rc, L.cell_lcap, L.cell_T, w.cells);
+    hipLaunchKernelGGL(k_wca, dim3(grid_for(L.ntot, 256)), dim3(256), 0, h.side, w.codes, w.bbox, w.cells, w.spos,
                        w.perm, w.md_force, L.n, L.ntot, L.cell_lcap, L.cell_T, mp->wca_sigma, mp->wca_eps, c12, rc, rcw,
                        make_double3(mp->box_lo[0], mp->box_lo[1], mp->box_lo[2]),
                        make_double3(mp->box_hi[0], mp->box_hi[1], mp->box_hi[2]));
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = hipEventRecord(h.join_ev, h.side)) != hipSuccess) return e;
+    if (L.expansion == 2) {
+        e = launch_upward_first_moments(h, s);  // order-2 cells
+        if (e != hipSuccess) return e;
+    }
+    if ((e = hipStreamWaitEvent(s, h.join_ev, 0)) != hipSuccess) return e;
+    e = launch_backward(h, st->mom, mp->d_hext, nullptr, w.ones, w.md_grad_r, w.md_grad_m, nullptr, s, nullptr,
+                        nullptr, true, order);
+    if (e != hipSuccess) return e;
     MDConst c{mp->dt, mp->kT, mp->gamma_t, mp->gamma_r, mp->mass, mp->inertia, mp->seed};
     hipLaunchKernelGGL(k_integrate, dim3(grid_for(L.ntot, 256)), dim3(256), 0, s, st->pos, st->vel, st->mom,
                        st->omega, w.md_grad_r, w.md_grad_m, w.md_force, st->d_step, L.n, L.ntot, c);
