@@ -134,9 +134,17 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint64_t *__r
     const int64_t lo = (int64_t)b * n + (int64_t)t * tile;
     const int64_t hi = min(lo + tile, (int64_t)(b + 1) * n);
     cnt[threadIdx.x] = 0;
+    // all of this thread's keys are loaded before the first count, so their latencies overlap
+    uint32_t d[kSortItems];
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r) {
+        const int64_t i = lo + (int64_t)r * kSortThreads + threadIdx.x;
+        d[r] = r < items && i < hi ? (uint32_t)(keys[i] >> shift) & (kRadixBins - 1) : kRadixBins;
+    }
     __syncthreads();
-    for (int64_t i = lo + threadIdx.x; i < hi; i += kSortThreads)
-        atomicAdd(&cnt[(keys[i] >> shift) & (kRadixBins - 1)], 1u);
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r)
+        if (d[r] < kRadixBins) atomicAdd(&cnt[d[r]], 1u);
     __syncthreads();
     hist[((int64_t)b * kRadixBins + threadIdx.x) * tiles + t] = cnt[threadIdx.x];
 }
@@ -392,8 +400,10 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
         const uint32_t *hd = hist + ((int64_t)b * kRadixBins + tid) * tiles;
         uint32_t pre = 0, tot = 0;
         if ((tiles & 3) == 0) {
-            // rows of a multiple of four counts start 16-byte aligned: read them four at a time
+            // rows of a multiple of four counts start 16-byte aligned: read them four at a time, sixteen
+            // loads in flight (one at a time, the row's L2 latencies add up to most of the kernel)
             const uint4 *h4 = (const uint4 *)hd;
+#pragma unroll 16
             for (int u4 = 0; u4 < tiles / 4; ++u4) {
                 const uint4 c = h4[u4];
                 const int u = 4 * u4;
@@ -401,6 +411,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
                 pre += (u < t ? c.x : 0u) + (u + 1 < t ? c.y : 0u) + (u + 2 < t ? c.z : 0u) + (u + 3 < t ? c.w : 0u);
             }
         } else {
+#pragma unroll 16
             for (int u = 0; u < tiles; ++u) {
                 const uint32_t c = hd[u];
                 tot += c;
@@ -553,9 +564,14 @@ __global__ __launch_bounds__(256) void k_oct_count(int64_t n, int64_t nint_tot, 
     int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (g >= nint_tot) return;
     const int64_t b = g / (n - 1), ib = b * (n - 1);
-    const int lev = bin_level(delta, g);
     const int cnt = last[g] - first[g] + 1;
     int out = 0;
+    if (cnt <= leaf) {  // no children whether or not the node is in the tree (most nodes)
+        nchild[g] = 0;
+        scan_in[g] = 0u;
+        return;
+    }
+    const int lev = bin_level(delta, g);
     // is this node the deepest cell of an octree run, and is that cell in the tree?
     const int p = bparent[g];
     bool in_tree;
@@ -574,7 +590,7 @@ __global__ __launch_bounds__(256) void k_oct_count(int64_t n, int64_t nint_tot, 
         const int pc = last[ib + x] - first[ib + x] + 1;
         in_tree = pc > leaf && bin_level(delta, ib + x) < kMaxLevel;
     }
-    if (in_tree && cnt > leaf) {
+    if (in_tree) {
         if (lev >= kMaxLevel) {
             set_flag(status, BH_FLAG_DEEP_LEAF);
         } else {
@@ -601,11 +617,8 @@ __global__ __launch_bounds__(256) void k_oct_count(int64_t n, int64_t nint_tot, 
     scan_in[g] = (uint32_t)out;
 }
 
-// Write the records of the children of every in-tree internal node (and of the roots).
-__device__ inline void write_leaf_of(int32_t *leaf_of, int64_t first, int cnt, int id, int64_t ntot)
-{
-    for (int k = 0; k < cnt && first + k < ntot; ++k) leaf_of[first + k] = id;
-}
+// Write the records of the children of every in-tree internal node (and of the roots).  The members'
+// leaf index is written afterwards by k_leaf_of, sixteen lanes per leaf.
 
 __global__ __launch_bounds__(256) void k_oct_emit(int64_t n, int64_t nint_tot, int64_t B, int leaf,
                                                   const int32_t *__restrict__ left,
@@ -616,7 +629,6 @@ __global__ __launch_bounds__(256) void k_oct_emit(int64_t n, int64_t nint_tot, i
                                                   const int32_t *__restrict__ nchild,
                                                   const uint32_t *__restrict__ scan,
                                                   NodeRec *__restrict__ nodes, int32_t *__restrict__ node_level,
-                                                  int32_t *__restrict__ leaf_of,
                                                   int32_t *__restrict__ octid, uint32_t *__restrict__ status,
                                                   int64_t max_nodes)
 {
@@ -641,7 +653,6 @@ __global__ __launch_bounds__(256) void k_oct_emit(int64_t n, int64_t nint_tot, i
             }
             octid[rg] = (int32_t)b;
         }
-        if (r.nchild == 0) write_leaf_of(leaf_of, b * n, (int)n, (int)b, B * n);
         nodes[b] = r;
         node_level[b] = lev;
     }
@@ -698,7 +709,6 @@ __global__ __launch_bounds__(256) void k_oct_emit(int64_t n, int64_t nint_tot, i
             r.parent = -1;  // set by k_oct_link
             nodes[id] = r;
             node_level[id] = clev;
-            if (cn == 0) write_leaf_of(leaf_of, b * n + cf, cc, id, B * n);
             ++id;
         } else if (sp > 5) {
             set_flag(status, BH_FLAG_TREE);
@@ -707,6 +717,24 @@ __global__ __launch_bounds__(256) void k_oct_emit(int64_t n, int64_t nint_tot, i
             stk[sp++] = right[ib + c];
             stk[sp++] = left[ib + c];
         }
+    }
+}
+
+// Leaf of every member: sixteen lanes per node of the tree (the node count is the build's, on the
+// device); lanes of internal nodes do nothing.
+constexpr int kLeafLanes = 16;
+__global__ __launch_bounds__(256) void k_leaf_of(const NodeRec *__restrict__ nodes, const uint32_t *__restrict__ status,
+                                                 int64_t max_nodes, int64_t ntot, int32_t *__restrict__ leaf_of)
+{
+    const int64_t nn = min((int64_t)status[2], max_nodes);
+    for (int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x; x < nn * kLeafLanes; x += (int64_t)gridDim.x * 256) {
+        const int64_t q = x / kLeafLanes;
+        const int k0 = (int)(x - q * kLeafLanes);
+        if (nodes[q].nchild != 0) continue;
+        const int64_t first = nodes[q].first;
+        const int cnt = nodes[q].count;
+        for (int k = k0; k < cnt; k += kLeafLanes)
+            if (first + k >= 0 && first + k < ntot) leaf_of[first + k] = (int32_t)q;
     }
 }
 
@@ -931,11 +959,9 @@ constexpr int kUpwardOneThreads = 1024;
 constexpr int64_t kUpwardOneMaxNodes = 1 << 16;
 // Larger trees: the levels at and below kUpwardDeepLevel hold a node only where more than leaf_size
 // particles share a cell 2^-kUpwardDeepLevel of the cube wide (none in the dense liquids and chain
-// systems simulated), so they take one workgroup launch; the top levels 0..kUpwardTopLevel (at most
-// 585 cells per system) take one more when the batch is small.
+// systems simulated), so they take one workgroup launch.  (The top levels are not merged: one
+// workgroup walks their few hundred cells more slowly than four grid launches.)
 constexpr int kUpwardDeepLevel = 10;
-constexpr int kUpwardTopLevel = 3;
-constexpr int64_t kUpwardTopMaxSystems = 7;  // 7 x 585 cells: four passes of 1024 threads
 
 template <int MODE>
 __global__ __launch_bounds__(kUpwardOneThreads) void k_upward_all(
@@ -970,13 +996,11 @@ static void upward(Handle &h, const double *vals, const double *vals2, hipStream
         return;
     }
     one(kMaxLevel, kUpwardDeepLevel);
-    const int top = L.B <= kUpwardTopMaxSystems ? kUpwardTopLevel + 1 : 0;
     const unsigned g = grid_for(L.max_nodes, 256, 512);
-    for (int level = kUpwardDeepLevel - 1; level >= top; --level)
+    for (int level = kUpwardDeepLevel - 1; level >= 0; --level)
         hipLaunchKernelGGL(k_upward_level<MODE>, dim3(g), dim3(256), 0, s, vals, vals2, L.ntot, L.n, w.nodes,
                            w.node_adj, w.node_m64, w.node_level, w.lvl, w.lvl_nodes, w.bbox, level, L.max_nodes,
                            w.node_q64, w.node_q32);
-    if (top > 0) one(kUpwardTopLevel, 0);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -1037,8 +1061,9 @@ hipError_t launch_build(Handle &h, const double *d_pos, hipStream_t s, const dou
     }
     hipLaunchKernelGGL(k_oct_emit, dim3(grid_for(nint > B ? nint : B, 256)), dim3(256), 0, s, n, nint, B,
                        (int)h.p.leaf_size, w.bin_left, w.bin_right, w.bin_first, w.bin_last, w.bin_delta,
-                       w.bin_nchild, w.bin_scan, w.nodes, w.node_level, w.leaf_of, w.bin_octid,
-                       w.status, L.max_nodes);
+                       w.bin_nchild, w.bin_scan, w.nodes, w.node_level, w.bin_octid, w.status, L.max_nodes);
+    hipLaunchKernelGGL(k_leaf_of, dim3(grid_for(L.max_nodes * kLeafLanes, 256, 8192)), dim3(256), 0, s, w.nodes,
+                       w.status, L.max_nodes, ntot, w.leaf_of);
     if (nint > 0)
         hipLaunchKernelGGL(k_oct_link, dim3(grid_for(nint, 256)), dim3(256), 0, s, nint, B,
                            w.bin_nchild, w.bin_scan, w.bin_octid, w.nodes, L.max_nodes);
