@@ -866,7 +866,10 @@ __device__ inline void upward_node(uint32_t q, const double *__restrict__ vals, 
             }
         }
     }
+    // sums in member (child) order, as the definition's; unrolled so that several members' loads are in
+    // flight at once (the additions stay in order: no reassociation without fast-math)
     if (nd.nchild == 0) {
+#pragma unroll 4
         for (int k = nd.first; k < nd.first + nd.count; ++k) {
             sx = sx + vals[k];
             sy = sy + vals[ntot + k];
@@ -878,6 +881,7 @@ __device__ inline void upward_node(uint32_t q, const double *__restrict__ vals, 
             }
         }
     } else {
+#pragma unroll 4
         for (int c = nd.child; c < nd.child + nd.nchild; ++c) {
             sx = sx + sums[8 * c + o];
             sy = sy + sums[8 * c + o + 1];
