@@ -157,6 +157,44 @@ def test_short_range_law_argument_checks():
         assert torch.equal(before[k], st[k]), k
 
 
+@pytest.mark.parametrize("tuning_id", [-1, 13])
+def test_steps_on_a_user_stream_are_ordered_with_it(tuning_id):
+    """md_step forks part of its work onto the handle's own stream.  On a user stream that is still busy
+    (a chain of products) when the state is written and the steps are enqueued, with no host
+    synchronisation anywhere, every step must see the state written before it and the copies enqueued
+    after it must see the step complete: the result equals the reference trajectory."""
+    w = workloads.uniform_cube(1500, 20.0, seed=8)
+    rng = np.random.default_rng(9)
+    st = _state(w, rng)
+    p = _params(20.0)
+    bh = BarnesHut(w.n, 1, 16, 0.5, "fp64", tuning_id=tuning_id)
+    src = _to_dev(st)
+    d = {k: torch.zeros_like(v) for k, v in src.items()}
+    he = torch.from_numpy(p["hext"]).cuda()
+    mp = _mdp(p, he)
+    a = torch.randn(2048, 2048, device="cuda")
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        for _ in range(8):  # keeps the stream busy while the host enqueues the rest
+            a = torch.tanh(a @ a)
+        for k in d:
+            d[k].copy_(src[k])
+        for _ in range(3):
+            bh.md_step(d, mp)
+        out = {k: v.clone() for k, v in d.items()}
+    s.synchronize()
+    ref = st
+    for k in range(3):
+        ref = omd.md_step(ref, p, k, theta=0.5, leaf=16)
+    assert int(out["step"].item()) == 3
+    for key in ("pos", "vel", "mom", "omega"):
+        g = out[key].cpu().numpy()
+        err = np.abs(g - ref[key]).max() / np.abs(ref[key]).max()
+        assert err <= 1e-11, (key, err)
+    assert bh.check_status() == 0
+
+
 def test_resume_continues_the_same_trajectory():
     w = workloads.uniform_cube(2000, 24.0, seed=6)
     rng = np.random.default_rng(7)
