@@ -79,9 +79,9 @@ void carve(const Layout &Lc, void *base, Workspace &w)
     w.codes = w.keys[0];
     w.spos = (double *)take(3 * 8 * nt);
     w.smom = (double *)take(3 * 8 * nt);
-    w.smom32 = (float *)take(3 * 4 * nt);
+    // one 48-byte source record per particle, in the handle's precision (src64 or src32, never both)
     w.src64 = take(48 * nt);
-    w.src32 = take(48 * nt);
+    w.src32 = w.src64;
     w.bin_left = (int32_t *)take(4 * bi);
     w.bin_right = (int32_t *)take(4 * bi);
     w.bin_first = (int32_t *)take(4 * bi);

@@ -1100,23 +1100,28 @@ __global__ __launch_bounds__(256) void k_pack_sources(const double *__restrict__
     if (k >= ntot) return;
     const double x = spos[k], y = spos[ntot + k], z = spos[2 * ntot + k];
     const double mx = smom[k], my = smom[ntot + k], mz = smom[2 * ntot + k];
-    double *a = src64 + 6 * k;
-    a[0] = x; a[1] = y; a[2] = z; a[3] = mx; a[4] = my; a[5] = mz;
-    double *b = src32 + 6 * k;
-    b[0] = x; b[1] = y; b[2] = z;
-    float *f = (float *)(b + 3);
-    f[0] = (float)mx; f[1] = (float)my; f[2] = (float)mz; f[3] = 0.0f;
+    if (src64) {
+        double *a = src64 + 6 * k;
+        a[0] = x; a[1] = y; a[2] = z; a[3] = mx; a[4] = my; a[5] = mz;
+    }
+    if (src32) {
+        double *b = src32 + 6 * k;
+        b[0] = x; b[1] = y; b[2] = z;
+        float *f = (float *)(b + 3);
+        f[0] = (float)mx; f[1] = (float)my; f[2] = (float)mz; f[3] = 0.0f;
+    }
 }
 
-// Moments in sorted order (FP64 and FP32) and the packed source records.
+// Moments in sorted order and the packed source records of the handle's precision.
 static void gather_moments(Handle &h, const double *d_mom, hipStream_t s)
 {
     const Layout &L = h.L;
     Workspace &w = h.w;
+    const bool mixed = h.p.precision == BH_FP32_MIXED;
     hipLaunchKernelGGL(k_gather3, dim3(grid_for(L.ntot, 256)), dim3(256), 0, s, d_mom, w.perm, L.n,
-                       L.ntot, w.smom, w.smom32, w.status);
+                       L.ntot, w.smom, (float *)nullptr, w.status);
     hipLaunchKernelGGL(k_pack_sources, dim3(grid_for(L.ntot, 256)), dim3(256), 0, s, w.spos, w.smom, L.ntot,
-                       (double *)w.src64, (double *)w.src32);
+                       mixed ? (double *)nullptr : (double *)w.src64, mixed ? (double *)w.src32 : (double *)nullptr);
 }
 
 // First moments of every node from the sorted moments and positions already in the workspace (after a

@@ -48,9 +48,8 @@ struct Workspace {
     uint64_t *codes;         // sorted codes (alias of the final keys)
     double *spos;            // 3 x N_tot sorted positions (SoA: x block, y block, z block)
     double *smom;            // 3 x N_tot sorted moments FP64
-    float *smom32;           // 3 x N_tot sorted moments FP32
-    void *src64;             // N_tot sorted source records (position, moment FP64), 48 bytes each
-    void *src32;             // N_tot sorted source records (position FP64, moment FP32), 48 bytes each
+    void *src64;             // N_tot sorted source records (position, moment FP64), 48 bytes each (FP64)
+    void *src32;             // the same buffer as records of position FP64, moment FP32 (FP32-mixed)
     // binary radix tree (per system: n-1 internal nodes, n leaves)
     int32_t *bin_left;       // internal node -> left child (>= 0 internal, < 0: leaf ~idx)
     int32_t *bin_right;
