@@ -150,7 +150,8 @@ typedef struct md_params {
 /* One MD step: bh_build on the current positions, field + adjoint of the energy, WCA forces, and the
  * integrator update.  Enqueued on the stream with no host synchronisation (capturable in a graph).  The
  * short-range forces and the ordering of the traversal's work run on the handle's own stream, forked from
- * `stream` (event record + wait) and joined back to it before the traversal: the step starts after
+ * `stream` (event record + wait) and joined back to it before the traversal (from 16384 particles over
+ * the batch; smaller steps run on `stream` alone): the step starts after
  * everything enqueued on `stream` before it and is complete for everything enqueued after it. */
 bh_status md_step(bh_handle *h, const md_state *s, const md_params *p, void *stream);
 

@@ -266,6 +266,9 @@ __global__ void k_step_inc(uint64_t *d_step)
     if (threadIdx.x == 0 && blockIdx.x == 0) *d_step += 1ull;
 }
 
+// Below this many particles (over the batch) the fork and join cost more than the overlap gains.
+constexpr int64_t kForkMinParticles = 1 << 14;
+
 hipError_t launch_md(Handle &h, const md_state *st, const md_params *mp, hipStream_t s)
 {
     const Layout &L = h.L;
@@ -276,17 +279,19 @@ hipError_t launch_md(Handle &h, const md_state *st, const md_params *mp, hipStre
     // (octree, levels, upward pass: short, latency-bound launches).  The side stream rejoins the caller's
     // before the traversal, which therefore has the whole device.  The step starts after everything
     // enqueued on the caller's stream before it and is complete for everything enqueued after it; under
-    // graph capture the fork and the join become edges.
+    // graph capture the fork and the join become edges.  Small systems keep everything on one stream.
     hipError_t e;
-    const bool order = uses_wave_order(h);
+    const bool fork = L.ntot >= kForkMinParticles;
+    const hipStream_t ss = fork ? h.side : s;
+    const bool order = fork && uses_wave_order(h);  // else launch_backward orders the items itself
     if (order) {
         if ((e = hipEventRecord(h.fork_ev, s)) != hipSuccess) return e;
         if ((e = hipStreamWaitEvent(h.side, h.fork_ev, 0)) != hipSuccess) return e;
         launch_order_waves(h, h.side);
     }
-    e = launch_build(h, st->pos, s, st->mom, h.sorted_ev);  // tree, centroids and moment sums
+    e = launch_build(h, st->pos, s, st->mom, fork ? h.sorted_ev : nullptr);  // tree, centroids, moment sums
     if (e != hipSuccess) return e;
-    if ((e = hipStreamWaitEvent(h.side, h.sorted_ev, 0)) != hipSuccess) return e;
+    if (fork && (e = hipStreamWaitEvent(h.side, h.sorted_ev, 0)) != hipSuccess) return e;
     // sr_kind 0: WCA, pair and wall cut at the potential minimum; 1: the paper's form, walls at half the pair cut
     const double wca_rc = 1.122462048309373;  // 2^(1/6)
     const bool lj = mp->sr_kind == 1;
@@ -294,20 +299,20 @@ hipError_t launch_md(Handle &h, const md_state *st, const md_params *mp, hipStre
     const double rc = lj ? (mp->sr_cut > 0.0 ? mp->sr_cut : 2.5 * mp->wca_sigma) : wca_rc * mp->wca_sigma;
     const double rcw = lj ? 0.5 * rc : wca_rc * 0.5 * mp->wca_sigma;
     const int64_t ncell = L.B * L.cell_T;
-    hipLaunchKernelGGL(k_clear_cells, dim3(grid_for(ncell, 256, 2048)), dim3(256), 0, h.side, w.cells, ncell);
-    hipLaunchKernelGGL(k_cell_fill, dim3(grid_for(L.ntot, 256)), dim3(256), 0, h.side, w.codes, w.bbox, L.n, L.ntot,
+    hipLaunchKernelGGL(k_clear_cells, dim3(grid_for(ncell, 256, 2048)), dim3(256), 0, ss, w.cells, ncell);
+    hipLaunchKernelGGL(k_cell_fill, dim3(grid_for(L.ntot, 256)), dim3(256), 0, ss, w.codes, w.bbox, L.n, L.ntot,
                        rc, L.cell_lcap, L.cell_T, w.cells);
-    hipLaunchKernelGGL(k_wca, dim3(grid_for(L.ntot, 256)), dim3(256), 0, h.side, w.codes, w.bbox, w.cells, w.spos,
+    hipLaunchKernelGGL(k_wca, dim3(grid_for(L.ntot, 256)), dim3(256), 0, ss, w.codes, w.bbox, w.cells, w.spos,
                        w.perm, w.md_force, L.n, L.ntot, L.cell_lcap, L.cell_T, mp->wca_sigma, mp->wca_eps, c12, rc, rcw,
                        make_double3(mp->box_lo[0], mp->box_lo[1], mp->box_lo[2]),
                        make_double3(mp->box_hi[0], mp->box_hi[1], mp->box_hi[2]));
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if ((e = hipEventRecord(h.join_ev, h.side)) != hipSuccess) return e;
+    if (fork && (e = hipEventRecord(h.join_ev, h.side)) != hipSuccess) return e;
     if (L.expansion == 2) {
         e = launch_upward_first_moments(h, s);  // order-2 cells
         if (e != hipSuccess) return e;
     }
-    if ((e = hipStreamWaitEvent(s, h.join_ev, 0)) != hipSuccess) return e;
+    if (fork && (e = hipStreamWaitEvent(s, h.join_ev, 0)) != hipSuccess) return e;
     e = launch_backward(h, st->mom, mp->d_hext, nullptr, w.ones, w.md_grad_r, w.md_grad_m, nullptr, s, nullptr,
                         nullptr, true, order);
     if (e != hipSuccess) return e;

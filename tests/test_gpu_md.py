@@ -4,6 +4,8 @@ differs at the 1e-6 relative level, which moves the state by dt * 1e-6 per step.
 a batch of non-interacting single-particle systems.  Resuming from a saved state continues the same trajectory:
 the noise is bit-exact (counter-based, device step counter); the forces agree to FP64 rounding (the adjoint
 reduces with FP64 atomics, whose order is not fixed)."""
+import functools
+
 import numpy as np
 import pytest
 import torch
@@ -157,17 +159,30 @@ def test_short_range_law_argument_checks():
         assert torch.equal(before[k], st[k]), k
 
 
+@functools.lru_cache(maxsize=1)
+def _two_systems_and_reference(steps):
+    """Two systems of 8192 particles (16384 over the batch) and their reference trajectory."""
+    w = workloads.uniform_cube(8192, 32.0, seed=8)
+    rng = np.random.default_rng(9)
+    one = _state(w, rng)
+    two = _state(w, rng)
+    st = {k: np.concatenate([one[k], two[k]]) for k in one}
+    p = _params(32.0)
+    p["hext"] = np.array([[0.0, 0.0, 0.5], [0.2, 0.0, 0.3]])
+    ref = st
+    for k in range(steps):
+        ref = omd.md_step(ref, p, k, theta=0.5, leaf=16)
+    return w.n, st, p, ref
+
+
 @pytest.mark.parametrize("tuning_id", [-1, 13])
 def test_steps_on_a_user_stream_are_ordered_with_it(tuning_id):
-    """md_step forks part of its work onto the handle's own stream.  On a user stream that is still busy
-    (a chain of products) when the state is written and the steps are enqueued, with no host
-    synchronisation anywhere, every step must see the state written before it and the copies enqueued
-    after it must see the step complete: the result equals the reference trajectory."""
-    w = workloads.uniform_cube(1500, 20.0, seed=8)
-    rng = np.random.default_rng(9)
-    st = _state(w, rng)
-    p = _params(20.0)
-    bh = BarnesHut(w.n, 1, 16, 0.5, "fp64", tuning_id=tuning_id)
+    """md_step forks part of its work onto the handle's own stream (from 16384 particles over the batch).
+    On a user stream that is still busy (a chain of products) when the state is written and the steps are
+    enqueued, with no host synchronisation anywhere, every step must see the state written before it and
+    the copies enqueued after it must see the step complete: the result equals the reference trajectory."""
+    n, st, p, ref = _two_systems_and_reference(3)
+    bh = BarnesHut(n, 2, 16, 0.5, "fp64", tuning_id=tuning_id)
     src = _to_dev(st)
     d = {k: torch.zeros_like(v) for k, v in src.items()}
     he = torch.from_numpy(p["hext"]).cuda()
@@ -184,9 +199,6 @@ def test_steps_on_a_user_stream_are_ordered_with_it(tuning_id):
             bh.md_step(d, mp)
         out = {k: v.clone() for k, v in d.items()}
     s.synchronize()
-    ref = st
-    for k in range(3):
-        ref = omd.md_step(ref, p, k, theta=0.5, leaf=16)
     assert int(out["step"].item()) == 3
     for key in ("pos", "vel", "mom", "omega"):
         g = out[key].cpu().numpy()
