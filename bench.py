@@ -55,6 +55,21 @@ def committed_traffic(kernel_key):
     return e["fetch_bytes"] + e["write_bytes"]
 
 
+def committed_valu_issue(kernel_key):
+    """Fraction of the device's VALU issue slots the kernel used, from profiles/valu_issue.json (rocprofv3
+    SQ_INSTS_VALU over 256 wave64 instructions per cycle), or None when the kernel sources changed since
+    the counters were taken."""
+    f = os.path.join(ROOT, "profiles", "valu_issue.json")
+    if not os.path.exists(f):
+        return None
+    with open(f) as fh:
+        d = json.load(fh)
+    e = d.get(kernel_key)
+    if not e or e.get("source_sha1") != kernel_source_sha1():
+        return None
+    return e["valu_issue_frac"]
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -444,6 +459,7 @@ def main():
                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR,
                 "frac_of_unpacked_fp32": achieved / PEAK_FP32_UNPACKED,
                 "traffic": committed_traffic(adj_key) if "adjoint" in kname else None,
+                "valu_issue_frac": committed_valu_issue(adj_key) if "adjoint" in kname else None,
                 "flops_per_launch": flops, "avg_kernel_ms": kt * 1e3}
 
     cpu = None
