@@ -69,3 +69,22 @@ def test_tree_small_systems(oracle_mod, n):
     out = run_field(w.pos, w.mom, leaf=16, counters=False)
     g = out["bh"].export_tree()
     _compare(w.pos, w.mom, 16, oracle_mod, gtree=g)
+
+
+def test_tree_dense_cluster_in_a_large_tree(oracle_mod):
+    """A tree of more than 2^16 nodes whose cells below level 10 are populated: 2000 of 40000 particles
+    packed in a cube 0.01 wide, so cells of levels 10 to about 16 hold more than a leaf.  Those levels
+    take the one-workgroup upward launch; their centres must still equal the oracle's bitwise."""
+    rng = np.random.default_rng(12)
+    w = workloads.uniform_cube(38000, 85.0, seed=12)
+    cluster = np.array([[40.0], [41.0], [42.0]]) + 0.01 * rng.random((3, 2000))
+    pos = np.concatenate([w.pos, cluster], axis=1)
+    mom = np.concatenate([w.mom, workloads.uniform_cube(2000, 85.0, seed=13).mom], axis=1)
+    t = oracle_mod.Tree(pos, mom, 16).export()
+    assert t["level"].max() >= 14 and (t["level"] >= 10).sum() > 100  # the deep levels are populated
+    out = run_field(pos, mom, leaf=16, counters=False)
+    assert out["flags"] == 0
+    g = out["bh"].export_tree()
+    assert g["first"].size > 0
+    ncells = _compare(pos, mom, 16, oracle_mod, gtree=g)
+    assert ncells == g["first"].size
