@@ -35,15 +35,15 @@ __device__ inline void scatter6(uint64_t who, int lane, int wcomp, double *p, T 
 // (g) and the field of b to the target's sums (FP32 partials since the last flush in MIXED mode, FP64
 // otherwise) and returns g and T(x) a for the scatter.  Lanes with `use` false add and return zeros.
 template <bool MIXED, typename T>
-__device__ inline void fused_pair(bool use, T x, T y, T z, T ax, T ay, T az, T bx, T by, T bz, T &gx, T &gy, T &gz,
-                                  T &tx, T &ty, T &tz, T &pgx, T &pgy, T &pgz, T &phx, T &phy, T &phz, double &grx,
-                                  double &gry, double &grz, double &hx, double &hy, double &hz)
+__device__ inline void fused_pair(bool use, T r2, T x, T y, T z, T ax, T ay, T az, T bx, T by, T bz, T &gx, T &gy,
+                                  T &gz, T &tx, T &ty, T &tz, T &pgx, T &pgy, T &pgz, T &phx, T &phy, T &phz,
+                                  double &grx, double &gry, double &grz, double &hx, double &hy, double &hz)
 {
     if constexpr (MIXED) {
-        adj_field<T>(use, x, y, z, ax, ay, az, bx, by, bz, gx, gy, gz, tx, ty, tz, phx, phy, phz);
+        adj_field_r2<T>(use, r2, x, y, z, ax, ay, az, bx, by, bz, gx, gy, gz, tx, ty, tz, phx, phy, phz);
         pgx += gx; pgy += gy; pgz += gz;
     } else {
-        adj_field<T>(use, x, y, z, ax, ay, az, bx, by, bz, gx, gy, gz, tx, ty, tz, hx, hy, hz);
+        adj_field_r2<T>(use, r2, x, y, z, ax, ay, az, bx, by, bz, gx, gy, gz, tx, ty, tz, hx, hy, hz);
         grx += gx; gry += gy; grz += gz;
     }
 }
@@ -81,12 +81,12 @@ __device__ inline void adj_leaf(AdjLds<T> &W, int lane, const Src *__restrict__ 
             const LdsTarget tg = W.tgt[tl];
             const T ax = W.hb[tl][0], ay = W.hb[tl][1], az = W.hb[tl][2];
             const T x = (T)(tg.rx - sk.x), y = (T)(tg.ry - sk.y), z = (T)(tg.rz - sk.z);
-            const T r2 = x * x + y * y + z * z;
+            const T r2 = norm2<T>(x, y, z);
             const bool other = tok && sok && k != tg.si;
             const bool use = other && r2 > (T)0;
             coincident |= other && !(r2 > (T)0);
             T qx, qy, qz, ux, uy, uz, hx = 0, hy = 0, hz = 0;
-            adj_field<T>(use, x, y, z, ax, ay, az, mx, my, mz, qx, qy, qz, ux, uy, uz, hx, hy, hz);
+            adj_field_r2<T>(use, r2, x, y, z, ax, ay, az, mx, my, mz, qx, qy, qz, ux, uy, uz, hx, hy, hz);
             s0 += qx; s1 += qy; s2 += qz;
             s3 += ux; s4 += uy; s5 += uz;
             T o0, o1;
@@ -216,8 +216,8 @@ __device__ __forceinline__ void adjoint_wave(int gw, FFBH_ADJ_PARAMS)
                 bx = (T)m[0]; by = (T)m[1]; bz = (T)m[2];
             }
             T gx, gy, gz, tx, ty, tz;
-            fused_pair<MIXED, T>(acc, (T)dx, (T)dy, (T)dz, ax, ay, az, bx, by, bz, gx, gy, gz, tx, ty, tz, pgx, pgy,
-                                 pgz, phx, phy, phz, grx, gry, grz, hx, hy, hz);
+            fused_pair<MIXED, T>(acc, (T)d2, (T)dx, (T)dy, (T)dz, ax, ay, az, bx, by, bz, gx, gy, gz, tx, ty, tz,
+                                 pgx, pgy, pgz, phx, phy, phz, grx, gry, grz, hx, hy, hz);
             T e0 = 0, e1 = 0, e2 = 0, e3 = 0, e4 = 0, e5 = 0;
             if constexpr (QUAD) {
                 const T *qd = (const T *)node_q + 16 * (int64_t)cur;
@@ -501,8 +501,8 @@ struct Tgt {
     // one pair against source (or cell) moment b at offset x: accumulates, returns g and T(x) a
     __device__ inline void pair(bool use, T x, T y, T z, T bx, T by, T bz, T &qx, T &qy, T &qz, T &ux, T &uy, T &uz)
     {
-        fused_pair<MIXED, T>(use, x, y, z, ax, ay, az, bx, by, bz, qx, qy, qz, ux, uy, uz, pgx, pgy, pgz, phx, phy,
-                             phz, gx, gy, gz, hx, hy, hz);
+        fused_pair<MIXED, T>(use, norm2<T>(x, y, z), x, y, z, ax, ay, az, bx, by, bz, qx, qy, qz, ux, uy, uz, pgx,
+                             pgy, pgz, phx, phy, phz, gx, gy, gz, hx, hy, hz);
     }
 };
 
@@ -737,8 +737,8 @@ __global__ __launch_bounds__(NW * 64) void k_adjoint_wg(
                 bx = (T)m[0]; by = (T)m[1]; bz = (T)m[2];
             }
             T gx, gy, gz, tx, ty, tz;
-            fused_pair<MIXED, T>(acc, (T)dx, (T)dy, (T)dz, ax, ay, az, bx, by, bz, gx, gy, gz, tx, ty, tz, pgx, pgy,
-                                 pgz, phx, phy, phz, grx, gry, grz, hx, hy, hz);
+            fused_pair<MIXED, T>(acc, (T)d2, (T)dx, (T)dy, (T)dz, ax, ay, az, bx, by, bz, gx, gy, gz, tx, ty, tz,
+                                 pgx, pgy, pgz, phx, phy, phz, grx, gry, grz, hx, hy, hz);
             vs = wave_total6<T>(lane, tx, ty, tz, gx, gy, gz);
         }
         const uint64_t open = mask & ~accm;
@@ -774,15 +774,15 @@ __global__ __launch_bounds__(NW * 64) void k_adjoint_wg(
                 const int k = nd.first + c0 + j;
                 const Src sk = *q;
                 const T x = (T)(rx - sk.x), y = (T)(ry - sk.y), z = (T)(rz - sk.z);
-                const T r2 = x * x + y * y + z * z;
+                const T r2 = norm2<T>(x, y, z);
                 const bool other = me && k != si;
                 const bool use = other && r2 > (T)0;
                 coincident |= other && !(r2 > (T)0);
                 T ws = 0;
                 if (ballot(use) != 0ull) {
                     T qx, qy, qz, ux, uy, uz;
-                    fused_pair<MIXED, T>(use, x, y, z, ax, ay, az, (T)sk.mx, (T)sk.my, (T)sk.mz, qx, qy, qz, ux, uy,
-                                         uz, pgx, pgy, pgz, phx, phy, phz, grx, gry, grz, hx, hy, hz);
+                    fused_pair<MIXED, T>(use, r2, x, y, z, ax, ay, az, (T)sk.mx, (T)sk.my, (T)sk.mz, qx, qy, qz, ux,
+                                         uy, uz, pgx, pgy, pgz, phx, phy, phz, grx, gry, grz, hx, hy, hz);
                     ws = wave_total6<T>(lane, qx, qy, qz, ux, uy, uz);
                 }
                 if (wcomp >= 0) lpart[wv][j][wcomp] = ws;

@@ -45,12 +45,12 @@ __device__ inline void field_leaf(FieldLds<T> &W, int lane, const Src *__restric
             const int tl = W.list[tok ? a : 0];
             const LdsTarget tg = W.tgt[tl];
             const T x = (T)(tg.rx - sk.x), y = (T)(tg.ry - sk.y), z = (T)(tg.rz - sk.z);
-            const T r2 = x * x + y * y + z * z;
+            const T r2 = norm2<T>(x, y, z);
             const bool other = tok && sok && k != tg.si;
             const bool use = other && r2 > (T)0;
             coincident |= other && !(r2 > (T)0);
             T hx = 0, hy = 0, hz = 0;
-            dip_acc<T>(use, x, y, z, mx, my, mz, hx, hy, hz);
+            dip_acc_r2<T>(use, r2, x, y, z, mx, my, mz, hx, hy, hz);
             const T v = group_sum3<G>(lane, hx, hy, hz);
             if (tok && wr) lds_add(&W.acc[tl][slot], v);
             if constexpr (COUNT) {
@@ -121,10 +121,10 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(7))) void k
         if (accm != 0ull) {
             // the whole wave computes; lanes that did not accept add zero
             if (MIXED) {
-                dip_acc<T>(acc, (T)dx, (T)dy, (T)dz, (T)nd.mx, (T)nd.my, (T)nd.mz, px, py, pz);
+                dip_acc_r2<T>(acc, (T)d2, (T)dx, (T)dy, (T)dz, (T)nd.mx, (T)nd.my, (T)nd.mz, px, py, pz);
             } else {
                 const double *m = node_m64 + 4 * (int64_t)cur;
-                dip_acc<double>(acc, dx, dy, dz, m[0], m[1], m[2], hx, hy, hz);
+                dip_acc_r2<double>(acc, d2, dx, dy, dz, m[0], m[1], m[2], hx, hy, hz);
             }
             if (QUAD) {
                 const T *D = (const T *)node_q + 16 * (int64_t)cur;

@@ -35,10 +35,10 @@ __device__ inline float rsqT<float>(float a) { return __builtin_amdgcn_rsqf(a); 
 // Field of dipole m at offset x (target minus source), Eq. (H_dip) rearranged as
 // h += (3 (m.x) x / |x|^2 - m) / |x|^3 when `use`; otherwise the inverse distance is replaced by zero
 // and h receives exactly zero, so lanes of a wave that do not take part need no select on the result.
+// r2 = |x|^2 comes from the caller (a far cell's is the acceptance test's FP64 distance, rounded once).
 template <typename T>
-__device__ inline void dip_acc(bool use, T x, T y, T z, T mx, T my, T mz, T &hx, T &hy, T &hz)
+__device__ inline void dip_acc_r2(bool use, T r2, T x, T y, T z, T mx, T my, T mz, T &hx, T &hy, T &hz)
 {
-    const T r2 = fmaT<T>(z, z, fmaT<T>(y, y, x * x));
     const T ri = use ? rsqT<T>(r2) : (T)0;
     const T ri2 = ri * ri;
     const T ri3 = ri2 * ri;
@@ -47,6 +47,15 @@ __device__ inline void dip_acc(bool use, T x, T y, T z, T mx, T my, T mz, T &hx,
     hx = fmaT<T>(fmaT<T>(t, x, -mx), ri3, hx);
     hy = fmaT<T>(fmaT<T>(t, y, -my), ri3, hy);
     hz = fmaT<T>(fmaT<T>(t, z, -mz), ri3, hz);
+}
+
+template <typename T>
+__device__ inline T norm2(T x, T y, T z) { return fmaT<T>(z, z, fmaT<T>(y, y, x * x)); }
+
+template <typename T>
+__device__ inline void dip_acc(bool use, T x, T y, T z, T mx, T my, T mz, T &hx, T &hy, T &hz)
+{
+    dip_acc_r2<T>(use, norm2<T>(x, y, z), x, y, z, mx, my, mz, hx, hy, hz);
 }
 
 // Field of a cell's first moment D (row-major, D[3k+b] = sum_j (r_j - c)_k m_j,b) at offset x from the
@@ -127,11 +136,11 @@ __device__ inline void first_moment_adj(bool use, T x, T y, T z, const T *D, T u
 //   h += T(x) b, the field of dipole b at x (Eq. H_dip),
 // sharing the distance powers and dot products.  When `use` is false the inverse distance is zero and
 // g, t and the increment of h are exactly zero.
+// r2 = |x|^2 comes from the caller (see dip_acc_r2).
 template <typename T>
-__device__ inline void adj_field(bool use, T x, T y, T z, T ax, T ay, T az, T bx, T by, T bz, T &gx, T &gy,
-                                 T &gz, T &tx, T &ty, T &tz, T &hx, T &hy, T &hz)
+__device__ inline void adj_field_r2(bool use, T r2, T x, T y, T z, T ax, T ay, T az, T bx, T by, T bz, T &gx,
+                                    T &gy, T &gz, T &tx, T &ty, T &tz, T &hx, T &hy, T &hz)
 {
-    const T r2 = fmaT<T>(z, z, fmaT<T>(y, y, x * x));
     const T ri = use ? rsqT<T>(r2) : (T)0;
     const T ri2 = ri * ri;
     const T ri3 = ri2 * ri;
@@ -152,6 +161,13 @@ __device__ inline void adj_field(bool use, T x, T y, T z, T ax, T ay, T az, T bx
     hx = fmaT<T>(fmaT<T>(tb, x, -bx), ri3, hx);
     hy = fmaT<T>(fmaT<T>(tb, y, -by), ri3, hy);
     hz = fmaT<T>(fmaT<T>(tb, z, -bz), ri3, hz);
+}
+
+template <typename T>
+__device__ inline void adj_field(bool use, T x, T y, T z, T ax, T ay, T az, T bx, T by, T bz, T &gx, T &gy,
+                                 T &gz, T &tx, T &ty, T &tz, T &hx, T &hy, T &hz)
+{
+    adj_field_r2<T>(use, norm2<T>(x, y, z), x, y, z, ax, ay, az, bx, by, bz, gx, gy, gz, tx, ty, tz, hx, hy, hz);
 }
 
 // ---- wave64 reductions (DPP) ---------------------------------------------------------------------
