@@ -144,20 +144,20 @@ __device__ inline void adj_field_r2(bool use, T r2, T x, T y, T z, T ax, T ay, T
     const T ri = use ? rsqT<T>(r2) : (T)0;
     const T ri2 = ri * ri;
     const T ri3 = ri2 * ri;
-    const T ri5 = ri3 * ri2;
+    const T k3 = (T)3 * ri2;  // shared by 3/|x|^5 and both 3 (.x)/|x|^2 factors
     const T adx = fmaT<T>(az, z, fmaT<T>(ay, y, ax * x));
     const T bdx = fmaT<T>(bz, z, fmaT<T>(by, y, bx * x));
     const T ab = fmaT<T>(az, bz, fmaT<T>(ay, by, ax * bx));
     const T c0 = fmaT<T>((T)-5 * adx * bdx, ri2, ab);
-    const T s = (T)3 * ri5;
+    const T s = k3 * ri3;
     gx = s * fmaT<T>(c0, x, fmaT<T>(bdx, ax, adx * bx));
     gy = s * fmaT<T>(c0, y, fmaT<T>(bdx, ay, adx * by));
     gz = s * fmaT<T>(c0, z, fmaT<T>(bdx, az, adx * bz));
-    const T ta = (T)3 * adx * ri2;
+    const T ta = adx * k3;
     tx = fmaT<T>(ta, x, -ax) * ri3;
     ty = fmaT<T>(ta, y, -ay) * ri3;
     tz = fmaT<T>(ta, z, -az) * ri3;
-    const T tb = (T)3 * bdx * ri2;
+    const T tb = bdx * k3;
     hx = fmaT<T>(fmaT<T>(tb, x, -bx), ri3, hx);
     hy = fmaT<T>(fmaT<T>(tb, y, -by), ri3, hy);
     hz = fmaT<T>(fmaT<T>(tb, z, -bz), ri3, hz);
