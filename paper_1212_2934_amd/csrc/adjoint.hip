@@ -194,10 +194,6 @@ __device__ __forceinline__ void adjoint_wave(int gw, FFBH_ADJ_PARAMS)
             break;
         }
         const NodeRec nd = nodes[cur];
-        if (nd.first < 0 || nd.count < 1 || (uint32_t)nd.first + (uint32_t)nd.count > (uint32_t)ntot) {
-            if (lane == 0) set_flag(status, BH_FLAG_TREE);
-            break;
-        }
         ++work;
         // masks of the lanes that take part, of the targets inside the node and of the acceptance test
         const uint64_t insm = ballot((unsigned)(si - nd.first) < (unsigned)nd.count);
@@ -246,7 +242,12 @@ __device__ __forceinline__ void adjoint_wave(int gw, FFBH_ADJ_PARAMS)
             st.push(lane, nd.child, nd.nchild, open);
             continue;
         }
-        // leaf: direct sums over its members, packed over the lanes that opened it
+        // leaf: direct sums over its members, packed over the lanes that opened it (the member range is
+        // checked here, where it is first used to index memory)
+        if (nd.first < 0 || nd.count < 1 || (uint32_t)nd.first + (uint32_t)nd.count > (uint32_t)ntot) {
+            if (lane == 0) set_flag(status, BH_FLAG_TREE);
+            break;
+        }
         if (lane_in(open)) W.list[lanes_below(open)] = lane;
         const int c = __builtin_popcountll(open);
         wave_lds_sync();
