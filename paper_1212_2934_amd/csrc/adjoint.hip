@@ -181,18 +181,21 @@ __device__ __forceinline__ void adjoint_wave(int gw, FFBH_ADJ_PARAMS)
         const NodeRec r = nodes[seg];
         const bool leaf_root = r.nchild == 0;
         const int first = leaf_root ? seg : r.child + part;
-        const int cnt = leaf_root ? (part == 0 ? 1 : 0) : (part < r.nchild ? 1 : 0);
+        int cnt = leaf_root ? (part == 0 ? 1 : 0) : (part < r.nchild ? 1 : 0);
+        if (cnt > 0 && (unsigned)first >= (unsigned)max_nodes) {
+            if (lane == 0) set_flag(status, BH_FLAG_TREE);
+            cnt = 0;
+        }
         st.init(first, cnt, ballot(valid));
     }
-    int guard = max_nodes;  // a wave visits each node at most once
+    // Node indices are checked where they enter the stack (the root above, child ranges at the push), so
+    // every visited node is in [0, max_nodes); a wave pushes each internal node's children at most once,
+    // so at most max_nodes pushes keep the walk finite whatever the tree holds.
+    int guard = max_nodes;
     uint32_t work = 0;      // node visits plus leaf pair rounds (wave-uniform)
     while (st.more()) {
         uint64_t mask;
         const int cur = st.pop(mask);
-        if (--guard < 0 || (unsigned)cur >= (unsigned)max_nodes) {
-            if (lane == 0) set_flag(status, BH_FLAG_TREE);
-            break;
-        }
         const NodeRec nd = nodes[cur];
         ++work;
         // masks of the lanes that take part, of the targets inside the node and of the acceptance test
@@ -232,45 +235,51 @@ __device__ __forceinline__ void adjoint_wave(int gw, FFBH_ADJ_PARAMS)
             scatter6<T>(accm, lane, wcomp, node_adj + 8 * (int64_t)cur, tx, ty, tz, gx, gy, gz);
             if constexpr (QUAD) scatter6<T>(accm, lane, wcomp, node_adjq + 8 * (int64_t)cur, e0, e1, e2, e3, e4, e5);
         }
+        // One loop exit and one back edge: error exits clear the stack instead of breaking, so that the
+        // accumulators stay in the same registers on every path (no copies at the merges).
         const uint64_t open = mask & ~accm;
-        if (open == 0ull) continue;
-        if (nd.nchild != 0) {
-            if (st.sp >= kStackMax) {
-                if (lane == 0) set_flag(status, BH_FLAG_STACK);
-                break;
-            }
-            st.push(lane, nd.child, nd.nchild, open);
-            continue;
-        }
-        // leaf: direct sums over its members, packed over the lanes that opened it (the member range is
-        // checked here, where it is first used to index memory)
-        if (nd.first < 0 || nd.count < 1 || (uint32_t)nd.first + (uint32_t)nd.count > (uint32_t)ntot) {
-            if (lane == 0) set_flag(status, BH_FLAG_TREE);
-            break;
-        }
-        if (lane_in(open)) W.list[lanes_below(open)] = lane;
-        const int c = __builtin_popcountll(open);
-        wave_lds_sync();
-        if (nd.count <= 4) adj_leaf<4>(W, lane, sr, g_rm, nd.first, nd.count, c, coincident);
-        else if (nd.count <= 8) adj_leaf<8>(W, lane, sr, g_rm, nd.first, nd.count, c, coincident);
-        else adj_leaf<16>(W, lane, sr, g_rm, nd.first, nd.count, c, coincident);
-        {
-            const int G = nd.count <= 4 ? 4 : nd.count <= 8 ? 8 : 16;
-            work += (uint32_t)(((nd.count + G - 1) / G) * ((c * G + kWave - 1) / kWave + 1));
-        }
-        T d[6];
+        if (open != 0ull) {
+            if (nd.nchild != 0) {
+                if (--guard < 0 || nd.child < 0 || nd.nchild > 8 || nd.child + nd.nchild > max_nodes) {
+                    if (lane == 0) set_flag(status, BH_FLAG_TREE);
+                    st.clear();
+                } else if (st.sp >= kStackMax) {
+                    if (lane == 0) set_flag(status, BH_FLAG_STACK);
+                    st.clear();
+                } else {
+                    st.push(lane, nd.child, nd.nchild, open);
+                }
+            } else if (nd.first < 0 || nd.count < 1 || (uint32_t)nd.first + (uint32_t)nd.count > (uint32_t)ntot) {
+                // the member range is checked here, where it is first used to index memory
+                if (lane == 0) set_flag(status, BH_FLAG_TREE);
+                st.clear();
+            } else {
+                // leaf: direct sums over its members, packed over the lanes that opened it
+                if (lane_in(open)) W.list[lanes_below(open)] = lane;
+                const int c = __builtin_popcountll(open);
+                wave_lds_sync();
+                if (nd.count <= 4) adj_leaf<4>(W, lane, sr, g_rm, nd.first, nd.count, c, coincident);
+                else if (nd.count <= 8) adj_leaf<8>(W, lane, sr, g_rm, nd.first, nd.count, c, coincident);
+                else adj_leaf<16>(W, lane, sr, g_rm, nd.first, nd.count, c, coincident);
+                {
+                    const int G = nd.count <= 4 ? 4 : nd.count <= 8 ? 8 : 16;
+                    work += (uint32_t)(((nd.count + G - 1) / G) * ((c * G + kWave - 1) / kWave + 1));
+                }
+                T d[6];
 #pragma unroll
-        for (int j = 0; j < 6; ++j) {
-            d[j] = W.acc[lane][j];
-            W.acc[lane][j] = (T)0;
-        }
-        if (MIXED) {
-            grx += (double)(pgx + d[0]); gry += (double)(pgy + d[1]); grz += (double)(pgz + d[2]);
-            hx += (double)(phx + d[3]); hy += (double)(phy + d[4]); hz += (double)(phz + d[5]);
-            pgx = pgy = pgz = phx = phy = phz = (T)0;
-        } else {
-            grx += (double)d[0]; gry += (double)d[1]; grz += (double)d[2];
-            hx += (double)d[3]; hy += (double)d[4]; hz += (double)d[5];
+                for (int j = 0; j < 6; ++j) {
+                    d[j] = W.acc[lane][j];
+                    W.acc[lane][j] = (T)0;
+                }
+                if (MIXED) {
+                    grx += (double)(pgx + d[0]); gry += (double)(pgy + d[1]); grz += (double)(pgz + d[2]);
+                    hx += (double)(phx + d[3]); hy += (double)(phy + d[4]); hz += (double)(phz + d[5]);
+                    pgx = pgy = pgz = phx = phy = phz = (T)0;
+                } else {
+                    grx += (double)d[0]; gry += (double)d[1]; grz += (double)d[2];
+                    hx += (double)d[3]; hy += (double)d[4]; hz += (double)d[5];
+                }
+            }
         }
     }
     if (MIXED) {

@@ -98,14 +98,13 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(7))) void k
 
     LaneStack st;
     st.init(seg, 1, ballot(valid));
-    int guard = max_nodes;  // a wave visits each node at most once
+    // Node indices are checked where they enter the stack (child ranges at the push; the root is the
+    // system's), so every visited node is in [0, max_nodes); a wave pushes each internal node's children
+    // at most once, so at most max_nodes pushes keep the walk finite whatever the tree holds.
+    int guard = max_nodes;
     while (st.more()) {
         uint64_t mask;
         const int cur = st.pop(mask);
-        if (--guard < 0 || (unsigned)cur >= (unsigned)max_nodes) {
-            if (lane == 0) set_flag(status, BH_FLAG_TREE);
-            break;
-        }
         const NodeRec nd = nodes[cur];
         // masks of the lanes that take part, of the targets inside the node and of the acceptance test
         const uint64_t insm = ballot((unsigned)(si - nd.first) < (unsigned)nd.count);
@@ -114,8 +113,9 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(7))) void k
         const double d2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
         const uint64_t accm = mask & ~insm & ballot(nd.s2 < theta2 * d2);
         const bool acc = lane_in(accm);
-        if (accm != 0ull) {
-            // the whole wave computes; lanes that did not accept add zero
+        {
+            // nearly every visit has accepting lanes, so the whole wave computes unconditionally (lanes that
+            // do not accept add exact zeros)
             if (MIXED) {
                 dip_acc_r2<T>(acc, (T)d2, (T)dx, (T)dy, (T)dz, (T)nd.mx, (T)nd.my, (T)nd.mz, px, py, pz);
             } else {
@@ -129,40 +129,46 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(7))) void k
             }
             if (COUNT) nfar += acc ? 1 : 0;
         }
+        // One loop exit and one back edge: error exits clear the stack instead of breaking, so that the
+        // accumulators stay in the same registers on every path (no copies at the merges).
         const uint64_t open = mask & ~accm;
-        if (open == 0ull) continue;
-        if (nd.nchild != 0) {
-            if (st.sp >= kStackMax) {
-                if (lane == 0) set_flag(status, BH_FLAG_STACK);
-                break;
+        if (open != 0ull) {
+            if (nd.nchild != 0) {
+                if (--guard < 0 || nd.child < 0 || nd.nchild > 8 || nd.child + nd.nchild > max_nodes) {
+                    if (lane == 0) set_flag(status, BH_FLAG_TREE);
+                    st.clear();
+                } else if (st.sp >= kStackMax) {
+                    if (lane == 0) set_flag(status, BH_FLAG_STACK);
+                    st.clear();
+                } else {
+                    st.push(lane, nd.child, nd.nchild, open);
+                }
+            } else if (nd.first < 0 || nd.count < 1 || (uint32_t)nd.first + (uint32_t)nd.count > (uint32_t)ntot) {
+                // the member range is checked here, where it is first used to index memory
+                if (lane == 0) set_flag(status, BH_FLAG_TREE);
+                st.clear();
+            } else {
+                // leaf: direct sums over its members, packed over the lanes that opened it
+                if (lane_in(open)) W.list[lanes_below(open)] = lane;
+                const int c = __builtin_popcountll(open);
+                wave_lds_sync();
+                if (nd.count <= 4) field_leaf<COUNT, 4>(W, lane, sr, nd.first, nd.count, c, coincident);
+                else if (nd.count <= 8) field_leaf<COUNT, 8>(W, lane, sr, nd.first, nd.count, c, coincident);
+                else field_leaf<COUNT, 16>(W, lane, sr, nd.first, nd.count, c, coincident);
+                wave_lds_sync();
+                const T a0 = W.acc[lane][0], a1 = W.acc[lane][1], a2 = W.acc[lane][2];
+                W.acc[lane][0] = W.acc[lane][1] = W.acc[lane][2] = (T)0;
+                if (COUNT) {
+                    nnear += W.cnt[lane];
+                    W.cnt[lane] = 0;
+                }
+                if (MIXED) {
+                    hx += (double)(px + a0); hy += (double)(py + a1); hz += (double)(pz + a2);
+                    px = py = pz = (T)0;
+                } else {
+                    hx += (double)a0; hy += (double)a1; hz += (double)a2;
+                }
             }
-            st.push(lane, nd.child, nd.nchild, open);
-            continue;
-        }
-        // leaf: direct sums over its members, packed over the lanes that opened it (the member range is
-        // checked here, where it is first used to index memory)
-        if (nd.first < 0 || nd.count < 1 || (uint32_t)nd.first + (uint32_t)nd.count > (uint32_t)ntot) {
-            if (lane == 0) set_flag(status, BH_FLAG_TREE);
-            break;
-        }
-        if (lane_in(open)) W.list[lanes_below(open)] = lane;
-        const int c = __builtin_popcountll(open);
-        wave_lds_sync();
-        if (nd.count <= 4) field_leaf<COUNT, 4>(W, lane, sr, nd.first, nd.count, c, coincident);
-        else if (nd.count <= 8) field_leaf<COUNT, 8>(W, lane, sr, nd.first, nd.count, c, coincident);
-        else field_leaf<COUNT, 16>(W, lane, sr, nd.first, nd.count, c, coincident);
-        wave_lds_sync();
-        const T a0 = W.acc[lane][0], a1 = W.acc[lane][1], a2 = W.acc[lane][2];
-        W.acc[lane][0] = W.acc[lane][1] = W.acc[lane][2] = (T)0;
-        if (COUNT) {
-            nnear += W.cnt[lane];
-            W.cnt[lane] = 0;
-        }
-        if (MIXED) {
-            hx += (double)(px + a0); hy += (double)(py + a1); hz += (double)(pz + a2);
-            px = py = pz = (T)0;
-        } else {
-            hx += (double)a0; hy += (double)a1; hz += (double)a2;
         }
     }
     if (MIXED) {

@@ -492,6 +492,12 @@ struct LaneStack {
         tmask = m;
     }
     __device__ inline bool more() const { return tleft > 0 || sp > 0; }
+    // Drop every range: the walk ends at the next more() (error exits, without a second loop exit).
+    __device__ inline void clear()
+    {
+        sp = 0;
+        tleft = 0;
+    }
     __device__ inline void push(int lane, int first, int count, uint64_t m)
     {
         if (tleft > 0) {
