@@ -26,9 +26,10 @@ __device__ inline void atomic_add_d(double *p, double v)
 template <typename T>
 __device__ inline void scatter6(uint64_t who, int lane, int wcomp, double *p, T v0, T v1, T v2, T v3, T v4, T v5)
 {
-    if (who == 0ull) return;
+    // reduced whatever `who` holds (no branch around the reduction, so the inputs need no copies); only
+    // the atomic is skipped for an empty mask
     const T t = wave_total6<T>(lane, v0, v1, v2, v3, v4, v5);
-    if (wcomp >= 0) atomic_add_d(p + wcomp, (double)t);
+    if (who != 0ull && wcomp >= 0) atomic_add_d(p + wcomp, (double)t);
 }
 
 // One pair of the fused traversal for a target with upstream field gradient a: adds the gathered dL/dr
@@ -40,8 +41,9 @@ __device__ inline void fused_pair(bool use, T r2, T x, T y, T z, T ax, T ay, T a
                                   double &grx, double &gry, double &grz, double &hx, double &hy, double &hz)
 {
     if constexpr (MIXED) {
-        adj_field_r2<T>(use, r2, x, y, z, ax, ay, az, bx, by, bz, gx, gy, gz, tx, ty, tz, phx, phy, phz);
-        pgx += gx; pgy += gy; pgz += gz;
+        T ug[3] = {pgx, pgy, pgz};
+        adj_field_r2<T, true>(use, r2, x, y, z, ax, ay, az, bx, by, bz, gx, gy, gz, tx, ty, tz, phx, phy, phz, ug);
+        pgx = ug[0]; pgy = ug[1]; pgz = ug[2];
     } else {
         adj_field_r2<T>(use, r2, x, y, z, ax, ay, az, bx, by, bz, gx, gy, gz, tx, ty, tz, hx, hy, hz);
         grx += gx; gry += gy; grz += gz;

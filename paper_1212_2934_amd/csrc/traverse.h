@@ -136,10 +136,12 @@ __device__ inline void first_moment_adj(bool use, T x, T y, T z, const T *D, T u
 //   h += T(x) b, the field of dipole b at x (Eq. H_dip),
 // sharing the distance powers and dot products.  When `use` is false the inverse distance is zero and
 // g, t and the increment of h are exactly zero.
-// r2 = |x|^2 comes from the caller (see dip_acc_r2).
-template <typename T>
+// r2 = |x|^2 comes from the caller (see dip_acc_r2).  With ACC, g is also added to (ugx, ugy, ugz) as
+// s w + u with one FMA per component (g itself is then only read by the caller's wave reduction, which
+// may overwrite it in place).
+template <typename T, bool ACC = false>
 __device__ inline void adj_field_r2(bool use, T r2, T x, T y, T z, T ax, T ay, T az, T bx, T by, T bz, T &gx,
-                                    T &gy, T &gz, T &tx, T &ty, T &tz, T &hx, T &hy, T &hz)
+                                    T &gy, T &gz, T &tx, T &ty, T &tz, T &hx, T &hy, T &hz, T *ug = nullptr)
 {
     const T ri = use ? rsqT<T>(r2) : (T)0;
     const T ri2 = ri * ri;
@@ -150,9 +152,17 @@ __device__ inline void adj_field_r2(bool use, T r2, T x, T y, T z, T ax, T ay, T
     const T ab = fmaT<T>(az, bz, fmaT<T>(ay, by, ax * bx));
     const T c0 = fmaT<T>((T)-5 * adx * bdx, ri2, ab);
     const T s = k3 * ri3;
-    gx = s * fmaT<T>(c0, x, fmaT<T>(bdx, ax, adx * bx));
-    gy = s * fmaT<T>(c0, y, fmaT<T>(bdx, ay, adx * by));
-    gz = s * fmaT<T>(c0, z, fmaT<T>(bdx, az, adx * bz));
+    const T wx = fmaT<T>(c0, x, fmaT<T>(bdx, ax, adx * bx));
+    const T wy = fmaT<T>(c0, y, fmaT<T>(bdx, ay, adx * by));
+    const T wz = fmaT<T>(c0, z, fmaT<T>(bdx, az, adx * bz));
+    gx = s * wx;
+    gy = s * wy;
+    gz = s * wz;
+    if constexpr (ACC) {
+        ug[0] = fmaT<T>(s, wx, ug[0]);
+        ug[1] = fmaT<T>(s, wy, ug[1]);
+        ug[2] = fmaT<T>(s, wz, ug[2]);
+    }
     const T ta = adx * k3;
     tx = fmaT<T>(ta, x, -ax) * ri3;
     ty = fmaT<T>(ta, y, -ay) * ri3;
