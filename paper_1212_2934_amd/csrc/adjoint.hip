@@ -328,10 +328,11 @@ __device__ __forceinline__ void adjoint_wave(int gw, FFBH_ADJ_PARAMS)
 // With `order`, the launch is persistent: each wave takes item after item from the work counter, in the
 // order given (light items of the previous launch last, so the launch does not end on a long item), until
 // the items run out.  Every wave reaches the exit: the counter only grows.
-// Four waves per SIMD: the FP64 walk fits 128 VGPRs with a few spilled bytes and runs 7 % faster than
-// at three; the FP32-mixed walk needs fewer registers and is unaffected.
+// Waves per SIMD: five for the FP32-mixed walk with the paper's cells (96 VGPRs, a few spilled bytes;
+// 3 % faster MD step than at four), four for the others (the FP64 walk fits 128 VGPRs and runs 7 % faster
+// than at three, but spills heavily at five).
 template <bool MIXED, bool QUAD>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_adjoint(
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(MIXED && !QUAD ? 5 : 4))) void k_adjoint(
     FFBH_ADJ_PARAMS, const uint32_t *__restrict__ order,
                                                  uint32_t *__restrict__ work_ctr)
 {
