@@ -5,17 +5,18 @@
 
 namespace ffbh {
 
-// 1/sqrt(a) in FP64: hardware estimate refined by two Newton steps y <- y + y (1 - a y^2) / 2.
+// 1/sqrt(a) in FP64: the hardware estimate y (relative error about 2^-23) refined by one third-order
+// step of the binomial series (1 - e)^(-1/2) = 1 + e/2 + 3e^2/8 + ..., e = 1 - a y^2:
+//   y <- y + y e (1/2 + 3e/8),
+// whose truncation error 5e^3/16 (about 2^-70) is far below FP64 rounding; five operations where two
+// Newton steps take eight.
 __device__ inline double rsqrt64(double a)
 {
-    double y = __builtin_amdgcn_rsq(a);
-#pragma unroll
-    for (int it = 0; it < 2; ++it) {
-        const double t = a * y;
-        const double r = __builtin_fma(-t, y, 1.0);
-        y = __builtin_fma(0.5 * y, r, y);
-    }
-    return y;
+    const double y = __builtin_amdgcn_rsq(a);
+    const double t = a * y;
+    const double e = __builtin_fma(-t, y, 1.0);
+    const double p = __builtin_fma(0.375, e, 0.5);
+    return __builtin_fma(y * e, p, y);
 }
 
 template <typename T>

@@ -77,3 +77,23 @@ def test_chains_2p20_sampled_targets(precision):
     e = errors(H.cpu().numpy()[:, idx], Href)
     tol = TOL[precision]
     assert e["l2"] <= tol and e["max"] <= 10 * tol, e
+
+
+def test_fp64_pair_field_to_rounding_over_distances():
+    """Two particles on the z axis, moments along z: the field at each is 2 m / r^3 along z (Eq. H_dip).
+    Over distances from 1e-3 to 1e3 the FP64 kernel (hardware 1/sqrt estimate plus one refinement step)
+    must agree to about ten units in the last place (a refinement short of full precision would not)."""
+    B = 241
+    r = np.logspace(-3.0, 3.0, B)
+    pos = np.zeros((B, 3, 2))
+    pos[:, 2, 0] = 0.37
+    pos[:, 2, 1] = 0.37 + r
+    mom = np.zeros((B, 3, 2))
+    mom[:, 2, :] = 1.0
+    H, _, _ = allpairs(_dev(pos), _dev(mom), None, "fp64")
+    H = H.cpu().numpy()
+    exact = 2.0 / ((pos[:, 2, 1] - pos[:, 2, 0]) ** 3)  # the distance the kernel sees, formed in FP64
+    for k in range(2):
+        rel = np.abs(H[:, 2, k] - exact) / exact
+        assert rel.max() <= 2e-15, (k, rel.max())  # a few roundings; a 2^-46 or worse 1/sqrt fails
+        assert np.abs(H[:, :2, k]).max() == 0.0
