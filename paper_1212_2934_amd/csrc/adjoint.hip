@@ -223,12 +223,13 @@ __device__ __forceinline__ void adjoint_wave(int gw, FFBH_ADJ_PARAMS)
             if constexpr (QUAD) {
                 const T *qd = (const T *)node_q + 16 * (int64_t)cur;
                 T Gx, Gy, Gz;
-                first_moment_adj<T>(acc, (T)dx, (T)dy, (T)dz, qd, ax, ay, az, Gx, Gy, Gz, e0, e1, e2, e3, e4, e5);
+                first_moment_adj_r2<T>(acc, (T)d2, (T)dx, (T)dy, (T)dz, qd, ax, ay, az, Gx, Gy, Gz, e0, e1, e2, e3, e4,
+                                       e5);
                 if constexpr (MIXED) {
-                    first_moment_acc<T>(acc, (T)dx, (T)dy, (T)dz, qd, phx, phy, phz);
+                    first_moment_acc_r2<T>(acc, (T)d2, (T)dx, (T)dy, (T)dz, qd, phx, phy, phz);
                     pgx += Gx; pgy += Gy; pgz += Gz;
                 } else {
-                    first_moment_acc<T>(acc, (T)dx, (T)dy, (T)dz, qd, hx, hy, hz);
+                    first_moment_acc_r2<T>(acc, (T)d2, (T)dx, (T)dy, (T)dz, qd, hx, hy, hz);
                     grx += Gx; gry += Gy; grz += Gz;
                 }
                 gx += Gx; gy += Gy; gz += Gz;

@@ -124,8 +124,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(7))) void k
             }
             if (QUAD) {
                 const T *D = (const T *)node_q + 16 * (int64_t)cur;
-                if (MIXED) first_moment_acc<T>(acc, (T)dx, (T)dy, (T)dz, D, px, py, pz);
-                else first_moment_acc<double>(acc, dx, dy, dz, (const double *)D, hx, hy, hz);
+                if (MIXED) first_moment_acc_r2<T>(acc, (T)d2, (T)dx, (T)dy, (T)dz, D, px, py, pz);
+                else first_moment_acc_r2<double>(acc, d2, dx, dy, dz, (const double *)D, hx, hy, hz);
             }
             if (COUNT) nfar += acc ? 1 : 0;
         }

@@ -64,9 +64,8 @@ __device__ inline void dip_acc(bool use, T x, T y, T z, T mx, T my, T mz, T &hx,
 //   h = -3 (D x + D^T x + x tr D) / |x|^5 + 15 (x.D x) x / |x|^7 .
 // When `use` is false the inverse distance is zero and the increment is exactly zero.
 template <typename T>
-__device__ inline void first_moment_acc(bool use, T x, T y, T z, const T *D, T &hx, T &hy, T &hz)
+__device__ inline void first_moment_acc_r2(bool use, T r2, T x, T y, T z, const T *D, T &hx, T &hy, T &hz)
 {
-    const T r2 = fmaT<T>(z, z, fmaT<T>(y, y, x * x));
     const T ri = use ? rsqT<T>(r2) : (T)0;
     const T ri2 = ri * ri;
     const T ri5 = ri2 * ri2 * ri;
@@ -84,6 +83,12 @@ __device__ inline void first_moment_acc(bool use, T x, T y, T z, const T *D, T &
     hz = fmaT<T>(fmaT<T>(s, z, (T)-3 * (u2 + w2 + z * tr)), ri5, hz);
 }
 
+template <typename T>
+__device__ inline void first_moment_acc(bool use, T x, T y, T z, const T *D, T &hx, T &hy, T &hz)
+{
+    first_moment_acc_r2<T>(use, norm2<T>(x, y, z), x, y, z, D, hx, hy, hz);
+}
+
 // Adjoint of the first-moment term for the target's upstream field gradient u: with phi = 1/|x|, the
 // term is h_D,a = -sum D_kb d_a d_b d_k phi, and for u . h_D
 //   G = d(u.h_D)/dx = -[105 (u.x) q x / r^9 - 15 (x (x.Du + u.Dx + (u.x) tr D) + u q + (u.x)(Dx + D^T x)) / r^7
@@ -91,10 +96,9 @@ __device__ inline void first_moment_acc(bool use, T x, T y, T z, const T *D, T &
 //   E = d(u.h_D)/dD = -[3 (x u^T + u x^T + (u.x) I) / r^5 - 15 (u.x) x x^T / r^7]    (symmetric)
 // E is returned as (xx, yy, zz, xy, xz, yz).  When `use` is false every output is exactly zero.
 template <typename T>
-__device__ inline void first_moment_adj(bool use, T x, T y, T z, const T *D, T ux, T uy, T uz, T &gx, T &gy,
-                                        T &gz, T &e0, T &e1, T &e2, T &e3, T &e4, T &e5)
+__device__ inline void first_moment_adj_r2(bool use, T r2, T x, T y, T z, const T *D, T ux, T uy, T uz, T &gx,
+                                           T &gy, T &gz, T &e0, T &e1, T &e2, T &e3, T &e4, T &e5)
 {
-    const T r2 = fmaT<T>(z, z, fmaT<T>(y, y, x * x));
     const T ri = use ? rsqT<T>(r2) : (T)0;
     const T ri2 = ri * ri;
     const T ri5 = ri2 * ri2 * ri, ri7 = ri5 * ri2, ri9 = ri7 * ri2;
@@ -127,6 +131,13 @@ __device__ inline void first_moment_adj(bool use, T x, T y, T z, const T *D, T u
     e3 = -(c5 * (uy * x + ux * y) - f * x * y);
     e4 = -(c5 * (uz * x + ux * z) - f * x * z);
     e5 = -(c5 * (uz * y + uy * z) - f * y * z);
+}
+
+template <typename T>
+__device__ inline void first_moment_adj(bool use, T x, T y, T z, const T *D, T ux, T uy, T uz, T &gx, T &gy,
+                                        T &gz, T &e0, T &e1, T &e2, T &e3, T &e4, T &e5)
+{
+    first_moment_adj_r2<T>(use, norm2<T>(x, y, z), x, y, z, D, ux, uy, uz, gx, gy, gz, e0, e1, e2, e3, e4, e5);
 }
 
 // Adjoint pair plus the forward field.  With a = upstream field gradient of the target, b = source
