@@ -62,7 +62,8 @@ __device__ inline void dip_acc(bool use, T x, T y, T z, T mx, T my, T mz, T &hx,
 // Field of a cell's first moment D (row-major, D[3k+b] = sum_j (r_j - c)_k m_j,b) at offset x from the
 // cell's centre c: the next term of the Taylor expansion of Eq. H_dip about c,
 //   h = -3 (D x + D^T x + x tr D) / |x|^5 + 15 (x.D x) x / |x|^7 .
-// When `use` is false the inverse distance is zero and the increment is exactly zero.
+// When `use` is false the inverse distance is zero and the increment is exactly zero.  r2 = |x|^2 comes
+// from the caller (see dip_acc_r2).
 template <typename T>
 __device__ inline void first_moment_acc_r2(bool use, T r2, T x, T y, T z, const T *D, T &hx, T &hy, T &hz)
 {
@@ -81,12 +82,6 @@ __device__ inline void first_moment_acc_r2(bool use, T r2, T x, T y, T z, const 
     hx = fmaT<T>(fmaT<T>(s, x, (T)-3 * (u0 + w0 + x * tr)), ri5, hx);
     hy = fmaT<T>(fmaT<T>(s, y, (T)-3 * (u1 + w1 + y * tr)), ri5, hy);
     hz = fmaT<T>(fmaT<T>(s, z, (T)-3 * (u2 + w2 + z * tr)), ri5, hz);
-}
-
-template <typename T>
-__device__ inline void first_moment_acc(bool use, T x, T y, T z, const T *D, T &hx, T &hy, T &hz)
-{
-    first_moment_acc_r2<T>(use, norm2<T>(x, y, z), x, y, z, D, hx, hy, hz);
 }
 
 // Adjoint of the first-moment term for the target's upstream field gradient u: with phi = 1/|x|, the
@@ -133,13 +128,6 @@ __device__ inline void first_moment_adj_r2(bool use, T r2, T x, T y, T z, const 
     e5 = -(c5 * (uz * y + uy * z) - f * y * z);
 }
 
-template <typename T>
-__device__ inline void first_moment_adj(bool use, T x, T y, T z, const T *D, T ux, T uy, T uz, T &gx, T &gy,
-                                        T &gz, T &e0, T &e1, T &e2, T &e3, T &e4, T &e5)
-{
-    first_moment_adj_r2<T>(use, norm2<T>(x, y, z), x, y, z, D, ux, uy, uz, gx, gy, gz, e0, e1, e2, e3, e4, e5);
-}
-
 // Adjoint pair plus the forward field.  With a = upstream field gradient of the target, b = source
 // moment, x = offset (target minus source):
 //   g  = 3 [ (a.b) x + (b.x) a + (a.x) b ] / |x|^5 - 15 (a.x)(b.x) x / |x|^7   (f_dip summand, Sec. 2)
@@ -148,9 +136,9 @@ __device__ inline void first_moment_adj(bool use, T x, T y, T z, const T *D, T u
 //   h += T(x) b, the field of dipole b at x (Eq. H_dip),
 // sharing the distance powers and dot products.  When `use` is false the inverse distance is zero and
 // g, t and the increment of h are exactly zero.
-// r2 = |x|^2 comes from the caller (see dip_acc_r2).  With ACC, g is also added to (ugx, ugy, ugz) as
-// s w + u with one FMA per component (g itself is then only read by the caller's wave reduction, which
-// may overwrite it in place).
+// r2 = |x|^2 comes from the caller (see dip_acc_r2).  With ACC, g is also added to ug[0..2] as s w + ug
+// with one FMA per component, where g = s w (g itself is then only read by the caller's wave reduction,
+// which may overwrite it in place).
 template <typename T, bool ACC = false>
 __device__ inline void adj_field_r2(bool use, T r2, T x, T y, T z, T ax, T ay, T az, T bx, T by, T bz, T &gx,
                                     T &gy, T &gz, T &tx, T &ty, T &tz, T &hx, T &hy, T &hz, T *ug = nullptr)
