@@ -455,6 +455,104 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     }
 }
 
+// Whole sort of one small system in one workgroup (systems of at most kSortSmallMax keys): the keys stay
+// in LDS for all eight passes, so a small system's sort is one launch instead of sixteen.  Each pass is
+// the tile pass of k_radix_scatter over the whole system: every wave ranks a contiguous chunk of keys
+// (ballot match masks, running per-wave digit counts), the digit starts and per-wave offsets place every
+// key, and the keys move to the other LDS buffer.  Stable, so the result is the multi-workgroup sort's.
+constexpr int kSortSmallThreads = 512;
+constexpr int kSortSmallMax = 2048;
+
+__global__ __launch_bounds__(kSortSmallThreads) void k_sort_small(uint64_t *__restrict__ keys,
+                                                                  uint32_t *__restrict__ vals, int n)
+{
+    constexpr int kWaves = kSortSmallThreads / kWave;
+    constexpr int kItems = kSortSmallMax / kSortSmallThreads;  // rounds of 64 keys per wave
+    __shared__ uint64_t sk[2][kSortSmallMax];
+    __shared__ uint32_t sv[2][kSortSmallMax];
+    __shared__ uint32_t wcnt[kWaves][kRadixBins];
+    __shared__ uint32_t lstart[kRadixBins];
+    __shared__ uint32_t dsum[kRadixBins / kWave];
+    const int64_t base = (int64_t)blockIdx.x * n;
+    const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
+    const uint32_t dmask = kRadixBins - 1;
+    const int cn = n < kSortSmallMax ? n : kSortSmallMax;
+    for (int i = tid; i < cn; i += kSortSmallThreads) {
+        sk[0][i] = keys[base + i];
+        sv[0][i] = vals[base + i];
+    }
+    // wave w ranks keys [w * chunk, (w + 1) * chunk) in rounds of 64
+    const int chunk = ((cn + kWaves * kWave - 1) / (kWaves * kWave)) * kWave;
+    const int c0 = wave * chunk;
+    for (int pass = 0; pass < kRadixPasses; ++pass) {
+        const int src = pass & 1, dst = src ^ 1, shift = pass * kRadixBits;
+        for (int w = 0; w < kWaves; ++w)
+            for (int d = tid; d < kRadixBins; d += kSortSmallThreads) wcnt[w][d] = 0u;
+        __syncthreads();  // loads (or the previous pass's moves) and the cleared counts are visible
+        uint32_t rank[kItems];
+        uint32_t dig[kItems];
+#pragma unroll
+        for (int r = 0; r < kItems; ++r) {
+            const int p = c0 + r * kWave + lane;
+            const bool valid = r * kWave < chunk && p < cn;
+            const uint32_t d = valid ? (uint32_t)(sk[src][p] >> shift) & dmask : 0u;
+            uint64_t m = __ballot(valid);
+#pragma unroll
+            for (int bit = 0; bit < kRadixBits; ++bit) {
+                const bool set = (d >> bit) & 1u;
+                const uint64_t v = __ballot(set);
+                m &= set ? v : ~v;
+            }
+            const uint32_t before = (uint32_t)__popcll(m & lt);
+            // one wave's LDS accesses complete in order: this read sees the previous round's update
+            const uint32_t cur = valid ? wcnt[wave][d] : 0u;
+            rank[r] = cur + before;
+            dig[r] = d;
+            if (valid && before == 0) wcnt[wave][d] = cur + (uint32_t)__popcll(m);
+        }
+        __syncthreads();
+        // threads below kRadixBins own one digit: per-wave offsets and the digit's start
+        uint32_t tot = 0;
+        if (tid < kRadixBins) {
+            for (int w = 0; w < kWaves; ++w) {
+                const uint32_t c = wcnt[w][tid];
+                wcnt[w][tid] = tot;
+                tot += c;
+            }
+        }
+        uint32_t incl = 0;
+        if (tid < kRadixBins) {
+            incl = wave_incl_scan_u32(tot, lane);
+            if (lane == kWave - 1) dsum[wave] = incl;
+        }
+        __syncthreads();
+        if (tid < kRadixBins) {
+            uint32_t woff = 0;
+            for (int w = 0; w < wave; ++w) woff += dsum[w];
+            lstart[tid] = woff + incl - tot;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kItems; ++r) {
+            const int p = c0 + r * kWave + lane;
+            if (r * kWave < chunk && p < cn) {
+                const uint32_t at = lstart[dig[r]] + wcnt[wave][dig[r]] + rank[r];
+                if (at < (uint32_t)kSortSmallMax) {  // always true for consistent counts
+                    sk[dst][at] = sk[src][p];
+                    sv[dst][at] = sv[src][p];
+                }
+            }
+        }
+        __syncthreads();  // every move (and every read of wcnt, lstart) done before the next pass
+    }
+    // kRadixPasses is even: the sorted keys are in buffer 0
+    for (int i = tid; i < cn; i += kSortSmallThreads) {
+        keys[base + i] = sk[0][i];
+        vals[base + i] = sv[0][i];
+    }
+}
+
 // Sorted positions (SoA, global over systems).
 __global__ __launch_bounds__(256) void k_gather3(const double *__restrict__ src, const uint32_t *__restrict__ perm,
                                                  int64_t n, int64_t ntot, double *__restrict__ dst,
@@ -1033,6 +1131,11 @@ hipError_t launch_build(Handle &h, const double *d_pos, hipStream_t s, const dou
                        w.keys[0], w.vals[0]);
     const int tiles = (int)L.tiles;
     const unsigned sblocks = (unsigned)(B * tiles);
+    if (n <= kSortSmallMax) {
+        // small systems: the whole sort in LDS, one workgroup per system
+        hipLaunchKernelGGL(k_sort_small, dim3((unsigned)B), dim3(kSortSmallThreads), 0, s, w.keys[0], w.vals[0],
+                           (int)n);
+    } else
     for (int pass = 0; pass < kRadixPasses; ++pass) {
         const int src = pass & 1, dst = src ^ 1;
         const int shift = pass * kRadixBits;
