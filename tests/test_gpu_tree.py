@@ -88,3 +88,19 @@ def test_tree_dense_cluster_in_a_large_tree(oracle_mod):
     assert g["first"].size > 0
     ncells = _compare(pos, mom, 16, oracle_mod, gtree=g)
     assert ncells == g["first"].size
+
+
+@pytest.mark.parametrize("n", [2000, 2048, 2049])
+def test_tree_batch_around_the_one_workgroup_sort(oracle_mod, n):
+    """Systems of at most 2048 particles sort in one workgroup each (all passes in LDS); 2049 takes the
+    multi-workgroup passes.  Both must give the oracle's order and cells for every system of a batch."""
+    ws = [workloads.config3(seed=200 + b, n=n) for b in range(3)]
+    pos = np.stack([w.pos for w in ws])
+    mom = np.stack([w.mom for w in ws])
+    out = run_field(pos, mom, counters=False)
+    assert out["flags"] == 0
+    g = out["bh"].export_tree()
+    total = 0
+    for b, w in enumerate(ws):
+        total += _compare(w.pos, w.mom, 16, oracle_mod, offset=b * n, gtree=g)
+    assert total == g["first"].size
