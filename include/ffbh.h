@@ -148,16 +148,16 @@ typedef struct md_params {
 } md_params;
 
 /* One MD step: bh_build on the current positions, field + adjoint of the energy, WCA forces, and the
- * integrator update.  Enqueued on the stream with no host synchronisation (capturable in a graph).  The
- * short-range forces and the ordering of the traversal's work run on the handle's own stream, forked from
- * `stream` (event record + wait) and joined back to it before the traversal (from 16384 particles over
- * the batch; smaller steps run on `stream` alone): the step starts after
- * everything enqueued on `stream` before it and is complete for everything enqueued after it. */
+ * integrator update.  Enqueued on the stream with no host synchronisation (capturable in a graph).  From
+ * 16384 particles over the batch, the short-range forces and the ordering of the traversal's work run on
+ * the handle's own stream, forked from `stream` (event record + wait) and joined back to it before the
+ * traversal; smaller steps run on `stream` alone.  Either way the step starts after everything enqueued
+ * on `stream` before it and is complete for everything enqueued on `stream` after it. */
 bh_status md_step(bh_handle *h, const md_state *s, const md_params *p, void *stream);
 
-/* Capture one md_step (everything it enqueues: kernel launches, and the fork to and join from the
- * handle's stream, which become graph edges) into a HIP graph on `stream`
- * and instantiate it into *graph_exec.  The stream must not be the null stream.  Replaying the graph
+/* Capture one md_step (everything it enqueues: kernel launches, and any fork to and join from the
+ * handle's stream, which become graph edges) into a HIP graph on `stream` and instantiate it into
+ * *graph_exec.  The stream must not be the null stream.  Replaying the graph
  * with bh_graph_launch performs one MD step on the same state buffers with the same parameters; the
  * noise advances with the device step counter, so replays continue the trajectory.  The handle,
  * workspace and state buffers must outlive the graph.  Release with bh_graph_destroy. */
