@@ -63,10 +63,10 @@ __device__ inline void field_leaf(FieldLds<T> &W, int lane, const Src *__restric
 }
 
 // QUAD: accepted cells add their first-moment term (order-2 cells; node_q holds D per node, stride 16).
-// Seven waves per SIMD: the FP64 walk fits 72 VGPRs with a few spilled bytes and runs 3 % faster than at
-// six; the FP32-mixed walk needs fewer registers and is unaffected.
+// Eight waves per SIMD (64 VGPRs): the FP64 walk spills a few bytes there and runs as fast as at seven;
+// the FP32-mixed walk fits without spilling and runs 2-3 % faster than with the hint at seven.
 template <bool MIXED, bool COUNT, bool QUAD>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(7))) void k_field(
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(8))) void k_field(
     const NodeRec *__restrict__ nodes, const double *__restrict__ node_m64, const double *__restrict__ spos,
     const double *__restrict__ smom, const void *__restrict__ src, const uint32_t *__restrict__ perm,
     const double *__restrict__ hext, double *__restrict__ H, double *__restrict__ Hs,
