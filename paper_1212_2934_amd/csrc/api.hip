@@ -452,7 +452,8 @@ bh_status bh_export_tree(bh_handle *hh, int32_t *d_perm, int32_t *d_first, int32
         hipLaunchKernelGGL(k_copy_u32, dim3(grid_for(h.L.ntot, 256)), dim3(256), 0, s, h.w.perm, h.L.ntot, d_perm);
     hipLaunchKernelGGL(k_export, dim3(grid_for(h.L.max_nodes, 256)), dim3(256), 0, s, h.w.nodes, h.w.node_level,
                        h.w.status + 2, d_first, d_count, d_level, d_nchild, d_child_first, d_centroid);
-    if (d_bbox) hipLaunchKernelGGL(k_copy_bbox, dim3(1), dim3(64), 0, s, h.w.bbox, h.L.B, d_bbox);
+    if (d_bbox)
+        hipLaunchKernelGGL(k_copy_bbox, dim3(grid_for(h.L.B, 64)), dim3(64), 0, s, h.w.bbox, h.L.B, d_bbox);
     return hipGetLastError() == hipSuccess ? BH_OK : BH_EDEVICE;
 }
 

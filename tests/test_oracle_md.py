@@ -3,10 +3,27 @@ deterministic friction decay of a free particle (exact geometric law of the Eule
 translational and rotational kinetic energy, and the Langevin magnetisation law <m.h> = L(|h|/kT) of
 non-interacting dipoles (Eq. Langevin, Sec. 5), which fixes the sign of the torque m x H and the noise
 amplitude together."""
+import json
+import os
+
 import numpy as np
 import pytest
 
 from oracle import md
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def test_philox_known_answer_vectors():
+    """The generator against the known-answer vectors its authors publish (Salmon et al., SC'11): a wrong
+    multiplier, Weyl constant, round count or word order changes every output word."""
+    with open(os.path.join(GOLDEN, "philox4x32_10_kat.json")) as f:
+        cases = json.load(f)["cases"]
+    for c in cases:
+        ctr = [np.array([int(x, 16)], np.uint64) for x in c["ctr"]]
+        k0, k1 = (np.uint64(int(x, 16)) for x in c["key"])
+        out = md.philox4x32_10(*ctr, k0, k1)
+        assert ["%08x" % int(w[0]) for w in out] == c["out"], c["name"]
 
 
 def test_philox_words_uniform_and_independent():
@@ -129,3 +146,64 @@ def test_paper_short_range_momentum_and_walls():
     W = md.wall_forces(x, lo, hi, 1.0, 1.0, kind=1)
     assert W[0, 0] == 0.0 and W[0, 1] > 0.0 and W[0, 2] < 0.0 and W[0, 3] == 0.0 and W[0, 4] == 0.0
     assert not W[1:].any()
+
+
+def _wca_potential(r, s, eps):
+    """WCA potential written from its definition (Weeks, Chandler, Andersen 1971): the Lennard-Jones
+    potential 4 eps [(s/r)^12 - (s/r)^6] cut at its minimum 2^(1/6) s and shifted up by eps, zero beyond."""
+    rc = 2.0 ** (1.0 / 6.0) * s
+    return np.where(r < rc, 4.0 * eps * ((s / r) ** 12 - (s / r) ** 6) + eps, 0.0)
+
+
+def test_wca_pair_force_law():
+    """The default short-range law: minus the derivative of the WCA potential (central differences of the
+    potential above, written independently of the force), repulsive everywhere inside the cut, exactly zero
+    at and beyond 2^(1/6) s, and equal and opposite on the two particles."""
+    s, eps = 1.3, 0.7
+    rc = 2.0 ** (1.0 / 6.0) * s
+    for r in (0.85 * s, 0.95 * s, s, 1.05 * s, 0.999 * rc):
+        pos = np.array([[0.0, r], [0.0, 0.0], [0.0, 0.0]])
+        F = md.wca_forces(pos, s, eps)
+        h = 1e-6 * r
+        fd = -(_wca_potential(r + h, s, eps) - _wca_potential(r - h, s, eps)) / (2.0 * h)
+        assert abs(F[0, 1] - fd) <= 1e-6 * max(1.0, abs(fd)), (r, F[0, 1], fd)
+        assert F[0, 1] > 0.0  # particle 1 (at +x) pushed away
+        assert F[0, 0] == -F[0, 1] and not F[1:].any()
+    # the force of the law is zero at the cut itself (the minimum of the unshifted potential)
+    at_cut = 24.0 * eps * (2.0 * 0.5 ** 2 - 0.5) / rc
+    assert abs(at_cut) < 1e-15
+    for r in (rc, 1.01 * rc, 2.0 * s):
+        pos = np.array([[0.0, r], [0.0, 0.0], [0.0, 0.0]])
+        assert not md.wca_forces(pos, s, eps).any(), r
+    # a skew pair: the force points along the separation with the magnitude of the radial law
+    d = np.array([0.4, -0.5, 0.6])
+    pos = np.stack([np.zeros(3), d], axis=1)
+    F = md.wca_forces(pos, s, eps)
+    r = np.linalg.norm(d)
+    h = 1e-6 * r
+    fr = -(_wca_potential(r + h, s, eps) - _wca_potential(r - h, s, eps)) / (2.0 * h)
+    np.testing.assert_allclose(F[:, 1], fr * d / r, rtol=1e-6)
+
+
+def test_wca_walls():
+    """WCA walls on the centre-to-face distance with s_w = s / 2: minus the derivative of the WCA potential
+    of s_w in that distance (pushing the particle into the box), zero from 2^(1/6) s_w on, floored at
+    s_w / 10, and each face acting only along its own axis."""
+    s, eps = 1.0, 1.0
+    sw = 0.5 * s
+    lo, hi = (0.0, 0.0, 0.0), (10.0, 10.0, 10.0)
+    for dist in (0.3, 0.45, 0.5, 0.55):
+        x = np.array([[dist, 10.0 - dist], [5.0, 5.0], [5.0, 5.0]])
+        W = md.wall_forces(x, lo, hi, s, eps, kind=0)
+        h = 1e-7
+        fd = -(_wca_potential(dist + h, sw, eps) - _wca_potential(dist - h, sw, eps)) / (2.0 * h)
+        assert abs(W[0, 0] - fd) <= 1e-6 * max(1.0, abs(fd)), (dist, W[0, 0], fd)
+        assert W[0, 0] > 0.0 and abs(W[0, 1] + W[0, 0]) <= 1e-12 * W[0, 0]  # 10 - (10 - d) rounds
+        assert not W[1:].any()
+    rcw = 2.0 ** (1.0 / 6.0) * sw
+    x = np.array([[rcw, 1.0, 5.0], [5.0] * 3, [5.0] * 3])
+    assert not md.wall_forces(x, lo, hi, s, eps, kind=0).any()
+    # below a tenth of s_w the distance is floored: the force stops growing
+    x = np.array([[0.01, 0.04], [5.0, 5.0], [5.0, 5.0]])
+    W = md.wall_forces(x, lo, hi, s, eps, kind=0)
+    assert W[0, 0] == W[0, 1] > 0.0
