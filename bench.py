@@ -6,11 +6,14 @@ with N(0, 0.1) jitter) at volume fraction 0.1 in a cube of side 176.41 d, theta 
 H_ext = 0 (synthetic, seeded).  A timed step is one MD step (md_step) on that input, i.e. one pass of
 the whole hot path: tree build (bounding cube, Morton codes, radix sort, octree, centroids), upward
 moment pass, forward field and energy, the adjoint (dE/dr, dE/dm) by re-traversal, WCA pair and wall
-forces by a tree range query, and the Euler-Maruyama update with Philox noise (dt 1e-3, kT 1,
+forces (partners from a cell grid cut from the build's Morton codes), and the Euler-Maruyama update with
+Philox noise (dt 1e-3, kT 1,
 gamma 0.1, M 1, I 0.1), replayed from a captured HIP graph.  value = MD steps/s in FP32-mixed
 precision; field evaluations/s (tree build + field), eager MD steps/s, FP64 figures and the batched slab
 workload (32 realisations x 2^16 particles in 256 x 256 x 8, graph-replayed MD steps) are reported beside
-it.
+it, each precision and workload in the launch shape the autotuner picks for its MD steps.  The gradients
+dE/dr and dE/dm of both precisions are compared with the FP64 oracle's (computed by the CPU-baseline leg):
+relative L2, 99.9th percentile and maximum per-particle error.
 
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
 """
@@ -233,6 +236,72 @@ def accuracy(args, workloads, BarnesHut, allpairs, md_params):
         print(f"| {theta} | order {order} | {fe:.3e} | {ms:.3f} |", flush=True)
 
 
+def grad_errors(g, ref):
+    """Relative L2, 99.9th percentile and maximum of the per-particle error |g_i - ref_i| /
+    max(|ref_i|, 1e-3 rms |ref|) of a (3, n) gradient."""
+    import numpy as np
+    g = g.reshape(3, -1).cpu().numpy()
+    d = np.linalg.norm(g - ref, axis=0)
+    r = np.linalg.norm(ref, axis=0)
+    per = d / np.maximum(r, 1e-3 * np.sqrt(np.mean(r * r)))
+    return {"rel_l2": float(np.linalg.norm(g - ref) / np.linalg.norm(ref)),
+            "p999": float(np.quantile(per, 0.999)), "max": float(per.max())}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(workload_npz, theta):
+    """The FP64 oracle timed on this host's cores (oracle/timing.py, each leg a child process of its own
+    thread count; timing build of the oracle compiled here with -O3 -march=native, no contraction):
+    the force evaluation of one MD step on all threads (the baseline value), the field on one core and the
+    all-pairs field (both extrapolated from sampled targets).  Returns (cpu_baseline dict, oracle gradient)."""
+    import subprocess
+    import tempfile
+    import numpy as np
+    env = dict(os.environ, FFBH_ORACLE_NATIVE="1")
+    subprocess.run([sys.executable, "-c", "import oracle; oracle.build(force=True)"], cwd=ROOT, env=env, check=True)
+    from oracle import NATIVE_CFLAGS
+
+    def leg(name, threads=None, out=None):
+        e = dict(env) if threads is None else dict(env, OMP_NUM_THREADS=str(threads))
+        cmd = [sys.executable, "-m", "oracle.timing", workload_npz, str(theta), name] + ([out] if out else [])
+        r = subprocess.run(cmd, cwd=ROOT, env=e, check=True, capture_output=True, text=True)
+        return json.loads(r.stdout.strip().splitlines()[-1])
+
+    with tempfile.TemporaryDirectory() as td:
+        gpath = os.path.join(td, "grad.npz")
+        force = leg("force", out=gpath)
+        z = np.load(gpath)
+        ref = {"dr": z["dr"], "dm": z["dm"]}
+    one = leg("field_sample", threads=1)
+    ap = leg("allpairs_sample")
+    n = force["n"]
+    cpu = {"value": 1.0 / force["force_s"], "unit": "MD steps/s", "cores": force["threads"], "kind": "oracle",
+           "sample": f"the force evaluation of one MD step at N={n} (tree build, Barnes-Hut field and adjoint for "
+                     f"every target, FP64; the WCA forces and the integrator are not timed): one warm-up, median "
+                     f"of 3 ({force['force_s']:.2f} s)",
+           "cpu_model": cpu_model(), "nproc": os.cpu_count(), "build_flags": " ".join(NATIVE_CFLAGS),
+           "force_eval_s_samples": force["force_samples_s"], "tree_build_s": force["build_s"],
+           "one_core_field_evals_per_s": 1.0 / one["field_s_extrapolated"],
+           "one_core_sample": f"tree build + Barnes-Hut field of {one['sample_targets']} sampled targets on "
+                              f"{one['threads']} thread, extrapolated to {n} targets "
+                              f"({one['field_s_extrapolated']:.2f} s, extrapolated)",
+           "allpairs_field_evals_per_s": 1.0 / ap["field_s_extrapolated"],
+           "allpairs_sample": f"exact all-pairs field of {ap['sample_targets']} sampled targets on {ap['threads']} "
+                              f"threads, extrapolated to {n} targets ({ap['field_s_extrapolated']:.1f} s, "
+                              "extrapolated)"}
+    return cpu, ref
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -318,7 +387,7 @@ def main():
     inter = n_far + n_near
     log(f"interactions per evaluation: far {n_far}, near {n_near}")
 
-    res, H_bh = {}, {}
+    res, H_bh, grads = {}, {}, {}
     for precision in ("fp32_mixed", "fp64"):
         bh = make(precision)
         ev = HipEvents(4)
@@ -378,6 +447,9 @@ def main():
             field_only()
             t_fwd += ev.seconds(0, 1)
         assert bh.check_status() == 0
+        # the energy gradient of this precision on the benchmark state (compared with the oracle's below)
+        grads[precision] = bh.field_backward(mom, hext, gE=ones)
+        assert bh.check_status() == 0
         bh.set_raw_timing_events(None)
         H_bh[precision] = field_only()[0].clone()
         res[precision] = dict(t_step=t_step, t_step_eager=t_step_eager, t_eval=t_eval, t_fwd_kernel=t_fwd / args.steps,
@@ -413,7 +485,7 @@ def main():
     del H_ap
 
     # batched slab: 32 independent realisations of 2^16 particles, graph-replayed MD steps
-    slab = {}
+    slab, slab_tuning = {}, {}
     if not args.no_slab:
         log("generating slab workload (32 x 2^16 in 256 x 256 x 8)")
         ws = workloads.cached("slab_b32_n65536_seed1005", lambda: workloads.config5())
@@ -423,11 +495,20 @@ def main():
         srng = np.random.default_rng(2005)
         smdp = md_params(1e-3, 1.0, 0.1, 0.1, 1.0, 0.1, 1.0, 1.0, C3(*ws.box_lo), C3(*ws.box_hi),
                          shext.data_ptr(), 2005)
+        svel = torch.from_numpy(srng.standard_normal(ws.pos.shape)).to(dev)
+        som = torch.from_numpy(srng.standard_normal(ws.pos.shape) * np.sqrt(10.0)).to(dev)
         for precision in ("fp32_mixed", "fp64"):
-            sbh = BarnesHut(ws.n, ws.batch, 16, 0.5, precision)
-            sst = {"pos": sp.clone(), "vel": torch.from_numpy(srng.standard_normal(ws.pos.shape)).to(dev),
-                   "mom": sm.clone(), "omega": torch.from_numpy(srng.standard_normal(ws.pos.shape) * np.sqrt(10.0)).to(dev),
+            sst = {"pos": sp.clone(), "vel": svel.clone(), "mom": sm.clone(), "omega": som.clone(),
                    "step": torch.zeros(1, dtype=torch.int64, device=dev)}
+            if args.tuning is not None:
+                stun = tuning[precision]
+            else:
+                t = autotune(sp, sm, shext, 0.5, 16, precision, repeats=3, md=(sst, smdp))
+                stun = t["tuning_id"]
+                log(f"autotune slab {precision}: tuning {stun} "
+                    f"({', '.join(f'{k}: {v:.2f} ms' for k, v in sorted(t['times_ms'].items()))})")
+            slab_tuning[precision] = stun
+            sbh = BarnesHut(ws.n, ws.batch, 16, 0.5, precision, tuning_id=stun)
             ss = torch.cuda.Stream()
             torch.cuda.synchronize()
             sg = sbh.capture_md_graph(sst, smdp, ss)
@@ -445,11 +526,9 @@ def main():
             del sg, sbh
 
     r32 = res["fp32_mixed"]
-    # dominant kernel of the FP32-mixed step
-    # the fused kernel that the chosen launch shape runs (waves walking together, or two targets per lane)
+    # dominant kernel of the FP32-mixed step: the fused forward + adjoint walk
     tid = tuning["fp32_mixed"]
-    adj_key = {4: "k_adjoint_wg<true, 2>", 5: "k_adjoint_wg<true, 4>", 6: "k_adjoint2<true>",
-               7: "k_adjoint2<true>"}.get(tid, "k_adjoint<true, false>")
+    adj_key = "k_adjoint<true, false>"
     if r32["t_adj_kernel"] >= r32["t_fwd_kernel"]:
         kname, kt, flops = f"{adj_key} (fused forward + adjoint, tuning {tid})", r32["t_adj_kernel"], FLOPS_ADJ * inter
     else:
@@ -462,18 +541,13 @@ def main():
                 "valu_issue_frac": committed_valu_issue(adj_key) if "adjoint" in kname else None,
                 "flops_per_launch": flops, "avg_kernel_ms": kt * 1e3}
 
-    cpu = None
+    cpu, grad_err = None, None
     if not args.no_cpu_baseline:
-        import oracle
-        log("timing the FP64 CPU oracle on the same workload (tree, field and adjoint for all targets)")
-        t0 = time.perf_counter()
-        tree = oracle.Tree(w.pos, w.mom, 16)
-        tree.energy_grad(args.theta, w.hext)
-        tc = time.perf_counter() - t0
-        cpu = {"value": 1.0 / tc, "unit": "MD steps/s", "cores": oracle.num_threads(), "kind": "oracle",
-               "sample": "the force evaluation of one MD step at N=2^20 (tree build, field and adjoint for "
-                         "every target, FP64); the oracle's all-pairs WCA and integrator are not timed, "
-                         f"{tc:.1f} s wall"}
+        log("timing the FP64 CPU oracle on the same workload (force evaluation, 1-core field, all-pairs)")
+        cpu, ref = cpu_baseline(workloads.cache_file("chains_n1048576_seed1003"), args.theta)
+        grad_err = {p: {"dE/dr": grad_errors(g[0], ref["dr"]), "dE/dm": grad_errors(g[1], ref["dm"])}
+                    for p, g in grads.items()}
+        log(f"gradient error against the FP64 oracle: {grad_err}")
 
     out = {
         "metric": METRIC,
@@ -498,6 +572,7 @@ def main():
         "md_steps_per_s_fp64": 1.0 / res["fp64"]["t_step"],
         "md_steps_per_s_fp32_eager": 1.0 / r32["t_step_eager"],
         "slab_b32_n65536_md_steps_per_s": {p: 1.0 / t for p, t in slab.items()} or None,
+        "slab_tuning_id": slab_tuning or None,
         "speedup_fp32_over_fp64_step": res["fp64"]["t_step"] / r32["t_step"],
         "interactions_per_eval": inter,
         "kernel_ms": {p: {"traversal": r["t_fwd_kernel"] * 1e3, "adjoint": r["t_adj_kernel"] * 1e3}
@@ -506,6 +581,7 @@ def main():
         "allpairs_ms": ap_ms,
         "field_rel_error_vs_allpairs_fp64": ap_err,
         "roofline": roofline,
+        "grad_error_vs_oracle_fp64": grad_err,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

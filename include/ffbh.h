@@ -71,13 +71,14 @@ typedef struct bh_params {
     int32_t leaf_size;  /* maximum particles per leaf, 1..64                                          */
     double theta;       /* opening parameter, >= 0 (0 gives the all-pairs sum)                        */
     int32_t precision;  /* BH_FP64: all arithmetic FP64.  BH_FP32_MIXED: pair arithmetic in FP32 on
-                           FP64 offsets, FP64 acceptance test, FP64 cell sums and accumulation        */
+                           FP64 offsets, FP64 acceptance test, FP64 cell sums and accumulation; the
+                           walk of bh_field_backward and md_step evaluates direct pairs closer than
+                           1.25 diameters in FP64 (up to six per target)                             */
     int32_t tuning_id;  /* traversal launch shape (see bh_num_tunings); -1 = default                  */
     int32_t expansion;  /* cells of the field, its adjoint and md_step: 0 or 1 = the paper's
                            pseudo-particles (Eq. magCenter); 2 = plus each accepted cell's first moment
                            D = sum_j (r_j - c) m_j^T, the next term of the Taylor expansion of Eq. H_dip
-                           about c (beyond the paper; field error one power of theta lower).  Order 2
-                           runs the adjoint walk with independent waves whatever tuning_id asks.       */
+                           about c (beyond the paper; field error one power of theta lower)           */
 } bh_params;
 
 typedef struct bh_handle bh_handle;

@@ -21,23 +21,35 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 _CFLAGS = ["-O2", "-std=c11", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared"]
+# The timing build of the CPU baseline: the same source and the same arithmetic (no contraction, no
+# fast-math), optimised for the host it runs on; built on that host, never shipped.
+_NATIVE_LIB = os.path.join(_HERE, "liboracle_native.so")
+NATIVE_CFLAGS = ["-O3", "-march=native", "-std=c11", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+                 "-shared"]
+
+
+def _native() -> bool:
+    return os.environ.get("FFBH_ORACLE_NATIVE") == "1"
 
 
 def build(force: bool = True) -> str:
-    """Compile oracle.c into liboracle.so next to it (gcc)."""
-    if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp"
-        subprocess.run(["gcc", *_CFLAGS, _SRC, "-o", tmp, "-lm"], check=True)
-        os.replace(tmp, _LIB)
-    return _LIB
+    """Compile oracle.c into liboracle.so next to it (gcc); with FFBH_ORACLE_NATIVE=1 the timing build
+    liboracle_native.so instead."""
+    out, flags = (_NATIVE_LIB, NATIVE_CFLAGS) if _native() else (_LIB, _CFLAGS)
+    if force or not os.path.exists(out):
+        tmp = out + ".tmp"
+        subprocess.run(["gcc", *flags, _SRC, "-o", tmp, "-lm"], check=True)
+        os.replace(tmp, out)
+    return out
 
 
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        path = _NATIVE_LIB if _native() else _LIB
+        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
             build()
-        L = C.CDLL(_LIB)
+        L = C.CDLL(path)
         P = C.c_void_p
         i64 = C.c_int64
         L.or_allpairs_field.argtypes = [i64, P, P, P]

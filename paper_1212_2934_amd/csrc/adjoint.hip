@@ -50,6 +50,22 @@ __device__ inline void fused_pair(bool use, T r2, T x, T y, T z, T ax, T ay, T a
     }
 }
 
+// Contact pairs of the FP32-mixed walk.  A chain bead's two neighbours pull it with forces of about 5 (in
+// reduced units) in opposite directions, and its net force can be a thousand times smaller, so the FP32
+// rounding of those two pairs (offset and arithmetic, about 1e-6 each) would dominate its error.  Direct
+// pairs closer than 1.25 d (measured on the FP32 offset) are therefore listed per target during the walk
+// and evaluated in FP64 after it, at most kCloseMax per target (any further ones stay FP32).
+constexpr int kCloseMax = 6;
+constexpr float kClose2 = 1.5625f;  // (1.25 d)^2
+template <bool ON>
+struct CloseList {
+};
+template <>
+struct CloseList<true> {
+    uint32_t n[kWave];             // listed partners per target lane
+    int32_t k[kWave][kCloseMax];   // their sorted indices
+};
+
 // Per-wave LDS of the fused traversal (dynamic shared memory, one record per wave of the block).
 template <typename T>
 struct AdjLds {
@@ -58,6 +74,7 @@ struct AdjLds {
     T acc[kWave][6];       // direct-sum g (0..2) and field (3..5) of the current leaf, by owner lane
     T sbuf[16][6];         // member totals of the current chunk: sum g (0..2), sum T(x) a (3..5)
     int list[kWave];       // lanes that opened the current leaf
+    CloseList<std::is_same<T, float>::value> cl;  // contact pairs deferred to FP64 (FP32-mixed walk)
 };
 
 // Direct sums of one leaf (first, count) for the c listed lanes, in groups of G lanes (see the compacted
@@ -85,7 +102,19 @@ __device__ inline void adj_leaf(AdjLds<T> &W, int lane, const Src *__restrict__ 
             const T x = (T)(tg.rx - sk.x), y = (T)(tg.ry - sk.y), z = (T)(tg.rz - sk.z);
             const T r2 = norm2<T>(x, y, z);
             const bool other = tok && sok && k != tg.si;
-            const bool use = other && r2 > (T)0;
+            bool deferred = false;
+            if constexpr (std::is_same<T, float>::value) {
+                // a contact pair goes to the target's list (evaluated in FP64 after the walk) while it has room
+                if (other && r2 > (T)0 && r2 < kClose2) {
+                    const uint32_t q = __hip_atomic_fetch_add(&W.cl.n[tl], 1u, __ATOMIC_RELAXED,
+                                                              __HIP_MEMORY_SCOPE_WAVEFRONT);
+                    if (q < (uint32_t)kCloseMax) {
+                        W.cl.k[tl][q] = k;
+                        deferred = true;
+                    }
+                }
+            }
+            const bool use = other && r2 > (T)0 && !deferred;
             coincident |= other && !(r2 > (T)0);
             T qx, qy, qz, ux, uy, uz, hx = 0, hy = 0, hz = 0;
             adj_field_r2<T>(use, r2, x, y, z, ax, ay, az, mx, my, mz, qx, qy, qz, ux, uy, uz, hx, hy, hz);
@@ -124,6 +153,37 @@ __device__ inline void adj_leaf(AdjLds<T> &W, int lane, const Src *__restrict__ 
             }
         }
         wave_lds_sync();
+    }
+}
+
+// The deferred contact pairs of one target lane, in FP64: offset from the FP64 positions, pair arithmetic
+// with the FP64 upstream gradient and source moment; g and the field go to the lane's FP64 sums, the
+// member's share (g and T(x) a) to its record with FP64 atomics.  Lanes walk their own lists together.
+__device__ inline void close_pairs(AdjLds<float> &W, int lane, bool valid, int si, double rx, double ry, double rz,
+                                   const double *__restrict__ spos, const double *__restrict__ smom,
+                                   const double *__restrict__ hbar, int64_t ntot, double *__restrict__ g_rm,
+                                   double &grx, double &gry, double &grz, double &hx, double &hy, double &hz)
+{
+    wave_lds_sync();
+    const uint32_t listed = valid ? W.cl.n[lane] : 0u;
+    const int cnt = listed < (uint32_t)kCloseMax ? (int)listed : kCloseMax;
+    const double ax = valid ? hbar[si] : 0.0, ay = valid ? hbar[ntot + si] : 0.0,
+                 az = valid ? hbar[2 * ntot + si] : 0.0;
+    for (int q = 0; q < kCloseMax; ++q) {
+        const bool on = q < cnt;
+        if (ballot(on) == 0ull) break;
+        const int k = on ? W.cl.k[lane][q] : si;
+        const double x = rx - spos[k], y = ry - spos[ntot + k], z = rz - spos[2 * ntot + k];
+        const double bx = smom[k], by = smom[ntot + k], bz = smom[2 * ntot + k];
+        double gx, gy, gz, tx, ty, tz;
+        adj_field_r2<double>(on, norm2<double>(x, y, z), x, y, z, ax, ay, az, bx, by, bz, gx, gy, gz, tx, ty, tz,
+                             hx, hy, hz);
+        grx += gx; gry += gy; grz += gz;
+        if (on) {
+            double *r = g_rm + 8 * (int64_t)k;
+            atomic_add_d(r, gx); atomic_add_d(r + 1, gy); atomic_add_d(r + 2, gz);
+            atomic_add_d(r + 3, tx); atomic_add_d(r + 4, ty); atomic_add_d(r + 5, tz);
+        }
     }
 }
 
@@ -173,6 +233,7 @@ __device__ __forceinline__ void adjoint_wave(int gw, FFBH_ADJ_PARAMS)
     W.hb[lane][0] = ax; W.hb[lane][1] = ay; W.hb[lane][2] = az;
 #pragma unroll
     for (int j = 0; j < 6; ++j) W.acc[lane][j] = (T)0;
+    if constexpr (MIXED) W.cl.n[lane] = 0u;
 
     LaneStack st;
     if (parts == 1) {
@@ -285,9 +346,10 @@ __device__ __forceinline__ void adjoint_wave(int gw, FFBH_ADJ_PARAMS)
             }
         }
     }
-    if (MIXED) {
+    if constexpr (MIXED) {
         grx += (double)pgx; gry += (double)pgy; grz += (double)pgz;
         hx += (double)phx; hy += (double)phy; hz += (double)phz;
+        close_pairs(W, lane, valid, si, rx, ry, rz, spos, smom, hbar, ntot, g_rm, grx, gry, grz, hx, hy, hz);
     }
     if (ballot(coincident) != 0ull && lane == 0) set_flag(status, BH_FLAG_COINCIDENT);
     if (wave_cost && lane == 0) wave_cost[gw] = work;
@@ -334,8 +396,7 @@ __device__ __forceinline__ void adjoint_wave(int gw, FFBH_ADJ_PARAMS)
 // than at three, but spills heavily at five).
 template <bool MIXED, bool QUAD>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(MIXED && !QUAD ? 5 : 4))) void k_adjoint(
-    FFBH_ADJ_PARAMS, const uint32_t *__restrict__ order,
-                                                 uint32_t *__restrict__ work_ctr)
+    FFBH_ADJ_PARAMS, const uint32_t *__restrict__ order, uint32_t *__restrict__ work_ctr)
 {
     if (!order) {
         const int wpb = blockDim.x / kWave;
@@ -490,365 +551,6 @@ __global__ __launch_bounds__(256) void k_parts_sum(const double *__restrict__ pa
     if ((threadIdx.x & (kWave - 1)) == 0 && local < n) e_part[(int64_t)seg * wps + local / kWave] = e;
 }
 
-// Two targets per lane: a wave owns 128 consecutive targets (lane l: targets l and 64 + l of its range).
-// Each lane computes both of its targets against the node (or source) on top of the stack, adds the two
-// contributions before the wave reduction, and one atomic request per node visit or leaf source then
-// covers 128 targets.  Per-target decisions and sums are unchanged.
-template <bool MIXED>
-struct Tgt {
-    using T = typename std::conditional<MIXED, float, double>::type;
-    double rx, ry, rz;
-    T ax, ay, az;
-    double gx, gy, gz, hx, hy, hz;  // FP64 accumulation
-    T pgx, pgy, pgz, phx, phy, phz;  // partial sums since the last flush (MIXED)
-    int si;
-    bool valid;
-
-    __device__ inline void flush()
-    {
-        if (MIXED) {
-            gx += (double)pgx; gy += (double)pgy; gz += (double)pgz;
-            hx += (double)phx; hy += (double)phy; hz += (double)phz;
-            pgx = pgy = pgz = phx = phy = phz = (T)0;
-        }
-    }
-    // one pair against source (or cell) moment b at offset x: accumulates, returns g and T(x) a
-    __device__ inline void pair(bool use, T x, T y, T z, T bx, T by, T bz, T &qx, T &qy, T &qz, T &ux, T &uy, T &uz)
-    {
-        fused_pair<MIXED, T>(use, norm2<T>(x, y, z), x, y, z, ax, ay, az, bx, by, bz, qx, qy, qz, ux, uy, uz, pgx,
-                             pgy, pgz, phx, phy, phz, gx, gy, gz, hx, hy, hz);
-    }
-};
-
-template <bool MIXED>
-__device__ inline void tgt_init(Tgt<MIXED> &t, const double *spos, const double *hbar, int64_t ntot, int64_t n,
-                                int seg, int local)
-{
-    using T = typename Tgt<MIXED>::T;
-    t.valid = local < n;
-    t.si = (int)(seg * n) + (t.valid ? local : 0);
-    t.rx = spos[t.si]; t.ry = spos[ntot + t.si]; t.rz = spos[2 * ntot + t.si];
-    t.ax = t.valid ? (T)hbar[t.si] : (T)0;
-    t.ay = t.valid ? (T)hbar[ntot + t.si] : (T)0;
-    t.az = t.valid ? (T)hbar[2 * ntot + t.si] : (T)0;
-    t.gx = t.gy = t.gz = t.hx = t.hy = t.hz = 0.0;
-    t.pgx = t.pgy = t.pgz = t.phx = t.phy = t.phz = (T)0;
-}
-
-template <bool MIXED>
-__device__ inline void tgt_finish(Tgt<MIXED> &t, const double *smom, const double *hext, const uint32_t *perm,
-                                  double *g_gather, double *Hs, double *Hout, int64_t ntot, int64_t n, int seg,
-                                  double &e)
-{
-    t.flush();
-    if (!t.valid) return;
-    const double mx = smom[t.si], my = smom[ntot + t.si], mz = smom[2 * ntot + t.si];
-    e += -0.5 * (mx * t.hx + my * t.hy + mz * t.hz);
-    if (hext) e -= mx * hext[3 * seg] + my * hext[3 * seg + 1] + mz * hext[3 * seg + 2];
-    g_gather[t.si] = t.gx;
-    g_gather[ntot + t.si] = t.gy;
-    g_gather[2 * ntot + t.si] = t.gz;
-    Hs[t.si] = t.hx;
-    Hs[ntot + t.si] = t.hy;
-    Hs[2 * ntot + t.si] = t.hz;
-    const int64_t i = (int64_t)perm[t.si] - (int64_t)seg * n;
-    if (Hout && i >= 0 && i < n) {
-        double *out = Hout + (int64_t)seg * 3 * n;
-        out[i] = t.hx;
-        out[n + i] = t.hy;
-        out[2 * n + i] = t.hz;
-    }
-}
-
-template <bool MIXED>
-__global__ __launch_bounds__(256) void k_adjoint2(
-    const NodeRec *__restrict__ nodes, const double *__restrict__ node_m64, const double *__restrict__ spos,
-    const double *__restrict__ smom, const void *__restrict__ src, const double *__restrict__ hbar,
-    const uint32_t *__restrict__ perm, const double *__restrict__ hext, double *__restrict__ g_gather,
-    double *__restrict__ g_rm, double *__restrict__ node_adj, double *__restrict__ Hs,
-    double *__restrict__ Hout, double *__restrict__ e_part, uint32_t *__restrict__ status, int64_t n, int64_t ntot,
-    int waves_per_seg, int num_waves, double theta2, int max_nodes)
-{
-    using T = typename std::conditional<MIXED, float, double>::type;
-    using Src = typename std::conditional<MIXED, Src32, Src64>::type;
-    const Src *__restrict__ sr = (const Src *)src;
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wcomp = total6_comp(lane);
-    const int wpb = blockDim.x / kWave;
-    const int gw = xcd_block(blockIdx.x, gridDim.x) * wpb + (int)(threadIdx.x / kWave);
-    if (gw >= num_waves) return;  // whole waves; num_waves counts waves of 128 targets
-    const int seg = gw / waves_per_seg;
-    const int base = (gw - seg * waves_per_seg) * 2 * kWave;
-    Tgt<MIXED> ta, tb;
-    tgt_init<MIXED>(ta, spos, hbar, ntot, n, seg, base + lane);
-    tgt_init<MIXED>(tb, spos, hbar, ntot, n, seg, base + kWave + lane);
-    bool coincident = false;
-
-    LaneStack2 st{0, 0, 0, 0, 0, 0};
-    st.push(lane, seg, 1, ballot(ta.valid), ballot(tb.valid));
-    int guard = max_nodes;
-    while (st.sp > 0) {
-        uint64_t ma, mb;
-        const int cur = st.pop(lane, ma, mb);
-        if (--guard < 0 || (unsigned)cur >= (unsigned)max_nodes) {
-            if (lane == 0) set_flag(status, BH_FLAG_TREE);
-            break;
-        }
-        const NodeRec nd = nodes[cur];
-        if (nd.first < 0 || nd.count < 1 || (uint32_t)nd.first + (uint32_t)nd.count > (uint32_t)ntot) {
-            if (lane == 0) set_flag(status, BH_FLAG_TREE);
-            break;
-        }
-        const bool act_a = lane_in(ma), act_b = lane_in(mb);
-        const double dxa = ta.rx - nd.cx, dya = ta.ry - nd.cy, dza = ta.rz - nd.cz;
-        const double dxb = tb.rx - nd.cx, dyb = tb.ry - nd.cy, dzb = tb.rz - nd.cz;
-        const bool acc_a = act_a && (unsigned)(ta.si - nd.first) >= (unsigned)nd.count &&
-                           nd.s2 < theta2 * __builtin_fma(dza, dza, __builtin_fma(dya, dya, dxa * dxa));
-        const bool acc_b = act_b && (unsigned)(tb.si - nd.first) >= (unsigned)nd.count &&
-                           nd.s2 < theta2 * __builtin_fma(dzb, dzb, __builtin_fma(dyb, dyb, dxb * dxb));
-        const uint64_t acca = ballot(acc_a), accb = ballot(acc_b);
-        if ((acca | accb) != 0ull) {
-            T bx, by, bz;
-            if (MIXED) {
-                bx = (T)nd.mx; by = (T)nd.my; bz = (T)nd.mz;
-            } else {
-                const double *m = node_m64 + 4 * (int64_t)cur;
-                bx = (T)m[0]; by = (T)m[1]; bz = (T)m[2];
-            }
-            T s0 = 0, s1 = 0, s2v = 0, s3 = 0, s4 = 0, s5 = 0;  // this lane's scatter values, both targets
-            if (acca) {
-                T gx, gy, gz, tx, ty, tz;
-                ta.pair(acc_a, (T)dxa, (T)dya, (T)dza, bx, by, bz, gx, gy, gz, tx, ty, tz);
-                s0 += tx; s1 += ty; s2v += tz;
-                s3 += gx; s4 += gy; s5 += gz;
-            }
-            if (accb) {
-                T gx, gy, gz, tx, ty, tz;
-                tb.pair(acc_b, (T)dxb, (T)dyb, (T)dzb, bx, by, bz, gx, gy, gz, tx, ty, tz);
-                s0 += tx; s1 += ty; s2v += tz;
-                s3 += gx; s4 += gy; s5 += gz;
-            }
-            // A_C += T(x) Hbar, S_C += g, over the accepting targets of the wave
-            scatter6<T>(acca | accb, lane, wcomp, node_adj + 8 * (int64_t)cur, s0, s1, s2v, s3, s4, s5);
-        }
-        const uint64_t opa = ballot(act_a && !acc_a), opb = ballot(act_b && !acc_b);
-        if ((opa | opb) == 0ull) continue;
-        if (nd.nchild != 0) {
-            if (st.sp >= kStackMax) {
-                if (lane == 0) set_flag(status, BH_FLAG_STACK);
-                break;
-            }
-            st.push(lane, nd.child, nd.nchild, opa, opb);
-            continue;
-        }
-        const bool me_a = lane_in(opa), me_b = lane_in(opb);
-        const Src *q = sr + nd.first;
-        for (int k = nd.first; k < nd.first + nd.count; ++k, ++q) {
-            const Src sk = *q;
-            const T xa = (T)(ta.rx - sk.x), ya = (T)(ta.ry - sk.y), za = (T)(ta.rz - sk.z);
-            const T xb = (T)(tb.rx - sk.x), yb = (T)(tb.ry - sk.y), zb = (T)(tb.rz - sk.z);
-            const T r2a = xa * xa + ya * ya + za * za, r2b = xb * xb + yb * yb + zb * zb;
-            const bool oa = me_a && k != ta.si, ob = me_b && k != tb.si;
-            const bool ua = oa && r2a > (T)0, ub = ob && r2b > (T)0;
-            coincident |= (oa && !(r2a > (T)0)) || (ob && !(r2b > (T)0));
-            const uint64_t usa = ballot(ua), usb = ballot(ub);
-            if ((usa | usb) == 0ull) continue;
-            T s0 = 0, s1 = 0, s2v = 0, s3 = 0, s4 = 0, s5 = 0;
-            if (usa) {
-                T qx, qy, qz, ux, uy, uz;
-                ta.pair(ua, xa, ya, za, (T)sk.mx, (T)sk.my, (T)sk.mz, qx, qy, qz, ux, uy, uz);
-                s0 += qx; s1 += qy; s2v += qz;
-                s3 += ux; s4 += uy; s5 += uz;
-            }
-            if (usb) {
-                T qx, qy, qz, ux, uy, uz;
-                tb.pair(ub, xb, yb, zb, (T)sk.mx, (T)sk.my, (T)sk.mz, qx, qy, qz, ux, uy, uz);
-                s0 += qx; s1 += qy; s2v += qz;
-                s3 += ux; s4 += uy; s5 += uz;
-            }
-            // sum g (subtracted from dL/dr_k downstream), dL/dm_k += sum T(x) Hbar over the wave's targets
-            scatter6<T>(usa | usb, lane, wcomp, g_rm + 8 * (int64_t)k, s0, s1, s2v, s3, s4, s5);
-        }
-        ta.flush();
-        tb.flush();
-    }
-    if (ballot(coincident) != 0ull && lane == 0) set_flag(status, BH_FLAG_COINCIDENT);
-    double e = 0.0;
-    tgt_finish<MIXED>(ta, smom, hext, perm, g_gather, Hs, Hout, ntot, n, seg, e);
-    tgt_finish<MIXED>(tb, smom, hext, perm, g_gather, Hs, Hout, ntot, n, seg, e);
-    e = wave_sum(e);
-    if (lane == 0) e_part[gw] = e;
-}
-
-// Workgroup-cooperative variant: NW waves (NW*64 consecutive targets of one system) walk the union of
-// their traversals in lock-step, one barrier per node visit.  Each wave reduces its lanes' scatter
-// values with DPP; the NW wave partials meet in LDS and one set of atomics per node (and per source of a
-// leaf) is issued for the whole workgroup instead of one per wave.  Every wave keeps its own lane stack;
-// the stacks stay identical because push and pop decisions use the workgroup-wide "any lane opened"
-// flag.  Per-lane decisions, and therefore every lane's sum, are those of the definition.
-template <bool MIXED, int NW>
-__global__ __launch_bounds__(NW * 64) void k_adjoint_wg(
-    const NodeRec *__restrict__ nodes, const double *__restrict__ node_m64, const double *__restrict__ spos,
-    const double *__restrict__ smom, const void *__restrict__ src, const double *__restrict__ hbar,
-    const uint32_t *__restrict__ perm, const double *__restrict__ hext, double *__restrict__ g_gather,
-    double *__restrict__ g_rm, double *__restrict__ node_adj, double *__restrict__ Hs,
-    double *__restrict__ Hout, double *__restrict__ e_part, uint32_t *__restrict__ status, int64_t n, int64_t ntot,
-    int waves_per_seg, int blocks_per_seg, double theta2, int max_nodes)
-{
-    using T = typename std::conditional<MIXED, float, double>::type;
-    using Src = typename std::conditional<MIXED, Src32, Src64>::type;
-    __shared__ T fpart[2][NW][6];      // far-node partials per wave, double-buffered by visit parity
-    __shared__ uint32_t flags[2][NW];  // bit 0: some lane of the wave opened the node; bit 1: accepted
-    __shared__ T lpart[NW][64][6];     // leaf source partials per wave (one chunk of up to 64 sources)
-    const Src *__restrict__ sr = (const Src *)src;
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wcomp = total6_comp(lane);
-    const int wv = (int)(threadIdx.x / kWave);
-    const int blk = xcd_block(blockIdx.x, gridDim.x);
-    const int seg = blk / blocks_per_seg;
-    const int wseg = (blk - seg * blocks_per_seg) * NW + wv;  // wave index within the system
-    const int local = wseg * kWave + lane;
-    const bool valid = wseg < waves_per_seg && local < n;
-    const int si = (int)(seg * n) + (valid ? local : 0);
-    const double rx = spos[si], ry = spos[ntot + si], rz = spos[2 * ntot + si];
-    const T ax = valid ? (T)hbar[si] : (T)0, ay = valid ? (T)hbar[ntot + si] : (T)0,
-            az = valid ? (T)hbar[2 * ntot + si] : (T)0;
-
-    double grx = 0.0, gry = 0.0, grz = 0.0, hx = 0.0, hy = 0.0, hz = 0.0;
-    T pgx = 0, pgy = 0, pgz = 0, phx = 0, phy = 0, phz = 0;
-    bool coincident = false;
-
-    LaneStack st;
-    st.init(seg, 1, ballot(valid));  // every wave starts at the root, even with no valid lane
-    int guard = max_nodes;
-    int par = 0;
-    bool broken = false;
-    while (st.more()) {
-        uint64_t mask;
-        const int cur = st.pop(mask);
-        if (--guard < 0 || (unsigned)cur >= (unsigned)max_nodes) {  // identical in every wave
-            broken = true;
-            break;
-        }
-        const NodeRec nd = nodes[cur];
-        if (nd.first < 0 || nd.count < 1 || (uint32_t)nd.first + (uint32_t)nd.count > (uint32_t)ntot) {
-            broken = true;
-            break;
-        }
-        // masks of the lanes that take part, of the targets inside the node and of the acceptance test
-        const uint64_t insm = ballot((unsigned)(si - nd.first) < (unsigned)nd.count);
-        const double dx = rx - nd.cx, dy = ry - nd.cy, dz = rz - nd.cz;
-        const double d2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
-        const uint64_t accm = mask & ~insm & ballot(nd.s2 < theta2 * d2);
-        const bool acc = lane_in(accm);
-        T vs = 0;
-        if (accm != 0ull) {
-            T bx, by, bz;
-            if (MIXED) {
-                bx = (T)nd.mx; by = (T)nd.my; bz = (T)nd.mz;
-            } else {
-                const double *m = node_m64 + 4 * (int64_t)cur;
-                bx = (T)m[0]; by = (T)m[1]; bz = (T)m[2];
-            }
-            T gx, gy, gz, tx, ty, tz;
-            fused_pair<MIXED, T>(acc, (T)d2, (T)dx, (T)dy, (T)dz, ax, ay, az, bx, by, bz, gx, gy, gz, tx, ty, tz,
-                                 pgx, pgy, pgz, phx, phy, phz, grx, gry, grz, hx, hy, hz);
-            vs = wave_total6<T>(lane, tx, ty, tz, gx, gy, gz);
-        }
-        const uint64_t open = mask & ~accm;
-        if (wcomp >= 0) fpart[par][wv][wcomp] = vs;
-        if (lane == 0) flags[par][wv] = (open != 0ull ? 1u : 0u) | (accm != 0ull ? 2u : 0u);
-        __syncthreads();
-        uint32_t any = 0u;
-#pragma unroll
-        for (int w = 0; w < NW; ++w) any |= flags[par][w];
-        if ((any & 2u) && wv == 0 && lane < 6) {
-            T sum = 0;
-#pragma unroll
-            for (int w = 0; w < NW; ++w) sum += fpart[par][w][lane];
-            atomic_add_d(node_adj + 8 * (int64_t)cur + lane, (double)sum);
-        }
-        par ^= 1;
-        if (!(any & 1u)) continue;
-        if (nd.nchild != 0) {
-            if (st.sp >= kStackMax) {
-                broken = true;
-                break;
-            }
-            st.push(lane, nd.child, nd.nchild, open);  // with this wave's mask, possibly empty
-            continue;
-        }
-        // leaf: sources in chunks of 64; per chunk every wave writes its per-source partials, then the
-        // workgroup adds them and issues one atomic per (source, component)
-        const bool me = lane_in(open);
-        for (int c0 = 0; c0 < nd.count; c0 += 64) {
-            const int cn = min(64, nd.count - c0);
-            const Src *q = sr + nd.first + c0;
-            for (int j = 0; j < cn; ++j, ++q) {
-                const int k = nd.first + c0 + j;
-                const Src sk = *q;
-                const T x = (T)(rx - sk.x), y = (T)(ry - sk.y), z = (T)(rz - sk.z);
-                const T r2 = norm2<T>(x, y, z);
-                const bool other = me && k != si;
-                const bool use = other && r2 > (T)0;
-                coincident |= other && !(r2 > (T)0);
-                T ws = 0;
-                if (ballot(use) != 0ull) {
-                    T qx, qy, qz, ux, uy, uz;
-                    fused_pair<MIXED, T>(use, r2, x, y, z, ax, ay, az, (T)sk.mx, (T)sk.my, (T)sk.mz, qx, qy, qz, ux,
-                                         uy, uz, pgx, pgy, pgz, phx, phy, phz, grx, gry, grz, hx, hy, hz);
-                    ws = wave_total6<T>(lane, qx, qy, qz, ux, uy, uz);
-                }
-                if (wcomp >= 0) lpart[wv][j][wcomp] = ws;
-            }
-            __syncthreads();
-            for (int p = threadIdx.x; p < cn * 6; p += NW * 64) {
-                const int j = p / 6, comp = p - 6 * j;
-                T sum = 0;
-#pragma unroll
-                for (int w = 0; w < NW; ++w) sum += lpart[w][j][comp];
-                if (sum != (T)0) atomic_add_d(g_rm + 8 * (int64_t)(nd.first + c0 + j) + comp, (double)sum);
-            }
-            __syncthreads();  // lpart is rewritten by the next chunk
-        }
-        if (MIXED) {
-            grx += (double)pgx; gry += (double)pgy; grz += (double)pgz;
-            hx += (double)phx; hy += (double)phy; hz += (double)phz;
-            pgx = pgy = pgz = phx = phy = phz = (T)0;
-        }
-    }
-    if (broken && threadIdx.x == 0) set_flag(status, BH_FLAG_TREE);
-    if (MIXED) {
-        grx += (double)pgx; gry += (double)pgy; grz += (double)pgz;
-        hx += (double)phx; hy += (double)phy; hz += (double)phz;
-    }
-    if (ballot(coincident) != 0ull && lane == 0) set_flag(status, BH_FLAG_COINCIDENT);
-
-    double e = 0.0;
-    if (valid) {
-        const double mx = smom[si], my = smom[ntot + si], mz = smom[2 * ntot + si];
-        e = -0.5 * (mx * hx + my * hy + mz * hz);
-        if (hext) e -= mx * hext[3 * seg] + my * hext[3 * seg + 1] + mz * hext[3 * seg + 2];
-    }
-    e = wave_sum(e);
-    if (lane == 0 && wseg < waves_per_seg) e_part[(int64_t)seg * waves_per_seg + wseg] = e;
-    if (valid) {
-        g_gather[si] = grx;
-        g_gather[ntot + si] = gry;
-        g_gather[2 * ntot + si] = grz;
-        Hs[si] = hx;
-        Hs[ntot + si] = hy;
-        Hs[2 * ntot + si] = hz;
-        const int64_t i = (int64_t)perm[si] - (int64_t)seg * n;
-        if (Hout && i >= 0 && i < n) {
-            double *out = Hout + (int64_t)seg * 3 * n;
-            out[i] = hx;
-            out[n + i] = hy;
-            out[2 * n + i] = hz;
-        }
-    }
-}
-
 // Upstream field gradient in sorted order: Hbar = gH - 1/2 gE m.
 __global__ __launch_bounds__(256) void k_hbar(const double *__restrict__ gH, const double *__restrict__ gE,
                                               const double *__restrict__ smom, const uint32_t *__restrict__ perm,
@@ -964,13 +666,7 @@ static int adjoint_items(const Handle &h)
     return (int)(h.L.B * wps * h.adj_parts);
 }
 
-bool uses_wave_order(const Handle &h)
-{
-    // order-2 cells take the independent-wave walk whatever the cooperative or two-target setting
-    const bool quad = h.L.expansion == 2;
-    const bool independent = quad || (h.adj_coop == 1 && !h.adj_two);
-    return independent && h.adj_sched && h.adj_parts == 1;
-}
+bool uses_wave_order(const Handle &h) { return h.adj_sched && h.adj_parts == 1; }
 
 void launch_order_waves(Handle &h, hipStream_t s)
 {
@@ -998,39 +694,10 @@ hipError_t launch_backward(Handle &h, const double *d_mom, const double *d_hext,
                            w.status + 2, L.max_nodes);
     hipLaunchKernelGGL(k_zero, dim3(grid_for(8 * L.ntot, 256, 4096)), dim3(256), 0, s, w.g_rm, 8 * L.ntot);
     const int wpb = h.waves_per_block;
-    const int waves_per_seg = (int)((L.n + kWave - 1) / kWave);
     const double theta2 = h.p.theta * h.p.theta;
     if (h.ev[2]) (void)hipEventRecord(h.ev[2], s);
     const bool mixed = h.p.precision == BH_FP32_MIXED;
-    // order-2 cells run the independent-wave walk whatever the shape's cooperative or two-target setting
-    const int nw = quad ? 1 : h.adj_coop;
-    if (nw > 1) {
-        const int bps = (waves_per_seg + nw - 1) / nw;
-        const unsigned gblocks = (unsigned)(L.B * bps);
-#define FFBH_WG(MX, NWV)                                                                                       \
-    hipLaunchKernelGGL((k_adjoint_wg<MX, NWV>), dim3(gblocks), dim3(NWV * kWave), 0, s, w.nodes, w.node_m64,  \
-                       w.spos, w.smom, MX ? w.src32 : w.src64, w.hbar, w.perm, d_hext, w.g_gather, w.g_rm,      \
-                       w.node_adj, w.Hs, d_H, w.e_part, w.status, L.n, L.ntot, waves_per_seg, bps, theta2,         \
-                       (int)L.max_nodes)
-        if (mixed && nw == 2) FFBH_WG(true, 2);
-        else if (mixed) FFBH_WG(true, 4);
-        else if (nw == 2) FFBH_WG(false, 2);
-        else FFBH_WG(false, 4);
-#undef FFBH_WG
-    } else if (h.adj_two && !quad) {
-        // waves of 128 targets; the energy partials are indexed by these waves
-        const int wps2 = (int)((L.n + 2 * kWave - 1) / (2 * kWave));
-        const int nw2 = (int)(L.B * wps2);
-        const unsigned blocks2 = (unsigned)((nw2 + wpb - 1) / wpb);
-        if (mixed)
-            hipLaunchKernelGGL(k_adjoint2<true>, dim3(blocks2), dim3(wpb * kWave), 0, s, w.nodes, w.node_m64, w.spos,
-                               w.smom, w.src32, w.hbar, w.perm, d_hext, w.g_gather, w.g_rm, w.node_adj, w.Hs, d_H,
-                               w.e_part, w.status, L.n, L.ntot, wps2, nw2, theta2, (int)L.max_nodes);
-        else
-            hipLaunchKernelGGL(k_adjoint2<false>, dim3(blocks2), dim3(wpb * kWave), 0, s, w.nodes, w.node_m64, w.spos,
-                               w.smom, w.src64, w.hbar, w.perm, d_hext, w.g_gather, w.g_rm, w.node_adj, w.Hs, d_H,
-                               w.e_part, w.status, L.n, L.ntot, wps2, nw2, theta2, (int)L.max_nodes);
-    } else {
+    {
         const int tpw = h.adj_tpw, parts = h.adj_parts;
         const int wps = (int)((L.n + tpw - 1) / tpw);
         const int nwv = adjoint_items(h);
@@ -1059,7 +726,7 @@ hipError_t launch_backward(Handle &h, const double *d_mom, const double *d_hext,
     }
     if (h.ev[3]) (void)hipEventRecord(h.ev[3], s);
     if (d_E)
-        launch_energy_final(h, d_E, s, nw > 1 || h.adj_parts > 1 ? kWave : h.adj_two ? 2 * kWave : h.adj_tpw);
+        launch_energy_final(h, d_E, s, h.adj_parts > 1 ? kWave : h.adj_tpw);
     hipLaunchKernelGGL(k_downward, dim3(grid_for(L.ntot, 256)), dim3(256), 0, s, w.nodes, w.leaf_of, w.node_adj,
                        w.g_gather, w.g_rm, w.Hs, d_hext, d_gE, w.perm, L.n, L.ntot, d_dpos, d_dmom,
                        L.max_nodes, quad ? w.node_adjq : nullptr, w.node_m64, w.spos, w.smom);

@@ -7,21 +7,16 @@ namespace ffbh {
 
 static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
-// Traversal launch shapes selectable by tuning_id: waves per workgroup of the independent-wave
-// traversals, how many waves walk the adjoint traversal together (1 = independently), whether adjoint
-// waves own two targets per lane, and how many targets an independent adjoint wave owns (fewer than 64
-// gives small systems more walks in flight).
-static const int kTuneWaves[] = {4, 1, 2, 8, 4, 4, 4, 2, 4, 4, 4, 4, 4, 2, 4, 1};
-static const int kTuneCoop[] = {1, 1, 1, 1, 2, 4, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1};
-static const int kTuneTwo[] = {0, 0, 0, 0, 0, 0, 1, 1, 0, 0, 0, 0, 0, 0, 0, 0};
-static const int kTuneTpw[] = {64, 64, 64, 64, 64, 64, 64, 64, 32, 16, 64, 32, 16, 64, 64, 64};
-// independent adjoint waves split each walk over the root's children (8 parts) or not (1)
-static const int kTuneParts[] = {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 8, 8, 8, 1, 1, 1};
-// independent adjoint waves in one persistent launch, heaviest items of the previous launch first
-static const int kTuneSched[] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 1};
+// Traversal launch shapes selectable by tuning_id: waves per workgroup of the traversals, how many
+// targets an adjoint wave owns (fewer than 64 gives small systems more walks in flight), whether each
+// adjoint walk is split over the root's children (8 parts) or not (1), and whether the adjoint waves run in
+// one persistent launch that orders its items by the previous launch's costs.
+static const int kTuneWaves[] = {4, 1, 2, 8, 4, 4, 4, 4, 4, 2, 4, 1};
+static const int kTuneTpw[] = {64, 64, 64, 64, 32, 16, 64, 32, 16, 64, 64, 64};
+static const int kTuneParts[] = {1, 1, 1, 1, 1, 1, 8, 8, 8, 1, 1, 1};
+static const int kTuneSched[] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 1};
 static const int kNumTunings = (int)(sizeof(kTuneWaves) / sizeof(kTuneWaves[0]));
-static_assert(sizeof(kTuneCoop) == sizeof(kTuneWaves) && sizeof(kTuneTwo) == sizeof(kTuneWaves) &&
-                  sizeof(kTuneTpw) == sizeof(kTuneWaves) && sizeof(kTuneParts) == sizeof(kTuneWaves) &&
+static_assert(sizeof(kTuneTpw) == sizeof(kTuneWaves) && sizeof(kTuneParts) == sizeof(kTuneWaves) &&
                   sizeof(kTuneSched) == sizeof(kTuneWaves),
               "one entry per tuning in every table");
 
@@ -247,8 +242,6 @@ bh_status bh_create(const bh_params *p, void *d_workspace, size_t workspace_byte
     }
     h.built = 0;
     h.waves_per_block = kTuneWaves[p->tuning_id < 0 ? 0 : p->tuning_id];
-    h.adj_coop = kTuneCoop[p->tuning_id < 0 ? 0 : p->tuning_id];
-    h.adj_two = kTuneTwo[p->tuning_id < 0 ? 0 : p->tuning_id];
     h.adj_tpw = kTuneTpw[p->tuning_id < 0 ? 0 : p->tuning_id];
     h.adj_parts = kTuneParts[p->tuning_id < 0 ? 0 : p->tuning_id];
     h.adj_sched = kTuneSched[p->tuning_id < 0 ? 0 : p->tuning_id];

@@ -113,8 +113,6 @@ struct Handle {
     int device;
     int built;           // a bh_build has been enqueued
     int waves_per_block; // traversal launch shape
-    int adj_coop;        // waves walking the adjoint traversal together (1: independent waves)
-    int adj_two;         // adjoint waves own two targets per lane
     int adj_tpw;         // targets per independent adjoint wave (16, 32 or 64)
     int adj_parts;       // independent adjoint walks split over the root's children (8) or not (1)
     int adj_sched;       // independent adjoint waves in one persistent, cost-ordered launch

@@ -7,8 +7,9 @@
 // Readings: the paper writes the rotation in polar angles (with the theta/phi equations garbled); the
 // vector form used here is m' = R(omega dt) m with I domega/dt = m x H_eff - gamma_r omega + noise,
 // H_eff = -dE/dm.  Noise per Cartesian component has variance 2 gamma kT dt (fluctuation-dissipation).
-// The paper's "Lennard-Jones" term is replaced by its purely repulsive WCA part (cut at 2^(1/6) sigma,
-// shifted to zero there), walls act on the centre-to-face distance with sigma_w = sigma / 2.
+// Short range (sr_kind): 0, the purely repulsive WCA potential (cut at 2^(1/6) sigma, shifted to zero
+// there); 1, the paper's "Lennard-Jones" law as printed (Eq. LJ).  Walls of the same law act on the
+// centre-to-face distance with sigma_w = sigma / 2.
 // Thermal noise: Philox4x32-10 (Salmon et al., SC'11) keyed by (seed, system), counter (step, particle,
 // draw), mapped to normals by the Box-Muller transform.
 #include "traverse.h"
@@ -57,7 +58,7 @@ __device__ inline void box_muller(uint32_t a, uint32_t b, double &n0, double &n1
     n1 = r * sin(t);
 }
 
-// ---- WCA short-range forces (tree range query) --------------------------------------------------------
+// ---- short-range forces (partners from a cell grid cut from the Morton codes) -----------------------------
 
 // Force on a particle at offset x = r_i - r_k from a short-range partner, 24 eps [c12 (s/r)^12 - (s/r)^6] x / r^2
 // for r < rc: c12 = 2 is the WCA repulsion, c12 = 1 the paper's form (Eq. LJ).

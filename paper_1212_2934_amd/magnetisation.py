@@ -36,9 +36,26 @@ def langevin(alpha: float) -> float:
     return 1.0 / math.tanh(alpha) - 1.0 / alpha
 
 
+FLAG_NAMES = {1: "NONFINITE", 2: "COINCIDENT", 4: "DEEP_LEAF", 8: "STACK", 16: "TREE"}
+
+
+def flag_names(bits: int) -> str:
+    """The status bits of bh_check_status by name ("0" when clear)."""
+    if bits == 0:
+        return "0"
+    return "|".join(v for k, v in FLAG_NAMES.items() if bits & k) + f" (0x{bits:x})"
+
+
 def run_point(alpha, n=1000, batch=64, phi=0.01, lam=0.28, steps_eq=3000, steps_avg=2000, every=50,
-              field_every=500, theta=0.5, precision="fp32_mixed", seed=7, dt=1e-3, gamma=0.1):
-    """One point of the magnetisation curve; returns a dict of averages."""
+              field_every=500, theta=0.5, precision="fp32_mixed", seed=7, dt=1e-3, gamma=0.1, check_every=0,
+              dump=None):
+    """One point of the magnetisation curve; returns a dict of averages.
+
+    check_every > 0: read the status word after every check_every steps of the equilibration and stop the
+    run at the first window that raised a flag; the window is then replayed one eager step at a time from
+    a copy of its starting state to find the first flagged step, whose starting state and those of the three
+    steps before it are written to `dump` (an .npz, if given; key suffix _0 for the flagged step, _1 for the
+    one before, ...) and whose number and bits are returned (the averages are then absent)."""
     kT = 2.0 / lam
     side = (n * math.pi / 6.0 / phi) ** (1.0 / 3.0)
     rng = np.random.default_rng(seed)
@@ -60,6 +77,10 @@ def run_point(alpha, n=1000, batch=64, phi=0.01, lam=0.28, steps_eq=3000, steps_
     stream = torch.cuda.Stream()
     torch.cuda.synchronize()
     graph = sim.capture_md_graph(st, mdp, stream)
+    if check_every > 0:
+        return _first_flag(st, mdp, graph, stream, sim, n, batch, theta, precision, steps_eq, check_every,
+                           dump, dict(alpha=alpha, n=n, batch=batch, phi=phi, kT=kT, dt=dt, gamma=gamma,
+                                      side=side, seed=seed))
     for _ in range(steps_eq):
         graph.launch(stream)
     uz, hz_bh, hz_ap, rel = [], [], [], []
@@ -91,6 +112,38 @@ def run_point(alpha, n=1000, batch=64, phi=0.01, lam=0.28, steps_eq=3000, steps_
             "steps_eq": steps_eq, "steps_avg": steps_avg, "dt": dt, "gamma": gamma}
 
 
+def _first_flag(st, mdp, graph, stream, sim, n, batch, theta, precision, steps, check_every, dump, info):
+    done = 0
+    while done < steps:
+        saved = {k: v.clone() for k, v in st.items()}
+        k = min(check_every, steps - done)
+        for _ in range(k):
+            graph.launch(stream)
+        stream.synchronize()
+        with torch.cuda.stream(stream):
+            bits = sim.check_status()
+        if bits:
+            # replay the window eagerly from its start (same step counter, so the same noise)
+            for key in st:
+                st[key].copy_(saved[key])
+            eager = BarnesHut(n, batch, 16, theta, precision)
+            history = []  # states at the start of the last few steps
+            for j in range(k):
+                history = (history + [{key: v.clone() for key, v in st.items()}])[-4:]
+                eager.md_step(st, mdp)
+                b = eager.check_status()
+                if b:
+                    if dump:
+                        # the states at the start of the flagged step and of the three before it
+                        out = {f"{key}_{m}": v.cpu().numpy() for m, h in enumerate(reversed(history))
+                               for key, v in h.items()}
+                        np.savez(dump, **out, **{f"info_{a}": np.asarray(v) for a, v in info.items()})
+                    return dict(info, first_flag_step=done + j, bits=b, bits_window=bits)
+            return dict(info, first_flag_step=None, bits=0, bits_window=bits, note="eager replay raised no flag")
+        done += k
+    return dict(info, first_flag_step=None, bits=0, bits_window=0)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--alphas", type=float, nargs="+", default=[0.5, 1.0, 2.0, 4.0, 8.0])
@@ -103,7 +156,18 @@ def main():
     ap.add_argument("--precision", default="fp32_mixed")
     ap.add_argument("--dt", type=float, default=1e-3)
     ap.add_argument("--gamma", type=float, default=0.1, help="translational and rotational friction")
+    ap.add_argument("--check-every", type=int, default=0,
+                    help="find the first flagged step of the equilibration (status read every K steps)")
+    ap.add_argument("--dump", default=None, help="with --check-every: .npz of the state before that step")
     a = ap.parse_args()
+    if a.check_every > 0:
+        for alpha in a.alphas:
+            r = run_point(alpha, n=a.n, batch=a.batch, phi=a.phi, lam=a.lam, steps_eq=a.steps_eq,
+                          precision=a.precision, dt=a.dt, gamma=a.gamma, check_every=a.check_every,
+                          dump=a.dump)
+            print(f"alpha {alpha:g}, dt {a.dt:g}, gamma {a.gamma:g}: first flagged step {r['first_flag_step']}, "
+                  f"bits {flag_names(r['bits'])} (window {flag_names(r['bits_window'])})", flush=True)
+        return
     print(f"dt {a.dt:g}, gamma {a.gamma:g}, N {a.n}, {a.batch} realisations, phi {a.phi:g}, lambda {a.lam:g}, "
           f"{a.steps_eq} + {a.steps_avg} steps")
     print()
@@ -115,7 +179,8 @@ def main():
                       steps_avg=a.steps_avg, precision=a.precision, dt=a.dt, gamma=a.gamma,
                       every=max(1, a.steps_avg // 40), field_every=max(1, a.steps_avg // 4))
         print(f"| {alpha:g} | {r['langevin']:.4f} | {r['uz']:.4f} | {r['uz_sem']:.4f} | {r['hz_bh']:.5f} | "
-              f"{r['hz_ap']:.5f} | {r['field_rel_l2_bh_vs_ap']:.2e} | {r['status_flags']} |", flush=True)
+              f"{r['hz_ap']:.5f} | {r['field_rel_l2_bh_vs_ap']:.2e} | {flag_names(r['status_flags'])} |",
+              flush=True)
 
 
 if __name__ == "__main__":

@@ -89,12 +89,13 @@ def rsa_uniform(rng: np.random.Generator, n: int, lo, hi, margin: float = 0.5,
 
 
 def rsa_chains(rng: np.random.Generator, n: int, lo, hi, spacing: float = 1.05, lmin: int = 2,
-               lmax: int = 20, jitter: float = 0.1, margin: float = 0.5, min_sep: float = D):
+               lmax: int = 20, jitter: float = 0.1, margin: float = 0.5, min_sep: float = D, lengths=None):
     """Straight chains of beads along random axes, lengths uniform in [lmin, lmax], spacing in d.
 
     Moments are the chain axis plus isotropic Gaussian jitter of standard deviation ``jitter``,
     normalised.  The last accepted chain is truncated so that exactly n beads are returned.
-    Returns (pos (3, n), mom (3, n)).
+    Returns (pos (3, n), mom (3, n)).  If ``lengths`` is a list, the realised length of every placed chain
+    (the truncated one included) is appended to it; the draws are the same either way.
     """
     lo = np.asarray(lo, float) + margin
     hi = np.asarray(hi, float) - margin
@@ -141,6 +142,9 @@ def rsa_chains(rng: np.random.Generator, n: int, lo, hi, spacing: float = 1.05, 
         new_b = np.concatenate([pts[start[c]:start[c] + lens[c]] for c in sel], axis=0)[:need] \
             if sel.size else np.zeros((0, 3))
         new_a = np.repeat(ax[sel], lens[sel], axis=0)[:need] if sel.size else np.zeros((0, 3))
+        if lengths is not None and sel.size:
+            taken = np.minimum(np.cumsum(lens[sel]), need)  # beads placed after each chain
+            lengths.extend(int(x) for x in np.diff(np.concatenate([[0], taken])) if x > 0)
         beads = np.concatenate([beads, new_b], axis=0)
         axes = np.concatenate([axes, new_a], axis=0)
     g = rng.standard_normal((n, 3))
@@ -192,11 +196,12 @@ def config2(seed: int = 1002) -> Workload:
                         name="uniform_n131072_phi0.05")
 
 
-def config3(seed: int = 1003, theta: float = 0.5, n: int = 1 << 20) -> Workload:
-    """Aggregated workload: N = 2^20 beads in straight chains (lengths 2-20, spacing 1.05) at phi 0.1."""
+def config3(seed: int = 1003, theta: float = 0.5, n: int = 1 << 20, lengths=None) -> Workload:
+    """Aggregated workload: N = 2^20 beads in straight chains (lengths 2-20, spacing 1.05) at phi 0.1.
+    lengths: optional list that receives the realised chain lengths (see rsa_chains)."""
     side = cube_side(n, 0.1)
     rng = np.random.default_rng(seed)
-    pos, mom = rsa_chains(rng, n, (0.0, 0.0, 0.0), (side, side, side))
+    pos, mom = rsa_chains(rng, n, (0.0, 0.0, 0.0), (side, side, side), lengths=lengths)
     return Workload(f"chains_n{n}_phi0.1", pos, mom, np.zeros(3), np.zeros(3), np.full(3, side),
                     theta, 16, seed)
 
@@ -264,13 +269,19 @@ def nearest_to_centre(pos: np.ndarray, k: int) -> np.ndarray:
     return np.sort(np.argsort(d2, kind="stable")[:k])
 
 
-def cached(name: str, make):
-    """Workload `name` from an on-disk cache (npz under $FFBH_CACHE or the temp dir), else make() it."""
+def cache_file(name: str) -> str:
+    """Path of workload `name` in the on-disk cache (npz under $FFBH_CACHE or the temp dir)."""
     import os
     import tempfile
     d = os.environ.get("FFBH_CACHE", os.path.join(tempfile.gettempdir(), "ffbh_cache"))
     os.makedirs(d, exist_ok=True)
-    f = os.path.join(d, name + ".npz")
+    return os.path.join(d, name + ".npz")
+
+
+def cached(name: str, make):
+    """Workload `name` from the on-disk cache (cache_file), else make() it and store it there."""
+    import os
+    f = cache_file(name)
     if os.path.exists(f):
         z = np.load(f)
         return Workload(str(z["name"]), z["pos"], z["mom"], z["hext"], z["box_lo"], z["box_hi"],
@@ -281,3 +292,20 @@ def cached(name: str, make):
              theta=w.theta, leaf_size=w.leaf_size, seed=w.seed)
     os.replace(tmp, f)
     return w
+
+
+def chain_length_table(n: int = 1 << 20, seed: int = 1003) -> str:
+    """Markdown histogram of the realised chain lengths of the chain workload (drawn uniform in [2, 20];
+    chains that overlap earlier ones or leave the box are redrawn whole, which favours short chains)."""
+    lengths = []
+    w = config3(seed=seed, n=n, lengths=lengths)
+    ln = np.asarray(lengths)
+    assert ln.sum() == w.n
+    rows = ["| length | chains | fraction of chains | fraction of beads |", "|---|---|---|---|"]
+    for L in range(1, 21):
+        k = int((ln == L).sum())
+        if k:
+            rows.append(f"| {L} | {k} | {k / ln.size:.4f} | {k * L / ln.sum():.4f} |")
+    rows.append(f"\n{ln.size} chains, {int(ln.sum())} beads; mean length {ln.mean():.2f} (drawn: 11.0), "
+                f"bead-weighted mean {float((ln * ln).sum() / ln.sum()):.2f}.")
+    return "\n".join(rows) + "\n"

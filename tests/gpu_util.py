@@ -42,3 +42,24 @@ def errors(H, Href):
 
 def energy_err(E, Eref, mom, Href):
     return abs(E - Eref) / (0.5 * np.abs((mom * Href).sum()))
+
+
+# Gradient bar (dE/dr, dE/dm and general vector-Jacobian products) against the FP64 oracle at equal theta:
+# FP64 relative L2 <= 1e-12 and every particle within 1e-10; FP32-mixed relative L2 and the 99.9th
+# percentile per-particle error <= 1e-5 (per-particle error as in errors(): floor 1e-3 rms).
+GRAD_TOL = {"fp64": 1e-12, "fp32_mixed": 1e-5}
+
+
+def grad_check(g, ref, precision, what=""):
+    """Assert the gradient bar for one gradient array (3, n) or (B, 3, n); returns the error figures."""
+    g, ref = np.asarray(g), np.asarray(ref)
+    e = errors(g.reshape(-1, 3, g.shape[-1]).transpose(1, 0, 2).reshape(3, -1),
+               ref.reshape(-1, 3, ref.shape[-1]).transpose(1, 0, 2).reshape(3, -1))
+    tol = GRAD_TOL[precision]
+    assert e["l2"] <= tol, (what, precision, e)
+    if precision == "fp64":
+        assert e["max"] <= 1e-10, (what, precision, e)
+    else:
+        assert e["p999"] <= 1e-5, (what, precision, e)
+    print(f"[grad] {what} {precision}: rel L2 {e['l2']:.2e}, p99.9 {e['p999']:.2e}, max {e['max']:.2e}")
+    return e

@@ -2,7 +2,8 @@
 == the all-pairs analytic gradient built from the paper's f_dip, and the invariants).
 
 E = -1/2 sum m.H - sum m.H_ext; dE/dr, dE/dm and a general vector-Jacobian product with upstream dL/dH.
-FP64 path within 1e-12 (relative L2; FP64 atomics only reorder sums), FP32-mixed within 1e-5.
+FP64 path: relative L2 within 1e-12 and every particle within 1e-10 (FP64 atomics only reorder sums);
+FP32-mixed: relative L2 and the 99.9th percentile of the per-particle error within 1e-5.
 """
 import numpy as np
 import pytest
@@ -10,6 +11,8 @@ import torch
 
 from paper_1212_2934_amd import workloads
 from paper_1212_2934_amd.binding import BarnesHut
+
+from gpu_util import grad_check
 
 pytestmark = pytest.mark.gpu
 TOL = {"fp64": 1e-12, "fp32_mixed": 1e-5}
@@ -33,20 +36,20 @@ def _gpu_grad(pos, mom, hext, theta, precision, gH=None, gE=1.0, leaf=16, want_d
     return [None if o is None else o.cpu().numpy() for o in out]
 
 
-# independent waves; 2 and 4 waves together; two targets per lane; 32 and 16 targets per wave; each walk
-# split over the root's children, with 64, 32 and 16 targets per wave; one persistent cost-ordered launch
-@pytest.mark.parametrize("tuning_id", [0, 4, 5, 6, 8, 9, 10, 11, 12, 13, 14, 15])
+# 64, 32 and 16 targets per wave; each walk split over the root's children, with 64, 32 and 16 targets per
+# wave; one persistent cost-ordered launch with 2, 4 and 1 waves per workgroup
+@pytest.mark.parametrize("tuning_id", [0, 4, 5, 6, 7, 8, 9, 10, 11])
 @pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
 def test_energy_gradient_config1(oracle_mod, precision, tuning_id):
     w = workloads.uniform_cube(4096, 32.0, seed=1001, hext=(0.0, 0.0, 1.0))
     H, E, dr, dm = oracle_mod.Tree(w.pos, w.mom, 16).energy_grad(0.5, w.hext)
     gdr, gdm, gdh = _gpu_grad(w.pos, w.mom, w.hext, 0.5, precision, want_dhext=True, tuning_id=tuning_id)
-    assert rel(gdr, dr) <= TOL[precision]
-    assert rel(gdm, dm) <= TOL[precision]
+    grad_check(gdr, dr, precision, f"dE/dr uniform 4096 tuning {tuning_id}")
+    grad_check(gdm, dm, precision, f"dE/dm uniform 4096 tuning {tuning_id}")
     np.testing.assert_allclose(gdh[0], -w.mom.sum(axis=1), rtol=1e-12)
 
 
-@pytest.mark.parametrize("tuning_id", [0, 5, 7, 9, 11, 14])
+@pytest.mark.parametrize("tuning_id", [0, 2, 5, 7, 10])
 @pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
 @pytest.mark.parametrize("theta", [0.3, 0.7])
 def test_general_vjp_chains(oracle_mod, precision, theta, tuning_id):
@@ -60,8 +63,8 @@ def test_general_vjp_chains(oracle_mod, precision, theta, tuning_id):
     dr, dm = t.vjp(theta, gH - 0.5 * gE * w.mom)
     dm = dm + gE * (-0.5 * H - hext[:, None])
     gdr, gdm = _gpu_grad(w.pos, w.mom, hext, theta, precision, gH=gH, gE=gE, tuning_id=tuning_id)
-    assert rel(gdr, dr) <= TOL[precision]
-    assert rel(gdm, dm) <= TOL[precision]
+    grad_check(gdr, dr, precision, f"dL/dr chains theta {theta} tuning {tuning_id}")
+    grad_check(gdm, dm, precision, f"dL/dm chains theta {theta} tuning {tuning_id}")
 
 
 def test_theta_zero_equals_allpairs_force(oracle_mod):
@@ -72,7 +75,7 @@ def test_theta_zero_equals_allpairs_force(oracle_mod):
     assert rel(gdm, -oracle_mod.allpairs_field(w.pos, w.mom)) <= 1e-12
 
 
-@pytest.mark.parametrize("tuning_id", [0, 4, 5, 6, 9, 10, 12, 13])
+@pytest.mark.parametrize("tuning_id", [0, 3, 5, 6, 8, 9])
 def test_batched_adjoint(oracle_mod, tuning_id):
     B, n = 3, 2000 + 77  # ragged: the last workgroup of each system is partly empty
     ws = [workloads.uniform_cube(n, 26.0, seed=30 + b) for b in range(B)]
@@ -82,11 +85,12 @@ def test_batched_adjoint(oracle_mod, tuning_id):
     gdr, gdm = _gpu_grad(pos, mom, hext, 0.5, "fp32_mixed", tuning_id=tuning_id)
     for b, x in enumerate(ws):
         _, _, dr, dm = oracle_mod.Tree(x.pos, x.mom, 16).energy_grad(0.5, hext)
-        assert rel(gdr[b], dr) <= 1e-5 and rel(gdm[b], dm) <= 1e-5
+        grad_check(gdr[b], dr, "fp32_mixed", f"dE/dr batch {b} tuning {tuning_id}")
+        grad_check(gdm[b], dm, "fp32_mixed", f"dE/dm batch {b} tuning {tuning_id}")
 
 
 @pytest.mark.parametrize("n", [1, 2, 3, 16, 17, 65, 300])
-@pytest.mark.parametrize("tuning_id", [0, 10])
+@pytest.mark.parametrize("tuning_id", [0, 6])
 def test_small_systems(oracle_mod, n, tuning_id):
     """Down to a single particle and a root that is a leaf (n <= 16), where a split walk has one part."""
     w = workloads.uniform_cube(n, 4.0 + n ** (1.0 / 3.0) * 2.0, seed=60 + n, hext=(0.3, 0.0, 0.5))
@@ -96,11 +100,11 @@ def test_small_systems(oracle_mod, n, tuning_id):
         assert np.abs(gdr).max() == 0.0
         np.testing.assert_allclose(gdm, dm, rtol=1e-14)
         return
-    assert rel(gdr, dr) <= 1e-12
-    assert rel(gdm, dm) <= 1e-12
+    grad_check(gdr, dr, "fp64", f"dE/dr n {n}")
+    grad_check(gdm, dm, "fp64", f"dE/dm n {n}")
 
 
-@pytest.mark.parametrize("tuning_id", [13, 15])
+@pytest.mark.parametrize("tuning_id", [9, 11])
 @pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
 def test_persistent_launch_repeats(oracle_mod, precision, tuning_id):
     """The persistent launch orders its items by the previous launch's costs: the first call runs them in
@@ -122,8 +126,8 @@ def test_persistent_launch_repeats(oracle_mod, precision, tuning_id):
         assert bh.check_status() == 0
         dr, dm = dr.cpu().numpy(), dm.cpu().numpy()
         for b in range(B):
-            assert rel(dr[b], refs[b][2]) <= TOL[precision], (call, b)
-            assert rel(dm[b], refs[b][3]) <= TOL[precision], (call, b)
+            grad_check(dr[b], refs[b][2], precision, f"dE/dr call {call} system {b}")
+            grad_check(dm[b], refs[b][3], precision, f"dE/dm call {call} system {b}")
 
 
 def test_invariants_at_full_size_c4():

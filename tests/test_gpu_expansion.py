@@ -75,7 +75,7 @@ def test_more_accurate_than_order_one(oracle_mod):
     assert e2 < 0.6 * e1, (e1, e2)
 
 
-@pytest.mark.parametrize("tuning_id", [0, 5, 6, 10, 13])  # coop and two-target shapes run the plain walk
+@pytest.mark.parametrize("tuning_id", [0, 3, 6, 9])
 @pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
 @pytest.mark.parametrize("theta", [0.5, 0.8])
 def test_adjoint_matches_oracle(oracle_mod, precision, theta, tuning_id):
@@ -137,7 +137,7 @@ def test_adjoint_small_systems(oracle_mod, n):
 
 
 @pytest.mark.parametrize("precision,tol,tuning_id", [("fp64", 1e-11, -1), ("fp32_mixed", 1e-8, -1),
-                                                     ("fp64", 1e-11, 15)])
+                                                     ("fp64", 1e-11, 11)])
 def test_md_trajectory_matches_reference(precision, tol, tuning_id):
     """MD steps with order-2 cells against the reference integrator with order-2 forces and torques."""
     from oracle import md as omd

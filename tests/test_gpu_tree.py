@@ -104,3 +104,42 @@ def test_tree_batch_around_the_one_workgroup_sort(oracle_mod, n):
     for b, w in enumerate(ws):
         total += _compare(w.pos, w.mom, 16, oracle_mod, offset=b * n, gtree=g)
     assert total == g["first"].size
+
+
+def _compare_arrays(pos, mom, leaf, oracle_mod, gtree):
+    """_compare for one large system, vectorised: the cells are matched by (first, count) after sorting."""
+    t = oracle_mod.Tree(pos, mom, leaf).export()
+    assert (gtree["perm"] == t["perm"]).all()
+    keep = t["nchild"] != 1
+    okey = t["first"][keep].astype(np.int64) * (1 << 32) + t["count"][keep]
+    oo = np.argsort(okey)
+    gkey = gtree["first"].astype(np.int64) * (1 << 32) + gtree["count"]
+    go = np.argsort(gkey)
+    assert okey.size == gkey.size
+    assert (okey[oo] == gkey[go]).all()
+    assert (t["level"][keep][oo] == gtree["level"][go]).all()
+    assert ((t["nchild"][keep][oo] == 0) == (gtree["nchild"][go] == 0)).all()
+    assert (t["c"][keep][oo] == gtree["centroid"][go]).all()  # bitwise
+    return okey.size
+
+
+@pytest.mark.parametrize("which", ["uniform_2p17", "chains_2p20", "uniform_1310727"])
+def test_tree_full_size_bitwise(oracle_mod, which):
+    """Radix-sort tiles of several keys per thread: two at 2^17 particles and sixteen at 2^20, both with
+    256 tiles per system, the most for which the scatter derives its offsets from the raw tile counts;
+    1310727 particles need 321 tiles and take the device-wide scan instead.  The sorted order, the cells
+    and their centres must equal the oracle's bit for bit."""
+    if which == "uniform_2p17":
+        w = workloads.config2()
+    elif which == "chains_2p20":
+        w = workloads.cached("chains_n1048576_seed1003", lambda: workloads.config3())
+    else:
+        n = 1310727
+        w = workloads.cached("uniform_n1310727_phi0.05",
+                             lambda: workloads.uniform_cube(n, workloads.cube_side(n, 0.05), 1007))
+    print(f"[tree] {which}: n {w.n}", flush=True)
+    out = run_field(w.pos, w.mom, leaf=16, counters=False)
+    assert out["flags"] == 0
+    g = out["bh"].export_tree()
+    ncells = _compare_arrays(w.pos, w.mom, 16, oracle_mod, g)
+    assert ncells == g["first"].size
