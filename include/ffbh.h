@@ -180,6 +180,23 @@ bh_status bh_graph_destroy(void *graph_exec);
 bh_status bh_allpairs(int64_t n, int32_t batch, int32_t precision, const double *d_pos, const double *d_mom,
                       const double *d_hext, double *d_H, double *d_dEdr, double *d_E, void *stream);
 
+/* For callers that cannot allocate memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): bh_build followed by bh_field in one call, with no handle, no caller workspace
+ * and no allocation of any kind.  The workspace is a fixed 64 MiB array of device memory that the library
+ * reserves on every device it runs on when its code is loaded there, and holds until the process ends;
+ * the first call on a device also looks up that array's address (do it once outside graph capture).
+ * Parameters as for bh_create (tuning_id selects the forward traversal's launch shape); d_pos, d_mom,
+ * d_hext, d_H and d_E as for bh_build and bh_field; d_flags (one uint32, device, or NULL) receives the
+ * device status word of this call (the BH_FLAG_* bits).  The results equal those of bh_create + bh_build +
+ * bh_field with the same parameters.
+ * Returns BH_EWORKSPACE, before anything is enqueued, when the parameters need more workspace than the
+ * array holds (bh_workspace_bytes > 64 MiB: up to about 65536 particles over the batch at leaf size 16),
+ * BH_EINVAL for bad parameters or pointers, BH_EDEVICE on a HIP failure.  Every call on one device uses
+ * the same array and leaves its contents behind; calls that overlap on one device (two streams, two
+ * threads, or a replayed graph overlapping another call) race and give wrong results: order them. */
+bh_status bh_field_noalloc(const bh_params *p, const double *d_pos, const double *d_mom, const double *d_hext,
+                           double *d_H, double *d_E, uint32_t *d_flags, void *stream);
+
 /* Read (and clear) the device status word; synchronises the stream.  Returns BH_EDEGENERATE if any
  * flag was set, BH_OK otherwise; the raw bits go to *flags if not NULL. */
 bh_status bh_check_status(bh_handle *h, void *stream, uint32_t *flags);

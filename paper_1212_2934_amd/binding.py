@@ -78,6 +78,8 @@ def lib():
         L.bh_morton_code.restype = C.c_uint64
         L.bh_allpairs.argtypes = [i64, i32, i32, P, P, P, P, P, P, P]
         L.bh_allpairs.restype = i32
+        L.bh_field_noalloc.argtypes = [C.POINTER(bh_params), P, P, P, P, P, P, P]
+        L.bh_field_noalloc.restype = i32
         L.bh_status_str.argtypes = [i32]
         L.bh_status_str.restype = C.c_char_p
         for f in ("bh_workspace_bytes", "bh_create", "bh_destroy", "bh_build", "bh_field",
@@ -91,7 +93,7 @@ def lib():
 EXPORTED = ["bh_workspace_bytes", "bh_num_tunings", "bh_create", "bh_destroy", "bh_build", "bh_field",
             "bh_field_backward", "md_step", "bh_check_status", "bh_enable_counters", "bh_num_nodes",
             "bh_export_tree", "bh_set_timing_events", "bh_graph_capture_md", "bh_graph_launch",
-            "bh_graph_destroy", "bh_allpairs", "bh_morton_code", "bh_status_str"]
+            "bh_graph_destroy", "bh_allpairs", "bh_field_noalloc", "bh_morton_code", "bh_status_str"]
 
 
 def _check(fn: str, st: int):
@@ -299,6 +301,40 @@ class MDGraph:
         if g is not None and _lib is not None:
             _lib.bh_graph_destroy(g)
             self._g = None
+
+
+def field_noalloc(pos, mom, hext=None, n=None, batch=1, leaf_size=16, theta=0.5, precision="fp32_mixed",
+                  tuning_id=-1, expansion=1, out=None):
+    """Build + field + energy through bh_field_noalloc (no handle, no workspace).
+
+    pos, mom: (B, 3, n) or, for one system, (3, n) contiguous float64 CUDA tensors; hext (3,) or (B, 3)
+    or None.  out: optional (H, E, flags) tensors to write into (H like pos, E (B,) float64, flags (1,)
+    int32); fresh ones otherwise.  Returns (H, E, flags) with the batch dimension of the input."""
+    squeeze = pos.dim() == 2
+    P = pos.unsqueeze(0) if squeeze else pos
+    M = mom.unsqueeze(0) if squeeze else mom
+    B, _, nn = P.shape
+    _dev64(P, (B, 3, nn), "pos")
+    _dev64(M, (B, 3, nn), "mom")
+    params = make_params(nn, B, leaf_size, theta, precision, tuning_id, expansion)
+    he = None
+    if hext is not None:
+        h = hext.reshape(1, 3).expand(B, 3) if hext.numel() == 3 else hext.reshape(B, 3)
+        he = _dev64(h.contiguous(), (B, 3), "hext")
+    if out is None:
+        H = torch.empty_like(P)
+        E = torch.empty(B, dtype=torch.float64, device=P.device)
+        F = torch.zeros(1, dtype=torch.int32, device=P.device)
+    else:
+        H, E, F = out
+        H = H.unsqueeze(0) if H.dim() == 2 else H
+        _dev64(H, (B, 3, nn), "H")
+        _dev64(E, (B,), "E")
+        if not (F.is_cuda and F.dtype == torch.int32 and F.numel() >= 1):
+            raise ValueError("flags must be an int32 CUDA tensor")
+    _check("bh_field_noalloc", lib().bh_field_noalloc(C.byref(params), _ptr(P), _ptr(M), _ptr(he), _ptr(H),
+                                                      _ptr(E), _ptr(F), _stream()))
+    return (H[0] if squeeze else H), E, F
 
 
 def morton_code(qx: int, qy: int, qz: int) -> int:

@@ -1,4 +1,5 @@
 // C ABI of libffbh: argument checking, workspace layout, and launch sequencing.
+#include <mutex>
 #include <new>
 
 #include "ffbh_internal.h"
@@ -178,6 +179,37 @@ __global__ void k_copy_bbox(const double *__restrict__ bbox, int64_t B, double *
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= B) return;
     for (int k = 0; k < 5; ++k) out[5 * b + k] = bbox[8 * b + k];
+}
+
+__global__ void k_copy_flags(const uint32_t *__restrict__ status, uint32_t *__restrict__ out)
+{
+    if (threadIdx.x == 0) *out = status[0];
+}
+
+// Workspace of bh_field_noalloc: one fixed array per device, reserved when the library's code is loaded
+// on that device.  In host code `scratch` names a host-side stand-in, never the device memory: host code
+// reaches the array only through the address hipGetSymbolAddress returns for the current device
+// (scratch_ptr below), which each device records once.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_dev[kMaxDevices];
+
+// Device address of this device's array (looked up on the first call on the device); nullptr on failure.
+static void *scratch_ptr(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[device]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr ||
+            ((uintptr_t)ptr % 256) != 0)
+            return nullptr;
+        g_scratch_dev[device] = ptr;
+    }
+    return g_scratch_dev[device];
 }
 
 }  // namespace ffbh
@@ -383,6 +415,43 @@ bh_status bh_allpairs(int64_t n, int32_t batch, int32_t precision, const double 
     if (launch_ap(n, batch, precision, d_pos, d_mom, d_hext, d_H, d_dEdr, d_E, (hipStream_t)stream) != hipSuccess)
         return BH_EDEVICE;
     return BH_OK;
+}
+
+bh_status bh_field_noalloc(const bh_params *p, const double *d_pos, const double *d_mom, const double *d_hext,
+                           double *d_H, double *d_E, uint32_t *d_flags, void *stream)
+{
+    if (!params_ok(p)) return BH_EINVAL;
+    const Layout L = plan_layout(*p);
+    if (L.bytes > kScratchBytes) return BH_EWORKSPACE;
+    if (!dptr_ok(d_pos) || !dptr_ok(d_mom) || !dptr_ok(d_H)) return BH_EINVAL;
+    if ((d_hext && !dptr_ok(d_hext)) || (d_E && !dptr_ok(d_E)) || (d_flags && ((uintptr_t)d_flags % 4) != 0))
+        return BH_EINVAL;
+    int device = -1;
+    if (hipGetDevice(&device) != hipSuccess) return BH_EDEVICE;
+    void *base = scratch_ptr(device);
+    if (!base) return BH_EDEVICE;
+    // a handle on the stack over the array: the traversal shape of tuning_id, no counters, no timing
+    // events, no side stream (the build and the field use none of them)
+    Handle h{};
+    h.p = *p;
+    h.L = L;
+    carve(L, base, h.w);
+    h.device = device;
+    h.built = 1;
+    const int tid = p->tuning_id < 0 ? 0 : p->tuning_id;
+    h.waves_per_block = kTuneWaves[tid];
+    h.adj_tpw = kTuneTpw[tid];
+    h.adj_parts = kTuneParts[tid];
+    h.adj_sched = 0;
+    hipStream_t s = (hipStream_t)stream;
+    // the array keeps the previous call's contents: the status word starts at zero (a kernel, not a
+    // memset, so that the call can be captured in a graph)
+    hipLaunchKernelGGL(k_init, dim3(1), dim3(256), 0, s, h.w.status, h.w.ones, (int64_t)L.B);
+    if (hipGetLastError() != hipSuccess) return BH_EDEVICE;
+    if (launch_build(h, d_pos, s) != hipSuccess) return BH_EDEVICE;
+    if (launch_field(h, d_mom, d_hext, d_H, d_E, s) != hipSuccess) return BH_EDEVICE;
+    if (d_flags) hipLaunchKernelGGL(k_copy_flags, dim3(1), dim3(64), 0, s, h.w.status, d_flags);
+    return hipGetLastError() == hipSuccess ? BH_OK : BH_EDEVICE;
 }
 
 bh_status bh_check_status(bh_handle *hh, void *stream, uint32_t *flags)
