@@ -41,7 +41,8 @@ def build() -> str:
     tmp = LIB + ".tmp"
     vmap = os.path.join(CSRC, "exports.map")
     r = subprocess.run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs,
-                        f"-Wl,--version-script={vmap}", "-o", tmp],
+                        f"-Wl,--version-script={vmap}", "-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx",
+                        "-Wl,-rpath,/opt/rocm/lib", "-o", tmp],
                        capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")

@@ -394,6 +394,14 @@ __device__ __forceinline__ void adjoint_wave(int gw, FFBH_ADJ_PARAMS)
 // Waves per SIMD: five for the FP32-mixed walk with the paper's cells (96 VGPRs, a few spilled bytes;
 // 3 % faster MD step than at four), four for the others (the FP64 walk fits 128 VGPRs and runs 7 % faster
 // than at three, but spills heavily at five).
+// Segments of the persistent launch's item order: segment x holds the items i with i * kXcds / nw == x,
+// which start at ceil(x nw / kXcds).
+constexpr int kXcds = 8;
+__host__ __device__ inline uint32_t order_segment_start(int x, int nw)
+{
+    return (uint32_t)(((int64_t)x * nw + kXcds - 1) / kXcds);
+}
+
 template <bool MIXED, bool QUAD>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(MIXED && !QUAD ? 5 : 4))) void k_adjoint(
     FFBH_ADJ_PARAMS, const uint32_t *__restrict__ order, uint32_t *__restrict__ work_ctr)
@@ -405,28 +413,39 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(MIXED && !Q
         adjoint_wave<MIXED, QUAD>(gw, FFBH_ADJ_ARGS);
         return;
     }
+    // The items are split into kXcds contiguous segments (neighbouring items share tree data).  Workgroups
+    // are dispatched to the XCDs round-robin, so workgroup b runs on XCD b mod kXcds: its waves take items
+    // of that XCD's segment first, keeping its L2 on one part of the tree, and then help the other
+    // segments.  Each segment has its own work counter, which only grows, so every wave reaches the exit.
     const int lane = threadIdx.x & (kWave - 1);
-    for (;;) {
-        uint32_t v = 0u;
-        if (lane == 0) v = atomicAdd(work_ctr, 1u);
-        const uint32_t item = __builtin_amdgcn_readfirstlane(v);
-        if (item >= (uint32_t)num_waves) return;
-        const uint32_t gw = order[item];
-        if (gw >= (uint32_t)num_waves) {
-            if (lane == 0) set_flag(status, BH_FLAG_TREE);
-            return;
+    const int home = (int)(blockIdx.x % kXcds);
+    for (int k = 0; k < kXcds; ++k) {
+        const int sg = (home + k) % kXcds;
+        const uint32_t s0 = order_segment_start(sg, num_waves), len = order_segment_start(sg + 1, num_waves) - s0;
+        for (;;) {
+            uint32_t v = 0u;
+            if (lane == 0) v = atomicAdd(work_ctr + sg, 1u);
+            const uint32_t item = __builtin_amdgcn_readfirstlane(v);
+            if (item >= len) break;
+            const uint32_t gw = order[s0 + item];
+            if (gw >= (uint32_t)num_waves) {
+                if (lane == 0) set_flag(status, BH_FLAG_TREE);
+                return;
+            }
+            adjoint_wave<MIXED, QUAD>((int)gw, FFBH_ADJ_ARGS);
         }
-        adjoint_wave<MIXED, QUAD>((int)gw, FFBH_ADJ_ARGS);
     }
 }
 
-// Order of the wave items of the next persistent launch, from the previous launch's costs: the items
-// outside the lightest ~30 % first, in index order (neighbouring items share tree data, so the launch
-// keeps its cache locality), then the light items, heaviest first (64 buckets of the cost range), so the
-// launch ends on short items.  A stable counting sort in one workgroup; then the work counter is reset.
-// Costs all zero (first launch) give the index order.
+// Order of the wave items of the next persistent launch, from the previous launch's costs, within each of
+// the kXcds segments of consecutive items: the items outside the lightest ~30 % (of the whole launch)
+// first, in index order (neighbouring items share tree data, so the launch keeps its cache locality), then
+// the light items, heaviest first (64 buckets of the cost range), so each segment ends on short items.  A
+// stable counting sort in one workgroup on the key (segment, class); then the segments' work counters are
+// reset.  Costs all zero (first launch) give the index order.
 constexpr int kOrderThreads = 1024;
 constexpr int kOrderBins = 64;
+constexpr int kOrderKeys = kXcds * kOrderBins;
 
 __global__ __launch_bounds__(kOrderThreads) void k_order_waves(const uint32_t *__restrict__ cost, int nw,
                                                                uint32_t *__restrict__ order,
@@ -435,8 +454,8 @@ __global__ __launch_bounds__(kOrderThreads) void k_order_waves(const uint32_t *_
     constexpr int kWaves = kOrderThreads / kWave;
     __shared__ uint32_t red[kWaves];
     __shared__ uint32_t fine[kOrderBins];  // items per cost bucket, lightest bucket first
-    __shared__ uint32_t hist[kOrderBins];  // items per key, then the start of each key
-    __shared__ uint32_t wcnt[kWaves][kOrderBins];
+    __shared__ uint32_t hist[kOrderKeys];  // items per key, then the start of each key
+    __shared__ uint32_t wcnt[kWaves][kOrderKeys];
     __shared__ int split;                  // buckets below it are the light items
     const int t = threadIdx.x, lane = t & (kWave - 1), wave = t / kWave;
     uint32_t mx = 0u;
@@ -458,32 +477,40 @@ __global__ __launch_bounds__(kOrderThreads) void k_order_waves(const uint32_t *_
         int sp = 0;
         while (sp < kOrderBins && (uint64_t)(acc + fine[sp]) * 10u <= (uint64_t)nw * 3u) acc += fine[sp++];
         split = sp;
-        uint32_t heavy = 0u;
-        for (int q = sp; q < kOrderBins; ++q) heavy += fine[q];
-        // key 0: heavy items; key k = 1..split: light bucket split - k (heaviest light bucket first)
+    }
+    __syncthreads();
+    const int sp = split;
+    // key = segment * kOrderBins + class; class 0: heavy items; class k = 1..split: light bucket split - k
+    // (heaviest light bucket first)
+    auto key_of = [&](int i, uint32_t c) -> int {
+        const int q = bucket(c);
+        const int seg = (int)(((int64_t)i * kXcds) / nw);
+        return seg * kOrderBins + (q >= sp ? 0 : sp - q);
+    };
+    // exclusive starts of the keys: count, then scan (one thread per key, then a serial scan)
+    for (int k = t; k < kOrderKeys; k += kOrderThreads) hist[k] = 0u;
+    __syncthreads();
+    for (int i = t; i < nw; i += kOrderThreads) atomicAdd(&hist[key_of(i, cost[i])], 1u);
+    __syncthreads();
+    if (t == 0) {
         uint32_t start = 0u;
-        for (int k = 0; k < kOrderBins; ++k) {
-            const uint32_t c = k == 0 ? heavy : k <= sp ? fine[sp - k] : 0u;
+        for (int k = 0; k < kOrderKeys; ++k) {
+            const uint32_t c = hist[k];
             hist[k] = start;
             start += c;
         }
     }
     __syncthreads();
-    const int sp = split;
-    auto key_of = [&](uint32_t c) -> int {
-        const int q = bucket(c);
-        return q >= sp ? 0 : sp - q;
-    };
     for (int c0 = 0; c0 < nw; c0 += kOrderThreads) {
-        for (int k = t; k < kWaves * kOrderBins; k += kOrderThreads) (&wcnt[0][0])[k] = 0u;
+        for (int k = t; k < kWaves * kOrderKeys; k += kOrderThreads) (&wcnt[0][0])[k] = 0u;
         __syncthreads();
         const int i = c0 + t;
         const bool ok = i < nw;
-        const int b = ok ? key_of(cost[i]) : 0;
+        const int b = ok ? key_of(i, cost[i]) : 0;
         // lanes of this wave with the same key, and this lane's rank among them
         uint64_t m = ballot(ok);
 #pragma unroll
-        for (int bit = 0; bit < 6; ++bit) {
+        for (int bit = 0; bit < 9; ++bit) {
             const bool set = (b >> bit) & 1;
             const uint64_t v = ballot(set);
             m &= set ? v : ~v;
@@ -491,14 +518,14 @@ __global__ __launch_bounds__(kOrderThreads) void k_order_waves(const uint32_t *_
         const int before = lanes_below(m);
         if (ok && before == 0) wcnt[wave][b] = (uint32_t)__builtin_popcountll(m);
         __syncthreads();
-        if (t < kOrderBins) {
-            uint32_t acc = hist[t];
+        for (int k = t; k < kOrderKeys; k += kOrderThreads) {
+            uint32_t acc = hist[k];
             for (int w = 0; w < kWaves; ++w) {
-                const uint32_t c = wcnt[w][t];
-                wcnt[w][t] = acc;
+                const uint32_t c = wcnt[w][k];
+                wcnt[w][k] = acc;
                 acc += c;
             }
-            hist[t] = acc;
+            hist[k] = acc;
         }
         __syncthreads();
         if (ok) {
@@ -507,7 +534,7 @@ __global__ __launch_bounds__(kOrderThreads) void k_order_waves(const uint32_t *_
         }
         __syncthreads();
     }
-    if (t == 0) *work_ctr = 0u;
+    if (t < kXcds) work_ctr[t] = 0u;
 }
 
 // Sum of the parts of a split adjoint walk for every target, in part order (so the result does not depend

@@ -2,9 +2,20 @@
 #include <mutex>
 #include <new>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "ffbh_internal.h"
 
 namespace ffbh {
+
+// A named range on the host timeline around each entry point (rocprofv3 --marker-trace shows them beside
+// the kernels the call enqueued).
+struct Range {
+    explicit Range(const char *name) { roctxRangePushA(name); }
+    ~Range() { roctxRangePop(); }
+    Range(const Range &) = delete;
+    Range &operator=(const Range &) = delete;
+};
 
 static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -313,6 +324,7 @@ bh_status bh_destroy(bh_handle *h)
 
 bh_status bh_build(bh_handle *hh, const double *d_pos, void *stream)
 {
+    const Range range("bh_build");
     if (!hh || !dptr_ok(d_pos)) return BH_EINVAL;
     if (launch_build(hh->h, d_pos, (hipStream_t)stream) != hipSuccess) return BH_EDEVICE;
     hh->h.built = 1;
@@ -322,6 +334,7 @@ bh_status bh_build(bh_handle *hh, const double *d_pos, void *stream)
 bh_status bh_field(bh_handle *hh, const double *d_mom, const double *d_hext, double *d_H, double *d_E,
                    void *stream)
 {
+    const Range range("bh_field");
     if (!hh || !dptr_ok(d_mom) || !dptr_ok(d_H)) return BH_EINVAL;
     if ((d_hext && !dptr_ok(d_hext)) || (d_E && !dptr_ok(d_E))) return BH_EINVAL;
     if (!hh->h.built) return BH_ESTATE;
@@ -332,6 +345,7 @@ bh_status bh_field(bh_handle *hh, const double *d_mom, const double *d_hext, dou
 bh_status bh_field_backward(bh_handle *hh, const double *d_mom, const double *d_hext, const double *d_gH,
                             const double *d_gE, double *d_dpos, double *d_dmom, double *d_dhext, void *stream)
 {
+    const Range range("bh_field_backward");
     if (!hh || !dptr_ok(d_mom) || !dptr_ok(d_dpos) || !dptr_ok(d_dmom)) return BH_EINVAL;
     if ((d_hext && !dptr_ok(d_hext)) || (d_gH && !dptr_ok(d_gH)) || (d_gE && !dptr_ok(d_gE)) ||
         (d_dhext && !dptr_ok(d_dhext)))
@@ -347,6 +361,7 @@ static bh_status md_args_ok(bh_handle *hh, const md_state *s, const md_params *p
 
 bh_status md_step(bh_handle *hh, const md_state *s, const md_params *p, void *stream)
 {
+    const Range range("md_step");
     bh_status st = md_args_ok(hh, s, p);
     if (st != BH_OK) return st;
     if (launch_md(hh->h, s, p, (hipStream_t)stream) != hipSuccess) return BH_EDEVICE;
@@ -372,6 +387,7 @@ static bh_status md_args_ok(bh_handle *hh, const md_state *s, const md_params *p
 
 bh_status bh_graph_capture_md(bh_handle *hh, const md_state *s, const md_params *p, void *stream, void **graph_exec)
 {
+    const Range range("bh_graph_capture_md");
     bh_status st = md_args_ok(hh, s, p);
     if (st != BH_OK) return st;
     if (!stream || !graph_exec) return BH_EINVAL;
@@ -395,6 +411,7 @@ bh_status bh_graph_capture_md(bh_handle *hh, const md_state *s, const md_params 
 
 bh_status bh_graph_launch(void *graph_exec, void *stream)
 {
+    const Range range("bh_graph_launch");
     if (!graph_exec) return BH_EINVAL;
     return hipGraphLaunch((hipGraphExec_t)graph_exec, (hipStream_t)stream) == hipSuccess ? BH_OK : BH_EDEVICE;
 }
@@ -408,6 +425,7 @@ bh_status bh_graph_destroy(void *graph_exec)
 bh_status bh_allpairs(int64_t n, int32_t batch, int32_t precision, const double *d_pos, const double *d_mom,
                       const double *d_hext, double *d_H, double *d_dEdr, double *d_E, void *stream)
 {
+    const Range range("bh_allpairs");
     if (n < 1 || batch < 1 || batch > 65535) return BH_EINVAL;
     if (precision != BH_FP64 && precision != BH_FP32_MIXED) return BH_EINVAL;
     if (!dptr_ok(d_pos) || !dptr_ok(d_mom) || !dptr_ok(d_H)) return BH_EINVAL;
@@ -420,6 +438,7 @@ bh_status bh_allpairs(int64_t n, int32_t batch, int32_t precision, const double 
 bh_status bh_field_noalloc(const bh_params *p, const double *d_pos, const double *d_mom, const double *d_hext,
                            double *d_H, double *d_E, uint32_t *d_flags, void *stream)
 {
+    const Range range("bh_field_noalloc");
     if (!params_ok(p)) return BH_EINVAL;
     const Layout L = plan_layout(*p);
     if (L.bytes > kScratchBytes) return BH_EWORKSPACE;
