@@ -207,3 +207,30 @@ def test_wca_walls():
     x = np.array([[0.01, 0.04], [5.0, 5.0], [5.0, 5.0]])
     W = md.wall_forces(x, lo, hi, s, eps, kind=0)
     assert W[0, 0] == W[0, 1] > 0.0
+
+
+def _wall_bounce(v0, eps, dt, z0=2.0, steps=100000):
+    """Outgoing speed of one particle thrown at a WCA wall under the explicit update (positions advance
+    with the velocity of the start of the step), no friction, no noise."""
+    pos = np.array([[5.0], [5.0], [z0]])
+    vel = np.array([[0.0], [0.0], [-v0]])
+    for _ in range(steps):
+        F = md.wall_forces(pos, (0.0, 0.0, 0.0), (10.0, 10.0, 10.0), 1.0, eps, 0)
+        pos, vel = pos + dt * vel, vel + dt * F
+        if pos[2, 0] > z0 and vel[2, 0] > 0:
+            return float(vel[2, 0])
+    raise AssertionError("no bounce")
+
+
+def test_explicit_step_gains_energy_at_a_stiff_wall():
+    """Stability limit of the explicit Euler-Maruyama step (Sec. 4) at WCA contacts: the position moves with
+    the old velocity, so the particle overshoots into the wall by v dt and leaves faster than it came.  At
+    eps = kT = 7.14 (the magnetisation benchmark's lambda = 0.28) and dt = 1e-3 the speed grows by 17 % at
+    5 and 80 % at 20, which a friction of 0.1 cannot remove; at dt = 2.5e-4 the gain at 20 is 13 %.  (The
+    pin is on the reference scheme; the GPU step follows it to 1e-12.)"""
+    g = lambda v0, eps, dt: _wall_bounce(v0, eps, dt) / v0
+    assert 1.15 < g(5.0, 7.142857, 1e-3) < 1.20
+    assert 1.7 < g(20.0, 7.142857, 1e-3) < 1.9
+    assert g(20.0, 7.142857, 1e-3) > g(10.0, 7.142857, 1e-3) > g(5.0, 7.142857, 1e-3)  # grows with speed
+    assert 1.10 < g(20.0, 7.142857, 2.5e-4) < 1.16
+    assert g(2.0, 1.0, 1e-3) < 1.07  # the benchmark's kT = eps = 1: thermal speeds gain a few per cent
