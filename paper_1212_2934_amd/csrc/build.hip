@@ -1195,22 +1195,38 @@ hipError_t launch_build(Handle &h, const double *d_pos, hipStream_t s, const dou
 
 namespace ffbh {
 
-// Sorted source records for the direct sums (position and moment of one particle in 48 bytes).
-__global__ __launch_bounds__(256) void k_pack_sources(const double *__restrict__ spos, const double *__restrict__ smom,
-                                                      int64_t ntot, double *__restrict__ src64, double *__restrict__ src32)
+// Moments gathered into sorted order (non-finite values flagged) and, in the same pass, the packed source
+// record of every sorted particle in the handle's precision (FP64 moment or FP32 moment after the FP64
+// position).
+__global__ __launch_bounds__(256) void k_gather_pack(const double *__restrict__ mom, const uint32_t *__restrict__ perm,
+                                                     const double *__restrict__ spos, int64_t n, int64_t ntot,
+                                                     double *__restrict__ smom, double *__restrict__ src64,
+                                                     double *__restrict__ src32, uint32_t *__restrict__ status)
 {
     const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (k >= ntot) return;
+    const int64_t o = perm[k];
+    if (o >= ntot) {
+        set_flag(status, BH_FLAG_TREE);
+        return;
+    }
+    const int64_t b = o / n, i = o - b * n;
+    const double *p = mom + b * 3 * n;
+    const double mx = p[i], my = p[n + i], mz = p[2 * n + i];
+    if (!__builtin_isfinite(mx) || !__builtin_isfinite(my) || !__builtin_isfinite(mz))
+        set_flag(status, BH_FLAG_NONFINITE);
+    smom[k] = mx;
+    smom[ntot + k] = my;
+    smom[2 * ntot + k] = mz;
     const double x = spos[k], y = spos[ntot + k], z = spos[2 * ntot + k];
-    const double mx = smom[k], my = smom[ntot + k], mz = smom[2 * ntot + k];
     if (src64) {
         double *a = src64 + 6 * k;
         a[0] = x; a[1] = y; a[2] = z; a[3] = mx; a[4] = my; a[5] = mz;
     }
     if (src32) {
-        double *b = src32 + 6 * k;
-        b[0] = x; b[1] = y; b[2] = z;
-        float *f = (float *)(b + 3);
+        double *r = src32 + 6 * k;
+        r[0] = x; r[1] = y; r[2] = z;
+        float *f = (float *)(r + 3);
         f[0] = (float)mx; f[1] = (float)my; f[2] = (float)mz; f[3] = 0.0f;
     }
 }
@@ -1221,10 +1237,9 @@ static void gather_moments(Handle &h, const double *d_mom, hipStream_t s)
     const Layout &L = h.L;
     Workspace &w = h.w;
     const bool mixed = h.p.precision == BH_FP32_MIXED;
-    hipLaunchKernelGGL(k_gather3, dim3(grid_for(L.ntot, 256)), dim3(256), 0, s, d_mom, w.perm, L.n,
-                       L.ntot, w.smom, (float *)nullptr, w.status);
-    hipLaunchKernelGGL(k_pack_sources, dim3(grid_for(L.ntot, 256)), dim3(256), 0, s, w.spos, w.smom, L.ntot,
-                       mixed ? (double *)nullptr : (double *)w.src64, mixed ? (double *)w.src32 : (double *)nullptr);
+    hipLaunchKernelGGL(k_gather_pack, dim3(grid_for(L.ntot, 256)), dim3(256), 0, s, d_mom, w.perm, w.spos, L.n,
+                       L.ntot, w.smom, mixed ? (double *)nullptr : (double *)w.src64,
+                       mixed ? (double *)w.src32 : (double *)nullptr, w.status);
 }
 
 // First moments of every node from the sorted moments and positions already in the workspace (after a

@@ -176,7 +176,7 @@ def test_dilute_md_2p17_100_steps_both_precisions(oracle_mod):
     print(f"[dilute MD] 100 steps: worst FP32-mixed field error {w32:.2e}, worst FP64 "
           f"{max(r[2]['l2'] for r in rows):.2e}, trajectories apart by {rows[-1][3]:.2e}")
     lines = ["| step | FP32-mixed rel. L2 | FP32-mixed p99.9 | FP32-mixed max | FP64 rel. L2 | FP64 max | "
-             "max |r_FP32 - r_FP64| |", "|---|---|---|---|---|---|---|"]
+             "max abs(r_FP32 - r_FP64) |", "|---|---|---|---|---|---|---|"]
     lines += [f"| {st} | {a['l2']:.2e} | {a['p999']:.2e} | {a['max']:.2e} | {b['l2']:.2e} | {b['max']:.2e} | "
               f"{d:.2e} |" for st, a, b, d in rows]
     _series_out("dilute_md_n131072_100_steps.md", "\n".join(lines) + "\n")

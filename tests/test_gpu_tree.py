@@ -143,3 +143,19 @@ def test_tree_full_size_bitwise(oracle_mod, which):
     g = out["bh"].export_tree()
     ncells = _compare_arrays(w.pos, w.mom, 16, oracle_mod, g)
     assert ncells == g["first"].size
+
+
+def test_exported_bounding_cubes_of_a_large_batch(oracle_mod):
+    """Every system's bounding cube (lo, side, scale) is exported, also beyond the 64th of a batch, and
+    equals the oracle's bit for bit (componentwise min and max, one IEEE division)."""
+    B, n = 70, 50
+    ws = [workloads.uniform_cube(n, 8.0 + 0.05 * b, seed=300 + b) for b in range(B)]
+    pos = np.stack([w.pos for w in ws])
+    mom = np.stack([w.mom for w in ws])
+    out = run_field(pos, mom, counters=False)
+    assert out["flags"] == 0
+    g = out["bh"].export_tree()
+    assert g["bbox"].shape == (B, 5)
+    for b, w in enumerate(ws):
+        ref = oracle_mod.Tree(w.pos, w.mom, 16).export()["bbox"]
+        assert (g["bbox"][b] == ref).all(), (b, g["bbox"][b], ref)
