@@ -96,13 +96,16 @@ int32_t bh_num_tunings(void);
 
 /* Create a handle (host memory, owned by the caller until bh_destroy) bound to the current HIP device
  * and to d_workspace (>= bh_workspace_bytes, 256-byte aligned, owned by the caller).  The handle also
- * owns one non-blocking HIP stream of default priority and three events, which md_step uses internally;
- * bh_destroy waits for that stream and releases them. */
+ * owns one non-blocking HIP stream of default priority and three events, which bh_build and md_step use
+ * internally (forked from and joined back into the caller's stream within the call); bh_destroy waits for
+ * that stream and releases them. */
 bh_status bh_create(const bh_params *p, void *d_workspace, size_t workspace_bytes, bh_handle **out);
 bh_status bh_destroy(bh_handle *h);
 
 /* Build the tree for positions d_pos (B, 3, n): bounding cube, Morton codes, radix sort, octree and
- * the geometric centre of every cell (Sec. 3.2 kernels 1-4, Eq. magCenter positions). */
+ * the geometric centre of every cell (Sec. 3.2 kernels 1-4, Eq. magCenter positions).  Systems of more
+ * than 2048 particles also get the order in which the traversals group their targets (Hilbert order of
+ * the particles' cells); it changes results only through the order of rounding. */
 bh_status bh_build(bh_handle *h, const double *d_pos, void *stream);
 
 /* Dipolar field and energy with the tree of the last bh_build (Eq. H_dip summed by the Sec. 3.2

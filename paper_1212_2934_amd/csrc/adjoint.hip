@@ -195,10 +195,11 @@ __device__ inline void close_pairs(AdjLds<float> &W, int lane, bool valid, int s
         double *__restrict__ Hout, double *__restrict__ e_part, uint32_t *__restrict__ status, int64_t n,        \
         int64_t ntot, int waves_per_seg, int num_waves, double theta2, int max_nodes, int tpw, int parts,        \
         double *__restrict__ part_buf, uint32_t *__restrict__ wave_cost, const void *__restrict__ node_q,         \
-        double *__restrict__ node_adjq
+        double *__restrict__ node_adjq, const uint32_t *__restrict__ tgt_order
 #define FFBH_ADJ_ARGS                                                                                           \
     nodes, node_m64, spos, smom, src, hbar, perm, hext, g_gather, g_rm, node_adj, Hs, Hout, e_part, status, n,   \
-        ntot, waves_per_seg, num_waves, theta2, max_nodes, tpw, parts, part_buf, wave_cost, node_q, node_adjq
+        ntot, waves_per_seg, num_waves, theta2, max_nodes, tpw, parts, part_buf, wave_cost, node_q, node_adjq,  \
+        tgt_order
 
 // The fused walk of wave item gw.  If wave_cost is not null, lane 0 stores there a deterministic measure of
 // the item's work (node visits plus leaf pair rounds), which orders the next launch.  QUAD: order-2 cells
@@ -219,7 +220,7 @@ __device__ __forceinline__ void adjoint_wave(int gw, FFBH_ADJ_PARAMS)
     const int grp = (gw - seg * per_seg) / parts, part = gw - seg * per_seg - grp * parts;
     const int local = grp * tpw + lane;
     const bool valid = lane < tpw && local < n;
-    const int si = (int)(seg * n) + (valid ? local : 0);
+    const int si = target_of(tgt_order, seg, n, local, valid);
     const double rx = spos[si], ry = spos[ntot + si], rz = spos[2 * ntot + si];
     const T ax = valid ? (T)hbar[si] : (T)0, ay = valid ? (T)hbar[ntot + si] : (T)0,
             az = valid ? (T)hbar[2 * ntot + si] : (T)0;
@@ -736,11 +737,12 @@ hipError_t launch_backward(Handle &h, const double *d_mom, const double *d_hext,
         const uint32_t *ord = sched ? w.wave_order : nullptr;
         uint32_t *cost = parts == 1 ? w.wave_cost : nullptr;
         const void *nq = mixed ? (const void *)w.node_q32 : (const void *)w.node_q64;
+        const uint32_t *tgt = uses_target_order(L) ? w.tgt_order : nullptr;
 #define FFBH_ADJ(MX, QD, T)                                                                                     \
     hipLaunchKernelGGL((k_adjoint<MX, QD>), dim3(grid), dim3(wpb * kWave), wpb * sizeof(AdjLds<T>), s, w.nodes,     \
                        w.node_m64, w.spos, w.smom, MX ? w.src32 : w.src64, w.hbar, w.perm, d_hext, w.g_gather,    \
                        w.g_rm, w.node_adj, w.Hs, d_H, w.e_part, w.status, L.n, L.ntot, wps, nwv, theta2,          \
-                       (int)L.max_nodes, tpw, parts, w.part_buf, cost, nq, w.node_adjq, ord, w.sched_ctr)
+                       (int)L.max_nodes, tpw, parts, w.part_buf, cost, nq, w.node_adjq, tgt, ord, w.sched_ctr)
         if (mixed && quad) FFBH_ADJ(true, true, float);
         else if (mixed) FFBH_ADJ(true, false, float);
         else if (quad) FFBH_ADJ(false, true, double);

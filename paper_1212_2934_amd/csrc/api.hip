@@ -84,6 +84,12 @@ void carve(const Layout &Lc, void *base, Workspace &w)
     w.scan_tmp = (uint32_t *)take(4 * ((size_t)(L.hist_len > L.bin_int ? L.hist_len : L.bin_int) / 4096 + 64));
     w.perm = w.vals[0];
     w.codes = w.keys[0];
+    // the target-order sort ping-pongs between (keys[1], vals[1]), free once the particles are sorted, and
+    // these; its scan has its own partial sums because it may run beside the octree's scan
+    const size_t no = uses_target_order(L) ? nt : 0;
+    w.hkeys = (uint64_t *)take(8 * no);
+    w.tgt_order = (uint32_t *)take(4 * no);
+    w.hscan_tmp = (uint32_t *)take(no ? 4 * ((size_t)L.hist_len / 4096 + 64) : 0);
     w.spos = (double *)take(3 * 8 * nt);
     w.smom = (double *)take(3 * 8 * nt);
     // one 48-byte source record per particle, in the handle's precision (src64 or src32, never both)
@@ -326,7 +332,10 @@ bh_status bh_build(bh_handle *hh, const double *d_pos, void *stream)
 {
     const Range range("bh_build");
     if (!hh || !dptr_ok(d_pos)) return BH_EINVAL;
-    if (launch_build(hh->h, d_pos, (hipStream_t)stream) != hipSuccess) return BH_EDEVICE;
+    // large builds put the targets in Hilbert order on the handle's side stream, beside the octree
+    Handle &h = hh->h;
+    const hipStream_t side = h.L.ntot >= kForkMinParticles && uses_target_order(h.L) ? h.side : nullptr;
+    if (launch_build(h, d_pos, (hipStream_t)stream, nullptr, side) != hipSuccess) return BH_EDEVICE;
     hh->h.built = 1;
     return BH_OK;
 }

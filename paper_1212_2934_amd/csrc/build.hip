@@ -1117,7 +1117,8 @@ static void upward(Handle &h, const double *vals, const double *vals2, hipStream
 
 static void gather_moments(Handle &h, const double *d_mom, hipStream_t s);
 
-hipError_t launch_build(Handle &h, const double *d_pos, hipStream_t s, const double *d_mom, hipEvent_t sorted_ev)
+hipError_t launch_build(Handle &h, const double *d_pos, hipStream_t s, const double *d_mom, hipStream_t side,
+                        bool join)
 {
     const Layout &L = h.L;
     Workspace &w = h.w;
@@ -1152,10 +1153,12 @@ hipError_t launch_build(Handle &h, const double *d_pos, hipStream_t s, const dou
     hipLaunchKernelGGL(k_gather3, dim3(grid_for(ntot, 256)), dim3(256), 0, s, d_pos, w.perm, n, ntot,
                        w.spos, (float *)nullptr, w.status);
     // the sorted codes, permutation and positions and the bounding cube are final from here on
-    if (sorted_ev) {
-        const hipError_t e = hipEventRecord(sorted_ev, s);
+    if (side) {
+        hipError_t e = hipEventRecord(h.sorted_ev, s);
+        if (e == hipSuccess) e = hipStreamWaitEvent(side, h.sorted_ev, 0);
         if (e != hipSuccess) return e;
     }
+    if (uses_target_order(L)) launch_target_order(h, side ? side : s);
     const int64_t nint = L.bin_int;  // B * (n - 1)
     if (nint > 0) {
         hipLaunchKernelGGL(k_karras, dim3(grid_for(nint, 256)), dim3(256), 0, s, w.codes, n, nint,
@@ -1188,7 +1191,89 @@ hipError_t launch_build(Handle &h, const double *d_pos, hipStream_t s, const dou
     } else {
         upward<0>(h, w.spos, nullptr, s);
     }
+    if (side && join) {
+        hipError_t e = hipEventRecord(h.join_ev, side);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, h.join_ev, 0);
+        if (e != hipSuccess) return e;
+    }
     return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------------
+// Target order: the traversal takes each wave's targets from a run of consecutive entries of this order.
+// Sorted (Morton) order jumps between distant cells at every boundary of the Z curve, and a wave whose
+// targets straddle such a jump walks the union of two far-apart neighbourhoods.  The Hilbert curve has no
+// jumps (consecutive cells share a face), so waves of targets taken in Hilbert order span smaller regions
+// and their union walks visit fewer nodes.  Results depend on the grouping only through the order of
+// FP32-mixed partial sums and of the adjoint's reductions.
+// ------------------------------------------------------------------------------------------------
+
+// Hilbert index of the cell (x, y, z) of a 2^b grid per axis: Skilling's transform of the axes to the
+// transposed index (J. Skilling, "Programming the Hilbert curve", AIP Conf. Proc. 707, 381 (2004)),
+// whose bits, interleaved from the most significant down with x first, are the index.
+template <int b>
+__device__ inline uint32_t hilbert_index(uint32_t x, uint32_t y, uint32_t z)
+{
+    uint32_t X[3] = {x, y, z};
+    // undo the excess work of the curve's reflections and rotations, from the coarsest bit down
+#pragma unroll
+    for (uint32_t Q = 1u << (b - 1); Q > 1u; Q >>= 1) {
+        const uint32_t P = Q - 1u;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const bool invert = (X[i] & Q) != 0u;
+            const uint32_t t = invert ? 0u : ((X[0] ^ X[i]) & P);  // exchange the low bits of X[0], X[i]
+            X[0] ^= invert ? P : t;
+            X[i] ^= t;
+        }
+    }
+    // Gray encode
+    X[1] ^= X[0];
+    X[2] ^= X[1];
+    uint32_t t = 0u;
+#pragma unroll
+    for (uint32_t Q = 1u << (b - 1); Q > 1u; Q >>= 1)
+        if (X[2] & Q) t ^= Q - 1u;
+    X[0] ^= t; X[1] ^= t; X[2] ^= t;
+    return (uint32_t)morton(X[0], X[1], X[2]);
+}
+
+// Key of sorted particle o: the Hilbert index of its cell at kHilbertBits bits per axis, read off the top
+// bits of its Morton code (the same cube); the value is o itself.
+__global__ __launch_bounds__(256) void k_hilbert_keys(const uint64_t *__restrict__ codes, int64_t ntot,
+                                                      uint64_t *__restrict__ keys, uint32_t *__restrict__ vals)
+{
+    const int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (o >= ntot) return;
+    const uint64_t c = codes[o] >> (3 * (kBits - kHilbertBits));
+    keys[o] = hilbert_index<kHilbertBits>(compact3(c >> 2), compact3(c >> 1), compact3(c));
+    vals[o] = (uint32_t)o;
+}
+
+void launch_target_order(Handle &h, hipStream_t s)
+{
+    const Layout &L = h.L;
+    Workspace &w = h.w;
+    hipLaunchKernelGGL(k_hilbert_keys, dim3(grid_for(L.ntot, 256)), dim3(256), 0, s, w.codes, L.ntot, w.keys[1],
+                       w.vals[1]);
+    // three stable 8-bit passes over the 24-bit keys, per system: (keys[1], vals[1]) -> (hkeys, tgt_order)
+    // -> (keys[1], vals[1]) -> (hkeys, tgt_order); within a cell the sorted order is kept
+    static_assert(kHilbertBits <= kRadixBits, "three radix passes cover the Hilbert keys");
+    static_assert(kTargetOrderMin > kSortSmallMax, "systems with a target order take the tiled sort");
+    uint64_t *kb[2] = {w.keys[1], w.hkeys};
+    uint32_t *vb[2] = {w.vals[1], w.tgt_order};
+    const int tiles = (int)L.tiles;
+    const unsigned sblocks = (unsigned)(L.B * tiles);
+    const int fused = tiles <= kFusedTiles;
+    for (int pass = 0; pass < 3; ++pass) {
+        const int src = pass & 1, dst = src ^ 1;
+        const int shift = pass * kRadixBits;
+        hipLaunchKernelGGL(k_radix_hist, dim3(sblocks), dim3(kSortThreads), 0, s, kb[src], L.n, tiles,
+                           L.sort_items, shift, w.hist);
+        if (!fused) scan_excl(w.hist, (int64_t)L.hist_len, w.hscan_tmp, nullptr, s);
+        hipLaunchKernelGGL(k_radix_scatter, dim3(sblocks), dim3(kSortThreads), 0, s, kb[src], vb[src], kb[dst],
+                           vb[dst], w.hist, L.n, tiles, L.sort_items, shift, L.ntot, fused);
+    }
 }
 
 }  // namespace ffbh

@@ -21,6 +21,9 @@ constexpr int kSortThreads = 256;
 constexpr int kSortItems = 16;                  // most keys per thread per tile
 constexpr int kMinTpw = 16;                     // fewest targets an adjoint wave owns
 constexpr int kStackMax = 64;                   // one traversal stack entry per lane of a wave
+constexpr int kHilbertBits = 8;                 // bits per axis of the Hilbert keys that group targets
+constexpr int64_t kTargetOrderMin = 2049;       // systems from this size group targets in Hilbert order
+constexpr int64_t kForkMinParticles = 1 << 14;  // fewer particles over the batch stay on one stream
 
 // Node record read by the traversal: one 64-byte line, fetched with a single scalar load.
 struct alignas(64) NodeRec {
@@ -45,6 +48,9 @@ struct Workspace {
     uint32_t *hist;          // radix histograms (B x 256 x tiles_per_system)
     uint32_t *scan_tmp;      // per-tile partial sums of the device-wide scan
     uint32_t *perm;          // sorted position -> global original index (alias of the final vals)
+    uint64_t *hkeys;         // N_tot Hilbert keys of the sorted particles (target-order sort)
+    uint32_t *tgt_order;     // N_tot: the traversal's targets of each system in Hilbert order (sorted positions)
+    uint32_t *hscan_tmp;     // per-tile partial sums of the target-order sort's scan
     uint64_t *codes;         // sorted codes (alias of the final keys)
     double *spos;            // 3 x N_tot sorted positions (SoA: x block, y block, z block)
     double *smom;            // 3 x N_tot sorted moments FP64
@@ -169,11 +175,22 @@ inline unsigned grid_for(int64_t work, int threads, int64_t cap = (int64_t)1 << 
     return (unsigned)g;
 }
 
+// Whether the traversals of this layout take their targets in Hilbert order (w.tgt_order) rather than in
+// sorted (Morton) order.
+inline bool uses_target_order(const Layout &L) { return L.n >= kTargetOrderMin; }
+
 // Launch helpers implemented per source file.
 // Tree build; with d_mom the moments are gathered and summed in the same upward pass (the MD step).
-// sorted_ev, if not null, is recorded once the sorted codes, permutation, positions and cube are final.
+// With a side stream, h.sorted_ev is recorded once the sorted codes, permutation, positions and cube are
+// final, the side stream waits for it and computes the traversal's target order beside the rest of the
+// build; with join the caller's stream then waits for the side stream at the end of the build, without
+// it the caller joins the side stream itself (h.join_ev) before the traversal.  Without a side stream
+// everything runs on s.
 hipError_t launch_build(Handle &h, const double *d_pos, hipStream_t s, const double *d_mom = nullptr,
-                        hipEvent_t sorted_ev = nullptr);
+                        hipStream_t side = nullptr, bool join = true);
+// Targets of every system in Hilbert order (the positions' cells at kHilbertBits bits per axis), sorted
+// positions as values: consecutive targets of a traversal wave then lie close together.
+void launch_target_order(Handle &h, hipStream_t s);
 hipError_t launch_upward_moments(Handle &h, const double *d_mom, hipStream_t s);
 hipError_t launch_upward_first_moments(Handle &h, hipStream_t s);
 hipError_t launch_field(Handle &h, const double *d_mom, const double *d_hext, double *d_H,

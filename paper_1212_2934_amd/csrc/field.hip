@@ -72,7 +72,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(8))) void k
     const double *__restrict__ hext, double *__restrict__ H, double *__restrict__ Hs,
     double *__restrict__ e_part, int32_t *__restrict__ cnt_far, int32_t *__restrict__ cnt_near,
     uint32_t *__restrict__ status, int64_t n, int64_t ntot, int waves_per_seg, int num_waves,
-    double theta2, int max_nodes, const void *__restrict__ node_q)
+    double theta2, int max_nodes, const void *__restrict__ node_q, const uint32_t *__restrict__ tgt_order)
 {
     using T = typename std::conditional<MIXED, float, double>::type;
     using Src = typename std::conditional<MIXED, Src32, Src64>::type;
@@ -84,7 +84,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(8))) void k
     const int seg = gw / waves_per_seg;
     const int local = (gw - seg * waves_per_seg) * kWave + lane;
     const bool valid = local < n;
-    const int si = (int)(seg * n) + (valid ? local : 0);
+    const int si = target_of(tgt_order, seg, n, local, valid);
     const double rx = spos[si], ry = spos[ntot + si], rz = spos[2 * ntot + si];
 
     double hx = 0.0, hy = 0.0, hz = 0.0;  // FP64 accumulation
@@ -239,7 +239,7 @@ static void launch_k_field(Handle &h, const double *d_hext, double *d_H, hipStre
     hipLaunchKernelGGL((k_field<MIXED, COUNT, QUAD>), dim3(blocks), dim3(wpb * kWave), lds, s, w.nodes,
                        w.node_m64, w.spos, w.smom, src, w.perm, d_hext, d_H, w.Hs, w.e_part,
                        h.cnt_far, h.cnt_near, w.status, L.n, L.ntot, waves_per_seg, (int)L.num_waves, theta2,
-                       (int)L.max_nodes, q);
+                       (int)L.max_nodes, q, uses_target_order(L) ? w.tgt_order : nullptr);
 }
 
 hipError_t launch_field(Handle &h, const double *d_mom, const double *d_hext, double *d_H, double *d_E,

@@ -267,17 +267,15 @@ __global__ void k_step_inc(uint64_t *d_step)
     if (threadIdx.x == 0 && blockIdx.x == 0) *d_step += 1ull;
 }
 
-// Below this many particles (over the batch) the fork and join cost more than the overlap gains.
-constexpr int64_t kForkMinParticles = 1 << 14;
-
 hipError_t launch_md(Handle &h, const md_state *st, const md_params *mp, hipStream_t s)
 {
     const Layout &L = h.L;
     Workspace &w = h.w;
     // Two streams.  The caller's carries build -> fused traversal -> downward pass -> integrator.  The
-    // side stream orders the traversal's items (from the costs of the previous step) and computes the
-    // short-range forces as soon as the build has sorted the particles, both beside the rest of the build
-    // (octree, levels, upward pass: short, latency-bound launches).  The side stream rejoins the caller's
+    // side stream orders the traversal's items (from the costs of the previous step) beside the bounding
+    // cube and the sort, and, as soon as the build has sorted the particles, puts the targets in Hilbert
+    // order and computes the short-range forces beside the rest of the build (octree, levels, upward pass:
+    // short, latency-bound launches).  The side stream rejoins the caller's
     // before the traversal, which therefore has the whole device.  The step starts after everything
     // enqueued on the caller's stream before it and is complete for everything enqueued after it; under
     // graph capture the fork and the join become edges.  Small systems keep everything on one stream.
@@ -290,9 +288,9 @@ hipError_t launch_md(Handle &h, const md_state *st, const md_params *mp, hipStre
         if ((e = hipStreamWaitEvent(h.side, h.fork_ev, 0)) != hipSuccess) return e;
         launch_order_waves(h, h.side);
     }
-    e = launch_build(h, st->pos, s, st->mom, fork ? h.sorted_ev : nullptr);  // tree, centroids, moment sums
+    // tree, centroids, moment sums; the target order on the side stream, which goes on below
+    e = launch_build(h, st->pos, s, st->mom, fork ? h.side : nullptr, false);
     if (e != hipSuccess) return e;
-    if (fork && (e = hipStreamWaitEvent(h.side, h.sorted_ev, 0)) != hipSuccess) return e;
     // sr_kind 0: WCA, pair and wall cut at the potential minimum; 1: the paper's form, walls at half the pair cut
     const double wca_rc = 1.122462048309373;  // 2^(1/6)
     const bool lj = mp->sr_kind == 1;

@@ -469,6 +469,17 @@ struct LdsTarget {
     int si, pad;
 };
 
+// Sorted position of target `local` of system seg: entry seg n + local of the target order, or seg n + local
+// without one.  Lanes past the system's end take its first particle (they only read it).
+__device__ inline int target_of(const uint32_t *__restrict__ order, int seg, int64_t n, int local, bool valid)
+{
+    const int base = (int)(seg * n);
+    if (!valid) return base;
+    if (!order) return base + local;
+    const uint32_t o = order[base + local];
+    return (o - (uint32_t)base) < (uint32_t)n ? (int)o : base + local;  // always in range for a consistent order
+}
+
 extern __shared__ __align__(16) unsigned char ffbh_dyn_lds[];
 
 // Logical block index, arranged so that each of the 8 XCDs (which receive workgroups round-robin)
