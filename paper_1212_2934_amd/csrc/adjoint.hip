@@ -195,11 +195,11 @@ __device__ inline void close_pairs(AdjLds<float> &W, int lane, bool valid, int s
         double *__restrict__ Hout, double *__restrict__ e_part, uint32_t *__restrict__ status, int64_t n,        \
         int64_t ntot, int waves_per_seg, int num_waves, double theta2, int max_nodes, int tpw, int parts,        \
         double *__restrict__ part_buf, uint32_t *__restrict__ wave_cost, const void *__restrict__ node_q,         \
-        double *__restrict__ node_adjq, const uint32_t *__restrict__ tgt_order
+        double *__restrict__ node_adjq, const uint32_t *__restrict__ tgt_order, int inside_test
 #define FFBH_ADJ_ARGS                                                                                           \
     nodes, node_m64, spos, smom, src, hbar, perm, hext, g_gather, g_rm, node_adj, Hs, Hout, e_part, status, n,   \
         ntot, waves_per_seg, num_waves, theta2, max_nodes, tpw, parts, part_buf, wave_cost, node_q, node_adjq,  \
-        tgt_order
+        tgt_order, inside_test
 
 // The fused walk of wave item gw.  If wave_cost is not null, lane 0 stores there a deterministic measure of
 // the item's work (node visits plus leaf pair rounds), which orders the next launch.  QUAD: order-2 cells
@@ -262,15 +262,16 @@ __device__ __forceinline__ void adjoint_wave(int gw, FFBH_ADJ_PARAMS)
         const int cur = st.pop(mask);
         const NodeRec nd = nodes[cur];
         ++work;
-        // masks of the lanes that take part, of the targets inside the node and of the acceptance test
-        const uint64_t insm = ballot((unsigned)(si - nd.first) < (unsigned)nd.count);
+        // masks of the lanes that take part, of the targets inside the node (opened whatever the test
+        // says; below kSelfRejectTheta2 the test rejects them itself) and of the acceptance test
+        uint64_t insm = 0ull;
+        if (inside_test) insm = ballot((unsigned)(si - nd.first) < (unsigned)nd.count);
         const double dx = rx - nd.cx, dy = ry - nd.cy, dz = rz - nd.cz;
         const double d2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
         const uint64_t accm = mask & ~insm & ballot(nd.s2 < theta2 * d2);
         const bool acc = lane_in(accm);
-        {
-            // nearly every visit has accepting lanes, so the pair is evaluated unconditionally (lanes that
-            // do not accept add zeros) and only the scatter is skipped for an empty mask
+        if (accm != 0ull) {
+            // the whole wave evaluates the pair (lanes that do not accept add zeros)
             T bx, by, bz;
             if (MIXED) {
                 bx = (T)nd.mx; by = (T)nd.my; bz = (T)nd.mz;
@@ -738,11 +739,13 @@ hipError_t launch_backward(Handle &h, const double *d_mom, const double *d_hext,
         uint32_t *cost = parts == 1 ? w.wave_cost : nullptr;
         const void *nq = mixed ? (const void *)w.node_q32 : (const void *)w.node_q64;
         const uint32_t *tgt = uses_target_order(L) ? w.tgt_order : nullptr;
+        const int inside = theta2 > kSelfRejectTheta2 ? 1 : 0;
 #define FFBH_ADJ(MX, QD, T)                                                                                     \
     hipLaunchKernelGGL((k_adjoint<MX, QD>), dim3(grid), dim3(wpb * kWave), wpb * sizeof(AdjLds<T>), s, w.nodes,     \
                        w.node_m64, w.spos, w.smom, MX ? w.src32 : w.src64, w.hbar, w.perm, d_hext, w.g_gather,    \
                        w.g_rm, w.node_adj, w.Hs, d_H, w.e_part, w.status, L.n, L.ntot, wps, nwv, theta2,          \
-                       (int)L.max_nodes, tpw, parts, w.part_buf, cost, nq, w.node_adjq, tgt, ord, w.sched_ctr)
+                       (int)L.max_nodes, tpw, parts, w.part_buf, cost, nq, w.node_adjq, tgt, inside, ord,         \
+                       w.sched_ctr)
         if (mixed && quad) FFBH_ADJ(true, true, float);
         else if (mixed) FFBH_ADJ(true, false, float);
         else if (quad) FFBH_ADJ(false, true, double);

@@ -853,63 +853,76 @@ __global__ __launch_bounds__(256) void k_oct_link(int64_t nint_tot, int64_t B, c
 }
 
 // ------------------------------------------------------------------------------------------------
-// Upward pass, level by level from the deepest cell level to the root.  A leaf sums its members in
-// sorted order starting from +0.0; a parent sums its children's sums in octant order (the order they
-// are stored in).  Every child of a level-l cell sits at a deeper level, so one launch per level (21
-// down to 0) sees all children finished.  Nodes are bucketed by level once per build.
+// Upward pass: first every leaf (in one launch: a leaf sums its members in sorted order starting from
+// +0.0, whatever its level), then the internal nodes level by level from the deepest cell level to the
+// root (a parent sums its children's sums in octant order, the order they are stored in).  Every child
+// of a level-l cell is a leaf or sits at a deeper level, so one launch per level (21 down to 0) sees all
+// children finished.  Nodes are bucketed once per build: internal nodes by level (buckets 0..21), leaves
+// in bucket kLeafBucket.
 //   MODE 0: positions -> centroid S / count and squared side into the node record, and the exact
 //           bounding box of the members (used by short-range neighbour queries).
 //   MODE 1: moments   -> FP64 moment sum into node_m64 and its FP32 rounding into the record.
 // ------------------------------------------------------------------------------------------------
 
-__global__ __launch_bounds__(256) void k_level_count(const int32_t *__restrict__ node_level,
+constexpr int kLeafBucket = kMaxLevel + 1;
+constexpr int kBuckets = kMaxLevel + 2;
+
+__device__ inline int bucket_of(const NodeRec *__restrict__ nodes, const int32_t *__restrict__ node_level, int64_t i)
+{
+    const int lev = node_level[i];
+    if ((unsigned)lev > (unsigned)kMaxLevel) return -1;
+    return nodes[i].nchild == 0 ? kLeafBucket : lev;
+}
+
+__global__ __launch_bounds__(256) void k_level_count(const NodeRec *__restrict__ nodes,
+                                                     const int32_t *__restrict__ node_level,
                                                      const uint32_t *__restrict__ num_nodes, int64_t max_nodes,
                                                      uint32_t *__restrict__ lvl)
 {
-    __shared__ uint32_t h[kMaxLevel + 1];
-    if (threadIdx.x <= kMaxLevel) h[threadIdx.x] = 0u;
+    __shared__ uint32_t h[kBuckets];
+    if (threadIdx.x < kBuckets) h[threadIdx.x] = 0u;
     __syncthreads();
     const int64_t nn = min((int64_t)*num_nodes, max_nodes);
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nn; i += (int64_t)gridDim.x * 256) {
-        const int lev = node_level[i];
-        if ((unsigned)lev <= (unsigned)kMaxLevel) atomicAdd(&h[lev], 1u);
+        const int bk = bucket_of(nodes, node_level, i);
+        if (bk >= 0) atomicAdd(&h[bk], 1u);
     }
     __syncthreads();
-    if (threadIdx.x <= kMaxLevel && h[threadIdx.x]) atomicAdd(&lvl[threadIdx.x], h[threadIdx.x]);
+    if (threadIdx.x < kBuckets && h[threadIdx.x]) atomicAdd(&lvl[threadIdx.x], h[threadIdx.x]);
 }
 
-// lvl[0..21] counts -> lvl[32..54] bucket starts (exclusive, 23 entries), lvl[64..85] cursors.
+// lvl[0..22] counts -> lvl[32..55] bucket starts (exclusive, 24 entries), lvl[64..86] cursors.
 __global__ void k_level_starts(uint32_t *lvl)
 {
     if (threadIdx.x != 0) return;
     uint32_t acc = 0;
-    for (int l = 0; l <= kMaxLevel; ++l) {
+    for (int l = 0; l < kBuckets; ++l) {
         lvl[32 + l] = acc;
         lvl[64 + l] = acc;
         acc += lvl[l];
     }
-    lvl[32 + kMaxLevel + 1] = acc;
+    lvl[32 + kBuckets] = acc;
 }
 
 // One block per 256 node ids: ranks within the block come from LDS atomics, and one global atomic per
-// level and block reserves the block's slots.
-__global__ __launch_bounds__(256) void k_level_scatter(const int32_t *__restrict__ node_level,
+// bucket and block reserves the block's slots.
+__global__ __launch_bounds__(256) void k_level_scatter(const NodeRec *__restrict__ nodes,
+                                                       const int32_t *__restrict__ node_level,
                                                        const uint32_t *__restrict__ num_nodes, int64_t max_nodes,
                                                        uint32_t *__restrict__ lvl, int32_t *__restrict__ lvl_nodes)
 {
-    __shared__ uint32_t cnt[kMaxLevel + 1], base[kMaxLevel + 1];
+    __shared__ uint32_t cnt[kBuckets], base[kBuckets];
     const int64_t nn = min((int64_t)*num_nodes, max_nodes);
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if ((int64_t)blockIdx.x * 256 >= nn) return;  // whole block beyond the nodes
-    if (threadIdx.x <= kMaxLevel) cnt[threadIdx.x] = 0u;
+    if (threadIdx.x < kBuckets) cnt[threadIdx.x] = 0u;
     __syncthreads();
-    int lev = i < nn ? node_level[i] : -1;
-    if (lev > kMaxLevel) lev = -1;
-    const uint32_t r = lev >= 0 ? atomicAdd(&cnt[lev], 1u) : 0u;
+    const int bk = i < nn ? bucket_of(nodes, node_level, i) : -1;
+    const uint32_t r = bk >= 0 ? atomicAdd(&cnt[bk], 1u) : 0u;
     __syncthreads();
-    if (threadIdx.x <= kMaxLevel && cnt[threadIdx.x]) base[threadIdx.x] = atomicAdd(&lvl[64 + threadIdx.x], cnt[threadIdx.x]);
+    if (threadIdx.x < kBuckets && cnt[threadIdx.x]) base[threadIdx.x] = atomicAdd(&lvl[64 + threadIdx.x], cnt[threadIdx.x]);
     __syncthreads();
-    if (lev >= 0 && (int64_t)base[lev] + r < max_nodes) lvl_nodes[base[lev] + r] = (int32_t)i;
+    if (bk >= 0 && (int64_t)base[bk] + r < max_nodes) lvl_nodes[base[bk] + r] = (int32_t)i;
 }
 
 __global__ void k_zero_u32(uint32_t *a, int len)
@@ -1053,13 +1066,13 @@ __global__ __launch_bounds__(256) void k_upward_level(const double *__restrict__
                           q64, q32);
 }
 
-// Levels level_hi down to level_lo in one workgroup, deepest first, a barrier between levels (the
-// children's sums are written by this workgroup before their parents read them): where the per-level
-// launches of k_upward_level would cost more than the work.  Any number of nodes is handled; few are
-// expected.
+// Buckets level_hi down to level_lo in one workgroup (kLeafBucket, the leaves, comes first; then the
+// internal nodes of levels 21 .. 0), a barrier between buckets (the children's sums are written by this
+// workgroup before their parents read them): where the per-level launches of k_upward_level would cost
+// more than the work.  Any number of nodes is handled; few are expected.
 constexpr int kUpwardOneThreads = 1024;
 constexpr int64_t kUpwardOneMaxNodes = 1 << 16;
-// Larger trees: the levels at and below kUpwardDeepLevel hold a node only where more than leaf_size
+// Larger trees: the levels at and below kUpwardDeepLevel hold an internal node only where more than leaf_size
 // particles share a cell 2^-kUpwardDeepLevel of the cube wide (none in the dense liquids and chain
 // systems simulated), so they take one workgroup launch.  (The top levels are not merged: one
 // workgroup walks their few hundred cells more slowly than four grid launches.)
@@ -1093,16 +1106,20 @@ static void upward(Handle &h, const double *vals, const double *vals2, hipStream
                            w.nodes, w.node_adj, w.node_m64, w.node_level, w.lvl, w.lvl_nodes, w.bbox, L.max_nodes,
                            w.node_q64, w.node_q32, level_hi, level_lo);
     };
+    auto level = [&](int bucket) {
+        const unsigned g = grid_for(L.max_nodes, 256, bucket == kLeafBucket ? 1024 : 512);
+        hipLaunchKernelGGL(k_upward_level<MODE>, dim3(g), dim3(256), 0, s, vals,
+                           vals2, L.ntot, L.n, w.nodes, w.node_adj, w.node_m64, w.node_level, w.lvl, w.lvl_nodes,
+                           w.bbox, bucket, L.max_nodes, w.node_q64, w.node_q32);
+    };
     if (L.max_nodes <= kUpwardOneMaxNodes) {
-        one(kMaxLevel, 0);
+        one(kLeafBucket, 0);  // the leaves, then levels 21 .. 0
         return;
     }
+    // the leaves hold every member: one launch over all of them; then the internal levels
+    level(kLeafBucket);
     one(kMaxLevel, kUpwardDeepLevel);
-    const unsigned g = grid_for(L.max_nodes, 256, 512);
-    for (int level = kUpwardDeepLevel - 1; level >= 0; --level)
-        hipLaunchKernelGGL(k_upward_level<MODE>, dim3(g), dim3(256), 0, s, vals, vals2, L.ntot, L.n, w.nodes,
-                           w.node_adj, w.node_m64, w.node_level, w.lvl, w.lvl_nodes, w.bbox, level, L.max_nodes,
-                           w.node_q64, w.node_q32);
+    for (int l = kUpwardDeepLevel - 1; l >= 0; --l) level(l);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -1179,11 +1196,11 @@ hipError_t launch_build(Handle &h, const double *d_pos, hipStream_t s, const dou
                            w.bin_nchild, w.bin_scan, w.bin_octid, w.nodes, L.max_nodes);
     // bucket the nodes by level, then the upward pass for the centroids
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(128), 0, s, w.lvl, 128);
-    hipLaunchKernelGGL(k_level_count, dim3(grid_for(L.max_nodes, 256, 1024)), dim3(256), 0, s, w.node_level,
-                       w.status + 2, L.max_nodes, w.lvl);
+    hipLaunchKernelGGL(k_level_count, dim3(grid_for(L.max_nodes, 256, 1024)), dim3(256), 0, s, w.nodes,
+                       w.node_level, w.status + 2, L.max_nodes, w.lvl);
     hipLaunchKernelGGL(k_level_starts, dim3(1), dim3(64), 0, s, w.lvl);
-    hipLaunchKernelGGL(k_level_scatter, dim3(grid_for(L.max_nodes, 256)), dim3(256), 0, s, w.node_level,
-                       w.status + 2, L.max_nodes, w.lvl, w.lvl_nodes);
+    hipLaunchKernelGGL(k_level_scatter, dim3(grid_for(L.max_nodes, 256)), dim3(256), 0, s, w.nodes,
+                       w.node_level, w.status + 2, L.max_nodes, w.lvl, w.lvl_nodes);
     if (d_mom) {
         // positions and moments summed in one upward pass
         gather_moments(h, d_mom, s);

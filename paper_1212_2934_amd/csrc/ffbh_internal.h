@@ -21,6 +21,10 @@ constexpr int kSortThreads = 256;
 constexpr int kSortItems = 16;                  // most keys per thread per tile
 constexpr int kMinTpw = 16;                     // fewest targets an adjoint wave owns
 constexpr int kStackMax = 64;                   // one traversal stack entry per lane of a wave
+// Largest theta^2 for which the acceptance test alone rejects every cell holding the target: target and
+// centre lie in the cell's cube of side s, so d^2 <= 3 s^2, and theta^2 d^2 < s^2 holds with a margin of
+// at least 10 %, far above rounding.  Up to it the traversals skip the explicit test for the target.
+constexpr double kSelfRejectTheta2 = 0.3;
 constexpr int kHilbertBits = 8;                 // bits per axis of the Hilbert keys that group targets
 constexpr int64_t kTargetOrderMin = 2049;       // systems from this size group targets in Hilbert order
 constexpr int64_t kForkMinParticles = 1 << 14;  // fewer particles over the batch stay on one stream
@@ -80,8 +84,8 @@ struct Workspace {
     float *node_q32;         // max_nodes x 16: the same rounded to FP32 (mixed-precision traversal)
     double *node_adjq;       // max_nodes x 8: dL/dD of each node, symmetric (xx, yy, zz, xy, xz, yz)
     double *ones;            // B: constant 1.0 (dL/dE for the MD force)
-    uint32_t *lvl;           // 128: per-level node counts [0,22), bucket starts [32,55), cursors [64,86)
-    int32_t *lvl_nodes;      // max_nodes: node ids bucketed by level
+    uint32_t *lvl;           // 128: per-bucket node counts [0,23), bucket starts [32,56), cursors [64,87)
+    int32_t *lvl_nodes;      // max_nodes: node ids bucketed (internal nodes by level 0..21, leaves in 22)
     int32_t *leaf_of;        // N_tot: sorted particle -> its leaf
     // traversal outputs and adjoint accumulators
     double *e_part;          // per wave energy partials

@@ -72,7 +72,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(8))) void k
     const double *__restrict__ hext, double *__restrict__ H, double *__restrict__ Hs,
     double *__restrict__ e_part, int32_t *__restrict__ cnt_far, int32_t *__restrict__ cnt_near,
     uint32_t *__restrict__ status, int64_t n, int64_t ntot, int waves_per_seg, int num_waves,
-    double theta2, int max_nodes, const void *__restrict__ node_q, const uint32_t *__restrict__ tgt_order)
+    double theta2, int max_nodes, const void *__restrict__ node_q, const uint32_t *__restrict__ tgt_order,
+    int inside_test)
 {
     using T = typename std::conditional<MIXED, float, double>::type;
     using Src = typename std::conditional<MIXED, Src32, Src64>::type;
@@ -106,16 +107,17 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(8))) void k
         uint64_t mask;
         const int cur = st.pop(mask);
         const NodeRec nd = nodes[cur];
-        // masks of the lanes that take part, of the targets inside the node and of the acceptance test
-        const uint64_t insm = ballot((unsigned)(si - nd.first) < (unsigned)nd.count);
+        // masks of the lanes that take part, of the targets inside the node (opened whatever the test
+        // says; below kSelfRejectTheta2 the test rejects them itself) and of the acceptance test
+        uint64_t insm = 0ull;
+        if (inside_test) insm = ballot((unsigned)(si - nd.first) < (unsigned)nd.count);
         // acceptance test in FP64, exactly as defined
         const double dx = rx - nd.cx, dy = ry - nd.cy, dz = rz - nd.cz;
         const double d2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
         const uint64_t accm = mask & ~insm & ballot(nd.s2 < theta2 * d2);
         const bool acc = lane_in(accm);
-        {
-            // nearly every visit has accepting lanes, so the whole wave computes unconditionally (lanes that
-            // do not accept add exact zeros)
+        if (accm != 0ull) {
+            // the whole wave computes (lanes that do not accept add exact zeros)
             if (MIXED) {
                 dip_acc_r2<T>(acc, (T)d2, (T)dx, (T)dy, (T)dz, (T)nd.mx, (T)nd.my, (T)nd.mz, px, py, pz);
             } else {
@@ -239,7 +241,8 @@ static void launch_k_field(Handle &h, const double *d_hext, double *d_H, hipStre
     hipLaunchKernelGGL((k_field<MIXED, COUNT, QUAD>), dim3(blocks), dim3(wpb * kWave), lds, s, w.nodes,
                        w.node_m64, w.spos, w.smom, src, w.perm, d_hext, d_H, w.Hs, w.e_part,
                        h.cnt_far, h.cnt_near, w.status, L.n, L.ntot, waves_per_seg, (int)L.num_waves, theta2,
-                       (int)L.max_nodes, q, uses_target_order(L) ? w.tgt_order : nullptr);
+                       (int)L.max_nodes, q, uses_target_order(L) ? w.tgt_order : nullptr,
+                       theta2 > kSelfRejectTheta2 ? 1 : 0);
 }
 
 hipError_t launch_field(Handle &h, const double *d_mom, const double *d_hext, double *d_H, double *d_E,
