@@ -100,7 +100,28 @@ int32_t bh_num_tunings(void);
  * internally (forked from and joined back into the caller's stream within the call); bh_destroy waits for
  * that stream and releases them. */
 bh_status bh_create(const bh_params *p, void *d_workspace, size_t workspace_bytes, bh_handle **out);
+/* Release a handle made by bh_create (BH_EINVAL for one made by bh_init). */
 bh_status bh_destroy(bh_handle *h);
+
+/* Bytes of host memory a handle occupies (the mem argument of bh_init). */
+size_t bh_handle_bytes(void);
+
+/* A handle in caller-owned memory, for callers that do not let the library allocate.  mem (at least
+ * bh_handle_bytes() bytes, 16-byte aligned, host memory owned by the caller) receives a handle bound to the
+ * current HIP device and to d_workspace, as bh_create makes it, but nothing is allocated: no host memory,
+ * no stream, no event.  Two small kernels that set the workspace's status word and constants are enqueued
+ * on `stream`; later calls on the handle are ordered after them by the caller, as any two calls are.
+ * Without a side stream bh_build and md_step enqueue all their work on the caller's stream: results equal
+ * those of a bh_create handle (the adjoint's to the rounding of its atomics), and large MD steps lose the
+ * overlap of the short-range forces with the tree build.  Errors: BH_EINVAL for a null, short or
+ * misaligned mem, bad parameters or a null out; BH_EWORKSPACE as for bh_create; BH_EDEVICE on a HIP error
+ * (mem then holds no handle).  End it with bh_fini. */
+bh_status bh_init(void *mem, size_t mem_bytes, const bh_params *p, void *d_workspace, size_t workspace_bytes,
+                  void *stream, bh_handle **out);
+
+/* End a handle made by bh_init.  Frees nothing: mem and the workspace are the caller's again once the
+ * handle's work enqueued so far has finished.  BH_EINVAL for a handle made by bh_create. */
+bh_status bh_fini(bh_handle *h);
 
 /* Build the tree for positions d_pos (B, 3, n): bounding cube, Morton codes, radix sort, octree and
  * the geometric centre of every cell (Sec. 3.2 kernels 1-4, Eq. magCenter positions).  Systems of more

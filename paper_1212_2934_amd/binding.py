@@ -59,6 +59,12 @@ def lib():
         L.bh_num_tunings.restype = i32
         L.bh_create.argtypes = [C.POINTER(bh_params), P, C.c_size_t, C.POINTER(P)]
         L.bh_destroy.argtypes = [P]
+        L.bh_handle_bytes.argtypes = []
+        L.bh_handle_bytes.restype = C.c_size_t
+        L.bh_init.argtypes = [P, C.c_size_t, C.POINTER(bh_params), P, C.c_size_t, P, C.POINTER(P)]
+        L.bh_init.restype = i32
+        L.bh_fini.argtypes = [P]
+        L.bh_fini.restype = i32
         L.bh_build.argtypes = [P, P, P]
         L.bh_field.argtypes = [P, P, P, P, P, P]
         L.bh_field_backward.argtypes = [P, P, P, P, P, P, P, P, P]
@@ -90,7 +96,8 @@ def lib():
     return _lib
 
 
-EXPORTED = ["bh_workspace_bytes", "bh_num_tunings", "bh_create", "bh_destroy", "bh_build", "bh_field",
+EXPORTED = ["bh_workspace_bytes", "bh_num_tunings", "bh_create", "bh_destroy", "bh_handle_bytes", "bh_init",
+            "bh_fini", "bh_build", "bh_field",
             "bh_field_backward", "md_step", "bh_check_status", "bh_enable_counters", "bh_num_nodes",
             "bh_export_tree", "bh_set_timing_events", "bh_graph_capture_md", "bh_graph_launch",
             "bh_graph_destroy", "bh_allpairs", "bh_field_noalloc", "bh_morton_code", "bh_status_str"]
@@ -139,7 +146,9 @@ class BarnesHut:
     """
 
     def __init__(self, n, batch=1, leaf_size=16, theta=0.5, precision="fp32_mixed", tuning_id=-1,
-                 device=None, expansion=1):
+                 device=None, expansion=1, caller_memory=False):
+        """caller_memory: the handle lives in host memory held here (bh_init) instead of the library's
+        (bh_create); it then has no side stream."""
         self.params = make_params(n, batch, leaf_size, theta, precision, tuning_id, expansion)
         self.n, self.batch = int(n), int(batch)
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None \
@@ -149,16 +158,28 @@ class BarnesHut:
         base = self.workspace.data_ptr()
         off = (-base) % 256
         h = C.c_void_p()
+        self._hmem = None
         with torch.cuda.device(self.device):
-            _check("bh_create", lib().bh_create(C.byref(self.params), C.c_void_p(base + off),
-                                                C.c_size_t(nbytes), C.byref(h)))
+            if caller_memory:
+                hb = int(lib().bh_handle_bytes())
+                self._hmem = (C.c_char * (hb + 16))()
+                addr = C.addressof(self._hmem)
+                _check("bh_init", lib().bh_init(C.c_void_p(addr + (-addr) % 16), C.c_size_t(hb),
+                                                C.byref(self.params), C.c_void_p(base + off), C.c_size_t(nbytes),
+                                                _stream(), C.byref(h)))
+            else:
+                _check("bh_create", lib().bh_create(C.byref(self.params), C.c_void_p(base + off),
+                                                    C.c_size_t(nbytes), C.byref(h)))
         self._h = h
         self._counters = None
 
     def __del__(self):
         h = getattr(self, "_h", None)
         if h is not None and _lib is not None:
-            _lib.bh_destroy(h)
+            if getattr(self, "_hmem", None) is not None:
+                _lib.bh_fini(h)
+            else:
+                _lib.bh_destroy(h)
             self._h = None
 
     # -- shapes -----------------------------------------------------------------------------------

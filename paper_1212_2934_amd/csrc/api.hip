@@ -238,6 +238,8 @@ struct bh_handle {
 };
 
 // The MD step's side stream and events (none of them carries timing).
+constexpr size_t kHandleAlign = 16;  // alignment bh_init asks of the caller's memory
+
 static hipError_t create_side(Handle &h)
 {
     h.side = nullptr;
@@ -274,6 +276,38 @@ uint64_t bh_morton_code(uint32_t qx, uint32_t qy, uint32_t qz)
     return morton(qx & kQMax, qy & kQMax, qz & kQMax);
 }
 
+// What bh_create and bh_init share: the handle's fields (no side stream yet) and the launch shape.
+static hipError_t setup_handle(Handle &h, const bh_params *p, const Layout &L, void *d_workspace)
+{
+    h.p = *p;
+    h.L = L;
+    carve(L, d_workspace, h.w);
+    h.side = nullptr;
+    h.fork_ev = h.sorted_ev = h.join_ev = nullptr;
+    h.built = 0;
+    const int tid = p->tuning_id < 0 ? 0 : p->tuning_id;
+    h.waves_per_block = kTuneWaves[tid];
+    h.adj_tpw = kTuneTpw[tid];
+    h.adj_parts = kTuneParts[tid];
+    h.adj_sched = kTuneSched[tid];
+    h.adj_resident = 0;
+    h.cnt_far = h.cnt_near = nullptr;
+    for (int k = 0; k < 4; ++k) h.ev[k] = nullptr;
+    hipError_t e = hipGetDevice(&h.device);
+    if (e == hipSuccess && h.adj_sched) e = adjoint_resident_blocks(h, h.adj_resident);
+    return e;
+}
+
+// The workspace words that must start at zero (status) or hold constants (ones, first-launch costs).
+static hipError_t init_workspace(Handle &h, hipStream_t s)
+{
+    const Layout &L = h.L;
+    hipLaunchKernelGGL(k_init, dim3(1), dim3(256), 0, s, h.w.status, h.w.ones, (int64_t)L.B);
+    hipLaunchKernelGGL(k_fill_u32, dim3(64), dim3(256), 0, s, h.w.wave_cost,
+                       (int64_t)(L.B * ((L.n + kMinTpw - 1) / kMinTpw)), 0u);
+    return hipGetLastError();
+}
+
 bh_status bh_create(const bh_params *p, void *d_workspace, size_t workspace_bytes, bh_handle **out)
 {
     if (!params_ok(p) || !out) return BH_EINVAL;
@@ -282,34 +316,17 @@ bh_status bh_create(const bh_params *p, void *d_workspace, size_t workspace_byte
     bh_handle *hh = new (std::nothrow) bh_handle();
     if (!hh) return BH_EDEVICE;
     Handle &h = hh->h;
-    h.p = *p;
-    h.L = L;
-    carve(L, d_workspace, h.w);
-    if (hipGetDevice(&h.device) != hipSuccess) {
+    h.owned = 1;
+    if (setup_handle(h, p, L, d_workspace) != hipSuccess) {
         delete hh;
         return BH_EDEVICE;
     }
-    h.built = 0;
-    h.waves_per_block = kTuneWaves[p->tuning_id < 0 ? 0 : p->tuning_id];
-    h.adj_tpw = kTuneTpw[p->tuning_id < 0 ? 0 : p->tuning_id];
-    h.adj_parts = kTuneParts[p->tuning_id < 0 ? 0 : p->tuning_id];
-    h.adj_sched = kTuneSched[p->tuning_id < 0 ? 0 : p->tuning_id];
-    h.adj_resident = 0;
-    if (h.adj_sched && adjoint_resident_blocks(h, h.adj_resident) != hipSuccess) {
-        delete hh;
-        return BH_EDEVICE;
-    }
-    h.cnt_far = h.cnt_near = nullptr;
-    for (int k = 0; k < 4; ++k) h.ev[k] = nullptr;
     if (create_side(h) != hipSuccess) {
         destroy_side(h);
         delete hh;
         return BH_EDEVICE;
     }
-    hipLaunchKernelGGL(k_init, dim3(1), dim3(256), 0, 0, h.w.status, h.w.ones, (int64_t)L.B);
-    hipLaunchKernelGGL(k_fill_u32, dim3(64), dim3(256), 0, 0, h.w.wave_cost,
-                       (int64_t)(L.B * ((L.n + kMinTpw - 1) / kMinTpw)), 0u);
-    if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+    if (init_workspace(h, nullptr) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
         destroy_side(h);
         delete hh;
         return BH_EDEVICE;
@@ -320,11 +337,39 @@ bh_status bh_create(const bh_params *p, void *d_workspace, size_t workspace_byte
 
 bh_status bh_destroy(bh_handle *h)
 {
-    if (!h) return BH_EINVAL;
+    if (!h || !h->h.owned) return BH_EINVAL;
     // a step still running on the side stream must not lose its stream
     if (h->h.side) (void)hipStreamSynchronize(h->h.side);
     destroy_side(h->h);
     delete h;
+    return BH_OK;
+}
+
+size_t bh_handle_bytes(void) { return sizeof(bh_handle); }
+
+bh_status bh_init(void *mem, size_t mem_bytes, const bh_params *p, void *d_workspace, size_t workspace_bytes,
+                  void *stream, bh_handle **out)
+{
+    if (!mem || mem_bytes < sizeof(bh_handle) || ((uintptr_t)mem % kHandleAlign) != 0) return BH_EINVAL;
+    if (!params_ok(p) || !out) return BH_EINVAL;
+    Layout L = plan_layout(*p);
+    if (!d_workspace || ((uintptr_t)d_workspace % 256) != 0 || workspace_bytes < L.bytes) return BH_EWORKSPACE;
+    static_assert(alignof(bh_handle) <= kHandleAlign, "handle alignment");
+    bh_handle *hh = new (mem) bh_handle();
+    Handle &h = hh->h;
+    h.owned = 0;
+    if (setup_handle(h, p, L, d_workspace) != hipSuccess || init_workspace(h, (hipStream_t)stream) != hipSuccess) {
+        hh->~bh_handle();
+        return BH_EDEVICE;
+    }
+    *out = hh;
+    return BH_OK;
+}
+
+bh_status bh_fini(bh_handle *h)
+{
+    if (!h || h->h.owned) return BH_EINVAL;
+    h->~bh_handle();
     return BH_OK;
 }
 

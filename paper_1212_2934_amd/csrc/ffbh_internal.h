@@ -122,6 +122,8 @@ struct Handle {
     Workspace w;
     int device;
     int built;           // a bh_build has been enqueued
+    int owned;           // 1: made by bh_create (host memory, side stream and events are the library's);
+                         // 0: made by bh_init in the caller's memory (nothing allocated, no side stream)
     int waves_per_block; // traversal launch shape
     int adj_tpw;         // targets per independent adjoint wave (16, 32 or 64)
     int adj_parts;       // independent adjoint walks split over the root's children (8) or not (1)

@@ -278,9 +278,10 @@ hipError_t launch_md(Handle &h, const md_state *st, const md_params *mp, hipStre
     // short, latency-bound launches).  The side stream rejoins the caller's
     // before the traversal, which therefore has the whole device.  The step starts after everything
     // enqueued on the caller's stream before it and is complete for everything enqueued after it; under
-    // graph capture the fork and the join become edges.  Small systems keep everything on one stream.
+    // graph capture the fork and the join become edges.  Small systems, and handles without a side stream,
+    // keep everything on one stream.
     hipError_t e;
-    const bool fork = L.ntot >= kForkMinParticles;
+    const bool fork = L.ntot >= kForkMinParticles && h.side != nullptr;  // a bh_init handle has no side stream
     const hipStream_t ss = fork ? h.side : s;
     const bool order = fork && uses_wave_order(h);  // else launch_backward orders the items itself
     if (order) {

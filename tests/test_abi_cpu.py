@@ -14,7 +14,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def _declared():
     src = open(os.path.join(ROOT, "include", "ffbh.h")).read()
-    return sorted(set(re.findall(r"^\s*(?:const char \*\s*|bh_status\s+|int32_t\s+|uint64_t\s+)(\w+)\s*\(",
+    return sorted(set(re.findall(r"^\s*(?:const char \*\s*|bh_status\s+|int32_t\s+|uint64_t\s+|size_t\s+)(\w+)\s*\(",
                                  src, re.M)))
 
 
@@ -49,6 +49,33 @@ def test_create_rejects_missing_or_small_workspace():
     assert L.bh_create(C.byref(p), C.c_void_p(257), 1 << 40, C.byref(h)) == binding.BH_EWORKSPACE
     assert L.bh_build(None, None, None) == binding.BH_EINVAL
     assert L.bh_field(None, None, None, None, None, None) == binding.BH_EINVAL
+
+
+def test_caller_owned_handle_rejects_bad_memory_before_any_device_call():
+    """bh_init checks the caller's handle memory, the parameters and the workspace before any HIP call;
+    bh_fini and bh_destroy refuse null handles."""
+    import ctypes as C
+    L = binding.lib()
+    hb = int(L.bh_handle_bytes())
+    assert 0 < hb < 4096
+    buf = (C.c_char * (hb + 64))()
+    base = C.addressof(buf)
+    mem = base + (-base) % 16
+    p = binding.make_params(1000, 1, 16, 0.5, "fp32_mixed")
+    ws = binding.workspace_bytes(p)
+    h = C.c_void_p()
+    EINVAL, EWS = binding.BH_EINVAL, binding.BH_EWORKSPACE
+    assert L.bh_init(None, hb, C.byref(p), C.c_void_p(256), ws, None, C.byref(h)) == EINVAL
+    assert L.bh_init(C.c_void_p(mem), hb - 1, C.byref(p), C.c_void_p(256), ws, None, C.byref(h)) == EINVAL
+    assert L.bh_init(C.c_void_p(mem + 8), hb, C.byref(p), C.c_void_p(256), ws, None, C.byref(h)) == EINVAL
+    bad = binding.make_params(0, 1, 16, 0.5, "fp32_mixed")
+    assert L.bh_init(C.c_void_p(mem), hb, C.byref(bad), C.c_void_p(256), ws, None, C.byref(h)) == EINVAL
+    assert L.bh_init(C.c_void_p(mem), hb, C.byref(p), C.c_void_p(256), ws, None, None) == EINVAL
+    assert L.bh_init(C.c_void_p(mem), hb, C.byref(p), None, ws, None, C.byref(h)) == EWS
+    assert L.bh_init(C.c_void_p(mem), hb, C.byref(p), C.c_void_p(257), ws, None, C.byref(h)) == EWS
+    assert L.bh_init(C.c_void_p(mem), hb, C.byref(p), C.c_void_p(256), ws - 1, None, C.byref(h)) == EWS
+    assert L.bh_fini(None) == EINVAL
+    assert L.bh_destroy(None) == EINVAL
 
 
 def test_workspace_grows_with_problem():

@@ -207,6 +207,36 @@ def test_steps_on_a_user_stream_are_ordered_with_it(tuning_id):
     assert bh.check_status() == 0
 
 
+@pytest.mark.parametrize("tuning_id", [-1, 9])
+def test_caller_owned_handle_steps_without_a_side_stream(tuning_id):
+    """A handle made by bh_init in caller memory has no side stream: md_step runs everything on the
+    caller's stream and follows the same reference trajectory; its build and field equal a bh_create
+    handle's bit for bit."""
+    n, st, p, ref = _two_systems_and_reference(3)
+    bh = BarnesHut(n, 2, 16, 0.5, "fp64", tuning_id=tuning_id, caller_memory=True)
+    d = _to_dev(st)
+    he = torch.from_numpy(p["hext"]).cuda()
+    mp = _mdp(p, he)
+    for _ in range(3):
+        bh.md_step(d, mp)
+    torch.cuda.synchronize()
+    assert int(d["step"].item()) == 3
+    for key in ("pos", "vel", "mom", "omega"):
+        g = d[key].cpu().numpy()
+        err = np.abs(g - ref[key]).max() / np.abs(ref[key]).max()
+        assert err <= 1e-11, (key, err)
+    assert bh.check_status() == 0
+    pos = torch.from_numpy(np.ascontiguousarray(st["pos"])).cuda()
+    mom = torch.from_numpy(np.ascontiguousarray(st["mom"])).cuda()
+    out = []
+    for caller_memory in (False, True):
+        h = BarnesHut(n, 2, 16, 0.5, "fp32_mixed", caller_memory=caller_memory)
+        h.build(pos)
+        out.append(h.field(mom, he))
+        assert h.check_status() == 0
+    assert torch.equal(out[0][0], out[1][0]) and torch.equal(out[0][1], out[1][1])
+
+
 def test_resume_continues_the_same_trajectory():
     w = workloads.uniform_cube(2000, 24.0, seed=6)
     rng = np.random.default_rng(7)
