@@ -23,13 +23,16 @@
  * bh_workspace_bytes, which must stay allocated while the handle is used.  All work is enqueued on the
  * caller's stream (a hipStream_t passed as void*, NULL = the null stream); no call synchronises with
  * the host except bh_check_status.  All calls on one handle -- and replays of graphs captured from it --
- * share its workspace, so they must be ordered: enqueue them on one stream or order the streams.  Two
- * handles never share state and may run concurrently.
+ * share its workspace, so they must be ordered: enqueue them on one stream or order the streams.  Each
+ * such call counts itself in and out on the device (its first and last kernels); a call that starts
+ * while another one is in flight on the handle sets BH_FLAG_OVERLAP, so the misuse is reported, though
+ * not prevented.  Two handles never share state and may run concurrently.
  *
  * Errors.  Arguments that can be checked on the host are checked before anything is enqueued; a
  * failing call returns a negative bh_status and enqueues nothing.  Conditions only the device can see
  * (non-finite input, two distinct particles at the same position, a cell that cannot be split below
- * leaf_size, traversal stack overflow) set bits in a device status word that bh_check_status reads.
+ * leaf_size, traversal stack overflow, overlapping calls) set bits in a device status word that
+ * bh_check_status reads and clears.
  */
 #ifndef FFBH_H
 #define FFBH_H
@@ -59,7 +62,10 @@ enum {
     BH_FLAG_COINCIDENT = 1u << 1,  /* two distinct particles at zero distance (pair skipped)         */
     BH_FLAG_DEEP_LEAF = 1u << 2,   /* a level-21 cell holds more than leaf_size particles            */
     BH_FLAG_STACK = 1u << 3,       /* traversal stack overflow (cannot happen for depth <= 21)       */
-    BH_FLAG_TREE = 1u << 4         /* internal consistency check failed; the affected walk stopped  */
+    BH_FLAG_TREE = 1u << 4,        /* internal consistency check failed; the affected walk stopped  */
+    BH_FLAG_OVERLAP = 1u << 5      /* a call on the handle ran while another was in flight on it (calls
+                                      on different streams not ordered with each other): both raced on
+                                      the workspace and their results are void                      */
 };
 
 enum { BH_FP64 = 0, BH_FP32_MIXED = 1 };

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libffbh.so")
 _lib = None
 
 BH_OK, BH_EINVAL, BH_EWORKSPACE, BH_EDEVICE, BH_EDEGENERATE, BH_ESTATE = 0, -1, -2, -3, -4, -5
-FLAG_NONFINITE, FLAG_COINCIDENT, FLAG_DEEP_LEAF, FLAG_STACK, FLAG_TREE = 1, 2, 4, 8, 16
+FLAG_NONFINITE, FLAG_COINCIDENT, FLAG_DEEP_LEAF, FLAG_STACK, FLAG_TREE, FLAG_OVERLAP = 1, 2, 4, 8, 16, 32
 FP64, FP32_MIXED = 0, 1
 PRECISIONS = {"fp64": FP64, "fp32_mixed": FP32_MIXED}
 

@@ -150,9 +150,20 @@ static bool params_ok(const bh_params *p)
 
 static bool dptr_ok(const void *p) { return p && ((uintptr_t)p % 8) == 0; }
 
+// Clears the flags only: the count of calls in flight stays (other streams may have calls running).
 __global__ void k_clear_status(uint32_t *status)
 {
-    if (threadIdx.x < 16) status[threadIdx.x] = 0u;
+    if (threadIdx.x == 0) status[0] = 0u;
+}
+
+// First and last kernel of the entry points whose own kernels do not count the call in and out.
+__global__ void k_enter(uint32_t *status)
+{
+    if (threadIdx.x == 0) call_enter(status);
+}
+__global__ void k_leave(uint32_t *status)
+{
+    if (threadIdx.x == 0) call_leave(status);
 }
 
 __global__ __launch_bounds__(256) void k_fill_u32(uint32_t *a, int64_t len, uint32_t v)
@@ -380,7 +391,10 @@ bh_status bh_build(bh_handle *hh, const double *d_pos, void *stream)
     // large builds put the targets in Hilbert order on the handle's side stream, beside the octree
     Handle &h = hh->h;
     const hipStream_t side = h.L.ntot >= kForkMinParticles && uses_target_order(h.L) ? h.side : nullptr;
-    if (launch_build(h, d_pos, (hipStream_t)stream, nullptr, side) != hipSuccess) return BH_EDEVICE;
+    const hipStream_t s = (hipStream_t)stream;
+    if (launch_build(h, d_pos, s, nullptr, side, true, true) != hipSuccess) return BH_EDEVICE;
+    hipLaunchKernelGGL(k_leave, dim3(1), dim3(64), 0, s, h.w.status);
+    if (hipGetLastError() != hipSuccess) return BH_EDEVICE;
     hh->h.built = 1;
     return BH_OK;
 }
@@ -392,8 +406,11 @@ bh_status bh_field(bh_handle *hh, const double *d_mom, const double *d_hext, dou
     if (!hh || !dptr_ok(d_mom) || !dptr_ok(d_H)) return BH_EINVAL;
     if ((d_hext && !dptr_ok(d_hext)) || (d_E && !dptr_ok(d_E))) return BH_EINVAL;
     if (!hh->h.built) return BH_ESTATE;
-    if (launch_field(hh->h, d_mom, d_hext, d_H, d_E, (hipStream_t)stream) != hipSuccess) return BH_EDEVICE;
-    return BH_OK;
+    const hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_enter, dim3(1), dim3(64), 0, s, hh->h.w.status);
+    if (launch_field(hh->h, d_mom, d_hext, d_H, d_E, s) != hipSuccess) return BH_EDEVICE;
+    hipLaunchKernelGGL(k_leave, dim3(1), dim3(64), 0, s, hh->h.w.status);
+    return hipGetLastError() == hipSuccess ? BH_OK : BH_EDEVICE;
 }
 
 bh_status bh_field_backward(bh_handle *hh, const double *d_mom, const double *d_hext, const double *d_gH,
@@ -405,10 +422,12 @@ bh_status bh_field_backward(bh_handle *hh, const double *d_mom, const double *d_
         (d_dhext && !dptr_ok(d_dhext)))
         return BH_EINVAL;
     if (!hh->h.built) return BH_ESTATE;
-    if (launch_backward(hh->h, d_mom, d_hext, d_gH, d_gE, d_dpos, d_dmom, d_dhext, (hipStream_t)stream) !=
-        hipSuccess)
+    const hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_enter, dim3(1), dim3(64), 0, s, hh->h.w.status);
+    if (launch_backward(hh->h, d_mom, d_hext, d_gH, d_gE, d_dpos, d_dmom, d_dhext, s) != hipSuccess)
         return BH_EDEVICE;
-    return BH_OK;
+    hipLaunchKernelGGL(k_leave, dim3(1), dim3(64), 0, s, hh->h.w.status);
+    return hipGetLastError() == hipSuccess ? BH_OK : BH_EDEVICE;
 }
 
 static bh_status md_args_ok(bh_handle *hh, const md_state *s, const md_params *p);

@@ -17,8 +17,9 @@ namespace ffbh {
 
 __global__ __launch_bounds__(256) void k_bbox_partial(const double *__restrict__ pos, int64_t n,
                                                       double *__restrict__ part,
-                                                      uint32_t *__restrict__ status)
+                                                      uint32_t *__restrict__ status, int enter)
 {
+    if (enter && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) call_enter(status);
     __shared__ double red[6][256];
     const int b = blockIdx.y;
     const double *p = pos + (int64_t)b * 3 * n;
@@ -1135,7 +1136,7 @@ static void upward(Handle &h, const double *vals, const double *vals2, hipStream
 static void gather_moments(Handle &h, const double *d_mom, hipStream_t s);
 
 hipError_t launch_build(Handle &h, const double *d_pos, hipStream_t s, const double *d_mom, hipStream_t side,
-                        bool join)
+                        bool join, bool enter)
 {
     const Layout &L = h.L;
     Workspace &w = h.w;
@@ -1143,7 +1144,7 @@ hipError_t launch_build(Handle &h, const double *d_pos, hipStream_t s, const dou
     // partial boxes: at most kBboxBlocks per system, no more than one workgroup per 256 particles
     const int nb = (int)((n + 255) / 256 < kBboxBlocks ? (n + 255) / 256 : kBboxBlocks);
     hipLaunchKernelGGL(k_bbox_partial, dim3((unsigned)nb, (unsigned)B), dim3(256), 0, s, d_pos, n,
-                       w.bbox_part, w.status);
+                       w.bbox_part, w.status, enter ? 1 : 0);
     hipLaunchKernelGGL(k_bbox_final, dim3((unsigned)B), dim3(256), 0, s, w.bbox_part, nb, w.bbox);
     hipLaunchKernelGGL(k_morton, dim3(grid_for(ntot, 256)), dim3(256), 0, s, d_pos, n, ntot, w.bbox,
                        w.keys[0], w.vals[0]);

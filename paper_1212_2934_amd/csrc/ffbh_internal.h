@@ -44,7 +44,7 @@ static_assert(sizeof(NodeRec) == 64, "node record must be one 64-byte line");
 
 // Device workspace, carved from the caller's buffer.  All arrays are global over the B systems.
 struct Workspace {
-    uint32_t *status;        // [0] flags, [1] node count, [2..] scratch counters
+    uint32_t *status;        // [0] flags, [1] scan total, [2] node count, [12] calls in flight
     double *bbox;            // B x 8: lo xyz, side, scale, (pad)
     double *bbox_part;       // B x kBboxBlocks x 6 partial min/max
     uint64_t *keys[2];       // N_tot sort keys (ping-pong)
@@ -173,6 +173,18 @@ __device__ inline void set_flag(uint32_t *status, uint32_t bit)
     atomicOr(status, bit);
 }
 
+// Calls in flight on a handle's workspace.  Every entry point that uses the workspace counts itself in
+// with its first kernel and out with its last, in its stream's order, so calls on one stream never see
+// each other.  A call that finds another one in flight (calls on one handle overlapping on streams that
+// are not ordered with each other) sets BH_FLAG_OVERLAP.  This detects the misuse; it does not prevent
+// the race.
+constexpr int kStatusInFlight = 12;  // status word slot of the count
+__device__ inline void call_enter(uint32_t *status)
+{
+    if (atomicAdd(status + kStatusInFlight, 1u) != 0u) set_flag(status, BH_FLAG_OVERLAP);
+}
+__device__ inline void call_leave(uint32_t *status) { atomicSub(status + kStatusInFlight, 1u); }
+
 inline unsigned grid_for(int64_t work, int threads, int64_t cap = (int64_t)1 << 30)
 {
     int64_t g = (work + threads - 1) / threads;
@@ -192,8 +204,9 @@ inline bool uses_target_order(const Layout &L) { return L.n >= kTargetOrderMin; 
 // build; with join the caller's stream then waits for the side stream at the end of the build, without
 // it the caller joins the side stream itself (h.join_ev) before the traversal.  Without a side stream
 // everything runs on s.
+// With enter, the build's first kernel counts the call in (call_enter).
 hipError_t launch_build(Handle &h, const double *d_pos, hipStream_t s, const double *d_mom = nullptr,
-                        hipStream_t side = nullptr, bool join = true);
+                        hipStream_t side = nullptr, bool join = true, bool enter = false);
 // Targets of every system in Hilbert order (the positions' cells at kHilbertBits bits per axis), sorted
 // positions as values: consecutive targets of a traversal wave then lie close together.
 void launch_target_order(Handle &h, hipStream_t s);

@@ -262,9 +262,13 @@ __global__ __launch_bounds__(256) void k_integrate(double *__restrict__ pos, dou
     }
 }
 
-__global__ void k_step_inc(uint64_t *d_step)
+// The step's last kernel: the device step counter, and the call counted out (call_leave).
+__global__ void k_step_inc(uint64_t *d_step, uint32_t *status)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *d_step += 1ull;
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        *d_step += 1ull;
+        call_leave(status);
+    }
 }
 
 hipError_t launch_md(Handle &h, const md_state *st, const md_params *mp, hipStream_t s)
@@ -290,7 +294,7 @@ hipError_t launch_md(Handle &h, const md_state *st, const md_params *mp, hipStre
         launch_order_waves(h, h.side);
     }
     // tree, centroids, moment sums; the target order on the side stream, which goes on below
-    e = launch_build(h, st->pos, s, st->mom, fork ? h.side : nullptr, false);
+    e = launch_build(h, st->pos, s, st->mom, fork ? h.side : nullptr, false, true);
     if (e != hipSuccess) return e;
     // sr_kind 0: WCA, pair and wall cut at the potential minimum; 1: the paper's form, walls at half the pair cut
     const double wca_rc = 1.122462048309373;  // 2^(1/6)
@@ -319,7 +323,7 @@ hipError_t launch_md(Handle &h, const md_state *st, const md_params *mp, hipStre
     MDConst c{mp->dt, mp->kT, mp->gamma_t, mp->gamma_r, mp->mass, mp->inertia, mp->seed};
     hipLaunchKernelGGL(k_integrate, dim3(grid_for(L.ntot, 256)), dim3(256), 0, s, st->pos, st->vel, st->mom,
                        st->omega, w.md_grad_r, w.md_grad_m, w.md_force, st->d_step, L.n, L.ntot, c);
-    hipLaunchKernelGGL(k_step_inc, dim3(1), dim3(64), 0, s, st->d_step);
+    hipLaunchKernelGGL(k_step_inc, dim3(1), dim3(64), 0, s, st->d_step, w.status);
     return hipGetLastError();
 }
 

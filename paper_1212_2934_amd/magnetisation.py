@@ -36,7 +36,7 @@ def langevin(alpha: float) -> float:
     return 1.0 / math.tanh(alpha) - 1.0 / alpha
 
 
-FLAG_NAMES = {1: "NONFINITE", 2: "COINCIDENT", 4: "DEEP_LEAF", 8: "STACK", 16: "TREE"}
+FLAG_NAMES = {1: "NONFINITE", 2: "COINCIDENT", 4: "DEEP_LEAF", 8: "STACK", 16: "TREE", 32: "OVERLAP"}
 
 
 def flag_names(bits: int) -> str:

@@ -1,0 +1,93 @@
+"""Calls in flight on a handle.  Every entry point that uses the workspace counts itself in on the device
+with its first kernel and out with its last; a call that finds another one in flight sets
+BH_FLAG_OVERLAP.  Calls ordered with each other, on one stream or on two streams joined by a wait, never
+raise it.  The misuse itself (two calls racing on one workspace) is not run: another call in flight is
+simulated from the host by writing the count into the workspace's status words before the call."""
+import numpy as np
+import pytest
+import torch
+
+from paper_1212_2934_amd import binding, workloads
+from paper_1212_2934_amd.binding import BarnesHut, md_params
+
+pytestmark = pytest.mark.gpu
+
+IN_FLIGHT = 12  # status word that counts the calls in flight (the workspace starts with the status words)
+
+
+def _status_words(bh):
+    base = bh.workspace.data_ptr()
+    off = (-base) % 256
+    return bh.workspace[off:off + 64].view(torch.int32)
+
+
+def _mdp(side):
+    C3 = __import__("ctypes").c_double * 3
+    return md_params(1e-4, 1.0, 0.1, 0.1, 1.0, 0.1, 1.0, 1.0, C3(0.0, 0.0, 0.0), C3(side, side, side), None, 7)
+
+
+def _system(n, seed):
+    w = workloads.uniform_cube(n, workloads.cube_side(n, 0.05), seed)
+    d = {k: torch.from_numpy(np.ascontiguousarray(getattr(w, k)[None])).cuda() for k in ("pos", "mom")}
+    d["vel"] = torch.zeros_like(d["pos"])
+    d["omega"] = torch.zeros_like(d["pos"])
+    d["step"] = torch.zeros(1, dtype=torch.int64, device="cuda")
+    return w, d
+
+
+def _calls(bh, d, mdp):
+    """Each entry point once, in stream order."""
+    bh.build(d["pos"])
+    bh.field(d["mom"])
+    bh.field_backward(d["mom"])
+    bh.md_step(d, mdp)
+
+
+@pytest.mark.parametrize("n", [3000, 20000])
+def test_ordered_calls_on_two_streams_raise_nothing(n):
+    """20000 particles: bh_build and md_step fork onto the handle's own stream as well."""
+    torch.cuda.set_device(0)
+    w, d = _system(n, 11)
+    bh = BarnesHut(n, 1, 16, 0.5, "fp32_mixed")
+    mdp = _mdp(workloads.cube_side(n, 0.05))
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    s1.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s1):
+        _calls(bh, d, mdp)
+    s2.wait_stream(s1)
+    with torch.cuda.stream(s2):
+        _calls(bh, d, mdp)
+    torch.cuda.current_stream().wait_stream(s2)
+    torch.cuda.synchronize()
+    assert bh.check_status() == 0
+    assert int(_status_words(bh)[IN_FLIGHT].item()) == 0
+
+
+@pytest.mark.parametrize("entry", ["build", "field", "field_backward", "md_step"])
+def test_a_call_that_finds_another_in_flight_is_flagged(entry):
+    torch.cuda.set_device(0)
+    n = 20000
+    w, d = _system(n, 12)
+    bh = BarnesHut(n, 1, 16, 0.5, "fp32_mixed")
+    mdp = _mdp(workloads.cube_side(n, 0.05))
+    bh.build(d["pos"])
+    torch.cuda.synchronize()
+    assert bh.check_status() == 0
+    words = _status_words(bh)
+    words[IN_FLIGHT] = 1  # as if a call on another stream were running
+    if entry == "build":
+        bh.build(d["pos"])
+    elif entry == "field":
+        bh.field(d["mom"])
+    elif entry == "field_backward":
+        bh.field_backward(d["mom"])
+    else:
+        bh.md_step(d, mdp)
+    torch.cuda.synchronize()
+    # the call counted itself in and out again: the simulated call is still in flight
+    assert int(words[IN_FLIGHT].item()) == 1
+    words[IN_FLIGHT] = 0
+    assert bh.check_status() == binding.FLAG_OVERLAP
+    bh.field(d["mom"])
+    torch.cuda.synchronize()
+    assert bh.check_status() == 0
