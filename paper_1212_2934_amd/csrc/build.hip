@@ -1136,7 +1136,7 @@ static void upward(Handle &h, const double *vals, const double *vals2, hipStream
 static void gather_moments(Handle &h, const double *d_mom, hipStream_t s);
 
 hipError_t launch_build(Handle &h, const double *d_pos, hipStream_t s, const double *d_mom, hipStream_t side,
-                        bool join, bool enter)
+                        bool join, bool enter, const SortedWork &after_sort)
 {
     const Layout &L = h.L;
     Workspace &w = h.w;
@@ -1177,6 +1177,12 @@ hipError_t launch_build(Handle &h, const double *d_pos, hipStream_t s, const dou
         if (e != hipSuccess) return e;
     }
     if (uses_target_order(L)) launch_target_order(h, side ? side : s);
+    if (after_sort) {
+        // enqueued here, before the octree kernels, so that the side stream's work is submitted (and, in a
+        // graph, ordered) ahead of them
+        const hipError_t e = after_sort(side ? side : s);
+        if (e != hipSuccess) return e;
+    }
     const int64_t nint = L.bin_int;  // B * (n - 1)
     if (nint > 0) {
         hipLaunchKernelGGL(k_karras, dim3(grid_for(nint, 256)), dim3(256), 0, s, w.codes, n, nint,

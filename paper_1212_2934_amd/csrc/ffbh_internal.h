@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <functional>
 #include <type_traits>
 
 #include "../../include/ffbh.h"
@@ -200,13 +201,15 @@ inline bool uses_target_order(const Layout &L) { return L.n >= kTargetOrderMin; 
 // Launch helpers implemented per source file.
 // Tree build; with d_mom the moments are gathered and summed in the same upward pass (the MD step).
 // With a side stream, h.sorted_ev is recorded once the sorted codes, permutation, positions and cube are
-// final, the side stream waits for it and computes the traversal's target order beside the rest of the
-// build; with join the caller's stream then waits for the side stream at the end of the build, without
-// it the caller joins the side stream itself (h.join_ev) before the traversal.  Without a side stream
-// everything runs on s.
+// final, the side stream waits for it and computes the traversal's target order, then enqueues
+// after_sort's work (which needs only the sorted particles), beside the rest of the build; with join the
+// caller's stream then waits for the side stream at the end of the build, without it the caller joins
+// the side stream itself (h.join_ev) before the traversal.  Without a side stream everything runs on s.
 // With enter, the build's first kernel counts the call in (call_enter).
+using SortedWork = std::function<hipError_t(hipStream_t)>;
 hipError_t launch_build(Handle &h, const double *d_pos, hipStream_t s, const double *d_mom = nullptr,
-                        hipStream_t side = nullptr, bool join = true, bool enter = false);
+                        hipStream_t side = nullptr, bool join = true, bool enter = false,
+                        const SortedWork &after_sort = nullptr);
 // Targets of every system in Hilbert order (the positions' cells at kHilbertBits bits per axis), sorted
 // positions as values: consecutive targets of a traversal wave then lie close together.
 void launch_target_order(Handle &h, hipStream_t s);
