@@ -52,10 +52,12 @@ __global__ __launch_bounds__(256) void k_bbox_partial(const double *__restrict__
 }
 
 // One workgroup of 256 per system folds the nb partial boxes (min and max are exact in any order).
+// Block 0 also clears the level-bucket counters (lvl, 128 words), which the build fills after the octree.
 __global__ __launch_bounds__(256) void k_bbox_final(const double *__restrict__ part, int nb,
-                                                    double *__restrict__ bbox)
+                                                    double *__restrict__ bbox, uint32_t *__restrict__ lvl)
 {
     __shared__ double red[6][256];
+    if (blockIdx.x == 0 && threadIdx.x < 128) lvl[threadIdx.x] = 0u;
     const int b = blockIdx.x;
     double v[6];
     for (int a = 0; a < 3; ++a) {
@@ -716,8 +718,13 @@ __global__ __launch_bounds__(256) void k_oct_count(int64_t n, int64_t nint_tot, 
     scan_in[g] = (uint32_t)out;
 }
 
-// Write the records of the children of every in-tree internal node (and of the roots).  The members'
-// leaf index is written afterwards by k_leaf_of, sixteen lanes per leaf.
+// Write the records of the children of every in-tree internal node (and of the roots), and, for each
+// leaf among them, its id as the leaf of its members.
+__device__ inline void stamp_leaf(int32_t *__restrict__ leaf_of, int64_t first, int count, int64_t end, int32_t id)
+{
+    for (int k = 0; k < count; ++k)
+        if (first + k < end) leaf_of[first + k] = id;
+}
 
 __global__ __launch_bounds__(256) void k_oct_emit(int64_t n, int64_t nint_tot, int64_t B, int leaf,
                                                   const int32_t *__restrict__ left,
@@ -729,7 +736,7 @@ __global__ __launch_bounds__(256) void k_oct_emit(int64_t n, int64_t nint_tot, i
                                                   const uint32_t *__restrict__ scan,
                                                   NodeRec *__restrict__ nodes, int32_t *__restrict__ node_level,
                                                   int32_t *__restrict__ octid, uint32_t *__restrict__ status,
-                                                  int64_t max_nodes)
+                                                  int64_t max_nodes, int32_t *__restrict__ leaf_of)
 {
     int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (g == 0) status[2] = (uint32_t)B + (nint_tot > 0 ? status[1] : 0u);  // number of nodes
@@ -754,6 +761,7 @@ __global__ __launch_bounds__(256) void k_oct_emit(int64_t n, int64_t nint_tot, i
         }
         nodes[b] = r;
         node_level[b] = lev;
+        if (r.nchild == 0) stamp_leaf(leaf_of, b * n, (int)n, b * n + n, (int32_t)b);
     }
     if (g >= nint_tot) return;
     const int nc = nchild[g];
@@ -808,6 +816,7 @@ __global__ __launch_bounds__(256) void k_oct_emit(int64_t n, int64_t nint_tot, i
             r.parent = -1;  // set by k_oct_link
             nodes[id] = r;
             node_level[id] = clev;
+            if (cn == 0) stamp_leaf(leaf_of, b * n + cf, cc, b * n + n, id);
             ++id;
         } else if (sp > 5) {
             set_flag(status, BH_FLAG_TREE);
@@ -816,24 +825,6 @@ __global__ __launch_bounds__(256) void k_oct_emit(int64_t n, int64_t nint_tot, i
             stk[sp++] = right[ib + c];
             stk[sp++] = left[ib + c];
         }
-    }
-}
-
-// Leaf of every member: sixteen lanes per node of the tree (the node count is the build's, on the
-// device); lanes of internal nodes do nothing.
-constexpr int kLeafLanes = 16;
-__global__ __launch_bounds__(256) void k_leaf_of(const NodeRec *__restrict__ nodes, const uint32_t *__restrict__ status,
-                                                 int64_t max_nodes, int64_t ntot, int32_t *__restrict__ leaf_of)
-{
-    const int64_t nn = min((int64_t)status[2], max_nodes);
-    for (int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x; x < nn * kLeafLanes; x += (int64_t)gridDim.x * 256) {
-        const int64_t q = x / kLeafLanes;
-        const int k0 = (int)(x - q * kLeafLanes);
-        if (nodes[q].nchild != 0) continue;
-        const int64_t first = nodes[q].first;
-        const int cnt = nodes[q].count;
-        for (int k = k0; k < cnt; k += kLeafLanes)
-            if (first + k >= 0 && first + k < ntot) leaf_of[first + k] = (int32_t)q;
     }
 }
 
@@ -924,11 +915,6 @@ __global__ __launch_bounds__(256) void k_level_scatter(const NodeRec *__restrict
     if (threadIdx.x < kBuckets && cnt[threadIdx.x]) base[threadIdx.x] = atomicAdd(&lvl[64 + threadIdx.x], cnt[threadIdx.x]);
     __syncthreads();
     if (bk >= 0 && (int64_t)base[bk] + r < max_nodes) lvl_nodes[base[bk] + r] = (int32_t)i;
-}
-
-__global__ void k_zero_u32(uint32_t *a, int len)
-{
-    for (int i = threadIdx.x; i < len; i += blockDim.x) a[i] = 0u;
 }
 
 // MODE 0: member positions -> centroids and s^2; MODE 1: member moments -> FP64 and FP32 moment sums;
@@ -1145,7 +1131,7 @@ hipError_t launch_build(Handle &h, const double *d_pos, hipStream_t s, const dou
     const int nb = (int)((n + 255) / 256 < kBboxBlocks ? (n + 255) / 256 : kBboxBlocks);
     hipLaunchKernelGGL(k_bbox_partial, dim3((unsigned)nb, (unsigned)B), dim3(256), 0, s, d_pos, n,
                        w.bbox_part, w.status, enter ? 1 : 0);
-    hipLaunchKernelGGL(k_bbox_final, dim3((unsigned)B), dim3(256), 0, s, w.bbox_part, nb, w.bbox);
+    hipLaunchKernelGGL(k_bbox_final, dim3((unsigned)B), dim3(256), 0, s, w.bbox_part, nb, w.bbox, w.lvl);
     hipLaunchKernelGGL(k_morton, dim3(grid_for(ntot, 256)), dim3(256), 0, s, d_pos, n, ntot, w.bbox,
                        w.keys[0], w.vals[0]);
     const int tiles = (int)L.tiles;
@@ -1195,14 +1181,12 @@ hipError_t launch_build(Handle &h, const double *d_pos, hipStream_t s, const dou
     }
     hipLaunchKernelGGL(k_oct_emit, dim3(grid_for(nint > B ? nint : B, 256)), dim3(256), 0, s, n, nint, B,
                        (int)h.p.leaf_size, w.bin_left, w.bin_right, w.bin_first, w.bin_last, w.bin_delta,
-                       w.bin_nchild, w.bin_scan, w.nodes, w.node_level, w.bin_octid, w.status, L.max_nodes);
-    hipLaunchKernelGGL(k_leaf_of, dim3(grid_for(L.max_nodes * kLeafLanes, 256, 8192)), dim3(256), 0, s, w.nodes,
-                       w.status, L.max_nodes, ntot, w.leaf_of);
+                       w.bin_nchild, w.bin_scan, w.nodes, w.node_level, w.bin_octid, w.status, L.max_nodes,
+                       w.leaf_of);
     if (nint > 0)
         hipLaunchKernelGGL(k_oct_link, dim3(grid_for(nint, 256)), dim3(256), 0, s, nint, B,
                            w.bin_nchild, w.bin_scan, w.bin_octid, w.nodes, L.max_nodes);
     // bucket the nodes by level, then the upward pass for the centroids
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(128), 0, s, w.lvl, 128);
     hipLaunchKernelGGL(k_level_count, dim3(grid_for(L.max_nodes, 256, 1024)), dim3(256), 0, s, w.nodes,
                        w.node_level, w.status + 2, L.max_nodes, w.lvl);
     hipLaunchKernelGGL(k_level_starts, dim3(1), dim3(64), 0, s, w.lvl);
