@@ -161,30 +161,41 @@ __global__ __launch_bounds__(256) void k_wca(const uint64_t *__restrict__ codes,
                   cz = (int)(compact3(code) >> down);
         const int cmax = (1 << L) - 1;
         const uint2 *tab = cells + b * T;
-        // per slab of nine cells, the member ranges are read before any member, so their loads overlap
-        // (all 27 at once takes 152 VGPRs and ran 30 % slower)
+        // Per slab of nine cells: the member ranges are read before any member, so their loads overlap
+        // (all 27 at once takes 152 VGPRs and ran 30 % slower).  The slab's members are then walked as one
+        // list (candidate t lies in the last cell whose running count is at most t), so a wave iterates
+        // as often as its busiest lane has candidates, not as often as the sum over the cells of the
+        // busiest lane per cell, and no load waits for another.
         for (int dz = -1; dz <= 1; ++dz) {
             const int nz = cz + dz;
             if ((unsigned)nz > (unsigned)cmax) continue;
-            uint2 rg[9];
+            uint32_t first[9], cnt[9];
 #pragma unroll
             for (int k = 0; k < 9; ++k) {
                 const int nx = cx + k % 3 - 1, ny = cy + k / 3 - 1;
                 const bool in = (unsigned)nx <= (unsigned)cmax && (unsigned)ny <= (unsigned)cmax;
-                rg[k] = in ? tab[(spread3_small((uint32_t)nx) << 2) | (spread3_small((uint32_t)ny) << 1) |
-                                 spread3_small((uint32_t)nz)]
-                           : make_uint2(0u, 0u);
+                const uint2 r = in ? tab[(spread3_small((uint32_t)nx) << 2) | (spread3_small((uint32_t)ny) << 1) |
+                                         spread3_small((uint32_t)nz)]
+                                   : make_uint2(0u, 0u);
+                // a range always lies inside this system's block of sorted particles
+                const int64_t j0 = (int64_t)r.x > lo_i ? (int64_t)r.x : lo_i;
+                const int64_t j1 = (int64_t)r.y < hi_i ? (int64_t)r.y : hi_i;
+                first[k] = (uint32_t)j0;
+                cnt[k] = j1 > j0 ? (uint32_t)(j1 - j0) : 0u;
             }
+            uint32_t start[9], tot = 0u;
 #pragma unroll
             for (int k = 0; k < 9; ++k) {
-                // a range always lies inside this system's block of sorted particles
-                const int64_t j0 = (int64_t)rg[k].x > lo_i ? (int64_t)rg[k].x : lo_i;
-                const int64_t j1 = (int64_t)rg[k].y < hi_i ? (int64_t)rg[k].y : hi_i;
-                for (int64_t j = j0; j < j1; ++j) {
-                    if (j == o) continue;
-                    sr_pair(rx - spos[j], ry - spos[ntot + j], rz - spos[2 * ntot + j], s2, eps, c12, rc2, fx, fy,
-                            fz);
-                }
+                start[k] = tot;
+                tot += cnt[k];
+            }
+            for (uint32_t t = 0; t < tot; ++t) {
+                uint32_t j = first[0] + t;
+#pragma unroll
+                for (int k = 1; k < 9; ++k)
+                    if (t >= start[k]) j = first[k] + (t - start[k]);
+                if ((int64_t)j == o) continue;
+                sr_pair(rx - spos[j], ry - spos[ntot + j], rz - spos[2 * ntot + j], s2, eps, c12, rc2, fx, fy, fz);
             }
         }
         // container walls
