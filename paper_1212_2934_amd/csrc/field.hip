@@ -63,17 +63,19 @@ __device__ inline void field_leaf(FieldLds<T> &W, int lane, const Src *__restric
 }
 
 // QUAD: accepted cells add their first-moment term (order-2 cells; node_q holds D per node, stride 16).
+// INSIDE: the explicit test for cells holding the target (needed above kSelfRejectTheta2); a template
+// argument rather than a kernel argument, because this walk is limited by scalar issue as much as by
+// vector issue and a branch per visit costs two scalar instructions.
 // Eight waves per SIMD (64 VGPRs): the FP64 walk spills a few bytes there and runs as fast as at seven;
 // the FP32-mixed walk fits without spilling and runs 2-3 % faster than with the hint at seven.
-template <bool MIXED, bool COUNT, bool QUAD>
+template <bool MIXED, bool COUNT, bool QUAD, bool INSIDE>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(8))) void k_field(
     const NodeRec *__restrict__ nodes, const double *__restrict__ node_m64, const double *__restrict__ spos,
     const double *__restrict__ smom, const void *__restrict__ src, const uint32_t *__restrict__ perm,
     const double *__restrict__ hext, double *__restrict__ H, double *__restrict__ Hs,
     double *__restrict__ e_part, int32_t *__restrict__ cnt_far, int32_t *__restrict__ cnt_near,
     uint32_t *__restrict__ status, int64_t n, int64_t ntot, int waves_per_seg, int num_waves,
-    double theta2, int max_nodes, const void *__restrict__ node_q, const uint32_t *__restrict__ tgt_order,
-    int inside_test)
+    double theta2, int max_nodes, const void *__restrict__ node_q, const uint32_t *__restrict__ tgt_order)
 {
     using T = typename std::conditional<MIXED, float, double>::type;
     using Src = typename std::conditional<MIXED, Src32, Src64>::type;
@@ -110,7 +112,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(8))) void k
         // masks of the lanes that take part, of the targets inside the node (opened whatever the test
         // says; below kSelfRejectTheta2 the test rejects them itself) and of the acceptance test
         uint64_t insm = 0ull;
-        if (inside_test) insm = ballot((unsigned)(si - nd.first) < (unsigned)nd.count);
+        if constexpr (INSIDE) insm = ballot((unsigned)(si - nd.first) < (unsigned)nd.count);
         // acceptance test in FP64, exactly as defined
         const double dx = rx - nd.cx, dy = ry - nd.cy, dz = rz - nd.cz;
         const double d2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
@@ -238,11 +240,15 @@ static void launch_k_field(Handle &h, const double *d_hext, double *d_H, hipStre
     using T = typename std::conditional<MIXED, float, double>::type;
     const size_t lds = (size_t)wpb * sizeof(FieldLds<T>);
     const void *q = MIXED ? (const void *)w.node_q32 : (const void *)w.node_q64;
-    hipLaunchKernelGGL((k_field<MIXED, COUNT, QUAD>), dim3(blocks), dim3(wpb * kWave), lds, s, w.nodes,
-                       w.node_m64, w.spos, w.smom, src, w.perm, d_hext, d_H, w.Hs, w.e_part,
-                       h.cnt_far, h.cnt_near, w.status, L.n, L.ntot, waves_per_seg, (int)L.num_waves, theta2,
-                       (int)L.max_nodes, q, uses_target_order(L) ? w.tgt_order : nullptr,
-                       theta2 > kSelfRejectTheta2 ? 1 : 0);
+    const uint32_t *tgt = uses_target_order(L) ? w.tgt_order : nullptr;
+#define FFBH_FIELD(INSIDE)                                                                                       \
+    hipLaunchKernelGGL((k_field<MIXED, COUNT, QUAD, INSIDE>), dim3(blocks), dim3(wpb * kWave), lds, s, w.nodes,      \
+                       w.node_m64, w.spos, w.smom, src, w.perm, d_hext, d_H, w.Hs, w.e_part, h.cnt_far,          \
+                       h.cnt_near, w.status, L.n, L.ntot, waves_per_seg, (int)L.num_waves, theta2,               \
+                       (int)L.max_nodes, q, tgt)
+    if (theta2 > kSelfRejectTheta2) FFBH_FIELD(true);
+    else FFBH_FIELD(false);
+#undef FFBH_FIELD
 }
 
 hipError_t launch_field(Handle &h, const double *d_mom, const double *d_hext, double *d_H, double *d_E,
