@@ -257,7 +257,7 @@ __device__ __forceinline__ void adjoint_wave(int gw, FFBH_ADJ_PARAMS)
     // so at most max_nodes pushes keep the walk finite whatever the tree holds.
     int guard = max_nodes;
     uint32_t work = 0;      // node visits plus leaf pair rounds (wave-uniform)
-    while (st.more()) {
+    while (st.more_any()) {
         uint64_t mask;
         const int cur = st.pop(mask);
         const NodeRec nd = nodes[cur];

@@ -28,7 +28,7 @@ struct FieldLds {
 // coincident, as in the definition of the direct sum.
 template <bool COUNT, int G, typename T, typename Src>
 __device__ inline void field_leaf(FieldLds<T> &W, int lane, const Src *__restrict__ sr, int first, int count, int c,
-                                  bool &coincident)
+                                  uint32_t &coincident)
 {
     const int grp = lane / G, b = lane % G;
     const int slot = group3_slot<G>(lane);
@@ -48,7 +48,7 @@ __device__ inline void field_leaf(FieldLds<T> &W, int lane, const Src *__restric
             const T r2 = norm2<T>(x, y, z);
             const bool other = tok && sok && k != tg.si;
             const bool use = other && r2 > (T)0;
-            coincident |= other && !(r2 > (T)0);
+            coincident |= other && !(r2 > (T)0) ? 1u : 0u;
             T hx = 0, hy = 0, hz = 0;
             dip_acc_r2<T>(use, r2, x, y, z, mx, my, mz, hx, hy, hz);
             const T v = group_sum3<G>(lane, hx, hy, hz);
@@ -93,7 +93,9 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(8))) void k
     double hx = 0.0, hy = 0.0, hz = 0.0;  // FP64 accumulation
     T px = 0, py = 0, pz = 0;             // partial sums since the last flush (MIXED only)
     int nfar = 0, nnear = 0;
-    bool coincident = false;
+    // a lane value, not a bool: a divergent bool carried around the walk loop costs scalar mask merges at
+    // every iteration
+    uint32_t coincident = 0u;
     FieldLds<T> &W = ((FieldLds<T> *)ffbh_dyn_lds)[threadIdx.x / kWave];
     W.tgt[lane] = LdsTarget{rx, ry, rz, si, 0};
     W.acc[lane][0] = W.acc[lane][1] = W.acc[lane][2] = (T)0;
@@ -107,7 +109,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(8))) void k
     int guard = max_nodes;
     while (st.more()) {
         uint64_t mask;
-        const int cur = st.pop(mask);
+        const int cur = st.pop_settled(mask);
         const NodeRec nd = nodes[cur];
         // masks of the lanes that take part, of the targets inside the node (opened whatever the test
         // says; below kSelfRejectTheta2 the test rejects them itself) and of the acceptance test
@@ -174,11 +176,12 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(8))) void k
                 }
             }
         }
+        st.settle();
     }
     if (MIXED) {
         hx += (double)px; hy += (double)py; hz += (double)pz;
     }
-    if (ballot(coincident) != 0ull && lane == 0) set_flag(status, BH_FLAG_COINCIDENT);
+    if (ballot(coincident != 0u) != 0ull && lane == 0) set_flag(status, BH_FLAG_COINCIDENT);
 
     // energy contribution of this wave: -1/2 m.H - m.H_ext
     double e = 0.0;

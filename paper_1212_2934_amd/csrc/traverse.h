@@ -512,7 +512,13 @@ struct LaneStack {
         tleft = __builtin_amdgcn_readfirstlane(count);
         tmask = m;
     }
-    __device__ inline bool more() const { return tleft > 0 || sp > 0; }
+    // Two ways to walk.  pop: the walked range is refilled from the parked ones when a take finds it
+    // empty (loop test more_any).  pop_settled: the caller refills it at the end of each visit (settle),
+    // so it is empty only when the walk is over, and the loop test (more) and the take are one compare and
+    // three increments; the forward walk, whose scalar issue is as busy as its vector issue, uses this
+    // one.  Both visit the nodes in the same order.
+    __device__ inline bool more() const { return tleft > 0; }
+    __device__ inline bool more_any() const { return tleft > 0 || sp > 0; }
     // Drop every range: the walk ends at the next more() (error exits, without a second loop exit).
     __device__ inline void clear()
     {
@@ -532,7 +538,16 @@ struct LaneStack {
         tleft = count;
         tmask = m;
     }
-    // Next node and its lane mask (call only while more()).
+    // Next node and its lane mask (call only while more(), with settle() at the end of every visit).
+    __device__ inline int pop_settled(uint64_t &m)
+    {
+        m = tmask;
+        --tleft;
+        return tnode++;
+    }
+    // Next node and its lane mask (call only while more_any(), so a range is parked when the walked one
+    // is empty).  The refill is written out here and in settle() rather than shared: each walk's register
+    // allocation (measured) depends on it.
     __device__ inline int pop(uint64_t &m)
     {
         if (tleft == 0) {
@@ -544,40 +559,20 @@ struct LaneStack {
             tleft = (int)(e >> 28) + 1;
             tmask = ((uint64_t)hi << 32) | lo;
         }
-        m = tmask;
-        --tleft;
-        return tnode++;
+        return pop_settled(m);
     }
-};
-
-// Stack for a wave that owns two targets per lane: entry e in lane e holds the packed node range and
-// the two 64-bit lane masks (first and second target of every lane).
-struct LaneStack2 {
-    int ent, a_lo, a_hi, b_lo, b_hi;
-    int sp;
-
-    __device__ inline void push(int lane, int first, int count, uint64_t ma, uint64_t mb)
+    // End of a visit: if the walked range has run out, the top parked range becomes the walked one.
+    __device__ inline void settle()
     {
-        const bool here = lane == sp;
-        ent = here ? (first | ((count - 1) << 28)) : ent;
-        a_lo = here ? (int)(uint32_t)ma : a_lo;
-        a_hi = here ? (int)(uint32_t)(ma >> 32) : a_hi;
-        b_lo = here ? (int)(uint32_t)mb : b_lo;
-        b_hi = here ? (int)(uint32_t)(mb >> 32) : b_hi;
-        ++sp;
-    }
-    __device__ inline int pop(int lane, uint64_t &ma, uint64_t &mb)
-    {
-        const int top = sp - 1;
-        const uint32_t e = (uint32_t)__builtin_amdgcn_readlane(ent, top);
-        ma = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(a_hi, top) << 32) |
-             (uint32_t)__builtin_amdgcn_readlane(a_lo, top);
-        mb = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(b_hi, top) << 32) |
-             (uint32_t)__builtin_amdgcn_readlane(b_lo, top);
-        const int c = (int)(e & 0x0fffffffu);
-        if (e >> 28) ent = (lane == top) ? (int)(e + 1u - (1u << 28)) : ent;
-        else sp = top;
-        return c;
+        if (tleft == 0 && sp > 0) {
+            --sp;
+            const uint32_t e = (uint32_t)__builtin_amdgcn_readlane(ent, sp);
+            const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane(mlo, sp);
+            const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane(mhi, sp);
+            tnode = (int)(e & 0x0fffffffu);
+            tleft = (int)(e >> 28) + 1;
+            tmask = ((uint64_t)hi << 32) | lo;
+        }
     }
 };
 
