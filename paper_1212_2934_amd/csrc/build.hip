@@ -458,6 +458,73 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     }
 }
 
+// The tiled sort orders the codes by their bits above the low kTieBits only, stably, so particles whose
+// codes agree above those bits (cells 2^-15 of the cube wide and finer: none in the excluded-volume
+// workloads) are left in index order.  The thread at the start of each such run orders it by the low
+// bits, stably, which gives the order of the full codes (ties in index order).  Short runs by insertion;
+// longer ones by a bottom-up merge through the second key buffer (free at this point), so any run,
+// even all particles at one point, takes O(L log L).
+constexpr int kTieInsertMax = 32;
+
+__device__ inline bool low_less(uint64_t a, uint64_t b)
+{
+    constexpr uint64_t m = (1ull << kTieBits) - 1ull;
+    return (a & m) < (b & m);
+}
+
+__global__ __launch_bounds__(256) void k_fix_ties(uint64_t *__restrict__ keys, uint32_t *__restrict__ vals,
+                                                  uint64_t *__restrict__ tkeys, uint32_t *__restrict__ tvals,
+                                                  int64_t n, int64_t ntot)
+{
+    const int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (o >= ntot) return;
+    const int64_t b = o / n, end = (b + 1) * n;
+    const uint64_t h = keys[o] >> kTieBits;
+    if (o > b * n && (keys[o - 1] >> kTieBits) == h) return;  // not the start of a run
+    if (o + 1 >= end || (keys[o + 1] >> kTieBits) != h) return;  // a run of one
+    int64_t e = o + 2;
+    while (e < end && (keys[e] >> kTieBits) == h) ++e;
+    const int64_t len = e - o;
+    if (len <= kTieInsertMax) {
+        for (int64_t i = o + 1; i < e; ++i) {
+            const uint64_t k = keys[i];
+            const uint32_t v = vals[i];
+            int64_t j = i;
+            while (j > o && low_less(k, keys[j - 1])) {
+                keys[j] = keys[j - 1];
+                vals[j] = vals[j - 1];
+                --j;
+            }
+            keys[j] = k;
+            vals[j] = v;
+        }
+        return;
+    }
+    // bottom-up merge sort of [o, e), stable, ping-ponging between the buffers
+    uint64_t *ka = keys, *kb = tkeys;
+    uint32_t *va = vals, *vb = tvals;
+    for (int64_t w = 1; w < len; w <<= 1) {
+        for (int64_t lo = o; lo < e; lo += 2 * w) {
+            const int64_t mid = min(lo + w, e), hi = min(lo + 2 * w, e);
+            int64_t i = lo, j = mid, k = lo;
+            while (i < mid && j < hi) {
+                if (low_less(ka[j], ka[i])) { kb[k] = ka[j]; vb[k] = va[j]; ++j; }
+                else { kb[k] = ka[i]; vb[k] = va[i]; ++i; }
+                ++k;
+            }
+            while (i < mid) { kb[k] = ka[i]; vb[k] = va[i]; ++i; ++k; }
+            while (j < hi) { kb[k] = ka[j]; vb[k] = va[j]; ++j; ++k; }
+        }
+        uint64_t *kt = ka; ka = kb; kb = kt;
+        uint32_t *vt = va; va = vb; vb = vt;
+    }
+    if (ka != keys)
+        for (int64_t i = o; i < e; ++i) {
+            keys[i] = ka[i];
+            vals[i] = va[i];
+        }
+}
+
 // Whole sort of one small system in one workgroup (systems of at most kSortSmallMax keys): the keys stay
 // in LDS for all eight passes, so a small system's sort is one launch instead of sixteen.  Each pass is
 // the tile pass of k_radix_scatter over the whole system: every wave ranks a contiguous chunk of keys
@@ -1140,8 +1207,9 @@ hipError_t launch_build(Handle &h, const double *d_pos, hipStream_t s, const dou
         // small systems: the whole sort in LDS, one workgroup per system
         hipLaunchKernelGGL(k_sort_small, dim3((unsigned)B), dim3(kSortSmallThreads), 0, s, w.keys[0], w.vals[0],
                            (int)n);
-    } else
-    for (int pass = 0; pass < kRadixPasses; ++pass) {
+    } else {
+    // the digits above the low kTieBits bits; k_fix_ties then orders the rare runs of equal upper bits
+    for (int pass = kTieBits / kRadixBits; pass < kRadixPasses; ++pass) {
         const int src = pass & 1, dst = src ^ 1;
         const int shift = pass * kRadixBits;
         hipLaunchKernelGGL(k_radix_hist, dim3(sblocks), dim3(kSortThreads), 0, s, w.keys[src], n, tiles,
@@ -1153,7 +1221,12 @@ hipError_t launch_build(Handle &h, const double *d_pos, hipStream_t s, const dou
                            w.vals[src], w.keys[dst], w.vals[dst], w.hist, n, tiles, L.sort_items, shift, ntot,
                            fused);
     }
-    // kRadixPasses is even: the sorted data is back in buffer 0
+    hipLaunchKernelGGL(k_fix_ties, dim3(grid_for(ntot, 256)), dim3(256), 0, s, w.keys[0], w.vals[0], w.keys[1],
+                       w.vals[1], n, ntot);
+    }
+    static_assert((kRadixPasses - kTieBits / kRadixBits) % 2 == 0 && kTieBits % kRadixBits == 0,
+                  "an even number of tiled passes leaves the sorted data in buffer 0");
+    // the sorted data is back in buffer 0
     hipLaunchKernelGGL(k_gather3, dim3(grid_for(ntot, 256)), dim3(256), 0, s, d_pos, w.perm, n, ntot,
                        w.spos, (float *)nullptr, w.status);
     // the sorted codes, permutation and positions and the bounding cube are final from here on

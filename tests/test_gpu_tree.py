@@ -90,6 +90,29 @@ def test_tree_dense_cluster_in_a_large_tree(oracle_mod):
     assert ncells == g["first"].size
 
 
+def test_sort_order_with_runs_of_equal_upper_code_bits(oracle_mod):
+    """The tiled sort orders the codes by their bits above the low 16 and then orders each run of equal
+    upper bits by the low bits: short runs by insertion, runs of more than 32 by a merge.  Clusters of 24
+    and of 80 particles 1e-4 wide (runs of 24 and 80 equal upper parts whose low bits are out of index
+    order) and 300 particles at one point (all 63 bits equal: ties stay in index order), inside 6000
+    uniform ones: the order must be the oracle's, bit for bit."""
+    rng = np.random.default_rng(21)
+    w = workloads.uniform_cube(6000, 50.0, seed=21)
+    parts = [w.pos]
+    for cnt, c in [(24, 11.0), (80, 23.0)]:
+        parts.append(np.array([[c], [c + 1.0], [c + 2.0]]) + 1e-4 * rng.random((3, cnt)))
+    parts.append(np.tile(np.array([[31.5], [7.25], [19.75]]), (1, 300)))
+    pos = np.concatenate(parts, axis=1)
+    # interleave the clusters with the uniform particles so that index order and code order differ
+    order = rng.permutation(pos.shape[1])
+    pos = np.ascontiguousarray(pos[:, order])
+    mom = workloads.uniform_cube(pos.shape[1], 50.0, seed=22).mom
+    t = oracle_mod.Tree(pos, mom, 16).export()
+    out = run_field(pos, mom, leaf=16, counters=False)
+    g = out["bh"].export_tree()
+    assert (g["perm"] == t["perm"]).all()
+
+
 @pytest.mark.parametrize("n", [2000, 2048, 2049])
 def test_tree_batch_around_the_one_workgroup_sort(oracle_mod, n):
     """Systems of at most 2048 particles sort in one workgroup each (all passes in LDS); 2049 takes the
