@@ -459,11 +459,13 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
 }
 
 // The tiled sort orders the codes by their bits above the low kTieBits only, stably, so particles whose
-// codes agree above those bits (cells 2^-15 of the cube wide and finer: none in the excluded-volume
-// workloads) are left in index order.  The thread at the start of each such run orders it by the low
-// bits, stably, which gives the order of the full codes (ties in index order).  Short runs by insertion;
-// longer ones by a bottom-up merge through the second key buffer (free at this point), so any run,
-// even all particles at one point, takes O(L log L).
+// codes agree above those bits are left in index order.  With 32 low bits left out the upper bits are the
+// cell 2^-10 of the cube wide (and one bit of the next level): at 2^20 particles in the chain workload's
+// cube that is 0.17 diameters, a cell no two particles that exclude each other share.  The thread at the
+// start of each run of equal upper bits orders the run by the low bits, stably, which gives the order of
+// the full codes (ties in index order).  Short runs by insertion; longer ones by a bottom-up merge through
+// the second key buffer (free at this point), so any run, even all particles at one point, takes
+// O(L log L).
 constexpr int kTieInsertMax = 32;
 
 __device__ inline bool low_less(uint64_t a, uint64_t b)

@@ -18,7 +18,7 @@ constexpr int kWave = 64;                       // CDNA wavefront width
 constexpr int kRadixBits = 8;
 constexpr int kRadixBins = 1 << kRadixBits;
 constexpr int kRadixPasses = 8;                 // 8 x 8 bits cover the 63-bit codes
-constexpr int kTieBits = 16;                    // low code bits the tiled sort leaves to k_fix_ties
+constexpr int kTieBits = 32;                    // low code bits the tiled sort leaves to k_fix_ties
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 16;                  // most keys per thread per tile
 constexpr int kMinTpw = 16;                     // fewest targets an adjoint wave owns

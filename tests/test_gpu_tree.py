@@ -91,7 +91,7 @@ def test_tree_dense_cluster_in_a_large_tree(oracle_mod):
 
 
 def test_sort_order_with_runs_of_equal_upper_code_bits(oracle_mod):
-    """The tiled sort orders the codes by their bits above the low 16 and then orders each run of equal
+    """The tiled sort orders the codes by their bits above the low 32 and then orders each run of equal
     upper bits by the low bits: short runs by insertion, runs of more than 32 by a merge.  Clusters of 24
     and of 80 particles 1e-4 wide (runs of 24 and 80 equal upper parts whose low bits are out of index
     order) and 300 particles at one point (all 63 bits equal: ties stay in index order), inside 6000
