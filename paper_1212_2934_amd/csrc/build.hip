@@ -1237,13 +1237,10 @@ hipError_t launch_build(Handle &h, const double *d_pos, hipStream_t s, const dou
         if (e == hipSuccess) e = hipStreamWaitEvent(side, h.sorted_ev, 0);
         if (e != hipSuccess) return e;
     }
-    if (uses_target_order(L)) launch_target_order(h, side ? side : s);
-    if (after_sort) {
-        // enqueued here, before the octree kernels, so that the side stream's work is submitted (and, in a
-        // graph, ordered) ahead of them
-        const hipError_t e = after_sort(side ? side : s);
-        if (e != hipSuccess) return e;
-    }
+    // Replayed graphs submit the kernels in the order they were captured, so the order of the enqueues
+    // below matters: the first octree kernels go first, the side stream's work next (before the rest of
+    // the octree, which it runs beside).  With the side stream's work first, the binary radix tree started
+    // up to 130 us after the sort in graph replays.
     const int64_t nint = L.bin_int;  // B * (n - 1)
     if (nint > 0) {
         hipLaunchKernelGGL(k_karras, dim3(grid_for(nint, 256)), dim3(256), 0, s, w.codes, n, nint,
@@ -1252,8 +1249,13 @@ hipError_t launch_build(Handle &h, const double *d_pos, hipStream_t s, const dou
         hipLaunchKernelGGL(k_oct_count, dim3(grid_for(nint, 256)), dim3(256), 0, s, n, nint,
                            (int)h.p.leaf_size, w.bin_left, w.bin_right, w.bin_first, w.bin_last,
                            w.bin_delta, w.bin_parent, w.bin_nchild, w.bin_scan, w.status);
-        scan_excl(w.bin_scan, nint, w.scan_tmp, w.status + 1, s);
     }
+    if (uses_target_order(L)) launch_target_order(h, side ? side : s);
+    if (after_sort) {
+        const hipError_t e = after_sort(side ? side : s);
+        if (e != hipSuccess) return e;
+    }
+    if (nint > 0) scan_excl(w.bin_scan, nint, w.scan_tmp, w.status + 1, s);
     hipLaunchKernelGGL(k_oct_emit, dim3(grid_for(nint > B ? nint : B, 256)), dim3(256), 0, s, n, nint, B,
                        (int)h.p.leaf_size, w.bin_left, w.bin_right, w.bin_first, w.bin_last, w.bin_delta,
                        w.bin_nchild, w.bin_scan, w.nodes, w.node_level, w.bin_octid, w.status, L.max_nodes,
