@@ -205,7 +205,8 @@ __device__ inline void close_pairs(AdjLds<float> &W, int lane, bool valid, int s
 // the item's work (node visits plus leaf pair rounds), which orders the next launch.  QUAD: order-2 cells
 // (node_q holds each node's first moment D, stride 16); an accepted cell adds its first-moment field, its
 // gradient to the target and (negated) to the cell centre, and d/dD to node_adjq (six values, stride 8).
-template <bool MIXED, bool QUAD>
+// SCALED: the node records hold s^2 / theta^2 and the acceptance test is s2 < d^2 (kMacScaled).
+template <bool MIXED, bool QUAD, bool SCALED>
 __device__ __forceinline__ void adjoint_wave(int gw, FFBH_ADJ_PARAMS)
 {
     using T = typename std::conditional<MIXED, float, double>::type;
@@ -268,7 +269,7 @@ __device__ __forceinline__ void adjoint_wave(int gw, FFBH_ADJ_PARAMS)
         if (inside_test) insm = ballot((unsigned)(si - nd.first) < (unsigned)nd.count);
         const double dx = rx - nd.cx, dy = ry - nd.cy, dz = rz - nd.cz;
         const double d2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
-        const uint64_t accm = mask & ~insm & ballot(nd.s2 < theta2 * d2);
+        const uint64_t accm = mask & ~insm & ballot(SCALED ? nd.s2 < d2 : nd.s2 < theta2 * d2);
         const bool acc = lane_in(accm);
         if (accm != 0ull) {
             // the whole wave evaluates the pair (lanes that do not accept add zeros)
@@ -404,7 +405,7 @@ __host__ __device__ inline uint32_t order_segment_start(int x, int nw)
     return (uint32_t)(((int64_t)x * nw + kXcds - 1) / kXcds);
 }
 
-template <bool MIXED, bool QUAD>
+template <bool MIXED, bool QUAD, bool SCALED>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(MIXED && !QUAD ? 5 : 4))) void k_adjoint(
     FFBH_ADJ_PARAMS, const uint32_t *__restrict__ order, uint32_t *__restrict__ work_ctr)
 {
@@ -412,7 +413,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(MIXED && !Q
         const int wpb = blockDim.x / kWave;
         const int gw = xcd_block(blockIdx.x, gridDim.x) * wpb + (int)(threadIdx.x / kWave);
         if (gw >= num_waves) return;
-        adjoint_wave<MIXED, QUAD>(gw, FFBH_ADJ_ARGS);
+        adjoint_wave<MIXED, QUAD, SCALED>(gw, FFBH_ADJ_ARGS);
         return;
     }
     // The items are split into kXcds contiguous segments (neighbouring items share tree data).  Workgroups
@@ -434,7 +435,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(MIXED && !Q
                 if (lane == 0) set_flag(status, BH_FLAG_TREE);
                 return;
             }
-            adjoint_wave<MIXED, QUAD>((int)gw, FFBH_ADJ_ARGS);
+            adjoint_wave<MIXED, QUAD, SCALED>((int)gw, FFBH_ADJ_ARGS);
         }
     }
 }
@@ -739,17 +740,26 @@ hipError_t launch_backward(Handle &h, const double *d_mom, const double *d_hext,
         uint32_t *cost = parts == 1 ? w.wave_cost : nullptr;
         const void *nq = mixed ? (const void *)w.node_q32 : (const void *)w.node_q64;
         const uint32_t *tgt = uses_target_order(L) ? w.tgt_order : nullptr;
-        const int inside = theta2 > kSelfRejectTheta2 ? 1 : 0;
-#define FFBH_ADJ(MX, QD, T)                                                                                     \
-    hipLaunchKernelGGL((k_adjoint<MX, QD>), dim3(grid), dim3(wpb * kWave), wpb * sizeof(AdjLds<T>), s, w.nodes,     \
+        const int mac = mac_form(theta2);
+        const int inside = mac == kMacInside ? 1 : 0;
+        const bool scaled = mac == kMacScaled;
+#define FFBH_ADJ(MX, QD, SC, T)                                                                                 \
+    hipLaunchKernelGGL((k_adjoint<MX, QD, SC>), dim3(grid), dim3(wpb * kWave), wpb * sizeof(AdjLds<T>), s, w.nodes, \
                        w.node_m64, w.spos, w.smom, MX ? w.src32 : w.src64, w.hbar, w.perm, d_hext, w.g_gather,    \
                        w.g_rm, w.node_adj, w.Hs, d_H, w.e_part, w.status, L.n, L.ntot, wps, nwv, theta2,          \
                        (int)L.max_nodes, tpw, parts, w.part_buf, cost, nq, w.node_adjq, tgt, inside, ord,         \
                        w.sched_ctr)
-        if (mixed && quad) FFBH_ADJ(true, true, float);
-        else if (mixed) FFBH_ADJ(true, false, float);
-        else if (quad) FFBH_ADJ(false, true, double);
-        else FFBH_ADJ(false, false, double);
+        if (scaled) {
+            if (mixed && quad) FFBH_ADJ(true, true, true, float);
+            else if (mixed) FFBH_ADJ(true, false, true, float);
+            else if (quad) FFBH_ADJ(false, true, true, double);
+            else FFBH_ADJ(false, false, true, double);
+        } else {
+            if (mixed && quad) FFBH_ADJ(true, true, false, float);
+            else if (mixed) FFBH_ADJ(true, false, false, float);
+            else if (quad) FFBH_ADJ(false, true, false, double);
+            else FFBH_ADJ(false, false, false, double);
+        }
 #undef FFBH_ADJ
         if (parts > 1)
             hipLaunchKernelGGL(k_parts_sum, dim3((unsigned)((L.n + 255) / 256), (unsigned)L.B), dim3(256), 0, s,
@@ -775,13 +785,17 @@ hipError_t adjoint_resident_blocks(Handle &h, int &blocks)
     int per_cu = 0, cus = 0;
     hipError_t e;
     const bool quad = h.L.expansion == 2;
-    if (h.p.precision == BH_FP32_MIXED)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, quad ? k_adjoint<true, true> : k_adjoint<true, false>,
-                                                         wpb * kWave, wpb * sizeof(AdjLds<float>));
-    else
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu,
-                                                         quad ? k_adjoint<false, true> : k_adjoint<false, false>,
-                                                         wpb * kWave, wpb * sizeof(AdjLds<double>));
+    const bool sc = mac_form(h.p.theta * h.p.theta) == kMacScaled;
+    // the instantiation the handle launches (the occupancy depends on its registers)
+    if (h.p.precision == BH_FP32_MIXED) {
+        auto k = quad ? (sc ? k_adjoint<true, true, true> : k_adjoint<true, true, false>)
+                      : (sc ? k_adjoint<true, false, true> : k_adjoint<true, false, false>);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, wpb * kWave, wpb * sizeof(AdjLds<float>));
+    } else {
+        auto k = quad ? (sc ? k_adjoint<false, true, true> : k_adjoint<false, true, false>)
+                      : (sc ? k_adjoint<false, false, true> : k_adjoint<false, false, false>);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, wpb * kWave, wpb * sizeof(AdjLds<double>));
+    }
     if (e != hipSuccess) return e;
     e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h.device);
     if (e != hipSuccess) return e;

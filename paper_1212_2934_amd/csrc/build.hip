@@ -54,7 +54,8 @@ __global__ __launch_bounds__(256) void k_bbox_partial(const double *__restrict__
 // One workgroup of 256 per system folds the nb partial boxes (min and max are exact in any order).
 // Block 0 also clears the level-bucket counters (lvl, 128 words), which the build fills after the octree.
 __global__ __launch_bounds__(256) void k_bbox_final(const double *__restrict__ part, int nb,
-                                                    double *__restrict__ bbox, uint32_t *__restrict__ lvl)
+                                                    double *__restrict__ bbox, uint32_t *__restrict__ lvl,
+                                                    double s2_scale)
 {
     __shared__ double red[6][256];
     if (blockIdx.x == 0 && threadIdx.x < 128) lvl[threadIdx.x] = 0u;
@@ -91,6 +92,7 @@ __global__ __launch_bounds__(256) void k_bbox_final(const double *__restrict__ p
     o[0] = red[0][0]; o[1] = red[1][0]; o[2] = red[2][0];
     o[3] = side;
     o[4] = side > 0.0 ? 2097152.0 / side : 0.0;
+    o[5] = s2_scale;  // factor of the squared cell sides in the node records (node_s2_scale)
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -1083,8 +1085,9 @@ __device__ inline void upward_node(uint32_t q, const double *__restrict__ vals, 
         nodes[id].cx = sx / cnt;
         nodes[id].cy = sy / cnt;
         nodes[id].cz = sz / cnt;
-        const double side = __builtin_ldexp(bbox[8 * (nd.first / n) + 3], -node_level[id]);
-        nodes[id].s2 = side * side;
+        const double *bb = bbox + 8 * (nd.first / n);
+        const double side = __builtin_ldexp(bb[3], -node_level[id]);
+        nodes[id].s2 = side * side * bb[5];  // bb[5]: 1, or 1 / theta^2 for the scaled acceptance test
     }
     if (MODE != 0) {
         node_m64[4 * id] = mx;
@@ -1200,7 +1203,8 @@ hipError_t launch_build(Handle &h, const double *d_pos, hipStream_t s, const dou
     const int nb = (int)((n + 255) / 256 < kBboxBlocks ? (n + 255) / 256 : kBboxBlocks);
     hipLaunchKernelGGL(k_bbox_partial, dim3((unsigned)nb, (unsigned)B), dim3(256), 0, s, d_pos, n,
                        w.bbox_part, w.status, enter ? 1 : 0);
-    hipLaunchKernelGGL(k_bbox_final, dim3((unsigned)B), dim3(256), 0, s, w.bbox_part, nb, w.bbox, w.lvl);
+    hipLaunchKernelGGL(k_bbox_final, dim3((unsigned)B), dim3(256), 0, s, w.bbox_part, nb, w.bbox, w.lvl,
+                       node_s2_scale(h.p.theta * h.p.theta));
     hipLaunchKernelGGL(k_morton, dim3(grid_for(ntot, 256)), dim3(256), 0, s, d_pos, n, ntot, w.bbox,
                        w.keys[0], w.vals[0]);
     const int tiles = (int)L.tiles;

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <cmath>
 #include <functional>
 #include <type_traits>
 
@@ -27,6 +28,24 @@ constexpr int kStackMax = 64;                   // one traversal stack entry per
 // centre lie in the cell's cube of side s, so d^2 <= 3 s^2, and theta^2 d^2 < s^2 holds with a margin of
 // at least 10 %, far above rounding.  Up to it the traversals skip the explicit test for the target.
 constexpr double kSelfRejectTheta2 = 0.3;
+
+// Form of the acceptance test s^2 < theta^2 d^2 that a handle's traversals evaluate.
+//   kMacInside: as written, plus the explicit test for cells holding the target (theta^2 above
+//     kSelfRejectTheta2);
+//   kMacPlain: as written; the test itself rejects the cells holding the target;
+//   kMacScaled: theta^2 a power of two up to kSelfRejectTheta2 (theta = 1/2, 1/4, ...): the node records
+//     hold s^2 / theta^2, which is exact, and the test is s2 < d^2.  Multiplying by a power of two is exact
+//     (d^2 is never near the FP64 underflow threshold), so the decision is the same, with one FP64
+//     multiplication fewer per node visit.
+enum MacForm { kMacInside = 0, kMacPlain = 1, kMacScaled = 2 };
+inline int mac_form(double theta2)
+{
+    if (theta2 > kSelfRejectTheta2) return kMacInside;
+    int e = 0;
+    return theta2 > 0.0 && std::frexp(theta2, &e) == 0.5 ? kMacScaled : kMacPlain;
+}
+// Factor of the squared cell sides in the node records (bbox slot 5 of each system).
+inline double node_s2_scale(double theta2) { return mac_form(theta2) == kMacScaled ? 1.0 / theta2 : 1.0; }
 constexpr int kHilbertBits = 8;                 // bits per axis of the Hilbert keys that group targets
 constexpr int64_t kTargetOrderMin = 2049;       // systems from this size group targets in Hilbert order
 constexpr int64_t kForkMinParticles = 1 << 14;  // fewer particles over the batch stay on one stream
@@ -47,7 +66,7 @@ static_assert(sizeof(NodeRec) == 64, "node record must be one 64-byte line");
 // Device workspace, carved from the caller's buffer.  All arrays are global over the B systems.
 struct Workspace {
     uint32_t *status;        // [0] flags, [1] scan total, [2] node count, [12] calls in flight
-    double *bbox;            // B x 8: lo xyz, side, scale, (pad)
+    double *bbox;            // B x 8: lo xyz, side, quantisation scale, node s^2 factor, (pad)
     double *bbox_part;       // B x kBboxBlocks x 6 partial min/max
     uint64_t *keys[2];       // N_tot sort keys (ping-pong)
     uint32_t *vals[2];       // N_tot sort values: global original index (ping-pong)

@@ -63,12 +63,13 @@ __device__ inline void field_leaf(FieldLds<T> &W, int lane, const Src *__restric
 }
 
 // QUAD: accepted cells add their first-moment term (order-2 cells; node_q holds D per node, stride 16).
-// INSIDE: the explicit test for cells holding the target (needed above kSelfRejectTheta2); a template
-// argument rather than a kernel argument, because this walk is limited by scalar issue as much as by
-// vector issue and a branch per visit costs two scalar instructions.
+// MAC: the form of the acceptance test (MacForm: with the explicit test for cells holding the target,
+// without it, or on squared sides scaled by 1/theta^2); a template argument rather than a kernel argument,
+// because this walk is limited by scalar issue as much as by vector issue and a branch per visit costs two
+// scalar instructions.
 // Eight waves per SIMD (64 VGPRs): the FP64 walk spills a few bytes there and runs as fast as at seven;
 // the FP32-mixed walk fits without spilling and runs 2-3 % faster than with the hint at seven.
-template <bool MIXED, bool COUNT, bool QUAD, bool INSIDE>
+template <bool MIXED, bool COUNT, bool QUAD, int MAC>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(8))) void k_field(
     const NodeRec *__restrict__ nodes, const double *__restrict__ node_m64, const double *__restrict__ spos,
     const double *__restrict__ smom, const void *__restrict__ src, const uint32_t *__restrict__ perm,
@@ -114,11 +115,11 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(8))) void k
         // masks of the lanes that take part, of the targets inside the node (opened whatever the test
         // says; below kSelfRejectTheta2 the test rejects them itself) and of the acceptance test
         uint64_t insm = 0ull;
-        if constexpr (INSIDE) insm = ballot((unsigned)(si - nd.first) < (unsigned)nd.count);
+        if constexpr (MAC == kMacInside) insm = ballot((unsigned)(si - nd.first) < (unsigned)nd.count);
         // acceptance test in FP64, exactly as defined
         const double dx = rx - nd.cx, dy = ry - nd.cy, dz = rz - nd.cz;
         const double d2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
-        const uint64_t accm = mask & ~insm & ballot(nd.s2 < theta2 * d2);
+        const uint64_t accm = mask & ~insm & ballot(MAC == kMacScaled ? nd.s2 < d2 : nd.s2 < theta2 * d2);
         const bool acc = lane_in(accm);
         if (accm != 0ull) {
             // the whole wave computes (lanes that do not accept add exact zeros)
@@ -244,13 +245,15 @@ static void launch_k_field(Handle &h, const double *d_hext, double *d_H, hipStre
     const size_t lds = (size_t)wpb * sizeof(FieldLds<T>);
     const void *q = MIXED ? (const void *)w.node_q32 : (const void *)w.node_q64;
     const uint32_t *tgt = uses_target_order(L) ? w.tgt_order : nullptr;
-#define FFBH_FIELD(INSIDE)                                                                                       \
-    hipLaunchKernelGGL((k_field<MIXED, COUNT, QUAD, INSIDE>), dim3(blocks), dim3(wpb * kWave), lds, s, w.nodes,      \
+#define FFBH_FIELD(MAC)                                                                                          \
+    hipLaunchKernelGGL((k_field<MIXED, COUNT, QUAD, MAC>), dim3(blocks), dim3(wpb * kWave), lds, s, w.nodes,         \
                        w.node_m64, w.spos, w.smom, src, w.perm, d_hext, d_H, w.Hs, w.e_part, h.cnt_far,          \
                        h.cnt_near, w.status, L.n, L.ntot, waves_per_seg, (int)L.num_waves, theta2,               \
                        (int)L.max_nodes, q, tgt)
-    if (theta2 > kSelfRejectTheta2) FFBH_FIELD(true);
-    else FFBH_FIELD(false);
+    const int mac = mac_form(theta2);
+    if (mac == kMacInside) FFBH_FIELD(kMacInside);
+    else if (mac == kMacScaled) FFBH_FIELD(kMacScaled);
+    else FFBH_FIELD(kMacPlain);
 #undef FFBH_FIELD
 }
 
