@@ -19,6 +19,7 @@ Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
 """
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -528,7 +529,11 @@ def main():
     r32 = res["fp32_mixed"]
     # dominant kernel of the FP32-mixed step: the fused forward + adjoint walk
     tid = tuning["fp32_mixed"]
-    adj_key = "k_adjoint<true, false>"
+    # the instantiation launched: its last argument says whether the acceptance test runs on squared sides
+    # scaled by 1 / theta^2 (theta^2 a power of two up to 0.3, theta = 0.5 here)
+    th2 = args.theta * args.theta
+    scaled = 0.0 < th2 <= 0.3 and math.frexp(th2)[0] == 0.5
+    adj_key = f"k_adjoint<true, false, {'true' if scaled else 'false'}>"
     if r32["t_adj_kernel"] >= r32["t_fwd_kernel"]:
         kname, kt, flops = f"{adj_key} (fused forward + adjoint, tuning {tid})", r32["t_adj_kernel"], FLOPS_ADJ * inter
     else:
