@@ -34,16 +34,18 @@ def _close(a, b, tol=1e-12):
     assert torch.equal(a["step"], b["step"])
 
 
-@pytest.mark.parametrize("precision,tuning_id", [("fp64", -1), ("fp32_mixed", -1), ("fp32_mixed", 10)])
-def test_batched_slab_graph_replay_matches_eager(precision, tuning_id):
+@pytest.mark.parametrize("precision,tuning_id,caller_memory", [("fp64", -1, False), ("fp32_mixed", -1, False),
+                                                               ("fp32_mixed", 10, False), ("fp32_mixed", 10, True)])
+def test_batched_slab_graph_replay_matches_eager(precision, tuning_id, caller_memory):
     """tuning 10: the persistent adjoint launch, whose item order comes from the previous replay's costs
-    (ordering kernel and work-counter reset inside the graph)."""
+    (ordering kernel and work-counter reset inside the graph).  caller_memory: handles made by bh_init,
+    whose steps (and so the captured graph) use no side stream."""
     w = workloads.config5(batch=4, n=4096, box=(64.0, 64.0, 8.0))
     hext = torch.from_numpy(w.hext).cuda()
     mdp = _mdp(w.box_lo, w.box_hi, hext)
     s0 = _state(w.pos, w.mom, 5)
     eager = {k: v.clone() for k, v in s0.items()}
-    bh = BarnesHut(w.n, w.batch, 16, 0.5, precision, tuning_id=tuning_id)
+    bh = BarnesHut(w.n, w.batch, 16, 0.5, precision, tuning_id=tuning_id, caller_memory=caller_memory)
     snaps = []
     for _ in range(4):
         bh.md_step(eager, mdp)
@@ -51,7 +53,7 @@ def test_batched_slab_graph_replay_matches_eager(precision, tuning_id):
     torch.cuda.synchronize()
 
     g_state = {k: v.clone() for k, v in s0.items()}
-    bh2 = BarnesHut(w.n, w.batch, 16, 0.5, precision, tuning_id=tuning_id)
+    bh2 = BarnesHut(w.n, w.batch, 16, 0.5, precision, tuning_id=tuning_id, caller_memory=caller_memory)
     stream = torch.cuda.Stream()
     torch.cuda.synchronize()
     graph = bh2.capture_md_graph(g_state, mdp, stream)
