@@ -126,3 +126,36 @@ def test_degenerate_inputs_flagged():
     pos[1, 3] = np.nan
     out = run_field(pos, w.mom, precision="fp64", counters=False)
     assert out["flags"] & 1  # non-finite
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
+def test_field_with_and_without_the_side_stream(oracle_mod, precision):
+    """Above 16384 particles bh_build puts the targets in Hilbert order on the handle's own stream, beside
+    the octree; a handle in caller-owned memory has no second stream and does it on the caller's.  Both
+    give the same bits, on the first field call, after a rebuild and on a second field call on the same
+    tree, and match the oracle."""
+    import torch
+    from paper_1212_2934_amd.binding import BarnesHut
+    w = workloads.config3(seed=97, n=40003)
+    t = oracle_mod.Tree(w.pos, w.mom, 16)
+    H, nf, nr = t.field(0.5)
+    E = oracle_mod.energy(w.mom, H, None)
+    p = torch.from_numpy(w.pos).cuda()
+    m = torch.from_numpy(w.mom).cuda()
+    outs = []
+    for caller_memory in (False, True):
+        bh = BarnesHut(w.n, 1, 16, 0.5, precision, caller_memory=caller_memory)
+        cnt = bh.enable_counters()
+        runs = []
+        for rebuild in (True, True, False):
+            if rebuild:
+                bh.build(p)
+            Hd, Ed = bh.field(m)
+            runs.append((Hd.cpu().numpy(), Ed.cpu().numpy(), cnt[0].cpu().numpy().copy(), cnt[1].cpu().numpy().copy()))
+        assert bh.check_status() == 0
+        for r in runs[1:]:
+            assert all((a == b).all() for a, b in zip(r, runs[0]))
+        outs.append(runs[0])
+    assert all((a == b).all() for a, b in zip(outs[0], outs[1]))
+    out = dict(H=outs[0][0], E=outs[0][1], flags=0, n_far=outs[0][2].reshape(-1), n_near=outs[0][3].reshape(-1))
+    _check(out, H, E, nf, nr, w.mom, precision)
