@@ -100,3 +100,38 @@ def test_noalloc_rejects_oversize_on_host():
     params = binding.make_params(0, 1, 16, 0.5, "fp64")
     assert binding.lib().bh_field_noalloc(C.byref(params), None, None, None, None, None, None, None) == \
         binding.BH_EINVAL
+
+
+@pytest.mark.gpu
+def test_noalloc_replayed_from_a_graph():
+    """The entry point captured in a graph (it allocates nothing and records no memset) and replayed on
+    new inputs written into the captured buffers: every replay, with eager work and a synchronisation
+    between replays, equals the handle path on the same inputs bit for bit."""
+    torch.cuda.set_device(0)
+    B, n = 2, 3000
+    pos, mom, he = _batch(n, B, 131, 26.0, (0.0, 0.0, 0.5))
+    H = torch.empty_like(pos)
+    E = torch.empty(B, dtype=torch.float64, device="cuda")
+    F = torch.zeros(1, dtype=torch.int32, device="cuda")
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):  # one eager call first (the device's array address is looked up once)
+        binding.field_noalloc(pos, mom, he, precision="fp32_mixed", out=(H, E, F))
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    print("[noalloc] capture: batch 2 x 3000", flush=True)
+    with torch.cuda.graph(graph):
+        binding.field_noalloc(pos, mom, he, precision="fp32_mixed", out=(H, E, F))
+    for r in range(3):
+        p2, m2, _ = _batch(n, B, 140 + r, 26.0, (0.0, 0.0, 0.5))
+        pos.copy_(p2)
+        mom.copy_(m2)
+        print(f"[noalloc] replay {r}", flush=True)
+        graph.replay()
+        torch.cuda.synchronize()
+        Hr, Er = _handle_path(p2, m2, he, "fp32_mixed")
+        torch.cuda.synchronize()
+        assert int(F.item()) == 0
+        assert torch.equal(H, Hr), r
+        assert torch.equal(E, Er), r
