@@ -77,3 +77,47 @@ def test_autotune_candidates_are_result_invariant(tmp_path):
     assert set(r["times_ms"]) == set(range(int(lib().bh_num_tunings())))
     r2 = autotune.autotune(pos, mom, None, 0.5, 16, "fp32_mixed", cache_path=cache)
     assert r2["tuning_id"] == r["tuning_id"]
+
+
+@pytest.mark.parametrize("precision,tuning_id", [("fp64", -1), ("fp32_mixed", 11)])
+def test_build_field_backward_captured_by_the_caller(precision, tuning_id):
+    """bh_build, bh_field and bh_field_backward captured by the caller (torch's graph capture) and replayed
+    on new inputs.  At 20000 particles the build forks the handle's own stream and joins it again, which
+    become edges of the graph; tuning 11 adds the persistent adjoint launch with its ordering kernel.
+    Every replay equals eager calls on a second handle: the field and energy bit for bit, the gradients to
+    FP64 rounding (the adjoint's node sums are atomic)."""
+    n = 20000
+    w = workloads.config3(seed=151, n=n)
+    pos = torch.from_numpy(w.pos).cuda()
+    mom = torch.from_numpy(w.mom).cuda()
+    gE = torch.ones(1, dtype=torch.float64, device="cuda")
+    bh = BarnesHut(n, 1, 16, 0.5, precision, tuning_id=tuning_id)
+    ref = BarnesHut(n, 1, 16, 0.5, precision, tuning_id=tuning_id)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):  # one eager pass before the capture
+        bh.build(pos)
+        bh.field(mom)
+        bh.field_backward(mom, gE=gE)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        bh.build(pos)
+        H, E = bh.field(mom)
+        dpos, dmom = bh.field_backward(mom, gE=gE)
+    for r in range(3):
+        w2 = workloads.config3(seed=160 + r, n=n)
+        pos.copy_(torch.from_numpy(w2.pos))
+        mom.copy_(torch.from_numpy(w2.mom))
+        graph.replay()
+        torch.cuda.synchronize()
+        ref.build(pos)
+        Hr, Er = ref.field(mom)
+        dpr, dmr = ref.field_backward(mom, gE=gE)
+        torch.cuda.synchronize()
+        assert torch.equal(H, Hr) and torch.equal(E, Er), r
+        for a, b in ((dpos, dpr), (dmom, dmr)):
+            err = ((a - b).abs().max() / b.abs().max()).item()
+            assert err <= 1e-12, (r, err)
+    assert bh.check_status() == 0 and ref.check_status() == 0
