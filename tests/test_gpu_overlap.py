@@ -91,3 +91,40 @@ def test_a_call_that_finds_another_in_flight_is_flagged(entry):
     bh.field(d["mom"])
     torch.cuda.synchronize()
     assert bh.check_status() == 0
+
+
+def test_two_handles_step_concurrently_on_unordered_streams():
+    """Calls on different handles share nothing (each has its own workspace and stream): two handles
+    stepping MD on two streams with no ordering between them give the trajectories each gives alone, and
+    neither flags an overlap."""
+    torch.cuda.set_device(0)
+    n = 20000
+    (wa, da), (wb, db) = _system(n, 31), _system(n, 32)
+    mdp = _mdp(workloads.cube_side(n, 0.05))
+    alone = []
+    for d in (da, db):
+        bh = BarnesHut(n, 1, 16, 0.5, "fp32_mixed")
+        st = {k: v.clone() for k, v in d.items()}
+        for _ in range(3):
+            bh.md_step(st, mdp)
+        torch.cuda.synchronize()
+        assert bh.check_status() == 0
+        alone.append(st)
+    ha, hb = BarnesHut(n, 1, 16, 0.5, "fp32_mixed"), BarnesHut(n, 1, 16, 0.5, "fp32_mixed")
+    sa, sb = torch.cuda.Stream(), torch.cuda.Stream()
+    sta = {k: v.clone() for k, v in da.items()}
+    stb = {k: v.clone() for k, v in db.items()}
+    sa.wait_stream(torch.cuda.current_stream())
+    sb.wait_stream(torch.cuda.current_stream())
+    for _ in range(3):
+        with torch.cuda.stream(sa):
+            ha.md_step(sta, mdp)
+        with torch.cuda.stream(sb):
+            hb.md_step(stb, mdp)
+    torch.cuda.synchronize()
+    assert ha.check_status() == 0 and hb.check_status() == 0
+    for st, ref in ((sta, alone[0]), (stb, alone[1])):
+        assert torch.equal(st["step"], ref["step"])
+        for k in ("pos", "vel", "mom", "omega"):
+            err = ((st[k] - ref[k]).abs().max() / ref[k].abs().max()).item()
+            assert err <= 1e-12, (k, err)
