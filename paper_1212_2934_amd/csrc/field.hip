@@ -2,7 +2,8 @@
 // E = -1/2 sum m.H - sum m.H_ext (Sec. 3.2 kernel 5: traversal with spatially close targets sharing a
 // wavefront).
 //
-// One wavefront owns 64 consecutive targets in (system, Morton) order.  The wave walks the union of
+// One wavefront owns 64 consecutive targets of its system's target order (Hilbert order above 2048
+// particles, sorted Morton order below).  The wave walks the union of
 // its lanes' traversals depth first, children in octant order: the node on top of the stack is
 // fetched once for the whole wave with a scalar load, every lane in the node's lane mask applies its
 // own acceptance test (FP64, exactly as the definition states), accepting lanes add the

@@ -483,7 +483,7 @@ __device__ inline int target_of(const uint32_t *__restrict__ order, int seg, int
 extern __shared__ __align__(16) unsigned char ffbh_dyn_lds[];
 
 // Logical block index, arranged so that each of the 8 XCDs (which receive workgroups round-robin)
-// works on one contiguous range of Morton-ordered targets and keeps those nodes in its own L2.
+// works on one contiguous range of the target order and keeps those nodes in its own L2.
 __device__ inline int xcd_block(int bid, int nb)
 {
     const int q = nb >> 3, r = nb & 7;
