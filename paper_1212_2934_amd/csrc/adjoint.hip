@@ -618,7 +618,8 @@ __global__ __launch_bounds__(256) void k_zero_nodes(double *__restrict__ a, cons
 // dL/dm_j += E_C (r_j - c_C) (E_C symmetric, stored as xx, yy, zz, xy, xz, yz).
 __global__ __launch_bounds__(256) void k_downward(
     const NodeRec *__restrict__ nodes, const int32_t *__restrict__ leaf_of, const double *__restrict__ node_adj,
-    const double *__restrict__ g_gather, const double *__restrict__ g_rm, const double *__restrict__ Hs, const double *__restrict__ hext, const double *__restrict__ gE,
+    const double *__restrict__ g_gather, const double *__restrict__ g_rm, const double *__restrict__ Hs,
+    const double *__restrict__ hext, const double *__restrict__ gE,
     const uint32_t *__restrict__ perm, int64_t n, int64_t ntot, double *__restrict__ dpos,
     double *__restrict__ dmom, int64_t max_nodes, const double *__restrict__ node_adjq,
     const double *__restrict__ node_m64, const double *__restrict__ spos, const double *__restrict__ smom)

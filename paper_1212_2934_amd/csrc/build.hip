@@ -531,10 +531,11 @@ __global__ __launch_bounds__(256) void k_fix_ties(uint64_t *__restrict__ keys, u
 
 // Whole sort of one small system in one workgroup (systems of at most kSortSmallMax keys): the keys stay
 // in LDS for all eight passes (the full codes, no tie fix needed), so a small system's sort is one launch
-// instead of the tiled path's nine (four passes of two launches, then the runs of equal upper bits).  Each pass is
-// the tile pass of k_radix_scatter over the whole system: every wave ranks a contiguous chunk of keys
-// (ballot match masks, running per-wave digit counts), the digit starts and per-wave offsets place every
-// key, and the keys move to the other LDS buffer.  Stable, so the result is the multi-workgroup sort's.
+// instead of the tiled path's nine (four passes of two launches, then the runs of equal upper bits).
+// Each pass is the tile pass of k_radix_scatter over the whole system: every wave ranks a contiguous
+// chunk of keys (ballot match masks, running per-wave digit counts), the digit starts and per-wave
+// offsets place every key, and the keys move to the other LDS buffer.  Stable, so the result is the
+// multi-workgroup sort's.
 constexpr int kSortSmallThreads = 512;
 constexpr int kSortSmallMax = 2048;
 
