@@ -7,11 +7,11 @@ H_ext = 0 (synthetic, seeded).  A timed step is one MD step (md_step) on that in
 the whole hot path: tree build (bounding cube, Morton codes, radix sort, octree, centroids), upward
 moment pass, forward field and energy, the adjoint (dE/dr, dE/dm) by re-traversal, WCA pair and wall
 forces (partners from a cell grid cut from the build's Morton codes), and the Euler-Maruyama update with
-Philox noise (dt 1e-3, kT 1,
-gamma 0.1, M 1, I 0.1), replayed from a captured HIP graph.  value = MD steps/s in FP32-mixed
+Philox noise (dt 1e-3, kT 1, gamma 0.1, M 1, I 0.1), replayed from a captured HIP graph.  value = MD steps/s in FP32-mixed
 precision; field evaluations/s (tree build + field), eager MD steps/s, FP64 figures and the batched slab
 workload (32 realisations x 2^16 particles in 256 x 256 x 8, graph-replayed MD steps) are reported beside
-it, each precision and workload in the launch shape the autotuner picks for its MD steps.  The gradients
+it, each precision and workload in the launch shape the autotuner picks for its MD steps (the field
+evaluations in the shape it picks for them: build + field).  The gradients
 dE/dr and dE/dm of both precisions are compared with the FP64 oracle's (computed by the CPU-baseline leg):
 relative L2, 99.9th percentile and maximum per-particle error.
 
@@ -374,8 +374,20 @@ def main():
         log(f"autotune {precision}: tuning {t['tuning_id']} "
             f"({', '.join(f'{k}: {v:.2f} ms' for k, v in sorted(t['times_ms'].items()))})")
 
-    def make(precision):
-        return BarnesHut(n, 1, 16, args.theta, precision, tuning_id=tuning[precision])
+    # the field evaluations' own shape (only the forward walk's waves per workgroup matter there)
+    tuning_field = {}
+    for precision in ("fp32_mixed", "fp64"):
+        if args.tuning is not None:
+            tuning_field[precision] = tuning[precision]
+            continue
+        t = autotune(pos, mom, hext, args.theta, 16, precision, repeats=3, field=True)
+        tuning_field[precision] = t["tuning_id"]
+        log(f"autotune field {precision}: tuning {t['tuning_id']} "
+            f"({', '.join(f'{k}: {v:.2f} ms' for k, v in sorted(t['times_ms'].items()))})")
+
+    def make(precision, field=False):
+        return BarnesHut(n, 1, 16, args.theta, precision,
+                         tuning_id=(tuning_field if field else tuning)[precision])
 
     # interaction counts (outside timing): identical for both precisions
     bh = make("fp32_mixed")
@@ -409,9 +421,11 @@ def main():
         def gstep():
             graph.launch(side_stream)
 
+        fbh = make(precision, field=True)
+
         def field_only():
-            bh.build(pos)
-            return bh.field(mom, hext)
+            fbh.build(pos)
+            return fbh.field(mom, hext)
 
         for _ in range(args.warmup):
             step()
@@ -435,7 +449,9 @@ def main():
         for _ in range(args.steps):  # adjoint kernel time, one step at a time
             step()
             t_adj += ev.seconds(2, 3)
-        # field evaluation alone (build + field)
+        # field evaluation alone (build + field), on the handle of the field evaluations' shape
+        bh.set_raw_timing_events(None)
+        fbh.set_raw_timing_events(ev.ev)
         for _ in range(args.warmup):
             field_only()
         torch.cuda.synchronize()
@@ -447,18 +463,18 @@ def main():
         for _ in range(args.steps):  # forward traversal kernel time
             field_only()
             t_fwd += ev.seconds(0, 1)
-        assert bh.check_status() == 0
+        assert bh.check_status() == 0 and fbh.check_status() == 0
+        fbh.set_raw_timing_events(None)
         # the energy gradient of this precision on the benchmark state (compared with the oracle's below)
         grads[precision] = bh.field_backward(mom, hext, gE=ones)
         assert bh.check_status() == 0
-        bh.set_raw_timing_events(None)
         H_bh[precision] = field_only()[0].clone()
         res[precision] = dict(t_step=t_step, t_step_eager=t_step_eager, t_eval=t_eval, t_fwd_kernel=t_fwd / args.steps,
                               t_adj_kernel=t_adj / args.steps)
         log(f"{precision}: md step (graph) {t_step * 1e3:.3f} ms, eager {t_step_eager * 1e3:.3f} ms, field eval {t_eval * 1e3:.3f} ms, forward traversal "
             f"{res[precision]['t_fwd_kernel'] * 1e3:.3f} ms, fused forward+adjoint traversal "
             f"{res[precision]['t_adj_kernel'] * 1e3:.3f} ms")
-        del bh
+        del bh, fbh
     torch.cuda.synchronize()
 
     # all-pairs reference on the same state: its time, and the Barnes-Hut field error against it
@@ -583,6 +599,7 @@ def main():
         "kernel_ms": {p: {"traversal": r["t_fwd_kernel"] * 1e3, "adjoint": r["t_adj_kernel"] * 1e3}
                       for p, r in res.items()},
         "tuning_id": tuning,
+        "tuning_id_field": tuning_field,
         "allpairs_ms": ap_ms,
         "field_rel_error_vs_allpairs_fp64": ap_err,
         "roofline": roofline,

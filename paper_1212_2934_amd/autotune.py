@@ -6,7 +6,8 @@ and the same adjoint to rounding (its scatters are reduced in a shape-dependent 
 time counts.  The fastest accepted candidate is cached in a JSON file keyed by device, system
 size, batch, theta, leaf size and precision.  The time is that of build + field + adjoint on the given
 state, or, when MD parameters are given, of MD steps from it (each step rebuilds the tree from moved
-particles, which is what a launch shape that learns from the previous launch meets in a simulation).
+particles, which is what a launch shape that learns from the previous launch meets in a simulation), or,
+with field=True, of field evaluations (build + field; only the forward walk's shape matters there).
 """
 from __future__ import annotations
 
@@ -19,22 +20,25 @@ import torch
 from .binding import BarnesHut, lib
 
 
-def _key(n, batch, theta, leaf, precision, md=False):
+def _key(n, batch, theta, leaf, precision, md=False, field=False):
     dev = torch.cuda.get_device_name(torch.cuda.current_device())
-    return f"{dev}|n={n}|b={batch}|theta={theta}|leaf={leaf}|{precision}" + ("|md" if md else "")
+    return (f"{dev}|n={n}|b={batch}|theta={theta}|leaf={leaf}|{precision}" + ("|md" if md else "") +
+            ("|field" if field else ""))
 
 
 def autotune(pos, mom, hext=None, theta=0.5, leaf=16, precision="fp32_mixed", repeats=3,
-             cache_path=None, verbose=False, md=None) -> dict:
-    """Pick the fastest result-invariant tuning_id for build + forward + adjoint on this input, or for
+             cache_path=None, verbose=False, md=None, field=False) -> dict:
+    """Pick the fastest result-invariant tuning_id for build + forward + adjoint on this input, for
     MD steps when md = (state, md_params) is given (state: pos, vel, mom, omega, step tensors; it is
-    copied, not advanced).
+    copied, not advanced), or for build + field when field is True.
 
     pos, mom: (B, 3, n) or (3, n) float64 CUDA tensors.  Returns {"tuning_id", "times_ms", "key"}.
     """
     batch = 1 if pos.dim() == 2 else pos.shape[0]
     n = pos.shape[-1]
-    key = _key(n, batch, theta, leaf, precision, md is not None)
+    if md is not None and field:
+        raise ValueError("time either MD steps or field evaluations")
+    key = _key(n, batch, theta, leaf, precision, md is not None, field)
     cache = {}
     if cache_path and os.path.exists(cache_path):
         with open(cache_path) as f:
@@ -73,6 +77,9 @@ def autotune(pos, mom, hext=None, theta=0.5, leaf=16, precision="fp32_mixed", re
             t0 = time.perf_counter()
             if md is not None:
                 bh.md_step(st, md[1])
+            elif field:
+                bh.build(pos)
+                bh.field(mom, hext)
             else:
                 bh.build(pos)
                 bh.field_backward(mom, hext, gE=ones)

@@ -121,3 +121,21 @@ def test_build_field_backward_captured_by_the_caller(precision, tuning_id):
             err = ((a - b).abs().max() / b.abs().max()).item()
             assert err <= 1e-12, (r, err)
     assert bh.check_status() == 0 and ref.check_status() == 0
+
+
+def test_autotune_field_mode_has_its_own_cache_entry(tmp_path):
+    """field=True times build + field only and is cached under its own key beside the default mode's."""
+    import json
+    w = workloads.config3(seed=6, n=20000)
+    pos = torch.from_numpy(w.pos).cuda()
+    mom = torch.from_numpy(w.mom).cuda()
+    cache = str(tmp_path / "tune.json")
+    a = autotune.autotune(pos, mom, None, 0.5, 16, "fp32_mixed", repeats=2, cache_path=cache)
+    f = autotune.autotune(pos, mom, None, 0.5, 16, "fp32_mixed", repeats=2, cache_path=cache, field=True)
+    from paper_1212_2934_amd.binding import lib
+    assert set(f["times_ms"]) == set(range(int(lib().bh_num_tunings())))
+    assert f["key"] != a["key"] and f["key"].endswith("|field")
+    with open(cache) as fh:
+        assert set(json.load(fh)) == {a["key"], f["key"]}
+    with pytest.raises(ValueError):
+        autotune.autotune(pos, mom, None, 0.5, 16, "fp32_mixed", md=({}, None), field=True)
