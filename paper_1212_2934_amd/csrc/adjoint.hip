@@ -703,10 +703,14 @@ static int adjoint_items(const Handle &h)
 
 bool uses_wave_order(const Handle &h) { return h.adj_sched && h.adj_parts == 1; }
 
+void launch_order_items(const uint32_t *cost, int nw, uint32_t *order, uint32_t *work_ctr, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_order_waves, dim3(1), dim3(kOrderThreads), 0, s, cost, nw, order, work_ctr);
+}
+
 void launch_order_waves(Handle &h, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_order_waves, dim3(1), dim3(kOrderThreads), 0, s, h.w.wave_cost, adjoint_items(h),
-                       h.w.wave_order, h.w.sched_ctr);
+    launch_order_items(h.w.wave_cost, adjoint_items(h), h.w.wave_order, h.w.sched_ctr, s);
 }
 
 hipError_t launch_backward(Handle &h, const double *d_mom, const double *d_hext, const double *d_gH,

@@ -128,6 +128,9 @@ void carve(const Layout &Lc, void *base, Workspace &w)
     w.wave_cost = (uint32_t *)take(4 * nwmax);
     w.wave_order = (uint32_t *)take(4 * nwmax);
     w.sched_ctr = (uint32_t *)take(64);
+    w.field_cost = (uint32_t *)take(4 * (size_t)L.num_waves);
+    w.field_order = (uint32_t *)take(4 * (size_t)L.num_waves);
+    w.field_ctr = (uint32_t *)take(64);
     const size_t qn = L.expansion == 2 ? mn : 0;  // first moments only for order-2 cells
     w.node_q64 = (double *)take(16 * 8 * qn);
     w.node_q32 = (float *)take(16 * 4 * qn);
@@ -302,6 +305,7 @@ static hipError_t setup_handle(Handle &h, const bh_params *p, const Layout &L, v
     h.adj_parts = kTuneParts[tid];
     h.adj_sched = kTuneSched[tid];
     h.adj_resident = 0;
+    h.field_sched = 0;
     h.cnt_far = h.cnt_near = nullptr;
     for (int k = 0; k < 4; ++k) h.ev[k] = nullptr;
     hipError_t e = hipGetDevice(&h.device);
@@ -316,6 +320,7 @@ static hipError_t init_workspace(Handle &h, hipStream_t s)
     hipLaunchKernelGGL(k_init, dim3(1), dim3(256), 0, s, h.w.status, h.w.ones, (int64_t)L.B);
     hipLaunchKernelGGL(k_fill_u32, dim3(64), dim3(256), 0, s, h.w.wave_cost,
                        (int64_t)(L.B * ((L.n + kMinTpw - 1) / kMinTpw)), 0u);
+    hipLaunchKernelGGL(k_fill_u32, dim3(64), dim3(256), 0, s, h.w.field_cost, L.num_waves, 0u);
     return hipGetLastError();
 }
 
@@ -392,7 +397,15 @@ bh_status bh_build(bh_handle *hh, const double *d_pos, void *stream)
     Handle &h = hh->h;
     const hipStream_t side = h.L.ntot >= kForkMinParticles && uses_target_order(h.L) ? h.side : nullptr;
     const hipStream_t s = (hipStream_t)stream;
-    if (launch_build(h, d_pos, s, nullptr, side, true, true) != hipSuccess) return BH_EDEVICE;
+    // with the side stream, the forward walk's wave items are ordered there too (from the costs of the
+    // previous walk), and the next bh_field takes them in that order
+    SortedWork order_field;
+    if (side) order_field = [&h](hipStream_t q) {
+        launch_order_field(h, q);
+        return hipGetLastError();
+    };
+    if (launch_build(h, d_pos, s, nullptr, side, true, true, order_field) != hipSuccess) return BH_EDEVICE;
+    h.field_sched = side ? 1 : 0;
     hipLaunchKernelGGL(k_leave, dim3(1), dim3(64), 0, s, h.w.status);
     if (hipGetLastError() != hipSuccess) return BH_EDEVICE;
     hh->h.built = 1;

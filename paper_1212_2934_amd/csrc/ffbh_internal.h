@@ -101,6 +101,9 @@ struct Workspace {
     uint32_t *wave_cost;     // per adjoint wave item: work of the last launch (orders the next one)
     uint32_t *wave_order;    // item order of the next persistent launch
     uint32_t *sched_ctr;     // [0]: work counter of the persistent launch
+    uint32_t *field_cost;    // per forward-walk wave item: work of the last walk (orders the next one)
+    uint32_t *field_order;   // wave -> item order of the next forward walk
+    uint32_t *field_ctr;     // counters the ordering kernel resets (unused by the forward walk)
     double *node_q64;        // max_nodes x 16: first moment D (row-major 3x3, then pad) per node, FP64
     float *node_q32;         // max_nodes x 16: the same rounded to FP32 (mixed-precision traversal)
     double *node_adjq;       // max_nodes x 8: dL/dD of each node, symmetric (xx, yy, zz, xy, xz, yz)
@@ -150,6 +153,7 @@ struct Handle {
     int adj_parts;       // independent adjoint walks split over the root's children (8) or not (1)
     int adj_sched;       // independent adjoint waves in one persistent, cost-ordered launch
     int adj_resident;    // workgroups of that launch resident at once (grid of the persistent launch)
+    int field_sched;     // the last bh_build ordered the forward walk's wave items (bh_field follows it)
     int32_t *cnt_far, *cnt_near;  // optional per-target counters (device)
     hipEvent_t ev[4];             // optional timing events around the traversal kernels
     // The MD step's side stream (default priority, non-blocking) and its fork/join events: the wave
@@ -247,6 +251,10 @@ hipError_t launch_backward(Handle &h, const double *d_mom, const double *d_hext,
 // that orders its items from the costs the previous traversal recorded.
 bool uses_wave_order(const Handle &h);
 void launch_order_waves(Handle &h, hipStream_t s);
+// The same ordering for any list of wave items: item order from per-item costs, work counters reset.
+void launch_order_items(const uint32_t *cost, int nw, uint32_t *order, uint32_t *work_ctr, hipStream_t s);
+// Order of the forward walk's items from the costs the previous forward walk recorded.
+void launch_order_field(Handle &h, hipStream_t s);
 void launch_energy_final(Handle &h, double *d_E, hipStream_t s, int targets_per_wave);
 hipError_t adjoint_resident_blocks(Handle &h, int &blocks);
 hipError_t launch_ap(int64_t n, int32_t batch, int32_t precision, const double *pos, const double *mom,

@@ -77,15 +77,23 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(8))) void k
     const double *__restrict__ hext, double *__restrict__ H, double *__restrict__ Hs,
     double *__restrict__ e_part, int32_t *__restrict__ cnt_far, int32_t *__restrict__ cnt_near,
     uint32_t *__restrict__ status, int64_t n, int64_t ntot, int waves_per_seg, int num_waves,
-    double theta2, int max_nodes, const void *__restrict__ node_q, const uint32_t *__restrict__ tgt_order)
+    double theta2, int max_nodes, const void *__restrict__ node_q, const uint32_t *__restrict__ tgt_order,
+    const uint32_t *__restrict__ order, uint32_t *__restrict__ wave_cost)
 {
     using T = typename std::conditional<MIXED, float, double>::type;
     using Src = typename std::conditional<MIXED, Src32, Src64>::type;
     const Src *__restrict__ sr = (const Src *)src;
     const int lane = threadIdx.x & (kWave - 1);
     const int wpb = blockDim.x / kWave;
-    const int gw = xcd_block(blockIdx.x, gridDim.x) * wpb + (int)(threadIdx.x / kWave);
-    if (gw >= num_waves) return;  // whole waves only
+    const int lin = xcd_block(blockIdx.x, gridDim.x) * wpb + (int)(threadIdx.x / kWave);
+    if (lin >= num_waves) return;  // whole waves only
+    // with an order, the wave takes the item at its place in it (heavy items of the previous walk first
+    // within each XCD's range, light ones last); an order outside the items is ignored
+    int gw = lin;
+    if (order) {
+        const uint32_t o = order[lin];
+        if (o < (uint32_t)num_waves) gw = (int)o;
+    }
     const int seg = gw / waves_per_seg;
     const int local = (gw - seg * waves_per_seg) * kWave + lane;
     const bool valid = local < n;
@@ -109,6 +117,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(8))) void k
     // system's), so every visited node is in [0, max_nodes); a wave pushes each internal node's children
     // at most once, so at most max_nodes pushes keep the walk finite whatever the tree holds.
     int guard = max_nodes;
+    uint32_t rounds = 0;  // leaf pair rounds (wave-uniform)
     while (st.more()) {
         uint64_t mask;
         const int cur = st.pop_settled(mask);
@@ -163,6 +172,10 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(8))) void k
                 if (nd.count <= 4) field_leaf<COUNT, 4>(W, lane, sr, nd.first, nd.count, c, coincident);
                 else if (nd.count <= 8) field_leaf<COUNT, 8>(W, lane, sr, nd.first, nd.count, c, coincident);
                 else field_leaf<COUNT, 16>(W, lane, sr, nd.first, nd.count, c, coincident);
+                {
+                    const int G = nd.count <= 4 ? 4 : nd.count <= 8 ? 8 : 16;
+                    rounds += (uint32_t)(((nd.count + G - 1) / G) * ((c * G + kWave - 1) / kWave + 1));
+                }
                 wave_lds_sync();
                 const T a0 = W.acc[lane][0], a1 = W.acc[lane][1], a2 = W.acc[lane][2];
                 W.acc[lane][0] = W.acc[lane][1] = W.acc[lane][2] = (T)0;
@@ -184,6 +197,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(8))) void k
         hx += (double)px; hy += (double)py; hz += (double)pz;
     }
     if (ballot(coincident != 0u) != 0ull && lane == 0) set_flag(status, BH_FLAG_COINCIDENT);
+    // the item's work (internal nodes opened, times eight, plus leaf pair rounds) orders the next walk
+    if (wave_cost && lane == 0) wave_cost[gw] = 8u * (uint32_t)(max_nodes - guard) + rounds;
 
     // energy contribution of this wave: -1/2 m.H - m.H_ext
     double e = 0.0;
@@ -250,7 +265,7 @@ static void launch_k_field(Handle &h, const double *d_hext, double *d_H, hipStre
     hipLaunchKernelGGL((k_field<MIXED, COUNT, QUAD, MAC>), dim3(blocks), dim3(wpb * kWave), lds, s, w.nodes,         \
                        w.node_m64, w.spos, w.smom, src, w.perm, d_hext, d_H, w.Hs, w.e_part, h.cnt_far,          \
                        h.cnt_near, w.status, L.n, L.ntot, waves_per_seg, (int)L.num_waves, theta2,               \
-                       (int)L.max_nodes, q, tgt)
+                       (int)L.max_nodes, q, tgt, h.field_sched ? w.field_order : nullptr, w.field_cost)
     const int mac = mac_form(theta2);
     if (mac == kMacInside) FFBH_FIELD(kMacInside);
     else if (mac == kMacScaled) FFBH_FIELD(kMacScaled);
@@ -280,6 +295,11 @@ hipError_t launch_field(Handle &h, const double *d_mom, const double *d_hext, do
     if (h.ev[1]) (void)hipEventRecord(h.ev[1], s);
     if (d_E) launch_energy_final(h, d_E, s, kWave);
     return hipGetLastError();
+}
+
+void launch_order_field(Handle &h, hipStream_t s)
+{
+    launch_order_items(h.w.field_cost, (int)h.L.num_waves, h.w.field_order, h.w.field_ctr, s);
 }
 
 void launch_energy_final(Handle &h, double *d_E, hipStream_t s, int targets_per_wave)
