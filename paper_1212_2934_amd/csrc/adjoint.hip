@@ -390,10 +390,11 @@ __device__ __forceinline__ void adjoint_wave(int gw, FFBH_ADJ_PARAMS)
     }
 }
 
-// Independent-wave fused traversal.  Without `order` every wave takes one item (its global wave index).
-// With `order`, the launch is persistent: each wave takes item after item from the work counter, in the
-// order given (light items of the previous launch last, so the launch does not end on a long item), until
-// the items run out.  Every wave reaches the exit: the counter only grows.
+// Independent-wave fused traversal.  Without work counters every wave takes one item: its global wave
+// index, or with `order` the item at that place of the order (light items of the previous launch last,
+// so the launch does not end on a long item).  With work counters the launch is persistent: each wave
+// takes item after item in the order given, until the items run out.  Every wave reaches the exit: the
+// counters only grow.
 // Waves per SIMD: five for the FP32-mixed walk with the paper's cells (96 VGPRs, a few spilled bytes;
 // 3 % faster MD step than at four), four for the others (the FP64 walk fits 128 VGPRs and runs 7 % faster
 // than at three, but spills heavily at five).
@@ -409,10 +410,17 @@ template <bool MIXED, bool QUAD, bool SCALED>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(MIXED && !QUAD ? 5 : 4))) void k_adjoint(
     FFBH_ADJ_PARAMS, const uint32_t *__restrict__ order, uint32_t *__restrict__ work_ctr)
 {
-    if (!order) {
+    if (!work_ctr) {
+        // one wave per item; with an order, wave lin takes item order[lin] (heavy items of the previous
+        // launch first within each XCD's range, light ones last)
         const int wpb = blockDim.x / kWave;
-        const int gw = xcd_block(blockIdx.x, gridDim.x) * wpb + (int)(threadIdx.x / kWave);
-        if (gw >= num_waves) return;
+        const int lin = xcd_block(blockIdx.x, gridDim.x) * wpb + (int)(threadIdx.x / kWave);
+        if (lin >= num_waves) return;
+        int gw = lin;
+        if (order) {
+            const uint32_t o = order[lin];
+            if (o < (uint32_t)num_waves) gw = (int)o;
+        }
         adjoint_wave<MIXED, QUAD, SCALED>(gw, FFBH_ADJ_ARGS);
         return;
     }
@@ -741,11 +749,14 @@ hipError_t launch_backward(Handle &h, const double *d_mom, const double *d_hext,
         const int wps = (int)((L.n + tpw - 1) / tpw);
         const int nwv = adjoint_items(h);
         const unsigned blk = (unsigned)((nwv + wpb - 1) / wpb);
-        // persistent, cost-ordered launch: as many workgroups as can be resident at once
+        // cost-ordered launches: persistent (adj_sched 1: as many workgroups as can be resident at once,
+        // items from per-XCD work counters) or one wave per item in that order (adj_sched 2)
         const bool sched = uses_wave_order(h);
         if (sched && !order_done) launch_order_waves(h, s);
-        const unsigned grid = sched && (unsigned)h.adj_resident < blk ? (unsigned)h.adj_resident : blk;
+        const bool persistent = sched && h.adj_sched == 1;
+        const unsigned grid = persistent && (unsigned)h.adj_resident < blk ? (unsigned)h.adj_resident : blk;
         const uint32_t *ord = sched ? w.wave_order : nullptr;
+        uint32_t *ctr = persistent ? w.sched_ctr : nullptr;
         uint32_t *cost = parts == 1 ? w.wave_cost : nullptr;
         const void *nq = mixed ? (const void *)w.node_q32 : (const void *)w.node_q64;
         const uint32_t *tgt = uses_target_order(L) ? w.tgt_order : nullptr;
@@ -756,8 +767,7 @@ hipError_t launch_backward(Handle &h, const double *d_mom, const double *d_hext,
     hipLaunchKernelGGL((k_adjoint<MX, QD, SC>), dim3(grid), dim3(wpb * kWave), wpb * sizeof(AdjLds<T>), s, w.nodes, \
                        w.node_m64, w.spos, w.smom, MX ? w.src32 : w.src64, w.hbar, w.perm, d_hext, w.g_gather,    \
                        w.g_rm, w.node_adj, w.Hs, d_H, w.e_part, w.status, L.n, L.ntot, wps, nwv, theta2,          \
-                       (int)L.max_nodes, tpw, parts, w.part_buf, cost, nq, w.node_adjq, tgt, inside, ord,         \
-                       w.sched_ctr)
+                       (int)L.max_nodes, tpw, parts, w.part_buf, cost, nq, w.node_adjq, tgt, inside, ord, ctr)
         if (scaled) {
             if (mixed && quad) FFBH_ADJ(true, true, true, float);
             else if (mixed) FFBH_ADJ(true, false, true, float);

@@ -22,11 +22,12 @@ static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 // Traversal launch shapes selectable by tuning_id: waves per workgroup of the traversals, how many
 // targets an adjoint wave owns (fewer than 64 gives small systems more walks in flight), whether each
 // adjoint walk is split over the root's children (8 parts) or not (1), and whether the adjoint waves run in
-// one persistent launch that orders its items by the previous launch's costs.
-static const int kTuneWaves[] = {4, 1, 2, 8, 4, 4, 4, 4, 4, 2, 4, 1};
-static const int kTuneTpw[] = {64, 64, 64, 64, 32, 16, 64, 32, 16, 64, 64, 64};
-static const int kTuneParts[] = {1, 1, 1, 1, 1, 1, 8, 8, 8, 1, 1, 1};
-static const int kTuneSched[] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 1};
+// one persistent launch that orders its items by the previous launch's costs (1) or one wave per item in
+// that order (2).
+static const int kTuneWaves[] = {4, 1, 2, 8, 4, 4, 4, 4, 4, 2, 4, 1, 1, 2, 4};
+static const int kTuneTpw[] = {64, 64, 64, 64, 32, 16, 64, 32, 16, 64, 64, 64, 64, 64, 64};
+static const int kTuneParts[] = {1, 1, 1, 1, 1, 1, 8, 8, 8, 1, 1, 1, 1, 1, 1};
+static const int kTuneSched[] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 2, 2, 2};
 static const int kNumTunings = (int)(sizeof(kTuneWaves) / sizeof(kTuneWaves[0]));
 static_assert(sizeof(kTuneTpw) == sizeof(kTuneWaves) && sizeof(kTuneParts) == sizeof(kTuneWaves) &&
                   sizeof(kTuneSched) == sizeof(kTuneWaves),

@@ -151,7 +151,8 @@ struct Handle {
     int waves_per_block; // traversal launch shape
     int adj_tpw;         // targets per independent adjoint wave (16, 32 or 64)
     int adj_parts;       // independent adjoint walks split over the root's children (8) or not (1)
-    int adj_sched;       // independent adjoint waves in one persistent, cost-ordered launch
+    int adj_sched;       // adjoint waves: 0 one per item in index order, 1 one persistent launch in the
+                         // previous launch's cost order, 2 one per item in that order
     int adj_resident;    // workgroups of that launch resident at once (grid of the persistent launch)
     int field_sched;     // the last bh_build ordered the forward walk's wave items (bh_field follows it)
     int32_t *cnt_far, *cnt_near;  // optional per-target counters (device)

@@ -37,8 +37,9 @@ def _gpu_grad(pos, mom, hext, theta, precision, gH=None, gE=1.0, leaf=16, want_d
 
 
 # 64, 32 and 16 targets per wave; each walk split over the root's children, with 64, 32 and 16 targets per
-# wave; one persistent cost-ordered launch with 2, 4 and 1 waves per workgroup
-@pytest.mark.parametrize("tuning_id", [0, 4, 5, 6, 7, 8, 9, 10, 11])
+# wave; one persistent cost-ordered launch with 2, 4 and 1 waves per workgroup; one wave per item in the
+# cost order with 1, 2 and 4 waves per workgroup
+@pytest.mark.parametrize("tuning_id", [0, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14])
 @pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
 def test_energy_gradient_config1(oracle_mod, precision, tuning_id):
     w = workloads.uniform_cube(4096, 32.0, seed=1001, hext=(0.0, 0.0, 1.0))
@@ -104,11 +105,12 @@ def test_small_systems(oracle_mod, n, tuning_id):
     grad_check(gdm, dm, "fp64", f"dE/dm n {n}")
 
 
-@pytest.mark.parametrize("tuning_id", [9, 11])
+@pytest.mark.parametrize("tuning_id", [9, 11, 12, 14])
 @pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
 def test_persistent_launch_repeats(oracle_mod, precision, tuning_id):
-    """The persistent launch orders its items by the previous launch's costs: the first call runs them in
-    index order, later calls heaviest first.  Every call agrees with the oracle (ragged batch of 3)."""
+    """The cost-ordered launches (persistent: 9, 11; one wave per item: 12, 14) order their items by the
+    previous launch's costs: the first call runs them in index order, later calls heavy items first and
+    light ones last.  Every call agrees with the oracle (ragged batch of 3)."""
     B, n = 3, 3000 + 5
     ws = [workloads.uniform_cube(n, 30.0, seed=70 + b) for b in range(B)]
     pos = np.stack([x.pos for x in ws])

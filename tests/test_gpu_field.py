@@ -107,7 +107,7 @@ def test_permutation_and_repeatability():
     assert (c["H"] == a["H"]).all() and c["E"][0] == a["E"][0]
 
 
-@pytest.mark.parametrize("tuning_id", list(range(12)))
+@pytest.mark.parametrize("tuning_id", list(range(15)))
 def test_launch_shape_invariance(tuning_id):
     w = workloads.config3(seed=81, n=5000)
     ref = run_field(w.pos, w.mom, precision="fp32_mixed", tuning_id=0)
