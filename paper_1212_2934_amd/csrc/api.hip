@@ -398,15 +398,19 @@ bh_status bh_build(bh_handle *hh, const double *d_pos, void *stream)
     Handle &h = hh->h;
     const hipStream_t side = h.L.ntot >= kForkMinParticles && uses_target_order(h.L) ? h.side : nullptr;
     const hipStream_t s = (hipStream_t)stream;
-    // with the side stream, the forward walk's wave items are ordered there too (from the costs of the
-    // previous walk), and the next bh_field takes them in that order
+    // the forward walk's wave items are ordered from the costs of the previous walk, and the next bh_field
+    // takes them in that order: beside the octree on the side stream, or after the build on the caller's
+    // stream for a handle without one (the ordering costs less than the walk's tail it removes from 16384
+    // particles up)
     SortedWork order_field;
     if (side) order_field = [&h](hipStream_t q) {
         launch_order_field(h, q);
         return hipGetLastError();
     };
+    const bool order_here = !side && h.L.ntot >= kForkMinParticles;
     if (launch_build(h, d_pos, s, nullptr, side, true, true, order_field) != hipSuccess) return BH_EDEVICE;
-    h.field_sched = side ? 1 : 0;
+    if (order_here) launch_order_field(h, s);
+    h.field_sched = side || order_here ? 1 : 0;
     hipLaunchKernelGGL(k_leave, dim3(1), dim3(64), 0, s, h.w.status);
     if (hipGetLastError() != hipSuccess) return BH_EDEVICE;
     hh->h.built = 1;
