@@ -96,8 +96,10 @@ bh_status bh_workspace_bytes(const bh_params *p, size_t *out_bytes);
  * forward field (bitwise) and interaction counts; the adjoint agrees to rounding (its sums are reduced in
  * another order).  Some shapes split each adjoint walk over the root's children and hold a partial-sum
  * buffer of 384 bytes per particle in the workspace (bh_workspace_bytes depends on tuning_id).  Others
- * launch the adjoint walk persistently and order its work by the cost each wave item had in the previous
- * call on the handle (the first call after bh_create runs the items in index order). */
+ * order the adjoint walk's wave items by the cost each had in the previous call on the handle (the first
+ * call after bh_create runs them in index order), in one persistent launch or one wave per item.  The
+ * forward walk of bh_field takes its items in the order of its previous call's costs in every shape, from
+ * 16384 particles up (ordered by bh_build). */
 int32_t bh_num_tunings(void);
 
 /* Create a handle (host memory, owned by the caller until bh_destroy) bound to the current HIP device
